@@ -1,0 +1,164 @@
+"""CPU oracle for masked multi-scale FAST detection in video — TEST INFRASTRUCTURE.
+
+A ctypes view of ``kpd_oracle.c`` (plain scalar C written from the paper's
+definitions; every reading of the paper it takes is listed at the top of that
+file). Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+CPU-baseline leg may import this package. The GPU library never does, and
+shares no code with it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kpd_oracle.c")
+LIB = os.path.join(HERE, "libkpd_oracle.so")
+GCC_CMD = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, SRC]
+
+KP_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("octave", "<i4"), ("score", "<i4")])
+KB_OFF = 0xFFFFFFFF
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def build() -> str:
+    subprocess.run(GCC_CMD, check=True)
+    return LIB
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        build()
+    L = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    i32, u32 = ctypes.c_int32, ctypes.c_uint32
+    L.orc_level_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+    L.orc_level_dims.restype = ctypes.c_long
+    L.orc_pyramid.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+    L.orc_ring.argtypes = [ctypes.c_int, P, P]
+    L.orc_arc9.argtypes = [ctypes.c_uint]
+    L.orc_score_level.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+    L.orc_detect.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int]
+    L.orc_cell_of.argtypes = [ctypes.c_int] * 7
+    L.orc_open.argtypes = [ctypes.c_int] * 6 + [i32, u32]
+    L.orc_open.restype = P
+    L.orc_close.argtypes = [P]
+    L.orc_close.restype = None
+    L.orc_set_thresholds.argtypes = [P, ctypes.c_int, i32, u32]
+    L.orc_push.argtypes = [P, P]
+    L.orc_get.argtypes = [P, P, ctypes.c_int, P, P, P]
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def level_dims(W: int, H: int, O: int):
+    ws = np.zeros(32, np.int32)
+    hs = np.zeros(32, np.int32)
+    lib().orc_level_dims(W, H, O, _ptr(ws), _ptr(hs))
+    return [(int(ws[o]), int(hs[o])) for o in range(O)]
+
+
+def pyramid(img: np.ndarray, O: int):
+    """Levels 0..O-1 as a list of uint8 arrays."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    dims = level_dims(W, H, O)
+    out = np.zeros(sum(w * h for w, h in dims), np.uint8)
+    assert lib().orc_pyramid(_ptr(img), W, H, O, _ptr(out)) == 0
+    levels, off = [], 0
+    for w, h in dims:
+        levels.append(out[off:off + w * h].reshape(h, w))
+        off += w * h
+    return levels
+
+
+def ring():
+    dx, dy = ctypes.c_int(), ctypes.c_int()
+    out = []
+    for k in range(16):
+        lib().orc_ring(k, ctypes.byref(dx), ctypes.byref(dy))
+        out.append((dx.value, dy.value))
+    return out
+
+
+def arc9(mask: int) -> bool:
+    return bool(lib().orc_arc9(mask))
+
+
+def score_level(level: np.ndarray, t: int) -> np.ndarray:
+    level = np.ascontiguousarray(level, dtype=np.uint8)
+    h, w = level.shape
+    V = np.zeros((h, w), np.uint16)
+    lib().orc_score_level(_ptr(level), w, h, t, _ptr(V))
+    return V
+
+
+def detect(img: np.ndarray, t: int, O: int) -> np.ndarray:
+    """Full-frame detection F(I): structured array (x, y, octave, score),
+    ordered by octave, y, x."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    cap = W * H + 16
+    out = np.zeros(cap, KP_DTYPE)
+    n = lib().orc_detect(_ptr(img), W, H, t, O, _ptr(out), cap)
+    assert n >= 0, n
+    return out[:n].copy()
+
+
+def cell_of(x: int, y: int, o: int, W: int, H: int, Nc: int, Nr: int) -> int:
+    return lib().orc_cell_of(x, y, o, W, H, Nc, Nr)
+
+
+class Stream:
+    """The oracle's video stream: push frames, read D_n, the mask M_n, the
+    per-cell SAD and the per-cell counts."""
+
+    def __init__(self, W: int, H: int, t: int, O: int, Nc: int, Nr: int, TI: int, TH: int = KB_OFF):
+        self.W, self.H, self.Nc, self.Nr = W, H, Nc, Nr
+        self.h = lib().orc_open(W, H, t, O, Nc, Nr, TI, TH & 0xFFFFFFFF)
+        if not self.h:
+            raise ValueError("bad oracle stream parameters")
+
+    def set_thresholds(self, t: int, TI: int, TH: int = KB_OFF):
+        lib().orc_set_thresholds(self.h, t, TI, TH & 0xFFFFFFFF)
+
+    def push(self, frame: np.ndarray) -> int:
+        frame = np.ascontiguousarray(frame, dtype=np.uint8)
+        assert frame.shape == (self.H, self.W)
+        n = lib().orc_push(self.h, _ptr(frame))
+        assert n >= 0
+        return n
+
+    def get(self):
+        nc = self.Nc * self.Nr
+        n = lib().orc_get(self.h, None, 0, None, None, None)
+        kps = np.zeros(max(n, 1), KP_DTYPE)
+        mask = np.zeros(nc, np.uint8)
+        sad = np.zeros(nc, np.int64)
+        cnt = np.zeros(nc, np.uint32)
+        n2 = lib().orc_get(self.h, _ptr(kps), len(kps), _ptr(mask), _ptr(sad), _ptr(cnt))
+        assert n2 == n
+        return kps[:n].copy(), mask, sad, cnt
+
+    def close(self):
+        if self.h:
+            lib().orc_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

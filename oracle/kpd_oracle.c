@@ -1,0 +1,386 @@
+/*
+ * CPU oracle for masked multi-scale FAST keypoint detection in video
+ * (Baroffio, Cesana, Redondi, Tagliasacchi, "Fast keypoint detection in video
+ * sequences", arXiv:1503.06959).
+ *
+ * TEST INFRASTRUCTURE. This file is a plain, slow, scalar, single-threaded
+ * statement of what the detection path computes. It exists only to check the
+ * GPU library: the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg may load it; the library itself never does. It shares no code, header,
+ * table or helper with the GPU path.
+ *
+ * Every function follows the paper's definitions in the paper's order:
+ *   Sec. 2     AST segment test on the radius-3 Bresenham circle; scale space
+ *              of octaves by downsampling; non-maxima suppression in a 3x3
+ *              scale-space neighbourhood keeping local maxima.
+ *   Sec. 3     feature set D_n of frame I_n; detection mask M_n; Eq. (1)
+ *              propagation of previous-frame features where the mask is 0.
+ *   Sec. 3.1   Eq. (2) intensity-difference mask (polarity and granularity
+ *              as read below).
+ *   Sec. 3.2   Eq. (3) keypoint histogram over the N_r x N_c bin grid,
+ *              Eq. (4) threshold T_H.
+ *
+ * Readings where the paper is silent or inconsistent (kept in one place):
+ *   R1  "O octaves" = levels 0..O-1; level o is the 2x2 box mean of level o-1
+ *       with round-half-up ((a+b+c+d+2)>>2), dimensions halved by floor.
+ *   R2  AST: n = 9 contiguous of the 16 ring pixels, strict inequalities
+ *       (brighter than I_p + t, darker than I_p - t).
+ *   R3  Corner score (the paper only says "local maxima"): the FAST score
+ *       V = max(sum over bright ring pixels of (c - p - t),
+ *               sum over dark ring pixels of (p - c - t)) for pixels passing
+ *       the segment test, 0 otherwise.
+ *   R4  Scale-space neighbourhood of level-o pixel (x,y): its 8 in-plane
+ *       neighbours; at level o-1 the pixels (x',y') with 2x-1<=x'<=2x+2 and
+ *       2y-1<=y'<=2y+2; at level o+1 the pixels (X,Y) with 2X-1<=x<=2X+2 and
+ *       2Y-1<=y<=2Y+2. Ties are broken by a strict total order: higher V
+ *       wins, then the finer octave, then the smaller (y,x). A pixel is a
+ *       keypoint iff V>0 and no neighbour beats it.
+ *   R5  No candidates within 3 pixels of a level's border.
+ *   R6  Cells: level-0 pixel (X,Y) lies in cell (floor(X*Nc/W), floor(Y*Nr/H));
+ *       a keypoint at (x,y) of level o lies in the cell of (x<<o, y<<o).
+ *   R7  Mask (Eq. 2 printed with inverted polarity; the text asks to detect
+ *       where the frame changes): a cell is marked when its summed absolute
+ *       level-0 difference exceeds T_I times its pixel count (the mean
+ *       absolute difference per pixel exceeds T_I), or when the previous
+ *       feature set has at least T_H keypoints in it (Eq. 4 uses >=).
+ *       The two tests are OR-ed. The first frame, and the frame after a change
+ *       of t, mark every cell.
+ *   R8  Eq. (1): D_n is the full-frame detection of I_n restricted to marked
+ *       cells together with D_{n-1} restricted to unmarked cells, listed by
+ *       cell (row-major), then octave, then y, then x.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t x, y, octave, score;
+} orc_kp;
+
+/* ---------------------------------------------------------------- pyramid */
+
+/* Level sizes under R1. Returns the total byte count of levels 0..O-1. */
+long orc_level_dims(int W, int H, int O, int* ws, int* hs)
+{
+    long total = 0;
+    int w = W, h = H;
+    for (int o = 0; o < O; ++o) {
+        ws[o] = w;
+        hs[o] = h;
+        total += (long)w * h;
+        w /= 2;
+        h /= 2;
+    }
+    return total;
+}
+
+/* Scale space (Sec. 2; Sec. 3.1 "smoothing and half-sampling"): levels
+ * 0..O-1 written back to back into `out`, level 0 being the frame itself. */
+int orc_pyramid(const uint8_t* img, int W, int H, int O, uint8_t* out)
+{
+    int ws[32], hs[32];
+    if (O < 1 || O > 32) return -1;
+    orc_level_dims(W, H, O, ws, hs);
+    memcpy(out, img, (size_t)W * H);
+    uint8_t* prev = out;
+    for (int o = 1; o < O; ++o) {
+        uint8_t* cur = prev + (size_t)ws[o - 1] * hs[o - 1];
+        for (int y = 0; y < hs[o]; ++y) {
+            for (int x = 0; x < ws[o]; ++x) {
+                int pw = ws[o - 1];
+                int a = prev[(2 * y) * pw + 2 * x];
+                int b = prev[(2 * y) * pw + 2 * x + 1];
+                int c = prev[(2 * y + 1) * pw + 2 * x];
+                int d = prev[(2 * y + 1) * pw + 2 * x + 1];
+                cur[y * ws[o] + x] = (uint8_t)((a + b + c + d + 2) >> 2);
+            }
+        }
+        prev = cur;
+    }
+    return 0;
+}
+
+/* ----------------------------------------------------------- segment test */
+
+/* The 16 pixels of the radius-3 Bresenham circle in circular order,
+ * starting straight up and going clockwise (Sec. 2). */
+static const int RING[16][2] = {
+    {0, -3}, {1, -3}, {2, -2}, {3, -1}, {3, 0}, {3, 1}, {2, 2}, {1, 3},
+    {0, 3}, {-1, 3}, {-2, 2}, {-3, 1}, {-3, 0}, {-3, -1}, {-2, -2}, {-1, -3},
+};
+
+int orc_ring(int k, int* dx, int* dy)
+{
+    if (k < 0 || k > 15) return -1;
+    *dx = RING[k][0];
+    *dy = RING[k][1];
+    return 0;
+}
+
+/* Is there a run of 9 contiguous set bits on the 16-position circle? */
+int orc_arc9(unsigned mask)
+{
+    for (int s = 0; s < 16; ++s) {
+        int run = 1;
+        for (int j = 0; j < 9; ++j) {
+            if (!((mask >> ((s + j) % 16)) & 1u)) { run = 0; break; }
+        }
+        if (run) return 1;
+    }
+    return 0;
+}
+
+/* Segment test and score (R2, R3, R5) for one pixel of one level. */
+static int score_at(const uint8_t* L, int w, int h, int x, int y, int t)
+{
+    if (x < 3 || y < 3 || x >= w - 3 || y >= h - 3) return 0;
+    int p = L[y * w + x];
+    unsigned bright = 0, dark = 0;
+    int sum_bright = 0, sum_dark = 0;
+    for (int k = 0; k < 16; ++k) {
+        int c = L[(y + RING[k][1]) * w + (x + RING[k][0])];
+        if (c > p + t) { bright |= 1u << k; sum_bright += c - p - t; }
+        if (c < p - t) { dark |= 1u << k; sum_dark += p - c - t; }
+    }
+    if (!orc_arc9(bright) && !orc_arc9(dark)) return 0;
+    return sum_bright > sum_dark ? sum_bright : sum_dark;
+}
+
+/* Score map V of one level; V = 0 for pixels failing the segment test. */
+int orc_score_level(const uint8_t* L, int w, int h, int t, uint16_t* V)
+{
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x)
+            V[y * w + x] = (uint16_t)score_at(L, w, h, x, y, t);
+    return 0;
+}
+
+/* --------------------------------------------------- scale-space maxima */
+
+/* q = (oq, xq, yq, vq) beats p = (op, xp, yp, vp) under the total order of R4. */
+static int beats(int vq, int oq, int yq, int xq, int vp, int op, int yp, int xp)
+{
+    if (vq != vp) return vq > vp;
+    if (oq != op) return oq < op;
+    if (yq != yp) return yq < yp;
+    return xq < xp;
+}
+
+/* Full-frame detection F(I) (Sec. 2): pyramid, segment test and score on
+ * every level, non-maxima suppression in the scale-space neighbourhood.
+ * Output order: octave, then y, then x. Returns the count, or -1 when `cap`
+ * is too small, or -2 on bad arguments. */
+int orc_detect(const uint8_t* img, int W, int H, int t, int O, orc_kp* out, int cap)
+{
+    int ws[32], hs[32];
+    if (O < 1 || O > 32 || W < 1 || H < 1) return -2;
+    long total = orc_level_dims(W, H, O, ws, hs);
+    uint8_t* pyr = (uint8_t*)malloc((size_t)total);
+    uint16_t* V = (uint16_t*)malloc((size_t)total * sizeof(uint16_t));
+    long off[33];
+    off[0] = 0;
+    for (int o = 0; o < O; ++o) off[o + 1] = off[o] + (long)ws[o] * hs[o];
+    orc_pyramid(img, W, H, O, pyr);
+    for (int o = 0; o < O; ++o)
+        orc_score_level(pyr + off[o], ws[o], hs[o], t, V + off[o]);
+
+    int n = 0;
+    for (int o = 0; o < O; ++o) {
+        for (int y = 0; y < hs[o]; ++y) {
+            for (int x = 0; x < ws[o]; ++x) {
+                int v = V[off[o] + (long)y * ws[o] + x];
+                if (v == 0) continue;
+                int keep = 1;
+                /* in-plane 8-neighbourhood */
+                for (int dy = -1; dy <= 1 && keep; ++dy)
+                    for (int dx = -1; dx <= 1 && keep; ++dx) {
+                        int qx = x + dx, qy = y + dy;
+                        if ((dx == 0 && dy == 0) || qx < 0 || qy < 0 || qx >= ws[o] || qy >= hs[o]) continue;
+                        int vq = V[off[o] + (long)qy * ws[o] + qx];
+                        if (beats(vq, o, qy, qx, v, o, y, x)) keep = 0;
+                    }
+                /* finer octave o-1: 2x-1 <= x' <= 2x+2 */
+                if (o > 0)
+                    for (int qy = 2 * y - 1; qy <= 2 * y + 2 && keep; ++qy)
+                        for (int qx = 2 * x - 1; qx <= 2 * x + 2 && keep; ++qx) {
+                            if (qx < 0 || qy < 0 || qx >= ws[o - 1] || qy >= hs[o - 1]) continue;
+                            int vq = V[off[o - 1] + (long)qy * ws[o - 1] + qx];
+                            if (beats(vq, o - 1, qy, qx, v, o, y, x)) keep = 0;
+                        }
+                /* coarser octave o+1: 2X-1 <= x <= 2X+2 */
+                if (o + 1 < O)
+                    for (int qy = y / 2 - 2; qy <= y / 2 + 2 && keep; ++qy)
+                        for (int qx = x / 2 - 2; qx <= x / 2 + 2 && keep; ++qx) {
+                            if (!(2 * qx - 1 <= x && x <= 2 * qx + 2)) continue;
+                            if (!(2 * qy - 1 <= y && y <= 2 * qy + 2)) continue;
+                            if (qx < 0 || qy < 0 || qx >= ws[o + 1] || qy >= hs[o + 1]) continue;
+                            int vq = V[off[o + 1] + (long)qy * ws[o + 1] + qx];
+                            if (beats(vq, o + 1, qy, qx, v, o, y, x)) keep = 0;
+                        }
+                if (!keep) continue;
+                if (n >= cap) { free(pyr); free(V); return -1; }
+                out[n].x = x;
+                out[n].y = y;
+                out[n].octave = o;
+                out[n].score = v;
+                ++n;
+            }
+        }
+    }
+    free(pyr);
+    free(V);
+    return n;
+}
+
+/* ------------------------------------------------------------------ cells */
+
+static int cell_col(int X, int W, int Nc) { return (int)(((long)X * Nc) / W); }
+static int cell_row(int Y, int H, int Nr) { return (int)(((long)Y * Nr) / H); }
+
+/* Cell index (row-major) of a keypoint at level o (R6). */
+int orc_cell_of(int x, int y, int o, int W, int H, int Nc, int Nr)
+{
+    int X = x << o, Y = y << o;
+    return cell_row(Y, H, Nr) * Nc + cell_col(X, W, Nc);
+}
+
+/* ----------------------------------------------------------------- stream */
+
+typedef struct {
+    int W, H, O, Nc, Nr;
+    int t;
+    int32_t TI;
+    uint32_t TH;
+    int n_frames;
+    int force_all;
+    uint8_t* prev;       /* I_{n-1} */
+    orc_kp* K;           /* D_{n-1}, then D_n */
+    int nK;
+    int capK;
+    uint8_t* mask;       /* M_n per cell */
+    int64_t* sad;        /* per-cell summed |I_n - I_{n-1}| */
+    uint32_t* count;     /* per-cell keypoint count of D_n */
+} orc_stream;
+
+orc_stream* orc_open(int W, int H, int t, int O, int Nc, int Nr, int32_t TI, uint32_t TH)
+{
+    if (W < 1 || H < 1 || O < 1 || O > 32 || Nc < 1 || Nr < 1 || Nc > W || Nr > H) return NULL;
+    orc_stream* s = (orc_stream*)calloc(1, sizeof(orc_stream));
+    s->W = W; s->H = H; s->O = O; s->Nc = Nc; s->Nr = Nr;
+    s->t = t; s->TI = TI; s->TH = TH;
+    s->prev = (uint8_t*)malloc((size_t)W * H);
+    s->capK = W * H + 16;  /* no two keypoints of one level are 8-neighbours */
+    s->K = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)s->capK);
+    s->mask = (uint8_t*)calloc((size_t)Nc * Nr, 1);
+    s->sad = (int64_t*)calloc((size_t)Nc * Nr, sizeof(int64_t));
+    s->count = (uint32_t*)calloc((size_t)Nc * Nr, sizeof(uint32_t));
+    s->force_all = 1;
+    return s;
+}
+
+void orc_close(orc_stream* s)
+{
+    if (!s) return;
+    free(s->prev); free(s->K); free(s->mask); free(s->sad); free(s->count);
+    free(s);
+}
+
+/* A change of t changes every score, so the next frame re-detects every
+ * cell; T_I and T_H apply from the next frame on. */
+int orc_set_thresholds(orc_stream* s, int t, int32_t TI, uint32_t TH)
+{
+    if (t != s->t) s->force_all = 1;
+    s->t = t; s->TI = TI; s->TH = TH;
+    return 0;
+}
+
+static int kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr;
+
+static int kp_cmp(const void* a, const void* b)
+{
+    const orc_kp* p = (const orc_kp*)a;
+    const orc_kp* q = (const orc_kp*)b;
+    int cp = orc_cell_of(p->x, p->y, p->octave, kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr);
+    int cq = orc_cell_of(q->x, q->y, q->octave, kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr);
+    if (cp != cq) return cp < cq ? -1 : 1;
+    if (p->octave != q->octave) return p->octave < q->octave ? -1 : 1;
+    if (p->y != q->y) return p->y < q->y ? -1 : 1;
+    if (p->x != q->x) return p->x < q->x ? -1 : 1;
+    return 0;
+}
+
+/* One frame: detection mask (Eqs. 2-4 as read in R7), full detection F(I_n),
+ * and Eq. (1). */
+int orc_push(orc_stream* s, const uint8_t* frame)
+{
+    const int W = s->W, H = s->H, Nc = s->Nc, Nr = s->Nr;
+    const int ncell = Nc * Nr;
+
+    /* detection mask M_n */
+    if (s->force_all) {
+        for (int c = 0; c < ncell; ++c) { s->mask[c] = 1; s->sad[c] = 0; }
+    } else {
+        int64_t* area = (int64_t*)calloc((size_t)ncell, sizeof(int64_t));
+        uint32_t* hist = (uint32_t*)calloc((size_t)ncell, sizeof(uint32_t));
+        for (int c = 0; c < ncell; ++c) s->sad[c] = 0;
+        for (int Y = 0; Y < H; ++Y)
+            for (int X = 0; X < W; ++X) {
+                int c = cell_row(Y, H, Nr) * Nc + cell_col(X, W, Nc);
+                int d = (int)frame[Y * W + X] - (int)s->prev[Y * W + X];
+                s->sad[c] += d < 0 ? -d : d;
+                area[c] += 1;
+            }
+        /* Eq. (3): histogram of the previous feature set over the bins */
+        for (int i = 0; i < s->nK; ++i)
+            hist[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)] += 1;
+        for (int c = 0; c < ncell; ++c) {
+            int id = s->sad[c] > (int64_t)s->TI * area[c];   /* Eq. (2), R7 */
+            int kb = hist[c] >= s->TH;                         /* Eq. (4) */
+            s->mask[c] = (uint8_t)(id || kb);
+        }
+        free(area);
+        free(hist);
+    }
+
+    /* full-frame detection of I_n */
+    orc_kp* F = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)s->capK);
+    int nF = orc_detect(frame, W, H, s->t, s->O, F, s->capK);
+    if (nF < 0) { free(F); return -1; }
+
+    /* Eq. (1): new features in marked cells, previous ones in the others */
+    orc_kp* D = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)(nF + s->nK + 1));
+    int nD = 0;
+    for (int i = 0; i < nF; ++i)
+        if (s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)]) D[nD++] = F[i];
+    for (int i = 0; i < s->nK; ++i)
+        if (!s->mask[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)]) D[nD++] = s->K[i];
+    kp_cmp_ctx_W = W; kp_cmp_ctx_H = H; kp_cmp_ctx_Nc = Nc; kp_cmp_ctx_Nr = Nr;
+    qsort(D, (size_t)nD, sizeof(orc_kp), kp_cmp);
+    if (nD > s->capK) { free(F); free(D); return -1; }
+    memcpy(s->K, D, sizeof(orc_kp) * (size_t)nD);
+    s->nK = nD;
+    for (int c = 0; c < ncell; ++c) s->count[c] = 0;
+    for (int i = 0; i < nD; ++i)
+        s->count[orc_cell_of(D[i].x, D[i].y, D[i].octave, W, H, Nc, Nr)] += 1;
+    free(F);
+    free(D);
+
+    memcpy(s->prev, frame, (size_t)W * H);
+    s->force_all = 0;
+    s->n_frames += 1;
+    return nD;
+}
+
+/* Copy out D_n; mask, per-cell SAD and per-cell counts are optional. */
+int orc_get(orc_stream* s, orc_kp* out, int cap, uint8_t* mask, int64_t* sad, uint32_t* count)
+{
+    int ncell = s->Nc * s->Nr;
+    if (out) {
+        if (cap < s->nK) return -1;
+        memcpy(out, s->K, sizeof(orc_kp) * (size_t)s->nK);
+    }
+    if (mask) memcpy(mask, s->mask, (size_t)ncell);
+    if (sad) memcpy(sad, s->sad, sizeof(int64_t) * (size_t)ncell);
+    if (count) memcpy(count, s->count, sizeof(uint32_t) * (size_t)ncell);
+    return s->nK;
+}

@@ -1,0 +1,168 @@
+"""Definition-literal brute force for tiny images (pure Python, slow).
+
+Written independently of the oracle and structured differently on purpose,
+so that a mistake in one of them shows up as a disagreement:
+  * the ring is generated with the midpoint circle algorithm and ordered by
+    angle, not taken from a table;
+  * the contiguous-arc test searches a doubled bit string;
+  * scale-space neighbours are defined geometrically, by the Chebyshev
+    distance between pixel-footprint centres in level-0 units;
+  * cells come from numpy integer arithmetic on coordinate grids.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+
+def bresenham_ring(r: int = 3) -> List[Tuple[int, int]]:
+    """Radius-r Bresenham (midpoint) circle, ordered clockwise on screen
+    (y grows downwards) starting straight up."""
+    pts = set()
+    x, y, d = 0, r, 1 - r
+    while x <= y:
+        for sx in (1, -1):
+            for sy in (1, -1):
+                pts.add((sx * x, sy * y))
+                pts.add((sx * y, sy * x))
+        if d < 0:
+            d += 2 * x + 3
+        else:
+            d += 2 * (x - y) + 5
+            y -= 1
+        x += 1
+    return sorted(pts, key=lambda p: math.atan2(p[0], -p[1]) % (2 * math.pi))
+
+
+RING = bresenham_ring(3)
+
+
+def has_arc(bits: List[bool], n: int = 9) -> bool:
+    s = "".join("1" if b else "0" for b in bits)
+    return "1" * n in (s + s)
+
+
+def pyramid(img: np.ndarray, O: int) -> List[np.ndarray]:
+    levels = [img.astype(np.int64)]
+    for _ in range(1, O):
+        p = levels[-1]
+        h, w = p.shape[0] // 2, p.shape[1] // 2
+        q = p[:2 * h, :2 * w]
+        s = q[0::2, 0::2] + q[0::2, 1::2] + q[1::2, 0::2] + q[1::2, 1::2]
+        levels.append((s + 2) // 4)
+    return [lv.astype(np.uint8) for lv in levels]
+
+
+def score(level: np.ndarray, x: int, y: int, t: int) -> int:
+    h, w = level.shape
+    if not (3 <= x < w - 3 and 3 <= y < h - 3):
+        return 0
+    p = int(level[y, x])
+    ring = [int(level[y + dy, x + dx]) for dx, dy in RING]
+    bright = [c > p + t for c in ring]
+    dark = [c < p - t for c in ring]
+    if not (has_arc(bright) or has_arc(dark)):
+        return 0
+    sb = sum(c - p - t for c in ring if c > p + t)
+    sd = sum(p - c - t for c in ring if c < p - t)
+    return max(sb, sd)
+
+
+def footprint_centre(o: int, x: int, y: int) -> Tuple[float, float]:
+    s = 2 ** o
+    return ((x + 0.5) * s, (y + 0.5) * s)
+
+
+def are_neighbours(p: Tuple[int, int, int], q: Tuple[int, int, int]) -> bool:
+    """p, q = (octave, x, y). Same level: the 8-neighbourhood. Adjacent
+    levels: footprint centres within 3/4 of the coarser pixel's size in both
+    axes (equivalently, the 4x4 finer block around the coarser pixel)."""
+    (op, xp, yp), (oq, xq, yq) = p, q
+    if p == q or abs(op - oq) > 1:
+        return False
+    cp, cq = footprint_centre(*p), footprint_centre(*q)
+    dx, dy = abs(cp[0] - cq[0]), abs(cp[1] - cq[1])
+    if op == oq:
+        s = 2 ** op
+        return max(dx, dy) <= s
+    s = 2 ** max(op, oq)
+    return max(dx, dy) <= 0.75 * s
+
+
+def precedes(a: Tuple[int, int, int, int], b: Tuple[int, int, int, int]) -> bool:
+    """a, b = (V, octave, y, x); True when a ranks above b."""
+    return (-a[0], a[1], a[2], a[3]) < (-b[0], b[1], b[2], b[3])
+
+
+def detect(img: np.ndarray, t: int, O: int) -> List[Tuple[int, int, int, int]]:
+    """F(I) as tuples (x, y, octave, V) ordered by octave, y, x."""
+    levels = pyramid(img, O)
+    cands: Dict[Tuple[int, int, int], int] = {}
+    for o, lv in enumerate(levels):
+        h, w = lv.shape
+        for y in range(h):
+            for x in range(w):
+                v = score(lv, x, y, t)
+                if v > 0:
+                    cands[(o, x, y)] = v
+    out = []
+    for p, v in cands.items():
+        beaten = False
+        for q, vq in cands.items():
+            if are_neighbours(p, q) and precedes((vq, q[0], q[2], q[1]), (v, p[0], p[2], p[1])):
+                beaten = True
+                break
+        if not beaten:
+            out.append((p[1], p[2], p[0], v))
+    out.sort(key=lambda k: (k[2], k[1], k[0]))
+    return out
+
+
+def cell_grid(W: int, H: int, Nc: int, Nr: int) -> np.ndarray:
+    """Cell index of every level-0 pixel, [H, W]."""
+    cx = (np.arange(W, dtype=np.int64) * Nc) // W
+    cy = (np.arange(H, dtype=np.int64) * Nr) // H
+    return cy[:, None] * Nc + cx[None, :]
+
+
+def kp_cell(k, W: int, H: int, Nc: int, Nr: int) -> int:
+    x, y, o = k[0], k[1], k[2]
+    X, Y = x * 2 ** o, y * 2 ** o
+    return (Y * Nr // H) * Nc + (X * Nc // W)
+
+
+class Stream:
+    """Eq. (1) over a frame sequence, by brute force."""
+
+    def __init__(self, W, H, t, O, Nc, Nr, TI, TH=0xFFFFFFFF):
+        self.W, self.H, self.t, self.O, self.Nc, self.Nr = W, H, t, O, Nc, Nr
+        self.TI, self.TH = TI, TH
+        self.prev = None
+        self.K: List[Tuple[int, int, int, int]] = []
+        self.force = True
+        self.cells = cell_grid(W, H, Nc, Nr)
+
+    def push(self, frame: np.ndarray):
+        nc = self.Nc * self.Nr
+        if self.force:
+            mask = np.ones(nc, bool)
+        else:
+            diff = np.abs(frame.astype(np.int64) - self.prev.astype(np.int64))
+            sad = np.zeros(nc, np.int64)
+            np.add.at(sad, self.cells.ravel(), diff.ravel())
+            area = np.bincount(self.cells.ravel(), minlength=nc)
+            hist = np.zeros(nc, np.int64)
+            for k in self.K:
+                hist[kp_cell(k, self.W, self.H, self.Nc, self.Nr)] += 1
+            mask = (sad > self.TI * area) | (hist >= self.TH)
+        F = detect(frame, self.t, self.O)
+        cell = lambda k: kp_cell(k, self.W, self.H, self.Nc, self.Nr)
+        new = [k for k in F if mask[cell(k)]] + [k for k in self.K if not mask[cell(k)]]
+        new.sort(key=lambda k: (cell(k), k[2], k[1], k[0]))
+        self.K = new
+        self.mask = mask.astype(np.uint8)
+        self.prev = frame.copy()
+        self.force = False
+        return new

@@ -1,0 +1,444 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test ties one part of the oracle to something other than itself:
+brute force written independently (tests/bruteforce.py), closed forms,
+exhaustive enumeration, invariants and metamorphic relations. A plausible
+mistake (wrong ring order, off-by-one arc length, a dropped -t term, a wrong
+rounding in the pyramid, a transposed neighbourhood, an inverted mask
+polarity) fails at least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import oracle
+
+KB_OFF = 0xFFFFFFFF
+
+
+def kps_tuples(arr):
+    return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
+
+
+# ---------------------------------------------------------------- segment test
+
+def test_ring_is_the_radius3_bresenham_circle_in_circular_order():
+    # Sec. 2: the AST samples the Bresenham circle of radius 3.
+    assert oracle.ring() == bf.RING
+    assert len(set(bf.RING)) == 16
+
+
+def test_arc9_exhaustive_over_all_16bit_masks():
+    # Sec. 2: n contiguous ring pixels; n = 9 of 16. All 65536 bright masks.
+    for m in range(1 << 16):
+        bits = [(m >> k) & 1 == 1 for k in range(16)]
+        assert oracle.arc9(m) == bf.has_arc(bits, 9), hex(m)
+
+
+def test_arc9_boundaries():
+    assert oracle.arc9(0x01FF)          # exactly 9 from position 0
+    assert not oracle.arc9(0x00FF)      # 8 is not enough
+    assert oracle.arc9(0xF01F)          # 9 wrapping through position 15 -> 0
+    assert not oracle.arc9(0xF00F)      # 8 wrapping
+    assert not oracle.arc9(0x5555)
+
+
+def _ring_image(p, ring_vals, size=9):
+    img = np.full((size, size), p, np.uint8)
+    c = size // 2
+    for (dx, dy), v in zip(bf.RING, ring_vals):
+        img[c + dy, c + dx] = v
+    return img, c
+
+
+@pytest.mark.parametrize("t", [1, 20, 55])
+def test_score_hand_computed_cases(t):
+    # 9 contiguous ring pixels exactly p+t+10, the rest equal to p: V = 9*10.
+    p = 100
+    vals = [p + t + 10] * 9 + [p] * 7
+    img, c = _ring_image(p, vals)
+    V = oracle.score_level(img, t)
+    assert V[c, c] == 90
+    # 8 contiguous bright only: not a corner.
+    vals = [p + t + 10] * 8 + [p] * 8
+    img, c = _ring_image(p, vals)
+    assert oracle.score_level(img, t)[c, c] == 0
+    # strictness: 9 pixels at exactly p+t are not brighter than p+t.
+    vals = [p + t] * 9 + [p] * 7
+    img, c = _ring_image(p, vals)
+    assert oracle.score_level(img, t)[c, c] == 0
+    # dark arc of 10, plus 2 isolated bright pixels: V = max(sum bright, sum dark)
+    vals = [p - t - 7] * 10 + [p, p + t + 3, p, p + t + 5, p, p]
+    img, c = _ring_image(p, vals)
+    assert oracle.score_level(img, t)[c, c] == max(10 * 7, 3 + 5)
+
+
+def test_score_extremes():
+    # darkest possible: p=255, all ring 0, t=1 -> 16 * 254 = 4064 (fits u16).
+    img, c = _ring_image(255, [0] * 16)
+    assert oracle.score_level(img, 1)[c, c] == 4064
+    img, c = _ring_image(0, [255] * 16)
+    assert oracle.score_level(img, 1)[c, c] == 4064
+
+
+def test_score_matches_bruteforce_random():
+    rng = np.random.default_rng(7)
+    for trial in range(6):
+        img = rng.integers(0, 256, size=(20, 23), dtype=np.uint8)
+        for t in (5, 30, 80):
+            V = oracle.score_level(img, t)
+            for y in range(20):
+                for x in range(23):
+                    assert V[y, x] == bf.score(img, x, y, t), (trial, t, x, y)
+
+
+def test_candidate_scores_are_in_range():
+    rng = np.random.default_rng(8)
+    img = rng.integers(0, 256, size=(64, 64), dtype=np.uint8)
+    for t in (1, 10, 40):
+        V = oracle.score_level(img, t).astype(np.int64)
+        nz = V[V > 0]
+        assert nz.size > 0
+        assert nz.min() >= 9 and nz.max() <= 4064
+        # border rows/columns never score (3-pixel ring)
+        assert not V[:3].any() and not V[-3:].any() and not V[:, :3].any() and not V[:, -3:].any()
+
+
+# --------------------------------------------------------------------- pyramid
+
+def test_pyramid_matches_numpy_blocks_and_odd_sizes():
+    rng = np.random.default_rng(3)
+    for (h, w) in [(37, 53), (64, 64), (135, 121), (8, 9)]:
+        img = rng.integers(0, 256, size=(h, w), dtype=np.uint8)
+        O = 4 if min(h, w) >= 16 else 3
+        got = oracle.pyramid(img, O)
+        ref = bf.pyramid(img, O)
+        assert [g.shape for g in got] == [r.shape for r in ref]
+        for g, r in zip(got, ref):
+            np.testing.assert_array_equal(g, r)
+
+
+def test_pyramid_block_constant_closed_form():
+    # an image constant on aligned 2^(O-1) blocks keeps its block values exactly
+    rng = np.random.default_rng(4)
+    blocks = rng.integers(0, 256, size=(5, 7), dtype=np.uint8)
+    O = 4
+    img = np.kron(blocks, np.ones((8, 8), np.uint8))
+    lv = oracle.pyramid(img, O)
+    for o in range(O):
+        s = 8 >> o
+        np.testing.assert_array_equal(lv[o], np.kron(blocks, np.ones((s, s), np.uint8)))
+
+
+def test_pyramid_round_half_up():
+    img = np.array([[0, 1], [0, 1]], np.uint8)       # mean 0.5 -> 1
+    assert oracle.pyramid(img, 2)[1][0, 0] == 1
+    img = np.array([[0, 1], [0, 0]], np.uint8)       # mean 0.25 -> 0
+    assert oracle.pyramid(img, 2)[1][0, 0] == 0
+    img = np.array([[255, 255], [255, 254]], np.uint8)  # 254.75 -> 255
+    assert oracle.pyramid(img, 2)[1][0, 0] == 255
+    img = np.array([[1, 2], [2, 1]], np.uint8)       # 1.5 -> 2
+    assert oracle.pyramid(img, 2)[1][0, 0] == 2
+
+
+# --------------------------------------------------------- detection and NMS
+
+def test_neighbourhood_relation_geometric_equals_index_form():
+    # the geometric relation used by the brute force is the index-range form
+    for o in range(1, 3):
+        for x in range(0, 8):
+            for xf in range(0, 20):
+                geo = bf.are_neighbours((o, x, 5), (o - 1, xf, 2 * 5))
+                idx = 2 * x - 1 <= xf <= 2 * x + 2
+                assert geo == idx
+                # symmetry
+                assert bf.are_neighbours((o - 1, xf, 10), (o, x, 5)) == geo
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_detect_matches_bruteforce_random(seed):
+    rng = np.random.default_rng(100 + seed)
+    h, w = int(rng.integers(14, 34)), int(rng.integers(14, 34))
+    # few grey levels -> many equal scores, exercising every tie-break
+    img = rng.choice(np.array([0, 60, 120, 200, 255], np.uint8), size=(h, w))
+    for O in (1, 2, 3):
+        for t in (10, 50):
+            assert kps_tuples(oracle.detect(img, t, O)) == bf.detect(img, t, O), (O, t)
+
+
+def test_detect_matches_bruteforce_smooth_scene():
+    from paper_1503_06959_amd import synth
+    sc = synth.Scene(48, 40, 2, 4, 6, 14, 0.5, 2.0, False, 77)
+    frames = synth.make_video(sc)
+    for f in frames:
+        for O in (1, 2, 3):
+            assert kps_tuples(oracle.detect(f, 12, O)) == bf.detect(f, 12, O)
+
+
+@pytest.mark.parametrize("t", [1, 20, 254])
+@pytest.mark.parametrize("O", [1, 3, 5])
+def test_constant_frame_has_no_keypoints(t, O):
+    for v in (0, 77, 255):
+        img = np.full((96, 128), v, np.uint8)
+        assert len(oracle.detect(img, t, O)) == 0
+
+
+@pytest.mark.parametrize("O,side,x0,y0", [
+    (1, 8, 6, 9), (1, 9, 11, 5), (1, 12, 7, 7), (1, 20, 10, 10),
+    (2, 12, 8, 8), (2, 16, 10, 12), (2, 24, 14, 6),
+    (3, 24, 16, 8), (3, 32, 8, 16), (3, 40, 12, 20), (3, 48, 8, 8),
+])
+def test_bright_square_gives_exactly_its_four_corners(O, side, x0, y0):
+    # Closed form: at a corner pixel of a noiseless square the ring holds 11
+    # contiguous pixels of the other intensity, so V = 11 * (delta - t); edge
+    # pixels next to it score 10 or 9 times, and coarser octaves tie and lose.
+    a, b, t = 40, 190, 30
+    img = np.full((y0 + side + 30, x0 + side + 30), a, np.uint8)
+    img[y0:y0 + side, x0:x0 + side] = b
+    got = kps_tuples(oracle.detect(img, t, O))
+    x1, y1 = x0 + side - 1, y0 + side - 1
+    v = 11 * (b - a - t)
+    assert got == [(x0, y0, 0, v), (x1, y0, 0, v), (x0, y1, 0, v), (x1, y1, 0, v)]
+
+
+def test_square_corner_neighbour_scores_closed_form():
+    a, b, t = 40, 190, 30
+    img = np.full((40, 40), a, np.uint8)
+    img[10:30, 10:30] = b
+    V = oracle.score_level(img, t)
+    d = b - a - t
+    assert V[10, 10] == 11 * d
+    assert V[10, 11] == 10 * d and V[11, 10] == 10 * d   # one step along an edge
+    assert V[10, 12] == 9 * d                             # two steps: 9-arc, still a corner
+    assert V[10, 13] == 0                                 # straight edge: 7 darker pixels only
+    assert V[9, 9] == 0                                   # outside the corner: 5 brighter pixels
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_nms_invariants_on_scene(seed):
+    from paper_1503_06959_amd import synth
+    sc = synth.Scene(160, 120, 1, 10, 10, 40, 0.5, 2.0, False, 300 + seed)
+    img = synth.make_video(sc)[0]
+    O, t = 3, 20
+    F = kps_tuples(oracle.detect(img, t, O))
+    assert len(F) > 0
+    levels = oracle.pyramid(img, O)
+    V = [oracle.score_level(lv, t) for lv in levels]
+    kp = {(k[2], k[0], k[1]) for k in F}
+    for k in F:
+        assert V[k[2]][k[1], k[0]] == k[3] > 0
+    # every candidate is either output or beaten by a neighbour (and outputs are not)
+    for o in range(O):
+        ys, xs = np.nonzero(V[o])
+        for y, x in zip(ys, xs):
+            p = (o, int(x), int(y))
+            v = int(V[o][y, x])
+            beaten = False
+            for oq in (o - 1, o, o + 1):
+                if oq < 0 or oq >= O:
+                    continue
+                s = 2.0 ** (oq - o)
+                cx, cy = (x + 0.5) / s, (y + 0.5) / s
+                for yq in range(int(cy) - 3, int(cy) + 4):
+                    for xq in range(int(cx) - 3, int(cx) + 4):
+                        if not (0 <= yq < V[oq].shape[0] and 0 <= xq < V[oq].shape[1]):
+                            continue
+                        q = (oq, xq, yq)
+                        if bf.are_neighbours(p, q) and bf.precedes(
+                                (int(V[oq][yq, xq]), oq, yq, xq), (v, o, int(y), int(x))):
+                            beaten = True
+            assert beaten == (p not in kp), p
+    # no two keypoints are neighbours
+    kl = sorted(kp)
+    for i, p in enumerate(kl):
+        for q in kl[i + 1:]:
+            assert not bf.are_neighbours(p, q)
+
+
+def test_translation_by_coarsest_pixel_translates_keypoints():
+    # shifting the content by a multiple of 2^(O-1) keeps every pyramid level
+    # aligned, so F translates exactly (content kept away from the borders)
+    from paper_1503_06959_amd import synth
+    O = 3
+    sc = synth.Scene(64, 64, 1, 5, 8, 20, 0.0, 2.0, False, 55)
+    content = synth.make_video(sc)[0]
+    canvas = np.full((160, 160), 128, np.uint8)
+    canvas[24:88, 32:96] = content
+    F0 = kps_tuples(oracle.detect(canvas, 20, O))
+    for sx, sy in [(4, 0), (0, 8), (12, 16), (-8, 4)]:
+        shifted = np.full_like(canvas, 128)
+        shifted[24 + sy:88 + sy, 32 + sx:96 + sx] = content
+        F1 = kps_tuples(oracle.detect(shifted, 20, O))
+        exp = sorted([(x + (sx >> o), y + (sy >> o), o, v) for (x, y, o, v) in F0],
+                     key=lambda k: (k[2], k[1], k[0]))
+        assert F1 == exp
+
+
+# ------------------------------------------------------------ mask and Eq. (1)
+
+def test_cells_of_keypoints():
+    W, H, Nc, Nr = 320, 240, 8, 6
+    for (x, y, o) in [(0, 0, 0), (39, 39, 0), (40, 0, 0), (19, 19, 1), (20, 20, 1), (9, 9, 2), (10, 10, 2),
+                      (319, 239, 0), (79, 59, 2)]:
+        assert oracle.cell_of(x, y, o, W, H, Nc, Nr) == bf.kp_cell((x, y, o), W, H, Nc, Nr)
+    # uneven division: cell = floor(X * Nc / W)
+    assert oracle.cell_of(99, 0, 0, 100, 10, 3, 1) == 2
+    assert oracle.cell_of(33, 0, 0, 100, 10, 3, 1) == 0
+    assert oracle.cell_of(34, 0, 0, 100, 10, 3, 1) == 1
+
+
+def _scene(seed=21, frames=6, w=96, h=72, pan=False, move=0.5):
+    from paper_1503_06959_amd import synth
+    return synth.make_video(synth.Scene(w, h, frames, 6, 8, 24, move, 2.0, pan, seed))
+
+
+@pytest.mark.parametrize("TI,TH", [(8, KB_OFF), (3, KB_OFF), (255, 2), (6, 3), (0, KB_OFF)])
+def test_stream_matches_bruteforce(TI, TH):
+    frames = _scene()
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    b = bf.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    for f in frames:
+        s.push(f)
+        exp = b.push(f)
+        kps, mask, sad, cnt = s.get()
+        assert kps_tuples(kps) == exp
+        np.testing.assert_array_equal(mask, b.mask)
+        assert cnt.sum() == len(exp)
+
+
+def test_stream_sad_is_block_sum():
+    frames = _scene(seed=5, frames=3)
+    W, H, Nc, Nr = 96, 72, 5, 3   # uneven cells
+    s = oracle.Stream(W, H, 20, 2, Nc, Nr, 4)
+    s.push(frames[0])
+    s.push(frames[1])
+    _, _, sad, _ = s.get()
+    cells = bf.cell_grid(W, H, Nc, Nr)
+    d = np.abs(frames[1].astype(np.int64) - frames[0].astype(np.int64))
+    exp = np.array([d[cells == c].sum() for c in range(Nc * Nr)])
+    np.testing.assert_array_equal(sad, exp)
+
+
+def test_first_frame_and_all_ones_mask_give_full_detection():
+    frames = _scene(seed=9)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, -1)
+    for f in frames:
+        s.push(f)
+        kps, mask, _, _ = s.get()
+        assert mask.all()
+        F = kps_tuples(oracle.detect(f, t, O))
+        key = lambda k: (bf.kp_cell(k, W, H, Nc, Nr), k[2], k[1], k[0])
+        assert kps_tuples(kps) == sorted(F, key=key)
+
+
+def test_unchanged_frame_reproduces_previous_set():
+    frames = _scene(seed=10)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    for TI, TH in [(0, KB_OFF), (8, KB_OFF), (255, 1), (2, 4)]:
+        s = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+        s.push(frames[0])
+        s.push(frames[1])
+        k1, _, _, _ = s.get()
+        s.push(frames[1])
+        k2, mask, sad, _ = s.get()
+        assert not sad.any()
+        assert kps_tuples(k2) == kps_tuples(k1)
+
+
+def test_marked_cells_redetect_unmarked_cells_carry():
+    frames = _scene(seed=11, frames=8, move=1.0)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, 3)
+    prev = None
+    for f in frames:
+        s.push(f)
+        kps, mask, _, _ = s.get()
+        cur = kps_tuples(kps)
+        F = kps_tuples(oracle.detect(f, t, O))
+        cell = lambda k: bf.kp_cell(k, W, H, Nc, Nr)
+        for c in range(Nc * Nr):
+            mine = [k for k in cur if cell(k) == c]
+            if mask[c]:
+                assert mine == [k for k in F if cell(k) == c]
+            else:
+                assert mine == [k for k in prev if cell(k) == c]
+        prev = cur
+
+
+def test_mask_polarity_marks_changed_cells():
+    # Eq. (2) as printed marks unchanged pixels; the text asks for the
+    # changed ones. A cell whose pixels all change by 20 must be marked at
+    # T_I = 8 and a cell with no change must not.
+    W, H = 64, 32
+    f0 = np.full((H, W), 100, np.uint8)
+    f1 = f0.copy()
+    f1[:, :32] = 120
+    s = oracle.Stream(W, H, 20, 1, 2, 1, 8)
+    s.push(f0)
+    s.push(f1)
+    _, mask, sad, _ = s.get()
+    assert list(mask) == [1, 0]
+    assert sad[0] == 20 * 32 * 32 and sad[1] == 0
+    # the threshold is strict: a mean difference equal to T_I does not mark
+    s = oracle.Stream(W, H, 20, 1, 2, 1, 20)
+    s.push(f0)
+    s.push(f1)
+    assert list(s.get()[1]) == [0, 0]
+
+
+def test_keypoint_binning_threshold_is_inclusive():
+    # Eq. (4): a bin is marked when its count is >= T_H.
+    a, b, t = 40, 190, 30
+    img = np.full((64, 64), a, np.uint8)
+    img[8:24, 8:24] = b          # 4 corners, all in cell 0 of a 2x2 grid
+    s = oracle.Stream(64, 64, t, 1, 2, 2, 255, 4)
+    s.push(img)
+    s.push(img)
+    assert list(s.get()[1]) == [1, 0, 0, 0]
+    s = oracle.Stream(64, 64, t, 1, 2, 2, 255, 5)
+    s.push(img)
+    s.push(img)
+    assert list(s.get()[1]) == [0, 0, 0, 0]
+
+
+def test_threshold_change_forces_full_redetection():
+    frames = _scene(seed=12)
+    W, H, O, Nc, Nr = 96, 72, 3, 6, 4
+    s = oracle.Stream(W, H, 15, O, Nc, Nr, 255)
+    s.push(frames[0])
+    s.push(frames[1])
+    assert not s.get()[1].any()
+    s.set_thresholds(25, 255)
+    s.push(frames[2])
+    kps, mask, _, _ = s.get()
+    assert mask.all()
+    F = kps_tuples(oracle.detect(frames[2], 25, O))
+    assert sorted(kps_tuples(kps)) == sorted(F)
+    s.set_thresholds(25, 200)        # T_I change only: not forced
+    s.push(frames[3])
+    assert not s.get()[1].any()
+
+
+# ------------------------------------------------------ stored regression values
+
+@pytest.mark.parametrize("name,det", [
+    ("c1_320x240_first4.txt", (30, 3, 8, 6, 8, KB_OFF)),
+    ("c1_320x240_kb2_first4.txt", (30, 3, 8, 6, 255, 2)),
+])
+def test_oracle_reproduces_stored_fixture(name, det):
+    from golden_io import read_stream_fixture
+    from paper_1503_06959_amd import synth
+    exp = read_stream_fixture(name)
+    sc = synth.SCENES["c1_320x240"]
+    frames = synth.make_video(sc, len(exp))
+    t, O, Nc, Nr, TI, TH = det
+    s = oracle.Stream(sc.width, sc.height, t, O, Nc, Nr, TI, TH)
+    for f, (mask_bits, kps) in zip(frames, exp):
+        s.push(f)
+        got, mask, _, _ = s.get()
+        assert "".join(str(int(m)) for m in mask) == mask_bits
+        assert kps_tuples(got) == kps
