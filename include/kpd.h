@@ -1,0 +1,162 @@
+/*
+ * kpd.h — C ABI of the MI355X (gfx950) masked multi-scale keypoint detector
+ * for video.
+ *
+ * The library implements the detection path of Baroffio et al., "Fast
+ * keypoint detection in video sequences" (arXiv:1503.06959):
+ *   - each frame I_n (Sec. 3) is split into an N_r x N_c grid of cells, the
+ *     bins of Sec. 3.2;
+ *   - a cell is marked for detection when its mean absolute frame-to-frame
+ *     difference exceeds T_I (Sec. 3.1, Eq. 2, with the polarity the text
+ *     describes: detect where the frame changes) or when the previous frame
+ *     left at least T_H keypoints in it (Sec. 3.2, Eqs. 3-4); the two tests
+ *     are OR-ed;
+ *   - in marked cells the FAST-9/16 segment test (Sec. 2, AST on the radius-3
+ *     Bresenham circle, threshold t) runs on every octave of a 2x2-box
+ *     pyramid (Sec. 2, Sec. 3.1), scores candidates with the FAST score
+ *     V = max(sum of (c - p - t) over brighter ring pixels, sum of
+ *     (p - c - t) over darker ones), and keeps the maxima of a 3x3
+ *     scale-space neighbourhood (Sec. 2);
+ *   - unmarked cells carry their previous keypoints forward (Sec. 3, Eq. 1).
+ *
+ * Memory and streams. The caller owns all device memory: it allocates one
+ * device arena per stream of at least stream_bytes() bytes (e.g. a torch
+ * uint8 tensor) and keeps it alive until close_stream(). The library never
+ * allocates or frees device memory. Work is enqueued on the caller's HIP
+ * stream (hipStream_t passed as void*; NULL = the default stream).
+ * Processes that also use PyTorch must load PyTorch first, so that both use
+ * one HIP runtime.
+ *
+ * Errors. Every call returns 0 (KPD_OK) or a negative KPD_E* code; a
+ * thread-local message is available from kpd_last_error(). No C++ exception
+ * crosses the ABI. One handle must not be used from two threads at once.
+ */
+#ifndef KPD_H
+#define KPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KPD_OK 0
+#define KPD_EINVAL (-1)   /* bad parameters, sizes, pitch or flags */
+#define KPD_ENOMEM (-2)   /* arena smaller than stream_bytes() */
+#define KPD_EDEVICE (-3)  /* a HIP call failed; see kpd_last_error() */
+#define KPD_ETRUNC (-4)   /* output capacity too small; *count holds the need */
+#define KPD_ESTATE (-5)   /* call out of order (get before push, closed handle) */
+
+#define KPD_KB_OFF 0xFFFFFFFFu  /* kb_thresh value that switches binning off */
+#define KPD_MAX_OCTAVES 8
+#define KPD_MAX_CELL 128        /* largest cell side, in level-0 pixels */
+#define KPD_MAX_DIM 16384       /* largest frame side */
+
+/* push_frame flags */
+#define KPD_FRAME_HOST 0          /* host pointer; copied into the arena */
+#define KPD_FRAME_DEVICE 1        /* device pointer; copied into the arena */
+#define KPD_FRAME_DEVICE_RETAIN 2 /* device pointer used in place (no copy) */
+
+/* Detector and mask parameters.
+ *   fast_t     AST threshold t (Sec. 2), 1..254.
+ *   n_octaves  number of pyramid levels O, counting level 0; 1..KPD_MAX_OCTAVES,
+ *              with (width >> (O-1)) >= 1 and (height >> (O-1)) >= 1.
+ *   grid_cols, grid_rows
+ *              N_c x N_r cell grid (Sec. 3.2). Level-0 pixel (X,Y) lies in
+ *              cell (floor(X*N_c/W), floor(Y*N_r/H)); every cell side must be
+ *              at most KPD_MAX_CELL pixels.
+ *   id_thresh  T_I: a cell is marked when its summed |I_n - I_{n-1}| exceeds
+ *              T_I times its pixel count. Negative: every cell is marked
+ *              (full-frame detection); >= 255: the test never fires.
+ *   kb_thresh  T_H: a cell is marked when D_{n-1} has >= T_H keypoints in it
+ *              (Eq. 4). 0: every cell is marked; KPD_KB_OFF: never fires. */
+typedef struct kpd_params {
+    int32_t fast_t;
+    int32_t n_octaves;
+    int32_t grid_cols;
+    int32_t grid_rows;
+    int32_t id_thresh;
+    uint32_t kb_thresh;
+} kpd_params;
+
+/* One feature of D_n (Sec. 3: position and scale; the integer part).
+ * x, y are coordinates at level `octave`; the level-0 footprint starts at
+ * (x << octave, y << octave), and that point decides the keypoint's cell.
+ * score is the FAST score V (9..4064). */
+typedef struct kpd_keypoint {
+    uint16_t x;
+    uint16_t y;
+    uint8_t octave;
+    uint8_t pad;
+    uint16_t score;
+} kpd_keypoint;
+
+typedef struct kpd_stream kpd_stream;
+
+/* Device arena bytes a stream of this shape needs; 0 when the parameters are
+ * invalid. Pure host computation. */
+size_t stream_bytes(int width, int height, const kpd_params* params);
+
+/* Open a video stream (Sec. 3: the sequence I_0, I_1, ...). `dev_arena` is a
+ * device pointer to `arena_bytes` bytes owned by the caller, 256-byte
+ * aligned. `hip_stream` is the hipStream_t all work goes to. O and the grid
+ * are fixed for the stream's life. Returns KPD_EINVAL for bad parameters,
+ * KPD_ENOMEM when arena_bytes < stream_bytes(). */
+int open_stream(int width, int height, const kpd_params* params, void* dev_arena,
+                size_t arena_bytes, void* hip_stream, kpd_stream** out);
+
+/* Change t, T_I and T_H from the next pushed frame on. A change of t re-marks
+ * every cell of the next frame, since carried scores depend on t. */
+int set_thresholds(kpd_stream* s, int32_t fast_t, int32_t id_thresh, uint32_t kb_thresh);
+
+/* Process the next frame I_n (uint8 grey, width x height, rows `pitch_bytes`
+ * apart, pitch >= width). Asynchronous: enqueues the mask, pyramid,
+ * detection and output kernels and returns. Flags:
+ *   KPD_FRAME_HOST           `frame` is host memory, copied into the arena;
+ *                            it must stay valid until the stream has
+ *                            synchronised (get_keypoints does).
+ *   KPD_FRAME_DEVICE         `frame` is device memory, copied into the arena.
+ *   KPD_FRAME_DEVICE_RETAIN  `frame` is device memory read in place; it must
+ *                            stay valid and unchanged until the work of the
+ *                            NEXT push_frame has completed (it is I_{n-1}
+ *                            then). The pitch must stay the same. */
+int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
+
+/* Wait for the last pushed frame and copy D_n to host memory `out`, ordered
+ * by cell (row-major), then octave, then y, then x. `*count` receives the
+ * number of keypoints; when it exceeds `capacity`, nothing is copied and
+ * KPD_ETRUNC is returned. `cell_mask` (nullable, N_r*N_c bytes, row-major)
+ * receives M_n (1 = detected this frame, 0 = carried). KPD_ESTATE before the
+ * first push. */
+int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* count,
+                  uint8_t* cell_mask);
+
+/* Release the handle (waits for its queued work). The arena may be freed
+ * afterwards. */
+int close_stream(kpd_stream* s);
+
+/* Message of the last failing call on this thread ("" when none). */
+const char* kpd_last_error(void);
+
+/* ------------------------------------------------------- inspection calls */
+
+/* Device-resident result of the last frame: pointer to the D_n list and to
+ * its uint32 length, valid until the next push_frame. Does not synchronise. */
+int kpd_device_result(kpd_stream* s, const kpd_keypoint** d_list, const uint32_t** d_count);
+
+/* Wait and copy per-cell statistics of the last frame: the summed absolute
+ * level-0 difference (uint32 per cell; meaningful only on frames whose mask
+ * was computed from data, i.e. not the first frame, not after a change of t,
+ * and not with T_I < 0 or T_H == 0) and the per-cell keypoint count of D_n.
+ * Either pointer may be NULL. */
+int kpd_cell_stats(kpd_stream* s, uint32_t* sad, uint32_t* counts);
+
+/* Wait and copy pyramid level o (1 <= o < O) of the last frame into `out`
+ * ((width >> o) x (height >> o) bytes, row-major, no padding). */
+int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPD_H */

@@ -1,0 +1,200 @@
+"""Python binding of the gfx950 keypoint-detection library (include/kpd.h).
+
+Argument marshalling only: every step of the detection path runs in the HIP
+kernels of ``libkpd.so``. PyTorch supplies device memory (one uint8 arena
+tensor per stream) and HIP streams. ``torch`` is imported before the library
+is loaded so that both use the same HIP runtime.
+
+The functions carry the C names: ``stream_bytes``, ``open_stream``,
+``set_thresholds``, ``push_frame``, ``get_keypoints``, ``close_stream``, plus
+the inspection calls ``cell_stats``, ``pyramid_level`` and ``device_result``.
+``Stream`` wraps them for one video stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading libkpd.so: one HIP runtime)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkpd.so")
+
+KPD_OK, KPD_EINVAL, KPD_ENOMEM, KPD_EDEVICE, KPD_ETRUNC, KPD_ESTATE = 0, -1, -2, -3, -4, -5
+KPD_KB_OFF = 0xFFFFFFFF
+FRAME_HOST, FRAME_DEVICE, FRAME_DEVICE_RETAIN = 0, 1, 2
+
+KEYPOINT_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2")])
+EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_keypoints",
+            "close_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats", "kpd_pyramid_level")
+
+
+class KpdParams(ctypes.Structure):
+    _fields_ = [("fast_t", ctypes.c_int32), ("n_octaves", ctypes.c_int32),
+                ("grid_cols", ctypes.c_int32), ("grid_rows", ctypes.c_int32),
+                ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32)]
+
+
+class KpdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"kpd error {code}: {msg}")
+        self.code = code
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1503_06959_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, sz = ctypes.c_void_p, ctypes.c_size_t
+    i32, u32 = ctypes.c_int32, ctypes.c_uint32
+    L.stream_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams)]
+    L.stream_bytes.restype = sz
+    L.open_stream.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), P, sz, P,
+                              ctypes.POINTER(P)]
+    L.set_thresholds.argtypes = [P, i32, i32, u32]
+    L.push_frame.argtypes = [P, P, sz, ctypes.c_int]
+    L.get_keypoints.argtypes = [P, P, sz, ctypes.POINTER(sz), P]
+    L.close_stream.argtypes = [P]
+    L.kpd_last_error.argtypes = []
+    L.kpd_last_error.restype = ctypes.c_char_p
+    L.kpd_device_result.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P)]
+    L.kpd_cell_stats.argtypes = [P, P, P]
+    L.kpd_pyramid_level.argtypes = [P, ctypes.c_int, P]
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int) -> int:
+    if rc != KPD_OK:
+        raise KpdError(rc, lib.kpd_last_error().decode())
+    return rc
+
+
+def make_params(fast_t: int, n_octaves: int, grid_cols: int, grid_rows: int,
+                id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF) -> KpdParams:
+    return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF)
+
+
+def stream_bytes(width: int, height: int, params: KpdParams) -> int:
+    n = lib.stream_bytes(width, height, ctypes.byref(params))
+    if n == 0:
+        raise KpdError(KPD_EINVAL, lib.kpd_last_error().decode())
+    return n
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def open_stream(width: int, height: int, params: KpdParams, arena: torch.Tensor, stream=None) -> int:
+    if arena.device.type != "cuda" or arena.dtype != torch.uint8 or not arena.is_contiguous():
+        raise ValueError("arena must be a contiguous uint8 CUDA tensor")
+    h = ctypes.c_void_p()
+    _check(lib.open_stream(width, height, ctypes.byref(params), arena.data_ptr(), arena.numel(),
+                           _stream_ptr(stream), ctypes.byref(h)))
+    return h.value
+
+
+def set_thresholds(handle: int, fast_t: int, id_thresh: int, kb_thresh: int = KPD_KB_OFF) -> None:
+    _check(lib.set_thresholds(handle, fast_t, id_thresh, kb_thresh & 0xFFFFFFFF))
+
+
+def push_frame(handle: int, frame, retain: bool = False) -> None:
+    """frame: numpy uint8 [H, W] (host, copied) or a CUDA uint8 tensor
+    [H, W] with unit column stride (copied, or read in place when `retain`)."""
+    if isinstance(frame, np.ndarray):
+        if frame.dtype != np.uint8 or frame.ndim != 2 or frame.strides[1] != 1:
+            raise ValueError("host frame must be a uint8 [H, W] array with unit column stride")
+        _check(lib.push_frame(handle, frame.ctypes.data, frame.strides[0], FRAME_HOST))
+        return
+    if not (isinstance(frame, torch.Tensor) and frame.device.type == "cuda" and frame.dtype == torch.uint8
+            and frame.dim() == 2 and frame.stride(1) == 1):
+        raise ValueError("device frame must be a CUDA uint8 [H, W] tensor with unit column stride")
+    _check(lib.push_frame(handle, frame.data_ptr(), frame.stride(0),
+                          FRAME_DEVICE_RETAIN if retain else FRAME_DEVICE))
+
+
+def get_keypoints(handle: int, n_cells: int, capacity: int = 4096) -> Tuple[np.ndarray, np.ndarray]:
+    """D_n as a structured array (x, y, octave, pad, score), and M_n."""
+    mask = np.zeros(n_cells, np.uint8)
+    out = np.zeros(max(capacity, 1), KEYPOINT_DTYPE)
+    cnt = ctypes.c_size_t()
+    rc = lib.get_keypoints(handle, out.ctypes.data, len(out), ctypes.byref(cnt), mask.ctypes.data)
+    if rc == KPD_ETRUNC:
+        out = np.zeros(cnt.value, KEYPOINT_DTYPE)
+        rc = lib.get_keypoints(handle, out.ctypes.data, len(out), ctypes.byref(cnt), mask.ctypes.data)
+    _check(rc)
+    return out[:cnt.value].copy(), mask
+
+
+def close_stream(handle: int) -> None:
+    _check(lib.close_stream(handle))
+
+
+def cell_stats(handle: int, n_cells: int) -> Tuple[np.ndarray, np.ndarray]:
+    sad = np.zeros(n_cells, np.uint32)
+    cnt = np.zeros(n_cells, np.uint32)
+    _check(lib.kpd_cell_stats(handle, sad.ctypes.data, cnt.ctypes.data))
+    return sad, cnt
+
+
+def pyramid_level(handle: int, octave: int, width: int, height: int) -> np.ndarray:
+    out = np.zeros((height >> octave, width >> octave), np.uint8)
+    _check(lib.kpd_pyramid_level(handle, octave, out.ctypes.data))
+    return out
+
+
+def device_result(handle: int) -> Tuple[int, int]:
+    lst, cnt = ctypes.c_void_p(), ctypes.c_void_p()
+    _check(lib.kpd_device_result(handle, ctypes.byref(lst), ctypes.byref(cnt)))
+    return lst.value, cnt.value
+
+
+class Stream:
+    """One video stream: owns its device arena and keeps retained frames alive."""
+
+    def __init__(self, width: int, height: int, params: KpdParams, stream=None, device="cuda"):
+        self.width, self.height, self.params = width, height, params
+        self.n_cells = params.grid_cols * params.grid_rows
+        self.nbytes = stream_bytes(width, height, params)
+        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        self.handle = open_stream(width, height, params, self.arena, stream)
+        self._held = [None, None]
+
+    def push(self, frame, retain: bool = False) -> None:
+        push_frame(self.handle, frame, retain)
+        if retain:
+            self._held = [self._held[1], frame]
+
+    def set_thresholds(self, fast_t: int, id_thresh: int, kb_thresh: int = KPD_KB_OFF) -> None:
+        set_thresholds(self.handle, fast_t, id_thresh, kb_thresh)
+
+    def keypoints(self) -> Tuple[np.ndarray, np.ndarray]:
+        return get_keypoints(self.handle, self.n_cells)
+
+    def cell_stats(self):
+        return cell_stats(self.handle, self.n_cells)
+
+    def level(self, octave: int) -> np.ndarray:
+        return pyramid_level(self.handle, octave, self.width, self.height)
+
+    def close(self) -> None:
+        if self.handle:
+            close_stream(self.handle)
+            self.handle = None
+            self._held = [None, None]
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

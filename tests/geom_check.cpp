@@ -1,0 +1,88 @@
+// Exhaustive host check of the library's cell geometry (compiled with g++ by
+// tests/test_abi_cpu.py). For one frame shape it verifies that
+//   1. the cells' decision boxes partition the detectable interior of every
+//      level, each pixel going to the cell of its footprint start (x<<o, y<<o);
+//   2. every scale-space neighbour read by a decision (8 in-plane pixels, the
+//      finer 4x4 block, the coarser 2x2 block) that lies in the detectable
+//      interior of its level is inside that level's score box;
+//   3. score boxes stay inside the detectable interior, so the ring of every
+//      scored pixel is inside the level.
+// Prints "ok <max_lds_bytes> <store_capacity>" or the first violation.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "../paper_1503_06959_amd/csrc/kpd_geom.h"
+
+using kpd::Box;
+
+static bool inside(const Box& b, int x, int y) { return x >= b.x0 && x < b.x1 && y >= b.y0 && y < b.y1; }
+
+int main(int argc, char** argv)
+{
+    if (argc != 6) { fprintf(stderr, "usage: W H O Nc Nr\n"); return 2; }
+    const int W = atoi(argv[1]), H = atoi(argv[2]), O = atoi(argv[3]), Nc = atoi(argv[4]), Nr = atoi(argv[5]);
+    int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];
+    for (int o = 0; o < O; ++o) { w[o] = W >> o; h[o] = H >> o; }
+    const int ncell = Nc * Nr;
+    std::vector<Box> dec((size_t)ncell * O), sb((size_t)ncell * O);
+    long cap = 0;
+    int lds = 0;
+    for (int c = 0; c < ncell; ++c) {
+        Box r = kpd::cell_rect(c, W, H, Nc, Nr);
+        for (int o = 0; o < O; ++o) dec[(size_t)c * O + o] = kpd::decision_box(r, o, w[o], h[o]);
+        for (int o = 0; o < O; ++o) {
+            sb[(size_t)c * O + o] = kpd::score_box(&dec[(size_t)c * O], o, O, w[o], h[o]);
+            cap += kpd::decision_capacity(dec[(size_t)c * O + o]);
+            const Box& s = sb[(size_t)c * O + o];
+            if (!kpd::box_empty(s) && (s.x0 < 3 || s.y0 < 3 || s.x1 > w[o] - 3 || s.y1 > h[o] - 3)) {
+                printf("score box outside interior c=%d o=%d\n", c, o);
+                return 1;
+            }
+        }
+        lds = kpd::imax(lds, kpd::cell_lds_bytes(&sb[(size_t)c * O], O));
+    }
+    auto interior = [&](int o, int x, int y) { return x >= 3 && y >= 3 && x < w[o] - 3 && y < h[o] - 3; };
+    for (int o = 0; o < O; ++o) {
+        for (int y = 3; y < h[o] - 3; ++y) {
+            for (int x = 3; x < w[o] - 3; ++x) {
+                const long X = (long)x << o, Y = (long)y << o;
+                const int owner = (int)((Y * Nr) / H) * Nc + (int)((X * Nc) / W);
+                int hits = 0;
+                for (int c = 0; c < ncell; ++c)
+                    if (inside(dec[(size_t)c * O + o], x, y)) {
+                        ++hits;
+                        if (c != owner) { printf("pixel o=%d (%d,%d) in cell %d, owner %d\n", o, x, y, c, owner); return 1; }
+                    }
+                if (hits != 1) { printf("pixel o=%d (%d,%d) in %d decision boxes\n", o, x, y, hits); return 1; }
+                const Box* S = &sb[(size_t)owner * O];
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx)
+                        if (interior(o, x + dx, y + dy) && !inside(S[o], x + dx, y + dy)) {
+                            printf("in-plane neighbour missing o=%d (%d,%d)\n", o, x, y);
+                            return 1;
+                        }
+                if (o > 0)
+                    for (int yy = 2 * y - 1; yy <= 2 * y + 2; ++yy)
+                        for (int xx = 2 * x - 1; xx <= 2 * x + 2; ++xx)
+                            if (interior(o - 1, xx, yy) && !inside(S[o - 1], xx, yy)) {
+                                printf("finer neighbour missing o=%d (%d,%d)\n", o, x, y);
+                                return 1;
+                            }
+                if (o + 1 < O)
+                    for (int YY = kpd::imax(0, y / 2 - 2); YY <= kpd::imin(h[o + 1] - 1, y / 2 + 2); ++YY) {
+                        if (!(2 * YY - 1 <= y && y <= 2 * YY + 2)) continue;
+                        for (int XX = kpd::imax(0, x / 2 - 2); XX <= kpd::imin(w[o + 1] - 1, x / 2 + 2); ++XX) {
+                            if (!(2 * XX - 1 <= x && x <= 2 * XX + 2)) continue;
+                            if (interior(o + 1, XX, YY) && !inside(S[o + 1], XX, YY)) {
+                                printf("coarser neighbour missing o=%d (%d,%d)\n", o, x, y);
+                                return 1;
+                            }
+                        }
+                    }
+            }
+        }
+    }
+    printf("ok %d %ld\n", lds, cap);
+    return 0;
+}
