@@ -1,0 +1,328 @@
+#!/usr/bin/env python3
+"""Throughput and latency of masked vs full-frame keypoint detection on one GPU.
+
+One step = one pass of the whole detection path (cell mask, pyramid,
+segment test + score + scale-space suppression, compaction, Eq. (1) output)
+over every frame of one synthetic video, frames already resident in HBM and
+pushed through the C ABI in place (no copy). The headline workload is the
+640x480, 300-frame single stream (FAST-9 t=20, 4 octaves, 16x12 cells,
+T_I = 8); the same line also carries the full-frame rate of that workload,
+the 1920x1080 single-stream rates, per-frame latency percentiles, the
+dominant kernel's roofline and the CPU oracle's rate on a bounded sample.
+
+Prints one JSON line on stdout. Usage:
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-hd]
+  python bench.py --copy-calibration MiB   (plain device copy, for counter scaling)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "masked-detect Mpixel/s & frames/s vs full-frame at 1 GPU; p50/p99 frame latency"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2_640x480")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hd", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
+    return ap.parse_args()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def level_sizes(W, H, O):
+    return [(W >> o) * (H >> o) for o in range(O)]
+
+
+class Workload:
+    def __init__(self, name: str):
+        import torch
+        from paper_1503_06959_amd import synth
+        self.name = name
+        self.sc = synth.SCENES[name]
+        self.det = synth.DETECTORS[name]
+        t0 = time.time()
+        self.frames = synth.make_video(self.sc)
+        log(f"[bench] generated {name}: {self.frames.shape} in {time.time() - t0:.1f}s")
+        self.dev = torch.from_numpy(self.frames).cuda()
+        self.F, self.H, self.W = self.frames.shape
+        self.ncell = self.det.grid_cols * self.det.grid_rows
+
+    def describe(self, id_thresh):
+        d = self.det
+        return (f"{self.name}: 1 stream, {self.F} frames {self.W}x{self.H} u8, FAST-9/16 t={d.fast_t}, "
+                f"{d.n_octaves} octaves, {d.grid_cols}x{d.grid_rows} cells, "
+                + ("full-frame (T_I<0)" if id_thresh < 0 else f"T_I={id_thresh}, T_H off"))
+
+
+def open_stream(wl: Workload, id_thresh: int):
+    from paper_1503_06959_amd import kpd
+    d = wl.det
+    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh)
+    return kpd.Stream(wl.W, wl.H, params)
+
+
+def one_pass(kpd, s, wl: Workload) -> None:
+    """Push every frame of the video in place; results stay on the device."""
+    kpd.reset_stream(s.handle)
+    h, dev, pitch = s.handle, wl.dev, wl.W
+    push = kpd.lib.push_frame
+    for i in range(wl.F):
+        rc = push(h, dev[i].data_ptr(), pitch, kpd.FRAME_DEVICE_RETAIN)
+        if rc:
+            raise kpd.KpdError(rc, kpd.lib.kpd_last_error().decode())
+
+
+def timed_passes(kpd, s, wl: Workload, steps: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        one_pass(kpd, s, wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_pass(kpd, s, wl)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def latency_pass(kpd, s, wl: Workload):
+    """Per-frame latency push -> keypoints on the host; also collects what
+    the algorithmic byte counts need (marked cells, keypoints in them)."""
+    import numpy as np
+    d = wl.det
+    kpd.reset_stream(s.handle)
+    lat, marked, new_kp, total_kp = [], [], [], []
+    for i in range(wl.F):
+        t0 = time.perf_counter()
+        kpd.push_frame(s.handle, wl.dev[i], retain=True)
+        k, m = s.keypoints()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        cell = ((k["y"].astype(np.int64) << k["octave"]) * d.grid_rows // wl.H) * d.grid_cols + \
+               ((k["x"].astype(np.int64) << k["octave"]) * d.grid_cols // wl.W)
+        marked.append(int(m.sum()))
+        new_kp.append(int(m[cell].sum()) if len(k) else 0)
+        total_kp.append(len(k))
+    lat = np.array(lat)
+    return {
+        "lat_p50": float(np.percentile(lat, 50)), "lat_p99": float(np.percentile(lat, 99)),
+        "marked": marked, "new_kp": new_kp, "total_kp": total_kp,
+    }
+
+
+def kernel_profile(kpd, s, wl: Workload, steps: int):
+    import numpy as np
+    kpd.profile(s.handle, True)
+    kpd.profile_read(s.handle)
+    for _ in range(steps):
+        one_pass(kpd, s, wl)
+    ms, n = kpd.profile_read(s.handle)
+    kpd.profile(s.handle, False)
+    return {name: (float(ms[k]), int(n[k])) for k, name in enumerate(kpd.KERNEL_NAMES)}
+
+
+def algorithmic_bytes(wl: Workload, st, masked: bool) -> dict:
+    """Bytes the method must move per launch of each kernel, averaged over
+    the frames of one pass. k_frame reads I_n (and I_{n-1} for the
+    intensity-difference test) and writes the coarser octaves; k_detect reads
+    the octave pixels of the marked cells, writes their keypoints and copies
+    the carried ones (Eq. 1). Score maps are an LDS intermediate and count
+    nothing. Frame 0 of a pass marks every cell."""
+    d = wl.det
+    N = wl.W * wl.H
+    lv = level_sizes(wl.W, wl.H, d.n_octaves)
+    P = sum(lv[1:])
+    F = wl.F
+    sad_frames = (F - 1) if masked else 0
+    frac = [m / wl.ncell for m in st["marked"]]
+    carried = [t - n for t, n in zip(st["total_kp"], st["new_kp"])]
+    detect = sum(f * sum(lv) for f in frac) + 8 * sum(st["new_kp"]) + 16 * sum(carried) + 24 * wl.ncell * F
+    return {
+        "k_frame": N + P + N * sad_frames / F,
+        "k_detect": detect / F,
+    }
+
+
+def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True):
+    s = open_stream(wl, id_thresh)
+    sec = timed_passes(kpd, s, wl, args.steps, args.warmup)
+    res = {"sec_per_pass": sec, "frames": wl.F,
+           "mpix_per_s": wl.F * wl.W * wl.H / sec / 1e6, "frames_per_s": wl.F / sec}
+    if want_latency:
+        res.update(latency_pass(kpd, s, wl))
+    if want_profile:
+        res["kernels"] = kernel_profile(kpd, s, wl, max(1, args.steps // 2))
+    s.close()
+    return res
+
+
+def roofline_of(wl: Workload, res, masked: bool, traffic=None):
+    """Dominant kernel by summed event-timed duration; achieved = algorithmic
+    bytes per launch / average launch duration."""
+    ab = algorithmic_bytes(wl, res, masked)
+    kern = res["kernels"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms, n = kern[dom]
+    avg_s = ms / 1e3 / max(n, 1)
+    achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
+    return {
+        "kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+        "algorithmic_bytes_per_launch": int(ab[dom]), "avg_launch_us": round(avg_s * 1e6, 3),
+        "launches": n,
+        "per_kernel_avg_us": {k: round(v[0] * 1e3 / max(v[1], 1), 3) for k, v in kern.items()},
+    }
+
+
+def cpu_baseline(wl: Workload, seconds: float):
+    import oracle
+    d = wl.det
+    s = oracle.Stream(wl.W, wl.H, d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, d.id_thresh, d.kb_thresh)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        for i in range(wl.F):
+            s.push(wl.frames[i])
+            n += 1
+            if time.perf_counter() - t0 >= seconds and n >= 30:
+                break
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    s.close()
+    return {
+        "value": round(n * wl.W * wl.H / dt / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+        "sample": f"{n} frames of {wl.name} through the oracle stream (mask + full-frame detection + Eq. 1), "
+                  f"{dt:.1f}s, single thread, {cpu_model()}, {os.cpu_count()} host cores visible",
+        "frames_per_s": round(n / dt, 2),
+    }
+
+
+def copy_calibration(mib: int) -> None:
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters read on the detection kernels."""
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); streams shard across GPUs "
+              f"without communication, see the design notes", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    from paper_1503_06959_amd import kpd
+
+    wl = Workload(args.workload)
+    log("[bench] masked pass")
+    masked = run_workload(kpd, wl, wl.det.id_thresh, args)
+    log(f"[bench] masked {masked['mpix_per_s']:.1f} Mpx/s; full-frame pass")
+    full = run_workload(kpd, wl, -1, args)
+    log(f"[bench] full-frame {full['mpix_per_s']:.1f} Mpx/s")
+    skipped = 1.0 - sum(masked["marked"][1:]) / max(1, (wl.F - 1) * wl.ncell)
+
+    out = {
+        "metric": METRIC,
+        "value": round(masked["mpix_per_s"], 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(masked["sec_per_pass"] * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": wl.describe(wl.det.id_thresh), "frames_per_step": wl.F,
+                   "frame": f"{wl.W}x{wl.H}", "parallelism": "1 stream, 1 GPU"},
+        "frames_per_s": round(masked["frames_per_s"], 1),
+        "latency_ms": {"p50": round(masked["lat_p50"], 4), "p99": round(masked["lat_p99"], 4),
+                       "what": "push_frame -> get_keypoints returned on the host, one frame in flight"},
+        "skipped_cell_frac": round(skipped, 4),
+        "full_frame": {"value": round(full["mpix_per_s"], 2), "unit": "Mpixel/s",
+                       "frames_per_s": round(full["frames_per_s"], 1),
+                       "ms_per_step": round(full["sec_per_pass"] * 1e3, 4),
+                       "latency_ms": {"p50": round(full["lat_p50"], 4), "p99": round(full["lat_p99"], 4)},
+                       "roofline": roofline_of(wl, full, False)},
+        "masked_over_full": round(masked["mpix_per_s"] / full["mpix_per_s"], 3),
+        "roofline": roofline_of(wl, masked, True),
+    }
+    if not args.no_hd:
+        del wl
+        torch.cuda.empty_cache()
+        hd = Workload("c3_1920x1080")
+        log("[bench] 1080p masked pass")
+        hm = run_workload(kpd, hd, hd.det.id_thresh, args, want_latency=True)
+        log("[bench] 1080p full-frame pass")
+        hf = run_workload(kpd, hd, -1, args, want_latency=True)
+        lv = level_sizes(hd.W, hd.H, hd.det.n_octaves)
+        N, P = lv[0], sum(lv[1:])
+        kps = sum(hf["total_kp"]) / hd.F
+        b_full = N + 2 * P + 8 * kps
+        eff = b_full * hd.F / hf["sec_per_pass"] / 1e9
+        out["hd_1080p"] = {
+            "workload": hd.describe(hd.det.id_thresh),
+            "masked": {"value": round(hm["mpix_per_s"], 2), "unit": "Mpixel/s",
+                       "frames_per_s": round(hm["frames_per_s"], 1),
+                       "latency_ms": {"p50": round(hm["lat_p50"], 4), "p99": round(hm["lat_p99"], 4)},
+                       "roofline": roofline_of(hd, hm, True)},
+            "full_frame": {"value": round(hf["mpix_per_s"], 2), "unit": "Mpixel/s",
+                           "frames_per_s": round(hf["frames_per_s"], 1),
+                           "latency_ms": {"p50": round(hf["lat_p50"], 4), "p99": round(hf["lat_p99"], 4)},
+                           "effective_hbm_GBs": round(eff, 2),
+                           "effective_hbm_frac": round(eff / HBM_PEAK_GBS, 5),
+                           "algorithmic_bytes_per_frame": int(b_full),
+                           "roofline": roofline_of(hd, hf, False)},
+        }
+        wl = hd
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        from paper_1503_06959_amd import synth
+        base = Workload(args.workload) if wl.name != args.workload else wl
+        out["cpu_baseline"] = cpu_baseline(base, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -120,7 +120,7 @@ int set_thresholds(kpd_stream* s, int32_t fast_t, int32_t id_thresh, uint32_t kb
  *   KPD_FRAME_DEVICE_RETAIN  `frame` is device memory read in place; it must
  *                            stay valid and unchanged until the work of the
  *                            NEXT push_frame has completed (it is I_{n-1}
- *                            then). The pitch must stay the same. */
+ *                            then). */
 int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
 
 /* Wait for the last pushed frame and copy D_n to host memory `out`, ordered
@@ -135,6 +135,11 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
 /* Release the handle (waits for its queued work). The arena may be freed
  * afterwards. */
 int close_stream(kpd_stream* s);
+
+/* Forget the previous frame (e.g. at a scene cut): the next pushed frame is
+ * treated like the first frame of a stream, which has no I_{n-1} or D_{n-1}
+ * to build a mask from, and re-detects every cell. Does not synchronise. */
+int reset_stream(kpd_stream* s);
 
 /* Message of the last failing call on this thread ("" when none). */
 const char* kpd_last_error(void);
@@ -155,6 +160,25 @@ int kpd_cell_stats(kpd_stream* s, uint32_t* sad, uint32_t* counts);
 /* Wait and copy pyramid level o (1 <= o < O) of the last frame into `out`
  * ((width >> o) x (height >> o) bytes, row-major, no padding). */
 int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
+
+/* ------------------------------------------------------ kernel timing */
+
+/* Kernels of one frame, in launch order: the pyramid-and-SAD pass over
+ * level-0 tiles, and the per-cell detection and output pass. */
+#define KPD_K_FRAME 0
+#define KPD_K_DETECT 1
+#define KPD_NKERNELS 2
+
+/* Switch per-kernel GPU timing on (1) or off (0). While on, every kernel
+ * launch of this stream is bracketed by two HIP events recorded on the
+ * stream's HIP stream; the library creates the events on first use and keeps
+ * them until close_stream. */
+int kpd_profile(kpd_stream* s, int enable);
+
+/* Wait for the stream, then add up the event-timed durations since the last
+ * read: ms[k] receives the summed milliseconds of kernel k and launches[k]
+ * the number of launches (arrays of KPD_NKERNELS; either may be NULL). */
+int kpd_profile_read(kpd_stream* s, double* ms, uint64_t* launches);
 
 #ifdef __cplusplus
 }

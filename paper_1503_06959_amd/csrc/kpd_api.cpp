@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/kpd.h"
@@ -30,29 +31,34 @@ int hip_fail(hipError_t e, const char* what)
     return KPD_EDEVICE;
 }
 
-#define KPD_HIP(call)                                   \
-    do {                                                \
-        hipError_t e_ = (call);                         \
+#define KPD_HIP(call)                                     \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Byte layout of one stream's device arena.
+// Byte layout of one stream's device arena. Per-frame state that the next
+// frame reads (per-cell counts and offsets, the keypoint list D_n, the
+// per-cell SAD) is double-buffered and indexed by frame parity.
 struct Layout {
     int W = 0, H = 0, O = 0, nc = 0, nr = 0, ncell = 0;
     int w[KPD_MAX_OCTAVES] = {}, h[KPD_MAX_OCTAVES] = {}, pitch[KPD_MAX_OCTAVES] = {};
     int slot_pitch = 0;
-    int pyr_tile = 64;
+    int tile = 32;       // k_frame level-0 tile side
+    int sad_slots = 1;   // cells one k_frame tile can touch
     size_t off_hdr = 0, off_slot[2] = {0, 0}, off_lvl[KPD_MAX_OCTAVES] = {};
-    size_t off_sad = 0, off_count = 0, off_offsets = 0, off_base = 0, off_mask = 0;
-    size_t off_store = 0, off_out = 0;
-    size_t store_cap = 0;
-    int lds_bytes = 0;
+    size_t off_sad[2] = {0, 0}, off_count[2] = {0, 0}, off_offs[2] = {0, 0}, off_list[2] = {0, 0};
+    size_t off_mask = 0, off_status = 0, off_colw = 0, off_rowh = 0, off_layouts = 0;
+    size_t list_cap = 0;
+    int lds_bytes = 0;   // k_detect dynamic LDS
     size_t total = 0;
-    std::vector<uint32_t> base;  // per-cell slot start in the keypoint store, plus the end
 };
+
+// header words
+constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrTicket = 2, kHdrErr = 3;
 
 bool valid_params(int W, int H, const kpd_params* p, std::string* why)
 {
@@ -86,46 +92,89 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->pitch[o] = kpd::round_up(L->w[o], 64);
     }
     L->slot_pitch = kpd::round_up(W, 64);
-    L->pyr_tile = std::max(64, 1 << (L->O - 1));
+    L->tile = std::max(32, 1 << (L->O - 1));
 
-    // per-cell keypoint slots and the detection kernel's LDS need
-    L->base.assign(L->ncell + 1, 0);
+    // cells a k_frame tile can touch, per axis
+    auto span_max = [](int len, int n, int T) {
+        int m = 1;
+        for (int x0 = 0; x0 < len; x0 += T) {
+            const int x1 = std::min(x0 + T, len) - 1;
+            m = std::max(m, (int)(((int64_t)x1 * n) / len) - (int)(((int64_t)x0 * n) / len) + 1);
+        }
+        return m;
+    };
+    L->sad_slots = span_max(W, L->nc, L->tile) * span_max(H, L->nr, L->tile);
+    if (kpd::frame_lds_bytes(L->tile, L->O, L->sad_slots) > 65536) {
+        *why = "grid too fine for the pyramid tile";
+        return false;
+    }
+
+    // keypoint list capacity and the detection kernel's LDS need
     size_t cap = 0;
     int lds = 0;
     for (int c = 0; c < L->ncell; ++c) {
         const kpd::Box r = kpd::cell_rect(c, W, H, L->nc, L->nr);
-        kpd::Box dec[KPD_MAX_OCTAVES], sb[KPD_MAX_OCTAVES];
-        for (int o = 0; o < L->O; ++o) dec[o] = kpd::decision_box(r, o, L->w[o], L->h[o]);
-        for (int o = 0; o < L->O; ++o) sb[o] = kpd::score_box(dec, o, L->O, L->w[o], L->h[o]);
-        L->base[c] = (uint32_t)cap;
-        for (int o = 0; o < L->O; ++o) cap += kpd::decision_capacity(dec[o]);
-        lds = std::max(lds, kpd::cell_lds_bytes(sb, L->O));
-        if (cap > 0xFFFFFFF0ull) { *why = "keypoint store too large"; return false; }
+        kpd::CellLayout CL;
+        kpd::cell_layout(r, L->O, L->w, L->h, &CL);
+        for (int o = 0; o < L->O; ++o) cap += kpd::decision_capacity(CL.dec[o]);
+        lds = std::max(lds, CL.bytes);
+        // the detection kernel queues score-pixel indices as 16-bit values
+        if (CL.sc_start[L->O] > 65535) { *why = "cell too large"; return false; }
+        if (cap > 0xFFFFFFF0ull) { *why = "keypoint list too large"; return false; }
     }
-    L->base[L->ncell] = (uint32_t)cap;
-    L->store_cap = std::max<size_t>(cap, 1);
-    L->lds_bytes = kpd::detect_lds_bytes(lds);
+    L->list_cap = std::max<size_t>(cap, 1);
+    L->lds_bytes = std::max(lds, 16);
 
     size_t off = 0;
     L->off_hdr = off; off = align_up(off + 64);
     for (int k = 0; k < 2; ++k) { L->off_slot[k] = off; off = align_up(off + (size_t)L->slot_pitch * H); }
     for (int o = 1; o < L->O; ++o) { L->off_lvl[o] = off; off = align_up(off + (size_t)L->pitch[o] * L->h[o]); }
     const size_t nc4 = (size_t)L->ncell * 4;
-    L->off_sad = off; off = align_up(off + nc4);
-    L->off_count = off; off = align_up(off + nc4);
-    L->off_offsets = off; off = align_up(off + nc4);
-    L->off_base = off; off = align_up(off + nc4 + 4);
+    for (int k = 0; k < 2; ++k) { L->off_sad[k] = off; off = align_up(off + nc4); }
+    for (int k = 0; k < 2; ++k) { L->off_count[k] = off; off = align_up(off + nc4); }
+    for (int k = 0; k < 2; ++k) { L->off_offs[k] = off; off = align_up(off + nc4); }
     L->off_mask = off; off = align_up(off + (size_t)L->ncell);
-    L->off_store = off; off = align_up(off + L->store_cap * sizeof(kpd_keypoint));
-    L->off_out = off; off = align_up(off + L->store_cap * sizeof(kpd_keypoint));
+    L->off_status = off; off = align_up(off + (size_t)L->ncell * 8);
+    L->off_colw = off; off = align_up(off + (size_t)L->nc * 2);
+    L->off_rowh = off; off = align_up(off + (size_t)L->nr * 2);
+    L->off_layouts = off; off = align_up(off + (size_t)L->ncell * sizeof(kpd::CellLayout));
+    for (int k = 0; k < 2; ++k) {
+        L->off_list[k] = off;
+        off = align_up(off + L->list_cap * sizeof(kpd_keypoint));
+    }
     L->total = off;
     return true;
 }
+
+// Opt-in per-kernel timing with event pairs recorded around each launch.
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> free_events;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double ms[KPD_NKERNELS] = {};
+    uint64_t launches[KPD_NKERNELS] = {};
+
+    hipError_t take(hipEvent_t* e)
+    {
+        if (!free_events.empty()) {
+            *e = free_events.back();
+            free_events.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreate(e);
+    }
+    ~KernelTimer()
+    {
+        for (auto& p : pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
+        for (auto e : free_events) hipEventDestroy(e);
+    }
+};
 
 }  // namespace
 
 struct kpd_stream {
     Layout L;
+    KernelTimer timer;
     kpd_params p{};
     hipStream_t stream = nullptr;
     uint8_t* arena = nullptr;
@@ -134,11 +183,41 @@ struct kpd_stream {
     int cur_slot = 0;
     const uint8_t* prev0 = nullptr;
     int prev_pitch = 0;
+    int prev_dw = 0;
     bool closed = false;
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
 };
+
+namespace {
+
+// Launch one kernel of the frame, bracketed by events when timing is on.
+template <typename F>
+hipError_t timed(kpd_stream* s, int kernel, F&& launch)
+{
+    if (!s->timer.on) return launch();
+    hipEvent_t a, b;
+    hipError_t e = s->timer.take(&a);
+    if (e == hipSuccess) e = s->timer.take(&b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(a, s->stream);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+    s->timer.pending.push_back({kernel, {a, b}});
+    return e;
+}
+
+// A level-0 frame can be read a dword at a time when its base and pitch are
+// 4-byte aligned and no dword of a row reaches past the row's last byte
+// (width a multiple of 4), or when it is one of the arena's padded slots.
+int dword_readable(const void* p, int pitch, int width, bool slot)
+{
+    if (slot) return 1;
+    return (reinterpret_cast<uintptr_t>(p) % 4 == 0 && pitch % 4 == 0 && width % 4 == 0) ? 1 : 0;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -168,21 +247,49 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (arena_bytes < L.total)
         return fail(KPD_ENOMEM, "arena has " + std::to_string(arena_bytes) + " bytes, stream needs " +
                                     std::to_string(L.total));
-    // cells of at most KPD_MAX_CELL pixels need < 64 KiB of LDS per workgroup
-    if (L.lds_bytes > 65536) return fail(KPD_EINVAL, "cells need more LDS than a workgroup can hold");
+    int dev = 0, lds_max = 0;
+    KPD_HIP(hipGetDevice(&dev));
+    KPD_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (L.lds_bytes > std::max(lds_max, 65536))
+        return fail(KPD_EINVAL, "cells need more LDS than a workgroup can hold");
+    KPD_HIP(kpd::set_detect_lds_limit(L.lds_bytes));
 
     kpd_stream* s = new (std::nothrow) kpd_stream();
     if (!s) return fail(KPD_ENOMEM, "host allocation failed");
-    s->L = std::move(L);
+    s->L = L;
     s->p = *params;
     s->stream = reinterpret_cast<hipStream_t>(hip_stream);
     s->arena = reinterpret_cast<uint8_t*>(dev_arena);
 
-    // constant per-cell slot starts, and zeroed counters
-    hipError_t e = hipMemcpyAsync(s->at<uint32_t>(s->L.off_base), s->L.base.data(), s->L.base.size() * 4,
-                                  hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->arena + s->L.off_hdr, 0, 64, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->arena + s->L.off_count, 0, (size_t)s->L.ncell * 4, s->stream);
+    // zero the header, both SAD accumulators, the counts and the look-back words
+    hipError_t e = hipMemsetAsync(s->arena + L.off_hdr, 0, 64, s->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipMemsetAsync(s->arena + L.off_sad[k], 0, (size_t)L.ncell * 4, s->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipMemsetAsync(s->arena + L.off_count[k], 0, (size_t)L.ncell * 4, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_status, 0, (size_t)L.ncell * 8, s->stream);
+    // constant cell column widths and row heights
+    std::vector<uint16_t> colw(L.nc), rowh(L.nr);
+    for (int j = 0; j < L.nc; ++j) {
+        int a0, a1;
+        kpd::cell_span(j, L.nc, L.W, &a0, &a1);
+        colw[j] = (uint16_t)(a1 - a0);
+    }
+    for (int j = 0; j < L.nr; ++j) {
+        int a0, a1;
+        kpd::cell_span(j, L.nr, L.H, &a0, &a1);
+        rowh[j] = (uint16_t)(a1 - a0);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->arena + L.off_colw, colw.data(), colw.size() * 2, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->arena + L.off_rowh, rowh.data(), rowh.size() * 2, hipMemcpyHostToDevice, s->stream);
+    std::vector<kpd::CellLayout> layouts(L.ncell);
+    for (int c = 0; c < L.ncell; ++c)
+        kpd::cell_layout(kpd::cell_rect(c, L.W, L.H, L.nc, L.nr), L.O, L.w, L.h, &layouts[c]);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->arena + L.off_layouts, layouts.data(), layouts.size() * sizeof(kpd::CellLayout),
+                           hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         delete s;
@@ -214,9 +321,11 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
 
     const uint8_t* cur;
     int cur_pitch;
+    int cur_dw;
     if (flags == KPD_FRAME_DEVICE_RETAIN) {
         cur = frame;
         cur_pitch = (int)pitch_bytes;
+        cur_dw = dword_readable(cur, cur_pitch, L.W, false);
     } else {
         uint8_t* dst = s->at<uint8_t>(L.off_slot[s->cur_slot]);
         KPD_HIP(hipMemcpy2DAsync(dst, L.slot_pitch, frame, pitch_bytes, L.W, L.H,
@@ -224,63 +333,76 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
                                  s->stream));
         cur = dst;
         cur_pitch = L.slot_pitch;
+        cur_dw = 1;
         s->cur_slot ^= 1;
     }
 
+    const uint32_t n = (uint32_t)s->n_pushed;
+    const int cur_k = n & 1, prev_k = cur_k ^ 1;
     const bool all_marked = s->force_all || s->p.id_thresh < 0 || s->p.kb_thresh == 0;
-    if (!all_marked) {
-        kpd::MaskArgs m{};
-        m.cur = cur; m.prev = s->prev0;
-        m.cur_pitch = cur_pitch; m.prev_pitch = s->prev_pitch;
-        m.W = L.W; m.H = L.H; m.nc = L.nc; m.nr = L.nr;
-        m.id_on = s->p.id_thresh < 255;
-        m.id_thresh = s->p.id_thresh;
-        m.kb_thresh = s->p.kb_thresh;
-        m.count = s->at<uint32_t>(L.off_count);
-        m.sad = s->at<uint32_t>(L.off_sad);
-        m.mask = s->at<uint8_t>(L.off_mask);
-        KPD_HIP(kpd::launch_cell_mask(m, L.ncell, s->stream));
-    }
+    const bool sad_on = !all_marked && s->p.id_thresh < 255;
 
-    if (L.O > 1) {
-        kpd::PyrArgs pa{};
-        pa.lvl0 = cur; pa.pitch0 = cur_pitch;
+    if (L.O > 1 || sad_on) {
+        kpd::FrameArgs fa{};
+        fa.cur = cur;
+        fa.cur_pitch = cur_pitch;
+        fa.cur_aligned = cur_dw;
+        fa.prev = sad_on ? s->prev0 : cur;
+        fa.prev_pitch = sad_on ? s->prev_pitch : cur_pitch;
+        fa.prev_aligned = sad_on ? s->prev_dw : cur_dw;
         for (int o = 1; o < L.O; ++o) {
-            pa.lvl[o] = s->at<uint8_t>(L.off_lvl[o]);
-            pa.pitch[o] = L.pitch[o];
-            pa.w[o] = L.w[o];
-            pa.h[o] = L.h[o];
+            fa.lvl[o] = s->at<uint8_t>(L.off_lvl[o]);
+            fa.pitch[o] = L.pitch[o];
         }
-        pa.W = L.W; pa.H = L.H; pa.O = L.O; pa.tile = L.pyr_tile;
-        KPD_HIP(kpd::launch_pyramid(pa, s->stream));
+        for (int o = 0; o < L.O; ++o) { fa.w[o] = L.w[o]; fa.h[o] = L.h[o]; }
+        fa.W = L.W; fa.H = L.H; fa.O = L.O; fa.nc = L.nc; fa.nr = L.nr;
+        fa.tile = L.tile;
+        fa.sad_on = sad_on ? 1 : 0;
+        fa.sad_slots = L.sad_slots;
+        fa.sad_lds_off = kpd::frame_sad_lds_off(L.tile, L.O);
+        fa.sad = s->at<uint32_t>(L.off_sad[cur_k]);
+        KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(fa, s->stream); }));
     }
 
     kpd::DetectArgs d{};
-    d.lvl[0] = cur; d.pitch[0] = cur_pitch; d.w[0] = L.W; d.h[0] = L.H;
+    d.lvl[0] = cur;
+    d.pitch[0] = cur_pitch;
     for (int o = 1; o < L.O; ++o) {
         d.lvl[o] = s->at<uint8_t>(L.off_lvl[o]);
         d.pitch[o] = L.pitch[o];
-        d.w[o] = L.w[o];
-        d.h[o] = L.h[o];
     }
+    for (int o = 0; o < L.O; ++o) { d.w[o] = L.w[o]; d.h[o] = L.h[o]; }
+    d.lvl0_aligned = cur_dw;
     d.W = L.W; d.H = L.H; d.O = L.O; d.nc = L.nc; d.nr = L.nr;
     d.t = s->p.fast_t;
     d.all_marked = all_marked ? 1 : 0;
+    d.id_on = sad_on ? 1 : 0;
+    d.id_thresh = s->p.id_thresh;
+    d.kb_thresh = s->p.kb_thresh;
+    d.sad = s->at<uint32_t>(L.off_sad[cur_k]);
+    d.sad_next = s->at<uint32_t>(L.off_sad[prev_k]);
     d.mask = s->at<uint8_t>(L.off_mask);
-    d.count = s->at<uint32_t>(L.off_count);
-    d.offsets = s->at<uint32_t>(L.off_offsets);
-    d.store_base = s->at<uint32_t>(L.off_base);
-    d.store = s->at<kpd_keypoint>(L.off_store);
-    d.hdr = s->at<uint32_t>(L.off_hdr);
-    KPD_HIP(kpd::launch_detect(d, L.ncell, L.lds_bytes, s->stream));
-
-    kpd::GatherArgs g{};
-    g.count = d.count; g.offsets = d.offsets; g.store_base = d.store_base; g.store = d.store;
-    g.out = s->at<kpd_keypoint>(L.off_out);
-    KPD_HIP(kpd::launch_gather(g, L.ncell, s->stream));
+    d.count_prev = s->at<uint32_t>(L.off_count[prev_k]);
+    d.off_prev = s->at<uint32_t>(L.off_offs[prev_k]);
+    d.list_prev = s->at<kpd_keypoint>(L.off_list[prev_k]);
+    d.count_cur = s->at<uint32_t>(L.off_count[cur_k]);
+    d.off_cur = s->at<uint32_t>(L.off_offs[cur_k]);
+    d.list_cur = s->at<kpd_keypoint>(L.off_list[cur_k]);
+    d.total_cur = s->at<uint32_t>(L.off_hdr) + (cur_k ? kHdrTotal1 : kHdrTotal0);
+    d.list_cap = (uint32_t)L.list_cap;
+    d.layouts = s->at<kpd::CellLayout>(L.off_layouts);
+    d.col_w = s->at<uint16_t>(L.off_colw);
+    d.row_h = s->at<uint16_t>(L.off_rowh);
+    d.status = s->at<unsigned long long>(L.off_status);
+    d.epoch = n + 1;
+    d.ticket = s->at<uint32_t>(L.off_hdr) + kHdrTicket;
+    d.ticket_base = n * (uint32_t)L.ncell;
+    d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
+    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(d, L.ncell, L.lds_bytes, s->stream); }));
 
     s->prev0 = cur;
     s->prev_pitch = cur_pitch;
+    s->prev_dw = cur_dw;
     s->force_all = false;
     s->n_pushed += 1;
     return KPD_OK;
@@ -291,14 +413,19 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (!count) return fail(KPD_EINVAL, "count is NULL");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
-    uint32_t total = 0;
-    KPD_HIP(hipMemcpyAsync(&total, s->at<uint32_t>(s->L.off_hdr), 4, hipMemcpyDeviceToHost, s->stream));
+    const int k = (s->n_pushed - 1) & 1;
+    uint32_t hdr[4] = {0, 0, 0, 0};
+    KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(s->L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
+    if (hdr[kHdrErr])
+        return fail(KPD_EDEVICE, hdr[kHdrErr] == 1 ? "a cell-offset wait timed out on the device"
+                                                   : "cell ticket out of step on the device");
+    const uint32_t total = hdr[k ? kHdrTotal1 : kHdrTotal0];
     *count = total;
     if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
     if (total > 0) {
         if (!out) return fail(KPD_EINVAL, "out is NULL");
-        KPD_HIP(hipMemcpyAsync(out, s->at<kpd_keypoint>(s->L.off_out), (size_t)total * sizeof(kpd_keypoint),
+        KPD_HIP(hipMemcpyAsync(out, s->at<kpd_keypoint>(s->L.off_list[k]), (size_t)total * sizeof(kpd_keypoint),
                                hipMemcpyDeviceToHost, s->stream));
     }
     if (cell_mask)
@@ -318,11 +445,49 @@ int close_stream(kpd_stream* s)
     return KPD_OK;
 }
 
+int reset_stream(kpd_stream* s)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    s->force_all = true;
+    return KPD_OK;
+}
+
+int kpd_profile(kpd_stream* s, int enable)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    s->timer.on = enable != 0;
+    return KPD_OK;
+}
+
+int kpd_profile_read(kpd_stream* s, double* ms, uint64_t* launches)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    KPD_HIP(hipStreamSynchronize(s->stream));
+    for (auto& p : s->timer.pending) {
+        float t = 0.f;
+        KPD_HIP(hipEventElapsedTime(&t, p.second.first, p.second.second));
+        s->timer.ms[p.first] += t;
+        s->timer.launches[p.first] += 1;
+        s->timer.free_events.push_back(p.second.first);
+        s->timer.free_events.push_back(p.second.second);
+    }
+    s->timer.pending.clear();
+    for (int k = 0; k < KPD_NKERNELS; ++k) {
+        if (ms) ms[k] = s->timer.ms[k];
+        if (launches) launches[k] = s->timer.launches[k];
+        s->timer.ms[k] = 0;
+        s->timer.launches[k] = 0;
+    }
+    return KPD_OK;
+}
+
 int kpd_device_result(kpd_stream* s, const kpd_keypoint** d_list, const uint32_t** d_count)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
-    if (d_list) *d_list = s->at<kpd_keypoint>(s->L.off_out);
-    if (d_count) *d_count = s->at<uint32_t>(s->L.off_hdr);
+    if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
+    const int k = (s->n_pushed - 1) & 1;
+    if (d_list) *d_list = s->at<kpd_keypoint>(s->L.off_list[k]);
+    if (d_count) *d_count = s->at<uint32_t>(s->L.off_hdr) + (k ? kHdrTotal1 : kHdrTotal0);
     return KPD_OK;
 }
 
@@ -330,10 +495,11 @@ int kpd_cell_stats(kpd_stream* s, uint32_t* sad, uint32_t* counts)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
+    const int k = (s->n_pushed - 1) & 1;
     const size_t n = (size_t)s->L.ncell * 4;
-    if (sad) KPD_HIP(hipMemcpyAsync(sad, s->at<uint32_t>(s->L.off_sad), n, hipMemcpyDeviceToHost, s->stream));
+    if (sad) KPD_HIP(hipMemcpyAsync(sad, s->at<uint32_t>(s->L.off_sad[k]), n, hipMemcpyDeviceToHost, s->stream));
     if (counts)
-        KPD_HIP(hipMemcpyAsync(counts, s->at<uint32_t>(s->L.off_count), n, hipMemcpyDeviceToHost, s->stream));
+        KPD_HIP(hipMemcpyAsync(counts, s->at<uint32_t>(s->L.off_count[k]), n, hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
     return KPD_OK;
 }

@@ -110,20 +110,102 @@ KPD_HD int decision_capacity(const Box& d)
 
 KPD_HD int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
-// Bytes of LDS the detection kernel needs for one cell: one uint16 score map
-// per level over its score box (each padded to 4 bytes), plus one uint8
-// pixel tile reused across levels covering the largest score box plus the
-// 3-pixel ring apron.
-KPD_HD int cell_lds_bytes(const Box* sbox, int O)
+// Threads per workgroup of the detection kernel and its waves.
+constexpr int kDetectBlock = 512;
+constexpr int kDetectWaves = kDetectBlock / 64;
+// Entries of each wave's private queue of pixels awaiting the full segment
+// test (a power of two, at least twice the wave width).
+constexpr int kQueue = 128;
+
+// floor(i / d) = (i * magic) >> 32 for i * d < 2^32, with magic = ceil(2^32 / d)
+// kept in 64 bits: the error i * (magic - 2^32/d) / 2^32 < i / 2^32 < 1/d
+// cannot carry the quotient past an integer.
+KPD_HD uint64_t div_magic(unsigned d) { return (0x100000000ull + d - 1) / d; }
+
+// Everything one detection workgroup needs to know about its cell, computed
+// once per stream on the host: the decision and score boxes of every level
+// and where each level's pixel tile, score map and the bitmasks live in LDS.
+//
+// LDS layout (bytes): [keep bitmask: nwords x u64][candidate bitmask: nwords
+// x u64][word offsets: nwords x u32][wave queues: waves x kQueue x u16]
+// [score maps: u16 per level][pixel tiles: u8 per level]. A level's pixel
+// tile covers its score box plus the 3-pixel ring apron; its first column is
+// rounded down to a multiple of 4 and its row pitch up to one, so that
+// 4-byte aligned rows can be loaded a dword at a time.
+struct CellLayout {
+    uint64_t ldm[KPD_MAX_OCTAVES];       // div magics: tile dwords per row,
+    uint64_t scm[KPD_MAX_OCTAVES];       // score-box width,
+    uint64_t dcm[KPD_MAX_OCTAVES];       // decision-box width
+    Box dec[KPD_MAX_OCTAVES];
+    Box sb[KPD_MAX_OCTAVES];
+    int tx0[KPD_MAX_OCTAVES], ty0[KPD_MAX_OCTAVES];   // level coords of tile (0,0)
+    int tpitch[KPD_MAX_OCTAVES], th[KPD_MAX_OCTAVES];
+    int toff[KPD_MAX_OCTAVES], voff[KPD_MAX_OCTAVES];
+    int ld_start[KPD_MAX_OCTAVES + 1];   // flattened dword-load index of each level
+    int sc_start[KPD_MAX_OCTAVES + 1];   // flattened score index of each level
+    int dc_start[KPD_MAX_OCTAVES + 1];   // flattened decision index of each level
+    int O;
+    int nwords;                          // words of each bitmask
+    int cand_off, woff_off, queue_off;
+    int bytes;
+};
+
+KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, CellLayout* L)
 {
-    int scores = 0, tile = 0;
-    for (int o = 0; o < O; ++o) {
-        if (box_empty(sbox[o])) continue;
-        scores += round_up(box_w(sbox[o]) * box_h(sbox[o]) * 2, 4);
-        int t = (box_w(sbox[o]) + 2 * kRingR) * (box_h(sbox[o]) + 2 * kRingR);
-        tile = imax(tile, t);
+    L->O = O;
+    for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
+        L->dec[o] = Box{0, 0, 0, 0};
+        L->sb[o] = Box{0, 0, 0, 0};
+        L->tx0[o] = L->ty0[o] = L->tpitch[o] = L->th[o] = L->toff[o] = L->voff[o] = 0;
+        L->ldm[o] = L->scm[o] = L->dcm[o] = 0;
     }
-    return scores + round_up(tile, 4);
+    for (int o = 0; o < O; ++o) L->dec[o] = decision_box(rect, o, w[o], h[o]);
+    for (int o = 0; o < O; ++o) L->sb[o] = score_box(L->dec, o, O, w[o], h[o]);
+    int nd = 0;
+    for (int o = 0; o < O; ++o) {
+        L->dc_start[o] = nd;
+        if (!box_empty(L->dec[o])) nd += box_w(L->dec[o]) * box_h(L->dec[o]);
+    }
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) L->dc_start[o] = nd;
+    L->nwords = (nd + 63) / 64;
+    int off = 0;
+    off += L->nwords * 8;
+    L->cand_off = off;
+    off += L->nwords * 8;
+    L->woff_off = off;
+    off += round_up(L->nwords * 4, 8);
+    L->queue_off = off;
+    off += kDetectWaves * kQueue * 2;
+    int sc = 0;
+    for (int o = 0; o < O; ++o) {
+        L->voff[o] = off;
+        L->sc_start[o] = sc;
+        if (!box_empty(L->sb[o])) {
+            const int n = box_w(L->sb[o]) * box_h(L->sb[o]);
+            off += round_up(n * 2, 4);
+            sc += n;
+        }
+    }
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) L->sc_start[o] = sc;
+    int ld = 0;
+    for (int o = 0; o < O; ++o) {
+        L->ld_start[o] = ld;
+        L->toff[o] = off;
+        if (box_empty(L->sb[o])) continue;
+        L->tx0[o] = (L->sb[o].x0 - kRingR) & ~3;
+        L->ty0[o] = L->sb[o].y0 - kRingR;
+        L->tpitch[o] = round_up(L->sb[o].x1 + kRingR - L->tx0[o], 4);
+        L->th[o] = box_h(L->sb[o]) + 2 * kRingR;
+        off += L->tpitch[o] * L->th[o];
+        ld += (L->tpitch[o] / 4) * L->th[o];
+    }
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) L->ld_start[o] = ld;
+    for (int o = 0; o < O; ++o) {
+        L->ldm[o] = div_magic(imax(L->tpitch[o] / 4, 1));
+        L->scm[o] = div_magic(imax(box_w(L->sb[o]), 1));
+        L->dcm[o] = div_magic(imax(box_w(L->dec[o]), 1));
+    }
+    L->bytes = off;
 }
 
 }  // namespace kpd

@@ -5,59 +5,64 @@
 #include <stdint.h>
 
 #include "../../include/kpd.h"
+#include "kpd_geom.h"
 
 namespace kpd {
 
-struct MaskArgs {
+// k_frame: pyramid of I_n and, optionally, per-cell SAD against I_{n-1}.
+struct FrameArgs {
     const uint8_t* cur;   // I_n, level 0
-    const uint8_t* prev;  // I_{n-1}, level 0
+    const uint8_t* prev;  // I_{n-1}, level 0 (read when sad_on)
     int cur_pitch, prev_pitch;
-    int W, H, nc, nr;
-    int id_on;            // T_I < 255: the intensity test can fire
-    int32_t id_thresh;
-    uint32_t kb_thresh;
-    const uint32_t* count;  // per-cell counts of D_{n-1}
-    uint32_t* sad;
-    uint8_t* mask;
-};
-
-struct PyrArgs {
-    const uint8_t* lvl0;
-    int pitch0;
-    uint8_t* lvl[KPD_MAX_OCTAVES];
+    int cur_aligned, prev_aligned;  // base and pitch 4-byte aligned
+    uint8_t* lvl[KPD_MAX_OCTAVES];  // levels 1..O-1
     int pitch[KPD_MAX_OCTAVES];
     int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];
-    int W, H, O;
-    int tile;  // level-0 tile side (power of two, >= 2^(O-1), >= 64)
+    int W, H, O, nc, nr;
+    int tile;        // level-0 tile side: power of two, >= 2^(O-1), >= 32
+    int sad_on;
+    int sad_slots;   // LDS per-cell partial slots (cells a tile can touch)
+    int sad_lds_off;
+    uint32_t* sad;   // per-cell SAD, accumulated; zero on entry
 };
 
+// k_detect: per-cell mark, detection, look-back offsets and output.
 struct DetectArgs {
     const uint8_t* lvl[KPD_MAX_OCTAVES];
     int pitch[KPD_MAX_OCTAVES];
     int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];
+    int lvl0_aligned;
     int W, H, O, nc, nr;
     int t;
     int all_marked;
+    int id_on;
+    int32_t id_thresh;
+    uint32_t kb_thresh;
+    const uint32_t* sad;     // this frame's per-cell SAD
+    uint32_t* sad_next;      // zeroed here for the next frame
     uint8_t* mask;
-    uint32_t* count;
-    uint32_t* offsets;
-    const uint32_t* store_base;  // ncell + 1 entries
-    kpd_keypoint* store;
-    uint32_t* hdr;  // [0] total keypoints of D_n, [1] workgroup ticket
+    const uint32_t* count_prev;
+    const uint32_t* off_prev;
+    const kpd_keypoint* list_prev;
+    uint32_t* count_cur;
+    uint32_t* off_cur;
+    kpd_keypoint* list_cur;
+    uint32_t* total_cur;
+    uint32_t list_cap;           // entries of each keypoint list
+    const CellLayout* layouts;   // per-cell detection layout, computed at open
+    const uint16_t* col_w;       // cell column widths (level-0 pixels)
+    const uint16_t* row_h;       // cell row heights
+    unsigned long long* status;  // per-cell count words of marked cells
+    uint32_t epoch;              // frame number + 1
+    uint32_t* ticket;            // running workgroup counter
+    uint32_t ticket_base;        // its value when this launch started
+    uint32_t* err;               // set when a look-back wait gives up
 };
 
-struct GatherArgs {
-    const uint32_t* count;
-    const uint32_t* offsets;
-    const uint32_t* store_base;
-    const kpd_keypoint* store;
-    kpd_keypoint* out;
-};
-
-hipError_t launch_cell_mask(const MaskArgs& a, int ncell, hipStream_t s);
-hipError_t launch_pyramid(const PyrArgs& a, hipStream_t s);
+int frame_sad_lds_off(int tile, int O);
+int frame_lds_bytes(int tile, int O, int sad_slots);
+hipError_t launch_frame(const FrameArgs& a, hipStream_t s);
+hipError_t set_detect_lds_limit(int lds_bytes);
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s);
-hipError_t launch_gather(const GatherArgs& a, int ncell, hipStream_t s);
-int detect_lds_bytes(int lds_bytes);
 
 }  // namespace kpd

@@ -1,18 +1,23 @@
-// gfx950 kernels of the masked multi-scale FAST detector.
+// gfx950 kernels of the masked multi-scale FAST detector. Two launches per
+// frame, both on the caller's stream:
 //
-// Per frame, on the caller's stream:
-//   k_cell_mask   per-cell SAD of I_n vs I_{n-1} and the mark decision
-//                 (Sec. 3.1 Eq. 2 as a per-cell mean absolute difference;
-//                 Sec. 3.2 Eqs. 3-4 from the per-cell counts of D_{n-1});
-//   k_pyramid     octave pyramid by 2x2 box average, round half up (Sec. 2,
-//                 Sec. 3.1), all levels of one level-0 tile per workgroup;
-//   k_detect      one workgroup per marked cell: AST segment test + FAST
-//                 score on every level over the cell's score boxes (LDS),
-//                 3x3 scale-space suppression (Sec. 2), ordered compaction
-//                 of the survivors into the cell's slot; the last workgroup
-//                 scans the per-cell counts into list offsets;
-//   k_gather      Eq. (1): concatenates every cell's slot (new keypoints in
-//                 marked cells, untouched carried ones elsewhere) into D_n.
+//   k_frame   one workgroup per level-0 tile (aligned to the coarsest
+//             octave): loads the tile of I_n a dword at a time, builds every
+//             coarser octave of it in LDS by 2x2 box average with round-half-
+//             up (Sec. 2, Sec. 3.1) and writes them out; when the
+//             intensity-difference mask is active it also sums |I_n - I_{n-1}|
+//             per cell (v_sad_u8 per dword, LDS partials, one atomic per
+//             tile and cell) for the per-cell mean-difference test (Sec. 3.1
+//             Eq. 2, read per cell).
+//   k_detect  one workgroup per cell, in cell order through a ticket: decides
+//             the cell's mark (Eq. 2 from the SAD, Eqs. 3-4 from the cell's
+//             count in D_{n-1}); in a marked cell it stages the pixel tiles of
+//             every octave in LDS, runs the segment test and FAST score over
+//             the cell's score boxes, keeps the scale-space maxima (Sec. 2)
+//             as a bitmask and ranks them with popcounts; a decoupled
+//             look-back over the cells' counts gives every cell its offset in
+//             D_n, and the cell writes its new keypoints there, or copies its
+//             D_{n-1} entries when unmarked (Eq. 1).
 #include <hip/hip_runtime.h>
 
 #include "kpd_geom.h"
@@ -20,95 +25,161 @@
 
 namespace kpd {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
+constexpr int kFrameBlock = 256;
+constexpr int kBlk = kDetectBlock;
+constexpr int kDetWaves = kDetectWaves;
 
-// floor(i / d) for i < 2^24 and 0 < d < 2^16 with magic = ceil(2^32 / d)
-// (kept in 64 bits so that d = 1 works): the rounding error
-// i * (magic - 2^32/d) / 2^32 stays below 1/d, so the floor is exact.
+// floor(i / d) with magic = div_magic(d) (see kpd_geom.h)
 __device__ __forceinline__ unsigned fast_div(unsigned i, uint64_t magic)
 {
     return (unsigned)(((uint64_t)i * magic) >> 32);
 }
-__device__ __forceinline__ uint64_t div_magic_dev(unsigned d) { return (0x100000000ull + d - 1) / d; }
 
-// ------------------------------------------------------------------ mask
+// ------------------------------------------------------------------ k_frame
 
-__global__ __launch_bounds__(kBlock) void k_cell_mask(MaskArgs a)
+__global__ __launch_bounds__(kFrameBlock) void k_frame(FrameArgs a)
 {
-    const int c = blockIdx.x;
+    extern __shared__ __align__(16) uint8_t sm[];
+    const int T = a.tile;
     const int tid = threadIdx.x;
-    const Box r = cell_rect(c, a.W, a.H, a.nc, a.nr);
-    const int cw = box_w(r), ch = box_h(r);
-    const uint64_t magic = div_magic_dev(cw);
-    unsigned sad = 0;
-    if (a.id_on) {
-        const int n = cw * ch;
-        for (int i = tid; i < n; i += kBlock) {
-            const int ry = fast_div(i, magic);
-            const int rx = i - ry * cw;
-            const int cur = a.cur[(size_t)(r.y0 + ry) * a.cur_pitch + r.x0 + rx];
-            const int prv = a.prev[(size_t)(r.y0 + ry) * a.prev_pitch + r.x0 + rx];
-            sad += (unsigned)abs(cur - prv);
+    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+    const int lgq = __builtin_ctz(T / 4);
+
+    // per-level output pointers and sizes, with static indices only
+    __shared__ uint8_t* s_out[KPD_MAX_OCTAVES];
+    __shared__ int s_pitch[KPD_MAX_OCTAVES], s_w[KPD_MAX_OCTAVES], s_h[KPD_MAX_OCTAVES];
+    if (tid == 0) {
+#pragma unroll
+        for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
+            s_out[o] = a.lvl[o];
+            s_pitch[o] = a.pitch[o];
+            s_w[o] = a.w[o];
+            s_h[o] = a.h[o];
         }
     }
-    // wave reduction, then across the 4 waves
-    for (int off = 32; off > 0; off >>= 1) sad += __shfl_xor(sad, off);
-    __shared__ unsigned part[kWaves];
-    if ((tid & 63) == 0) part[tid >> 6] = sad;
-    __syncthreads();
-    if (tid == 0) {
-        unsigned s = 0;
-        for (int w = 0; w < kWaves; ++w) s += part[w];
-        a.sad[c] = s;
-        const bool id = a.id_on && (int64_t)s > (int64_t)a.id_thresh * (int64_t)(cw * ch);
-        const bool kb = a.count[c] >= a.kb_thresh;
-        a.mask[c] = (uint8_t)(id || kb);
+    // LDS: level buffers (T^2, (T/2)^2, ...), then the per-cell SAD partials
+    // and the tile's column/row -> local cell tables.
+    uint32_t* sadl = reinterpret_cast<uint32_t*>(sm + a.sad_lds_off);
+    uint16_t* colcell = reinterpret_cast<uint16_t*>(sm + a.sad_lds_off + 4 * a.sad_slots);
+    uint16_t* rowcell = colcell + T;
+    const int xe = min(x0 + T, a.W), ye = min(y0 + T, a.H);
+    const int cx0 = (int)(((int64_t)x0 * a.nc) / a.W);
+    const int cy0 = (int)(((int64_t)y0 * a.nr) / a.H);
+    const int ncx = (int)(((int64_t)(xe - 1) * a.nc) / a.W) - cx0 + 1;
+    const int ncy = (int)(((int64_t)(ye - 1) * a.nr) / a.H) - cy0 + 1;
+    if (a.sad_on) {
+        for (int i = tid; i < a.sad_slots; i += kFrameBlock) sadl[i] = 0;
+        for (int i = tid; i < T; i += kFrameBlock) {
+            colcell[i] = (uint16_t)(x0 + i < a.W ? (int)(((int64_t)(x0 + i) * a.nc) / a.W) - cx0 : 0);
+            rowcell[i] = (uint16_t)(y0 + i < a.H ? (int)(((int64_t)(y0 + i) * a.nr) / a.H) - cy0 : 0);
+        }
     }
-}
+    __syncthreads();
 
-// --------------------------------------------------------------- pyramid
+    // level 0 tile (and the SAD against I_{n-1})
+    uint8_t* L0 = sm;
+    const int ndw = T * T / 4;
+    for (int i = tid; i < ndw; i += kFrameBlock) {
+        const int ry = i >> lgq, cq = i & (T / 4 - 1);
+        const int gy = y0 + ry, gx = x0 + 4 * cq;
+        uint32_t v = 0, pv = 0;
+        if (gy < a.H && gx < a.W) {
+            const uint8_t* src = a.cur + (size_t)gy * a.cur_pitch + gx;
+            if (a.cur_aligned) {
+                v = *reinterpret_cast<const uint32_t*>(src);
+            } else {
+                for (int k = 0; k < 4; ++k)
+                    if (gx + k < a.W) v |= (uint32_t)src[k] << (8 * k);
+            }
+            if (a.sad_on) {
+                const uint8_t* ps = a.prev + (size_t)gy * a.prev_pitch + gx;
+                if (a.prev_aligned) {
+                    pv = *reinterpret_cast<const uint32_t*>(ps);
+                } else {
+                    for (int k = 0; k < 4; ++k)
+                        if (gx + k < a.W) pv |= (uint32_t)ps[k] << (8 * k);
+                }
+                const int lc = 4 * cq;
+                const int rc = rowcell[ry] * ncx;
+                if (gx + 3 < a.W && colcell[lc] == colcell[lc + 3]) {
+                    atomicAdd(&sadl[rc + colcell[lc]], __builtin_amdgcn_sad_u8(v, pv, 0u));
+                } else {
+                    for (int k = 0; k < 4 && gx + k < a.W; ++k) {
+                        const uint32_t m = 0xFFu << (8 * k);
+                        atomicAdd(&sadl[rc + colcell[lc + k]], __builtin_amdgcn_sad_u8(v & m, pv & m, 0u));
+                    }
+                }
+            }
+        }
+        *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v;
+    }
+    __syncthreads();
+    if (a.sad_on) {
+        for (int i = tid; i < ncx * ncy; i += kFrameBlock) {
+            const uint32_t s = sadl[i];
+            if (s) atomicAdd(&a.sad[(cy0 + i / ncx) * a.nc + cx0 + i % ncx], s);
+        }
+    }
 
-__global__ __launch_bounds__(kBlock) void k_pyramid(PyrArgs a)
-{
-    extern __shared__ uint8_t smem[];
-    const int T = a.tile;           // level-0 tile side, a power of two >= 2^(O-1)
-    uint8_t* buf0 = smem;
-    uint8_t* buf1 = smem + (T / 2) * (T / 2);
-    const int tid = threadIdx.x;
-    uint8_t* prev = nullptr;
-    uint8_t* cur = buf0;
+    // coarser octaves, four outputs per thread while a level row holds >= 4
+    int src_off = 0;
     for (int o = 1; o < a.O; ++o) {
         const int ts = T >> o;
-        const int lg = __builtin_ctz(ts);
-        const int wo = a.w[o], ho = a.h[o];
-        uint8_t* dst = a.lvl[o];
-        const int pitch = a.pitch[o];
-        for (int i = tid; i < ts * ts; i += kBlock) {
-            const int yy = i >> lg, xx = i & (ts - 1);
-            const int gx = blockIdx.x * ts + xx, gy = blockIdx.y * ts + yy;
-            int v = 0;
-            if (o == 1) {
-                if (gx < wo && gy < ho) {
-                    const uint8_t* s0 = a.lvl0 + (size_t)(2 * gy) * a.pitch0 + 2 * gx;
-                    const uint8_t* s1 = s0 + a.pitch0;
-                    v = (s0[0] + s0[1] + s1[0] + s1[1] + 2) >> 2;
+        const int dst_off = src_off + 4 * ts * ts;
+        const uint8_t* src = sm + src_off;
+        uint8_t* dst = sm + dst_off;
+        src_off = dst_off;
+        const int wo = s_w[o], ho = s_h[o];
+        const int gx0 = x0 >> o, gy0 = y0 >> o;
+        uint8_t* out = s_out[o];
+        const int pitch = s_pitch[o];
+        if (ts >= 4) {
+            const int q = ts / 4;
+            const int lq = __builtin_ctz(q);
+            for (int g = tid; g < ts * q; g += kFrameBlock) {
+                const int yy = g >> lq, xq = g & (q - 1);
+                const uint8_t* r0 = src + (2 * yy) * (2 * ts) + 8 * xq;
+                const uint8_t* r1 = r0 + 2 * ts;
+                const uint32_t a0 = *reinterpret_cast<const uint32_t*>(r0);
+                const uint32_t a1 = *reinterpret_cast<const uint32_t*>(r0 + 4);
+                const uint32_t b0 = *reinterpret_cast<const uint32_t*>(r1);
+                const uint32_t b1 = *reinterpret_cast<const uint32_t*>(r1 + 4);
+                uint32_t packed = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t ra = k < 2 ? a0 : a1, rb = k < 2 ? b0 : b1;
+                    const int sh = 16 * (k & 1);
+                    const uint32_t s = ((ra >> sh) & 0xFF) + ((ra >> (sh + 8)) & 0xFF) + ((rb >> sh) & 0xFF) +
+                                       ((rb >> (sh + 8)) & 0xFF) + 2;
+                    packed |= (s >> 2) << (8 * k);
                 }
-            } else {
-                const int ps = ts * 2;
-                const uint8_t* s0 = prev + (2 * yy) * ps + 2 * xx;
-                v = (s0[0] + s0[1] + s0[ps] + s0[ps + 1] + 2) >> 2;
+                *reinterpret_cast<uint32_t*>(dst + yy * ts + 4 * xq) = packed;
+                const int gy = gy0 + yy, gx = gx0 + 4 * xq;
+                if (gy < ho && gx < wo) {
+                    uint8_t* p = out + (size_t)gy * pitch + gx;
+                    if (gx + 3 < wo) {
+                        *reinterpret_cast<uint32_t*>(p) = packed;
+                    } else {
+                        for (int k = 0; k < 4 && gx + k < wo; ++k) p[k] = (uint8_t)(packed >> (8 * k));
+                    }
+                }
             }
-            cur[i] = (uint8_t)v;
-            if (gx < wo && gy < ho) dst[(size_t)gy * pitch + gx] = (uint8_t)v;
+        } else {
+            for (int g = tid; g < ts * ts; g += kFrameBlock) {
+                const int yy = g / ts, xx = g % ts;
+                const uint8_t* r0 = src + (2 * yy) * (2 * ts) + 2 * xx;
+                const uint8_t* r1 = r0 + 2 * ts;
+                const uint8_t v = (uint8_t)((r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
+                dst[yy * ts + xx] = v;
+                const int gy = gy0 + yy, gx = gx0 + xx;
+                if (gy < ho && gx < wo) out[(size_t)gy * pitch + gx] = v;
+            }
         }
         __syncthreads();
-        prev = cur;
-        cur = (cur == buf0) ? buf1 : buf0;
     }
 }
 
-// ---------------------------------------------------------------- detect
+// ----------------------------------------------------------------- k_detect
 
 // Radius-3 Bresenham circle, clockwise from straight up (Sec. 2).
 __constant__ int8_t kRingDx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
@@ -125,18 +196,26 @@ __device__ __forceinline__ bool has_arc9(unsigned m)
     return (r & 0xFFFFu) != 0;
 }
 
-// Segment test and FAST score of the pixel at P (row pitch pw) for
-// threshold t; 0 for pixels that are not corners.
-__device__ __forceinline__ int fast_score(const uint8_t* P, int pw, int t)
+// Necessary condition for a corner at P (row pitch pw): any 9-arc of the 16
+// ring pixels holds position k or k+8 for every k, so a bright arc needs one
+// of {up, down} and one of {right, left} brighter than p + t (darker than
+// p - t for a dark arc).
+__device__ __forceinline__ bool compass_pass(const uint8_t* P, int pw, int t)
 {
     const int p = P[0];
     const int hi = p + t, lo = p - t;
     const int n = P[-3 * pw], s = P[3 * pw], e = P[3], w = P[-3];
-    // Any 9-arc of 16 holds ring position k or k+8 for every k, so a
-    // bright arc needs one of {up, down} and one of {right, left} brighter.
     const bool maybe_b = max(n, s) > hi && max(e, w) > hi;
     const bool maybe_d = min(n, s) < lo && min(e, w) < lo;
-    if (!(maybe_b || maybe_d)) return 0;
+    return maybe_b || maybe_d;
+}
+
+// Segment test and FAST score of the pixel at P for threshold t (Sec. 2);
+// 0 for pixels that are not corners.
+__device__ __forceinline__ int full_score(const uint8_t* P, int pw, int t)
+{
+    const int p = P[0];
+    const int hi = p + t, lo = p - t;
     unsigned bm = 0, dm = 0;
     int sb = 0, sd = 0;
 #pragma unroll
@@ -150,226 +229,358 @@ __device__ __forceinline__ int fast_score(const uint8_t* P, int pw, int t)
     return max(sb, sd);
 }
 
-// Score maps of one workgroup: level o covers box sb[o] at LDS offset voff[o].
-struct ScoreMaps {
-    const uint8_t* smem;
-    const Box* sb;
-    const int* voff;
-};
-
-__device__ __forceinline__ int vget(const ScoreMaps& M, int o, int x, int y)
+__device__ __forceinline__ int level_of(const int* start, int O, int i)
 {
-    const Box b = M.sb[o];
+    int o = 0;
+    while (o + 1 < O && i >= start[o + 1]) ++o;
+    return o;
+}
+
+// Score of level-o pixel (x, y) from the LDS maps; 0 outside the score box.
+__device__ __forceinline__ int vget(const uint8_t* sm, const CellLayout& L, int o, int x, int y)
+{
+    const Box b = L.sb[o];
     if (x < b.x0 || x >= b.x1 || y < b.y0 || y >= b.y1) return 0;
-    const uint16_t* v = reinterpret_cast<const uint16_t*>(M.smem + M.voff[o]);
+    const uint16_t* v = reinterpret_cast<const uint16_t*>(sm + L.voff[o]);
     return v[(y - b.y0) * (b.x1 - b.x0) + (x - b.x0)];
 }
 
 // p = (o, x, y) with score v > 0 is a keypoint when no scale-space neighbour
 // ranks above it: higher score, or equal score and a finer octave, or equal
 // score and octave and an earlier (y, x).
-__device__ bool is_local_max(const ScoreMaps& M, int o, int O, int x, int y, int v)
+__device__ bool is_local_max(const uint8_t* sm, const CellLayout& L, int o, int O, int x, int y, int v)
 {
     // in-plane: the three pixels above and the one to the left precede p
-    if (vget(M, o, x - 1, y - 1) >= v || vget(M, o, x, y - 1) >= v || vget(M, o, x + 1, y - 1) >= v ||
-        vget(M, o, x - 1, y) >= v)
+    if (vget(sm, L, o, x - 1, y - 1) >= v || vget(sm, L, o, x, y - 1) >= v ||
+        vget(sm, L, o, x + 1, y - 1) >= v || vget(sm, L, o, x - 1, y) >= v)
         return false;
-    if (vget(M, o, x + 1, y) > v || vget(M, o, x - 1, y + 1) > v || vget(M, o, x, y + 1) > v ||
-        vget(M, o, x + 1, y + 1) > v)
+    if (vget(sm, L, o, x + 1, y) > v || vget(sm, L, o, x - 1, y + 1) > v || vget(sm, L, o, x, y + 1) > v ||
+        vget(sm, L, o, x + 1, y + 1) > v)
         return false;
     if (o > 0) {
         for (int yy = 2 * y - 1; yy <= 2 * y + 2; ++yy)
             for (int xx = 2 * x - 1; xx <= 2 * x + 2; ++xx)
-                if (vget(M, o - 1, xx, yy) >= v) return false;
+                if (vget(sm, L, o - 1, xx, yy) >= v) return false;
     }
     if (o + 1 < O) {
         for (int yy = (y - 1) >> 1; yy <= (y + 1) >> 1; ++yy)
             for (int xx = (x - 1) >> 1; xx <= (x + 1) >> 1; ++xx)
-                if (vget(M, o + 1, xx, yy) > v) return false;
+                if (vget(sm, L, o + 1, xx, yy) > v) return false;
     }
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_detect(DetectArgs a)
+// Count word of a marked cell: [63:32] frame epoch, [31:0] the cell's number
+// of keypoints in D_n. Unmarked cells publish nothing: their count is
+// D_{n-1}'s, which every workgroup can read.
+constexpr int kSpinLimit = 1 << 20;  // about a second: far beyond any real wait
+
+// Mark decision of cell c (Eq. 2 per cell from the SAD, Eqs. 3-4 from the
+// cell's count in D_{n-1}); every workgroup can evaluate it for any cell.
+__device__ __forceinline__ bool cell_marked(const DetectArgs& a, int c)
 {
-    extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ Box s_dec[KPD_MAX_OCTAVES];
-    __shared__ Box s_sb[KPD_MAX_OCTAVES];
-    __shared__ int s_voff[KPD_MAX_OCTAVES];
-    __shared__ int s_tile_off;
-    __shared__ unsigned s_wcount[kWaves];
-    __shared__ int s_last;
+    if (a.all_marked) return true;
+    const int cx = c % a.nc, cy = c / a.nc;
+    const int64_t area = (int64_t)a.col_w[cx] * a.row_h[cy];
+    const bool id = a.id_on && (int64_t)a.sad[c] > (int64_t)a.id_thresh * area;
+    const bool kb = a.count_prev[c] >= a.kb_thresh;
+    return id || kb;
+}
+
+__global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    __shared__ CellLayout L;
+    __shared__ int s_c, s_mark;
+    __shared__ uint32_t s_n, s_excl, s_part[kDetWaves];
+    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
+    __shared__ int s_pitch[KPD_MAX_OCTAVES];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int c = blockIdx.x;
     const int O = a.O;
 
-    bool active = a.all_marked || a.mask[c];
-    if (active) {
-        if (tid == 0) {
-            if (a.all_marked) a.mask[c] = 1;
-            const Box r = cell_rect(c, a.W, a.H, a.nc, a.nr);
-            for (int o = 0; o < O; ++o) s_dec[o] = decision_box(r, o, a.w[o], a.h[o]);
-            int off = 0;
-            for (int o = 0; o < O; ++o) {
-                s_sb[o] = score_box(s_dec, o, O, a.w[o], a.h[o]);
-                s_voff[o] = off;
-                if (!box_empty(s_sb[o])) off += round_up(box_w(s_sb[o]) * box_h(s_sb[o]) * 2, 4);
+    if (tid == 0) {
+#pragma unroll
+        for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
+            s_lvl[o] = a.lvl[o];
+            s_pitch[o] = a.pitch[o];
+        }
+        // cells are taken in ticket order, so every cell a workgroup waits on
+        // below belongs to a workgroup that is already running
+        const int c = (int)(atomicAdd(a.ticket, 1u) - a.ticket_base);
+        s_c = c;
+        s_mark = 0;
+        if (c < 0 || c >= a.nc * a.nr) {  // counter out of step: refuse the frame
+            __hip_atomic_store(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_mark = -1;
+        } else {
+            const bool mark = cell_marked(a, c);
+            a.mask[c] = (uint8_t)mark;
+            a.sad_next[c] = 0;
+            s_mark = mark;
+        }
+    }
+    __syncthreads();
+    if (s_mark < 0) return;
+    const int c = s_c;
+    const bool mark = s_mark != 0;
+    uint64_t* keepw = reinterpret_cast<uint64_t*>(sm);
+
+    if (mark) {
+        // 0) the cell's precomputed layout, one dword per thread
+        {
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
+            for (int i = tid; i < (int)(sizeof(CellLayout) / 4); i += kBlk) dst[i] = src[i];
+        }
+        __syncthreads();
+        uint64_t* candw = reinterpret_cast<uint64_t*>(sm + L.cand_off);
+        for (int i = tid; i < L.nwords; i += kBlk) candw[i] = 0;
+
+        // 1) pixel tiles of every octave, a dword per load, four loads in flight
+        const int nld = L.ld_start[O];
+        for (int base = tid; base < nld; base += 4 * kBlk) {
+            uint32_t val[4];
+            int dst[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = base + u * kBlk;
+                dst[u] = -1;
+                val[u] = 0;
+                if (i < nld) {
+                    const int o = level_of(L.ld_start, O, i);
+                    const unsigned j = i - L.ld_start[o];
+                    const int q = L.tpitch[o] / 4;
+                    const int ry = fast_div(j, L.ldm[o]), cq = j - ry * q;
+                    const int gy = L.ty0[o] + ry, gx = L.tx0[o] + 4 * cq;
+                    const uint8_t* src = s_lvl[o] + (size_t)gy * s_pitch[o] + gx;
+                    if (o > 0 || a.lvl0_aligned) {
+                        val[u] = *reinterpret_cast<const uint32_t*>(src);
+                    } else {
+                        uint32_t v = 0;
+                        for (int k = 0; k < 4; ++k)
+                            if (gx + k < a.W) v |= (uint32_t)src[k] << (8 * k);
+                        val[u] = v;
+                    }
+                    dst[u] = L.toff[o] + ry * L.tpitch[o] + 4 * cq;
+                }
             }
-            s_tile_off = off;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (dst[u] >= 0) *reinterpret_cast<uint32_t*>(sm + dst[u]) = val[u];
         }
         __syncthreads();
 
-        uint8_t* tile = smem + s_tile_off;
-        // 1) scores of every level over its score box
-        for (int o = 0; o < O; ++o) {
-            const Box sb = s_sb[o];
-            if (box_empty(sb)) continue;
-            const int vw = box_w(sb), vh = box_h(sb);
-            const int tw = vw + 6, th = vh + 6;
-            const uint8_t* src = a.lvl[o];
-            const int pitch = a.pitch[o];
-            const uint64_t mt = div_magic_dev(tw);
-            for (int i = tid; i < tw * th; i += kBlock) {
-                const int ry = fast_div(i, mt), rx = i - ry * tw;
-                tile[i] = src[(size_t)(sb.y0 - 3 + ry) * pitch + (sb.x0 - 3 + rx)];
+        // 2) segment test and score over every octave's score box. Each wave
+        //    takes a contiguous range of score pixels, clears their scores,
+        //    and queues those that pass the four-compass-point test; the full
+        //    16-pixel test runs 64 queued pixels at a time, so lanes stay busy.
+        {
+            const int nsc = L.sc_start[O];
+            const int per = ((nsc + kDetWaves - 1) / kDetWaves + 63) & ~63;
+            const int i0 = wave * per, i1 = min(i0 + per, nsc);
+            uint16_t* queue = reinterpret_cast<uint16_t*>(sm + L.queue_off) + wave * kQueue;
+            uint32_t q_tail = 0, q_head = 0;
+            auto full_test = [&](int entry_count) {
+                // lanes < entry_count score queue[q_head + lane]
+                if (lane < entry_count) {
+                    const int i = queue[(q_head + lane) & (kQueue - 1)];
+                    const int o = level_of(L.sc_start, O, i);
+                    const unsigned j = i - L.sc_start[o];
+                    const Box sb = L.sb[o];
+                    const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
+                    const uint8_t* P = sm + L.toff[o] + (ry + kRingR) * L.tpitch[o] + (sb.x0 + rx - L.tx0[o]);
+                    const int v = full_score(P, L.tpitch[o], a.t);
+                    reinterpret_cast<uint16_t*>(sm + L.voff[o])[j] = (uint16_t)v;
+                    const Box d = L.dec[o];
+                    const int x = sb.x0 + rx, y = sb.y0 + ry;
+                    if (v > 0 && x >= d.x0 && x < d.x1 && y >= d.y0 && y < d.y1) {
+                        const int bit = L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
+                        atomicOr(&candw[bit >> 6], 1ull << (bit & 63));
+                    }
+                }
+                q_head += entry_count;
+            };
+            for (int base = i0; base < i1; base += 64) {
+                const int i = base + lane;
+                bool pass = false;
+                if (i < i1) {
+                    const int o = level_of(L.sc_start, O, i);
+                    const unsigned j = i - L.sc_start[o];
+                    const Box sb = L.sb[o];
+                    const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
+                    const uint8_t* P = sm + L.toff[o] + (ry + kRingR) * L.tpitch[o] + (sb.x0 + rx - L.tx0[o]);
+                    reinterpret_cast<uint16_t*>(sm + L.voff[o])[j] = 0;
+                    pass = compass_pass(P, L.tpitch[o], a.t);
+                }
+                const uint64_t bal = __ballot(pass);
+                if (pass) {
+                    const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                    queue[(q_tail + below) & (kQueue - 1)] = (uint16_t)i;
+                }
+                q_tail += (uint32_t)__popcll(bal);
+                __builtin_amdgcn_wave_barrier();
+                if (q_tail - q_head >= 64) {
+                    full_test(64);
+                    __builtin_amdgcn_wave_barrier();
+                }
             }
-            __syncthreads();
-            uint16_t* V = reinterpret_cast<uint16_t*>(smem + s_voff[o]);
-            const uint64_t mv = div_magic_dev(vw);
-            for (int i = tid; i < vw * vh; i += kBlock) {
-                const int ry = fast_div(i, mv), rx = i - ry * vw;
-                V[i] = (uint16_t)fast_score(tile + (ry + 3) * tw + (rx + 3), tw, a.t);
-            }
-            __syncthreads();
+            if (q_tail != q_head) full_test((int)(q_tail - q_head));
         }
+        __syncthreads();
 
-        // 2) suppression and ordered compaction, octave by octave, raster order
-        const ScoreMaps M{smem, s_sb, s_voff};
-        kpd_keypoint* slot = a.store + a.store_base[c];
-        const unsigned slot_cap = a.store_base[c + 1] - a.store_base[c];
-        unsigned base = 0;
-        for (int o = 0; o < O; ++o) {
-            const Box d = s_dec[o];
-            if (box_empty(d)) continue;
-            const int dw = box_w(d);
-            const int n = dw * box_h(d);
-            const uint64_t md = div_magic_dev(dw);
-            for (int chunk = 0; chunk < n; chunk += kBlock) {
-                const int i = chunk + tid;
-                bool keep = false;
-                int x = 0, y = 0, v = 0;
-                if (i < n) {
-                    const int ry = fast_div(i, md);
-                    y = d.y0 + ry;
-                    x = d.x0 + (i - ry * dw);
-                    v = vget(M, o, x, y);
-                    if (v > 0) keep = is_local_max(M, o, O, x, y, v);
-                }
-                const unsigned long long bal = __ballot(keep);
-                const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                if (lane == 0) s_wcount[wave] = (unsigned)__popcll(bal);
-                __syncthreads();
-                unsigned woff = 0, tot = 0;
-                for (int w2 = 0; w2 < kWaves; ++w2) {
-                    const unsigned cnt = s_wcount[w2];
-                    woff += (w2 < wave) ? cnt : 0u;
-                    tot += cnt;
-                }
-                // a cell never holds more than its slot (one keypoint per 2x2
-                // block of each decision box); the bound only guards the store
-                if (keep && base + woff + below < slot_cap) {
-                    kpd_keypoint k;
-                    k.x = (uint16_t)x; k.y = (uint16_t)y; k.octave = (uint8_t)o; k.pad = 0;
-                    k.score = (uint16_t)v;
-                    slot[base + woff + below] = k;
-                }
-                base += tot;
-                __syncthreads();
+        // 3) scale-space maxima of the candidates, one 64-pixel word per wave
+        //    pass; words without candidates are skipped whole
+        for (int w = wave; w < L.nwords; w += kDetWaves) {
+            const uint64_t cand = candw[w];
+            bool keep = false;
+            if (cand != 0 && ((cand >> lane) & 1)) {
+                const int i = w * 64 + lane;
+                const int o = level_of(L.dc_start, O, i);
+                const unsigned j = i - L.dc_start[o];
+                const Box d = L.dec[o];
+                const int ry = fast_div(j, L.dcm[o]);
+                const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
+                keep = is_local_max(sm, L, o, O, x, y, vget(sm, L, o, x, y));
             }
+            const uint64_t bal = __ballot(keep);
+            if (lane == 0) keepw[w] = bal;
         }
-        if (tid == 0) a.count[c] = base;
+        __syncthreads();
+
+        // 4) rank: exclusive popcount prefix over the keep words (wave 0)
+        if (wave == 0) {
+            const int nw = L.nwords;
+            uint32_t* woff = reinterpret_cast<uint32_t*>(sm + L.woff_off);
+            const int per = (nw + 63) / 64;
+            const int w0 = lane * per, w1 = min(w0 + per, nw);
+            uint32_t sum = 0;
+            for (int w = w0; w < w1; ++w) sum += (uint32_t)__popcll(keepw[w]);
+            uint32_t incl = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t up = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += up;
+            }
+            uint32_t run = incl - sum;
+            for (int w = w0; w < w1; ++w) {
+                woff[w] = run;
+                run += (uint32_t)__popcll(keepw[w]);
+            }
+            if (lane == 63) s_n = incl;
+        }
+        __syncthreads();
     }
 
-    // 3) the last workgroup to finish scans the per-cell counts into offsets
+    // 5) this cell's offset in D_n: the counts of all earlier cells, carried
+    //    ones read from D_{n-1}'s counts, marked ones from their count words
+    //    (earlier cells' workgroups took earlier tickets, so they are running)
+    if (tid == 0) {
+        const uint32_t own = mark ? s_n : a.count_prev[c];
+        s_n = own;
+        if (mark)
+            __hip_atomic_store(&a.status[c], ((uint64_t)a.epoch << 32) | own, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint32_t acc = 0;
+    bool ok = true;
+    for (int p = tid; p < c; p += kBlk) {
+        if (!cell_marked(a, p)) {
+            acc += a.count_prev[p];
+            continue;
+        }
+        int spins = 0;
+        while (true) {
+            const uint64_t st = __hip_atomic_load(&a.status[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(st >> 32) == a.epoch) {
+                acc += (uint32_t)st;
+                break;
+            }
+            if (++spins > kSpinLimit) { ok = false; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    if (!ok) __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) s_part[wave] = acc;
     __syncthreads();
     if (tid == 0) {
-        __threadfence();
-        const unsigned ticket = atomicAdd(&a.hdr[1], 1u);
-        s_last = (ticket == gridDim.x - 1);
+        uint32_t excl = 0;
+        for (int w = 0; w < kDetWaves; ++w) excl += s_part[w];
+        a.count_cur[c] = s_n;
+        a.off_cur[c] = excl;
+        if (c == a.nc * a.nr - 1) *a.total_cur = excl + s_n;
+        s_excl = excl;
     }
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const int ncell = a.nc * a.nr;
-    const int per = (ncell + kBlock - 1) / kBlock;
-    const int c0 = tid * per, c1 = min(c0 + per, ncell);
-    unsigned sum = 0;
-    for (int cc = c0; cc < c1; ++cc) sum += __hip_atomic_load(&a.count[cc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned* scan = reinterpret_cast<unsigned*>(smem);
-    scan[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const unsigned add = tid >= off ? scan[tid - off] : 0u;
-        __syncthreads();
-        scan[tid] += add;
-        __syncthreads();
-    }
-    unsigned run = scan[tid] - sum;  // exclusive prefix
-    for (int cc = c0; cc < c1; ++cc) {
-        a.offsets[cc] = run;
-        run += __hip_atomic_load(&a.count[cc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (tid == kBlock - 1) {
-        a.hdr[0] = scan[kBlock - 1];
-        a.hdr[1] = 0;  // reset the ticket for the next frame
-    }
-}
+    const uint32_t excl = s_excl, n = s_n;
 
-// ---------------------------------------------------------------- gather
-
-__global__ __launch_bounds__(64) void k_gather(GatherArgs a)
-{
-    const int c = blockIdx.x;
-    const unsigned n = a.count[c];
-    const unsigned off = a.offsets[c];
-    const kpd_keypoint* src = a.store + a.store_base[c];
-    for (unsigned i = threadIdx.x; i < n; i += 64) a.out[off + i] = src[i];
+    // 6) write D_n entries of this cell: the ranked maxima, or D_{n-1}'s
+    if (mark) {
+        const uint32_t* woff = reinterpret_cast<const uint32_t*>(sm + L.woff_off);
+        for (int w = tid; w < L.nwords; w += kBlk) {
+            uint64_t bits = keepw[w];
+            uint32_t pos = excl + woff[w];
+            while (bits) {
+                const int b = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                const int i = w * 64 + b;
+                const int o = level_of(L.dc_start, O, i);
+                const unsigned j = i - L.dc_start[o];
+                const Box d = L.dec[o];
+                const int ry = fast_div(j, L.dcm[o]);
+                const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
+                kpd_keypoint k;
+                k.x = (uint16_t)x;
+                k.y = (uint16_t)y;
+                k.octave = (uint8_t)o;
+                k.pad = 0;
+                k.score = (uint16_t)vget(sm, L, o, x, y);
+                // at most one keypoint per 2x2 block keeps pos below the capacity
+                if (pos < a.list_cap) a.list_cur[pos] = k;
+                ++pos;
+            }
+        }
+    } else {
+        const uint32_t src0 = a.off_prev[c];
+        for (uint32_t j = tid; j < n; j += kBlk)
+            if (src0 + j < a.list_cap && excl + j < a.list_cap) a.list_cur[excl + j] = a.list_prev[src0 + j];
+    }
 }
 
 // ------------------------------------------------------------- launchers
 
-// The last workgroup's count scan reuses the dynamic LDS: at least one word
-// per thread.
-int detect_lds_bytes(int lds_bytes) { return lds_bytes < kBlock * 4 ? kBlock * 4 : lds_bytes; }
-
-hipError_t launch_cell_mask(const MaskArgs& a, int ncell, hipStream_t s)
+int frame_sad_lds_off(int tile, int O)
 {
-    hipLaunchKernelGGL(k_cell_mask, dim3(ncell), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    int lv = 0;
+    for (int o = 0; o < O; ++o) lv += (tile >> o) * (tile >> o);
+    return round_up(lv, 16);
 }
 
-hipError_t launch_pyramid(const PyrArgs& a, hipStream_t s)
+int frame_lds_bytes(int tile, int O, int sad_slots)
+{
+    return frame_sad_lds_off(tile, O) + 4 * sad_slots + 2 * 2 * tile;
+}
+
+hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
 {
     const int T = a.tile;
     dim3 grid((a.W + T - 1) / T, (a.H + T - 1) / T);
-    const size_t lds = 2 * (size_t)(T / 2) * (T / 2);
-    hipLaunchKernelGGL(k_pyramid, grid, dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(k_frame, grid, dim3(kFrameBlock), frame_lds_bytes(T, a.O, a.sad_slots), s, a);
     return hipGetLastError();
+}
+
+hipError_t set_detect_lds_limit(int lds_bytes)
+{
+    if (lds_bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
 }
 
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s)
 {
-    const int lds = detect_lds_bytes(lds_bytes);
-    hipLaunchKernelGGL(k_detect, dim3(ncell), dim3(kBlock), lds, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather(const GatherArgs& a, int ncell, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_gather, dim3(ncell), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_detect, dim3(ncell), dim3(kBlk), lds_bytes, s, a);
     return hipGetLastError();
 }
 

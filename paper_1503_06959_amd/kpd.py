@@ -28,7 +28,9 @@ FRAME_HOST, FRAME_DEVICE, FRAME_DEVICE_RETAIN = 0, 1, 2
 
 KEYPOINT_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2")])
 EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_keypoints",
-            "close_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats", "kpd_pyramid_level")
+            "close_stream", "reset_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats",
+            "kpd_pyramid_level", "kpd_profile", "kpd_profile_read")
+KERNEL_NAMES = ("k_frame", "k_detect")
 
 
 class KpdParams(ctypes.Structure):
@@ -62,6 +64,9 @@ def _load() -> ctypes.CDLL:
     L.kpd_device_result.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P)]
     L.kpd_cell_stats.argtypes = [P, P, P]
     L.kpd_pyramid_level.argtypes = [P, ctypes.c_int, P]
+    L.reset_stream.argtypes = [P]
+    L.kpd_profile.argtypes = [P, ctypes.c_int]
+    L.kpd_profile_read.argtypes = [P, P, P]
     return L
 
 
@@ -139,6 +144,23 @@ def close_stream(handle: int) -> None:
     _check(lib.close_stream(handle))
 
 
+def reset_stream(handle: int) -> None:
+    _check(lib.reset_stream(handle))
+
+
+def profile(handle: int, enable: bool) -> None:
+    _check(lib.kpd_profile(handle, 1 if enable else 0))
+
+
+def profile_read(handle: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Summed event-timed milliseconds and launch counts per kernel
+    (KERNEL_NAMES order) since the last read."""
+    ms = np.zeros(len(KERNEL_NAMES), np.float64)
+    n = np.zeros(len(KERNEL_NAMES), np.uint64)
+    _check(lib.kpd_profile_read(handle, ms.ctypes.data, n.ctypes.data))
+    return ms, n
+
+
 def cell_stats(handle: int, n_cells: int) -> Tuple[np.ndarray, np.ndarray]:
     sad = np.zeros(n_cells, np.uint32)
     cnt = np.zeros(n_cells, np.uint32)
@@ -183,6 +205,9 @@ class Stream:
 
     def cell_stats(self):
         return cell_stats(self.handle, self.n_cells)
+
+    def reset(self) -> None:
+        reset_stream(self.handle)
 
     def level(self, octave: int) -> np.ndarray:
         return pyramid_level(self.handle, octave, self.width, self.height)

@@ -40,7 +40,19 @@ int main(int argc, char** argv)
                 return 1;
             }
         }
-        lds = kpd::imax(lds, kpd::cell_lds_bytes(&sb[(size_t)c * O], O));
+        kpd::CellLayout CL;
+        kpd::cell_layout(r, O, w, h, &CL);
+        lds = kpd::imax(lds, CL.bytes);
+        for (int o = 0; o < O; ++o) {
+            const Box& s = CL.sb[o];
+            if (kpd::box_empty(s)) continue;
+            // the pixel tile holds the score box plus the ring apron, inside the level
+            if (CL.tx0[o] > s.x0 - 3 || CL.tx0[o] + CL.tpitch[o] < s.x1 + 3 || CL.tx0[o] % 4 ||
+                CL.tx0[o] < 0 || CL.tx0[o] + CL.tpitch[o] > ((w[o] + 3) & ~3)) {
+                printf("tile columns wrong c=%d o=%d\n", c, o);
+                return 1;
+            }
+        }
     }
     auto interior = [&](int o, int x, int y) { return x >= 3 && y >= 3 && x < w[o] - 3 && y < h[o] - 3; };
     for (int o = 0; o < O; ++o) {

@@ -275,3 +275,34 @@ def test_deterministic_and_independent_streams(kpd):
         assert gpu_tuples(ka) == orc_tuples(o.get()[0])
     a.close()
     b.close()
+
+
+def test_reset_stream_acts_like_a_first_frame(kpd):
+    frames = scene_frames("c1_320x240", 5)
+    g = kpd.Stream(320, 240, kpd.make_params(30, 3, 8, 6, 8))
+    for i in range(3):
+        g.push(frames[i])
+    g.reset()
+    g.push(frames[3])
+    k, m = g.keypoints()
+    assert m.all()
+    o = oracle.Stream(320, 240, 30, 3, 8, 6, 8)
+    o.push(frames[3])
+    assert gpu_tuples(k) == orc_tuples(o.get()[0])
+    g.close()
+
+
+def test_kernel_timing_counts_launches(kpd):
+    frames = scene_frames("c1_320x240", 4)
+    g = kpd.Stream(320, 240, kpd.make_params(30, 3, 8, 6, 8))
+    kpd.profile(g.handle, True)
+    for f in frames:
+        g.push(f)
+    ms, n = kpd.profile_read(g.handle)
+    assert list(n) == [4, 4]
+    assert (ms > 0).all()
+    kpd.profile(g.handle, False)
+    g.push(frames[0])
+    ms, n = kpd.profile_read(g.handle)
+    assert list(n) == [0, 0]
+    g.close()
