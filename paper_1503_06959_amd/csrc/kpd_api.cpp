@@ -58,7 +58,7 @@ struct Layout {
 };
 
 // header words
-constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrTicket = 2, kHdrErr = 3;
+constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrErr = 3;
 
 bool valid_params(int W, int H, const kpd_params* p, std::string* why)
 {
@@ -395,8 +395,6 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
     d.row_h = s->at<uint16_t>(L.off_rowh);
     d.status = s->at<unsigned long long>(L.off_status);
     d.epoch = n + 1;
-    d.ticket = s->at<uint32_t>(L.off_hdr) + kHdrTicket;
-    d.ticket_base = n * (uint32_t)L.ncell;
     d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
     KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(d, L.ncell, L.lds_bytes, s->stream); }));
 
@@ -417,9 +415,7 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
     uint32_t hdr[4] = {0, 0, 0, 0};
     KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(s->L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
-    if (hdr[kHdrErr])
-        return fail(KPD_EDEVICE, hdr[kHdrErr] == 1 ? "a cell-offset wait timed out on the device"
-                                                   : "cell ticket out of step on the device");
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
     const uint32_t total = hdr[k ? kHdrTotal1 : kHdrTotal0];
     *count = total;
     if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the keypoint count");

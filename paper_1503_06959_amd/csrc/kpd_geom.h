@@ -72,13 +72,13 @@ KPD_HD void box_union(Box* acc, bool* have, const Box& b)
     acc->y0 = imin(acc->y0, b.y0); acc->y1 = imax(acc->y1, b.y1);
 }
 
-// Score region of level o for one cell: every level-o pixel whose score the
-// scale-space suppression of the cell's decisions can read. Decisions at
-// level o read their 8 in-plane neighbours; decisions at level o+1 read the
-// finer 4x4 block [2X-1, 2X+2]; decisions at level o-1 read the coarser
-// pixels X with 2X-1 <= x <= 2X+2, i.e. [(x-1)>>1, (x+1)>>1]. The result is
-// clipped to the detectable interior, outside which every score is 0.
-KPD_HD Box score_box(const Box* dec, int o, int O, int wo, int ho)
+// Query region of level o for one cell: every level-o pixel whose score the
+// scale-space suppression of the cell's decisions reads. Decisions at level o
+// read their 8 in-plane neighbours; decisions at level o+1 read the finer 4x4
+// block [2X-1, 2X+2]; decisions at level o-1 read the coarser pixels X with
+// 2X-1 <= x <= 2X+2, i.e. [(x-1)>>1, (x+1)>>1]. Every such pixel lies inside
+// the level (decisions keep 3 pixels from the border).
+KPD_HD Box query_box(const Box* dec, int o, int O)
 {
     Box acc = {0, 0, 0, 0};
     bool have = false;
@@ -90,10 +90,17 @@ KPD_HD Box score_box(const Box* dec, int o, int O, int wo, int ho)
     }
     if (o > 0 && !box_empty(dec[o - 1])) {
         const Box& f = dec[o - 1];
-        box_union(&acc, &have, Box{(f.x0 - 1) >> 1, ((f.x1 - 1 + 1) >> 1) + 1,
-                                   (f.y0 - 1) >> 1, ((f.y1 - 1 + 1) >> 1) + 1});
+        box_union(&acc, &have, Box{(f.x0 - 1) >> 1, (f.x1 >> 1) + 1, (f.y0 - 1) >> 1, (f.y1 >> 1) + 1});
     }
-    if (!have) return Box{0, 0, 0, 0};
+    return have ? acc : Box{0, 0, 0, 0};
+}
+
+// Score region of level o: the query region clipped to the detectable
+// interior [3, w_o - 3) x [3, h_o - 3), outside which every score is 0.
+KPD_HD Box score_box(const Box* dec, int o, int O, int wo, int ho)
+{
+    Box acc = query_box(dec, o, O);
+    if (box_empty(acc)) return Box{0, 0, 0, 0};
     acc.x0 = imax(acc.x0, kRingR); acc.x1 = imin(acc.x1, wo - kRingR);
     acc.y0 = imax(acc.y0, kRingR); acc.y1 = imin(acc.y1, ho - kRingR);
     if (box_empty(acc)) return Box{0, 0, 0, 0};
@@ -113,9 +120,11 @@ KPD_HD int round_up(int v, int a) { return (v + a - 1) / a * a; }
 // Threads per workgroup of the detection kernel and its waves.
 constexpr int kDetectBlock = 512;
 constexpr int kDetectWaves = kDetectBlock / 64;
-// Entries of each wave's private queue of pixels awaiting the full segment
-// test (a power of two, at least twice the wave width).
-constexpr int kQueue = 128;
+// Pixels a wave tests per pass (four per lane) and the entries of each
+// wave's private queue of pixels awaiting the full segment test: a power of
+// two holding one pass on top of a part-filled batch of 64.
+constexpr int kChunk = 256;
+constexpr int kQueue = 512;
 
 // floor(i / d) = (i * magic) >> 32 for i * d < 2^32, with magic = ceil(2^32 / d)
 // kept in 64 bits: the error i * (magic - 2^32/d) / 2^32 < i / 2^32 < 1/d
@@ -128,22 +137,28 @@ KPD_HD uint64_t div_magic(unsigned d) { return (0x100000000ull + d - 1) / d; }
 //
 // LDS layout (bytes): [keep bitmask: nwords x u64][candidate bitmask: nwords
 // x u64][word offsets: nwords x u32][wave queues: waves x kQueue x u16]
-// [score maps: u16 per level][pixel tiles: u8 per level]. A level's pixel
-// tile covers its score box plus the 3-pixel ring apron; its first column is
-// rounded down to a multiple of 4 and its row pitch up to one, so that
-// 4-byte aligned rows can be loaded a dword at a time.
+// [score maps: u16 per level, each over its query box, zero outside the
+// score box][pixel tiles: u8 per level]. A level's pixel tile covers its score
+// box plus the 3-pixel ring apron; its first column is rounded down to a
+// multiple of 4 and its row pitch up to one, so that 4-byte aligned rows can
+// be loaded a dword at a time. Score pixels are processed in chunks of
+// kChunk that never straddle two levels.
 struct CellLayout {
     uint64_t ldm[KPD_MAX_OCTAVES];       // div magics: tile dwords per row,
     uint64_t scm[KPD_MAX_OCTAVES];       // score-box width,
     uint64_t dcm[KPD_MAX_OCTAVES];       // decision-box width
     Box dec[KPD_MAX_OCTAVES];
     Box sb[KPD_MAX_OCTAVES];
+    Box qb[KPD_MAX_OCTAVES];             // score-map extent (query box)
     int tx0[KPD_MAX_OCTAVES], ty0[KPD_MAX_OCTAVES];   // level coords of tile (0,0)
     int tpitch[KPD_MAX_OCTAVES], th[KPD_MAX_OCTAVES];
     int toff[KPD_MAX_OCTAVES], voff[KPD_MAX_OCTAVES];
     int ld_start[KPD_MAX_OCTAVES + 1];   // flattened dword-load index of each level
     int sc_start[KPD_MAX_OCTAVES + 1];   // flattened score index of each level
     int dc_start[KPD_MAX_OCTAVES + 1];   // flattened decision index of each level
+    int ck_start[KPD_MAX_OCTAVES + 1];   // first score chunk of each level
+    int vpitch[KPD_MAX_OCTAVES];         // score-map row pitch (query-box width)
+    int vbytes;                          // bytes of all score maps (zeroed per cell)
     int O;
     int nwords;                          // words of each bitmask
     int cand_off, woff_off, queue_off;
@@ -156,11 +171,13 @@ KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, Cell
     for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
         L->dec[o] = Box{0, 0, 0, 0};
         L->sb[o] = Box{0, 0, 0, 0};
-        L->tx0[o] = L->ty0[o] = L->tpitch[o] = L->th[o] = L->toff[o] = L->voff[o] = 0;
+        L->qb[o] = Box{0, 0, 0, 0};
+        L->tx0[o] = L->ty0[o] = L->tpitch[o] = L->th[o] = L->toff[o] = L->voff[o] = L->vpitch[o] = 0;
         L->ldm[o] = L->scm[o] = L->dcm[o] = 0;
     }
     for (int o = 0; o < O; ++o) L->dec[o] = decision_box(rect, o, w[o], h[o]);
     for (int o = 0; o < O; ++o) L->sb[o] = score_box(L->dec, o, O, w[o], h[o]);
+    for (int o = 0; o < O; ++o) L->qb[o] = query_box(L->dec, o, O);
     int nd = 0;
     for (int o = 0; o < O; ++o) {
         L->dc_start[o] = nd;
@@ -176,17 +193,25 @@ KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, Cell
     off += round_up(L->nwords * 4, 8);
     L->queue_off = off;
     off += kDetectWaves * kQueue * 2;
-    int sc = 0;
+    int sc = 0, ck = 0;
+    const int v0 = off;
     for (int o = 0; o < O; ++o) {
         L->voff[o] = off;
         L->sc_start[o] = sc;
+        L->ck_start[o] = ck;
+        L->vpitch[o] = 0;
+        if (!box_empty(L->qb[o])) {
+            L->vpitch[o] = box_w(L->qb[o]);
+            off += round_up(L->vpitch[o] * box_h(L->qb[o]) * 2, 4);
+        }
         if (!box_empty(L->sb[o])) {
             const int n = box_w(L->sb[o]) * box_h(L->sb[o]);
-            off += round_up(n * 2, 4);
             sc += n;
+            ck += (n + kChunk - 1) / kChunk;
         }
     }
-    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) L->sc_start[o] = sc;
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) { L->sc_start[o] = sc; L->ck_start[o] = ck; }
+    L->vbytes = off - v0;
     int ld = 0;
     for (int o = 0; o < O; ++o) {
         L->ld_start[o] = ld;

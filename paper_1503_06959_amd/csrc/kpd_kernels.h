@@ -54,9 +54,7 @@ struct DetectArgs {
     const uint16_t* row_h;       // cell row heights
     unsigned long long* status;  // per-cell count words of marked cells
     uint32_t epoch;              // frame number + 1
-    uint32_t* ticket;            // running workgroup counter
-    uint32_t ticket_base;        // its value when this launch started
-    uint32_t* err;               // set when a look-back wait gives up
+    uint32_t* err;               // set when a wait for an earlier cell gives up
 };
 
 int frame_sad_lds_off(int tile, int O);

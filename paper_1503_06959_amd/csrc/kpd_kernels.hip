@@ -9,7 +9,7 @@
 //             per cell (v_sad_u8 per dword, LDS partials, one atomic per
 //             tile and cell) for the per-cell mean-difference test (Sec. 3.1
 //             Eq. 2, read per cell).
-//   k_detect  one workgroup per cell, in cell order through a ticket: decides
+//   k_detect  one workgroup per cell, in cell order: decides
 //             the cell's mark (Eq. 2 from the SAD, Eqs. 3-4 from the cell's
 //             count in D_{n-1}); in a marked cell it stages the pixel tiles of
 //             every octave in LDS, runs the segment test and FAST score over
@@ -236,38 +236,47 @@ __device__ __forceinline__ int level_of(const int* start, int O, int i)
     return o;
 }
 
-// Score of level-o pixel (x, y) from the LDS maps; 0 outside the score box.
+// Score of level-o pixel (x, y) from the LDS maps. Every pixel the
+// suppression reads lies inside its level's map (the query box); pixels
+// outside the score box hold 0.
 __device__ __forceinline__ int vget(const uint8_t* sm, const CellLayout& L, int o, int x, int y)
 {
-    const Box b = L.sb[o];
-    if (x < b.x0 || x >= b.x1 || y < b.y0 || y >= b.y1) return 0;
     const uint16_t* v = reinterpret_cast<const uint16_t*>(sm + L.voff[o]);
-    return v[(y - b.y0) * (b.x1 - b.x0) + (x - b.x0)];
+    return v[(y - L.qb[o].y0) * L.vpitch[o] + (x - L.qb[o].x0)];
 }
 
 // p = (o, x, y) with score v > 0 is a keypoint when no scale-space neighbour
 // ranks above it: higher score, or equal score and a finer octave, or equal
-// score and octave and an earlier (y, x).
+// score and octave and an earlier (y, x). All 28 neighbour reads are
+// independent, so they are issued together.
 __device__ bool is_local_max(const uint8_t* sm, const CellLayout& L, int o, int O, int x, int y, int v)
 {
+    const uint16_t* V = reinterpret_cast<const uint16_t*>(sm + L.voff[o]);
+    const int pv = L.vpitch[o];
+    const uint16_t* c = V + (y - L.qb[o].y0) * pv + (x - L.qb[o].x0);
     // in-plane: the three pixels above and the one to the left precede p
-    if (vget(sm, L, o, x - 1, y - 1) >= v || vget(sm, L, o, x, y - 1) >= v ||
-        vget(sm, L, o, x + 1, y - 1) >= v || vget(sm, L, o, x - 1, y) >= v)
-        return false;
-    if (vget(sm, L, o, x + 1, y) > v || vget(sm, L, o, x - 1, y + 1) > v || vget(sm, L, o, x, y + 1) > v ||
-        vget(sm, L, o, x + 1, y + 1) > v)
-        return false;
+    const int before = max(max((int)c[-pv - 1], (int)c[-pv]), max((int)c[-pv + 1], (int)c[-1]));
+    const int after = max(max((int)c[1], (int)c[pv - 1]), max((int)c[pv], (int)c[pv + 1]));
+    bool keep = before < v && after <= v;
     if (o > 0) {
-        for (int yy = 2 * y - 1; yy <= 2 * y + 2; ++yy)
-            for (int xx = 2 * x - 1; xx <= 2 * x + 2; ++xx)
-                if (vget(sm, L, o - 1, xx, yy) >= v) return false;
+        const uint16_t* F = reinterpret_cast<const uint16_t*>(sm + L.voff[o - 1]);
+        const int pf = L.vpitch[o - 1];
+        const uint16_t* f = F + (2 * y - 1 - L.qb[o - 1].y0) * pf + (2 * x - 1 - L.qb[o - 1].x0);
+        int m = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m = max(m, (int)f[r * pf + k]);
+        keep = keep && m < v;
     }
     if (o + 1 < O) {
-        for (int yy = (y - 1) >> 1; yy <= (y + 1) >> 1; ++yy)
-            for (int xx = (x - 1) >> 1; xx <= (x + 1) >> 1; ++xx)
-                if (vget(sm, L, o + 1, xx, yy) > v) return false;
+        const uint16_t* C = reinterpret_cast<const uint16_t*>(sm + L.voff[o + 1]);
+        const int pc = L.vpitch[o + 1];
+        const uint16_t* q = C + (((y - 1) >> 1) - L.qb[o + 1].y0) * pc + (((x - 1) >> 1) - L.qb[o + 1].x0);
+        const int m = max(max((int)q[0], (int)q[1]), max((int)q[pc], (int)q[pc + 1]));
+        keep = keep && m <= v;
     }
-    return true;
+    return keep;
 }
 
 // Count word of a marked cell: [63:32] frame epoch, [31:0] the cell's number
@@ -306,23 +315,19 @@ __global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
             s_lvl[o] = a.lvl[o];
             s_pitch[o] = a.pitch[o];
         }
-        // cells are taken in ticket order, so every cell a workgroup waits on
-        // below belongs to a workgroup that is already running
-        const int c = (int)(atomicAdd(a.ticket, 1u) - a.ticket_base);
+        // One workgroup per cell, in cell order. A workgroup only ever waits
+        // for lower-numbered cells, and each XCD dispatches its workgroups in
+        // index order, so the lowest unfinished cell can always run; the
+        // bounded spin below turns any failure of that into an error flag
+        // rather than a hang.
+        const int c = blockIdx.x;
         s_c = c;
-        s_mark = 0;
-        if (c < 0 || c >= a.nc * a.nr) {  // counter out of step: refuse the frame
-            __hip_atomic_store(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_mark = -1;
-        } else {
-            const bool mark = cell_marked(a, c);
-            a.mask[c] = (uint8_t)mark;
-            a.sad_next[c] = 0;
-            s_mark = mark;
-        }
+        const bool mark = cell_marked(a, c);
+        a.mask[c] = (uint8_t)mark;
+        a.sad_next[c] = 0;
+        s_mark = mark;
     }
     __syncthreads();
-    if (s_mark < 0) return;
     const int c = s_c;
     const bool mark = s_mark != 0;
     uint64_t* keepw = reinterpret_cast<uint64_t*>(sm);
@@ -337,6 +342,10 @@ __global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
         __syncthreads();
         uint64_t* candw = reinterpret_cast<uint64_t*>(sm + L.cand_off);
         for (int i = tid; i < L.nwords; i += kBlk) candw[i] = 0;
+        {
+            uint32_t* v = reinterpret_cast<uint32_t*>(sm + L.voff[0]);
+            for (int i = tid; i < L.vbytes / 4; i += kBlk) v[i] = 0;
+        }
 
         // 1) pixel tiles of every octave, a dword per load, four loads in flight
         const int nld = L.ld_start[O];
@@ -372,19 +381,15 @@ __global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
         }
         __syncthreads();
 
-        // 2) segment test and score over every octave's score box. Each wave
-        //    takes a contiguous range of score pixels, clears their scores,
-        //    and queues those that pass the four-compass-point test; the full
-        //    16-pixel test runs 64 queued pixels at a time, so lanes stay busy.
+        // 2) segment test and score over every octave's score box. Waves take
+        //    chunks of kChunk pixels of one level (four per lane) and queue
+        //    those that pass the four-compass-point test; the full 16-pixel
+        //    test runs 64 queued pixels at a time, so lanes stay busy.
         {
-            const int nsc = L.sc_start[O];
-            const int per = ((nsc + kDetWaves - 1) / kDetWaves + 63) & ~63;
-            const int i0 = wave * per, i1 = min(i0 + per, nsc);
             uint16_t* queue = reinterpret_cast<uint16_t*>(sm + L.queue_off) + wave * kQueue;
             uint32_t q_tail = 0, q_head = 0;
-            auto full_test = [&](int entry_count) {
-                // lanes < entry_count score queue[q_head + lane]
-                if (lane < entry_count) {
+            auto full_test = [&](int count) {
+                if (lane < count) {
                     const int i = queue[(q_head + lane) & (kQueue - 1)];
                     const int o = level_of(L.sc_start, O, i);
                     const unsigned j = i - L.sc_start[o];
@@ -392,37 +397,49 @@ __global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
                     const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
                     const uint8_t* P = sm + L.toff[o] + (ry + kRingR) * L.tpitch[o] + (sb.x0 + rx - L.tx0[o]);
                     const int v = full_score(P, L.tpitch[o], a.t);
-                    reinterpret_cast<uint16_t*>(sm + L.voff[o])[j] = (uint16_t)v;
-                    const Box d = L.dec[o];
                     const int x = sb.x0 + rx, y = sb.y0 + ry;
-                    if (v > 0 && x >= d.x0 && x < d.x1 && y >= d.y0 && y < d.y1) {
-                        const int bit = L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
-                        atomicOr(&candw[bit >> 6], 1ull << (bit & 63));
+                    if (v > 0) {
+                        reinterpret_cast<uint16_t*>(sm + L.voff[o])[(y - L.qb[o].y0) * L.vpitch[o] + (x - L.qb[o].x0)] =
+                            (uint16_t)v;
+                        const Box d = L.dec[o];
+                        if (x >= d.x0 && x < d.x1 && y >= d.y0 && y < d.y1) {
+                            const int bit = L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
+                            atomicOr(&candw[bit >> 6], 1ull << (bit & 63));
+                        }
                     }
                 }
-                q_head += entry_count;
+                q_head += count;
             };
-            for (int base = i0; base < i1; base += 64) {
-                const int i = base + lane;
-                bool pass = false;
-                if (i < i1) {
-                    const int o = level_of(L.sc_start, O, i);
-                    const unsigned j = i - L.sc_start[o];
-                    const Box sb = L.sb[o];
-                    const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
-                    const uint8_t* P = sm + L.toff[o] + (ry + kRingR) * L.tpitch[o] + (sb.x0 + rx - L.tx0[o]);
-                    reinterpret_cast<uint16_t*>(sm + L.voff[o])[j] = 0;
-                    pass = compass_pass(P, L.tpitch[o], a.t);
+            const int nck = L.ck_start[O];
+            for (int ck = wave; ck < nck; ck += kDetWaves) {
+                const int o = level_of(L.ck_start, O, ck);
+                const Box sb = L.sb[o];
+                const int n = box_w(sb) * box_h(sb);
+                const int tp = L.tpitch[o];
+                const uint8_t* T0 = sm + L.toff[o] + kRingR * tp + (sb.x0 - L.tx0[o]);
+                const int j0 = (ck - L.ck_start[o]) * kChunk;
+                bool pass[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * 64 + lane;
+                    pass[u] = false;
+                    if (j < n) {
+                        const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
+                        pass[u] = compass_pass(T0 + ry * tp + rx, tp, a.t);
+                    }
                 }
-                const uint64_t bal = __ballot(pass);
-                if (pass) {
-                    const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                    queue[(q_tail + below) & (kQueue - 1)] = (uint16_t)i;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint64_t bal = __ballot(pass[u]);
+                    if (pass[u]) {
+                        const unsigned below = __builtin_amdgcn_mbcnt_hi(
+                            (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                        queue[(q_tail + below) & (kQueue - 1)] = (uint16_t)(L.sc_start[o] + j0 + u * 64 + lane);
+                    }
+                    q_tail += (uint32_t)__popcll(bal);
                 }
-                q_tail += (uint32_t)__popcll(bal);
                 __builtin_amdgcn_wave_barrier();
-                if (q_tail - q_head >= 64) {
+                while (q_tail - q_head >= 64) {
                     full_test(64);
                     __builtin_amdgcn_wave_barrier();
                 }
@@ -475,7 +492,6 @@ __global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
 
     // 5) this cell's offset in D_n: the counts of all earlier cells, carried
     //    ones read from D_{n-1}'s counts, marked ones from their count words
-    //    (earlier cells' workgroups took earlier tickets, so they are running)
     if (tid == 0) {
         const uint32_t own = mark ? s_n : a.count_prev[c];
         s_n = own;

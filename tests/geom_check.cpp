@@ -43,6 +43,32 @@ int main(int argc, char** argv)
         kpd::CellLayout CL;
         kpd::cell_layout(r, O, w, h, &CL);
         lds = kpd::imax(lds, CL.bytes);
+        // every neighbour a decision reads lies in its level's score map
+        auto padded = [&](int o, int x, int y) {
+            const Box& q = CL.qb[o];
+            const Box& s = CL.sb[o];
+            // the score box lies inside the query box, and the query box inside the level
+            if (!kpd::box_empty(s) && (s.x0 < q.x0 || s.x1 > q.x1 || s.y0 < q.y0 || s.y1 > q.y1)) return false;
+            if (q.x0 < 0 || q.y0 < 0 || q.x1 > w[o] || q.y1 > h[o]) return false;
+            return x >= q.x0 && x < q.x1 && y >= q.y0 && y < q.y1;
+        };
+        for (int o = 0; o < O; ++o) {
+            const Box& d = CL.dec[o];
+            if (kpd::box_empty(d)) continue;
+            for (int y = d.y0; y < d.y1; ++y)
+                for (int x = d.x0; x < d.x1; ++x) {
+                    bool okq = true;
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) okq = okq && padded(o, x + dx, y + dy);
+                    if (o > 0)
+                        for (int yy = 2 * y - 1; yy <= 2 * y + 2; ++yy)
+                            for (int xx = 2 * x - 1; xx <= 2 * x + 2; ++xx) okq = okq && padded(o - 1, xx, yy);
+                    if (o + 1 < O)
+                        for (int yy = (y - 1) >> 1; yy <= (y + 1) >> 1; ++yy)
+                            for (int xx = (x - 1) >> 1; xx <= (x + 1) >> 1; ++xx) okq = okq && padded(o + 1, xx, yy);
+                    if (!okq) { printf("query outside padded score map c=%d o=%d (%d,%d)\n", c, o, x, y); return 1; }
+                }
+        }
         for (int o = 0; o < O; ++o) {
             const Box& s = CL.sb[o];
             if (kpd::box_empty(s)) continue;
