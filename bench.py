@@ -152,11 +152,11 @@ def kernel_profile(kpd, s, wl: Workload, steps: int):
 
 def algorithmic_bytes(wl: Workload, st, masked: bool) -> dict:
     """Bytes the method must move per launch of each kernel, averaged over
-    the frames of one pass. k_frame reads I_n (and I_{n-1} for the
-    intensity-difference test) and writes the coarser octaves; k_detect reads
-    the octave pixels of the marked cells, writes their keypoints and copies
-    the carried ones (Eq. 1). Score maps are an LDS intermediate and count
-    nothing. Frame 0 of a pass marks every cell."""
+    the frames of one pass. The tile pass reads I_n (and I_{n-1} for the
+    intensity-difference test) and writes the coarser octaves; the cell pass
+    reads the octave pixels of the marked cells, writes their keypoints and
+    copies the carried ones (Eq. 1). Score maps are an LDS intermediate and
+    count nothing. Frame 0 of a pass marks every cell."""
     d = wl.det
     N = wl.W * wl.H
     lv = level_sizes(wl.W, wl.H, d.n_octaves)
@@ -166,10 +166,7 @@ def algorithmic_bytes(wl: Workload, st, masked: bool) -> dict:
     frac = [m / wl.ncell for m in st["marked"]]
     carried = [t - n for t, n in zip(st["total_kp"], st["new_kp"])]
     detect = sum(f * sum(lv) for f in frac) + 8 * sum(st["new_kp"]) + 16 * sum(carried) + 24 * wl.ncell * F
-    return {
-        "k_frame": N + P + N * sad_frames / F,
-        "k_detect": detect / F,
-    }
+    return {"k_frame": N + P + N * sad_frames / F, "k_detect": detect / F}
 
 
 def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True):

@@ -47,13 +47,14 @@ struct Layout {
     int W = 0, H = 0, O = 0, nc = 0, nr = 0, ncell = 0;
     int w[KPD_MAX_OCTAVES] = {}, h[KPD_MAX_OCTAVES] = {}, pitch[KPD_MAX_OCTAVES] = {};
     int slot_pitch = 0;
-    int tile = 32;       // k_frame level-0 tile side
-    int sad_slots = 1;   // cells one k_frame tile can touch
+    int tile = 32;       // level-0 tile side of the pyramid/SAD workgroups
+    int tiles_x = 0, tiles_y = 0;
+    int sad_slots = 1;   // cells one tile can touch
     size_t off_hdr = 0, off_slot[2] = {0, 0}, off_lvl[KPD_MAX_OCTAVES] = {};
     size_t off_sad[2] = {0, 0}, off_count[2] = {0, 0}, off_offs[2] = {0, 0}, off_list[2] = {0, 0};
     size_t off_mask = 0, off_status = 0, off_colw = 0, off_rowh = 0, off_layouts = 0;
     size_t list_cap = 0;
-    int lds_bytes = 0;   // k_detect dynamic LDS
+    int lds_bytes = 0;   // dynamic LDS of the cell pass
     size_t total = 0;
 };
 
@@ -93,6 +94,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     }
     L->slot_pitch = kpd::round_up(W, 64);
     L->tile = std::max(32, 1 << (L->O - 1));
+    L->tiles_x = (W + L->tile - 1) / L->tile;
+    L->tiles_y = (H + L->tile - 1) / L->tile;
 
     // cells a k_frame tile can touch, per axis
     auto span_max = [](int len, int n, int T) {
@@ -310,7 +313,14 @@ int set_thresholds(kpd_stream* s, int32_t fast_t, int32_t id_thresh, uint32_t kb
     return KPD_OK;
 }
 
-int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
+}  // extern "C"
+
+namespace {
+
+// Validate and stage the next frame of `s`: copy it into an arena slot when
+// asked to, and fill the tick arguments of both passes. The stream state
+// advances only in advance_frame, once the work is enqueued.
+int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags, kpd::TickArgs* t)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     const Layout& L = s->L;
@@ -342,29 +352,29 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
     const bool all_marked = s->force_all || s->p.id_thresh < 0 || s->p.kb_thresh == 0;
     const bool sad_on = !all_marked && s->p.id_thresh < 255;
 
-    if (L.O > 1 || sad_on) {
-        kpd::FrameArgs fa{};
-        fa.cur = cur;
-        fa.cur_pitch = cur_pitch;
-        fa.cur_aligned = cur_dw;
-        fa.prev = sad_on ? s->prev0 : cur;
-        fa.prev_pitch = sad_on ? s->prev_pitch : cur_pitch;
-        fa.prev_aligned = sad_on ? s->prev_dw : cur_dw;
-        for (int o = 1; o < L.O; ++o) {
-            fa.lvl[o] = s->at<uint8_t>(L.off_lvl[o]);
-            fa.pitch[o] = L.pitch[o];
-        }
-        for (int o = 0; o < L.O; ++o) { fa.w[o] = L.w[o]; fa.h[o] = L.h[o]; }
-        fa.W = L.W; fa.H = L.H; fa.O = L.O; fa.nc = L.nc; fa.nr = L.nr;
-        fa.tile = L.tile;
-        fa.sad_on = sad_on ? 1 : 0;
-        fa.sad_slots = L.sad_slots;
-        fa.sad_lds_off = kpd::frame_sad_lds_off(L.tile, L.O);
-        fa.sad = s->at<uint32_t>(L.off_sad[cur_k]);
-        KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(fa, s->stream); }));
+    *t = kpd::TickArgs{};
+    kpd::FrameArgs& fa = t->f;
+    fa.cur = cur;
+    fa.cur_pitch = cur_pitch;
+    fa.cur_aligned = cur_dw;
+    fa.prev = sad_on ? s->prev0 : cur;
+    fa.prev_pitch = sad_on ? s->prev_pitch : cur_pitch;
+    fa.prev_aligned = sad_on ? s->prev_dw : cur_dw;
+    for (int o = 1; o < L.O; ++o) {
+        fa.lvl[o] = s->at<uint8_t>(L.off_lvl[o]);
+        fa.pitch[o] = L.pitch[o];
     }
+    for (int o = 0; o < L.O; ++o) { fa.w[o] = L.w[o]; fa.h[o] = L.h[o]; }
+    fa.W = L.W; fa.H = L.H; fa.O = L.O; fa.nc = L.nc; fa.nr = L.nr;
+    fa.tile = L.tile;
+    fa.tiles_x = L.tiles_x;
+    fa.ntiles = L.tiles_x * L.tiles_y;
+    fa.sad_on = sad_on ? 1 : 0;
+    fa.sad_slots = L.sad_slots;
+    fa.sad_lds_off = kpd::frame_sad_lds_off(L.tile, L.O);
+    fa.sad = s->at<uint32_t>(L.off_sad[cur_k]);
 
-    kpd::DetectArgs d{};
+    kpd::DetectArgs& d = t->d;
     d.lvl[0] = cur;
     d.pitch[0] = cur_pitch;
     for (int o = 1; o < L.O; ++o) {
@@ -396,13 +406,36 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
     d.status = s->at<unsigned long long>(L.off_status);
     d.epoch = n + 1;
     d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
-    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(d, L.ncell, L.lds_bytes, s->stream); }));
 
-    s->prev0 = cur;
-    s->prev_pitch = cur_pitch;
-    s->prev_dw = cur_dw;
+    t->active = 1;
+    // the tile pass is skipped when there is neither a pyramid nor a SAD to build
+    t->f_on = (L.O > 1 || sad_on) ? 1 : 0;
+    return KPD_OK;
+}
+
+void advance_frame(kpd_stream* s, const kpd::TickArgs& t)
+{
+    s->prev0 = t.f.cur;
+    s->prev_pitch = t.f.cur_pitch;
+    s->prev_dw = t.f.cur_aligned;
     s->force_all = false;
     s->n_pushed += 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
+{
+    kpd::TickArgs t;
+    const int rc = stage_frame(s, frame, pitch_bytes, flags, &t);
+    if (rc != KPD_OK) return rc;
+    const Layout& L = s->L;
+    if (t.f_on)
+        KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(t.f, s->stream); }));
+    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, L.lds_bytes, s->stream); }));
+    advance_frame(s, t);
     return KPD_OK;
 }
 

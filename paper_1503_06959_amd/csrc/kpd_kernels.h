@@ -20,6 +20,8 @@ struct FrameArgs {
     int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];
     int W, H, O, nc, nr;
     int tile;        // level-0 tile side: power of two, >= 2^(O-1), >= 32
+    int tiles_x;     // tiles per row
+    int ntiles;      // tiles in the frame
     int sad_on;
     int sad_slots;   // LDS per-cell partial slots (cells a tile can touch)
     int sad_lds_off;
@@ -57,10 +59,23 @@ struct DetectArgs {
     uint32_t* err;               // set when a wait for an earlier cell gives up
 };
 
+// Everything one stream needs for one batch tick. tile_base and cell_base
+// are the stream's first workgroups in the tick's two launches.
+struct TickArgs {
+    FrameArgs f;
+    DetectArgs d;
+    int active;     // the stream has a frame in this tick
+    int f_on;       // the tile pass runs (pyramid or SAD needed)
+    int tile_base, cell_base;
+};
+
 int frame_sad_lds_off(int tile, int O);
 int frame_lds_bytes(int tile, int O, int sad_slots);
-hipError_t launch_frame(const FrameArgs& a, hipStream_t s);
 hipError_t set_detect_lds_limit(int lds_bytes);
+hipError_t launch_frame(const FrameArgs& a, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s);
+hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s);
+hipError_t launch_detect_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes,
+                               hipStream_t s);
 
 }  // namespace kpd

@@ -1,23 +1,31 @@
 // gfx950 kernels of the masked multi-scale FAST detector. Two launches per
-// frame, both on the caller's stream:
+// frame of one stream (k_frame1, k_detect1) or per batch tick over many
+// streams (k_frame_batch, k_detect_batch); both pairs run the same bodies:
 //
-//   k_frame   one workgroup per level-0 tile (aligned to the coarsest
-//             octave): loads the tile of I_n a dword at a time, builds every
-//             coarser octave of it in LDS by 2x2 box average with round-half-
-//             up (Sec. 2, Sec. 3.1) and writes them out; when the
-//             intensity-difference mask is active it also sums |I_n - I_{n-1}|
-//             per cell (v_sad_u8 per dword, LDS partials, one atomic per
-//             tile and cell) for the per-cell mean-difference test (Sec. 3.1
-//             Eq. 2, read per cell).
-//   k_detect  one workgroup per cell, in cell order: decides
-//             the cell's mark (Eq. 2 from the SAD, Eqs. 3-4 from the cell's
-//             count in D_{n-1}); in a marked cell it stages the pixel tiles of
-//             every octave in LDS, runs the segment test and FAST score over
-//             the cell's score boxes, keeps the scale-space maxima (Sec. 2)
-//             as a bitmask and ranks them with popcounts; a decoupled
-//             look-back over the cells' counts gives every cell its offset in
-//             D_n, and the cell writes its new keypoints there, or copies its
-//             D_{n-1} entries when unmarked (Eq. 1).
+//   frame_tile   one workgroup per level-0 tile, aligned to the coarsest
+//                octave: loads the tile of I_n a dword at a time, builds every
+//                coarser octave of it in LDS by 2x2 box average with
+//                round-half-up (Sec. 2, Sec. 3.1) and writes them out; when
+//                the intensity-difference mask is active it also sums
+//                |I_n - I_{n-1}| per cell (v_sad_u8 per dword, LDS partials,
+//                one atomic per tile and cell) for the per-cell
+//                mean-difference test (Sec. 3.1 Eq. 2, read per cell).
+//   detect_cell  one workgroup per cell, in cell order: decides the cell's
+//                mark (Eq. 2 from the SAD, Eqs. 3-4 from the cell's count in
+//                D_{n-1}); in a marked cell it stages the pixel tiles of every
+//                octave in LDS, runs the segment test and FAST score over the
+//                cell's score boxes, keeps the scale-space maxima (Sec. 2) as
+//                a bitmask and ranks them with popcounts; the counts of
+//                earlier cells give the cell's offset in D_n, where it writes
+//                its new keypoints, or copies its D_{n-1} entries when
+//                unmarked (Eq. 1).
+//
+// The kernel boundary between the two passes publishes the pyramid and the
+// SAD to every XCD at once. Inside the cell pass, a cell only waits for the
+// counts of lower-numbered cells of its stream (relaxed agent-scope count
+// words, no fences); each XCD dispatches its workgroups in index order, so
+// the lowest unfinished cell can always run, and every wait is bounded and
+// sets an error flag instead of hanging.
 #include <hip/hip_runtime.h>
 
 #include "kpd_geom.h"
@@ -37,12 +45,11 @@ __device__ __forceinline__ unsigned fast_div(unsigned i, uint64_t magic)
 
 // ------------------------------------------------------------------ k_frame
 
-__global__ __launch_bounds__(kFrameBlock) void k_frame(FrameArgs a)
+__device__ void frame_tile(const FrameArgs& a, int bx, int by, uint8_t* sm)
 {
-    extern __shared__ __align__(16) uint8_t sm[];
     const int T = a.tile;
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+    const int x0 = bx * T, y0 = by * T;
     const int lgq = __builtin_ctz(T / 4);
 
     // per-level output pointers and sizes, with static indices only
@@ -296,9 +303,8 @@ __device__ __forceinline__ bool cell_marked(const DetectArgs& a, int c)
     return id || kb;
 }
 
-__global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
+__device__ void detect_cell(const DetectArgs& a, int cell, uint8_t* sm)
 {
-    extern __shared__ __align__(16) uint8_t sm[];
     __shared__ CellLayout L;
     __shared__ int s_c, s_mark;
     __shared__ uint32_t s_n, s_excl, s_part[kDetWaves];
@@ -315,12 +321,7 @@ __global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
             s_lvl[o] = a.lvl[o];
             s_pitch[o] = a.pitch[o];
         }
-        // One workgroup per cell, in cell order. A workgroup only ever waits
-        // for lower-numbered cells, and each XCD dispatches its workgroups in
-        // index order, so the lowest unfinished cell can always run; the
-        // bounded spin below turns any failure of that into an error flag
-        // rather than a hang.
-        const int c = blockIdx.x;
+        const int c = cell;
         s_c = c;
         const bool mark = cell_marked(a, c);
         a.mask[c] = (uint8_t)mark;
@@ -565,6 +566,54 @@ __global__ __launch_bounds__(kBlk) void k_detect(DetectArgs a)
     }
 }
 
+// ----------------------------------------------------------------- kernels
+
+// Workgroups are dealt to the 8 XCDs round-robin by index. The tile pass
+// runs on a grid rounded up to a multiple of 8 and hands XCD k the k-th
+// contiguous band of row-major tiles, so tiles that share cache lines share
+// an L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_band_tile(int b, int ntiles)
+{
+    const int per = (ntiles + kXcds - 1) / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+// One frame of one stream.
+__global__ __launch_bounds__(kFrameBlock) void k_frame1(FrameArgs a)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const int tile = xcd_band_tile(blockIdx.x, a.ntiles);
+    if (tile >= a.ntiles) return;
+    frame_tile(a, tile % a.tiles_x, tile / a.tiles_x, sm);
+}
+
+__global__ __launch_bounds__(kBlk) void k_detect1(DetectArgs a)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    detect_cell(a, blockIdx.x, sm);
+}
+
+// One batch tick: workgroup b works for stream map[b] (streams' workgroups
+// are contiguous and in stream order); inactive streams' workgroups exit.
+__global__ __launch_bounds__(kFrameBlock) void k_frame_batch(const TickArgs* table, const uint16_t* map)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const TickArgs& t = table[map[blockIdx.x]];
+    const int local = (int)blockIdx.x - t.tile_base;
+    if (!t.active || !t.f_on) return;
+    frame_tile(t.f, local % t.f.tiles_x, local / t.f.tiles_x, sm);
+}
+
+__global__ __launch_bounds__(kBlk) void k_detect_batch(const TickArgs* table, const uint16_t* map)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const TickArgs& t = table[map[blockIdx.x]];
+    if (!t.active) return;
+    detect_cell(t.d, (int)blockIdx.x - t.cell_base, sm);
+}
+
 // ------------------------------------------------------------- launchers
 
 int frame_sad_lds_off(int tile, int O)
@@ -579,24 +628,39 @@ int frame_lds_bytes(int tile, int O, int sad_slots)
     return frame_sad_lds_off(tile, O) + 4 * sad_slots + 2 * 2 * tile;
 }
 
-hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
-{
-    const int T = a.tile;
-    dim3 grid((a.W + T - 1) / T, (a.H + T - 1) / T);
-    hipLaunchKernelGGL(k_frame, grid, dim3(kFrameBlock), frame_lds_bytes(T, a.O, a.sad_slots), s, a);
-    return hipGetLastError();
-}
-
 hipError_t set_detect_lds_limit(int lds_bytes)
 {
     if (lds_bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect1),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_batch),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+
+hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
+{
+    const int grid = (a.ntiles + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(k_frame1, dim3(grid), dim3(kFrameBlock), frame_lds_bytes(a.tile, a.O, a.sad_slots), s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect, dim3(ncell), dim3(kBlk), lds_bytes, s, a);
+    hipLaunchKernelGGL(k_detect1, dim3(ncell), dim3(kBlk), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_frame_batch, dim3(nblocks), dim3(kFrameBlock), lds_bytes, s, table, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_detect_batch, dim3(nblocks), dim3(kBlk), lds_bytes, s, table, map);
     return hipGetLastError();
 }
 
