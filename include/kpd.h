@@ -70,7 +70,11 @@ extern "C" {
  *              T_I times its pixel count. Negative: every cell is marked
  *              (full-frame detection); >= 255: the test never fires.
  *   kb_thresh  T_H: a cell is marked when D_{n-1} has >= T_H keypoints in it
- *              (Eq. 4). 0: every cell is marked; KPD_KB_OFF: never fires. */
+ *              (Eq. 4). 0: every cell is marked; KPD_KB_OFF: never fires.
+ *   tile       side of the level-0 tiles of the pyramid/difference pass, a
+ *              tuning knob that never changes results: 0 picks the default,
+ *              otherwise a power of two in 32..128 and >= 2^(O-1).
+ *   reserved   must be 0. */
 typedef struct kpd_params {
     int32_t fast_t;
     int32_t n_octaves;
@@ -78,6 +82,8 @@ typedef struct kpd_params {
     int32_t grid_rows;
     int32_t id_thresh;
     uint32_t kb_thresh;
+    int32_t tile;
+    int32_t reserved;
 } kpd_params;
 
 /* One feature of D_n (Sec. 3: position and scale; the integer part).
@@ -143,6 +149,43 @@ int reset_stream(kpd_stream* s);
 
 /* Message of the last failing call on this thread ("" when none). */
 const char* kpd_last_error(void);
+
+/* ------------------------------------------------------------- batching */
+
+/* A batch runs the next frame of many streams (of any sizes and parameters)
+ * in one tick: two launches that cover every attached stream with a staged
+ * frame, optionally replayed from a captured HIP graph. Results are exactly
+ * those of pushing each stream's frame alone. */
+typedef struct kpd_batch kpd_batch;
+
+/* Device scratch bytes of a batch holding up to `max_streams` streams whose
+ * tiles and cells need at most `max_blocks` workgroups per launch. */
+size_t batch_bytes(int max_streams, int max_blocks);
+
+/* Open a batch on `hip_stream`; `dev_scratch` (caller-owned, 256-byte
+ * aligned, >= batch_bytes()) holds the tick tables. use_graph = 1 captures
+ * each tick's table upload and launches once per set of attached streams
+ * and replays it. */
+int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
+               int use_graph, kpd_batch** out);
+
+/* Attach or detach a stream. The stream must have been opened on the
+ * batch's HIP stream. KPD_ENOMEM when the batch's stream or workgroup
+ * capacity would be exceeded. */
+int batch_attach(kpd_batch* b, kpd_stream* s);
+int batch_detach(kpd_batch* b, kpd_stream* s);
+
+/* Stage the next frame of an attached stream for the next tick (same frame
+ * and flag rules as push_frame; a copy is enqueued at once). At most one
+ * frame per stream per tick: KPD_ESTATE if one is already staged. */
+int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
+
+/* Run one tick over every attached stream with a staged frame.
+ * Asynchronous; get_keypoints on a stream waits for it. */
+int batch_tick(kpd_batch* b);
+
+/* Wait for the batch's work and release it. Attached streams stay open. */
+int close_batch(kpd_batch* b);
 
 /* ------------------------------------------------------- inspection calls */
 

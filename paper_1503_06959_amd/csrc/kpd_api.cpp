@@ -79,6 +79,12 @@ bool valid_params(int W, int H, const kpd_params* p, std::string* why)
         *why = "cells larger than KPD_MAX_CELL pixels";
         return false;
     }
+    if (p->tile != 0 && (p->tile < 32 || p->tile > 128 || (p->tile & (p->tile - 1)) ||
+                         p->tile < (1 << (p->n_octaves - 1)))) {
+        *why = "tile must be 0 or a power of two in 32..128 and >= 2^(O-1)";
+        return false;
+    }
+    if (p->reserved != 0) { *why = "reserved must be 0"; return false; }
     return true;
 }
 
@@ -93,7 +99,7 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->pitch[o] = kpd::round_up(L->w[o], 64);
     }
     L->slot_pitch = kpd::round_up(W, 64);
-    L->tile = std::max(32, 1 << (L->O - 1));
+    L->tile = p->tile ? p->tile : std::max(32, 1 << (L->O - 1));
     L->tiles_x = (W + L->tile - 1) / L->tile;
     L->tiles_y = (H + L->tile - 1) / L->tile;
 
@@ -530,6 +536,247 @@ int kpd_cell_stats(kpd_stream* s, uint32_t* sad, uint32_t* counts)
     if (counts)
         KPD_HIP(hipMemcpyAsync(counts, s->at<uint32_t>(s->L.off_count[k]), n, hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
+    return KPD_OK;
+}
+
+// ---------------------------------------------------------------- batching
+
+}  // extern "C"
+
+struct kpd_batch {
+    hipStream_t stream = nullptr;
+    int max_streams = 0, max_blocks = 0;
+    bool use_graph = true;
+    uint8_t* scratch = nullptr;
+    kpd::TickArgs* dev_table[2] = {nullptr, nullptr};
+    uint16_t* dev_fmap = nullptr;
+    uint16_t* dev_cmap = nullptr;
+    kpd::TickArgs* host_table[2] = {nullptr, nullptr};  // pinned
+    hipEvent_t table_free[2] = {nullptr, nullptr};      // upload of host_table[k] done
+    bool table_used[2] = {false, false};
+    std::vector<kpd_stream*> streams;
+    std::vector<kpd::TickArgs> staged;                  // per attached stream
+    std::vector<char> has_frame;
+    int frame_blocks = 0, cell_blocks = 0;
+    int frame_lds = 16, detect_lds = 16;
+    bool maps_dirty = true;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    uint64_t ticks = 0;
+};
+
+namespace {
+
+size_t batch_layout(int max_streams, int max_blocks, size_t* off_table, size_t* off_fmap, size_t* off_cmap)
+{
+    size_t off = 0;
+    off_table[0] = off; off = align_up(off + (size_t)max_streams * sizeof(kpd::TickArgs));
+    off_table[1] = off; off = align_up(off + (size_t)max_streams * sizeof(kpd::TickArgs));
+    *off_fmap = off; off = align_up(off + (size_t)max_blocks * 2);
+    *off_cmap = off; off = align_up(off + (size_t)max_blocks * 2);
+    return off;
+}
+
+void drop_graphs(kpd_batch* b)
+{
+    for (int k = 0; k < 2; ++k)
+        if (b->graph[k]) { hipGraphExecDestroy(b->graph[k]); b->graph[k] = nullptr; }
+}
+
+// Rebuild the workgroup -> stream maps after the attached set changed.
+int rebuild_maps(kpd_batch* b)
+{
+    std::vector<uint16_t> fmap, cmap;
+    int fl = 16, dl = 16;
+    for (size_t i = 0; i < b->streams.size(); ++i) {
+        const Layout& L = b->streams[i]->L;
+        const int nt = L.tiles_x * L.tiles_y;
+        fmap.insert(fmap.end(), (size_t)nt, (uint16_t)i);
+        cmap.insert(cmap.end(), (size_t)L.ncell, (uint16_t)i);
+        fl = std::max(fl, kpd::frame_lds_bytes(L.tile, L.O, L.sad_slots));
+        dl = std::max(dl, L.lds_bytes);
+    }
+    if ((int)fmap.size() > b->max_blocks || (int)cmap.size() > b->max_blocks)
+        return fail(KPD_ENOMEM, "batch workgroup capacity exceeded");
+    KPD_HIP(hipStreamSynchronize(b->stream));  // no tick in flight reads the old maps
+    if (!fmap.empty()) KPD_HIP(hipMemcpy(b->dev_fmap, fmap.data(), fmap.size() * 2, hipMemcpyHostToDevice));
+    if (!cmap.empty()) KPD_HIP(hipMemcpy(b->dev_cmap, cmap.data(), cmap.size() * 2, hipMemcpyHostToDevice));
+    KPD_HIP(kpd::set_detect_lds_limit(dl));
+    b->frame_blocks = (int)fmap.size();
+    b->cell_blocks = (int)cmap.size();
+    b->frame_lds = fl;
+    b->detect_lds = dl;
+    drop_graphs(b);
+    b->maps_dirty = false;
+    return KPD_OK;
+}
+
+// Enqueue one tick reading table k: upload, tile pass, cell pass.
+hipError_t enqueue_tick(kpd_batch* b, int k)
+{
+    const size_t n = b->streams.size();
+    hipError_t e = hipMemcpyAsync(b->dev_table[k], b->host_table[k], n * sizeof(kpd::TickArgs),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->frame_blocks)
+        e = kpd::launch_frame_batch(b->dev_table[k], b->dev_fmap, b->frame_blocks, b->frame_lds, b->stream);
+    if (e == hipSuccess && b->cell_blocks)
+        e = kpd::launch_detect_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->detect_lds, b->stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t batch_bytes(int max_streams, int max_blocks)
+{
+    if (max_streams < 1 || max_streams > 65535 || max_blocks < 1) return 0;
+    size_t t[2], f, c;
+    return batch_layout(max_streams, max_blocks, t, &f, &c);
+}
+
+int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
+               int use_graph, kpd_batch** out)
+{
+    if (!out) return fail(KPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_streams < 1 || max_streams > 65535 || max_blocks < 1) return fail(KPD_EINVAL, "bad batch capacity");
+    size_t t[2], f, c;
+    const size_t need = batch_layout(max_streams, max_blocks, t, &f, &c);
+    if (!dev_scratch || reinterpret_cast<uintptr_t>(dev_scratch) % kAlign)
+        return fail(KPD_EINVAL, "scratch is NULL or not 256-byte aligned");
+    if (scratch_bytes < need) return fail(KPD_ENOMEM, "batch scratch too small");
+    kpd_batch* b = new (std::nothrow) kpd_batch();
+    if (!b) return fail(KPD_ENOMEM, "host allocation failed");
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->max_streams = max_streams;
+    b->max_blocks = max_blocks;
+    b->use_graph = use_graph != 0;
+    b->scratch = reinterpret_cast<uint8_t*>(dev_scratch);
+    for (int k = 0; k < 2; ++k) b->dev_table[k] = reinterpret_cast<kpd::TickArgs*>(b->scratch + t[k]);
+    b->dev_fmap = reinterpret_cast<uint16_t*>(b->scratch + f);
+    b->dev_cmap = reinterpret_cast<uint16_t*>(b->scratch + c);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->host_table[k]), (size_t)max_streams * sizeof(kpd::TickArgs),
+                          hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->table_free[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        close_batch(b);
+        return hip_fail(e, "open_batch");
+    }
+    *out = b;
+    return KPD_OK;
+}
+
+int batch_attach(kpd_batch* b, kpd_stream* s)
+{
+    if (!b || !s || s->closed) return fail(KPD_ESTATE, "batch or stream is closed");
+    if (s->stream != b->stream) return fail(KPD_EINVAL, "stream was opened on another HIP stream");
+    if (std::find(b->streams.begin(), b->streams.end(), s) != b->streams.end())
+        return fail(KPD_EINVAL, "stream already attached");
+    if ((int)b->streams.size() >= b->max_streams) return fail(KPD_ENOMEM, "batch stream capacity exceeded");
+    b->streams.push_back(s);
+    b->staged.push_back(kpd::TickArgs{});
+    b->has_frame.push_back(0);
+    const int rc = rebuild_maps(b);
+    if (rc != KPD_OK) {
+        b->streams.pop_back();
+        b->staged.pop_back();
+        b->has_frame.pop_back();
+        rebuild_maps(b);
+    }
+    return rc;
+}
+
+int batch_detach(kpd_batch* b, kpd_stream* s)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    auto it = std::find(b->streams.begin(), b->streams.end(), s);
+    if (it == b->streams.end()) return fail(KPD_EINVAL, "stream not attached");
+    const size_t i = (size_t)(it - b->streams.begin());
+    if (b->has_frame[i]) return fail(KPD_ESTATE, "stream has a staged frame; tick first");
+    b->streams.erase(it);
+    b->staged.erase(b->staged.begin() + (long)i);
+    b->has_frame.erase(b->has_frame.begin() + (long)i);
+    return rebuild_maps(b);
+}
+
+int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    auto it = std::find(b->streams.begin(), b->streams.end(), s);
+    if (it == b->streams.end()) return fail(KPD_EINVAL, "stream not attached");
+    const size_t i = (size_t)(it - b->streams.begin());
+    if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
+    const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
+    if (rc != KPD_OK) return rc;
+    b->has_frame[i] = 1;
+    return KPD_OK;
+}
+
+int batch_tick(kpd_batch* b)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (b->maps_dirty) {
+        const int rc = rebuild_maps(b);
+        if (rc != KPD_OK) return rc;
+    }
+    const int k = (int)(b->ticks & 1);
+    // the previous upload from this host table must have left it
+    if (b->table_used[k]) KPD_HIP(hipEventSynchronize(b->table_free[k]));
+    int fbase = 0, cbase = 0;
+    bool any = false;
+    for (size_t i = 0; i < b->streams.size(); ++i) {
+        kpd::TickArgs t = b->has_frame[i] ? b->staged[i] : kpd::TickArgs{};
+        const Layout& L = b->streams[i]->L;
+        t.active = b->has_frame[i] ? 1 : 0;
+        t.tile_base = fbase;
+        t.cell_base = cbase;
+        fbase += L.tiles_x * L.tiles_y;
+        cbase += L.ncell;
+        b->host_table[k][i] = t;
+        any = any || t.active;
+    }
+    if (!any) return KPD_OK;
+    if (b->use_graph) {
+        if (!b->graph[k]) {
+            hipGraph_t g = nullptr;
+            KPD_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t ce = enqueue_tick(b, k);
+            const hipError_t ee = hipStreamEndCapture(b->stream, &g);
+            if (ce != hipSuccess) { if (g) hipGraphDestroy(g); return hip_fail(ce, "batch tick capture"); }
+            if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+            const hipError_t ie = hipGraphInstantiate(&b->graph[k], g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ie != hipSuccess) { b->graph[k] = nullptr; return hip_fail(ie, "hipGraphInstantiate"); }
+        }
+        KPD_HIP(hipGraphLaunch(b->graph[k], b->stream));
+    } else {
+        KPD_HIP(enqueue_tick(b, k));
+    }
+    KPD_HIP(hipEventRecord(b->table_free[k], b->stream));
+    b->table_used[k] = true;
+    for (size_t i = 0; i < b->streams.size(); ++i)
+        if (b->has_frame[i]) {
+            advance_frame(b->streams[i], b->staged[i]);
+            b->has_frame[i] = 0;
+        }
+    b->ticks += 1;
+    return KPD_OK;
+}
+
+int close_batch(kpd_batch* b)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    const hipError_t e = hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    for (int k = 0; k < 2; ++k) {
+        if (b->host_table[k]) hipHostFree(b->host_table[k]);
+        if (b->table_free[k]) hipEventDestroy(b->table_free[k]);
+    }
+    delete b;
+    if (e != hipSuccess) return hip_fail(e, "close_batch");
     return KPD_OK;
 }
 

@@ -29,14 +29,16 @@ FRAME_HOST, FRAME_DEVICE, FRAME_DEVICE_RETAIN = 0, 1, 2
 KEYPOINT_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2")])
 EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_keypoints",
             "close_stream", "reset_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats",
-            "kpd_pyramid_level", "kpd_profile", "kpd_profile_read")
+            "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
+            "batch_attach", "batch_detach", "batch_push", "batch_tick", "close_batch")
 KERNEL_NAMES = ("k_frame", "k_detect")
 
 
 class KpdParams(ctypes.Structure):
     _fields_ = [("fast_t", ctypes.c_int32), ("n_octaves", ctypes.c_int32),
                 ("grid_cols", ctypes.c_int32), ("grid_rows", ctypes.c_int32),
-                ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32)]
+                ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32),
+                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KpdError(RuntimeError):
@@ -67,6 +69,14 @@ def _load() -> ctypes.CDLL:
     L.reset_stream.argtypes = [P]
     L.kpd_profile.argtypes = [P, ctypes.c_int]
     L.kpd_profile_read.argtypes = [P, P, P]
+    L.batch_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.batch_bytes.restype = sz
+    L.open_batch.argtypes = [ctypes.c_int, ctypes.c_int, P, sz, P, ctypes.c_int, ctypes.POINTER(P)]
+    L.batch_attach.argtypes = [P, P]
+    L.batch_detach.argtypes = [P, P]
+    L.batch_push.argtypes = [P, P, P, sz, ctypes.c_int]
+    L.batch_tick.argtypes = [P]
+    L.close_batch.argtypes = [P]
     return L
 
 
@@ -80,8 +90,8 @@ def _check(rc: int) -> int:
 
 
 def make_params(fast_t: int, n_octaves: int, grid_cols: int, grid_rows: int,
-                id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF) -> KpdParams:
-    return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF)
+                id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0) -> KpdParams:
+    return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, 0)
 
 
 def stream_bytes(width: int, height: int, params: KpdParams) -> int:
@@ -178,6 +188,49 @@ def device_result(handle: int) -> Tuple[int, int]:
     lst, cnt = ctypes.c_void_p(), ctypes.c_void_p()
     _check(lib.kpd_device_result(handle, ctypes.byref(lst), ctypes.byref(cnt)))
     return lst.value, cnt.value
+
+
+def _frame_args(frame, retain: bool):
+    if isinstance(frame, np.ndarray):
+        if frame.dtype != np.uint8 or frame.ndim != 2 or frame.strides[1] != 1:
+            raise ValueError("host frame must be a uint8 [H, W] array with unit column stride")
+        return frame.ctypes.data, frame.strides[0], FRAME_HOST
+    if not (isinstance(frame, torch.Tensor) and frame.device.type == "cuda" and frame.dtype == torch.uint8
+            and frame.dim() == 2 and frame.stride(1) == 1):
+        raise ValueError("device frame must be a CUDA uint8 [H, W] tensor with unit column stride")
+    return frame.data_ptr(), frame.stride(0), FRAME_DEVICE_RETAIN if retain else FRAME_DEVICE
+
+
+def batch_bytes(max_streams: int, max_blocks: int) -> int:
+    return lib.batch_bytes(max_streams, max_blocks)
+
+
+def open_batch(max_streams: int, max_blocks: int, scratch: torch.Tensor, stream, use_graph: bool = True) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.open_batch(max_streams, max_blocks, scratch.data_ptr(), scratch.numel(), _stream_ptr(stream),
+                          1 if use_graph else 0, ctypes.byref(h)))
+    return h.value
+
+
+def batch_attach(batch: int, handle: int) -> None:
+    _check(lib.batch_attach(batch, handle))
+
+
+def batch_detach(batch: int, handle: int) -> None:
+    _check(lib.batch_detach(batch, handle))
+
+
+def batch_push(batch: int, handle: int, frame, retain: bool = False) -> None:
+    ptr, pitch, flags = _frame_args(frame, retain)
+    _check(lib.batch_push(batch, handle, ptr, pitch, flags))
+
+
+def batch_tick(batch: int) -> None:
+    _check(lib.batch_tick(batch))
+
+
+def close_batch(batch: int) -> None:
+    _check(lib.close_batch(batch))
 
 
 class Stream:

@@ -1,0 +1,158 @@
+"""GPU parity of batched ticks: many streams of mixed resolutions and
+parameters advance one frame per tick through two table-driven launches
+(replayed from a captured HIP graph), and every stream's keypoints and mask
+must equal its own oracle run, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06959_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KB_OFF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def kpd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_06959_amd import kpd as k
+    return k
+
+
+def tuples(arr):
+    return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
+
+
+def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode="retain"):
+    """specs: list of (Scene, (t, O, Nc, Nr, TI, TH, tile)). Every tick each
+    stream not skipped pushes its next frame; after the tick every stream's
+    D_n and mask are compared with its oracle."""
+    import torch
+    from paper_1503_06959_amd.batch import Batch
+    b = Batch(max_streams=len(specs) + 2, use_graph=use_graph)
+    streams = []
+    for sc, det in specs:
+        t, O, Nc, Nr, TI, TH, tile = det
+        frames = synth.make_video(sc, n_ticks)
+        g = b.open_stream(sc.width, sc.height, kpd.make_params(t, O, Nc, Nr, TI, TH, tile))
+        o = oracle.Stream(sc.width, sc.height, t, O, Nc, Nr, TI, TH)
+        dev = torch.from_numpy(frames).cuda() if mode != "host" else None
+        streams.append(dict(g=g, o=o, frames=frames, dev=dev, next=0))
+    torch.cuda.synchronize()
+    for tick in range(n_ticks):
+        pushed = []
+        for si, st in enumerate(streams):
+            if skip(si, tick) or st["next"] >= n_ticks:
+                continue
+            i = st["next"]
+            if mode == "host":
+                b.push(st["g"], st["frames"][i])
+            else:
+                with torch.cuda.stream(b.torch_stream):
+                    b.push(st["g"], st["dev"][i], retain=(mode == "retain"))
+            st["o"].push(st["frames"][i])
+            st["next"] += 1
+            pushed.append(si)
+        b.tick()
+        for si in pushed:
+            st = streams[si]
+            gk, gm = st["g"].keypoints()
+            ok, om, _, _ = st["o"].get()
+            assert tuples(gk) == tuples(ok), f"stream {si} tick {tick}"
+            np.testing.assert_array_equal(gm, om, err_msg=f"mask stream {si} tick {tick}")
+    b.close()
+    return streams
+
+
+def mixed_specs(n=8, seed0=4000):
+    specs = []
+    for s in range(n):
+        res = [(320, 240), (640, 480), (1280, 720)][s % 3]
+        det, m, smin, smax, sig = synth.RES_PRESETS[res]
+        sc = synth.Scene(res[0], res[1], 8, m, smin, smax, synth.MOTION_LEVELS[s % 3], sig, False, seed0 + s)
+        TI, TH = [(8, KB_OFF), (4, 2), (-1, KB_OFF), (255, 1)][s % 4]
+        specs.append((sc, (det.fast_t, det.n_octaves, det.grid_cols, det.grid_rows, TI, TH, 0)))
+    return specs
+
+
+def test_mixed_streams_graph(kpd):
+    run_batch(kpd, mixed_specs(8), 6, use_graph=True)
+
+
+def test_mixed_streams_eager_and_host_frames(kpd):
+    run_batch(kpd, mixed_specs(5, 4100), 4, use_graph=False, mode="host")
+
+
+def test_streams_skipping_ticks(kpd):
+    # streams with no frame in a tick are inactive; their state must not move
+    run_batch(kpd, mixed_specs(6, 4200), 7, use_graph=True, skip=lambda s, t: (s + t) % 3 == 0)
+
+
+def test_tile_size_does_not_change_results(kpd):
+    base = mixed_specs(3, 4300)
+    specs = []
+    for sc, det in base:
+        for tile in (0, 64, 128):
+            if tile and tile < (1 << (det[1] - 1)):
+                continue
+            specs.append((sc, det[:6] + (tile,)))
+    run_batch(kpd, specs, 4)
+
+
+def test_batch_of_64_mixed_streams(kpd):
+    specs = []
+    for sc, det in synth.batch_streams(8):
+        specs.append((sc, (det.fast_t, det.n_octaves, det.grid_cols, det.grid_rows, det.id_thresh,
+                           det.kb_thresh, 0)))
+    run_batch(kpd, specs, 8)
+
+
+def test_attach_detach_between_ticks(kpd):
+    import torch
+    from paper_1503_06959_amd.batch import Batch
+    b = Batch(max_streams=4)
+    sc = synth.SCENES["c1_320x240"]
+    frames = synth.make_video(sc, 6)
+    p = kpd.make_params(30, 3, 8, 6, 8)
+    g1 = b.open_stream(320, 240, p)
+    o1 = oracle.Stream(320, 240, 30, 3, 8, 6, 8)
+    g2 = b.open_stream(320, 240, p)
+    o2 = oracle.Stream(320, 240, 30, 3, 8, 6, 8)
+    for i in range(6):
+        if i == 2:
+            b.detach(g2)
+        if i == 4:
+            b.attach(g2)
+        b.push(g1, frames[i])
+        o1.push(frames[i])
+        if i < 2 or i >= 4:
+            b.push(g2, frames[i])
+            o2.push(frames[i])
+        b.tick()
+        assert tuples(g1.keypoints()[0]) == tuples(o1.get()[0])
+        if i < 2 or i >= 4:
+            assert tuples(g2.keypoints()[0]) == tuples(o2.get()[0])
+    b.close()
+
+
+def test_batch_errors(kpd):
+    import ctypes
+    from paper_1503_06959_amd.batch import Batch
+    b = Batch(max_streams=1)
+    p = kpd.make_params(30, 3, 8, 6, 8)
+    g = b.open_stream(320, 240, p)
+    f = synth.make_video(synth.SCENES["c1_320x240"], 1)[0]
+    b.push(g, f)
+    # one frame per stream per tick
+    assert kpd.lib.batch_push(b.handle, g.handle, f.ctypes.data, 320, 0) == kpd.KPD_ESTATE
+    # capacity
+    other = kpd.Stream(320, 240, p, stream=b.torch_stream)
+    assert kpd.lib.batch_attach(b.handle, other.handle) == kpd.KPD_ENOMEM
+    # a stream on another HIP stream
+    b.tick()
+    g.keypoints()
+    other.close()
+    b.close()
