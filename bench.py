@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-hd", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-ticks", type=int, default=120)
+    ap.add_argument("--batch-clip", type=int, default=40)
     return ap.parse_args()
 
 
@@ -224,6 +227,102 @@ def cpu_baseline(wl: Workload, seconds: float):
     }
 
 
+def _gen_clip(args):
+    from paper_1503_06959_amd import synth
+    sc, n = args
+    return synth.make_video(sc, n)
+
+
+def pingpong(k: int, n: int) -> int:
+    """Index of tick k when an n-frame clip plays forward and back."""
+    if n == 1:
+        return 0
+    m = k % (2 * n - 2)
+    return m if m < n else 2 * n - 2 - m
+
+
+def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
+    """64 mixed-resolution streams (24 x 320x240, 24 x 640x480, 16 x 1280x720),
+    one frame each per tick: batched ticks (two graph-replayed launches per
+    tick) against plain per-stream pushes (two launches per stream and
+    frame) over the same frames."""
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1503_06959_amd import autotune, synth
+    from paper_1503_06959_amd.batch import Batch
+    specs = synth.batch_streams(clip)
+    t0 = time.time()
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        clips = list(ex.map(_gen_clip, [(sc, clip) for sc, _ in specs]))
+    log(f"[bench] generated 64 clips of {clip} frames in {time.time() - t0:.1f}s")
+    devs = [torch.from_numpy(c).cuda() for c in clips]
+    tiles = {}
+    for sc, det in specs:
+        key = autotune.class_key(sc.width, sc.height, det)
+        if key not in tiles:
+            tiles[key] = autotune.best_tile(sc.width, sc.height, det)[0]
+    px_per_tick = sum(sc.width * sc.height for sc, _ in specs)
+
+    b = Batch(max_streams=len(specs))
+    bs = [b.open_stream(sc.width, sc.height,
+                        kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, d.id_thresh, d.kb_thresh,
+                                        tiles[autotune.class_key(sc.width, sc.height, d)]))
+          for sc, d in specs]
+    push = kpd.lib.batch_push
+    def tick(k):
+        i = pingpong(k, clip)
+        for s, dev in zip(bs, devs):
+            rc = push(b.handle, s.handle, dev[i].data_ptr(), dev.shape[2], kpd.FRAME_DEVICE_RETAIN)
+            if rc:
+                raise kpd.KpdError(rc, kpd.lib.kpd_last_error().decode())
+        kpd.batch_tick(b.handle)
+    for k in range(warmup):
+        tick(k)
+    b.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + n_ticks):
+        tick(k)
+    b.synchronize()
+    sec_b = (time.perf_counter() - t0) / n_ticks
+    for s in bs:
+        b.detach(s)
+        s.close()
+    b.close()
+
+    ts = torch.cuda.Stream()
+    ps = [kpd.Stream(sc.width, sc.height,
+                     kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, d.id_thresh, d.kb_thresh),
+                     stream=ts) for sc, d in specs]
+    pf = kpd.lib.push_frame
+    def plain(k):
+        i = pingpong(k, clip)
+        for s, dev in zip(ps, devs):
+            rc = pf(s.handle, dev[i].data_ptr(), dev.shape[2], kpd.FRAME_DEVICE_RETAIN)
+            if rc:
+                raise kpd.KpdError(rc, kpd.lib.kpd_last_error().decode())
+    for k in range(warmup):
+        plain(k)
+    ts.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + n_ticks):
+        plain(k)
+    ts.synchronize()
+    sec_p = (time.perf_counter() - t0) / n_ticks
+    for s in ps:
+        s.close()
+    return {
+        "workload": f"64 streams (24 x 320x240, 24 x 640x480, 16 x 1280x720), {clip}-frame clips played "
+                    f"forward and back, {n_ticks} timed ticks, T_I=8, per-resolution presets",
+        "batched": {"mpix_per_s": round(px_per_tick / sec_b / 1e6, 2), "frames_per_s": round(64 / sec_b, 1),
+                    "ms_per_tick": round(sec_b * 1e3, 4), "launches_per_tick": 2, "hip_graph": True,
+                    "tiles": tiles},
+        "plain_per_stream": {"mpix_per_s": round(px_per_tick / sec_p / 1e6, 2),
+                             "frames_per_s": round(64 / sec_p, 1), "ms_per_tick": round(sec_p * 1e3, 4),
+                             "launches_per_tick": 128},
+        "batched_over_plain": round(sec_p / sec_b, 3),
+    }
+
+
 def copy_calibration(mib: int) -> None:
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters read on the detection kernels."""
@@ -313,10 +412,16 @@ def main():
                            "roofline": roofline_of(hd, hf, False)},
         }
         wl = hd
+    if not args.no_batch:
+        del wl
+        torch.cuda.empty_cache()
+        log("[bench] batched 64-stream ticks")
+        out["batched_64_streams"] = batched_workload(kpd, args.batch_ticks, args.batch_clip, args.warmup)
+        wl = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         from paper_1503_06959_amd import synth
-        base = Workload(args.workload) if wl.name != args.workload else wl
+        base = Workload(args.workload) if wl is None or wl.name != args.workload else wl
         out["cpu_baseline"] = cpu_baseline(base, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
