@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-horizon", type=float, default=48.0)
+    ap.add_argument("--serve-speedup", type=float, default=4.0)
+    ap.add_argument("--serve-budget-mib", type=int, default=1024)
     ap.add_argument("--batch-ticks", type=int, default=120)
     ap.add_argument("--batch-clip", type=int, default=40)
     return ap.parse_args()
@@ -323,6 +327,36 @@ def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
     }
 
 
+def serving_workload(horizon: float, speedup: float, budget_mib: int) -> dict:
+    """Poisson arrivals (8 streams/s, 200-2000 frames at 30 fps, resolutions
+    uniform over 320x240 .. 1920x1080), at most 256 concurrent streams,
+    admitted against an HBM budget; batched ticks against plain per-stream
+    pushes on the same request trace."""
+    import torch
+    from paper_1503_06959_amd import autotune, kpd, serve, synth
+    t0 = time.time()
+    bank = serve.ClipBank(n_clips=2, clip_len=48, workers=min(16, os.cpu_count() or 1))
+    log(f"[bench] serving clip bank ready in {time.time() - t0:.1f}s")
+    tiles = {}
+    for res in serve.RESOLUTIONS:
+        tiles[res] = autotune.best_tile(res[0], res[1], synth.RES_PRESETS[res][0])[0]
+    reqs = serve.poisson_requests(8.0, horizon, 5000, clip_len=48)
+    out = {"workload": f"Poisson arrivals 8 streams/s for {horizon:.0f}s of stream time (x{speedup:g} wall speed), "
+                       f"200-2000 frames at 30 fps, resolutions uniform over "
+                       f"{'/'.join(f'{w}x{h}' for w, h in serve.RESOLUTIONS)}, <= 256 concurrent, "
+                       f"HBM budget {budget_mib} MiB, {len(reqs)} requests"}
+    for cls in (serve.BatchedBackend, serve.PlainBackend):
+        be = cls(max_streams=256, tiles=tiles)
+        srv = serve.Server(be, bank, reqs, budget_bytes=budget_mib << 20, max_streams=256, speedup=speedup)
+        st = srv.run(horizon)
+        be.shutdown()
+        torch.cuda.synchronize()
+        out[be.name] = st.summary()
+        log(f"[bench] serving {be.name}: {out[be.name]}")
+    out["batched_over_plain_mpix"] = round(out["batched"]["mpix_per_s"] / max(out["plain"]["mpix_per_s"], 1e-9), 3)
+    return out
+
+
 def copy_calibration(mib: int) -> None:
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters read on the detection kernels."""
@@ -418,6 +452,11 @@ def main():
         log("[bench] batched 64-stream ticks")
         out["batched_64_streams"] = batched_workload(kpd, args.batch_ticks, args.batch_clip, args.warmup)
         wl = None
+    if not args.no_serve:
+        wl = None
+        torch.cuda.empty_cache()
+        log("[bench] serving")
+        out["serving"] = serving_workload(args.serve_horizon, args.serve_speedup, args.serve_budget_mib)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         from paper_1503_06959_amd import synth

@@ -184,6 +184,15 @@ int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_b
  * Asynchronous; get_keypoints on a stream waits for it. */
 int batch_tick(kpd_batch* b);
 
+/* Gather the results of the last tick: counts[i] (uint32, device memory)
+ * receives the size of D_n of the i-th attached stream (attach order; 0 for
+ * streams without a frame in that tick), and `out` (device memory, `out_cap`
+ * entries) their keypoints concatenated in that order, each stream's in
+ * D_n's own order. Entries past out_cap are dropped; the counts still report
+ * full sizes. Asynchronous on the batch's HIP stream; must follow the tick
+ * it gathers, before the next tick. */
+int batch_gather(kpd_batch* b, kpd_keypoint* out, size_t out_cap, uint32_t* counts);
+
 /* Wait for the batch's work and release it. Attached streams stay open. */
 int close_batch(kpd_batch* b);
 

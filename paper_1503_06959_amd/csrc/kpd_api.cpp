@@ -766,6 +766,18 @@ int batch_tick(kpd_batch* b)
     return KPD_OK;
 }
 
+int batch_gather(kpd_batch* b, kpd_keypoint* out, size_t out_cap, uint32_t* counts)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!out || !counts) return fail(KPD_EINVAL, "NULL output");
+    if (b->ticks == 0) return fail(KPD_ESTATE, "no tick yet");
+    if (b->streams.empty()) return KPD_OK;
+    const int k = (int)((b->ticks - 1) & 1);
+    const uint32_t cap = out_cap > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)out_cap;
+    KPD_HIP(kpd::launch_gather_batch(b->dev_table[k], (int)b->streams.size(), out, cap, counts, b->stream));
+    return KPD_OK;
+}
+
 int close_batch(kpd_batch* b)
 {
     if (!b) return fail(KPD_ESTATE, "batch is closed");

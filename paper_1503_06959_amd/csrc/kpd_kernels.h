@@ -75,6 +75,8 @@ hipError_t set_detect_lds_limit(int lds_bytes);
 hipError_t launch_frame(const FrameArgs& a, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s);
 hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s);
+hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, uint32_t out_cap, uint32_t* counts,
+                               hipStream_t s);
 hipError_t launch_detect_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes,
                                hipStream_t s);
 

@@ -614,7 +614,35 @@ __global__ __launch_bounds__(kBlk) void k_detect_batch(const TickArgs* table, co
     detect_cell(t.d, (int)blockIdx.x - t.cell_base, sm);
 }
 
+// Concatenate the D_n of every active stream of a tick table (one workgroup
+// per stream; offsets from the counts of lower-numbered streams).
+__global__ __launch_bounds__(256) void k_gather_batch(const TickArgs* table, int n, kpd_keypoint* out,
+                                                      uint32_t out_cap, uint32_t* counts)
+{
+    const int i = blockIdx.x;
+    __shared__ uint32_t s_part[4];
+    uint32_t acc = 0;
+    for (int j = threadIdx.x; j < i; j += 256)
+        if (table[j].active) acc += *table[j].d.total_cur;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const uint32_t base = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    const TickArgs& t = table[i];
+    const uint32_t cnt = t.active ? *t.d.total_cur : 0u;
+    if (threadIdx.x == 0) counts[i] = cnt;
+    for (uint32_t k = threadIdx.x; k < cnt; k += 256)
+        if (base + k < out_cap) out[base + k] = t.d.list_cur[k];
+}
+
 // ------------------------------------------------------------- launchers
+
+hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, uint32_t out_cap, uint32_t* counts,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_batch, dim3(n), dim3(256), 0, s, table, n, out, out_cap, counts);
+    return hipGetLastError();
+}
 
 int frame_sad_lds_off(int tile, int O)
 {

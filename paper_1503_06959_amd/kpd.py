@@ -30,7 +30,7 @@ KEYPOINT_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("octave", "u1"), ("pad",
 EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_keypoints",
             "close_stream", "reset_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats",
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
-            "batch_attach", "batch_detach", "batch_push", "batch_tick", "close_batch")
+            "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch")
 KERNEL_NAMES = ("k_frame", "k_detect")
 
 
@@ -76,6 +76,7 @@ def _load() -> ctypes.CDLL:
     L.batch_detach.argtypes = [P, P]
     L.batch_push.argtypes = [P, P, P, sz, ctypes.c_int]
     L.batch_tick.argtypes = [P]
+    L.batch_gather.argtypes = [P, P, sz, P]
     L.close_batch.argtypes = [P]
     return L
 
@@ -227,6 +228,12 @@ def batch_push(batch: int, handle: int, frame, retain: bool = False) -> None:
 
 def batch_tick(batch: int) -> None:
     _check(lib.batch_tick(batch))
+
+
+def batch_gather(batch: int, out: torch.Tensor, counts: torch.Tensor) -> None:
+    """out: CUDA uint8 tensor viewed as keypoint records (8 bytes each);
+    counts: CUDA int32/uint32 tensor with one entry per attached stream."""
+    _check(lib.batch_gather(batch, out.data_ptr(), out.numel() // 8, counts.data_ptr()))
 
 
 def close_batch(batch: int) -> None:
