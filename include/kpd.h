@@ -52,6 +52,7 @@ extern "C" {
 #define KPD_MAX_OCTAVES 8
 #define KPD_MAX_CELL 128        /* largest cell side, in level-0 pixels */
 #define KPD_MAX_DIM 16384       /* largest frame side */
+#define KPD_MAX_CHUNK 32        /* most frames per push_frames call */
 
 /* push_frame flags */
 #define KPD_FRAME_HOST 0          /* host pointer; copied into the arena */
@@ -74,7 +75,10 @@ extern "C" {
  *   tile       side of the level-0 tiles of the pyramid/difference pass, a
  *              tuning knob that never changes results: 0 picks the default,
  *              otherwise a power of two in 32..128 and >= 2^(O-1).
- *   reserved   must be 0. */
+ *   chunk_frames
+ *              most frames one push_frames call may take (0 or 1: the
+ *              stream takes single frames only; at most KPD_MAX_CHUNK). It
+ *              sizes the arena. */
 typedef struct kpd_params {
     int32_t fast_t;
     int32_t n_octaves;
@@ -83,7 +87,7 @@ typedef struct kpd_params {
     int32_t id_thresh;
     uint32_t kb_thresh;
     int32_t tile;
-    int32_t reserved;
+    int32_t chunk_frames;
 } kpd_params;
 
 /* One feature of D_n (Sec. 3: position and scale; the integer part).
@@ -128,6 +132,17 @@ int set_thresholds(kpd_stream* s, int32_t fast_t, int32_t id_thresh, uint32_t kb
  *                            NEXT push_frame has completed (it is I_{n-1}
  *                            then). */
 int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
+
+/* Process `n_frames` consecutive frames (1 <= n_frames <= chunk_frames) in
+ * one pass of three launches: a pyramid/difference pass over all of them, a
+ * detection pass over every (frame, cell), and a copy pass for carried cells.
+ * Frame i is the device buffer frames + i * frame_stride (rows pitch_bytes
+ * apart), read in place under the KPD_FRAME_DEVICE_RETAIN rules (the last
+ * frame is I_{n-1} of the next push). Results are exactly those of pushing
+ * the frames one by one: get_keypoints then returns the last frame's D_n,
+ * and kpd_chunk_result every frame's. KPD_EINVAL if the stream was opened
+ * without chunk_frames >= 2. */
+int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes, int n_frames);
 
 /* Wait for the last pushed frame and copy D_n to host memory `out`, ordered
  * by cell (row-major), then octave, then y, then x. `*count` receives the
@@ -202,6 +217,16 @@ int close_batch(kpd_batch* b);
  * its uint32 length, valid until the next push_frame. Does not synchronise. */
 int kpd_device_result(kpd_stream* s, const kpd_keypoint** d_list, const uint32_t** d_count);
 
+/* Device-resident D_n of frame i (0-based) of the last push_frames call:
+ * pointer to the list and to its uint32 length, valid until the next push.
+ * Does not synchronise. */
+int kpd_chunk_result(kpd_stream* s, int i, const kpd_keypoint** d_list, const uint32_t** d_count);
+
+/* Wait and copy D_n of frame i (0-based) of the last push_frames call to
+ * host memory, with get_keypoints' count/capacity rules (KPD_ETRUNC with
+ * *count set when capacity is too small). */
+int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count);
+
 /* Wait and copy per-cell statistics of the last frame: the summed absolute
  * level-0 difference (uint32 per cell; meaningful only on frames whose mask
  * was computed from data, i.e. not the first frame, not after a change of t,
@@ -215,11 +240,13 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
 
 /* ------------------------------------------------------ kernel timing */
 
-/* Kernels of one frame, in launch order: the pyramid-and-SAD pass over
- * level-0 tiles, and the per-cell detection and output pass. */
+/* Kernels of one push, in launch order: the pyramid-and-SAD pass over
+ * level-0 tiles, the per-cell detection and output pass, and (push_frames
+ * only) the copy pass of carried cells. */
 #define KPD_K_FRAME 0
 #define KPD_K_DETECT 1
-#define KPD_NKERNELS 2
+#define KPD_K_CARRY 2   /* copy pass of push_frames */
+#define KPD_NKERNELS 3
 
 /* Switch per-kernel GPU timing on (1) or off (0). While on, every kernel
  * launch of this stream is bracketed by two HIP events recorded on the

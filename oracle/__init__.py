@@ -53,6 +53,7 @@ def lib() -> ctypes.CDLL:
     L.orc_close.argtypes = [P]
     L.orc_close.restype = None
     L.orc_set_thresholds.argtypes = [P, ctypes.c_int, i32, u32]
+    L.orc_reset.argtypes = [P]
     L.orc_push.argtypes = [P, P]
     L.orc_get.argtypes = [P, P, ctypes.c_int, P, P, P]
     _lib = L
@@ -133,6 +134,9 @@ class Stream:
 
     def set_thresholds(self, t: int, TI: int, TH: int = KB_OFF):
         lib().orc_set_thresholds(self.h, t, TI, TH & 0xFFFFFFFF)
+
+    def reset(self):
+        lib().orc_reset(self.h)
 
     def push(self, frame: np.ndarray) -> int:
         frame = np.ascontiguousarray(frame, dtype=np.uint8)

@@ -294,6 +294,14 @@ int orc_set_thresholds(orc_stream* s, int t, int32_t TI, uint32_t TH)
     return 0;
 }
 
+/* A reset (a scene cut signalled by the caller) treats the next frame like
+ * the first one: every cell is detected. */
+int orc_reset(orc_stream* s)
+{
+    s->force_all = 1;
+    return 0;
+}
+
 static int kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr;
 
 static int kp_cmp(const void* a, const void* b)

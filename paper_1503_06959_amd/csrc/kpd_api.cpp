@@ -41,8 +41,9 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Byte layout of one stream's device arena. Per-frame state that the next
-// frame reads (per-cell counts and offsets, the keypoint list D_n, the
-// per-cell SAD) is double-buffered and indexed by frame parity.
+// frame reads is double-buffered: the per-cell SAD by frame parity, the
+// per-cell counts and offsets and the keypoint list D_n by alternation (the
+// stream remembers which buffer holds the latest D_n).
 struct Layout {
     int W = 0, H = 0, O = 0, nc = 0, nr = 0, ncell = 0;
     int w[KPD_MAX_OCTAVES] = {}, h[KPD_MAX_OCTAVES] = {}, pitch[KPD_MAX_OCTAVES] = {};
@@ -53,6 +54,13 @@ struct Layout {
     size_t off_hdr = 0, off_slot[2] = {0, 0}, off_lvl[KPD_MAX_OCTAVES] = {};
     size_t off_sad[2] = {0, 0}, off_count[2] = {0, 0}, off_offs[2] = {0, 0}, off_list[2] = {0, 0};
     size_t off_mask = 0, off_status = 0, off_colw = 0, off_rowh = 0, off_layouts = 0;
+    // chunks of consecutive frames (push_frames): K copies of the octaves and
+    // per-frame counts, offsets, lists, SAD, count/source words and copy
+    // descriptors, plus the chunk's argument tables (two sets)
+    int K = 1;
+    size_t pyr_stride = 0;
+    size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
+    size_t off_cntw = 0, off_srcw = 0, off_carry = 0, off_ctab[2] = {0, 0}, off_ftab[2] = {0, 0}, off_fmap = 0;
     size_t list_cap = 0;
     int lds_bytes = 0;   // dynamic LDS of the cell pass
     size_t total = 0;
@@ -84,7 +92,10 @@ bool valid_params(int W, int H, const kpd_params* p, std::string* why)
         *why = "tile must be 0 or a power of two in 32..128 and >= 2^(O-1)";
         return false;
     }
-    if (p->reserved != 0) { *why = "reserved must be 0"; return false; }
+    if (p->chunk_frames < 0 || p->chunk_frames > KPD_MAX_CHUNK) {
+        *why = "chunk_frames out of range";
+        return false;
+    }
     return true;
 }
 
@@ -134,10 +145,19 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->list_cap = std::max<size_t>(cap, 1);
     L->lds_bytes = std::max(lds, 16);
 
+    L->K = std::max(1, (int)p->chunk_frames);
+    if (L->K > 1 && L->list_cap >= (1u << 26)) {
+        *why = "frame too large for chunks";
+        return false;
+    }
+
     size_t off = 0;
     L->off_hdr = off; off = align_up(off + 64);
     for (int k = 0; k < 2; ++k) { L->off_slot[k] = off; off = align_up(off + (size_t)L->slot_pitch * H); }
+    const size_t pyr0 = off;
     for (int o = 1; o < L->O; ++o) { L->off_lvl[o] = off; off = align_up(off + (size_t)L->pitch[o] * L->h[o]); }
+    L->pyr_stride = off - pyr0;
+    off += L->pyr_stride * (size_t)(L->K - 1);
     const size_t nc4 = (size_t)L->ncell * 4;
     for (int k = 0; k < 2; ++k) { L->off_sad[k] = off; off = align_up(off + nc4); }
     for (int k = 0; k < 2; ++k) { L->off_count[k] = off; off = align_up(off + nc4); }
@@ -150,6 +170,21 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     for (int k = 0; k < 2; ++k) {
         L->off_list[k] = off;
         off = align_up(off + L->list_cap * sizeof(kpd_keypoint));
+    }
+    if (L->K > 1) {
+        const size_t kc = (size_t)L->K * L->ncell;
+        L->off_csad = off; off = align_up(off + kc * 4);
+        L->off_ccount = off; off = align_up(off + kc * 4);
+        L->off_coffs = off; off = align_up(off + kc * 4);
+        L->off_ctotal = off; off = align_up(off + (size_t)L->K * 4);
+        L->off_cntw = off; off = align_up(off + kc * 8);
+        L->off_srcw = off; off = align_up(off + kc * 8);
+        L->off_carry = off; off = align_up(off + kc * sizeof(kpd::CarryDesc));
+        L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
+        L->off_clist = off; off += L->clist_stride * (size_t)L->K;
+        for (int k = 0; k < 2; ++k) { L->off_ctab[k] = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs)); }
+        for (int k = 0; k < 2; ++k) { L->off_ftab[k] = off; off = align_up(off + (size_t)L->K * sizeof(kpd::TickArgs)); }
+        L->off_fmap = off; off = align_up(off + (size_t)L->K * L->tiles_x * L->tiles_y * 2);
     }
     L->total = off;
     return true;
@@ -193,7 +228,23 @@ struct kpd_stream {
     const uint8_t* prev0 = nullptr;
     int prev_pitch = 0;
     int prev_dw = 0;
+    int fb_last = 1;          // which of the two single-frame buffers holds the latest D_n
+    int chunk_n = 0;          // frames of the last push_frames call
+    kpd::ChunkArgs* ctab_host[2] = {nullptr, nullptr};  // pinned
+    kpd::TickArgs* ftab_host[2] = {nullptr, nullptr};   // pinned
+    hipEvent_t ctab_free[2] = {nullptr, nullptr};
+    bool ctab_used[2] = {false, false};
+    uint64_t chunks = 0;
     bool closed = false;
+
+    ~kpd_stream()
+    {
+        for (int k = 0; k < 2; ++k) {
+            if (ctab_host[k]) hipHostFree(ctab_host[k]);
+            if (ftab_host[k]) hipHostFree(ftab_host[k]);
+            if (ctab_free[k]) hipEventDestroy(ctab_free[k]);
+        }
+    }
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
@@ -299,6 +350,26 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_layouts, layouts.data(), layouts.size() * sizeof(kpd::CellLayout),
                            hipMemcpyHostToDevice, s->stream);
+    std::vector<uint16_t> fmap;
+    if (L.K > 1) {
+        const int nt = L.tiles_x * L.tiles_y;
+        fmap.resize((size_t)L.K * nt);
+        for (size_t b = 0; b < fmap.size(); ++b) fmap[b] = (uint16_t)(b / nt);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->arena + L.off_fmap, fmap.data(), fmap.size() * 2, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(s->arena + L.off_csad, 0, (size_t)L.K * L.ncell * 4, s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_cntw, 0, (size_t)L.K * L.ncell * 8, s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_srcw, 0, (size_t)L.K * L.ncell * 8, s->stream);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = hipHostMalloc(reinterpret_cast<void**>(&s->ctab_host[k]), (size_t)L.K * sizeof(kpd::ChunkArgs),
+                              hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipHostMalloc(reinterpret_cast<void**>(&s->ftab_host[k]), (size_t)L.K * sizeof(kpd::TickArgs),
+                                  hipHostMallocDefault);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ctab_free[k], hipEventDisableTiming);
+        }
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         delete s;
@@ -354,7 +425,8 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     }
 
     const uint32_t n = (uint32_t)s->n_pushed;
-    const int cur_k = n & 1, prev_k = cur_k ^ 1;
+    const int cur_k = n & 1, prev_k = cur_k ^ 1;       // SAD accumulators go by frame parity
+    const int fb_prev = s->fb_last, fb_cur = 1 - s->fb_last;  // keypoint buffers alternate
     const bool all_marked = s->force_all || s->p.id_thresh < 0 || s->p.kb_thresh == 0;
     const bool sad_on = !all_marked && s->p.id_thresh < 255;
 
@@ -398,13 +470,13 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     d.sad = s->at<uint32_t>(L.off_sad[cur_k]);
     d.sad_next = s->at<uint32_t>(L.off_sad[prev_k]);
     d.mask = s->at<uint8_t>(L.off_mask);
-    d.count_prev = s->at<uint32_t>(L.off_count[prev_k]);
-    d.off_prev = s->at<uint32_t>(L.off_offs[prev_k]);
-    d.list_prev = s->at<kpd_keypoint>(L.off_list[prev_k]);
-    d.count_cur = s->at<uint32_t>(L.off_count[cur_k]);
-    d.off_cur = s->at<uint32_t>(L.off_offs[cur_k]);
-    d.list_cur = s->at<kpd_keypoint>(L.off_list[cur_k]);
-    d.total_cur = s->at<uint32_t>(L.off_hdr) + (cur_k ? kHdrTotal1 : kHdrTotal0);
+    d.count_prev = s->at<uint32_t>(L.off_count[fb_prev]);
+    d.off_prev = s->at<uint32_t>(L.off_offs[fb_prev]);
+    d.list_prev = s->at<kpd_keypoint>(L.off_list[fb_prev]);
+    d.count_cur = s->at<uint32_t>(L.off_count[fb_cur]);
+    d.off_cur = s->at<uint32_t>(L.off_offs[fb_cur]);
+    d.list_cur = s->at<kpd_keypoint>(L.off_list[fb_cur]);
+    d.total_cur = s->at<uint32_t>(L.off_hdr) + (fb_cur ? kHdrTotal1 : kHdrTotal0);
     d.list_cap = (uint32_t)L.list_cap;
     d.layouts = s->at<kpd::CellLayout>(L.off_layouts);
     d.col_w = s->at<uint16_t>(L.off_colw);
@@ -426,6 +498,8 @@ void advance_frame(kpd_stream* s, const kpd::TickArgs& t)
     s->prev_dw = t.f.cur_aligned;
     s->force_all = false;
     s->n_pushed += 1;
+    s->fb_last = 1 - s->fb_last;
+    s->chunk_n = 0;
 }
 
 }  // namespace
@@ -445,12 +519,183 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
     return KPD_OK;
 }
 
+int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes, int n_frames)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    const Layout& L = s->L;
+    if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
+    if (!frames) return fail(KPD_EINVAL, "frames is NULL");
+    if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
+    if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
+    if (n_frames > 1 && frame_stride < pitch_bytes * (size_t)(L.H - 1) + (size_t)L.W)
+        return fail(KPD_EINVAL, "frames overlap");
+    const int k = (int)(s->chunks & 1);
+    if (s->ctab_used[k]) KPD_HIP(hipEventSynchronize(s->ctab_free[k]));
+
+    const uint32_t n0 = (uint32_t)s->n_pushed;
+    const int pitch = (int)pitch_bytes;
+    const int fb_prev = s->fb_last, fb_next = 1 - s->fb_last;
+    const size_t kc = (size_t)L.ncell;
+    kpd::ChunkArgs* ct = s->ctab_host[k];
+    kpd::TickArgs* ft = s->ftab_host[k];
+    bool any_tiles = false;
+    for (int j = 0; j < n_frames; ++j) {
+        const uint8_t* cur = frames + (size_t)j * frame_stride;
+        const int cur_dw = dword_readable(cur, pitch, L.W, false);
+        const bool all_marked = (j == 0 && s->force_all) || s->p.id_thresh < 0 || s->p.kb_thresh == 0;
+        const bool sad_on = !all_marked && s->p.id_thresh < 255;
+        uint8_t* pyr = s->arena + L.pyr_stride * (size_t)j;   // octave copy j
+
+        kpd::TickArgs& t = ft[j];
+        t = kpd::TickArgs{};
+        kpd::FrameArgs& fa = t.f;
+        fa.cur = cur;
+        fa.cur_pitch = pitch;
+        fa.cur_aligned = cur_dw;
+        fa.prev = !sad_on ? cur : (j == 0 ? s->prev0 : frames + (size_t)(j - 1) * frame_stride);
+        fa.prev_pitch = !sad_on ? pitch : (j == 0 ? s->prev_pitch : pitch);
+        fa.prev_aligned = !sad_on ? cur_dw : (j == 0 ? s->prev_dw : dword_readable(fa.prev, pitch, L.W, false));
+        for (int o = 1; o < L.O; ++o) {
+            fa.lvl[o] = pyr + L.off_lvl[o];
+            fa.pitch[o] = L.pitch[o];
+        }
+        for (int o = 0; o < L.O; ++o) { fa.w[o] = L.w[o]; fa.h[o] = L.h[o]; }
+        fa.W = L.W; fa.H = L.H; fa.O = L.O; fa.nc = L.nc; fa.nr = L.nr;
+        fa.tile = L.tile;
+        fa.tiles_x = L.tiles_x;
+        fa.ntiles = L.tiles_x * L.tiles_y;
+        fa.sad_on = sad_on ? 1 : 0;
+        fa.sad_slots = L.sad_slots;
+        fa.sad_lds_off = kpd::frame_sad_lds_off(L.tile, L.O);
+        fa.sad = s->at<uint32_t>(L.off_csad) + (size_t)j * kc;
+        t.active = 1;
+        t.f_on = (L.O > 1 || sad_on) ? 1 : 0;
+        t.tile_base = j * fa.ntiles;
+        any_tiles = any_tiles || t.f_on;
+
+        kpd::ChunkArgs& c = ct[j];
+        c = kpd::ChunkArgs{};
+        kpd::DetectArgs& d = c.d;
+        d.lvl[0] = cur;
+        d.pitch[0] = pitch;
+        for (int o = 1; o < L.O; ++o) {
+            d.lvl[o] = pyr + L.off_lvl[o];
+            d.pitch[o] = L.pitch[o];
+        }
+        for (int o = 0; o < L.O; ++o) { d.w[o] = L.w[o]; d.h[o] = L.h[o]; }
+        d.lvl0_aligned = cur_dw;
+        d.W = L.W; d.H = L.H; d.O = L.O; d.nc = L.nc; d.nr = L.nr;
+        d.t = s->p.fast_t;
+        d.all_marked = all_marked ? 1 : 0;
+        d.id_on = sad_on ? 1 : 0;
+        d.id_thresh = s->p.id_thresh;
+        d.kb_thresh = s->p.kb_thresh;
+        d.sad = fa.sad;
+        d.mask = s->at<uint8_t>(L.off_mask);
+        d.count_cur = s->at<uint32_t>(L.off_ccount) + (size_t)j * kc;
+        d.off_cur = s->at<uint32_t>(L.off_coffs) + (size_t)j * kc;
+        d.list_cur = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_clist + L.clist_stride * (size_t)j);
+        d.total_cur = s->at<uint32_t>(L.off_ctotal) + j;
+        d.list_cap = (uint32_t)L.list_cap;
+        d.layouts = s->at<kpd::CellLayout>(L.off_layouts);
+        d.col_w = s->at<uint16_t>(L.off_colw);
+        d.row_h = s->at<uint16_t>(L.off_rowh);
+        d.epoch = n0 + (uint32_t)j + 1;
+        d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
+        c.j = j;
+        c.last = j == n_frames - 1 ? 1 : 0;
+        c.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);
+        c.prev_offs = s->at<uint32_t>(L.off_offs[fb_prev]);
+        c.cnt_words = s->at<unsigned long long>(L.off_cntw) + (size_t)j * kc;
+        c.cnt_words_prev = j ? c.cnt_words - kc : nullptr;
+        c.src_words = s->at<unsigned long long>(L.off_srcw) + (size_t)j * kc;
+        c.src_words_prev = j ? c.src_words - kc : nullptr;
+        c.carry = s->at<kpd::CarryDesc>(L.off_carry) + (size_t)j * kc;
+    }
+
+    kpd::ChunkArgs* ctab = s->at<kpd::ChunkArgs>(L.off_ctab[k]);
+    kpd::TickArgs* ftab = s->at<kpd::TickArgs>(L.off_ftab[k]);
+    KPD_HIP(hipMemcpyAsync(ctab, ct, (size_t)n_frames * sizeof(kpd::ChunkArgs), hipMemcpyHostToDevice, s->stream));
+    KPD_HIP(hipMemcpyAsync(ftab, ft, (size_t)n_frames * sizeof(kpd::TickArgs), hipMemcpyHostToDevice, s->stream));
+    KPD_HIP(hipEventRecord(s->ctab_free[k], s->stream));
+    s->ctab_used[k] = true;
+    const int nt = L.tiles_x * L.tiles_y;
+    if (any_tiles)
+        KPD_HIP(timed(s, KPD_K_FRAME, [&] {
+            return kpd::launch_frame_batch(ftab, s->at<uint16_t>(L.off_fmap), n_frames * nt,
+                                           kpd::frame_lds_bytes(L.tile, L.O, L.sad_slots), s->stream);
+        }));
+    KPD_HIP(timed(s, KPD_K_DETECT, [&] {
+        return kpd::launch_detect_chunk(ctab, n_frames, L.ncell, L.lds_bytes, s->stream);
+    }));
+    kpd::CarryArgs ca{};
+    ca.ncell = L.ncell;
+    ca.last = n_frames - 1;
+    ca.list_cap = (uint32_t)L.list_cap;
+    ca.list_stride = L.clist_stride / sizeof(kpd_keypoint);
+    ca.lists = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_clist);
+    ca.prev_list = s->at<kpd_keypoint>(L.off_list[fb_prev]);
+    ca.carry = s->at<kpd::CarryDesc>(L.off_carry);
+    ca.next_list = s->at<kpd_keypoint>(L.off_list[fb_next]);
+    ca.next_count = s->at<uint32_t>(L.off_count[fb_next]);
+    ca.next_offs = s->at<uint32_t>(L.off_offs[fb_next]);
+    ca.next_total = s->at<uint32_t>(L.off_hdr) + (fb_next ? kHdrTotal1 : kHdrTotal0);
+    ca.sad_chunk = s->at<uint32_t>(L.off_csad);
+    const uint32_t n_last = n0 + (uint32_t)n_frames - 1;
+    ca.sad_stats = s->at<uint32_t>(L.off_sad[n_last & 1]);
+    ca.sad_single_next = s->at<uint32_t>(L.off_sad[(n_last + 1) & 1]);
+    KPD_HIP(timed(s, KPD_K_CARRY, [&] { return kpd::launch_carry_chunk(ca, n_frames, s->stream); }));
+
+    const uint8_t* last = frames + (size_t)(n_frames - 1) * frame_stride;
+    s->prev0 = last;
+    s->prev_pitch = pitch;
+    s->prev_dw = dword_readable(last, pitch, L.W, false);
+    s->force_all = false;
+    s->n_pushed += n_frames;
+    s->fb_last = fb_next;
+    s->chunk_n = n_frames;
+    s->chunks += 1;
+    return KPD_OK;
+}
+
+int kpd_chunk_result(kpd_stream* s, int i, const kpd_keypoint** d_list, const uint32_t** d_count)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (i < 0 || i >= s->chunk_n) return fail(KPD_EINVAL, "no such frame in the last chunk");
+    const Layout& L = s->L;
+    if (d_list) *d_list = reinterpret_cast<const kpd_keypoint*>(s->arena + L.off_clist + L.clist_stride * (size_t)i);
+    if (d_count) *d_count = s->at<uint32_t>(L.off_ctotal) + i;
+    return KPD_OK;
+}
+
+int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!count) return fail(KPD_EINVAL, "count is NULL");
+    if (i < 0 || i >= s->chunk_n) return fail(KPD_EINVAL, "no such frame in the last chunk");
+    const Layout& L = s->L;
+    uint32_t hdr[4] = {0, 0, 0, 0}, total = 0;
+    KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
+    KPD_HIP(hipMemcpyAsync(&total, s->at<uint32_t>(L.off_ctotal) + i, 4, hipMemcpyDeviceToHost, s->stream));
+    KPD_HIP(hipStreamSynchronize(s->stream));
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
+    *count = total;
+    if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
+    if (total > 0) {
+        if (!out) return fail(KPD_EINVAL, "out is NULL");
+        KPD_HIP(hipMemcpyAsync(out, s->arena + L.off_clist + L.clist_stride * (size_t)i,
+                               (size_t)total * sizeof(kpd_keypoint), hipMemcpyDeviceToHost, s->stream));
+        KPD_HIP(hipStreamSynchronize(s->stream));
+    }
+    return KPD_OK;
+}
+
 int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (!count) return fail(KPD_EINVAL, "count is NULL");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
-    const int k = (s->n_pushed - 1) & 1;
+    const int k = s->fb_last;
     uint32_t hdr[4] = {0, 0, 0, 0};
     KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(s->L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
@@ -520,7 +765,7 @@ int kpd_device_result(kpd_stream* s, const kpd_keypoint** d_list, const uint32_t
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
-    const int k = (s->n_pushed - 1) & 1;
+    const int k = s->fb_last;
     if (d_list) *d_list = s->at<kpd_keypoint>(s->L.off_list[k]);
     if (d_count) *d_count = s->at<uint32_t>(s->L.off_hdr) + (k ? kHdrTotal1 : kHdrTotal0);
     return KPD_OK;
@@ -534,7 +779,8 @@ int kpd_cell_stats(kpd_stream* s, uint32_t* sad, uint32_t* counts)
     const size_t n = (size_t)s->L.ncell * 4;
     if (sad) KPD_HIP(hipMemcpyAsync(sad, s->at<uint32_t>(s->L.off_sad[k]), n, hipMemcpyDeviceToHost, s->stream));
     if (counts)
-        KPD_HIP(hipMemcpyAsync(counts, s->at<uint32_t>(s->L.off_count[k]), n, hipMemcpyDeviceToHost, s->stream));
+        KPD_HIP(hipMemcpyAsync(counts, s->at<uint32_t>(s->L.off_count[s->fb_last]), n, hipMemcpyDeviceToHost,
+                               s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
     return KPD_OK;
 }
@@ -798,8 +1044,9 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out)
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
     if (octave < 1 || octave >= s->L.O || !out) return fail(KPD_EINVAL, "bad octave or NULL output");
     const Layout& L = s->L;
-    KPD_HIP(hipMemcpy2DAsync(out, L.w[octave], s->at<uint8_t>(L.off_lvl[octave]), L.pitch[octave], L.w[octave],
-                             L.h[octave], hipMemcpyDeviceToHost, s->stream));
+    const size_t copy = s->chunk_n > 0 ? (size_t)(s->chunk_n - 1) : 0;   // the last frame's octaves
+    KPD_HIP(hipMemcpy2DAsync(out, L.w[octave], s->arena + L.pyr_stride * copy + L.off_lvl[octave], L.pitch[octave],
+                             L.w[octave], L.h[octave], hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
     return KPD_OK;
 }

@@ -69,6 +69,49 @@ struct TickArgs {
     int tile_base, cell_base;
 };
 
+// A chunk of consecutive frames of one stream.
+constexpr uint32_t kChunkPrev = 63;  // source id of the list before the chunk
+
+struct CarryDesc {
+    uint32_t src_id;   // chunk frame whose list holds the cell's entries, or kChunkPrev
+    uint32_t src_off;  // their first index there
+    uint32_t count;
+    uint32_t dst_off;  // the cell's first index in its own frame's list
+    uint32_t carried;  // 1: copy the entries (the cell was not marked)
+    uint32_t pad[3];
+};
+
+struct ChunkArgs {
+    DetectArgs d;                               // frame j's detection arguments
+    int j, last;                                // frame index in the chunk, is it the last
+    const uint32_t* prev_count;                 // counts of the frame before the chunk
+    const uint32_t* prev_offs;                  // and their offsets
+    unsigned long long* cnt_words;              // frame j's count words
+    const unsigned long long* cnt_words_prev;   // frame j-1's
+    unsigned long long* src_words;              // frame j's source words
+    const unsigned long long* src_words_prev;   // frame j-1's
+    CarryDesc* carry;                           // frame j's copy descriptors
+};
+
+struct CarryArgs {
+    int ncell, last;
+    uint32_t list_cap;
+    size_t list_stride;          // entries between consecutive chunk lists
+    kpd_keypoint* lists;         // chunk lists
+    const kpd_keypoint* prev_list;
+    const CarryDesc* carry;      // chunk frames x cells
+    kpd_keypoint* next_list;     // buffers the frame after the chunk reads
+    uint32_t* next_count;
+    uint32_t* next_offs;
+    uint32_t* next_total;
+    uint32_t* sad_chunk;         // chunk frames x cells, cleared here
+    uint32_t* sad_stats;         // receives the last frame's SAD
+    uint32_t* sad_single_next;   // cleared for the next single frame
+};
+
+hipError_t launch_detect_chunk(const ChunkArgs* table, int n_frames, int ncell, int lds_bytes, hipStream_t s);
+hipError_t launch_carry_chunk(const CarryArgs& a, int n_frames, hipStream_t s);
+
 int frame_sad_lds_off(int tile, int O);
 int frame_lds_bytes(int tile, int O, int sad_slots);
 hipError_t set_detect_lds_limit(int lds_bytes);

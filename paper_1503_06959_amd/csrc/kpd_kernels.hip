@@ -303,193 +303,282 @@ __device__ __forceinline__ bool cell_marked(const DetectArgs& a, int c)
     return id || kb;
 }
 
-__device__ void detect_cell(const DetectArgs& a, int cell, uint8_t* sm)
+// Steps 0-4 for a marked cell c: stage the octave tiles, score, suppress and
+// rank. Leaves the keep bitmask and word offsets in LDS and the cell's number
+// of keypoints in *s_n (valid after the final barrier).
+__device__ __forceinline__ void detect_marked(const DetectArgs& a, int c, uint8_t* sm, CellLayout& L, const uint8_t* const* s_lvl,
+                              const int* s_pitch, uint32_t* s_n)
 {
-    __shared__ CellLayout L;
-    __shared__ int s_c, s_mark;
-    __shared__ uint32_t s_n, s_excl, s_part[kDetWaves];
-    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
-    __shared__ int s_pitch[KPD_MAX_OCTAVES];
-
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int O = a.O;
+    uint64_t* keepw = reinterpret_cast<uint64_t*>(sm);
+    // 0) the cell's precomputed layout, one dword per thread
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
+        for (int i = tid; i < (int)(sizeof(CellLayout) / 4); i += kBlk) dst[i] = src[i];
+    }
+    __syncthreads();
+    uint64_t* candw = reinterpret_cast<uint64_t*>(sm + L.cand_off);
+    for (int i = tid; i < L.nwords; i += kBlk) candw[i] = 0;
+    {
+        uint32_t* v = reinterpret_cast<uint32_t*>(sm + L.voff[0]);
+        for (int i = tid; i < L.vbytes / 4; i += kBlk) v[i] = 0;
+    }
+
+    // 1) pixel tiles of every octave, a dword per load, four loads in flight
+    const int nld = L.ld_start[O];
+    for (int base = tid; base < nld; base += 4 * kBlk) {
+        uint32_t val[4];
+        int dst[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * kBlk;
+            dst[u] = -1;
+            val[u] = 0;
+            if (i < nld) {
+                const int o = level_of(L.ld_start, O, i);
+                const unsigned j = i - L.ld_start[o];
+                const int q = L.tpitch[o] / 4;
+                const int ry = fast_div(j, L.ldm[o]), cq = j - ry * q;
+                const int gy = L.ty0[o] + ry, gx = L.tx0[o] + 4 * cq;
+                const uint8_t* src = s_lvl[o] + (size_t)gy * s_pitch[o] + gx;
+                if (o > 0 || a.lvl0_aligned) {
+                    val[u] = *reinterpret_cast<const uint32_t*>(src);
+                } else {
+                    uint32_t v = 0;
+                    for (int k = 0; k < 4; ++k)
+                        if (gx + k < a.W) v |= (uint32_t)src[k] << (8 * k);
+                    val[u] = v;
+                }
+                dst[u] = L.toff[o] + ry * L.tpitch[o] + 4 * cq;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (dst[u] >= 0) *reinterpret_cast<uint32_t*>(sm + dst[u]) = val[u];
+    }
+    __syncthreads();
+
+    // 2) segment test and score over every octave's score box. Waves take
+    //    chunks of kChunk pixels of one level (four per lane) and queue
+    //    those that pass the four-compass-point test; the full 16-pixel
+    //    test runs 64 queued pixels at a time, so lanes stay busy.
+    {
+        uint16_t* queue = reinterpret_cast<uint16_t*>(sm + L.queue_off) + wave * kQueue;
+        uint32_t q_tail = 0, q_head = 0;
+        auto full_test = [&](int count) {
+            if (lane < count) {
+                const int i = queue[(q_head + lane) & (kQueue - 1)];
+                const int o = level_of(L.sc_start, O, i);
+                const unsigned j = i - L.sc_start[o];
+                const Box sb = L.sb[o];
+                const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
+                const uint8_t* P = sm + L.toff[o] + (ry + kRingR) * L.tpitch[o] + (sb.x0 + rx - L.tx0[o]);
+                const int v = full_score(P, L.tpitch[o], a.t);
+                const int x = sb.x0 + rx, y = sb.y0 + ry;
+                if (v > 0) {
+                    reinterpret_cast<uint16_t*>(sm + L.voff[o])[(y - L.qb[o].y0) * L.vpitch[o] + (x - L.qb[o].x0)] =
+                        (uint16_t)v;
+                    const Box d = L.dec[o];
+                    if (x >= d.x0 && x < d.x1 && y >= d.y0 && y < d.y1) {
+                        const int bit = L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
+                        atomicOr(&candw[bit >> 6], 1ull << (bit & 63));
+                    }
+                }
+            }
+            q_head += count;
+        };
+        const int nck = L.ck_start[O];
+        for (int ck = wave; ck < nck; ck += kDetWaves) {
+            const int o = level_of(L.ck_start, O, ck);
+            const Box sb = L.sb[o];
+            const int n = box_w(sb) * box_h(sb);
+            const int tp = L.tpitch[o];
+            const uint8_t* T0 = sm + L.toff[o] + kRingR * tp + (sb.x0 - L.tx0[o]);
+            const int j0 = (ck - L.ck_start[o]) * kChunk;
+            bool pass[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * 64 + lane;
+                pass[u] = false;
+                if (j < n) {
+                    const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
+                    pass[u] = compass_pass(T0 + ry * tp + rx, tp, a.t);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t bal = __ballot(pass[u]);
+                if (pass[u]) {
+                    const unsigned below = __builtin_amdgcn_mbcnt_hi(
+                        (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                    queue[(q_tail + below) & (kQueue - 1)] = (uint16_t)(L.sc_start[o] + j0 + u * 64 + lane);
+                }
+                q_tail += (uint32_t)__popcll(bal);
+            }
+            __builtin_amdgcn_wave_barrier();
+            while (q_tail - q_head >= 64) {
+                full_test(64);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (q_tail != q_head) full_test((int)(q_tail - q_head));
+    }
+    __syncthreads();
+
+    // 3) scale-space maxima of the candidates, one 64-pixel word per wave
+    //    pass; words without candidates are skipped whole
+    for (int w = wave; w < L.nwords; w += kDetWaves) {
+        const uint64_t cand = candw[w];
+        bool keep = false;
+        if (cand != 0 && ((cand >> lane) & 1)) {
+            const int i = w * 64 + lane;
+            const int o = level_of(L.dc_start, O, i);
+            const unsigned j = i - L.dc_start[o];
+            const Box d = L.dec[o];
+            const int ry = fast_div(j, L.dcm[o]);
+            const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
+            keep = is_local_max(sm, L, o, O, x, y, vget(sm, L, o, x, y));
+        }
+        const uint64_t bal = __ballot(keep);
+        if (lane == 0) keepw[w] = bal;
+    }
+    __syncthreads();
+
+    // 4) rank: exclusive popcount prefix over the keep words (wave 0)
+    if (wave == 0) {
+        const int nw = L.nwords;
+        uint32_t* woff = reinterpret_cast<uint32_t*>(sm + L.woff_off);
+        const int per = (nw + 63) / 64;
+        const int w0 = lane * per, w1 = min(w0 + per, nw);
+        uint32_t sum = 0;
+        for (int w = w0; w < w1; ++w) sum += (uint32_t)__popcll(keepw[w]);
+        uint32_t incl = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t up = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += up;
+        }
+        uint32_t run = incl - sum;
+        for (int w = w0; w < w1; ++w) {
+            woff[w] = run;
+            run += (uint32_t)__popcll(keepw[w]);
+        }
+        if (lane == 63) *s_n = incl;
+    }
+    __syncthreads();
+}
+
+// Step 6 for a marked cell: write its ranked maxima from position excl on.
+__device__ __forceinline__ void emit_marked(const DetectArgs& a, const CellLayout& L, const uint8_t* sm, uint32_t excl,
+                            kpd_keypoint* list, uint32_t cap)
+{
+    const int tid = threadIdx.x;
+    const int O = a.O;
+    const uint64_t* keepw = reinterpret_cast<const uint64_t*>(sm);
+    const uint32_t* woff = reinterpret_cast<const uint32_t*>(sm + L.woff_off);
+    for (int w = tid; w < L.nwords; w += kBlk) {
+        uint64_t bits = keepw[w];
+        uint32_t pos = excl + woff[w];
+        while (bits) {
+            const int b = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const int i = w * 64 + b;
+            const int o = level_of(L.dc_start, O, i);
+            const unsigned j = i - L.dc_start[o];
+            const Box d = L.dec[o];
+            const int ry = fast_div(j, L.dcm[o]);
+            const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
+            kpd_keypoint k;
+            k.x = (uint16_t)x;
+            k.y = (uint16_t)y;
+            k.octave = (uint8_t)o;
+            k.pad = 0;
+            k.score = (uint16_t)vget(sm, L, o, x, y);
+            // at most one keypoint per 2x2 block keeps pos below the capacity
+            if (pos < cap) list[pos] = k;
+            ++pos;
+        }
+    }
+}
+
+// Sum over cells [0, c) of their count words for `epoch`, spinning on each
+// until it is published (block-wide; the result is valid in every thread).
+__device__ uint32_t sum_count_words(const unsigned long long* words, int c, uint32_t epoch, uint32_t* err,
+                                    uint32_t* s_part)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    uint32_t acc = 0;
+    bool ok = true;
+    for (int p = tid; p < c; p += kBlk) {
+        int spins = 0;
+        while (true) {
+            const uint64_t st = __hip_atomic_load(&words[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(st >> 32) == epoch) {
+                acc += (uint32_t)st;
+                break;
+            }
+            if (++spins > kSpinLimit) { ok = false; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    if (!ok) __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    __syncthreads();
+    if (lane == 0) s_part[wave] = acc;
+    __syncthreads();
+    uint32_t sum = 0;
+    for (int w = 0; w < kDetWaves; ++w) sum += s_part[w];
+    return sum;
+}
+
+// Spin on one word until it carries `epoch` (one thread).
+__device__ uint64_t wait_word(const unsigned long long* w, uint32_t epoch, uint32_t* err)
+{
+    int spins = 0;
+    while (true) {
+        const uint64_t st = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(st >> 32) == epoch) return st;
+        if (++spins > kSpinLimit) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return st;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ void load_level_ptrs(const DetectArgs& a, const uint8_t** s_lvl, int* s_pitch)
+{
+#pragma unroll
+    for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
+        s_lvl[o] = a.lvl[o];
+        s_pitch[o] = a.pitch[o];
+    }
+}
+
+// One frame of one stream: cell c's mark, detection, offset and output.
+__device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
+{
+    __shared__ CellLayout L;
+    __shared__ int s_mark;
+    __shared__ uint32_t s_n, s_excl, s_part[kDetWaves];
+    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
+    __shared__ int s_pitch[KPD_MAX_OCTAVES];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
 
     if (tid == 0) {
-#pragma unroll
-        for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
-            s_lvl[o] = a.lvl[o];
-            s_pitch[o] = a.pitch[o];
-        }
-        const int c = cell;
-        s_c = c;
+        load_level_ptrs(a, s_lvl, s_pitch);
         const bool mark = cell_marked(a, c);
         a.mask[c] = (uint8_t)mark;
         a.sad_next[c] = 0;
         s_mark = mark;
     }
     __syncthreads();
-    const int c = s_c;
     const bool mark = s_mark != 0;
-    uint64_t* keepw = reinterpret_cast<uint64_t*>(sm);
-
-    if (mark) {
-        // 0) the cell's precomputed layout, one dword per thread
-        {
-            const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
-            uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
-            for (int i = tid; i < (int)(sizeof(CellLayout) / 4); i += kBlk) dst[i] = src[i];
-        }
-        __syncthreads();
-        uint64_t* candw = reinterpret_cast<uint64_t*>(sm + L.cand_off);
-        for (int i = tid; i < L.nwords; i += kBlk) candw[i] = 0;
-        {
-            uint32_t* v = reinterpret_cast<uint32_t*>(sm + L.voff[0]);
-            for (int i = tid; i < L.vbytes / 4; i += kBlk) v[i] = 0;
-        }
-
-        // 1) pixel tiles of every octave, a dword per load, four loads in flight
-        const int nld = L.ld_start[O];
-        for (int base = tid; base < nld; base += 4 * kBlk) {
-            uint32_t val[4];
-            int dst[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = base + u * kBlk;
-                dst[u] = -1;
-                val[u] = 0;
-                if (i < nld) {
-                    const int o = level_of(L.ld_start, O, i);
-                    const unsigned j = i - L.ld_start[o];
-                    const int q = L.tpitch[o] / 4;
-                    const int ry = fast_div(j, L.ldm[o]), cq = j - ry * q;
-                    const int gy = L.ty0[o] + ry, gx = L.tx0[o] + 4 * cq;
-                    const uint8_t* src = s_lvl[o] + (size_t)gy * s_pitch[o] + gx;
-                    if (o > 0 || a.lvl0_aligned) {
-                        val[u] = *reinterpret_cast<const uint32_t*>(src);
-                    } else {
-                        uint32_t v = 0;
-                        for (int k = 0; k < 4; ++k)
-                            if (gx + k < a.W) v |= (uint32_t)src[k] << (8 * k);
-                        val[u] = v;
-                    }
-                    dst[u] = L.toff[o] + ry * L.tpitch[o] + 4 * cq;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (dst[u] >= 0) *reinterpret_cast<uint32_t*>(sm + dst[u]) = val[u];
-        }
-        __syncthreads();
-
-        // 2) segment test and score over every octave's score box. Waves take
-        //    chunks of kChunk pixels of one level (four per lane) and queue
-        //    those that pass the four-compass-point test; the full 16-pixel
-        //    test runs 64 queued pixels at a time, so lanes stay busy.
-        {
-            uint16_t* queue = reinterpret_cast<uint16_t*>(sm + L.queue_off) + wave * kQueue;
-            uint32_t q_tail = 0, q_head = 0;
-            auto full_test = [&](int count) {
-                if (lane < count) {
-                    const int i = queue[(q_head + lane) & (kQueue - 1)];
-                    const int o = level_of(L.sc_start, O, i);
-                    const unsigned j = i - L.sc_start[o];
-                    const Box sb = L.sb[o];
-                    const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
-                    const uint8_t* P = sm + L.toff[o] + (ry + kRingR) * L.tpitch[o] + (sb.x0 + rx - L.tx0[o]);
-                    const int v = full_score(P, L.tpitch[o], a.t);
-                    const int x = sb.x0 + rx, y = sb.y0 + ry;
-                    if (v > 0) {
-                        reinterpret_cast<uint16_t*>(sm + L.voff[o])[(y - L.qb[o].y0) * L.vpitch[o] + (x - L.qb[o].x0)] =
-                            (uint16_t)v;
-                        const Box d = L.dec[o];
-                        if (x >= d.x0 && x < d.x1 && y >= d.y0 && y < d.y1) {
-                            const int bit = L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
-                            atomicOr(&candw[bit >> 6], 1ull << (bit & 63));
-                        }
-                    }
-                }
-                q_head += count;
-            };
-            const int nck = L.ck_start[O];
-            for (int ck = wave; ck < nck; ck += kDetWaves) {
-                const int o = level_of(L.ck_start, O, ck);
-                const Box sb = L.sb[o];
-                const int n = box_w(sb) * box_h(sb);
-                const int tp = L.tpitch[o];
-                const uint8_t* T0 = sm + L.toff[o] + kRingR * tp + (sb.x0 - L.tx0[o]);
-                const int j0 = (ck - L.ck_start[o]) * kChunk;
-                bool pass[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = j0 + u * 64 + lane;
-                    pass[u] = false;
-                    if (j < n) {
-                        const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
-                        pass[u] = compass_pass(T0 + ry * tp + rx, tp, a.t);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint64_t bal = __ballot(pass[u]);
-                    if (pass[u]) {
-                        const unsigned below = __builtin_amdgcn_mbcnt_hi(
-                            (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                        queue[(q_tail + below) & (kQueue - 1)] = (uint16_t)(L.sc_start[o] + j0 + u * 64 + lane);
-                    }
-                    q_tail += (uint32_t)__popcll(bal);
-                }
-                __builtin_amdgcn_wave_barrier();
-                while (q_tail - q_head >= 64) {
-                    full_test(64);
-                    __builtin_amdgcn_wave_barrier();
-                }
-            }
-            if (q_tail != q_head) full_test((int)(q_tail - q_head));
-        }
-        __syncthreads();
-
-        // 3) scale-space maxima of the candidates, one 64-pixel word per wave
-        //    pass; words without candidates are skipped whole
-        for (int w = wave; w < L.nwords; w += kDetWaves) {
-            const uint64_t cand = candw[w];
-            bool keep = false;
-            if (cand != 0 && ((cand >> lane) & 1)) {
-                const int i = w * 64 + lane;
-                const int o = level_of(L.dc_start, O, i);
-                const unsigned j = i - L.dc_start[o];
-                const Box d = L.dec[o];
-                const int ry = fast_div(j, L.dcm[o]);
-                const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
-                keep = is_local_max(sm, L, o, O, x, y, vget(sm, L, o, x, y));
-            }
-            const uint64_t bal = __ballot(keep);
-            if (lane == 0) keepw[w] = bal;
-        }
-        __syncthreads();
-
-        // 4) rank: exclusive popcount prefix over the keep words (wave 0)
-        if (wave == 0) {
-            const int nw = L.nwords;
-            uint32_t* woff = reinterpret_cast<uint32_t*>(sm + L.woff_off);
-            const int per = (nw + 63) / 64;
-            const int w0 = lane * per, w1 = min(w0 + per, nw);
-            uint32_t sum = 0;
-            for (int w = w0; w < w1; ++w) sum += (uint32_t)__popcll(keepw[w]);
-            uint32_t incl = sum;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t up = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += up;
-            }
-            uint32_t run = incl - sum;
-            for (int w = w0; w < w1; ++w) {
-                woff[w] = run;
-                run += (uint32_t)__popcll(keepw[w]);
-            }
-            if (lane == 63) s_n = incl;
-        }
-        __syncthreads();
-    }
+    if (mark) detect_marked(a, c, sm, L, s_lvl, s_pitch, &s_n);
 
     // 5) this cell's offset in D_n: the counts of all earlier cells, carried
     //    ones read from D_{n-1}'s counts, marked ones from their count words
@@ -535,35 +624,80 @@ __device__ void detect_cell(const DetectArgs& a, int cell, uint8_t* sm)
 
     // 6) write D_n entries of this cell: the ranked maxima, or D_{n-1}'s
     if (mark) {
-        const uint32_t* woff = reinterpret_cast<const uint32_t*>(sm + L.woff_off);
-        for (int w = tid; w < L.nwords; w += kBlk) {
-            uint64_t bits = keepw[w];
-            uint32_t pos = excl + woff[w];
-            while (bits) {
-                const int b = __builtin_ctzll(bits);
-                bits &= bits - 1;
-                const int i = w * 64 + b;
-                const int o = level_of(L.dc_start, O, i);
-                const unsigned j = i - L.dc_start[o];
-                const Box d = L.dec[o];
-                const int ry = fast_div(j, L.dcm[o]);
-                const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
-                kpd_keypoint k;
-                k.x = (uint16_t)x;
-                k.y = (uint16_t)y;
-                k.octave = (uint8_t)o;
-                k.pad = 0;
-                k.score = (uint16_t)vget(sm, L, o, x, y);
-                // at most one keypoint per 2x2 block keeps pos below the capacity
-                if (pos < a.list_cap) a.list_cur[pos] = k;
-                ++pos;
-            }
-        }
+        emit_marked(a, L, sm, excl, a.list_cur, a.list_cap);
     } else {
         const uint32_t src0 = a.off_prev[c];
         for (uint32_t j = tid; j < n; j += kBlk)
             if (src0 + j < a.list_cap && excl + j < a.list_cap) a.list_cur[excl + j] = a.list_prev[src0 + j];
     }
+}
+
+// One frame j of a chunk of consecutive frames of one stream. Every cell
+// publishes its count (for frame j's later cells and frame j+1's marks) and
+// where its entries live (for frame j+1's carried cells): its own list when
+// marked, else wherever the cell's entries of frame j-1 live. Carried cells
+// only record a copy descriptor here; the copies run in the next launch,
+// once every list written by this one is visible on every XCD.
+__device__ void detect_cell_chunk(const ChunkArgs& t, int c, uint8_t* sm)
+{
+    __shared__ CellLayout L;
+    __shared__ int s_mark;
+    __shared__ uint32_t s_n, s_cprev, s_part[kDetWaves];
+    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
+    __shared__ int s_pitch[KPD_MAX_OCTAVES];
+    const DetectArgs& a = t.d;
+    const int tid = threadIdx.x;
+
+    if (tid == 0) {
+        load_level_ptrs(a, s_lvl, s_pitch);
+        const uint32_t cprev =
+            t.j == 0 ? t.prev_count[c] : (uint32_t)wait_word(&t.cnt_words_prev[c], a.epoch - 1, a.err);
+        bool mark = a.all_marked != 0;
+        if (!mark) {
+            const int cx = c % a.nc, cy = c / a.nc;
+            const int64_t area = (int64_t)a.col_w[cx] * a.row_h[cy];
+            mark = (a.id_on && (int64_t)a.sad[c] > (int64_t)a.id_thresh * area) || cprev >= a.kb_thresh;
+        }
+        if (t.last) a.mask[c] = (uint8_t)mark;
+        s_mark = mark;
+        s_cprev = cprev;
+    }
+    __syncthreads();
+    const bool mark = s_mark != 0;
+    if (mark) detect_marked(a, c, sm, L, s_lvl, s_pitch, &s_n);
+    __syncthreads();
+    const uint32_t own = mark ? s_n : s_cprev;
+    if (tid == 0)
+        __hip_atomic_store(&t.cnt_words[c], ((uint64_t)a.epoch << 32) | own, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t excl = sum_count_words(t.cnt_words, c, a.epoch, a.err, s_part);
+    if (tid == 0) {
+        uint32_t src_id, src_off;
+        if (mark) {
+            src_id = (uint32_t)t.j;
+            src_off = excl;
+        } else if (t.j == 0) {
+            src_id = kChunkPrev;
+            src_off = t.prev_offs[c];
+        } else {
+            const uint64_t st = wait_word(&t.src_words_prev[c], a.epoch - 1, a.err);
+            src_id = (uint32_t)(st >> 26) & 63u;
+            src_off = (uint32_t)st & ((1u << 26) - 1);
+        }
+        __hip_atomic_store(&t.src_words[c], ((uint64_t)a.epoch << 32) | ((uint64_t)src_id << 26) | src_off,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.count_cur[c] = own;
+        a.off_cur[c] = excl;
+        if (c == a.nc * a.nr - 1) *a.total_cur = excl + own;
+        CarryDesc cd;
+        cd.src_id = src_id;
+        cd.src_off = src_off;
+        cd.count = own;
+        cd.dst_off = excl;
+        cd.carried = mark ? 0u : 1u;
+        t.carry[c] = cd;
+    }
+    if (mark) emit_marked(a, L, sm, excl, a.list_cur, a.list_cap);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -593,6 +727,50 @@ __global__ __launch_bounds__(kBlk) void k_detect1(DetectArgs a)
 {
     extern __shared__ __align__(16) uint8_t sm[];
     detect_cell(a, blockIdx.x, sm);
+}
+
+// A chunk of consecutive frames of one stream: workgroup b is cell
+// b % ncell of frame b / ncell (frames in order, cells in order).
+__global__ __launch_bounds__(kBlk) void k_detect_chunk(const ChunkArgs* table, int ncell)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const int j = blockIdx.x / ncell;
+    detect_cell_chunk(table[j], (int)blockIdx.x - j * ncell, sm);
+}
+
+// Copies of a chunk: carried cells' entries into their frame's list, the
+// chunk's last D_n into the stream's next single-frame buffers, and the
+// chunk's per-cell SAD accumulators cleared for the next chunk.
+__global__ __launch_bounds__(64) void k_carry_chunk(CarryArgs a)
+{
+    const int j = blockIdx.x / a.ncell;
+    const int c = (int)blockIdx.x - j * a.ncell;
+    CarryDesc cd = a.carry[(size_t)j * a.ncell + c];
+    // a source outside this chunk can only come from a timed-out wait (the
+    // error flag is set): copy nothing then
+    if (cd.src_id != kChunkPrev && cd.src_id > (uint32_t)a.last) cd.count = 0;
+    const kpd_keypoint* src =
+        (cd.src_id == kChunkPrev ? a.prev_list : a.lists + (size_t)cd.src_id * a.list_stride) + cd.src_off;
+    kpd_keypoint* dst = a.lists + (size_t)j * a.list_stride + cd.dst_off;
+    if (cd.carried)
+        for (uint32_t k = threadIdx.x; k < cd.count; k += 64)
+            if (cd.src_off + k < a.list_cap && cd.dst_off + k < a.list_cap) dst[k] = src[k];
+    if (j == a.last) {
+        // the chunk's D_n also lands in the buffers the next frame reads
+        const kpd_keypoint* fsrc = cd.carried ? src : dst;
+        for (uint32_t k = threadIdx.x; k < cd.count; k += 64)
+            if ((cd.carried ? cd.src_off : cd.dst_off) + k < a.list_cap && cd.dst_off + k < a.list_cap)
+                a.next_list[cd.dst_off + k] = fsrc[k];
+        if (threadIdx.x == 0) {
+            a.next_count[c] = cd.count;
+            a.next_offs[c] = cd.dst_off;
+            if (c == a.ncell - 1) *a.next_total = cd.dst_off + cd.count;
+            a.sad_stats[c] = a.sad_chunk[(size_t)j * a.ncell + c];
+            a.sad_single_next[c] = 0;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.sad_chunk[(size_t)j * a.ncell + c] = 0;
 }
 
 // One batch tick: workgroup b works for stream map[b] (streams' workgroups
@@ -662,6 +840,9 @@ hipError_t set_detect_lds_limit(int lds_bytes)
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect1),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_chunk), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_bytes);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_batch),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
 }
@@ -676,6 +857,18 @@ hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s)
 {
     hipLaunchKernelGGL(k_detect1, dim3(ncell), dim3(kBlk), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_chunk(const ChunkArgs* table, int n_frames, int ncell, int lds_bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_detect_chunk, dim3(n_frames * ncell), dim3(kBlk), lds_bytes, s, table, ncell);
+    return hipGetLastError();
+}
+
+hipError_t launch_carry_chunk(const CarryArgs& a, int n_frames, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_carry_chunk, dim3(n_frames * a.ncell), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

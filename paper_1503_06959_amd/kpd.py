@@ -30,15 +30,16 @@ KEYPOINT_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("octave", "u1"), ("pad",
 EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_keypoints",
             "close_stream", "reset_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats",
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
-            "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch")
-KERNEL_NAMES = ("k_frame", "k_detect")
+            "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
+            "push_frames", "kpd_chunk_result", "get_chunk_keypoints")
+KERNEL_NAMES = ("k_frame", "k_detect", "k_carry")
 
 
 class KpdParams(ctypes.Structure):
     _fields_ = [("fast_t", ctypes.c_int32), ("n_octaves", ctypes.c_int32),
                 ("grid_cols", ctypes.c_int32), ("grid_rows", ctypes.c_int32),
                 ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32),
-                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("chunk_frames", ctypes.c_int32)]
 
 
 class KpdError(RuntimeError):
@@ -78,6 +79,9 @@ def _load() -> ctypes.CDLL:
     L.batch_tick.argtypes = [P]
     L.batch_gather.argtypes = [P, P, sz, P]
     L.close_batch.argtypes = [P]
+    L.push_frames.argtypes = [P, P, sz, sz, ctypes.c_int]
+    L.kpd_chunk_result.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P)]
+    L.get_chunk_keypoints.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
     return L
 
 
@@ -91,8 +95,8 @@ def _check(rc: int) -> int:
 
 
 def make_params(fast_t: int, n_octaves: int, grid_cols: int, grid_rows: int,
-                id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0) -> KpdParams:
-    return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, 0)
+                id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0, chunk_frames: int = 0) -> KpdParams:
+    return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, chunk_frames)
 
 
 def stream_bytes(width: int, height: int, params: KpdParams) -> int:
@@ -149,6 +153,32 @@ def get_keypoints(handle: int, n_cells: int, capacity: int = 4096) -> Tuple[np.n
         rc = lib.get_keypoints(handle, out.ctypes.data, len(out), ctypes.byref(cnt), mask.ctypes.data)
     _check(rc)
     return out[:cnt.value].copy(), mask
+
+
+def push_frames(handle: int, frames: torch.Tensor) -> None:
+    """frames: CUDA uint8 tensor [n, H, W] with unit column stride, read in
+    place (the caller keeps it alive until the next push)."""
+    if not (isinstance(frames, torch.Tensor) and frames.device.type == "cuda" and frames.dtype == torch.uint8
+            and frames.dim() == 3 and frames.stride(2) == 1):
+        raise ValueError("frames must be a CUDA uint8 [n, H, W] tensor with unit column stride")
+    _check(lib.push_frames(handle, frames.data_ptr(), frames.stride(0), frames.stride(1), frames.shape[0]))
+
+
+def get_chunk_keypoints(handle: int, i: int, capacity: int = 4096) -> np.ndarray:
+    out = np.zeros(max(capacity, 1), KEYPOINT_DTYPE)
+    cnt = ctypes.c_size_t()
+    rc = lib.get_chunk_keypoints(handle, i, out.ctypes.data, len(out), ctypes.byref(cnt))
+    if rc == KPD_ETRUNC:
+        out = np.zeros(cnt.value, KEYPOINT_DTYPE)
+        rc = lib.get_chunk_keypoints(handle, i, out.ctypes.data, len(out), ctypes.byref(cnt))
+    _check(rc)
+    return out[:cnt.value].copy()
+
+
+def chunk_result(handle: int, i: int) -> Tuple[int, int]:
+    lst, cnt = ctypes.c_void_p(), ctypes.c_void_p()
+    _check(lib.kpd_chunk_result(handle, i, ctypes.byref(lst), ctypes.byref(cnt)))
+    return lst.value, cnt.value
 
 
 def close_stream(handle: int) -> None:
@@ -256,6 +286,14 @@ class Stream:
         push_frame(self.handle, frame, retain)
         if retain:
             self._held = [self._held[1], frame]
+
+    def push_chunk(self, frames: torch.Tensor) -> None:
+        """Several consecutive frames [n, H, W] in one call (n <= chunk_frames)."""
+        push_frames(self.handle, frames)
+        self._held = [self._held[1], frames]
+
+    def chunk_keypoints(self, i: int) -> np.ndarray:
+        return get_chunk_keypoints(self.handle, i)
 
     def set_thresholds(self, fast_t: int, id_thresh: int, kb_thresh: int = KPD_KB_OFF) -> None:
         set_thresholds(self.handle, fast_t, id_thresh, kb_thresh)

@@ -1,0 +1,173 @@
+"""GPU parity of chunked pushes: push_frames runs several consecutive frames
+of one stream in one pass (three launches), and every frame's D_n, the last
+frame's mask, counts and SAD, and later single-frame pushes must equal the
+oracle's frame-by-frame run, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06959_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KB_OFF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def kpd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_06959_amd import kpd as k
+    return k
+
+
+def tuples(arr):
+    return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
+
+
+def det_of(name, **kw):
+    d = synth.DETECTORS[name]
+    v = dict(t=d.fast_t, O=d.n_octaves, Nc=d.grid_cols, Nr=d.grid_rows, TI=d.id_thresh, TH=d.kb_thresh)
+    v.update(kw)
+    return (v["t"], v["O"], v["Nc"], v["Nr"], v["TI"], v["TH"])
+
+
+def run_chunks(kpd, frames, det, plan, K, resets=(), thresholds=None, pad_rows=0, pad_frame=0):
+    """plan: list of chunk lengths (0 = one single-frame push_frame call).
+    Frames go to the GPU as one device buffer [F, H + pad_rows, W + pad] so
+    that chunks read them in place; the oracle takes them one by one."""
+    import torch
+    F, H, W = frames.shape
+    t, O, Nc, Nr, TI, TH = det
+    g = kpd.Stream(W, H, kpd.make_params(t, O, Nc, Nr, TI, TH, 0, K))
+    o = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    buf = np.zeros((F, H + pad_rows, W + pad_frame), np.uint8)
+    buf[:, :H, :W] = frames
+    dev = torch.from_numpy(buf).cuda()
+    view = dev[:, :H, :W]
+    i = 0
+    for step, n in enumerate(plan):
+        if i >= F:
+            break
+        if step in resets:
+            g.reset()
+            o.reset()
+        if thresholds and step in thresholds:
+            g.set_thresholds(*thresholds[step])
+            o.set_thresholds(*thresholds[step])
+        if n == 0:
+            g.push(view[i], retain=True)
+            o.push(frames[i])
+            ok, om, osad, ocnt = o.get()
+            gk, gm = g.keypoints()
+            assert tuples(gk) == tuples(ok), f"single frame {i}"
+            np.testing.assert_array_equal(gm, om, err_msg=f"mask frame {i}")
+            i += 1
+            continue
+        n = min(n, F - i)
+        g.push_chunk(view[i:i + n])
+        for j in range(n):
+            o.push(frames[i + j])
+            ok, om, osad, ocnt = o.get()
+            assert tuples(g.chunk_keypoints(j)) == tuples(ok), f"chunk at {i} frame {i + j}"
+        gk, gm = g.keypoints()
+        assert tuples(gk) == tuples(ok), f"last frame of chunk at {i}"
+        np.testing.assert_array_equal(gm, om, err_msg=f"mask after chunk at {i}")
+        gsad, gcnt = g.cell_stats()
+        np.testing.assert_array_equal(gcnt, ocnt, err_msg=f"counts after chunk at {i}")
+        if om.any() and not om.all() and TI >= 0 and TI < 255:
+            np.testing.assert_array_equal(gsad.astype(np.int64), osad, err_msg=f"sad after chunk at {i}")
+        i += n
+    g.close()
+
+
+def test_c1_chunks_of_every_length(kpd):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 30)
+    run_chunks(kpd, frames, det_of("c1_320x240"), [1, 2, 3, 4, 5, 6, 8, 1], K=8)
+
+
+def test_c2_chunks_mixed_with_single_pushes(kpd):
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 60)
+    run_chunks(kpd, frames, det_of("c2_640x480"), [0, 8, 0, 0, 16, 3, 0, 16, 16], K=16)
+
+
+def test_c2_keyframe_mode_chunks(kpd):
+    # counts decide marks (T_H): a chunk's frame j reads frame j-1's counts
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 40)
+    run_chunks(kpd, frames, det_of("c2_640x480", TH=3), [8, 8, 0, 8, 8, 8], K=8)
+    run_chunks(kpd, frames, det_of("c2_640x480", TI=255, TH=2), [4, 4, 4, 0, 4], K=4)
+
+
+@pytest.mark.parametrize("TI,TH", [(-1, KB_OFF), (8, 0), (255, KB_OFF), (0, KB_OFF)])
+def test_c1_chunk_mask_modes(kpd, TI, TH):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 12)
+    run_chunks(kpd, frames, det_of("c1_320x240", TI=TI, TH=TH), [4, 0, 7], K=8)
+
+
+def test_c3_1080p_chunks(kpd):
+    frames = synth.make_video(synth.SCENES["c3_1920x1080"], 24)
+    run_chunks(kpd, frames, det_of("c3_1920x1080"), [8, 8, 0, 7], K=8)
+
+
+def test_chunks_with_resets_thresholds_and_padding(kpd):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 30)
+    det = det_of("c1_320x240")
+    run_chunks(kpd, frames, det, [5, 5, 5, 0, 5, 5, 5], K=6, resets=(1, 4),
+               thresholds={2: (det[0], 4, 2), 5: (det[0] + 5, 4, 2)}, pad_rows=3, pad_frame=17)
+
+
+def test_chunk_odd_shapes(kpd):
+    for W, H, det in [(333, 251, (25, 4, 7, 5, 4, KB_OFF)), (9, 13, (10, 2, 3, 2, 2, 3)),
+                      (127, 255, (15, 7, 1, 2, 8, KB_OFF))]:
+        sc = synth.Scene(W, H, 9, 6, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 900 + W)
+        run_chunks(kpd, synth.make_video(sc), det, [3, 0, 5], K=5)
+
+
+def test_pyramid_after_chunk_is_last_frame(kpd):
+    import torch
+    sc = synth.SCENES["c1_320x240"]
+    d = synth.DETECTORS["c1_320x240"]
+    frames = synth.make_video(sc, 4)
+    g = kpd.Stream(320, 240, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, 8, KB_OFF, 0, 4))
+    dev = torch.from_numpy(frames).cuda()
+    g.push_chunk(dev)
+    ref = oracle.pyramid(frames[3], d.n_octaves)
+    for o in range(1, d.n_octaves):
+        np.testing.assert_array_equal(g.level(o), ref[o])
+    g.close()
+
+
+def test_chunk_errors(kpd):
+    import torch
+    frames = torch.from_numpy(synth.make_video(synth.SCENES["c1_320x240"], 4)).cuda()
+    plain = kpd.Stream(320, 240, kpd.make_params(30, 3, 8, 6))
+    with pytest.raises(kpd.KpdError):
+        plain.push_chunk(frames)                       # opened without chunk_frames
+    plain.close()
+    g = kpd.Stream(320, 240, kpd.make_params(30, 3, 8, 6, 8, KB_OFF, 0, 3))
+    with pytest.raises(kpd.KpdError):
+        g.push_chunk(frames)                           # 4 frames > chunk_frames
+    with pytest.raises(kpd.KpdError):
+        g.chunk_keypoints(0)                           # no chunk yet
+    # overlapping frames
+    assert kpd.lib.push_frames(g.handle, frames.data_ptr(), 320, 320, 2) == kpd.KPD_EINVAL
+    g.push_chunk(frames[:2])
+    with pytest.raises(kpd.KpdError):
+        g.chunk_keypoints(2)
+    g.push(frames[2], retain=True)
+    with pytest.raises(kpd.KpdError):
+        g.chunk_keypoints(0)                           # a single push ends the chunk's results
+    g.close()
+
+
+def test_chunk_timing_counts_launches(kpd):
+    import torch
+    frames = torch.from_numpy(synth.make_video(synth.SCENES["c1_320x240"], 8)).cuda()
+    g = kpd.Stream(320, 240, kpd.make_params(30, 3, 8, 6, 8, KB_OFF, 0, 4))
+    kpd.profile(g.handle, True)
+    g.push_chunk(frames[:4])
+    g.push_chunk(frames[4:])
+    ms, n = kpd.profile_read(g.handle)
+    assert list(n) == [2, 2, 2]
+    g.close()

@@ -423,6 +423,22 @@ def test_threshold_change_forces_full_redetection():
     assert not s.get()[1].any()
 
 
+def test_reset_forces_full_redetection_once():
+    frames = _scene(seed=13)
+    W, H, O, Nc, Nr = 96, 72, 3, 6, 4
+    s = oracle.Stream(W, H, 15, O, Nc, Nr, 255)
+    s.push(frames[0])
+    s.push(frames[1])
+    assert not s.get()[1].any()
+    s.reset()
+    s.push(frames[2])
+    kps, mask, _, _ = s.get()
+    assert mask.all()
+    assert sorted(kps_tuples(kps)) == sorted(kps_tuples(oracle.detect(frames[2], 15, O)))
+    s.push(frames[3])                # only the frame after the reset
+    assert not s.get()[1].any()
+
+
 # ------------------------------------------------------ stored regression values
 
 @pytest.mark.parametrize("name,det", [
