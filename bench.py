@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--serve-budget-mib", type=int, default=1024)
     ap.add_argument("--batch-ticks", type=int, default=120)
     ap.add_argument("--batch-clip", type=int, default=40)
+    ap.add_argument("--chunk", type=int, default=32, help="frames per push_frames call in the chunked section")
+    ap.add_argument("--no-chunk", action="store_true")
+    ap.add_argument("--mode", choices=("both", "masked", "full"), default="both",
+                    help="masked or full: run only that pass of --workload and print its line (for profiling)")
+    ap.add_argument("--chunked", action="store_true", help="with --mode: push --chunk frames per call")
     return ap.parse_args()
 
 
@@ -92,17 +97,28 @@ class Workload:
                 + ("full-frame (T_I<0)" if id_thresh < 0 else f"T_I={id_thresh}, T_H off"))
 
 
-def open_stream(wl: Workload, id_thresh: int):
+def open_stream(wl: Workload, id_thresh: int, chunk: int = 0):
     from paper_1503_06959_amd import kpd
     d = wl.det
-    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh)
-    return kpd.Stream(wl.W, wl.H, params)
+    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh, 0, chunk)
+    s = kpd.Stream(wl.W, wl.H, params)
+    s.chunk = chunk
+    return s
 
 
 def one_pass(kpd, s, wl: Workload) -> None:
-    """Push every frame of the video in place; results stay on the device."""
+    """Push every frame of the video in place (one frame per call, or
+    chunks of s.chunk consecutive frames); results stay on the device."""
     kpd.reset_stream(s.handle)
     h, dev, pitch = s.handle, wl.dev, wl.W
+    if s.chunk > 1:
+        push = kpd.lib.push_frames
+        base, stride = dev.data_ptr(), wl.W * wl.H
+        for i in range(0, wl.F, s.chunk):
+            rc = push(h, base + i * stride, stride, pitch, min(s.chunk, wl.F - i))
+            if rc:
+                raise kpd.KpdError(rc, kpd.lib.kpd_last_error().decode())
+        return
     push = kpd.lib.push_frame
     for i in range(wl.F):
         rc = push(h, dev[i].data_ptr(), pitch, kpd.FRAME_DEVICE_RETAIN)
@@ -120,6 +136,24 @@ def timed_passes(kpd, s, wl: Workload, steps: int, warmup: int) -> float:
         one_pass(kpd, s, wl)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def chunk_latency(kpd, s, wl: Workload, reps: int = 3):
+    """Milliseconds from push_frames of one chunk to the last frame's
+    keypoints on the host (the first frame of a chunk waits for the whole
+    chunk to arrive before this starts)."""
+    import numpy as np
+    lat = []
+    base, stride = wl.dev.data_ptr(), wl.W * wl.H
+    for _ in range(reps):
+        kpd.reset_stream(s.handle)
+        for i in range(0, wl.F, s.chunk):
+            t0 = time.perf_counter()
+            kpd._check(kpd.lib.push_frames(s.handle, base + i * stride, stride, wl.W, min(s.chunk, wl.F - i)))
+            s.keypoints()
+            lat.append((time.perf_counter() - t0) * 1e3)
+    lat = np.array(lat)
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
 def latency_pass(kpd, s, wl: Workload):
@@ -147,23 +181,31 @@ def latency_pass(kpd, s, wl: Workload):
 
 
 def kernel_profile(kpd, s, wl: Workload, steps: int):
-    import numpy as np
+    """Event-timed milliseconds and launch counts per kernel over `steps`
+    passes (events on the stream the kernels are launched on)."""
     kpd.profile(s.handle, True)
     kpd.profile_read(s.handle)
     for _ in range(steps):
         one_pass(kpd, s, wl)
     ms, n = kpd.profile_read(s.handle)
     kpd.profile(s.handle, False)
-    return {name: (float(ms[k]), int(n[k])) for k, name in enumerate(kpd.KERNEL_NAMES)}
+    out = {name: (float(ms[k]), int(n[k])) for k, name in enumerate(kpd.KERNEL_NAMES) if n[k]}
+    out["passes"] = steps
+    return out
 
 
-def algorithmic_bytes(wl: Workload, st, masked: bool) -> dict:
-    """Bytes the method must move per launch of each kernel, averaged over
-    the frames of one pass. The tile pass reads I_n (and I_{n-1} for the
-    intensity-difference test) and writes the coarser octaves; the cell pass
-    reads the octave pixels of the marked cells, writes their keypoints and
-    copies the carried ones (Eq. 1). Score maps are an LDS intermediate and
-    count nothing. Frame 0 of a pass marks every cell."""
+def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> dict:
+    """Bytes the method must move per pass over the video, per kernel.
+    The tile pass reads I_n (and I_{n-1} for the intensity-difference test)
+    and writes the coarser octaves. The cell pass reads the octave pixels of
+    the marked cells, writes their keypoints, and carries the others' (Eq. 1)
+    with a 16-byte read+write per entry; 24 bytes per cell and frame cover
+    the per-cell counts, offsets and SAD. In chunks the cell pass writes
+    only the marked cells' keypoints (plus 16 bytes of mark, count and SAD
+    per cell and frame) and the compaction pass reads and writes every
+    frame's whole D_n (16 bytes per entry) plus the per-cell metadata.
+    Score maps are an LDS intermediate and count nothing. Frame 0 of a pass
+    marks every cell."""
     d = wl.det
     N = wl.W * wl.H
     lv = level_sizes(wl.W, wl.H, d.n_octaves)
@@ -171,37 +213,73 @@ def algorithmic_bytes(wl: Workload, st, masked: bool) -> dict:
     F = wl.F
     sad_frames = (F - 1) if masked else 0
     frac = [m / wl.ncell for m in st["marked"]]
-    carried = [t - n for t, n in zip(st["total_kp"], st["new_kp"])]
-    detect = sum(f * sum(lv) for f in frac) + 8 * sum(st["new_kp"]) + 16 * sum(carried) + 24 * wl.ncell * F
-    return {"k_frame": N + P + N * sad_frames / F, "k_detect": detect / F}
+    carried = sum(t - n for t, n in zip(st["total_kp"], st["new_kp"]))
+    meta = 24 * wl.ncell * F
+    scan = sum(f * sum(lv) for f in frac) + 8 * sum(st["new_kp"])
+    out = {"k_frame": F * (N + P) + N * sad_frames}
+    if chunked:
+        out["k_detect"] = scan + 16 * wl.ncell * F
+        out["k_compact"] = 16 * sum(st["total_kp"]) + meta
+    else:
+        out["k_detect"] = scan + 16 * carried + meta
+    return out
 
 
-def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True):
-    s = open_stream(wl, id_thresh)
+def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True, chunk=0):
+    s = open_stream(wl, id_thresh, chunk)
     sec = timed_passes(kpd, s, wl, args.steps, args.warmup)
-    res = {"sec_per_pass": sec, "frames": wl.F,
+    res = {"sec_per_pass": sec, "frames": wl.F, "chunk": chunk,
            "mpix_per_s": wl.F * wl.W * wl.H / sec / 1e6, "frames_per_s": wl.F / sec}
     if want_latency:
-        res.update(latency_pass(kpd, s, wl))
+        if chunk > 1:
+            res["lat_p50"], res["lat_p99"] = chunk_latency(kpd, s, wl)
+        else:
+            res.update(latency_pass(kpd, s, wl))
     if want_profile:
         res["kernels"] = kernel_profile(kpd, s, wl, max(1, args.steps // 2))
     s.close()
     return res
 
 
-def roofline_of(wl: Workload, res, masked: bool, traffic=None):
+def chunked_section(kpd, wl: Workload, args, masked, full) -> dict:
+    """The same video through push_frames, args.chunk frames per call
+    (identical results; the tests check it frame by frame). `masked` and
+    `full` are the per-frame runs, whose keypoint statistics the roofline's
+    algorithmic bytes reuse."""
+    K = args.chunk
+    log(f"[bench] {wl.name} chunked ({K} frames per call)")
+    out = {"chunk_frames": K, "calls_per_pass": -(-wl.F // K)}
+    for key, ti, single, is_masked in (("masked", wl.det.id_thresh, masked, True),
+                                       ("full_frame", -1, full, False)):
+        r = run_workload(kpd, wl, ti, args, chunk=K)
+        out[key] = {"value": round(r["mpix_per_s"], 2), "unit": "Mpixel/s",
+                    "frames_per_s": round(r["frames_per_s"], 1),
+                    "ms_per_step": round(r["sec_per_pass"] * 1e3, 4),
+                    "over_per_frame_push": round(r["mpix_per_s"] / single["mpix_per_s"], 3),
+                    "chunk_latency_ms": {"p50": round(r["lat_p50"], 4), "p99": round(r["lat_p99"], 4),
+                                         "what": "push_frames of one chunk -> last frame's keypoints on the host"},
+                    "roofline": roofline_of(wl, r, is_masked, stats=single)}
+    return out
+
+
+def roofline_of(wl: Workload, res, masked: bool, traffic=None, stats=None):
     """Dominant kernel by summed event-timed duration; achieved = algorithmic
-    bytes per launch / average launch duration."""
-    ab = algorithmic_bytes(wl, res, masked)
-    kern = res["kernels"]
+    bytes per launch / average launch duration. `stats` (marked cells and
+    keypoint counts per frame) default to the run's own."""
+    st = dict(stats or res)
+    st["chunk"] = res.get("chunk", 0)
+    ab = algorithmic_bytes(wl, st, masked, chunked=res.get("chunk", 0) > 1)
+    kern = {k: v for k, v in res["kernels"].items() if k != "passes"}
+    passes = res["kernels"]["passes"]
     dom = max(kern, key=lambda k: kern[k][0])
     ms, n = kern[dom]
+    per_launch = ab[dom] * passes / max(n, 1)
     avg_s = ms / 1e3 / max(n, 1)
-    achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
+    achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
     return {
         "kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-        "algorithmic_bytes_per_launch": int(ab[dom]), "avg_launch_us": round(avg_s * 1e6, 3),
+        "algorithmic_bytes_per_launch": int(per_launch), "avg_launch_us": round(avg_s * 1e6, 3),
         "launches": n,
         "per_kernel_avg_us": {k: round(v[0] * 1e3 / max(v[1], 1), 3) for k, v in kern.items()},
     }
@@ -384,6 +462,18 @@ def main():
     from paper_1503_06959_amd import kpd
 
     wl = Workload(args.workload)
+    if args.mode != "both":
+        masked = args.mode == "masked"
+        chunk = args.chunk if args.chunked else 0
+        log(f"[bench] {args.mode} pass only, chunk {chunk}")
+        r = run_workload(kpd, wl, wl.det.id_thresh if masked else -1, args, chunk=chunk)
+        stats = r if chunk <= 1 else run_workload(kpd, wl, wl.det.id_thresh if masked else -1, args,
+                                                  want_profile=False)
+        print(json.dumps({"workload": wl.describe(wl.det.id_thresh if masked else -1), "chunk": chunk,
+                          "value": round(r["mpix_per_s"], 2), "unit": "Mpixel/s",
+                          "frames_per_s": round(r["frames_per_s"], 1),
+                          "roofline": roofline_of(wl, r, masked, stats=stats)}), flush=True)
+        return
     log("[bench] masked pass")
     masked = run_workload(kpd, wl, wl.det.id_thresh, args)
     log(f"[bench] masked {masked['mpix_per_s']:.1f} Mpx/s; full-frame pass")
@@ -418,6 +508,8 @@ def main():
         "masked_over_full": round(masked["mpix_per_s"] / full["mpix_per_s"], 3),
         "roofline": roofline_of(wl, masked, True),
     }
+    if not args.no_chunk:
+        out["chunked"] = chunked_section(kpd, wl, args, masked, full)
     if not args.no_hd:
         del wl
         torch.cuda.empty_cache()
@@ -445,6 +537,8 @@ def main():
                            "algorithmic_bytes_per_frame": int(b_full),
                            "roofline": roofline_of(hd, hf, False)},
         }
+        if not args.no_chunk:
+            out["hd_1080p"]["chunked"] = chunked_section(kpd, hd, args, hm, hf)
         wl = hd
     if not args.no_batch:
         del wl

@@ -135,7 +135,7 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
 
 /* Process `n_frames` consecutive frames (1 <= n_frames <= chunk_frames) in
  * one pass of three launches: a pyramid/difference pass over all of them, a
- * detection pass over every (frame, cell), and a copy pass for carried cells.
+ * detection pass over every (frame, cell), and a compaction pass per frame.
  * Frame i is the device buffer frames + i * frame_stride (rows pitch_bytes
  * apart), read in place under the KPD_FRAME_DEVICE_RETAIN rules (the last
  * frame is I_{n-1} of the next push). Results are exactly those of pushing
@@ -241,11 +241,11 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
 /* ------------------------------------------------------ kernel timing */
 
 /* Kernels of one push, in launch order: the pyramid-and-SAD pass over
- * level-0 tiles, the per-cell detection and output pass, and (push_frames
- * only) the copy pass of carried cells. */
+ * level-0 tiles, the per-cell detection pass, and (push_frames only) the
+ * compaction pass that builds each frame's D_n in cell order. */
 #define KPD_K_FRAME 0
 #define KPD_K_DETECT 1
-#define KPD_K_CARRY 2   /* copy pass of push_frames */
+#define KPD_K_COMPACT 2 /* compaction pass of push_frames */
 #define KPD_NKERNELS 3
 
 /* Switch per-kernel GPU timing on (1) or off (0). While on, every kernel

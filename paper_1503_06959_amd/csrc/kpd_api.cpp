@@ -54,13 +54,16 @@ struct Layout {
     size_t off_hdr = 0, off_slot[2] = {0, 0}, off_lvl[KPD_MAX_OCTAVES] = {};
     size_t off_sad[2] = {0, 0}, off_count[2] = {0, 0}, off_offs[2] = {0, 0}, off_list[2] = {0, 0};
     size_t off_mask = 0, off_status = 0, off_colw = 0, off_rowh = 0, off_layouts = 0;
-    // chunks of consecutive frames (push_frames): K copies of the octaves and
-    // per-frame counts, offsets, lists, SAD, count/source words and copy
-    // descriptors, plus the chunk's argument tables (two sets)
-    int K = 1;
+    // chunks of consecutive frames (push_frames): K copies of the octaves,
+    // per-frame SAD, sparse lists with per-cell counts, count words, marks
+    // (cell-major, Kp bytes per cell), dense lists with counts, offsets and
+    // totals, the cells' sparse bases, and the chunk's argument tables (two
+    // sets)
+    int K = 1, Kp = 4;
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
-    size_t off_cntw = 0, off_srcw = 0, off_carry = 0, off_ctab[2] = {0, 0}, off_ftab[2] = {0, 0}, off_fmap = 0;
+    size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0;
+    size_t off_cntw = 0, off_ctab[2] = {0, 0}, off_ftab[2] = {0, 0}, off_fmap = 0;
     size_t list_cap = 0;
     int lds_bytes = 0;   // dynamic LDS of the cell pass
     size_t total = 0;
@@ -178,10 +181,13 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_coffs = off; off = align_up(off + kc * 4);
         L->off_ctotal = off; off = align_up(off + (size_t)L->K * 4);
         L->off_cntw = off; off = align_up(off + kc * 8);
-        L->off_srcw = off; off = align_up(off + kc * 8);
-        L->off_carry = off; off = align_up(off + kc * sizeof(kpd::CarryDesc));
+        L->Kp = (L->K + 3) / 4 * 4;
+        L->off_marks = off; off = align_up(off + (size_t)L->ncell * L->Kp);
+        L->off_own = off; off = align_up(off + kc * 4);
+        L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
         L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
-        L->off_clist = off; off += L->clist_stride * (size_t)L->K;
+        L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
+        L->off_clist = off; off += L->clist_stride * (size_t)(L->K - 1);   // the last frame's D goes to D_n
         for (int k = 0; k < 2; ++k) { L->off_ctab[k] = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs)); }
         for (int k = 0; k < 2; ++k) { L->off_ftab[k] = off; off = align_up(off + (size_t)L->K * sizeof(kpd::TickArgs)); }
         L->off_fmap = off; off = align_up(off + (size_t)L->K * L->tiles_x * L->tiles_y * 2);
@@ -351,6 +357,7 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         e = hipMemcpyAsync(s->arena + L.off_layouts, layouts.data(), layouts.size() * sizeof(kpd::CellLayout),
                            hipMemcpyHostToDevice, s->stream);
     std::vector<uint16_t> fmap;
+    std::vector<uint32_t> cbase;
     if (L.K > 1) {
         const int nt = L.tiles_x * L.tiles_y;
         fmap.resize((size_t)L.K * nt);
@@ -360,7 +367,19 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         if (e == hipSuccess)
             e = hipMemsetAsync(s->arena + L.off_csad, 0, (size_t)L.K * L.ncell * 4, s->stream);
         if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_cntw, 0, (size_t)L.K * L.ncell * 8, s->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_srcw, 0, (size_t)L.K * L.ncell * 8, s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_marks, 0, (size_t)L.ncell * L.Kp, s->stream);
+        cbase.resize(L.ncell);
+        uint32_t acc = 0;
+        for (int c = 0; c < L.ncell; ++c) {
+            cbase[c] = acc;
+            const kpd::Box r = kpd::cell_rect(c, L.W, L.H, L.nc, L.nr);
+            kpd::CellLayout CL;
+            kpd::cell_layout(r, L.O, L.w, L.h, &CL);
+            for (int o = 0; o < L.O; ++o) acc += (uint32_t)kpd::decision_capacity(CL.dec[o]);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice,
+                               s->stream);
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
             e = hipHostMalloc(reinterpret_cast<void**>(&s->ctab_host[k]), (size_t)L.K * sizeof(kpd::ChunkArgs),
                               hipHostMallocDefault);
@@ -531,6 +550,9 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         return fail(KPD_EINVAL, "frames overlap");
     const int k = (int)(s->chunks & 1);
     if (s->ctab_used[k]) KPD_HIP(hipEventSynchronize(s->ctab_free[k]));
+    // marks read the previous frame's counts only when T_H can mark a cell
+    // and the parameters do not mark every cell anyway
+    const bool kb_chain = s->p.kb_thresh != KPD_KB_OFF && s->p.kb_thresh != 0 && s->p.id_thresh >= 0;
 
     const uint32_t n0 = (uint32_t)s->n_pushed;
     const int pitch = (int)pitch_bytes;
@@ -592,10 +614,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         d.kb_thresh = s->p.kb_thresh;
         d.sad = fa.sad;
         d.mask = s->at<uint8_t>(L.off_mask);
-        d.count_cur = s->at<uint32_t>(L.off_ccount) + (size_t)j * kc;
-        d.off_cur = s->at<uint32_t>(L.off_coffs) + (size_t)j * kc;
-        d.list_cur = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_clist + L.clist_stride * (size_t)j);
-        d.total_cur = s->at<uint32_t>(L.off_ctotal) + j;
+        d.list_cur = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_sparse + L.clist_stride * (size_t)j);
         d.list_cap = (uint32_t)L.list_cap;
         d.layouts = s->at<kpd::CellLayout>(L.off_layouts);
         d.col_w = s->at<uint16_t>(L.off_colw);
@@ -604,13 +623,14 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
         c.j = j;
         c.last = j == n_frames - 1 ? 1 : 0;
+        c.kb_chain = kb_chain ? 1 : 0;
+        c.K = L.Kp;
         c.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);
-        c.prev_offs = s->at<uint32_t>(L.off_offs[fb_prev]);
+        c.cell_base = s->at<uint32_t>(L.off_cbase);
+        c.marks = s->at<uint8_t>(L.off_marks);
+        c.own_count = s->at<uint32_t>(L.off_own) + (size_t)j * kc;
         c.cnt_words = s->at<unsigned long long>(L.off_cntw) + (size_t)j * kc;
         c.cnt_words_prev = j ? c.cnt_words - kc : nullptr;
-        c.src_words = s->at<unsigned long long>(L.off_srcw) + (size_t)j * kc;
-        c.src_words_prev = j ? c.src_words - kc : nullptr;
-        c.carry = s->at<kpd::CarryDesc>(L.off_carry) + (size_t)j * kc;
     }
 
     kpd::ChunkArgs* ctab = s->at<kpd::ChunkArgs>(L.off_ctab[k]);
@@ -628,14 +648,23 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     KPD_HIP(timed(s, KPD_K_DETECT, [&] {
         return kpd::launch_detect_chunk(ctab, n_frames, L.ncell, L.lds_bytes, s->stream);
     }));
-    kpd::CarryArgs ca{};
+    kpd::CompactArgs ca{};
     ca.ncell = L.ncell;
     ca.last = n_frames - 1;
+    ca.K = L.Kp;
     ca.list_cap = (uint32_t)L.list_cap;
     ca.list_stride = L.clist_stride / sizeof(kpd_keypoint);
-    ca.lists = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_clist);
+    ca.sparse = reinterpret_cast<const kpd_keypoint*>(s->arena + L.off_sparse);
+    ca.cell_base = s->at<uint32_t>(L.off_cbase);
+    ca.marks = s->at<uint8_t>(L.off_marks);
+    ca.own_count = s->at<uint32_t>(L.off_own);
     ca.prev_list = s->at<kpd_keypoint>(L.off_list[fb_prev]);
-    ca.carry = s->at<kpd::CarryDesc>(L.off_carry);
+    ca.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);
+    ca.prev_offs = s->at<uint32_t>(L.off_offs[fb_prev]);
+    ca.lists = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_clist);
+    ca.counts = s->at<uint32_t>(L.off_ccount);
+    ca.offs = s->at<uint32_t>(L.off_coffs);
+    ca.totals = s->at<uint32_t>(L.off_ctotal);
     ca.next_list = s->at<kpd_keypoint>(L.off_list[fb_next]);
     ca.next_count = s->at<uint32_t>(L.off_count[fb_next]);
     ca.next_offs = s->at<uint32_t>(L.off_offs[fb_next]);
@@ -644,7 +673,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     const uint32_t n_last = n0 + (uint32_t)n_frames - 1;
     ca.sad_stats = s->at<uint32_t>(L.off_sad[n_last & 1]);
     ca.sad_single_next = s->at<uint32_t>(L.off_sad[(n_last + 1) & 1]);
-    KPD_HIP(timed(s, KPD_K_CARRY, [&] { return kpd::launch_carry_chunk(ca, n_frames, s->stream); }));
+    KPD_HIP(timed(s, KPD_K_COMPACT, [&] { return kpd::launch_compact_chunk(ca, n_frames, s->stream); }));
 
     const uint8_t* last = frames + (size_t)(n_frames - 1) * frame_stride;
     s->prev0 = last;
@@ -663,6 +692,7 @@ int kpd_chunk_result(kpd_stream* s, int i, const kpd_keypoint** d_list, const ui
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (i < 0 || i >= s->chunk_n) return fail(KPD_EINVAL, "no such frame in the last chunk");
     const Layout& L = s->L;
+    if (i == s->chunk_n - 1) return kpd_device_result(s, d_list, d_count);   // the last frame's D is D_n
     if (d_list) *d_list = reinterpret_cast<const kpd_keypoint*>(s->arena + L.off_clist + L.clist_stride * (size_t)i);
     if (d_count) *d_count = s->at<uint32_t>(L.off_ctotal) + i;
     return KPD_OK;
@@ -673,6 +703,7 @@ int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (!count) return fail(KPD_EINVAL, "count is NULL");
     if (i < 0 || i >= s->chunk_n) return fail(KPD_EINVAL, "no such frame in the last chunk");
+    if (i == s->chunk_n - 1) return get_keypoints(s, out, capacity, count, nullptr);   // D_n itself
     const Layout& L = s->L;
     uint32_t hdr[4] = {0, 0, 0, 0}, total = 0;
     KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));

@@ -69,48 +69,52 @@ struct TickArgs {
     int tile_base, cell_base;
 };
 
-// A chunk of consecutive frames of one stream.
-constexpr uint32_t kChunkPrev = 63;  // source id of the list before the chunk
-
-struct CarryDesc {
-    uint32_t src_id;   // chunk frame whose list holds the cell's entries, or kChunkPrev
-    uint32_t src_off;  // their first index there
-    uint32_t count;
-    uint32_t dst_off;  // the cell's first index in its own frame's list
-    uint32_t carried;  // 1: copy the entries (the cell was not marked)
-    uint32_t pad[3];
-};
-
+// A chunk of consecutive frames of one stream, in two passes after the
+// tile pass. The detection pass writes each marked cell's keypoints at the
+// cell's fixed base in its frame's sparse list (no cross-cell offsets, so no
+// waits between cells) and records the mark. The compaction pass (one
+// workgroup per frame) finds for every cell the last chunk frame up to its
+// own where the cell was marked, or the list before the chunk, and copies
+// the entries into the frame's list in cell order (Eq. 1).
 struct ChunkArgs {
-    DetectArgs d;                               // frame j's detection arguments
+    DetectArgs d;                               // frame j's detection arguments (list_cur = sparse list j)
     int j, last;                                // frame index in the chunk, is it the last
+    int kb_chain;                               // marks read frame j-1's counts (T_H active)
+    int K;                                      // mark bytes per cell
     const uint32_t* prev_count;                 // counts of the frame before the chunk
-    const uint32_t* prev_offs;                  // and their offsets
-    unsigned long long* cnt_words;              // frame j's count words
+    const uint32_t* cell_base;                  // each cell's first index in a sparse list
+    uint8_t* marks;                             // cells x K mark bytes (cell-major)
+    uint32_t* own_count;                        // frame j's per-cell counts of marked cells
+    unsigned long long* cnt_words;              // frame j's count words ([63:32] epoch)
     const unsigned long long* cnt_words_prev;   // frame j-1's
-    unsigned long long* src_words;              // frame j's source words
-    const unsigned long long* src_words_prev;   // frame j-1's
-    CarryDesc* carry;                           // frame j's copy descriptors
 };
 
-struct CarryArgs {
-    int ncell, last;
+struct CompactArgs {
+    int ncell, last, K;
     uint32_t list_cap;
-    size_t list_stride;          // entries between consecutive chunk lists
-    kpd_keypoint* lists;         // chunk lists
-    const kpd_keypoint* prev_list;
-    const CarryDesc* carry;      // chunk frames x cells
-    kpd_keypoint* next_list;     // buffers the frame after the chunk reads
+    size_t list_stride;              // entries between consecutive chunk lists
+    const kpd_keypoint* sparse;      // chunk frames' sparse lists
+    const uint32_t* cell_base;
+    const uint8_t* marks;
+    const uint32_t* own_count;       // chunk frames x cells
+    const kpd_keypoint* prev_list;   // D before the chunk, its counts and offsets
+    const uint32_t* prev_count;
+    const uint32_t* prev_offs;
+    kpd_keypoint* lists;             // chunk frames' lists (all but the last)
+    uint32_t* counts;                // chunk frames x cells
+    uint32_t* offs;
+    uint32_t* totals;                // one per chunk frame
+    kpd_keypoint* next_list;         // the last frame's D, where the next push reads it
     uint32_t* next_count;
     uint32_t* next_offs;
     uint32_t* next_total;
-    uint32_t* sad_chunk;         // chunk frames x cells, cleared here
-    uint32_t* sad_stats;         // receives the last frame's SAD
-    uint32_t* sad_single_next;   // cleared for the next single frame
+    uint32_t* sad_chunk;             // chunk frames x cells, cleared here
+    uint32_t* sad_stats;             // receives the last frame's SAD
+    uint32_t* sad_single_next;       // cleared for the next single frame
 };
 
 hipError_t launch_detect_chunk(const ChunkArgs* table, int n_frames, int ncell, int lds_bytes, hipStream_t s);
-hipError_t launch_carry_chunk(const CarryArgs& a, int n_frames, hipStream_t s);
+hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t s);
 
 int frame_sad_lds_off(int tile, int O);
 int frame_lds_bytes(int tile, int O, int sad_slots);

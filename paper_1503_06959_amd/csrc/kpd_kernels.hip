@@ -632,17 +632,15 @@ __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
     }
 }
 
-// One frame j of a chunk of consecutive frames of one stream. Every cell
-// publishes its count (for frame j's later cells and frame j+1's marks) and
-// where its entries live (for frame j+1's carried cells): its own list when
-// marked, else wherever the cell's entries of frame j-1 live. Carried cells
-// only record a copy descriptor here; the copies run in the next launch,
-// once every list written by this one is visible on every XCD.
+// One frame j of a chunk of consecutive frames of one stream: cell c's
+// mark and, when marked, its keypoints at the cell's fixed base in frame j's
+// sparse list. With T_H active the mark needs the cell's count in frame
+// j-1, published by that frame's workgroup for the cell as a count word.
 __device__ void detect_cell_chunk(const ChunkArgs& t, int c, uint8_t* sm)
 {
     __shared__ CellLayout L;
     __shared__ int s_mark;
-    __shared__ uint32_t s_n, s_cprev, s_part[kDetWaves];
+    __shared__ uint32_t s_n, s_cprev;
     __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
     __shared__ int s_pitch[KPD_MAX_OCTAVES];
     const DetectArgs& a = t.d;
@@ -650,54 +648,38 @@ __device__ void detect_cell_chunk(const ChunkArgs& t, int c, uint8_t* sm)
 
     if (tid == 0) {
         load_level_ptrs(a, s_lvl, s_pitch);
-        const uint32_t cprev =
-            t.j == 0 ? t.prev_count[c] : (uint32_t)wait_word(&t.cnt_words_prev[c], a.epoch - 1, a.err);
         bool mark = a.all_marked != 0;
+        uint32_t cprev = 0;
         if (!mark) {
             const int cx = c % a.nc, cy = c / a.nc;
             const int64_t area = (int64_t)a.col_w[cx] * a.row_h[cy];
-            mark = (a.id_on && (int64_t)a.sad[c] > (int64_t)a.id_thresh * area) || cprev >= a.kb_thresh;
+            mark = a.id_on && (int64_t)a.sad[c] > (int64_t)a.id_thresh * area;
         }
+        if (!mark && t.kb_chain) {
+            cprev = t.j == 0 ? t.prev_count[c] : (uint32_t)wait_word(&t.cnt_words_prev[c], a.epoch - 1, a.err);
+            mark = cprev >= a.kb_thresh;
+        }
+        t.marks[(size_t)c * t.K + t.j] = (uint8_t)mark;
         if (t.last) a.mask[c] = (uint8_t)mark;
         s_mark = mark;
         s_cprev = cprev;
     }
     __syncthreads();
-    const bool mark = s_mark != 0;
-    if (mark) detect_marked(a, c, sm, L, s_lvl, s_pitch, &s_n);
-    __syncthreads();
-    const uint32_t own = mark ? s_n : s_cprev;
-    if (tid == 0)
-        __hip_atomic_store(&t.cnt_words[c], ((uint64_t)a.epoch << 32) | own, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t excl = sum_count_words(t.cnt_words, c, a.epoch, a.err, s_part);
-    if (tid == 0) {
-        uint32_t src_id, src_off;
-        if (mark) {
-            src_id = (uint32_t)t.j;
-            src_off = excl;
-        } else if (t.j == 0) {
-            src_id = kChunkPrev;
-            src_off = t.prev_offs[c];
-        } else {
-            const uint64_t st = wait_word(&t.src_words_prev[c], a.epoch - 1, a.err);
-            src_id = (uint32_t)(st >> 26) & 63u;
-            src_off = (uint32_t)st & ((1u << 26) - 1);
-        }
-        __hip_atomic_store(&t.src_words[c], ((uint64_t)a.epoch << 32) | ((uint64_t)src_id << 26) | src_off,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.count_cur[c] = own;
-        a.off_cur[c] = excl;
-        if (c == a.nc * a.nr - 1) *a.total_cur = excl + own;
-        CarryDesc cd;
-        cd.src_id = src_id;
-        cd.src_off = src_off;
-        cd.count = own;
-        cd.dst_off = excl;
-        cd.carried = mark ? 0u : 1u;
-        t.carry[c] = cd;
+    if (!s_mark) {
+        if (t.kb_chain && tid == 0)
+            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)a.epoch << 32) | s_cprev, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        return;
     }
-    if (mark) emit_marked(a, L, sm, excl, a.list_cur, a.list_cap);
+    detect_marked(a, c, sm, L, s_lvl, s_pitch, &s_n);
+    __syncthreads();
+    if (tid == 0) {
+        t.own_count[c] = s_n;
+        if (t.kb_chain)
+            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)a.epoch << 32) | s_n, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    emit_marked(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -738,39 +720,98 @@ __global__ __launch_bounds__(kBlk) void k_detect_chunk(const ChunkArgs* table, i
     detect_cell_chunk(table[j], (int)blockIdx.x - j * ncell, sm);
 }
 
-// Copies of a chunk: carried cells' entries into their frame's list, the
-// chunk's last D_n into the stream's next single-frame buffers, and the
-// chunk's per-cell SAD accumulators cleared for the next chunk.
-__global__ __launch_bounds__(64) void k_carry_chunk(CarryArgs a)
+// Compaction of a chunk, one workgroup per frame j, cells in tiles of
+// kCompact: each cell's source (the last chunk frame up to j that marked it,
+// else the list before the chunk) and count, their exclusive prefix (the
+// cell's offset in frame j's list), then a flat copy of the tile's entries.
+// The last frame's list goes where the next push reads it. Also clears the
+// chunk's SAD accumulators and hands the last frame's SAD to the statistics.
+constexpr int kCompact = 512;
+
+__global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
 {
-    const int j = blockIdx.x / a.ncell;
-    const int c = (int)blockIdx.x - j * a.ncell;
-    CarryDesc cd = a.carry[(size_t)j * a.ncell + c];
-    // a source outside this chunk can only come from a timed-out wait (the
-    // error flag is set): copy nothing then
-    if (cd.src_id != kChunkPrev && cd.src_id > (uint32_t)a.last) cd.count = 0;
-    const kpd_keypoint* src =
-        (cd.src_id == kChunkPrev ? a.prev_list : a.lists + (size_t)cd.src_id * a.list_stride) + cd.src_off;
-    kpd_keypoint* dst = a.lists + (size_t)j * a.list_stride + cd.dst_off;
-    if (cd.carried)
-        for (uint32_t k = threadIdx.x; k < cd.count; k += 64)
-            if (cd.src_off + k < a.list_cap && cd.dst_off + k < a.list_cap) dst[k] = src[k];
-    if (j == a.last) {
-        // the chunk's D_n also lands in the buffers the next frame reads
-        const kpd_keypoint* fsrc = cd.carried ? src : dst;
-        for (uint32_t k = threadIdx.x; k < cd.count; k += 64)
-            if ((cd.carried ? cd.src_off : cd.dst_off) + k < a.list_cap && cd.dst_off + k < a.list_cap)
-                a.next_list[cd.dst_off + k] = fsrc[k];
-        if (threadIdx.x == 0) {
-            a.next_count[c] = cd.count;
-            a.next_offs[c] = cd.dst_off;
-            if (c == a.ncell - 1) *a.next_total = cd.dst_off + cd.count;
-            a.sad_stats[c] = a.sad_chunk[(size_t)j * a.ncell + c];
-            a.sad_single_next[c] = 0;
-        }
-    }
+    __shared__ uint32_t s_excl[kCompact], s_src[kCompact], s_wsum[kCompact / 64];
+    __shared__ int s_frame[kCompact];
+    __shared__ uint32_t s_base;
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool last = j == a.last;
+    const size_t jc = (size_t)j * a.ncell;
+    kpd_keypoint* dst = last ? a.next_list : a.lists + (size_t)j * a.list_stride;
+    uint32_t* cnt_out = last ? a.next_count : a.counts + jc;
+    uint32_t* off_out = last ? a.next_offs : a.offs + jc;
+    const uint32_t upto = j >= 31 ? 0xFFFFFFFFu : ((2u << j) - 1u);
+    if (tid == 0) s_base = 0;
     __syncthreads();
-    if (threadIdx.x == 0) a.sad_chunk[(size_t)j * a.ncell + c] = 0;
+
+    for (int c0 = 0; c0 < a.ncell; c0 += kCompact) {
+        const int c = c0 + tid;
+        const int ntile = min(kCompact, a.ncell - c0);
+        const uint32_t base = s_base;
+        uint32_t n = 0, src = 0;
+        int f = -1;
+        if (c < a.ncell) {
+            // marks of frames 0..j of this cell as bits (bytes are 0 or 1)
+            const uint32_t* m4 = reinterpret_cast<const uint32_t*>(a.marks + (size_t)c * a.K);
+            uint32_t bits = 0;
+            for (int q = 0; q * 4 <= j; ++q) {
+                const uint32_t w = m4[q];
+                bits |= ((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u)) << (4 * q);
+            }
+            bits &= upto;
+            if (bits) {
+                f = 31 - __clz(bits);
+                n = a.own_count[(size_t)f * a.ncell + c];
+                src = a.cell_base[c];
+            } else {
+                n = a.prev_count[c];
+                src = a.prev_offs[c];
+            }
+        }
+        uint32_t incl = n;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();
+        uint32_t wbase = 0;
+        for (int w = 0; w < wave; ++w) wbase += s_wsum[w];
+        const uint32_t excl = base + wbase + incl - n;
+        s_excl[tid] = excl;
+        s_src[tid] = src;
+        s_frame[tid] = f;
+        if (c < a.ncell) {
+            cnt_out[c] = n;
+            off_out[c] = excl;
+            if (last) {
+                a.sad_stats[c] = a.sad_chunk[jc + c];
+                a.sad_single_next[c] = 0;
+            }
+            a.sad_chunk[jc + c] = 0;
+        }
+        __syncthreads();
+        // every thread needs the tile's end: the last cell's thread publishes it
+        if (tid == ntile - 1) s_wsum[0] = excl + n;
+        __syncthreads();
+        const uint32_t t1 = s_wsum[0];
+        for (uint32_t d = base + tid; d < t1; d += kCompact) {
+            int lo = 0, hi = ntile - 1;   // largest cell of the tile starting at or before d
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_excl[mid] <= d) lo = mid;
+                else hi = mid - 1;
+            }
+            const int sf = s_frame[lo];
+            const kpd_keypoint* sp = sf >= 0 ? a.sparse + (size_t)sf * a.list_stride : a.prev_list;
+            const uint32_t so = s_src[lo] + (d - s_excl[lo]);
+            if (so < a.list_cap && d < a.list_cap) dst[d] = sp[so];
+        }
+        __syncthreads();
+        if (tid == 0) s_base = t1;
+        __syncthreads();
+    }
+    if (tid == 0) *(last ? a.next_total : a.totals + j) = s_base;
 }
 
 // One batch tick: workgroup b works for stream map[b] (streams' workgroups
@@ -866,9 +907,9 @@ hipError_t launch_detect_chunk(const ChunkArgs* table, int n_frames, int ncell, 
     return hipGetLastError();
 }
 
-hipError_t launch_carry_chunk(const CarryArgs& a, int n_frames, hipStream_t s)
+hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_carry_chunk, dim3(n_frames * a.ncell), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_compact_chunk, dim3(n_frames), dim3(kCompact), 0, s, a);
     return hipGetLastError();
 }
 
