@@ -6,9 +6,12 @@ segment test + score + scale-space suppression, compaction, Eq. (1) output)
 over every frame of one synthetic video, frames already resident in HBM and
 pushed through the C ABI in place (no copy). The headline workload is the
 640x480, 300-frame single stream (FAST-9 t=20, 4 octaves, 16x12 cells,
-T_I = 8); the same line also carries the full-frame rate of that workload,
-the 1920x1080 single-stream rates, per-frame latency percentiles, the
-dominant kernel's roofline and the CPU oracle's rate on a bounded sample.
+T_I = 8), pushed 32 consecutive frames per push_frames call (results are
+identical to one push per frame). The same line also carries the
+full-frame rate of that workload, the streaming mode (one push_frame per
+frame) with its per-frame latency percentiles, the 1920x1080 rates, the
+batched 64-stream and serving sections, the dominant kernel's roofline and
+the CPU oracle's rate on a bounded sample.
 
 Prints one JSON line on stdout. Usage:
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-hd]
@@ -39,8 +42,8 @@ def log(msg: str) -> None:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2_640x480")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hd", action="store_true")
@@ -53,11 +56,11 @@ def parse():
     ap.add_argument("--serve-budget-mib", type=int, default=1024)
     ap.add_argument("--batch-ticks", type=int, default=120)
     ap.add_argument("--batch-clip", type=int, default=40)
-    ap.add_argument("--chunk", type=int, default=32, help="frames per push_frames call in the chunked section")
-    ap.add_argument("--no-chunk", action="store_true")
+    ap.add_argument("--chunk", type=int, default=32, help="frames per push_frames call (at most 32)")
     ap.add_argument("--mode", choices=("both", "masked", "full"), default="both",
                     help="masked or full: run only that pass of --workload and print its line (for profiling)")
     ap.add_argument("--chunked", action="store_true", help="with --mode: push --chunk frames per call")
+    ap.add_argument("--tile", type=int, default=0, help="level-0 tile of the tile pass (0: the library default)")
     return ap.parse_args()
 
 
@@ -97,10 +100,13 @@ class Workload:
                 + ("full-frame (T_I<0)" if id_thresh < 0 else f"T_I={id_thresh}, T_H off"))
 
 
+TILE = 0
+
+
 def open_stream(wl: Workload, id_thresh: int, chunk: int = 0):
     from paper_1503_06959_amd import kpd
     d = wl.det
-    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh, 0, chunk)
+    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh, TILE, chunk)
     s = kpd.Stream(wl.W, wl.H, params)
     s.chunk = chunk
     return s
@@ -239,27 +245,6 @@ def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, wan
         res["kernels"] = kernel_profile(kpd, s, wl, max(1, args.steps // 2))
     s.close()
     return res
-
-
-def chunked_section(kpd, wl: Workload, args, masked, full) -> dict:
-    """The same video through push_frames, args.chunk frames per call
-    (identical results; the tests check it frame by frame). `masked` and
-    `full` are the per-frame runs, whose keypoint statistics the roofline's
-    algorithmic bytes reuse."""
-    K = args.chunk
-    log(f"[bench] {wl.name} chunked ({K} frames per call)")
-    out = {"chunk_frames": K, "calls_per_pass": -(-wl.F // K)}
-    for key, ti, single, is_masked in (("masked", wl.det.id_thresh, masked, True),
-                                       ("full_frame", -1, full, False)):
-        r = run_workload(kpd, wl, ti, args, chunk=K)
-        out[key] = {"value": round(r["mpix_per_s"], 2), "unit": "Mpixel/s",
-                    "frames_per_s": round(r["frames_per_s"], 1),
-                    "ms_per_step": round(r["sec_per_pass"] * 1e3, 4),
-                    "over_per_frame_push": round(r["mpix_per_s"] / single["mpix_per_s"], 3),
-                    "chunk_latency_ms": {"p50": round(r["lat_p50"], 4), "p99": round(r["lat_p99"], 4),
-                                         "what": "push_frames of one chunk -> last frame's keypoints on the host"},
-                    "roofline": roofline_of(wl, r, is_masked, stats=single)}
-    return out
 
 
 def roofline_of(wl: Workload, res, masked: bool, traffic=None, stats=None):
@@ -460,6 +445,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     from paper_1503_06959_amd import kpd
+    global TILE
+    TILE = args.tile
 
     wl = Workload(args.workload)
     if args.mode != "both":
@@ -474,71 +461,104 @@ def main():
                           "frames_per_s": round(r["frames_per_s"], 1),
                           "roofline": roofline_of(wl, r, masked, stats=stats)}), flush=True)
         return
-    log("[bench] masked pass")
+    K = args.chunk
+    log(f"[bench] masked pass, chunks of {K}")
+    masked_c = run_workload(kpd, wl, wl.det.id_thresh, args, chunk=K)
+    log(f"[bench] masked {masked_c['mpix_per_s']:.1f} Mpx/s; full-frame pass")
+    full_c = run_workload(kpd, wl, -1, args, chunk=K)
+    log(f"[bench] full-frame {full_c['mpix_per_s']:.1f} Mpx/s; per-frame pushes")
     masked = run_workload(kpd, wl, wl.det.id_thresh, args)
-    log(f"[bench] masked {masked['mpix_per_s']:.1f} Mpx/s; full-frame pass")
     full = run_workload(kpd, wl, -1, args)
-    log(f"[bench] full-frame {full['mpix_per_s']:.1f} Mpx/s")
+    log(f"[bench] per-frame masked {masked['mpix_per_s']:.1f}, full {full['mpix_per_s']:.1f} Mpx/s")
     skipped = 1.0 - sum(masked["marked"][1:]) / max(1, (wl.F - 1) * wl.ncell)
 
     out = {
         "metric": METRIC,
-        "value": round(masked["mpix_per_s"], 2),
+        "value": round(masked_c["mpix_per_s"], 2),
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(masked["sec_per_pass"] * 1e3, 4),
+        "ms_per_step": round(masked_c["sec_per_pass"] * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": wl.describe(wl.det.id_thresh), "frames_per_step": wl.F,
-                   "frame": f"{wl.W}x{wl.H}", "parallelism": "1 stream, 1 GPU"},
-        "frames_per_s": round(masked["frames_per_s"], 1),
+                   "frame": f"{wl.W}x{wl.H}", "push": f"push_frames, {K} consecutive frames per call",
+                   "parallelism": "1 stream, 1 GPU"},
+        "frames_per_s": round(masked_c["frames_per_s"], 1),
         "latency_ms": {"p50": round(masked["lat_p50"], 4), "p99": round(masked["lat_p99"], 4),
-                       "what": "push_frame -> get_keypoints returned on the host, one frame in flight"},
+                       "what": "streaming: push_frame -> get_keypoints on the host, one frame in flight"},
+        "chunk_latency_ms": {"p50": round(masked_c["lat_p50"], 4), "p99": round(masked_c["lat_p99"], 4),
+                             "what": f"push_frames of {K} frames -> last frame's keypoints on the host"},
         "skipped_cell_frac": round(skipped, 4),
-        "full_frame": {"value": round(full["mpix_per_s"], 2), "unit": "Mpixel/s",
-                       "frames_per_s": round(full["frames_per_s"], 1),
-                       "ms_per_step": round(full["sec_per_pass"] * 1e3, 4),
-                       "latency_ms": {"p50": round(full["lat_p50"], 4), "p99": round(full["lat_p99"], 4)},
-                       "roofline": roofline_of(wl, full, False)},
-        "masked_over_full": round(masked["mpix_per_s"] / full["mpix_per_s"], 3),
-        "roofline": roofline_of(wl, masked, True),
+        "full_frame": {"value": round(full_c["mpix_per_s"], 2), "unit": "Mpixel/s",
+                       "frames_per_s": round(full_c["frames_per_s"], 1),
+                       "ms_per_step": round(full_c["sec_per_pass"] * 1e3, 4),
+                       "chunk_latency_ms": {"p50": round(full_c["lat_p50"], 4),
+                                            "p99": round(full_c["lat_p99"], 4)},
+                       "roofline": roofline_of(wl, full_c, False, stats=full)},
+        "masked_over_full": round(masked_c["mpix_per_s"] / full_c["mpix_per_s"], 3),
+        "roofline": roofline_of(wl, masked_c, True, stats=masked),
+        "per_frame_push": {
+            "what": "streaming mode: one push_frame call per frame",
+            "masked": {"value": round(masked["mpix_per_s"], 2), "unit": "Mpixel/s",
+                       "frames_per_s": round(masked["frames_per_s"], 1),
+                       "ms_per_step": round(masked["sec_per_pass"] * 1e3, 4),
+                       "latency_ms": {"p50": round(masked["lat_p50"], 4), "p99": round(masked["lat_p99"], 4)},
+                       "roofline": roofline_of(wl, masked, True)},
+            "full_frame": {"value": round(full["mpix_per_s"], 2), "unit": "Mpixel/s",
+                           "frames_per_s": round(full["frames_per_s"], 1),
+                           "ms_per_step": round(full["sec_per_pass"] * 1e3, 4),
+                           "latency_ms": {"p50": round(full["lat_p50"], 4), "p99": round(full["lat_p99"], 4)},
+                           "roofline": roofline_of(wl, full, False)},
+            "masked_over_full": round(masked["mpix_per_s"] / full["mpix_per_s"], 3),
+        },
     }
-    if not args.no_chunk:
-        out["chunked"] = chunked_section(kpd, wl, args, masked, full)
     if not args.no_hd:
         del wl
         torch.cuda.empty_cache()
         hd = Workload("c3_1920x1080")
-        log("[bench] 1080p masked pass")
-        hm = run_workload(kpd, hd, hd.det.id_thresh, args, want_latency=True)
-        log("[bench] 1080p full-frame pass")
-        hf = run_workload(kpd, hd, -1, args, want_latency=True)
+        log("[bench] 1080p passes")
+        hmc = run_workload(kpd, hd, hd.det.id_thresh, args, chunk=K)
+        hfc = run_workload(kpd, hd, -1, args, chunk=K)
+        hm = run_workload(kpd, hd, hd.det.id_thresh, args)
+        hf = run_workload(kpd, hd, -1, args)
         lv = level_sizes(hd.W, hd.H, hd.det.n_octaves)
         N, P = lv[0], sum(lv[1:])
         kps = sum(hf["total_kp"]) / hd.F
         b_full = N + 2 * P + 8 * kps
-        eff = b_full * hd.F / hf["sec_per_pass"] / 1e9
+
+        def eff(r):
+            e = b_full * hd.F / r["sec_per_pass"] / 1e9
+            return {"effective_hbm_GBs": round(e, 2), "effective_hbm_frac": round(e / HBM_PEAK_GBS, 5),
+                    "algorithmic_bytes_per_frame": int(b_full)}
+
         out["hd_1080p"] = {
             "workload": hd.describe(hd.det.id_thresh),
-            "masked": {"value": round(hm["mpix_per_s"], 2), "unit": "Mpixel/s",
-                       "frames_per_s": round(hm["frames_per_s"], 1),
-                       "latency_ms": {"p50": round(hm["lat_p50"], 4), "p99": round(hm["lat_p99"], 4)},
-                       "roofline": roofline_of(hd, hm, True)},
-            "full_frame": {"value": round(hf["mpix_per_s"], 2), "unit": "Mpixel/s",
-                           "frames_per_s": round(hf["frames_per_s"], 1),
-                           "latency_ms": {"p50": round(hf["lat_p50"], 4), "p99": round(hf["lat_p99"], 4)},
-                           "effective_hbm_GBs": round(eff, 2),
-                           "effective_hbm_frac": round(eff / HBM_PEAK_GBS, 5),
-                           "algorithmic_bytes_per_frame": int(b_full),
-                           "roofline": roofline_of(hd, hf, False)},
+            "push": f"push_frames, {K} consecutive frames per call",
+            "masked": {"value": round(hmc["mpix_per_s"], 2), "unit": "Mpixel/s",
+                       "frames_per_s": round(hmc["frames_per_s"], 1),
+                       "chunk_latency_ms": {"p50": round(hmc["lat_p50"], 4), "p99": round(hmc["lat_p99"], 4)},
+                       "roofline": roofline_of(hd, hmc, True, stats=hm)},
+            "full_frame": dict({"value": round(hfc["mpix_per_s"], 2), "unit": "Mpixel/s",
+                                "frames_per_s": round(hfc["frames_per_s"], 1),
+                                "chunk_latency_ms": {"p50": round(hfc["lat_p50"], 4),
+                                                     "p99": round(hfc["lat_p99"], 4)},
+                                "roofline": roofline_of(hd, hfc, False, stats=hf)}, **eff(hfc)),
+            "per_frame_push": {
+                "masked": {"value": round(hm["mpix_per_s"], 2), "unit": "Mpixel/s",
+                           "frames_per_s": round(hm["frames_per_s"], 1),
+                           "latency_ms": {"p50": round(hm["lat_p50"], 4), "p99": round(hm["lat_p99"], 4)},
+                           "roofline": roofline_of(hd, hm, True)},
+                "full_frame": dict({"value": round(hf["mpix_per_s"], 2), "unit": "Mpixel/s",
+                                    "frames_per_s": round(hf["frames_per_s"], 1),
+                                    "latency_ms": {"p50": round(hf["lat_p50"], 4), "p99": round(hf["lat_p99"], 4)},
+                                    "roofline": roofline_of(hd, hf, False)}, **eff(hf)),
+            },
         }
-        if not args.no_chunk:
-            out["hd_1080p"]["chunked"] = chunked_section(kpd, hd, args, hm, hf)
         wl = hd
     if not args.no_batch:
         del wl

@@ -57,13 +57,14 @@ struct Layout {
     // chunks of consecutive frames (push_frames): K copies of the octaves,
     // per-frame SAD, sparse lists with per-cell counts, count words, marks
     // (cell-major, Kp bytes per cell), dense lists with counts, offsets and
-    // totals, the cells' sparse bases, and the chunk's argument tables (two
-    // sets)
+    // totals, the cells' sparse bases, and the fixed per-frame argument
+    // tables of the tile and detection passes
     int K = 1, Kp = 4;
+    int ctile = 32, ctiles_x = 0, ctiles_y = 0, csad_slots = 1;   // tile pass of chunks
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
     size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0;
-    size_t off_cntw = 0, off_ctab[2] = {0, 0}, off_ftab[2] = {0, 0}, off_fmap = 0;
+    size_t off_cntw = 0, off_ctab = 0, off_ftab = 0;
     size_t list_cap = 0;
     int lds_bytes = 0;   // dynamic LDS of the cell pass
     size_t total = 0;
@@ -131,6 +132,20 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         *why = "grid too fine for the pyramid tile";
         return false;
     }
+    // A chunk has many frames' tiles to spread over the chip, so its tile
+    // pass takes the widest tile that fits (whole 128-byte rows per tile
+    // row); a single frame keeps the smaller tile for more workgroups.
+    L->ctile = L->tile;
+    for (int T = 128; T > L->tile; T >>= 1) {
+        const int slots = span_max(W, L->nc, T) * span_max(H, L->nr, T);
+        if (kpd::frame_lds_bytes(T, L->O, slots) <= 65536) {
+            L->ctile = T;
+            break;
+        }
+    }
+    L->ctiles_x = (W + L->ctile - 1) / L->ctile;
+    L->ctiles_y = (H + L->ctile - 1) / L->ctile;
+    L->csad_slots = span_max(W, L->nc, L->ctile) * span_max(H, L->nr, L->ctile);
 
     // keypoint list capacity and the detection kernel's LDS need
     size_t cap = 0;
@@ -188,9 +203,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
         L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
         L->off_clist = off; off += L->clist_stride * (size_t)(L->K - 1);   // the last frame's D goes to D_n
-        for (int k = 0; k < 2; ++k) { L->off_ctab[k] = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs)); }
-        for (int k = 0; k < 2; ++k) { L->off_ftab[k] = off; off = align_up(off + (size_t)L->K * sizeof(kpd::TickArgs)); }
-        L->off_fmap = off; off = align_up(off + (size_t)L->K * L->tiles_x * L->tiles_y * 2);
+        L->off_ctab = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs));
+        L->off_ftab = off; off = align_up(off + (size_t)L->K * sizeof(kpd::FrameArgs));
     }
     L->total = off;
     return true;
@@ -236,21 +250,7 @@ struct kpd_stream {
     int prev_dw = 0;
     int fb_last = 1;          // which of the two single-frame buffers holds the latest D_n
     int chunk_n = 0;          // frames of the last push_frames call
-    kpd::ChunkArgs* ctab_host[2] = {nullptr, nullptr};  // pinned
-    kpd::TickArgs* ftab_host[2] = {nullptr, nullptr};   // pinned
-    hipEvent_t ctab_free[2] = {nullptr, nullptr};
-    bool ctab_used[2] = {false, false};
-    uint64_t chunks = 0;
     bool closed = false;
-
-    ~kpd_stream()
-    {
-        for (int k = 0; k < 2; ++k) {
-            if (ctab_host[k]) hipHostFree(ctab_host[k]);
-            if (ftab_host[k]) hipHostFree(ftab_host[k]);
-            if (ctab_free[k]) hipEventDestroy(ctab_free[k]);
-        }
-    }
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
@@ -299,6 +299,65 @@ size_t stream_bytes(int width, int height, const kpd_params* params)
     }
     return L.total;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Fixed per-frame arguments of the chunk passes: frame j's octave copy, SAD
+// accumulators, sparse list, count words and marks. What changes between
+// chunks travels in the ChunkHead kernel argument.
+void chunk_tables(kpd_stream* s, std::vector<kpd::ChunkArgs>* ctab, std::vector<kpd::FrameArgs>* ftab)
+{
+    const Layout& L = s->L;
+    const size_t kc = (size_t)L.ncell;
+    ctab->assign(L.K, kpd::ChunkArgs{});
+    ftab->assign(L.K, kpd::FrameArgs{});
+    for (int j = 0; j < L.K; ++j) {
+        uint8_t* pyr = s->arena + L.pyr_stride * (size_t)j;
+        kpd::FrameArgs& fa = (*ftab)[j];
+        for (int o = 1; o < L.O; ++o) {
+            fa.lvl[o] = pyr + L.off_lvl[o];
+            fa.pitch[o] = L.pitch[o];
+        }
+        for (int o = 0; o < L.O; ++o) { fa.w[o] = L.w[o]; fa.h[o] = L.h[o]; }
+        fa.W = L.W; fa.H = L.H; fa.O = L.O; fa.nc = L.nc; fa.nr = L.nr;
+        fa.tile = L.ctile;
+        fa.tiles_x = L.ctiles_x;
+        fa.ntiles = L.ctiles_x * L.ctiles_y;
+        fa.sad_slots = L.csad_slots;
+        fa.sad_lds_off = kpd::frame_sad_lds_off(L.ctile, L.O);
+        fa.sad = s->at<uint32_t>(L.off_csad) + (size_t)j * kc;
+
+        kpd::ChunkArgs& c = (*ctab)[j];
+        kpd::DetectArgs& d = c.d;
+        for (int o = 1; o < L.O; ++o) {
+            d.lvl[o] = pyr + L.off_lvl[o];
+            d.pitch[o] = L.pitch[o];
+        }
+        for (int o = 0; o < L.O; ++o) { d.w[o] = L.w[o]; d.h[o] = L.h[o]; }
+        d.W = L.W; d.H = L.H; d.O = L.O; d.nc = L.nc; d.nr = L.nr;
+        d.sad = fa.sad;
+        d.mask = s->at<uint8_t>(L.off_mask);
+        d.list_cur = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_sparse + L.clist_stride * (size_t)j);
+        d.list_cap = (uint32_t)L.list_cap;
+        d.layouts = s->at<kpd::CellLayout>(L.off_layouts);
+        d.col_w = s->at<uint16_t>(L.off_colw);
+        d.row_h = s->at<uint16_t>(L.off_rowh);
+        d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
+        c.j = j;
+        c.K = L.Kp;
+        c.cell_base = s->at<uint32_t>(L.off_cbase);
+        c.marks = s->at<uint8_t>(L.off_marks);
+        c.own_count = s->at<uint32_t>(L.off_own) + (size_t)j * kc;
+        c.cnt_words = s->at<unsigned long long>(L.off_cntw) + (size_t)j * kc;
+        c.cnt_words_prev = j ? c.cnt_words - kc : nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
 
 int open_stream(int width, int height, const kpd_params* params, void* dev_arena, size_t arena_bytes,
                 void* hip_stream, kpd_stream** out)
@@ -356,14 +415,10 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_layouts, layouts.data(), layouts.size() * sizeof(kpd::CellLayout),
                            hipMemcpyHostToDevice, s->stream);
-    std::vector<uint16_t> fmap;
     std::vector<uint32_t> cbase;
+    std::vector<kpd::ChunkArgs> ctab;
+    std::vector<kpd::FrameArgs> ftab;
     if (L.K > 1) {
-        const int nt = L.tiles_x * L.tiles_y;
-        fmap.resize((size_t)L.K * nt);
-        for (size_t b = 0; b < fmap.size(); ++b) fmap[b] = (uint16_t)(b / nt);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->arena + L.off_fmap, fmap.data(), fmap.size() * 2, hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess)
             e = hipMemsetAsync(s->arena + L.off_csad, 0, (size_t)L.K * L.ncell * 4, s->stream);
         if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_cntw, 0, (size_t)L.K * L.ncell * 8, s->stream);
@@ -372,22 +427,18 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         uint32_t acc = 0;
         for (int c = 0; c < L.ncell; ++c) {
             cbase[c] = acc;
-            const kpd::Box r = kpd::cell_rect(c, L.W, L.H, L.nc, L.nr);
-            kpd::CellLayout CL;
-            kpd::cell_layout(r, L.O, L.w, L.h, &CL);
-            for (int o = 0; o < L.O; ++o) acc += (uint32_t)kpd::decision_capacity(CL.dec[o]);
+            for (int o = 0; o < L.O; ++o) acc += (uint32_t)kpd::decision_capacity(layouts[c].dec[o]);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice,
                                s->stream);
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-            e = hipHostMalloc(reinterpret_cast<void**>(&s->ctab_host[k]), (size_t)L.K * sizeof(kpd::ChunkArgs),
-                              hipHostMallocDefault);
-            if (e == hipSuccess)
-                e = hipHostMalloc(reinterpret_cast<void**>(&s->ftab_host[k]), (size_t)L.K * sizeof(kpd::TickArgs),
-                                  hipHostMallocDefault);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ctab_free[k], hipEventDisableTiming);
-        }
+        chunk_tables(s, &ctab, &ftab);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->arena + L.off_ctab, ctab.data(), ctab.size() * sizeof(kpd::ChunkArgs),
+                               hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->arena + L.off_ftab, ftab.data(), ftab.size() * sizeof(kpd::FrameArgs),
+                               hipMemcpyHostToDevice, s->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
@@ -548,106 +599,40 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
     if (n_frames > 1 && frame_stride < pitch_bytes * (size_t)(L.H - 1) + (size_t)L.W)
         return fail(KPD_EINVAL, "frames overlap");
-    const int k = (int)(s->chunks & 1);
-    if (s->ctab_used[k]) KPD_HIP(hipEventSynchronize(s->ctab_free[k]));
+    const int pitch = (int)pitch_bytes;
+    const uint32_t n0 = (uint32_t)s->n_pushed;
+    const int fb_prev = s->fb_last, fb_next = 1 - s->fb_last;
+    kpd::ChunkHead h{};
+    h.frames = frames;
+    h.stride = frame_stride;
+    h.pitch = pitch;
+    h.aligned = dword_readable(frames, pitch, L.W, false) && frame_stride % 4 == 0;
+    h.prev0 = s->prev0 ? s->prev0 : frames;   // read only when frame 0 tests intensity differences
+    h.prev0_pitch = s->prev0 ? s->prev_pitch : pitch;
+    h.prev0_aligned = s->prev0 ? s->prev_dw : h.aligned;
+    h.n_frames = n_frames;
+    h.epoch0 = n0 + 1;
+    h.force0 = s->force_all ? 1 : 0;
+    h.all_marked = (s->p.id_thresh < 0 || s->p.kb_thresh == 0) ? 1 : 0;
+    h.t = s->p.fast_t;
+    h.id_thresh = s->p.id_thresh;
+    h.kb_thresh = s->p.kb_thresh;
     // marks read the previous frame's counts only when T_H can mark a cell
     // and the parameters do not mark every cell anyway
-    const bool kb_chain = s->p.kb_thresh != KPD_KB_OFF && s->p.kb_thresh != 0 && s->p.id_thresh >= 0;
-
-    const uint32_t n0 = (uint32_t)s->n_pushed;
-    const int pitch = (int)pitch_bytes;
-    const int fb_prev = s->fb_last, fb_next = 1 - s->fb_last;
-    const size_t kc = (size_t)L.ncell;
-    kpd::ChunkArgs* ct = s->ctab_host[k];
-    kpd::TickArgs* ft = s->ftab_host[k];
-    bool any_tiles = false;
-    for (int j = 0; j < n_frames; ++j) {
-        const uint8_t* cur = frames + (size_t)j * frame_stride;
-        const int cur_dw = dword_readable(cur, pitch, L.W, false);
-        const bool all_marked = (j == 0 && s->force_all) || s->p.id_thresh < 0 || s->p.kb_thresh == 0;
-        const bool sad_on = !all_marked && s->p.id_thresh < 255;
-        uint8_t* pyr = s->arena + L.pyr_stride * (size_t)j;   // octave copy j
-
-        kpd::TickArgs& t = ft[j];
-        t = kpd::TickArgs{};
-        kpd::FrameArgs& fa = t.f;
-        fa.cur = cur;
-        fa.cur_pitch = pitch;
-        fa.cur_aligned = cur_dw;
-        fa.prev = !sad_on ? cur : (j == 0 ? s->prev0 : frames + (size_t)(j - 1) * frame_stride);
-        fa.prev_pitch = !sad_on ? pitch : (j == 0 ? s->prev_pitch : pitch);
-        fa.prev_aligned = !sad_on ? cur_dw : (j == 0 ? s->prev_dw : dword_readable(fa.prev, pitch, L.W, false));
-        for (int o = 1; o < L.O; ++o) {
-            fa.lvl[o] = pyr + L.off_lvl[o];
-            fa.pitch[o] = L.pitch[o];
-        }
-        for (int o = 0; o < L.O; ++o) { fa.w[o] = L.w[o]; fa.h[o] = L.h[o]; }
-        fa.W = L.W; fa.H = L.H; fa.O = L.O; fa.nc = L.nc; fa.nr = L.nr;
-        fa.tile = L.tile;
-        fa.tiles_x = L.tiles_x;
-        fa.ntiles = L.tiles_x * L.tiles_y;
-        fa.sad_on = sad_on ? 1 : 0;
-        fa.sad_slots = L.sad_slots;
-        fa.sad_lds_off = kpd::frame_sad_lds_off(L.tile, L.O);
-        fa.sad = s->at<uint32_t>(L.off_csad) + (size_t)j * kc;
-        t.active = 1;
-        t.f_on = (L.O > 1 || sad_on) ? 1 : 0;
-        t.tile_base = j * fa.ntiles;
-        any_tiles = any_tiles || t.f_on;
-
-        kpd::ChunkArgs& c = ct[j];
-        c = kpd::ChunkArgs{};
-        kpd::DetectArgs& d = c.d;
-        d.lvl[0] = cur;
-        d.pitch[0] = pitch;
-        for (int o = 1; o < L.O; ++o) {
-            d.lvl[o] = pyr + L.off_lvl[o];
-            d.pitch[o] = L.pitch[o];
-        }
-        for (int o = 0; o < L.O; ++o) { d.w[o] = L.w[o]; d.h[o] = L.h[o]; }
-        d.lvl0_aligned = cur_dw;
-        d.W = L.W; d.H = L.H; d.O = L.O; d.nc = L.nc; d.nr = L.nr;
-        d.t = s->p.fast_t;
-        d.all_marked = all_marked ? 1 : 0;
-        d.id_on = sad_on ? 1 : 0;
-        d.id_thresh = s->p.id_thresh;
-        d.kb_thresh = s->p.kb_thresh;
-        d.sad = fa.sad;
-        d.mask = s->at<uint8_t>(L.off_mask);
-        d.list_cur = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_sparse + L.clist_stride * (size_t)j);
-        d.list_cap = (uint32_t)L.list_cap;
-        d.layouts = s->at<kpd::CellLayout>(L.off_layouts);
-        d.col_w = s->at<uint16_t>(L.off_colw);
-        d.row_h = s->at<uint16_t>(L.off_rowh);
-        d.epoch = n0 + (uint32_t)j + 1;
-        d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
-        c.j = j;
-        c.last = j == n_frames - 1 ? 1 : 0;
-        c.kb_chain = kb_chain ? 1 : 0;
-        c.K = L.Kp;
-        c.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);
-        c.cell_base = s->at<uint32_t>(L.off_cbase);
-        c.marks = s->at<uint8_t>(L.off_marks);
-        c.own_count = s->at<uint32_t>(L.off_own) + (size_t)j * kc;
-        c.cnt_words = s->at<unsigned long long>(L.off_cntw) + (size_t)j * kc;
-        c.cnt_words_prev = j ? c.cnt_words - kc : nullptr;
-    }
-
-    kpd::ChunkArgs* ctab = s->at<kpd::ChunkArgs>(L.off_ctab[k]);
-    kpd::TickArgs* ftab = s->at<kpd::TickArgs>(L.off_ftab[k]);
-    KPD_HIP(hipMemcpyAsync(ctab, ct, (size_t)n_frames * sizeof(kpd::ChunkArgs), hipMemcpyHostToDevice, s->stream));
-    KPD_HIP(hipMemcpyAsync(ftab, ft, (size_t)n_frames * sizeof(kpd::TickArgs), hipMemcpyHostToDevice, s->stream));
-    KPD_HIP(hipEventRecord(s->ctab_free[k], s->stream));
-    s->ctab_used[k] = true;
-    const int nt = L.tiles_x * L.tiles_y;
+    h.kb_chain = (s->p.kb_thresh != KPD_KB_OFF && !h.all_marked) ? 1 : 0;
+    h.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);
+    h.ntiles = L.ctiles_x * L.ctiles_y;
+    h.ncell = L.ncell;
+    // the tile pass is needed for coarser octaves or intensity differences
+    const bool any_tiles = L.O > 1 || (s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
+                                       (n_frames > 1 || !h.force0));
+    const kpd::ChunkArgs* ctab = s->at<kpd::ChunkArgs>(L.off_ctab);
+    const kpd::FrameArgs* ftab = s->at<kpd::FrameArgs>(L.off_ftab);
     if (any_tiles)
         KPD_HIP(timed(s, KPD_K_FRAME, [&] {
-            return kpd::launch_frame_batch(ftab, s->at<uint16_t>(L.off_fmap), n_frames * nt,
-                                           kpd::frame_lds_bytes(L.tile, L.O, L.sad_slots), s->stream);
+            return kpd::launch_frame_chunk(ftab, h, kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots), s->stream);
         }));
-    KPD_HIP(timed(s, KPD_K_DETECT, [&] {
-        return kpd::launch_detect_chunk(ctab, n_frames, L.ncell, L.lds_bytes, s->stream);
-    }));
+    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_chunk(ctab, h, L.lds_bytes, s->stream); }));
     kpd::CompactArgs ca{};
     ca.ncell = L.ncell;
     ca.last = n_frames - 1;
@@ -683,7 +668,6 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     s->n_pushed += n_frames;
     s->fb_last = fb_next;
     s->chunk_n = n_frames;
-    s->chunks += 1;
     return KPD_OK;
 }
 

@@ -28,6 +28,15 @@ struct FrameArgs {
     uint32_t* sad;   // per-cell SAD, accumulated; zero on entry
 };
 
+// The frame-dependent inputs of one tile pass.
+struct FrameSrc {
+    const uint8_t* cur;
+    const uint8_t* prev;
+    int cur_pitch, prev_pitch;
+    int cur_aligned, prev_aligned;
+    int sad_on;
+};
+
 // k_detect: per-cell mark, detection, look-back offsets and output.
 struct DetectArgs {
     const uint8_t* lvl[KPD_MAX_OCTAVES];
@@ -77,16 +86,34 @@ struct TickArgs {
 // own where the cell was marked, or the list before the chunk, and copies
 // the entries into the frame's list in cell order (Eq. 1).
 struct ChunkArgs {
-    DetectArgs d;                               // frame j's detection arguments (list_cur = sparse list j)
-    int j, last;                                // frame index in the chunk, is it the last
-    int kb_chain;                               // marks read frame j-1's counts (T_H active)
+    DetectArgs d;                               // frame j's fixed detection arguments (list_cur = sparse list j)
+    int j;                                      // frame index in the chunk
     int K;                                      // mark bytes per cell
-    const uint32_t* prev_count;                 // counts of the frame before the chunk
     const uint32_t* cell_base;                  // each cell's first index in a sparse list
     uint8_t* marks;                             // cells x K mark bytes (cell-major)
     uint32_t* own_count;                        // frame j's per-cell counts of marked cells
     unsigned long long* cnt_words;              // frame j's count words ([63:32] epoch)
     const unsigned long long* cnt_words_prev;   // frame j-1's
+};
+
+// What changes from one chunk to the next, passed by value: the frames, the
+// frame before the chunk, thresholds and the buffers that alternate.
+struct ChunkHead {
+    const uint8_t* frames;      // frame j at frames + j * stride
+    const uint8_t* prev0;       // the frame before the chunk
+    size_t stride;
+    int pitch, prev0_pitch;
+    int aligned, prev0_aligned; // rows dword-readable
+    int n_frames;
+    uint32_t epoch0;            // epoch of frame 0 (frame number + 1)
+    int force0;                 // frame 0 marks every cell (first frame, reset, new t)
+    int all_marked;             // the parameters mark every cell
+    int t;
+    int32_t id_thresh;
+    uint32_t kb_thresh;
+    int kb_chain;               // marks read the previous frame's counts (T_H active)
+    const uint32_t* prev_count; // counts of the frame before the chunk
+    int ntiles, ncell;          // tiles and cells per frame
 };
 
 struct CompactArgs {
@@ -113,7 +140,8 @@ struct CompactArgs {
     uint32_t* sad_single_next;       // cleared for the next single frame
 };
 
-hipError_t launch_detect_chunk(const ChunkArgs* table, int n_frames, int ncell, int lds_bytes, hipStream_t s);
+hipError_t launch_frame_chunk(const FrameArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
+hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t s);
 
 int frame_sad_lds_off(int tile, int O);

@@ -45,7 +45,7 @@ __device__ __forceinline__ unsigned fast_div(unsigned i, uint64_t magic)
 
 // ------------------------------------------------------------------ k_frame
 
-__device__ void frame_tile(const FrameArgs& a, int bx, int by, uint8_t* sm)
+__device__ void frame_tile(const FrameArgs& a, const FrameSrc& f, int bx, int by, uint8_t* sm)
 {
     const int T = a.tile;
     const int tid = threadIdx.x;
@@ -74,7 +74,7 @@ __device__ void frame_tile(const FrameArgs& a, int bx, int by, uint8_t* sm)
     const int cy0 = (int)(((int64_t)y0 * a.nr) / a.H);
     const int ncx = (int)(((int64_t)(xe - 1) * a.nc) / a.W) - cx0 + 1;
     const int ncy = (int)(((int64_t)(ye - 1) * a.nr) / a.H) - cy0 + 1;
-    if (a.sad_on) {
+    if (f.sad_on) {
         for (int i = tid; i < a.sad_slots; i += kFrameBlock) sadl[i] = 0;
         for (int i = tid; i < T; i += kFrameBlock) {
             colcell[i] = (uint16_t)(x0 + i < a.W ? (int)(((int64_t)(x0 + i) * a.nc) / a.W) - cx0 : 0);
@@ -91,16 +91,16 @@ __device__ void frame_tile(const FrameArgs& a, int bx, int by, uint8_t* sm)
         const int gy = y0 + ry, gx = x0 + 4 * cq;
         uint32_t v = 0, pv = 0;
         if (gy < a.H && gx < a.W) {
-            const uint8_t* src = a.cur + (size_t)gy * a.cur_pitch + gx;
-            if (a.cur_aligned) {
+            const uint8_t* src = f.cur + (size_t)gy * f.cur_pitch + gx;
+            if (f.cur_aligned) {
                 v = *reinterpret_cast<const uint32_t*>(src);
             } else {
                 for (int k = 0; k < 4; ++k)
                     if (gx + k < a.W) v |= (uint32_t)src[k] << (8 * k);
             }
-            if (a.sad_on) {
-                const uint8_t* ps = a.prev + (size_t)gy * a.prev_pitch + gx;
-                if (a.prev_aligned) {
+            if (f.sad_on) {
+                const uint8_t* ps = f.prev + (size_t)gy * f.prev_pitch + gx;
+                if (f.prev_aligned) {
                     pv = *reinterpret_cast<const uint32_t*>(ps);
                 } else {
                     for (int k = 0; k < 4; ++k)
@@ -121,7 +121,7 @@ __device__ void frame_tile(const FrameArgs& a, int bx, int by, uint8_t* sm)
         *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v;
     }
     __syncthreads();
-    if (a.sad_on) {
+    if (f.sad_on) {
         for (int i = tid; i < ncx * ncy; i += kFrameBlock) {
             const uint32_t s = sadl[i];
             if (s) atomicAdd(&a.sad[(cy0 + i / ncx) * a.nc + cx0 + i % ncx], s);
@@ -306,8 +306,9 @@ __device__ __forceinline__ bool cell_marked(const DetectArgs& a, int c)
 // Steps 0-4 for a marked cell c: stage the octave tiles, score, suppress and
 // rank. Leaves the keep bitmask and word offsets in LDS and the cell's number
 // of keypoints in *s_n (valid after the final barrier).
-__device__ __forceinline__ void detect_marked(const DetectArgs& a, int c, uint8_t* sm, CellLayout& L, const uint8_t* const* s_lvl,
-                              const int* s_pitch, uint32_t* s_n)
+__device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lvl0_aligned, int c, uint8_t* sm,
+                                              CellLayout& L, const uint8_t* const* s_lvl, const int* s_pitch,
+                                              uint32_t* s_n)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -344,7 +345,7 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int c, uint8_
                 const int ry = fast_div(j, L.ldm[o]), cq = j - ry * q;
                 const int gy = L.ty0[o] + ry, gx = L.tx0[o] + 4 * cq;
                 const uint8_t* src = s_lvl[o] + (size_t)gy * s_pitch[o] + gx;
-                if (o > 0 || a.lvl0_aligned) {
+                if (o > 0 || lvl0_aligned) {
                     val[u] = *reinterpret_cast<const uint32_t*>(src);
                 } else {
                     uint32_t v = 0;
@@ -376,7 +377,7 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int c, uint8_
                 const Box sb = L.sb[o];
                 const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
                 const uint8_t* P = sm + L.toff[o] + (ry + kRingR) * L.tpitch[o] + (sb.x0 + rx - L.tx0[o]);
-                const int v = full_score(P, L.tpitch[o], a.t);
+                const int v = full_score(P, L.tpitch[o], t);
                 const int x = sb.x0 + rx, y = sb.y0 + ry;
                 if (v > 0) {
                     reinterpret_cast<uint16_t*>(sm + L.voff[o])[(y - L.qb[o].y0) * L.vpitch[o] + (x - L.qb[o].x0)] =
@@ -405,7 +406,7 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int c, uint8_
                 pass[u] = false;
                 if (j < n) {
                     const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
-                    pass[u] = compass_pass(T0 + ry * tp + rx, tp, a.t);
+                    pass[u] = compass_pass(T0 + ry * tp + rx, tp, t);
                 }
             }
 #pragma unroll
@@ -578,7 +579,7 @@ __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
     }
     __syncthreads();
     const bool mark = s_mark != 0;
-    if (mark) detect_marked(a, c, sm, L, s_lvl, s_pitch, &s_n);
+    if (mark) detect_marked(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n);
 
     // 5) this cell's offset in D_n: the counts of all earlier cells, carried
     //    ones read from D_{n-1}'s counts, marked ones from their count words
@@ -632,11 +633,18 @@ __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
     }
 }
 
+// Frame j of a chunk marks every cell: frame 0 after a first frame, reset or
+// new t, or every frame when the parameters say so.
+__device__ __forceinline__ bool chunk_all_marked(const ChunkHead& h, int j)
+{
+    return h.all_marked || (j == 0 && h.force0);
+}
+
 // One frame j of a chunk of consecutive frames of one stream: cell c's
 // mark and, when marked, its keypoints at the cell's fixed base in frame j's
 // sparse list. With T_H active the mark needs the cell's count in frame
 // j-1, published by that frame's workgroup for the cell as a count word.
-__device__ void detect_cell_chunk(const ChunkArgs& t, int c, uint8_t* sm)
+__device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c, uint8_t* sm)
 {
     __shared__ CellLayout L;
     __shared__ int s_mark;
@@ -645,38 +653,43 @@ __device__ void detect_cell_chunk(const ChunkArgs& t, int c, uint8_t* sm)
     __shared__ int s_pitch[KPD_MAX_OCTAVES];
     const DetectArgs& a = t.d;
     const int tid = threadIdx.x;
+    const int j = t.j;
+    const uint32_t epoch = h.epoch0 + (uint32_t)j;
+    const bool all = chunk_all_marked(h, j);
 
     if (tid == 0) {
         load_level_ptrs(a, s_lvl, s_pitch);
-        bool mark = a.all_marked != 0;
+        s_lvl[0] = h.frames + (size_t)j * h.stride;
+        s_pitch[0] = h.pitch;
+        bool mark = all;
         uint32_t cprev = 0;
-        if (!mark) {
+        if (!mark && h.id_thresh < 255) {
             const int cx = c % a.nc, cy = c / a.nc;
             const int64_t area = (int64_t)a.col_w[cx] * a.row_h[cy];
-            mark = a.id_on && (int64_t)a.sad[c] > (int64_t)a.id_thresh * area;
+            mark = (int64_t)a.sad[c] > (int64_t)h.id_thresh * area;
         }
-        if (!mark && t.kb_chain) {
-            cprev = t.j == 0 ? t.prev_count[c] : (uint32_t)wait_word(&t.cnt_words_prev[c], a.epoch - 1, a.err);
-            mark = cprev >= a.kb_thresh;
+        if (!mark && h.kb_chain) {
+            cprev = j == 0 ? h.prev_count[c] : (uint32_t)wait_word(&t.cnt_words_prev[c], epoch - 1, a.err);
+            mark = cprev >= h.kb_thresh;
         }
-        t.marks[(size_t)c * t.K + t.j] = (uint8_t)mark;
-        if (t.last) a.mask[c] = (uint8_t)mark;
+        t.marks[(size_t)c * t.K + j] = (uint8_t)mark;
+        if (j == h.n_frames - 1) a.mask[c] = (uint8_t)mark;
         s_mark = mark;
         s_cprev = cprev;
     }
     __syncthreads();
     if (!s_mark) {
-        if (t.kb_chain && tid == 0)
-            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)a.epoch << 32) | s_cprev, __ATOMIC_RELAXED,
+        if (h.kb_chain && tid == 0)
+            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)epoch << 32) | s_cprev, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    detect_marked(a, c, sm, L, s_lvl, s_pitch, &s_n);
+    detect_marked(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
     __syncthreads();
     if (tid == 0) {
         t.own_count[c] = s_n;
-        if (t.kb_chain)
-            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)a.epoch << 32) | s_n, __ATOMIC_RELAXED,
+        if (h.kb_chain)
+            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)epoch << 32) | s_n, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
     emit_marked(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
@@ -702,7 +715,8 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame1(FrameArgs a)
     extern __shared__ __align__(16) uint8_t sm[];
     const int tile = xcd_band_tile(blockIdx.x, a.ntiles);
     if (tile >= a.ntiles) return;
-    frame_tile(a, tile % a.tiles_x, tile / a.tiles_x, sm);
+    const FrameSrc f{a.cur, a.prev, a.cur_pitch, a.prev_pitch, a.cur_aligned, a.prev_aligned, a.sad_on};
+    frame_tile(a, f, tile % a.tiles_x, tile / a.tiles_x, sm);
 }
 
 __global__ __launch_bounds__(kBlk) void k_detect1(DetectArgs a)
@@ -711,13 +725,36 @@ __global__ __launch_bounds__(kBlk) void k_detect1(DetectArgs a)
     detect_cell(a, blockIdx.x, sm);
 }
 
-// A chunk of consecutive frames of one stream: workgroup b is cell
-// b % ncell of frame b / ncell (frames in order, cells in order).
-__global__ __launch_bounds__(kBlk) void k_detect_chunk(const ChunkArgs* table, int ncell)
+// Tile pass of a chunk: tiles of all its frames banded over the XCDs;
+// frame j's tile source is frame j of the chunk and its predecessor.
+__global__ __launch_bounds__(kFrameBlock) void k_frame_chunk(const FrameArgs* table, ChunkHead h)
 {
     extern __shared__ __align__(16) uint8_t sm[];
-    const int j = blockIdx.x / ncell;
-    detect_cell_chunk(table[j], (int)blockIdx.x - j * ncell, sm);
+    const int nblocks = h.n_frames * h.ntiles;
+    const int b = xcd_band_tile(blockIdx.x, nblocks);
+    if (b >= nblocks) return;
+    const int j = b / h.ntiles, local = b - j * h.ntiles;
+    const FrameArgs& a = table[j];
+    const bool sad_on = !chunk_all_marked(h, j) && h.id_thresh < 255;
+    if (a.O == 1 && !sad_on) return;
+    FrameSrc f;
+    f.cur = h.frames + (size_t)j * h.stride;
+    f.cur_pitch = h.pitch;
+    f.cur_aligned = h.aligned;
+    f.prev = j == 0 ? h.prev0 : f.cur - h.stride;
+    f.prev_pitch = j == 0 ? h.prev0_pitch : h.pitch;
+    f.prev_aligned = j == 0 ? h.prev0_aligned : h.aligned;
+    f.sad_on = sad_on ? 1 : 0;
+    frame_tile(a, f, local % a.tiles_x, local / a.tiles_x, sm);
+}
+
+// Detection pass of a chunk: workgroup b is cell b % ncell of frame
+// b / ncell (frames in order, cells in order).
+__global__ __launch_bounds__(kBlk) void k_detect_chunk(const ChunkArgs* table, ChunkHead h)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const int j = blockIdx.x / h.ncell;
+    detect_cell_chunk(table[j], h, (int)blockIdx.x - j * h.ncell, sm);
 }
 
 // Compaction of a chunk, one workgroup per frame j, cells in tiles of
@@ -816,13 +853,18 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
 
 // One batch tick: workgroup b works for stream map[b] (streams' workgroups
 // are contiguous and in stream order); inactive streams' workgroups exit.
-__global__ __launch_bounds__(kFrameBlock) void k_frame_batch(const TickArgs* table, const uint16_t* map)
+// Tiles are banded over the XCDs across the whole grid, as in k_frame1.
+__global__ __launch_bounds__(kFrameBlock) void k_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks)
 {
     extern __shared__ __align__(16) uint8_t sm[];
-    const TickArgs& t = table[map[blockIdx.x]];
-    const int local = (int)blockIdx.x - t.tile_base;
+    const int b = xcd_band_tile(blockIdx.x, nblocks);
+    if (b >= nblocks) return;
+    const TickArgs& t = table[map[b]];
+    const int local = b - t.tile_base;
     if (!t.active || !t.f_on) return;
-    frame_tile(t.f, local % t.f.tiles_x, local / t.f.tiles_x, sm);
+    const FrameArgs& a = t.f;
+    const FrameSrc f{a.cur, a.prev, a.cur_pitch, a.prev_pitch, a.cur_aligned, a.prev_aligned, a.sad_on};
+    frame_tile(a, f, local % a.tiles_x, local / a.tiles_x, sm);
 }
 
 __global__ __launch_bounds__(kBlk) void k_detect_batch(const TickArgs* table, const uint16_t* map)
@@ -901,9 +943,17 @@ hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_detect_chunk(const ChunkArgs* table, int n_frames, int ncell, int lds_bytes, hipStream_t s)
+hipError_t launch_frame_chunk(const FrameArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect_chunk, dim3(n_frames * ncell), dim3(kBlk), lds_bytes, s, table, ncell);
+    const int nblocks = h.n_frames * h.ntiles;
+    const int grid = (nblocks + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(k_frame_chunk, dim3(grid), dim3(kFrameBlock), lds_bytes, s, table, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_detect_chunk, dim3(h.n_frames * h.ncell), dim3(kBlk), lds_bytes, s, table, h);
     return hipGetLastError();
 }
 
@@ -915,7 +965,8 @@ hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t 
 
 hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_frame_batch, dim3(nblocks), dim3(kFrameBlock), lds_bytes, s, table, map);
+    const int grid = (nblocks + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(k_frame_batch, dim3(grid), dim3(kFrameBlock), lds_bytes, s, table, map, nblocks);
     return hipGetLastError();
 }
 
