@@ -61,6 +61,8 @@ def parse():
                     help="masked or full: run only that pass of --workload and print its line (for profiling)")
     ap.add_argument("--chunked", action="store_true", help="with --mode: push --chunk frames per call")
     ap.add_argument("--tile", type=int, default=0, help="level-0 tile of the tile pass (0: the library default)")
+    ap.add_argument("--profile-script", metavar="OUTDIR", help="print the rocprofv3 script for the profiles")
+    ap.add_argument("--summarize-profiles", metavar="OUTDIR", help="write profiles/ from that script's output")
     return ap.parse_args()
 
 
@@ -261,6 +263,8 @@ def roofline_of(wl: Workload, res, masked: bool, traffic=None, stats=None):
     per_launch = ab[dom] * passes / max(n, 1)
     avg_s = ms / 1e3 / max(n, 1)
     achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    if traffic is None:
+        traffic = traffic_for(wl.name, masked, res.get("chunk", 0), dom)
     return {
         "kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
@@ -420,6 +424,138 @@ def serving_workload(horizon: float, speedup: float, budget_mib: int) -> dict:
     return out
 
 
+# rocprofv3 runs whose summaries live under profiles/: kernel traces of the
+# bench itself, and HBM byte counters (FETCH_SIZE, WRITE_SIZE, one counter
+# per run) of single-mode passes and of a plain copy that scales them.
+PROFILE_CASES = {
+    "kt_c2_640x480_bench": ("trace", "--no-hd --no-batch --no-serve --no-cpu-baseline --steps 10 --warmup 2"),
+    "kt_c2_640x480_masked_chunked": ("trace", "--workload c2_640x480 --mode masked --chunked --steps 20 --warmup 2"),
+    "kt_c3_1920x1080_full_chunked": ("trace", "--workload c3_1920x1080 --mode full --chunked --steps 10 --warmup 2"),
+    "pmc_c2_640x480_masked_chunked": ("pmc", "--workload c2_640x480 --mode masked --chunked --steps 2 --warmup 0"),
+    "pmc_c2_640x480_full_chunked": ("pmc", "--workload c2_640x480 --mode full --chunked --steps 2 --warmup 0"),
+    "pmc_c3_1920x1080_full_chunked": ("pmc", "--workload c3_1920x1080 --mode full --chunked --steps 2 --warmup 0"),
+    "pmc_copy_256MiB": ("pmc", "--copy-calibration 256"),
+}
+PMC_COUNTERS = ("FETCH_SIZE", "WRITE_SIZE")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ("kpd_kernels.hip", "kpd_kernels.h", "kpd_geom.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1503_06959_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_command(case: str, out: str, counter: str = "", root: str = "$R") -> str:
+    kind, args = PROFILE_CASES[case]
+    if kind == "trace":
+        return (f"rocprofv3 --kernel-trace --stats --output-format csv -d {out}/{case} -o kt -- "
+                f"python3 {root}/bench.py {args}")
+    return (f"rocprofv3 --pmc {counter} --output-format csv -d {out}/{case}_{counter} -o p -- "
+            f"python3 {root}/bench.py {args}")
+
+
+def profile_script(out: str) -> str:
+    """Shell script that runs every profiling case (started from the
+    repository root, R; the profiler runs from /tmp; one counter per --pmc
+    run, each under its own time limit). `out` is relative to R."""
+    out = "$R/" + out
+    lines = ["set -o pipefail", "R=$(pwd)", f"mkdir -p {out}", "cd /tmp && export TMPDIR=/tmp"]
+    for case, (kind, _) in PROFILE_CASES.items():
+        if kind == "trace":
+            lines.append(f"timeout -k 10 300 {profile_command(case, out)} > {out}/{case}.out 2> {out}/{case}.log "
+                         f"|| exit $?")
+        else:
+            for c in PMC_COUNTERS:
+                lines.append(f"timeout -s KILL 90 {profile_command(case, out, c)} > {out}/{case}_{c}.out "
+                             f"2> {out}/{case}_{c}.log || exit $?")
+        lines.append(f"echo {case} done")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_profiles(out: str) -> None:
+    """Write profiles/*.txt and profiles/traffic.json from the csv files of
+    profile_script's runs."""
+    import csv
+    from collections import defaultdict
+    pdir = os.path.join(ROOT, "profiles")
+    os.makedirs(pdir, exist_ok=True)
+    short = lambda n: n.split("(")[0].replace("kpd::", "")
+    for case, (kind, _) in PROFILE_CASES.items():
+        if kind != "trace":
+            continue
+        path = os.path.join(out, case, "kt_kernel_stats.csv")
+        rows = list(csv.DictReader(open(path)))
+        lines = [f"# kernel durations, {case}", "", "command (R = the repository root, run from /tmp):",
+                 "  " + profile_command(case, "$R/gpurun_out/prof"), "",
+                 f"{'kernel':40s} {'calls':>7s} {'avg_us':>10s} {'min_us':>9s} {'max_us':>9s} {'share':>7s}"]
+        for r in rows:
+            lines.append(f"{short(r['Name']):40s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.3f} "
+                         f"{float(r['MinNs']) / 1e3:9.3f} {float(r['MaxNs']) / 1e3:9.3f} "
+                         f"{float(r['Percentage']):6.2f}%")
+        open(os.path.join(pdir, f"kernel_trace_{case[3:]}.txt"), "w").write("\n".join(lines) + "\n")
+
+    def pmc(case, counter):
+        path = os.path.join(out, f"{case}_{counter}", "p_counter_collection.csv")
+        agg = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+
+    copy_bytes = 256 << 20
+    fc, wc = pmc("pmc_copy_256MiB", "FETCH_SIZE"), pmc("pmc_copy_256MiB", "WRITE_SIZE")
+    f_scale = copy_bytes / (fc["__amd_rocclr_copyBuffer"][0] * 1024)
+    w_scale = copy_bytes / (wc["__amd_rocclr_copyBuffer"][0] * 1024)
+    traffic = {"kernel_source_sha256": kernel_source_hash(), "fetch_scale": round(f_scale, 4),
+               "write_scale": round(w_scale, 4), "per_launch_bytes": {}}
+    lines = ["# HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch, one counter per run)", "",
+             f"scale: a plain copy of {copy_bytes} bytes reads FETCH_SIZE {fc['__amd_rocclr_copyBuffer'][0]:.1f} KiB "
+             f"and WRITE_SIZE {wc['__amd_rocclr_copyBuffer'][0]:.1f} KiB per dispatch, so bytes = "
+             f"FETCH_SIZE x 1024 x {f_scale:.3f} + WRITE_SIZE x 1024 x {w_scale:.3f}", "",
+             "commands (R = the repository root, run from /tmp):"]
+    for case in PROFILE_CASES:
+        if PROFILE_CASES[case][0] == "pmc":
+            for c in PMC_COUNTERS:
+                lines.append("  " + profile_command(case, "$R/gpurun_out/prof", c))
+    lines += ["", f"{'case':34s} {'kernel':16s} {'dispatches':>10s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} "
+                  f"{'bytes/launch':>13s}"]
+    for case, (kind, _) in PROFILE_CASES.items():
+        if kind != "pmc" or case == "pmc_copy_256MiB":
+            continue
+        f, w = pmc(case, "FETCH_SIZE"), pmc(case, "WRITE_SIZE")
+        wl, mode = case[4:].rsplit("_", 2)[0], case[4:].rsplit("_", 2)[1]
+        for k in sorted(f):
+            if not k.startswith("k_") or k not in w:
+                continue
+            b = f[k][0] * 1024 * f_scale + w[k][0] * 1024 * w_scale
+            name = {"k_frame_chunk": "k_frame", "k_detect_chunk": "k_detect", "k_compact_chunk": "k_compact",
+                    "k_frame1": "k_frame", "k_detect1": "k_detect"}.get(k, k)
+            key = f"{wl}/{mode}/{'chunk' if k.endswith('_chunk') else 'frame'}/{name}"
+            traffic["per_launch_bytes"][key] = int(b)
+            lines.append(f"{case[4:]:34s} {k:16s} {f[k][1]:10d} {f[k][0]:11.2f} {w[k][0]:11.2f} {int(b):13d}")
+    open(os.path.join(pdir, "hbm_traffic_chunked_and_single.txt"), "w").write("\n".join(lines) + "\n")
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(traffic, fh, indent=1, sort_keys=True)
+
+
+def traffic_for(wl_name: str, masked: bool, chunk: int, kernel: str):
+    """Counter-measured HBM bytes per launch of this kernel on this workload,
+    or None when not measured or when the kernels changed since."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    key = f"{wl_name}/{'masked' if masked else 'full'}/{'chunk' if chunk > 1 else 'frame'}/{kernel}"
+    return t["per_launch_bytes"].get(key)
+
+
 def copy_calibration(mib: int) -> None:
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters read on the detection kernels."""
@@ -436,6 +572,12 @@ def copy_calibration(mib: int) -> None:
 
 def main():
     args = parse()
+    if args.profile_script:
+        sys.stdout.write(profile_script(args.profile_script))
+        return
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); streams shard across GPUs "
               f"without communication, see the design notes", file=sys.stderr)
