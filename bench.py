@@ -6,8 +6,8 @@ segment test + score + scale-space suppression, compaction, Eq. (1) output)
 over every frame of one synthetic video, frames already resident in HBM and
 pushed through the C ABI in place (no copy). The headline workload is the
 640x480, 300-frame single stream (FAST-9 t=20, 4 octaves, 16x12 cells,
-T_I = 8), pushed 32 consecutive frames per push_frames call (results are
-identical to one push per frame). The same line also carries the
+T_I = 8), pushed up to 256 consecutive frames per push_frames call
+(results are identical to one push per frame). The same line also carries the
 full-frame rate of that workload, the streaming mode (one push_frame per
 frame) with its per-frame latency percentiles, the 1920x1080 rates, the
 batched 64-stream and serving sections, the dominant kernel's roofline and
@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--serve-budget-mib", type=int, default=1024)
     ap.add_argument("--batch-ticks", type=int, default=120)
     ap.add_argument("--batch-clip", type=int, default=40)
-    ap.add_argument("--chunk", type=int, default=32, help="frames per push_frames call (at most 32)")
+    ap.add_argument("--chunk", type=int, default=256, help="frames per push_frames call (at most 256)")
     ap.add_argument("--mode", choices=("both", "masked", "full"), default="both",
                     help="masked or full: run only that pass of --workload and print its line (for profiling)")
     ap.add_argument("--chunked", action="store_true", help="with --mode: push --chunk frames per call")
@@ -228,6 +228,7 @@ def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> 
     if chunked:
         out["k_detect"] = scan + 16 * wl.ncell * F
         out["k_compact"] = 16 * sum(st["total_kp"]) + meta
+        out["k_mark"] = 8 * wl.ncell * F
     else:
         out["k_detect"] = scan + 16 * carried + meta
     return out

@@ -52,7 +52,7 @@ extern "C" {
 #define KPD_MAX_OCTAVES 8
 #define KPD_MAX_CELL 128        /* largest cell side, in level-0 pixels */
 #define KPD_MAX_DIM 16384       /* largest frame side */
-#define KPD_MAX_CHUNK 32        /* most frames per push_frames call */
+#define KPD_MAX_CHUNK 256       /* most frames per push_frames call */
 
 /* push_frame flags */
 #define KPD_FRAME_HOST 0          /* host pointer; copied into the arena */
@@ -248,7 +248,8 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
 #define KPD_K_FRAME 0
 #define KPD_K_DETECT 1
 #define KPD_K_COMPACT 2 /* compaction pass of push_frames */
-#define KPD_NKERNELS 3
+#define KPD_K_MARK 3    /* mark pass of push_frames when marks need no counts */
+#define KPD_NKERNELS 4
 
 /* Switch per-kernel GPU timing on (1) or off (0). While on, every kernel
  * launch of this stream is bracketed by two HIP events recorded on the

@@ -63,7 +63,7 @@ struct Layout {
     int ctile = 32, ctiles_x = 0, ctiles_y = 0, csad_slots = 1;   // tile pass of chunks
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
-    size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0;
+    size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0, off_work = 0;
     size_t off_cntw = 0, off_ctab = 0, off_ftab = 0;
     size_t list_cap = 0;
     int lds_bytes = 0;   // dynamic LDS of the cell pass
@@ -71,7 +71,7 @@ struct Layout {
 };
 
 // header words
-constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrErr = 3;
+constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrErr = 3, kHdrWork = 4;
 
 bool valid_params(int W, int H, const kpd_params* p, std::string* why)
 {
@@ -164,10 +164,6 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->lds_bytes = std::max(lds, 16);
 
     L->K = std::max(1, (int)p->chunk_frames);
-    if (L->K > 1 && L->list_cap >= (1u << 26)) {
-        *why = "frame too large for chunks";
-        return false;
-    }
 
     size_t off = 0;
     L->off_hdr = off; off = align_up(off + 64);
@@ -196,10 +192,11 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_coffs = off; off = align_up(off + kc * 4);
         L->off_ctotal = off; off = align_up(off + (size_t)L->K * 4);
         L->off_cntw = off; off = align_up(off + kc * 8);
-        L->Kp = (L->K + 3) / 4 * 4;
+        L->Kp = (L->K + 15) / 16 * 16;
         L->off_marks = off; off = align_up(off + (size_t)L->ncell * L->Kp);
         L->off_own = off; off = align_up(off + kc * 4);
         L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
+        L->off_work = off; off = align_up(off + kc * 4);
         L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
         L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
         L->off_clist = off; off += L->clist_stride * (size_t)(L->K - 1);   // the last frame's D goes to D_n
@@ -623,6 +620,15 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     h.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);
     h.ntiles = L.ctiles_x * L.ctiles_y;
     h.ncell = L.ncell;
+    h.nc = L.nc;
+    h.sad0 = s->at<uint32_t>(L.off_csad);
+    h.col_w = s->at<uint16_t>(L.off_colw);
+    h.row_h = s->at<uint16_t>(L.off_rowh);
+    h.marks = s->at<uint8_t>(L.off_marks);
+    h.mask = s->at<uint8_t>(L.off_mask);
+    h.Kp = L.Kp;
+    h.work = s->at<uint32_t>(L.off_work);
+    h.work_count = s->at<uint32_t>(L.off_hdr) + kHdrWork;
     // the tile pass is needed for coarser octaves or intensity differences
     const bool any_tiles = L.O > 1 || (s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
                                        (n_frames > 1 || !h.force0));
@@ -632,7 +638,15 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         KPD_HIP(timed(s, KPD_K_FRAME, [&] {
             return kpd::launch_frame_chunk(ftab, h, kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots), s->stream);
         }));
-    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_chunk(ctab, h, L.lds_bytes, s->stream); }));
+    if (h.all_marked || h.kb_chain) {
+        // every cell, or marks that wait on the previous frame's counts:
+        // one workgroup per (frame, cell)
+        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_chunk(ctab, h, L.lds_bytes, s->stream); }));
+    } else {
+        // marks from the SAD alone: list the marked cells, detect only those
+        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(h, s->stream); }));
+        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_list(ctab, h, L.lds_bytes, s->stream); }));
+    }
     kpd::CompactArgs ca{};
     ca.ncell = L.ncell;
     ca.last = n_frames - 1;
@@ -658,6 +672,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     const uint32_t n_last = n0 + (uint32_t)n_frames - 1;
     ca.sad_stats = s->at<uint32_t>(L.off_sad[n_last & 1]);
     ca.sad_single_next = s->at<uint32_t>(L.off_sad[(n_last + 1) & 1]);
+    ca.work_count = h.work_count;
     KPD_HIP(timed(s, KPD_K_COMPACT, [&] { return kpd::launch_compact_chunk(ca, n_frames, s->stream); }));
 
     const uint8_t* last = frames + (size_t)(n_frames - 1) * frame_stride;

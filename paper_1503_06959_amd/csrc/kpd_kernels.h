@@ -114,6 +114,17 @@ struct ChunkHead {
     int kb_chain;               // marks read the previous frame's counts (T_H active)
     const uint32_t* prev_count; // counts of the frame before the chunk
     int ntiles, ncell;          // tiles and cells per frame
+    int nc;                     // cell columns
+    // marks decided before detection (no T_H chain): the mark pass lists
+    // the marked (frame, cell) items and the detection pass runs only those
+    const uint32_t* sad0;       // frame j's SAD at sad0 + j * ncell
+    const uint16_t* col_w;
+    const uint16_t* row_h;
+    uint8_t* marks;             // cells x Kp mark bytes
+    uint8_t* mask;              // M of the last frame
+    int Kp;
+    uint32_t* work;             // marked items j * ncell + c
+    uint32_t* work_count;       // their number; cleared by the compaction pass
 };
 
 struct CompactArgs {
@@ -138,10 +149,13 @@ struct CompactArgs {
     uint32_t* sad_chunk;             // chunk frames x cells, cleared here
     uint32_t* sad_stats;             // receives the last frame's SAD
     uint32_t* sad_single_next;       // cleared for the next single frame
+    uint32_t* work_count;            // cleared for the next chunk
 };
 
 hipError_t launch_frame_chunk(const FrameArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
+hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s);
+hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t s);
 
 int frame_sad_lds_off(int tile, int O);

@@ -45,7 +45,8 @@ __device__ __forceinline__ unsigned fast_div(unsigned i, uint64_t magic)
 
 // ------------------------------------------------------------------ k_frame
 
-__device__ void frame_tile(const FrameArgs& a, const FrameSrc& f, int bx, int by, uint8_t* sm)
+template <int B>
+__device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int by, uint8_t* sm)
 {
     const int T = a.tile;
     const int tid = threadIdx.x;
@@ -83,43 +84,74 @@ __device__ void frame_tile(const FrameArgs& a, const FrameSrc& f, int bx, int by
     }
     __syncthreads();
 
-    // level 0 tile (and the SAD against I_{n-1})
+    // level 0 tile (and the SAD against I_{n-1}). Each thread keeps one
+    // dword column of the tile (T/4 <= kFrameBlock) and walks down rows
+    // kFrameBlock*4/T apart, loading B rows per step (all of them) so that the
+    // loads are in flight together. The SAD of consecutive dwords of one
+    // cell is summed in a register and added to the cell's LDS slot when
+    // the cell changes; dwords straddling a cell column border go byte by
+    // byte.
     uint8_t* L0 = sm;
     const int ndw = T * T / 4;
-    for (int i = tid; i < ndw; i += kFrameBlock) {
-        const int ry = i >> lgq, cq = i & (T / 4 - 1);
-        const int gy = y0 + ry, gx = x0 + 4 * cq;
-        uint32_t v = 0, pv = 0;
-        if (gy < a.H && gx < a.W) {
-            const uint8_t* src = f.cur + (size_t)gy * f.cur_pitch + gx;
-            if (f.cur_aligned) {
-                v = *reinterpret_cast<const uint32_t*>(src);
-            } else {
-                for (int k = 0; k < 4; ++k)
-                    if (gx + k < a.W) v |= (uint32_t)src[k] << (8 * k);
-            }
-            if (f.sad_on) {
-                const uint8_t* ps = f.prev + (size_t)gy * f.prev_pitch + gx;
-                if (f.prev_aligned) {
-                    pv = *reinterpret_cast<const uint32_t*>(ps);
+    const int cq = tid & (T / 4 - 1);
+    const int gx = x0 + 4 * cq;
+    const int rstep = kFrameBlock >> lgq;   // rows between a thread's dwords
+    const bool straddle = f.sad_on && (gx + 3 >= a.W || colcell[4 * cq] != colcell[4 * cq + 3]);
+    uint32_t acc = 0;
+    int acc_slot = -1;
+    for (int i0 = tid; i0 < ndw; i0 += B * kFrameBlock) {
+        uint32_t v[B], pv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int ry = (i0 >> lgq) + u * rstep;
+            const int gy = y0 + ry;
+            v[u] = 0;
+            pv[u] = 0;
+            if (ry < T && gy < a.H && gx < a.W) {
+                const uint8_t* src = f.cur + (size_t)gy * f.cur_pitch + gx;
+                if (f.cur_aligned) {
+                    v[u] = *reinterpret_cast<const uint32_t*>(src);
                 } else {
                     for (int k = 0; k < 4; ++k)
-                        if (gx + k < a.W) pv |= (uint32_t)ps[k] << (8 * k);
+                        if (gx + k < a.W) v[u] |= (uint32_t)src[k] << (8 * k);
                 }
-                const int lc = 4 * cq;
-                const int rc = rowcell[ry] * ncx;
-                if (gx + 3 < a.W && colcell[lc] == colcell[lc + 3]) {
-                    atomicAdd(&sadl[rc + colcell[lc]], __builtin_amdgcn_sad_u8(v, pv, 0u));
-                } else {
-                    for (int k = 0; k < 4 && gx + k < a.W; ++k) {
-                        const uint32_t m = 0xFFu << (8 * k);
-                        atomicAdd(&sadl[rc + colcell[lc + k]], __builtin_amdgcn_sad_u8(v & m, pv & m, 0u));
+                if (f.sad_on) {
+                    const uint8_t* ps = f.prev + (size_t)gy * f.prev_pitch + gx;
+                    if (f.prev_aligned) {
+                        pv[u] = *reinterpret_cast<const uint32_t*>(ps);
+                    } else {
+                        for (int k = 0; k < 4; ++k)
+                            if (gx + k < a.W) pv[u] |= (uint32_t)ps[k] << (8 * k);
                     }
                 }
             }
         }
-        *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int ry = (i0 >> lgq) + u * rstep;
+            if (ry >= T) continue;
+            *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v[u];
+            const int gy = y0 + ry;
+            if (!f.sad_on || gy >= a.H || gx >= a.W) continue;
+            const int rc = rowcell[ry] * ncx;
+            if (!straddle) {
+                const int slot = rc + colcell[4 * cq];
+                const uint32_t d = __builtin_amdgcn_sad_u8(v[u], pv[u], 0u);
+                if (slot != acc_slot) {
+                    if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
+                    acc_slot = slot;
+                    acc = 0;
+                }
+                acc += d;
+            } else {
+                for (int k = 0; k < 4 && gx + k < a.W; ++k) {
+                    const uint32_t m = 0xFFu << (8 * k);
+                    atomicAdd(&sadl[rc + colcell[4 * cq + k]], __builtin_amdgcn_sad_u8(v[u] & m, pv[u] & m, 0u));
+                }
+            }
+        }
     }
+    if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
     __syncthreads();
     if (f.sad_on) {
         for (int i = tid; i < ncx * ncy; i += kFrameBlock) {
@@ -184,6 +216,15 @@ __device__ void frame_tile(const FrameArgs& a, const FrameSrc& f, int bx, int by
         }
         __syncthreads();
     }
+}
+
+// A thread holds T*T/4/kFrameBlock level-0 dwords of its tile: 1, 4 or 16
+// for T = 32, 64, 128, loaded up to 8 at a time.
+__device__ __forceinline__ void frame_tile(const FrameArgs& a, const FrameSrc& f, int bx, int by, uint8_t* sm)
+{
+    if (a.tile <= 32) frame_tile_b<1>(a, f, bx, by, sm);
+    else if (a.tile == 64) frame_tile_b<4>(a, f, bx, by, sm);
+    else frame_tile_b<8>(a, f, bx, by, sm);
 }
 
 // ----------------------------------------------------------------- k_detect
@@ -695,6 +736,26 @@ __device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c,
     emit_marked(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
 }
 
+// Detection of marked cell c of chunk frame j (mark known, no count word).
+__device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8_t* sm)
+{
+    __shared__ CellLayout L;
+    __shared__ uint32_t s_n;
+    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
+    __shared__ int s_pitch[KPD_MAX_OCTAVES];
+    const DetectArgs& a = t.d;
+    if (threadIdx.x == 0) {
+        load_level_ptrs(a, s_lvl, s_pitch);
+        s_lvl[0] = h.frames + (size_t)t.j * h.stride;
+        s_pitch[0] = h.pitch;
+    }
+    __syncthreads();
+    detect_marked(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
+    if (threadIdx.x == 0) t.own_count[c] = s_n;
+    emit_marked(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
+    __syncthreads();   // L and the LDS maps are reused by the next item
+}
+
 // ----------------------------------------------------------------- kernels
 
 // Workgroups are dealt to the 8 XCDs round-robin by index. The tile pass
@@ -757,6 +818,59 @@ __global__ __launch_bounds__(kBlk) void k_detect_chunk(const ChunkArgs* table, C
     detect_cell_chunk(table[j], h, (int)blockIdx.x - j * h.ncell, sm);
 }
 
+// Mark pass of a chunk whose marks need no counts: one thread per (frame,
+// cell) decides the mark, records it and appends marked items to the work
+// list (one atomic per wave).
+constexpr int kMarkBlock = 1024;
+
+__global__ __launch_bounds__(kMarkBlock) void k_mark_chunk(ChunkHead h)
+{
+    __shared__ uint32_t s_count, s_base;
+    const int n = h.n_frames * h.ncell;
+    const int i = blockIdx.x * kMarkBlock + threadIdx.x;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    bool mark = false;
+    if (i < n) {
+        const int j = i / h.ncell, c = i - j * h.ncell;
+        mark = chunk_all_marked(h, j);
+        if (!mark && h.id_thresh < 255) {
+            const int cx = c % h.nc, cy = c / h.nc;
+            const int64_t area = (int64_t)h.col_w[cx] * h.row_h[cy];
+            mark = (int64_t)h.sad0[(size_t)j * h.ncell + c] > (int64_t)h.id_thresh * area;
+        }
+        h.marks[(size_t)c * h.Kp + j] = (uint8_t)mark;
+        if (j == h.n_frames - 1) h.mask[c] = (uint8_t)mark;
+    }
+    // workgroup-local slots first, then one global atomic per workgroup
+    const uint64_t bal = __ballot(mark);
+    const int lane = threadIdx.x & 63;
+    const int leader = bal ? __builtin_ctzll(bal) : 0;
+    uint32_t wbase = 0;
+    if (bal && lane == leader) wbase = atomicAdd(&s_count, (uint32_t)__popcll(bal));
+    wbase = __shfl(wbase, leader);
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_count ? atomicAdd(h.work_count, s_count) : 0;
+    __syncthreads();
+    if (mark) {
+        const unsigned below =
+            __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+        h.work[s_base + wbase + below] = (uint32_t)i;
+    }
+}
+
+// Detection pass over the work list: workgroup b takes items b, b + grid, ...
+__global__ __launch_bounds__(kBlk) void k_detect_list(const ChunkArgs* table, ChunkHead h)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const uint32_t n = *h.work_count;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const uint32_t item = h.work[it];
+        const int j = (int)(item / (uint32_t)h.ncell);
+        detect_item(table[j], h, (int)(item - (uint32_t)j * h.ncell), sm);
+    }
+}
+
 // Compaction of a chunk, one workgroup per frame j, cells in tiles of
 // kCompact: each cell's source (the last chunk frame up to j that marked it,
 // else the list before the chunk) and count, their exclusive prefix (the
@@ -764,6 +878,7 @@ __global__ __launch_bounds__(kBlk) void k_detect_chunk(const ChunkArgs* table, C
 // The last frame's list goes where the next push reads it. Also clears the
 // chunk's SAD accumulators and hands the last frame's SAD to the statistics.
 constexpr int kCompact = 512;
+constexpr int kMaxChunk = KPD_MAX_CHUNK;
 
 __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
 {
@@ -777,7 +892,6 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
     kpd_keypoint* dst = last ? a.next_list : a.lists + (size_t)j * a.list_stride;
     uint32_t* cnt_out = last ? a.next_count : a.counts + jc;
     uint32_t* off_out = last ? a.next_offs : a.offs + jc;
-    const uint32_t upto = j >= 31 ? 0xFFFFFFFFu : ((2u << j) - 1u);
     if (tid == 0) s_base = 0;
     __syncthreads();
 
@@ -788,16 +902,30 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
         uint32_t n = 0, src = 0;
         int f = -1;
         if (c < a.ncell) {
-            // marks of frames 0..j of this cell as bits (bytes are 0 or 1)
-            const uint32_t* m4 = reinterpret_cast<const uint32_t*>(a.marks + (size_t)c * a.K);
-            uint32_t bits = 0;
-            for (int q = 0; q * 4 <= j; ++q) {
-                const uint32_t w = m4[q];
-                bits |= ((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u)) << (4 * q);
+            // the newest frame <= j that marked this cell: mark bytes (0 or
+            // 1) 16 frames per load, all loads issued before any is used
+            const uint4* m16 = reinterpret_cast<const uint4*>(a.marks + (size_t)c * a.K);
+            const int qj = j >> 4;
+#pragma unroll
+            for (int q0 = 0; q0 < kMaxChunk / 16; q0 += 4) {
+                if (q0 > qj) break;
+                uint4 w[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (q0 + u <= qj) w[u] = m16[q0 + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (q0 + u > qj) break;
+                    const uint32_t d[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+                    uint32_t b = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        b |= ((d[k] & 1u) | ((d[k] >> 7) & 2u) | ((d[k] >> 14) & 4u) | ((d[k] >> 21) & 8u)) << (4 * k);
+                    if (q0 + u == qj) b &= (2u << (j & 15)) - 1u;
+                    if (b) f = 16 * (q0 + u) + 31 - __clz(b);
+                }
             }
-            bits &= upto;
-            if (bits) {
-                f = 31 - __clz(bits);
+            if (f >= 0) {
                 n = a.own_count[(size_t)f * a.ncell + c];
                 src = a.cell_base[c];
             } else {
@@ -849,6 +977,7 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
         __syncthreads();
     }
     if (tid == 0) *(last ? a.next_total : a.totals + j) = s_base;
+    if (j == 0 && tid == 0) *a.work_count = 0;
 }
 
 // One batch tick: workgroup b works for stream map[b] (streams' workgroups
@@ -923,6 +1052,9 @@ hipError_t set_detect_lds_limit(int lds_bytes)
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect1),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_list), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_bytes);
+    if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_chunk), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_bytes);
     if (e != hipSuccess) return e;
@@ -954,6 +1086,21 @@ hipError_t launch_frame_chunk(const FrameArgs* table, const ChunkHead& h, int ld
 hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
 {
     hipLaunchKernelGGL(k_detect_chunk, dim3(h.n_frames * h.ncell), dim3(kBlk), lds_bytes, s, table, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s)
+{
+    const int n = h.n_frames * h.ncell;
+    hipLaunchKernelGGL(k_mark_chunk, dim3((n + kMarkBlock - 1) / kMarkBlock), dim3(kMarkBlock), 0, s, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
+{
+    const int items = h.n_frames * h.ncell;
+    const int grid = items < 1024 ? items : 1024;
+    hipLaunchKernelGGL(k_detect_list, dim3(grid), dim3(kBlk), lds_bytes, s, table, h);
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
             "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints")
-KERNEL_NAMES = ("k_frame", "k_detect", "k_compact")
+KERNEL_NAMES = ("k_frame", "k_detect", "k_compact", "k_mark")
 
 
 class KpdParams(ctypes.Structure):

@@ -169,5 +169,23 @@ def test_chunk_timing_counts_launches(kpd):
     g.push_chunk(frames[:4])
     g.push_chunk(frames[4:])
     ms, n = kpd.profile_read(g.handle)
-    assert list(n) == [2, 2, 2]
+    assert list(n) == [2, 2, 2, 2]    # marks from the SAD alone: a mark pass runs too
     g.close()
+    g = kpd.Stream(320, 240, kpd.make_params(30, 3, 8, 6, -1, KB_OFF, 0, 4))
+    kpd.profile(g.handle, True)
+    g.push_chunk(frames[:4])
+    ms, n = kpd.profile_read(g.handle)
+    assert list(n) == [1, 1, 1, 0]    # every cell marked: no mark pass
+    g.close()
+
+
+def test_c2_chunks_of_64_frames(kpd):
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 140)
+    run_chunks(kpd, frames, det_of("c2_640x480"), [64, 0, 64, 11], K=64)
+    run_chunks(kpd, frames[:70], det_of("c2_640x480", TH=3), [64, 6], K=64)
+
+
+def test_c1_chunk_of_256_frames(kpd):
+    # the largest chunk: the compaction scans up to 256 mark bytes per cell
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 262)
+    run_chunks(kpd, frames, det_of("c1_320x240"), [256, 0, 5], K=256)
