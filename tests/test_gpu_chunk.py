@@ -189,3 +189,43 @@ def test_c1_chunk_of_256_frames(kpd):
     # the largest chunk: the compaction scans up to 256 mark bytes per cell
     frames = synth.make_video(synth.SCENES["c1_320x240"], 262)
     run_chunks(kpd, frames, det_of("c1_320x240"), [256, 0, 5], K=256)
+
+
+# ------------------------------------------- the launch configuration bench.py times
+
+def test_c2_300_frames_in_bench_chunks(kpd):
+    # the 640x480 video as the bench pushes it: one chunk of 256, one of 44
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 300)
+    run_chunks(kpd, frames, det_of("c2_640x480"), [256, 44], K=256)
+
+
+def test_c3_300_frames_in_bench_chunks_sampled(kpd):
+    # 1920x1080 at full length through 256 + 44 frame chunks: every 10th
+    # frame and the last compared with the oracle stream; in full-frame mode
+    # sampled frames are compared with a fresh oracle stream's first frame
+    import torch
+    sc = synth.SCENES["c3_1920x1080"]
+    frames = synth.make_video(sc, 300)
+    dev = torch.from_numpy(frames).cuda()
+    for TI in (8, -1):
+        det = det_of("c3_1920x1080", TI=TI)
+        g = kpd.Stream(1920, 1080, kpd.make_params(*det, 0, 256))
+        got = {}
+        for start, n in ((0, 256), (256, 44)):
+            g.push_chunk(dev[start:start + n])
+            for j in range(n):
+                i = start + j
+                if i % 10 == 0 or i == 299 or (TI < 0 and i in (37, 255, 256)):
+                    got[i] = tuples(g.chunk_keypoints(j))
+        g.close()
+        if TI >= 0:
+            o = oracle.Stream(1920, 1080, *det)
+            for i in range(300):
+                o.push(frames[i])
+                if i in got:
+                    assert got[i] == tuples(o.get()[0]), f"frame {i}"
+        else:
+            for i, k in got.items():
+                o = oracle.Stream(1920, 1080, *det)
+                o.push(frames[i])
+                assert k == tuples(o.get()[0]), f"full-frame frame {i}"
