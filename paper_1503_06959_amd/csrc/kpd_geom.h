@@ -120,10 +120,9 @@ KPD_HD int round_up(int v, int a) { return (v + a - 1) / a * a; }
 // Threads per workgroup of the detection kernel and its waves.
 constexpr int kDetectBlock = 512;
 constexpr int kDetectWaves = kDetectBlock / 64;
-// Pixels a wave tests per pass (four per lane) and the entries of each
-// wave's private queue of pixels awaiting the full segment test: a power of
-// two holding one pass on top of a part-filled batch of 64.
-constexpr int kChunk = 256;
+// Entries of each wave's private queue of pixels awaiting the full segment
+// test: a power of two holding one pass (64 groups of four pixels) on top of
+// a part-filled batch of 64.
 constexpr int kQueue = 512;
 
 // floor(i / d) = (i * magic) >> 32 for i * d < 2^32, with magic = ceil(2^32 / d)
@@ -141,8 +140,9 @@ KPD_HD uint64_t div_magic(unsigned d) { return (0x100000000ull + d - 1) / d; }
 // score box][pixel tiles: u8 per level]. A level's pixel tile covers its score
 // box plus the 3-pixel ring apron; its first column is rounded down to a
 // multiple of 4 and its row pitch up to one, so that 4-byte aligned rows can
-// be loaded a dword at a time. Score pixels are processed in chunks of
-// kChunk that never straddle two levels.
+// be loaded a dword at a time. Score pixels are tested in groups of four
+// tile columns (one dword of a tile row); groups that cover any score pixel
+// of a row are taken 64 at a time, in chunks that never straddle two levels.
 struct CellLayout {
     uint64_t ldm[KPD_MAX_OCTAVES];       // div magics: tile dwords per row,
     uint64_t scm[KPD_MAX_OCTAVES];       // score-box width,
@@ -156,7 +156,10 @@ struct CellLayout {
     int ld_start[KPD_MAX_OCTAVES + 1];   // flattened dword-load index of each level
     int sc_start[KPD_MAX_OCTAVES + 1];   // flattened score index of each level
     int dc_start[KPD_MAX_OCTAVES + 1];   // flattened decision index of each level
-    int ck_start[KPD_MAX_OCTAVES + 1];   // first score chunk of each level
+    int ck_start[KPD_MAX_OCTAVES + 1];   // first group chunk (64 groups) of each level
+    uint64_t gcm[KPD_MAX_OCTAVES];       // div magic: groups per score row
+    int gx0[KPD_MAX_OCTAVES];            // tile dword column of each score row's first group
+    int ngx[KPD_MAX_OCTAVES];            // groups (4 tile columns) per score row
     int vpitch[KPD_MAX_OCTAVES];         // score-map row pitch (query-box width)
     int vbytes;                          // bytes of all score maps (zeroed per cell)
     int O;
@@ -173,7 +176,8 @@ KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, Cell
         L->sb[o] = Box{0, 0, 0, 0};
         L->qb[o] = Box{0, 0, 0, 0};
         L->tx0[o] = L->ty0[o] = L->tpitch[o] = L->th[o] = L->toff[o] = L->voff[o] = L->vpitch[o] = 0;
-        L->ldm[o] = L->scm[o] = L->dcm[o] = 0;
+        L->ldm[o] = L->scm[o] = L->dcm[o] = L->gcm[o] = 0;
+        L->gx0[o] = L->ngx[o] = 0;
     }
     for (int o = 0; o < O; ++o) L->dec[o] = decision_box(rect, o, w[o], h[o]);
     for (int o = 0; o < O; ++o) L->sb[o] = score_box(L->dec, o, O, w[o], h[o]);
@@ -198,37 +202,38 @@ KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, Cell
     for (int o = 0; o < O; ++o) {
         L->voff[o] = off;
         L->sc_start[o] = sc;
-        L->ck_start[o] = ck;
         L->vpitch[o] = 0;
         if (!box_empty(L->qb[o])) {
             L->vpitch[o] = box_w(L->qb[o]);
             off += round_up(L->vpitch[o] * box_h(L->qb[o]) * 2, 4);
         }
-        if (!box_empty(L->sb[o])) {
-            const int n = box_w(L->sb[o]) * box_h(L->sb[o]);
-            sc += n;
-            ck += (n + kChunk - 1) / kChunk;
-        }
+        if (!box_empty(L->sb[o])) sc += box_w(L->sb[o]) * box_h(L->sb[o]);
     }
-    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) { L->sc_start[o] = sc; L->ck_start[o] = ck; }
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) L->sc_start[o] = sc;
     L->vbytes = off - v0;
     int ld = 0;
     for (int o = 0; o < O; ++o) {
         L->ld_start[o] = ld;
+        L->ck_start[o] = ck;
         L->toff[o] = off;
+        L->gx0[o] = L->ngx[o] = 0;
         if (box_empty(L->sb[o])) continue;
         L->tx0[o] = (L->sb[o].x0 - kRingR) & ~3;
         L->ty0[o] = L->sb[o].y0 - kRingR;
         L->tpitch[o] = round_up(L->sb[o].x1 + kRingR - L->tx0[o], 4);
         L->th[o] = box_h(L->sb[o]) + 2 * kRingR;
+        L->gx0[o] = (L->sb[o].x0 - L->tx0[o]) >> 2;
+        L->ngx[o] = ((L->sb[o].x1 - 1 - L->tx0[o]) >> 2) - L->gx0[o] + 1;
+        ck += (L->ngx[o] * box_h(L->sb[o]) + 63) / 64;
         off += L->tpitch[o] * L->th[o];
         ld += (L->tpitch[o] / 4) * L->th[o];
     }
-    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) L->ld_start[o] = ld;
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) { L->ld_start[o] = ld; L->ck_start[o] = ck; }
     for (int o = 0; o < O; ++o) {
         L->ldm[o] = div_magic(imax(L->tpitch[o] / 4, 1));
         L->scm[o] = div_magic(imax(box_w(L->sb[o]), 1));
         L->dcm[o] = div_magic(imax(box_w(L->dec[o]), 1));
+        L->gcm[o] = div_magic(imax(L->ngx[o], 1));
     }
     L->bytes = off;
 }

@@ -363,7 +363,10 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
     }
     __syncthreads();
     uint64_t* candw = reinterpret_cast<uint64_t*>(sm + L.cand_off);
-    for (int i = tid; i < L.nwords; i += kBlk) candw[i] = 0;
+    for (int i = tid; i < L.nwords; i += kBlk) {
+        candw[i] = 0;
+        keepw[i] = 0;
+    }
     {
         uint32_t* v = reinterpret_cast<uint32_t*>(sm + L.voff[0]);
         for (int i = tid; i < L.vbytes / 4; i += kBlk) v[i] = 0;
@@ -403,10 +406,12 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
     }
     __syncthreads();
 
-    // 2) segment test and score over every octave's score box. Waves take
-    //    chunks of kChunk pixels of one level (four per lane) and queue
-    //    those that pass the four-compass-point test; the full 16-pixel
-    //    test runs 64 queued pixels at a time, so lanes stay busy.
+    // 2) segment test and score over every octave's score box. A lane takes
+    //    a group of four pixels of a score row (one dword of the tile row),
+    //    reads the dwords holding their compass points (N and S at rows -3
+    //    and +3, E and W shifted out of the neighbouring dwords) and queues
+    //    the pixels that pass the four-compass-point test; the full
+    //    16-pixel test runs 64 queued pixels at a time, so lanes stay busy.
     {
         uint16_t* queue = reinterpret_cast<uint16_t*>(sm + L.queue_off) + wave * kQueue;
         uint32_t q_tail = 0, q_head = 0;
@@ -436,27 +441,48 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
         for (int ck = wave; ck < nck; ck += kDetWaves) {
             const int o = level_of(L.ck_start, O, ck);
             const Box sb = L.sb[o];
-            const int n = box_w(sb) * box_h(sb);
-            const int tp = L.tpitch[o];
-            const uint8_t* T0 = sm + L.toff[o] + kRingR * tp + (sb.x0 - L.tx0[o]);
-            const int j0 = (ck - L.ck_start[o]) * kChunk;
-            bool pass[4];
+            const int tp = L.tpitch[o], tx0 = L.tx0[o];
+            const int ngx = L.ngx[o], gx0 = L.gx0[o];
+            const int wsb = box_w(sb);
+            const int lo_col = sb.x0 - tx0, hi_col = sb.x1 - tx0;   // score columns in the tile
+            const int sc0 = L.sc_start[o];
+            const uint8_t* base = sm + L.toff[o] + kRingR * tp;      // tile row of score row 0
+            const int g = (ck - L.ck_start[o]) * 64 + lane;
+            uint32_t pass = 0;
+            int ry = 0, cx = 0;
+            if (g < ngx * box_h(sb)) {
+                ry = fast_div(g, L.gcm[o]);
+                cx = 4 * (gx0 + g - ry * ngx);
+                const uint8_t* P = base + ry * tp + cx;
+                const uint32_t c = *reinterpret_cast<const uint32_t*>(P);
+                const uint32_t cm = *reinterpret_cast<const uint32_t*>(P - 4);
+                const uint32_t cp = *reinterpret_cast<const uint32_t*>(P + 4);
+                const uint32_t nw = *reinterpret_cast<const uint32_t*>(P - 3 * tp);
+                const uint32_t sw = *reinterpret_cast<const uint32_t*>(P + 3 * tp);
+                const uint32_t ew = __builtin_amdgcn_alignbyte(cp, c, 3);   // bytes x+3
+                const uint32_t ww = __builtin_amdgcn_alignbyte(c, cm, 1);   // bytes x-3
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = j0 + u * 64 + lane;
-                pass[u] = false;
-                if (j < n) {
-                    const int ry = fast_div(j, L.scm[o]), rx = j - ry * box_w(sb);
-                    pass[u] = compass_pass(T0 + ry * tp + rx, tp, t);
+                for (int k = 0; k < 4; ++k) {
+                    const int sh = 8 * k;
+                    const int p = (c >> sh) & 0xFF;
+                    const int n = (nw >> sh) & 0xFF, so = (sw >> sh) & 0xFF;
+                    const int e = (ew >> sh) & 0xFF, w = (ww >> sh) & 0xFF;
+                    const int hi = p + t, lo = p - t;
+                    const bool b = min(max(n, so), max(e, w)) > hi;
+                    const bool d = max(min(n, so), min(e, w)) < lo;
+                    const bool in = cx + k >= lo_col && cx + k < hi_col;
+                    pass |= (uint32_t)((b || d) && in) << k;
                 }
             }
+            const int idx0 = sc0 + ry * wsb + (cx - lo_col);   // score index of byte 0
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint64_t bal = __ballot(pass[u]);
-                if (pass[u]) {
+            for (int k = 0; k < 4; ++k) {
+                const bool pk = (pass >> k) & 1;
+                const uint64_t bal = __ballot(pk);
+                if (pk) {
                     const unsigned below = __builtin_amdgcn_mbcnt_hi(
                         (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                    queue[(q_tail + below) & (kQueue - 1)] = (uint16_t)(L.sc_start[o] + j0 + u * 64 + lane);
+                    queue[(q_tail + below) & (kQueue - 1)] = (uint16_t)(idx0 + k);
                 }
                 q_tail += (uint32_t)__popcll(bal);
             }
@@ -470,22 +496,60 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
     }
     __syncthreads();
 
-    // 3) scale-space maxima of the candidates, one 64-pixel word per wave
-    //    pass; words without candidates are skipped whole
-    for (int w = wave; w < L.nwords; w += kDetWaves) {
-        const uint64_t cand = candw[w];
-        bool keep = false;
-        if (cand != 0 && ((cand >> lane) & 1)) {
-            const int i = w * 64 + lane;
-            const int o = level_of(L.dc_start, O, i);
-            const unsigned j = i - L.dc_start[o];
-            const Box d = L.dec[o];
-            const int ry = fast_div(j, L.dcm[o]);
-            const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
-            keep = is_local_max(sm, L, o, O, x, y, vget(sm, L, o, x, y));
+    // 3) scale-space maxima of the candidates. Each wave scans 64 candidate
+    //    words at a time (one per lane), queues the candidates' decision
+    //    indices in its LDS queue, and runs the neighbourhood test on 64
+    //    queued candidates at a time; survivors set their keep bit.
+    {
+        uint16_t* queue = reinterpret_cast<uint16_t*>(sm + L.queue_off) + wave * kQueue;
+        uint32_t q_head = 0, q_tail = 0;
+        auto nms = [&](int count) {
+            if (lane < count) {
+                const int i = queue[(q_head + lane) & (kQueue - 1)];
+                const int o = level_of(L.dc_start, O, i);
+                const unsigned j = i - L.dc_start[o];
+                const Box d = L.dec[o];
+                const int ry = fast_div(j, L.dcm[o]);
+                const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
+                if (is_local_max(sm, L, o, O, x, y, vget(sm, L, o, x, y)))
+                    atomicOr(&keepw[i >> 6], 1ull << (i & 63));
+            }
+            q_head += count;
+        };
+        constexpr uint32_t kWindow = kQueue - 64;   // entries added between drains
+        const int nw = L.nwords;
+        for (int w0 = wave * 64; w0 < nw; w0 += kDetWaves * 64) {
+            const int w = w0 + lane;
+            const uint64_t word = w < nw ? candw[w] : 0ull;
+            const uint32_t cnt = (uint32_t)__popcll(word);
+            uint32_t incl = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t up = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += up;
+            }
+            const uint32_t total = __shfl(incl, 63, 64);
+            const uint32_t excl = incl - cnt;
+            for (uint32_t win = 0; win < total; win += kWindow) {
+                const uint32_t wend = min(win + kWindow, total);
+                if (excl < wend && excl + cnt > win) {
+                    uint64_t b = word;
+                    uint32_t e = excl;
+                    while (b) {
+                        const int k = __builtin_ctzll(b);
+                        b &= b - 1;
+                        if (e >= win && e < wend) queue[(q_tail + e - win) & (kQueue - 1)] = (uint16_t)(w * 64 + k);
+                        ++e;
+                    }
+                }
+                q_tail += wend - win;
+                __builtin_amdgcn_wave_barrier();
+                while (q_tail - q_head >= 64) {
+                    nms(64);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
         }
-        const uint64_t bal = __ballot(keep);
-        if (lane == 0) keepw[w] = bal;
+        if (q_tail != q_head) nms((int)(q_tail - q_head));
     }
     __syncthreads();
 

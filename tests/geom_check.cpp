@@ -78,6 +78,35 @@ int main(int argc, char** argv)
                 printf("tile columns wrong c=%d o=%d\n", c, o);
                 return 1;
             }
+            // the group scan visits every score pixel exactly once, with the
+            // score index the full test decodes, and its dword reads (the
+            // group, its two neighbours, rows -3 and +3) stay in the tile
+            const int tp = CL.tpitch[o], hs = kpd::box_h(s), ws = kpd::box_w(s);
+            std::vector<int> seen((size_t)ws * hs, 0);
+            const int lo_col = s.x0 - CL.tx0[o], hi_col = s.x1 - CL.tx0[o];
+            const int ngroups = CL.ngx[o] * hs;
+            if (CL.ck_start[o + 1] - CL.ck_start[o] != (ngroups + 63) / 64) {
+                printf("group chunks wrong c=%d o=%d\n", c, o);
+                return 1;
+            }
+            for (int g = 0; g < ngroups; ++g) {
+                const int ry = (int)(((uint64_t)g * CL.gcm[o]) >> 32);
+                if (ry != g / CL.ngx[o]) { printf("group magic wrong c=%d o=%d\n", c, o); return 1; }
+                const int cx = 4 * (CL.gx0[o] + g - ry * CL.ngx[o]);
+                const long P = (long)(ry + 3) * tp + cx;   // relative to the tile start
+                if (P - 4 < 0 || P + 8 > (long)tp * CL.th[o] || P - 3L * tp < 0 || P + 3L * tp + 4 > (long)tp * CL.th[o]) {
+                    printf("group read outside the tile c=%d o=%d g=%d\n", c, o, g);
+                    return 1;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    if (cx + k < lo_col || cx + k >= hi_col) continue;
+                    const int idx = ry * ws + (cx + k - lo_col);
+                    if (idx < 0 || idx >= ws * hs) { printf("group index out of range c=%d o=%d\n", c, o); return 1; }
+                    ++seen[idx];
+                }
+            }
+            for (int v : seen)
+                if (v != 1) { printf("group scan misses or repeats a score pixel c=%d o=%d\n", c, o); return 1; }
         }
     }
     auto interior = [&](int o, int x, int y) { return x >= 3 && y >= 3 && x < w[o] - 3 && y < h[o] - 3; };
