@@ -92,66 +92,155 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
     // the cell changes; dwords straddling a cell column border go byte by
     // byte.
     uint8_t* L0 = sm;
-    const int ndw = T * T / 4;
-    const int cq = tid & (T / 4 - 1);
-    const int gx = x0 + 4 * cq;
-    const int rstep = kFrameBlock >> lgq;   // rows between a thread's dwords
-    const bool straddle = f.sad_on && (gx + 3 >= a.W || colcell[4 * cq] != colcell[4 * cq + 3]);
     uint32_t acc = 0;
     int acc_slot = -1;
-    for (int i0 = tid; i0 < ndw; i0 += B * kFrameBlock) {
-        uint32_t v[B], pv[B];
+    if constexpr (B == 0) {
+        // 128-px tiles: thread (rb, seg) holds rows 4rb..4rb+3, columns
+        // 16seg..16seg+15, so eight lanes read a whole 128-byte row; a row
+        // segment inside the frame and 16-byte aligned is one 16-byte load.
+        // A segment's SAD goes to at most two cells (its first dword's and
+        // its last dword's), summed in registers while the row cell stays.
+        const int rb = tid >> 3, seg = tid & 7;
+        const int cx = 16 * seg;
+        const int gxs = x0 + cx;
+        int cc[4];
+        bool two = true;   // every dword in one cell, the first's or the last's
+        if (f.sad_on) {
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const int ry = (i0 >> lgq) + u * rstep;
-            const int gy = y0 + ry;
-            v[u] = 0;
-            pv[u] = 0;
-            if (ry < T && gy < a.H && gx < a.W) {
-                const uint8_t* src = f.cur + (size_t)gy * f.cur_pitch + gx;
-                if (f.cur_aligned) {
-                    v[u] = *reinterpret_cast<const uint32_t*>(src);
+            for (int d = 0; d < 4; ++d) {
+                cc[d] = colcell[cx + 4 * d];
+                two = two && gxs + 4 * d + 3 < a.W && colcell[cx + 4 * d + 3] == cc[d];
+            }
+            two = two && (cc[1] == cc[0] || cc[1] == cc[3]) && (cc[2] == cc[0] || cc[2] == cc[3]);
+        }
+        uint4 v[4], pv[4];
+        auto load = [&](const uint8_t* row, bool al) -> uint4 {
+            uint4 r = make_uint4(0u, 0u, 0u, 0u);
+            const uint8_t* src = row + gxs;
+            if (al && gxs + 15 < a.W && (reinterpret_cast<uintptr_t>(src) & 15) == 0)
+                return *reinterpret_cast<const uint4*>(src);
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int gx = gxs + 4 * d;
+                if (al && gx + 3 < a.W) {
+                    w[d] = *reinterpret_cast<const uint32_t*>(src + 4 * d);
                 } else {
                     for (int k = 0; k < 4; ++k)
-                        if (gx + k < a.W) v[u] |= (uint32_t)src[k] << (8 * k);
+                        if (gx + k < a.W) w[d] |= (uint32_t)src[4 * d + k] << (8 * k);
                 }
-                if (f.sad_on) {
-                    const uint8_t* ps = f.prev + (size_t)gy * f.prev_pitch + gx;
-                    if (f.prev_aligned) {
-                        pv[u] = *reinterpret_cast<const uint32_t*>(ps);
+            }
+            r.x = w[0]; r.y = w[1]; r.z = w[2]; r.w = w[3];
+            return r;
+        };
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int gy = y0 + 4 * rb + u;
+            v[u] = make_uint4(0u, 0u, 0u, 0u);
+            pv[u] = v[u];
+            if (gy < a.H && gxs < a.W) {
+                v[u] = load(f.cur + (size_t)gy * f.cur_pitch, f.cur_aligned);
+                if (f.sad_on) pv[u] = load(f.prev + (size_t)gy * f.prev_pitch, f.prev_aligned);
+            }
+        }
+        uint32_t accr = 0;   // the segment's second cell
+        int row_slot = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int ry = 4 * rb + u;
+            *reinterpret_cast<uint4*>(L0 + ry * T + cx) = v[u];
+            const int gy = y0 + ry;
+            if (!f.sad_on || gy >= a.H || gxs >= a.W) continue;
+            const int rc = rowcell[ry] * ncx;
+            const uint32_t cw[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+            const uint32_t pw[4] = {pv[u].x, pv[u].y, pv[u].z, pv[u].w};
+            if (two) {
+                if (rc != row_slot) {
+                    if (row_slot >= 0) {
+                        if (acc) atomicAdd(&sadl[row_slot + cc[0]], acc);
+                        if (accr) atomicAdd(&sadl[row_slot + cc[3]], accr);
+                    }
+                    row_slot = rc;
+                    acc = accr = 0;
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const uint32_t sd = __builtin_amdgcn_sad_u8(cw[d], pw[d], 0u);
+                    if (cc[d] == cc[0]) acc += sd;
+                    else accr += sd;
+                }
+            } else {
+                for (int d = 0; d < 4; ++d)
+                    for (int k = 0; k < 4 && gxs + 4 * d + k < a.W; ++k) {
+                        const uint32_t m = 0xFFu << (8 * k);
+                        atomicAdd(&sadl[rc + colcell[cx + 4 * d + k]], __builtin_amdgcn_sad_u8(cw[d] & m, pw[d] & m, 0u));
+                    }
+            }
+        }
+        if (row_slot >= 0) {
+            if (acc) atomicAdd(&sadl[row_slot + cc[0]], acc);
+            if (accr) atomicAdd(&sadl[row_slot + cc[3]], accr);
+        }
+    } else {
+        const int ndw = T * T / 4;
+        const int cq = tid & (T / 4 - 1);
+        const int gx = x0 + 4 * cq;
+        const int rstep = kFrameBlock >> lgq;   // rows between a thread's dwords
+        const bool straddle = f.sad_on && (gx + 3 >= a.W || colcell[4 * cq] != colcell[4 * cq + 3]);
+        for (int i0 = tid; i0 < ndw; i0 += B * kFrameBlock) {
+            uint32_t v[B], pv[B];
+    #pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int ry = (i0 >> lgq) + u * rstep;
+                const int gy = y0 + ry;
+                v[u] = 0;
+                pv[u] = 0;
+                if (ry < T && gy < a.H && gx < a.W) {
+                    const uint8_t* src = f.cur + (size_t)gy * f.cur_pitch + gx;
+                    if (f.cur_aligned) {
+                        v[u] = *reinterpret_cast<const uint32_t*>(src);
                     } else {
                         for (int k = 0; k < 4; ++k)
-                            if (gx + k < a.W) pv[u] |= (uint32_t)ps[k] << (8 * k);
+                            if (gx + k < a.W) v[u] |= (uint32_t)src[k] << (8 * k);
+                    }
+                    if (f.sad_on) {
+                        const uint8_t* ps = f.prev + (size_t)gy * f.prev_pitch + gx;
+                        if (f.prev_aligned) {
+                            pv[u] = *reinterpret_cast<const uint32_t*>(ps);
+                        } else {
+                            for (int k = 0; k < 4; ++k)
+                                if (gx + k < a.W) pv[u] |= (uint32_t)ps[k] << (8 * k);
+                        }
+                    }
+                }
+            }
+    #pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int ry = (i0 >> lgq) + u * rstep;
+                if (ry >= T) continue;
+                *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v[u];
+                const int gy = y0 + ry;
+                if (!f.sad_on || gy >= a.H || gx >= a.W) continue;
+                const int rc = rowcell[ry] * ncx;
+                if (!straddle) {
+                    const int slot = rc + colcell[4 * cq];
+                    const uint32_t d = __builtin_amdgcn_sad_u8(v[u], pv[u], 0u);
+                    if (slot != acc_slot) {
+                        if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
+                        acc_slot = slot;
+                        acc = 0;
+                    }
+                    acc += d;
+                } else {
+                    for (int k = 0; k < 4 && gx + k < a.W; ++k) {
+                        const uint32_t m = 0xFFu << (8 * k);
+                        atomicAdd(&sadl[rc + colcell[4 * cq + k]], __builtin_amdgcn_sad_u8(v[u] & m, pv[u] & m, 0u));
                     }
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const int ry = (i0 >> lgq) + u * rstep;
-            if (ry >= T) continue;
-            *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v[u];
-            const int gy = y0 + ry;
-            if (!f.sad_on || gy >= a.H || gx >= a.W) continue;
-            const int rc = rowcell[ry] * ncx;
-            if (!straddle) {
-                const int slot = rc + colcell[4 * cq];
-                const uint32_t d = __builtin_amdgcn_sad_u8(v[u], pv[u], 0u);
-                if (slot != acc_slot) {
-                    if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
-                    acc_slot = slot;
-                    acc = 0;
-                }
-                acc += d;
-            } else {
-                for (int k = 0; k < 4 && gx + k < a.W; ++k) {
-                    const uint32_t m = 0xFFu << (8 * k);
-                    atomicAdd(&sadl[rc + colcell[4 * cq + k]], __builtin_amdgcn_sad_u8(v[u] & m, pv[u] & m, 0u));
-                }
-            }
-        }
+        if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
     }
-    if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
     __syncthreads();
     if (f.sad_on) {
         for (int i = tid; i < ncx * ncy; i += kFrameBlock) {
@@ -219,12 +308,12 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
 }
 
 // A thread holds T*T/4/kFrameBlock level-0 dwords of its tile: 1, 4 or 16
-// for T = 32, 64, 128, loaded up to 8 at a time.
+// for T = 32, 64, 128 (the last as four 16-byte row segments).
 __device__ __forceinline__ void frame_tile(const FrameArgs& a, const FrameSrc& f, int bx, int by, uint8_t* sm)
 {
     if (a.tile <= 32) frame_tile_b<1>(a, f, bx, by, sm);
     else if (a.tile == 64) frame_tile_b<4>(a, f, bx, by, sm);
-    else frame_tile_b<8>(a, f, bx, by, sm);
+    else frame_tile_b<0>(a, f, bx, by, sm);
 }
 
 // ----------------------------------------------------------------- k_detect
