@@ -164,6 +164,28 @@ def chunk_latency(kpd, s, wl: Workload, reps: int = 3):
     return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
+def host_frames_pass(kpd, wl: Workload, steps: int) -> dict:
+    """Streaming from host memory: every push copies the frame over PCIe
+    into the stream's arena slot (pageable numpy frames)."""
+    import torch
+    s = open_stream(wl, wl.det.id_thresh)
+    frames = [wl.frames[i] for i in range(wl.F)]
+    for i in range(min(wl.F, 20)):
+        kpd.push_frame(s.handle, frames[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        kpd.reset_stream(s.handle)
+        for f in frames:
+            kpd.push_frame(s.handle, f)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    s.close()
+    return {"value": round(wl.F * wl.W * wl.H / dt / 1e6, 2), "unit": "Mpixel/s",
+            "frames_per_s": round(wl.F / dt, 1),
+            "what": "push_frame from pageable host memory (copy included), masked, one frame per call"}
+
+
 def latency_pass(kpd, s, wl: Workload):
     """Per-frame latency push -> keypoints on the host; also collects what
     the algorithmic byte counts need (marked cells, keypoints in them)."""
@@ -660,6 +682,7 @@ def main():
             "masked_over_full": round(masked["mpix_per_s"] / full["mpix_per_s"], 3),
         },
     }
+    out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:
         del wl
         torch.cuda.empty_cache()

@@ -54,6 +54,7 @@ struct Layout {
     size_t off_hdr = 0, off_slot[2] = {0, 0}, off_lvl[KPD_MAX_OCTAVES] = {};
     size_t off_sad[2] = {0, 0}, off_count[2] = {0, 0}, off_offs[2] = {0, 0}, off_list[2] = {0, 0};
     size_t off_mask = 0, off_status = 0, off_colw = 0, off_rowh = 0, off_layouts = 0;
+    size_t off_colmap = 0, off_rowmap = 0;   // cell column / row of every level-0 column / row
     // chunks of consecutive frames (push_frames): K copies of the octaves,
     // per-frame SAD, sparse lists with per-cell counts, count words, marks
     // (cell-major, Kp bytes per cell), dense lists with counts, offsets and
@@ -180,6 +181,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->off_status = off; off = align_up(off + (size_t)L->ncell * 8);
     L->off_colw = off; off = align_up(off + (size_t)L->nc * 2);
     L->off_rowh = off; off = align_up(off + (size_t)L->nr * 2);
+    L->off_colmap = off; off = align_up(off + (size_t)W * 2);
+    L->off_rowmap = off; off = align_up(off + (size_t)H * 2);
     L->off_layouts = off; off = align_up(off + (size_t)L->ncell * sizeof(kpd::CellLayout));
     for (int k = 0; k < 2; ++k) {
         L->off_list[k] = off;
@@ -325,6 +328,8 @@ void chunk_tables(kpd_stream* s, std::vector<kpd::ChunkArgs>* ctab, std::vector<
         fa.sad_slots = L.csad_slots;
         fa.sad_lds_off = kpd::frame_sad_lds_off(L.ctile, L.O);
         fa.sad = s->at<uint32_t>(L.off_csad) + (size_t)j * kc;
+        fa.colmap = s->at<uint16_t>(L.off_colmap);
+        fa.rowmap = s->at<uint16_t>(L.off_rowmap);
 
         kpd::ChunkArgs& c = (*ctab)[j];
         kpd::DetectArgs& d = c.d;
@@ -406,6 +411,15 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         e = hipMemcpyAsync(s->arena + L.off_colw, colw.data(), colw.size() * 2, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_rowh, rowh.data(), rowh.size() * 2, hipMemcpyHostToDevice, s->stream);
+    std::vector<uint16_t> colmap(L.W), rowmap(L.H);
+    for (int x = 0; x < L.W; ++x) colmap[x] = (uint16_t)(((int64_t)x * L.nc) / L.W);
+    for (int y = 0; y < L.H; ++y) rowmap[y] = (uint16_t)(((int64_t)y * L.nr) / L.H);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->arena + L.off_colmap, colmap.data(), colmap.size() * 2, hipMemcpyHostToDevice,
+                           s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->arena + L.off_rowmap, rowmap.data(), rowmap.size() * 2, hipMemcpyHostToDevice,
+                           s->stream);
     std::vector<kpd::CellLayout> layouts(L.ncell);
     for (int c = 0; c < L.ncell; ++c)
         kpd::cell_layout(kpd::cell_rect(c, L.W, L.H, L.nc, L.nr), L.O, L.w, L.h, &layouts[c]);
@@ -518,6 +532,8 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     fa.sad_slots = L.sad_slots;
     fa.sad_lds_off = kpd::frame_sad_lds_off(L.tile, L.O);
     fa.sad = s->at<uint32_t>(L.off_sad[cur_k]);
+    fa.colmap = s->at<uint16_t>(L.off_colmap);
+    fa.rowmap = s->at<uint16_t>(L.off_rowmap);
 
     kpd::DetectArgs& d = t->d;
     d.lvl[0] = cur;

@@ -26,6 +26,8 @@ struct FrameArgs {
     int sad_slots;   // LDS per-cell partial slots (cells a tile can touch)
     int sad_lds_off;
     uint32_t* sad;   // per-cell SAD, accumulated; zero on entry
+    const uint16_t* colmap;   // cell column of every level-0 column (W entries)
+    const uint16_t* rowmap;   // cell row of every level-0 row (H entries)
 };
 
 // The frame-dependent inputs of one tile pass.

@@ -1,31 +1,42 @@
 // gfx950 kernels of the masked multi-scale FAST detector. Two launches per
 // frame of one stream (k_frame1, k_detect1) or per batch tick over many
-// streams (k_frame_batch, k_detect_batch); both pairs run the same bodies:
+// streams (k_frame_batch, k_detect_batch); three or four per chunk of
+// consecutive frames of one stream (k_frame_chunk, then k_mark_chunk and
+// k_detect_list, or k_detect_chunk, then k_compact_chunk). All of them run
+// the same bodies:
 //
 //   frame_tile   one workgroup per level-0 tile, aligned to the coarsest
-//                octave: loads the tile of I_n a dword at a time, builds every
-//                coarser octave of it in LDS by 2x2 box average with
-//                round-half-up (Sec. 2, Sec. 3.1) and writes them out; when
-//                the intensity-difference mask is active it also sums
-//                |I_n - I_{n-1}| per cell (v_sad_u8 per dword, LDS partials,
-//                one atomic per tile and cell) for the per-cell
-//                mean-difference test (Sec. 3.1 Eq. 2, read per cell).
-//   detect_cell  one workgroup per cell, in cell order: decides the cell's
-//                mark (Eq. 2 from the SAD, Eqs. 3-4 from the cell's count in
-//                D_{n-1}); in a marked cell it stages the pixel tiles of every
-//                octave in LDS, runs the segment test and FAST score over the
-//                cell's score boxes, keeps the scale-space maxima (Sec. 2) as
-//                a bitmask and ranks them with popcounts; the counts of
-//                earlier cells give the cell's offset in D_n, where it writes
-//                its new keypoints, or copies its D_{n-1} entries when
-//                unmarked (Eq. 1).
+//                octave: loads the tile of I_n (dwords, or 16-byte row
+//                segments for 128-px tiles), builds every coarser octave of
+//                it in LDS by 2x2 box average with round-half-up (Sec. 2,
+//                Sec. 3.1) and writes them out; when the intensity-difference
+//                mask is active it also sums |I_n - I_{n-1}| per cell
+//                (v_sad_u8 per dword, register and LDS partials, one atomic
+//                per tile and cell) for the per-cell mean-difference test
+//                (Sec. 3.1 Eq. 2, read per cell).
+//   detect_marked  one workgroup per marked cell: stages the pixel tiles of
+//                every octave in LDS, runs the compass pre-test on dword
+//                groups and the segment test and FAST score on the
+//                survivors over the cell's score boxes, keeps the
+//                scale-space maxima (Sec. 2) as a bitmask and ranks them
+//                with popcounts.
+//   detect_cell  (single frames, batch ticks) decides the cell's mark (Eq. 2
+//                from the SAD, Eqs. 3-4 from the cell's count in D_{n-1});
+//                the counts of earlier cells give the cell's offset in D_n,
+//                where it writes its new keypoints, or copies its D_{n-1}
+//                entries when unmarked (Eq. 1).
+//   chunks       write each marked cell's keypoints at a fixed per-cell base
+//                of the frame's sparse list; the compaction pass applies
+//                Eq. 1 across the chunk and builds each frame's D_n in cell
+//                order.
 //
-// The kernel boundary between the two passes publishes the pyramid and the
-// SAD to every XCD at once. Inside the cell pass, a cell only waits for the
-// counts of lower-numbered cells of its stream (relaxed agent-scope count
-// words, no fences); each XCD dispatches its workgroups in index order, so
-// the lowest unfinished cell can always run, and every wait is bounded and
-// sets an error flag instead of hanging.
+// The kernel boundary between passes publishes the pyramid and the SAD to
+// every XCD at once. Inside a single-frame cell pass, a cell only waits for
+// the counts of lower-numbered cells of its stream (relaxed agent-scope
+// count words, no fences); each XCD dispatches its workgroups in index
+// order, so the lowest unfinished cell can always run, and every wait is
+// bounded and sets an error flag instead of hanging. In a chunk, only T_H
+// marking waits, on the same cell's count word of the previous frame.
 #include <hip/hip_runtime.h>
 
 #include "kpd_geom.h"
@@ -71,15 +82,18 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
     uint16_t* colcell = reinterpret_cast<uint16_t*>(sm + a.sad_lds_off + 4 * a.sad_slots);
     uint16_t* rowcell = colcell + T;
     const int xe = min(x0 + T, a.W), ye = min(y0 + T, a.H);
-    const int cx0 = (int)(((int64_t)x0 * a.nc) / a.W);
-    const int cy0 = (int)(((int64_t)y0 * a.nr) / a.H);
-    const int ncx = (int)(((int64_t)(xe - 1) * a.nc) / a.W) - cx0 + 1;
-    const int ncy = (int)(((int64_t)(ye - 1) * a.nr) / a.H) - cy0 + 1;
+    int cx0 = 0, cy0 = 0, ncx = 1, ncy = 1;
     if (f.sad_on) {
+        // cells of the tile's columns and rows from the stream's maps
+        // (column X is in cell column floor(X * Nc / W))
+        cx0 = a.colmap[x0];
+        cy0 = a.rowmap[y0];
+        ncx = a.colmap[xe - 1] - cx0 + 1;
+        ncy = a.rowmap[ye - 1] - cy0 + 1;
         for (int i = tid; i < a.sad_slots; i += kFrameBlock) sadl[i] = 0;
         for (int i = tid; i < T; i += kFrameBlock) {
-            colcell[i] = (uint16_t)(x0 + i < a.W ? (int)(((int64_t)(x0 + i) * a.nc) / a.W) - cx0 : 0);
-            rowcell[i] = (uint16_t)(y0 + i < a.H ? (int)(((int64_t)(y0 + i) * a.nr) / a.H) - cy0 : 0);
+            colcell[i] = (uint16_t)(x0 + i < a.W ? a.colmap[x0 + i] - cx0 : 0);
+            rowcell[i] = (uint16_t)(y0 + i < a.H ? a.rowmap[y0 + i] - cy0 : 0);
         }
     }
     __syncthreads();
