@@ -624,6 +624,7 @@ def main():
         print(json.dumps({"workload": wl.describe(wl.det.id_thresh if masked else -1), "chunk": chunk,
                           "value": round(r["mpix_per_s"], 2), "unit": "Mpixel/s",
                           "frames_per_s": round(r["frames_per_s"], 1),
+                          "latency_ms": {"p50": round(r["lat_p50"], 4), "p99": round(r["lat_p99"], 4)},
                           "roofline": roofline_of(wl, r, masked, stats=stats)}), flush=True)
         return
     K = args.chunk

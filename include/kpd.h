@@ -113,8 +113,10 @@ size_t stream_bytes(int width, int height, const kpd_params* params);
 /* Open a video stream (Sec. 3: the sequence I_0, I_1, ...). `dev_arena` is a
  * device pointer to `arena_bytes` bytes owned by the caller, 256-byte
  * aligned. `hip_stream` is the hipStream_t all work goes to. O and the grid
- * are fixed for the stream's life. Returns KPD_EINVAL for bad parameters,
- * KPD_ENOMEM when arena_bytes < stream_bytes(). */
+ * are fixed for the stream's life. The library allocates no device memory;
+ * it takes a small pinned host buffer (under 40 KB plus a byte per cell) for
+ * reading results back. Returns KPD_EINVAL for bad parameters, KPD_ENOMEM
+ * when arena_bytes < stream_bytes(). */
 int open_stream(int width, int height, const kpd_params* params, void* dev_arena,
                 size_t arena_bytes, void* hip_stream, kpd_stream** out);
 

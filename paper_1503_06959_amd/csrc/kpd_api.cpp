@@ -73,6 +73,7 @@ struct Layout {
 
 // header words
 constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrErr = 3, kHdrWork = 4;
+constexpr size_t kStage = 4096;   // D_n entries staged by get_keypoints
 
 bool valid_params(int W, int H, const kpd_params* p, std::string* why)
 {
@@ -251,6 +252,14 @@ struct kpd_stream {
     int fb_last = 1;          // which of the two single-frame buffers holds the latest D_n
     int chunk_n = 0;          // frames of the last push_frames call
     bool closed = false;
+    // pinned host staging for get_keypoints: header, the first kStage
+    // entries of D_n and the mask come back in one round trip
+    uint8_t* stage = nullptr;
+
+    ~kpd_stream()
+    {
+        if (stage) hipHostFree(stage);
+    }
 
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(arena + off); }
@@ -451,6 +460,9 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
             e = hipMemcpyAsync(s->arena + L.off_ftab, ftab.data(), ftab.size() * sizeof(kpd::FrameArgs),
                                hipMemcpyHostToDevice, s->stream);
     }
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->stage), 64 + kStage * sizeof(kpd_keypoint) + (size_t)L.ncell,
+                          hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         delete s;
@@ -741,23 +753,36 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (!count) return fail(KPD_EINVAL, "count is NULL");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
+    const Layout& L = s->L;
     const int k = s->fb_last;
-    uint32_t hdr[4] = {0, 0, 0, 0};
-    KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(s->L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
+    // one round trip: the header, the first entries of D_n and the mask
+    const size_t pre = std::min(L.list_cap, kStage);
+    uint8_t* st_list = s->stage + 64;
+    uint8_t* st_mask = st_list + kStage * sizeof(kpd_keypoint);
+    KPD_HIP(hipMemcpyAsync(s->stage, s->at<uint32_t>(L.off_hdr), 16, hipMemcpyDeviceToHost, s->stream));
+    KPD_HIP(hipMemcpyAsync(st_list, s->at<kpd_keypoint>(L.off_list[k]), pre * sizeof(kpd_keypoint),
+                           hipMemcpyDeviceToHost, s->stream));
+    if (cell_mask)
+        KPD_HIP(hipMemcpyAsync(st_mask, s->at<uint8_t>(L.off_mask), (size_t)L.ncell, hipMemcpyDeviceToHost,
+                               s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
+    uint32_t hdr[4];
+    std::memcpy(hdr, s->stage, sizeof(hdr));
     if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
     const uint32_t total = hdr[k ? kHdrTotal1 : kHdrTotal0];
     *count = total;
     if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
     if (total > 0) {
         if (!out) return fail(KPD_EINVAL, "out is NULL");
-        KPD_HIP(hipMemcpyAsync(out, s->at<kpd_keypoint>(s->L.off_list[k]), (size_t)total * sizeof(kpd_keypoint),
-                               hipMemcpyDeviceToHost, s->stream));
+        const size_t first = std::min<size_t>(total, pre);
+        std::memcpy(out, st_list, first * sizeof(kpd_keypoint));
+        if (total > first) {
+            KPD_HIP(hipMemcpyAsync(out + first, s->at<kpd_keypoint>(L.off_list[k]) + first,
+                                   (size_t)(total - first) * sizeof(kpd_keypoint), hipMemcpyDeviceToHost, s->stream));
+            KPD_HIP(hipStreamSynchronize(s->stream));
+        }
     }
-    if (cell_mask)
-        KPD_HIP(hipMemcpyAsync(cell_mask, s->at<uint8_t>(s->L.off_mask), (size_t)s->L.ncell,
-                               hipMemcpyDeviceToHost, s->stream));
-    KPD_HIP(hipStreamSynchronize(s->stream));
+    if (cell_mask) std::memcpy(cell_mask, st_mask, (size_t)L.ncell);
     return KPD_OK;
 }
 

@@ -281,6 +281,7 @@ class Stream:
         self.stream = stream
         self.handle = open_stream(width, height, params, self.arena, stream)
         self._held = [None, None]
+        self._out = None
 
     def push(self, frame, retain: bool = False) -> None:
         push_frame(self.handle, frame, retain)
@@ -299,7 +300,19 @@ class Stream:
         set_thresholds(self.handle, fast_t, id_thresh, kb_thresh)
 
     def keypoints(self) -> Tuple[np.ndarray, np.ndarray]:
-        return get_keypoints(self.handle, self.n_cells)
+        """D_n (a copy) and M_n of the last push."""
+        if self._out is None:
+            self._out = np.zeros(4096, KEYPOINT_DTYPE)
+        mask = np.zeros(self.n_cells, np.uint8)
+        cnt = ctypes.c_size_t()
+        rc = lib.get_keypoints(self.handle, self._out.ctypes.data, len(self._out), ctypes.byref(cnt),
+                               mask.ctypes.data)
+        if rc == KPD_ETRUNC:
+            self._out = np.zeros(cnt.value, KEYPOINT_DTYPE)
+            rc = lib.get_keypoints(self.handle, self._out.ctypes.data, len(self._out), ctypes.byref(cnt),
+                                   mask.ctypes.data)
+        _check(rc)
+        return self._out[:cnt.value].copy(), mask
 
     def cell_stats(self):
         return cell_stats(self.handle, self.n_cells)
