@@ -6,9 +6,13 @@ tensor per stream) and HIP streams. ``torch`` is imported before the library
 is loaded so that both use the same HIP runtime.
 
 The functions carry the C names: ``stream_bytes``, ``open_stream``,
-``set_thresholds``, ``push_frame``, ``get_keypoints``, ``close_stream``, plus
-the inspection calls ``cell_stats``, ``pyramid_level`` and ``device_result``.
-``Stream`` wraps them for one video stream.
+``set_thresholds``, ``push_frame``, ``push_frames`` (a chunk of consecutive
+frames), ``get_keypoints``, ``get_chunk_keypoints``, ``close_stream``,
+``reset_stream``, the batch calls (``open_batch``, ``batch_attach``,
+``batch_push``, ``batch_tick``, ``batch_gather``, ...), plus the inspection
+calls ``cell_stats``, ``pyramid_level``, ``device_result``,
+``chunk_result`` and ``profile``/``profile_read``. ``Stream`` wraps them for
+one video stream.
 """
 from __future__ import annotations
 
