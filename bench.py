@@ -408,7 +408,7 @@ def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
         "workload": f"64 streams (24 x 320x240, 24 x 640x480, 16 x 1280x720), {clip}-frame clips played "
                     f"forward and back, {n_ticks} timed ticks, T_I=8, per-resolution presets",
         "batched": {"mpix_per_s": round(px_per_tick / sec_b / 1e6, 2), "frames_per_s": round(64 / sec_b, 1),
-                    "ms_per_tick": round(sec_b * 1e3, 4), "launches_per_tick": 2, "hip_graph": True,
+                    "ms_per_tick": round(sec_b * 1e3, 4), "launches_per_tick": 4, "hip_graph": True,
                     "tiles": tiles},
         "plain_per_stream": {"mpix_per_s": round(px_per_tick / sec_p / 1e6, 2),
                              "frames_per_s": round(64 / sec_p, 1), "ms_per_tick": round(sec_p * 1e3, 4),

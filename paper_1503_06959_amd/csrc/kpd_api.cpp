@@ -55,6 +55,8 @@ struct Layout {
     size_t off_sad[2] = {0, 0}, off_count[2] = {0, 0}, off_offs[2] = {0, 0}, off_list[2] = {0, 0};
     size_t off_mask = 0, off_status = 0, off_colw = 0, off_rowh = 0, off_layouts = 0;
     size_t off_colmap = 0, off_rowmap = 0;   // cell column / row of every level-0 column / row
+    // batch ticks: marked cells' keypoints at fixed per-cell bases, and counts
+    size_t off_sparse1 = 0, off_own1 = 0;
     // chunks of consecutive frames (push_frames): K copies of the octaves,
     // per-frame SAD, sparse lists with per-cell counts, count words, marks
     // (cell-major, Kp bytes per cell), dense lists with counts, offsets and
@@ -189,6 +191,9 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_list[k] = off;
         off = align_up(off + L->list_cap * sizeof(kpd_keypoint));
     }
+    L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
+    L->off_own1 = off; off = align_up(off + (size_t)L->ncell * 4);
+    L->off_sparse1 = off; off = align_up(off + L->list_cap * sizeof(kpd_keypoint));
     if (L->K > 1) {
         const size_t kc = (size_t)L->K * L->ncell;
         L->off_csad = off; off = align_up(off + kc * 4);
@@ -199,7 +204,6 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->Kp = (L->K + 15) / 16 * 16;
         L->off_marks = off; off = align_up(off + (size_t)L->ncell * L->Kp);
         L->off_own = off; off = align_up(off + kc * 4);
-        L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
         L->off_work = off; off = align_up(off + kc * 4);
         L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
         L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
@@ -435,7 +439,16 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_layouts, layouts.data(), layouts.size() * sizeof(kpd::CellLayout),
                            hipMemcpyHostToDevice, s->stream);
-    std::vector<uint32_t> cbase;
+    std::vector<uint32_t> cbase(L.ncell);
+    {
+        uint32_t acc = 0;
+        for (int c = 0; c < L.ncell; ++c) {
+            cbase[c] = acc;
+            for (int o = 0; o < L.O; ++o) acc += (uint32_t)kpd::decision_capacity(layouts[c].dec[o]);
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice, s->stream);
     std::vector<kpd::ChunkArgs> ctab;
     std::vector<kpd::FrameArgs> ftab;
     if (L.K > 1) {
@@ -443,15 +456,6 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
             e = hipMemsetAsync(s->arena + L.off_csad, 0, (size_t)L.K * L.ncell * 4, s->stream);
         if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_cntw, 0, (size_t)L.K * L.ncell * 8, s->stream);
         if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_marks, 0, (size_t)L.ncell * L.Kp, s->stream);
-        cbase.resize(L.ncell);
-        uint32_t acc = 0;
-        for (int c = 0; c < L.ncell; ++c) {
-            cbase[c] = acc;
-            for (int o = 0; o < L.O; ++o) acc += (uint32_t)kpd::decision_capacity(layouts[c].dec[o]);
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice,
-                               s->stream);
         chunk_tables(s, &ctab, &ftab);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->arena + L.off_ctab, ctab.data(), ctab.size() * sizeof(kpd::ChunkArgs),
@@ -546,6 +550,9 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     fa.sad = s->at<uint32_t>(L.off_sad[cur_k]);
     fa.colmap = s->at<uint16_t>(L.off_colmap);
     fa.rowmap = s->at<uint16_t>(L.off_rowmap);
+    t->sparse = s->at<kpd_keypoint>(L.off_sparse1);
+    t->sparse_base = s->at<uint32_t>(L.off_cbase);
+    t->own_count = s->at<uint32_t>(L.off_own1);
 
     kpd::DetectArgs& d = t->d;
     d.lvl[0] = cur;
@@ -868,6 +875,8 @@ struct kpd_batch {
     kpd::TickArgs* dev_table[2] = {nullptr, nullptr};
     uint16_t* dev_fmap = nullptr;
     uint16_t* dev_cmap = nullptr;
+    uint32_t* dev_work = nullptr;         // marked cells of a tick (global cell indices)
+    uint32_t* dev_work_count = nullptr;   // their number, cleared by the compaction pass
     kpd::TickArgs* host_table[2] = {nullptr, nullptr};  // pinned
     hipEvent_t table_free[2] = {nullptr, nullptr};      // upload of host_table[k] done
     bool table_used[2] = {false, false};
@@ -883,13 +892,18 @@ struct kpd_batch {
 
 namespace {
 
-size_t batch_layout(int max_streams, int max_blocks, size_t* off_table, size_t* off_fmap, size_t* off_cmap)
+// Batch scratch: two tick tables, the workgroup -> stream maps of the tile
+// and cell passes, the work list of marked cells and its counter.
+size_t batch_layout(int max_streams, int max_blocks, size_t* off_table, size_t* off_fmap, size_t* off_cmap,
+                    size_t* off_work = nullptr)
 {
     size_t off = 0;
     off_table[0] = off; off = align_up(off + (size_t)max_streams * sizeof(kpd::TickArgs));
     off_table[1] = off; off = align_up(off + (size_t)max_streams * sizeof(kpd::TickArgs));
     *off_fmap = off; off = align_up(off + (size_t)max_blocks * 2);
     *off_cmap = off; off = align_up(off + (size_t)max_blocks * 2);
+    if (off_work) *off_work = off;
+    off = align_up(off + 256 + (size_t)max_blocks * 4);   // counter, then the list
     return off;
 }
 
@@ -927,7 +941,8 @@ int rebuild_maps(kpd_batch* b)
     return KPD_OK;
 }
 
-// Enqueue one tick reading table k: upload, tile pass, cell pass.
+// Enqueue one tick reading table k: upload, tile pass, mark pass, detection
+// of the marked cells, compaction of every stream's D_n.
 hipError_t enqueue_tick(kpd_batch* b, int k)
 {
     const size_t n = b->streams.size();
@@ -936,7 +951,13 @@ hipError_t enqueue_tick(kpd_batch* b, int k)
     if (e == hipSuccess && b->frame_blocks)
         e = kpd::launch_frame_batch(b->dev_table[k], b->dev_fmap, b->frame_blocks, b->frame_lds, b->stream);
     if (e == hipSuccess && b->cell_blocks)
-        e = kpd::launch_detect_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->detect_lds, b->stream);
+        e = kpd::launch_mark_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->dev_work, b->dev_work_count,
+                                   b->stream);
+    if (e == hipSuccess && b->cell_blocks)
+        e = kpd::launch_detect_list_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->dev_work,
+                                          b->dev_work_count, b->detect_lds, b->stream);
+    if (e == hipSuccess && n)
+        e = kpd::launch_compact_batch(b->dev_table[k], (int)n, b->dev_work_count, b->stream);
     return e;
 }
 
@@ -957,8 +978,8 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
     if (!out) return fail(KPD_EINVAL, "out is NULL");
     *out = nullptr;
     if (max_streams < 1 || max_streams > 65535 || max_blocks < 1) return fail(KPD_EINVAL, "bad batch capacity");
-    size_t t[2], f, c;
-    const size_t need = batch_layout(max_streams, max_blocks, t, &f, &c);
+    size_t t[2], f, c, w;
+    const size_t need = batch_layout(max_streams, max_blocks, t, &f, &c, &w);
     if (!dev_scratch || reinterpret_cast<uintptr_t>(dev_scratch) % kAlign)
         return fail(KPD_EINVAL, "scratch is NULL or not 256-byte aligned");
     if (scratch_bytes < need) return fail(KPD_ENOMEM, "batch scratch too small");
@@ -972,7 +993,10 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
     for (int k = 0; k < 2; ++k) b->dev_table[k] = reinterpret_cast<kpd::TickArgs*>(b->scratch + t[k]);
     b->dev_fmap = reinterpret_cast<uint16_t*>(b->scratch + f);
     b->dev_cmap = reinterpret_cast<uint16_t*>(b->scratch + c);
-    hipError_t e = hipSuccess;
+    b->dev_work_count = reinterpret_cast<uint32_t*>(b->scratch + w);
+    b->dev_work = reinterpret_cast<uint32_t*>(b->scratch + w + 256);
+    hipError_t e = hipMemsetAsync(b->dev_work_count, 0, 4, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
         e = hipHostMalloc(reinterpret_cast<void**>(&b->host_table[k]), (size_t)max_streams * sizeof(kpd::TickArgs),
                           hipHostMallocDefault);

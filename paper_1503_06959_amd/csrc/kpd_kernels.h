@@ -78,6 +78,11 @@ struct TickArgs {
     int active;     // the stream has a frame in this tick
     int f_on;       // the tile pass runs (pyramid or SAD needed)
     int tile_base, cell_base;
+    // marked cells' keypoints at fixed per-cell bases of a sparse list, and
+    // their counts; the tick's compaction pass builds D_n from them
+    kpd_keypoint* sparse;
+    const uint32_t* sparse_base;
+    uint32_t* own_count;
 };
 
 // A chunk of consecutive frames of one stream, in two passes after the
@@ -168,7 +173,10 @@ hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStrea
 hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, uint32_t out_cap, uint32_t* counts,
                                hipStream_t s);
-hipError_t launch_detect_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes,
-                               hipStream_t s);
+hipError_t launch_mark_batch(const TickArgs* table, const uint16_t* map, int ncells, uint32_t* work,
+                             uint32_t* work_count, hipStream_t s);
+hipError_t launch_detect_list_batch(const TickArgs* table, const uint16_t* map, int ncells, const uint32_t* work,
+                                    const uint32_t* work_count, int lds_bytes, hipStream_t s);
+hipError_t launch_compact_batch(const TickArgs* table, int n, uint32_t* work_count, hipStream_t s);
 
 }  // namespace kpd

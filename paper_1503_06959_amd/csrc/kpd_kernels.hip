@@ -1,9 +1,9 @@
 // gfx950 kernels of the masked multi-scale FAST detector. Two launches per
-// frame of one stream (k_frame1, k_detect1) or per batch tick over many
-// streams (k_frame_batch, k_detect_batch); three or four per chunk of
-// consecutive frames of one stream (k_frame_chunk, then k_mark_chunk and
-// k_detect_list, or k_detect_chunk, then k_compact_chunk). All of them run
-// the same bodies:
+// frame of one stream (k_frame1, k_detect1); four per batch tick over many
+// streams (k_frame_batch, k_mark_batch, k_detect_list_batch,
+// k_compact_batch); three or four per chunk of consecutive frames of one
+// stream (k_frame_chunk, then k_mark_chunk and k_detect_list, or
+// k_detect_chunk, then k_compact_chunk). All of them run the same bodies:
 //
 //   frame_tile   one workgroup per level-0 tile, aligned to the coarsest
 //                octave: loads the tile of I_n (dwords, or 16-byte row
@@ -25,10 +25,10 @@
 //                the counts of earlier cells give the cell's offset in D_n,
 //                where it writes its new keypoints, or copies its D_{n-1}
 //                entries when unmarked (Eq. 1).
-//   chunks       write each marked cell's keypoints at a fixed per-cell base
-//                of the frame's sparse list; the compaction pass applies
-//                Eq. 1 across the chunk and builds each frame's D_n in cell
-//                order.
+//   chunks and batch ticks
+//                write each marked cell's keypoints at a fixed per-cell base
+//                of a sparse list; a compaction pass (compact_frame) applies
+//                Eq. 1 and builds each frame's D_n in cell order.
 //
 // The kernel boundary between passes publishes the pyramid and the SAD to
 // every XCD at once. Inside a single-frame cell pass, a cell only waits for
@@ -1047,59 +1047,30 @@ __global__ __launch_bounds__(kBlk) void k_detect_list(const ChunkArgs* table, Ch
 constexpr int kCompact = 512;
 constexpr int kMaxChunk = KPD_MAX_CHUNK;
 
-__global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
+// Compaction core, one workgroup per frame: cells in tiles of kCompact.
+// source(c, &n, &src) gives cell c's count and the address of its first
+// entry (and may record per-cell side results); the counts' exclusive
+// prefix is the cell's offset in D_n, and a flat copy (each entry finds its
+// cell by binary search in LDS) writes D_n in cell order. Writes the counts,
+// offsets and total of D_n. A source whose entries would leave their list
+// has been clamped by source().
+template <class Source>
+__device__ void compact_frame(int ncell, uint32_t list_cap, kpd_keypoint* dst, uint32_t* cnt_out,
+                              uint32_t* off_out, uint32_t* total_out, Source&& source)
 {
-    __shared__ uint32_t s_excl[kCompact], s_src[kCompact], s_wsum[kCompact / 64];
-    __shared__ int s_frame[kCompact];
+    __shared__ uint32_t s_excl[kCompact], s_wsum[kCompact / 64];
+    __shared__ const kpd_keypoint* s_src[kCompact];
     __shared__ uint32_t s_base;
-    const int j = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool last = j == a.last;
-    const size_t jc = (size_t)j * a.ncell;
-    kpd_keypoint* dst = last ? a.next_list : a.lists + (size_t)j * a.list_stride;
-    uint32_t* cnt_out = last ? a.next_count : a.counts + jc;
-    uint32_t* off_out = last ? a.next_offs : a.offs + jc;
     if (tid == 0) s_base = 0;
     __syncthreads();
-
-    for (int c0 = 0; c0 < a.ncell; c0 += kCompact) {
+    for (int c0 = 0; c0 < ncell; c0 += kCompact) {
         const int c = c0 + tid;
-        const int ntile = min(kCompact, a.ncell - c0);
+        const int ntile = min(kCompact, ncell - c0);
         const uint32_t base = s_base;
-        uint32_t n = 0, src = 0;
-        int f = -1;
-        if (c < a.ncell) {
-            // the newest frame <= j that marked this cell: mark bytes (0 or
-            // 1) 16 frames per load, all loads issued before any is used
-            const uint4* m16 = reinterpret_cast<const uint4*>(a.marks + (size_t)c * a.K);
-            const int qj = j >> 4;
-#pragma unroll
-            for (int q0 = 0; q0 < kMaxChunk / 16; q0 += 4) {
-                if (q0 > qj) break;
-                uint4 w[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (q0 + u <= qj) w[u] = m16[q0 + u];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (q0 + u > qj) break;
-                    const uint32_t d[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
-                    uint32_t b = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        b |= ((d[k] & 1u) | ((d[k] >> 7) & 2u) | ((d[k] >> 14) & 4u) | ((d[k] >> 21) & 8u)) << (4 * k);
-                    if (q0 + u == qj) b &= (2u << (j & 15)) - 1u;
-                    if (b) f = 16 * (q0 + u) + 31 - __clz(b);
-                }
-            }
-            if (f >= 0) {
-                n = a.own_count[(size_t)f * a.ncell + c];
-                src = a.cell_base[c];
-            } else {
-                n = a.prev_count[c];
-                src = a.prev_offs[c];
-            }
-        }
+        uint32_t n = 0;
+        const kpd_keypoint* src = nullptr;
+        if (c < ncell) source(c, &n, &src);
         uint32_t incl = n;
         for (int d = 1; d < 64; d <<= 1) {
             const uint32_t v = __shfl_up(incl, d);
@@ -1112,15 +1083,9 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
         const uint32_t excl = base + wbase + incl - n;
         s_excl[tid] = excl;
         s_src[tid] = src;
-        s_frame[tid] = f;
-        if (c < a.ncell) {
+        if (c < ncell) {
             cnt_out[c] = n;
             off_out[c] = excl;
-            if (last) {
-                a.sad_stats[c] = a.sad_chunk[jc + c];
-                a.sad_single_next[c] = 0;
-            }
-            a.sad_chunk[jc + c] = 0;
         }
         __syncthreads();
         // every thread needs the tile's end: the last cell's thread publishes it
@@ -1134,17 +1099,71 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
                 if (s_excl[mid] <= d) lo = mid;
                 else hi = mid - 1;
             }
-            const int sf = s_frame[lo];
-            const kpd_keypoint* sp = sf >= 0 ? a.sparse + (size_t)sf * a.list_stride : a.prev_list;
-            const uint32_t so = s_src[lo] + (d - s_excl[lo]);
-            if (so < a.list_cap && d < a.list_cap) dst[d] = sp[so];
+            if (d < list_cap) dst[d] = s_src[lo][d - s_excl[lo]];
         }
         __syncthreads();
         if (tid == 0) s_base = t1;
         __syncthreads();
     }
-    if (tid == 0) *(last ? a.next_total : a.totals + j) = s_base;
-    if (j == 0 && tid == 0) *a.work_count = 0;
+    if (tid == 0) *total_out = s_base;
+}
+
+// Entries of a cell that stay inside their list of `cap` entries.
+__device__ __forceinline__ uint32_t clamp_count(uint32_t off, uint32_t n, uint32_t cap)
+{
+    return off >= cap ? 0u : min(n, cap - off);
+}
+
+__global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
+{
+    const int j = blockIdx.x;
+    const bool last = j == a.last;
+    const size_t jc = (size_t)j * a.ncell;
+    kpd_keypoint* dst = last ? a.next_list : a.lists + (size_t)j * a.list_stride;
+    uint32_t* cnt_out = last ? a.next_count : a.counts + jc;
+    uint32_t* off_out = last ? a.next_offs : a.offs + jc;
+    compact_frame(a.ncell, a.list_cap, dst, cnt_out, off_out, last ? a.next_total : a.totals + j,
+                  [&](int c, uint32_t* n, const kpd_keypoint** src) {
+        // the newest frame <= j that marked this cell: mark bytes (0 or 1)
+        // 16 frames per load, all loads issued before any is used
+        const uint4* m16 = reinterpret_cast<const uint4*>(a.marks + (size_t)c * a.K);
+        const int qj = j >> 4;
+        int f = -1;
+#pragma unroll
+        for (int q0 = 0; q0 < kMaxChunk / 16; q0 += 4) {
+            if (q0 > qj) break;
+            uint4 w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q0 + u <= qj) w[u] = m16[q0 + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (q0 + u > qj) break;
+                const uint32_t d[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+                uint32_t b = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    b |= ((d[k] & 1u) | ((d[k] >> 7) & 2u) | ((d[k] >> 14) & 4u) | ((d[k] >> 21) & 8u)) << (4 * k);
+                if (q0 + u == qj) b &= (2u << (j & 15)) - 1u;
+                if (b) f = 16 * (q0 + u) + 31 - __clz(b);
+            }
+        }
+        if (f >= 0) {
+            const uint32_t off = a.cell_base[c];
+            *n = clamp_count(off, a.own_count[(size_t)f * a.ncell + c], a.list_cap);
+            *src = a.sparse + (size_t)f * a.list_stride + off;
+        } else {
+            const uint32_t off = a.prev_offs[c];
+            *n = clamp_count(off, a.prev_count[c], a.list_cap);
+            *src = a.prev_list + off;
+        }
+        if (last) {
+            a.sad_stats[c] = a.sad_chunk[jc + c];
+            a.sad_single_next[c] = 0;
+        }
+        a.sad_chunk[jc + c] = 0;
+    });
+    if (j == 0 && threadIdx.x == 0) *a.work_count = 0;
 }
 
 // One batch tick: workgroup b works for stream map[b] (streams' workgroups
@@ -1163,12 +1182,87 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame_batch(const TickArgs* tab
     frame_tile(a, f, local % a.tiles_x, local / a.tiles_x, sm);
 }
 
-__global__ __launch_bounds__(kBlk) void k_detect_batch(const TickArgs* table, const uint16_t* map)
+
+// A batch tick in four passes after the tile pass's: marks of every cell
+// of every active stream with the marked cells listed, detection of the
+// listed cells into per-stream sparse lists, and compaction of each
+// stream's D_n (Eq. 1). D_{n-1} is final before the tick, so the marks need
+// no waits.
+__global__ __launch_bounds__(kMarkBlock) void k_mark_batch(const TickArgs* table, const uint16_t* map, int ncells,
+                                                           uint32_t* work, uint32_t* work_count)
+{
+    __shared__ uint32_t s_count, s_base;
+    const int g = blockIdx.x * kMarkBlock + threadIdx.x;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    bool mark = false;
+    if (g < ncells) {
+        const TickArgs& t = table[map[g]];
+        if (t.active) {
+            const int c = g - t.cell_base;
+            mark = cell_marked(t.d, c);
+            t.d.mask[c] = (uint8_t)mark;
+            t.d.sad_next[c] = 0;
+        }
+    }
+    const uint64_t bal = __ballot(mark);
+    const int lane = threadIdx.x & 63;
+    const int leader = bal ? __builtin_ctzll(bal) : 0;
+    uint32_t wbase = 0;
+    if (bal && lane == leader) wbase = atomicAdd(&s_count, (uint32_t)__popcll(bal));
+    wbase = __shfl(wbase, leader);
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_count ? atomicAdd(work_count, s_count) : 0;
+    __syncthreads();
+    if (mark) {
+        const unsigned below =
+            __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+        work[s_base + wbase + below] = (uint32_t)g;
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_detect_list_batch(const TickArgs* table, const uint16_t* map,
+                                                            const uint32_t* work, const uint32_t* work_count)
 {
     extern __shared__ __align__(16) uint8_t sm[];
-    const TickArgs& t = table[map[blockIdx.x]];
-    if (!t.active) return;
-    detect_cell(t.d, (int)blockIdx.x - t.cell_base, sm);
+    __shared__ CellLayout L;
+    __shared__ uint32_t s_n;
+    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
+    __shared__ int s_pitch[KPD_MAX_OCTAVES];
+    const uint32_t n = *work_count;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const int g = (int)work[it];
+        const TickArgs& t = table[map[g]];
+        const DetectArgs& a = t.d;
+        const int c = g - t.cell_base;
+        if (threadIdx.x == 0) load_level_ptrs(a, s_lvl, s_pitch);
+        __syncthreads();
+        detect_marked(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n);
+        if (threadIdx.x == 0) t.own_count[c] = s_n;
+        emit_marked(a, L, sm, t.sparse_base[c], t.sparse, a.list_cap);
+        __syncthreads();   // L and the LDS maps are reused by the next item
+    }
+}
+
+__global__ __launch_bounds__(kCompact) void k_compact_batch(const TickArgs* table, uint32_t* work_count)
+{
+    const TickArgs& t = table[blockIdx.x];
+    if (t.active) {
+        const DetectArgs& a = t.d;
+        compact_frame(a.nc * a.nr, a.list_cap, a.list_cur, a.count_cur, a.off_cur, a.total_cur,
+                      [&](int c, uint32_t* n, const kpd_keypoint** src) {
+            if (a.mask[c]) {
+                const uint32_t off = t.sparse_base[c];
+                *n = clamp_count(off, t.own_count[c], a.list_cap);
+                *src = t.sparse + off;
+            } else {
+                const uint32_t off = a.off_prev[c];
+                *n = clamp_count(off, a.count_prev[c], a.list_cap);
+                *src = a.list_prev + off;
+            }
+        });
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *work_count = 0;
 }
 
 // Concatenate the D_n of every active stream of a tick table (one workgroup
@@ -1222,10 +1316,10 @@ hipError_t set_detect_lds_limit(int lds_bytes)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_list), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_bytes);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_chunk), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lds_bytes);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_list_batch),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_batch),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_chunk),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
 }
 
@@ -1284,11 +1378,27 @@ hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nb
     return hipGetLastError();
 }
 
-hipError_t launch_detect_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes,
-                               hipStream_t s)
+hipError_t launch_mark_batch(const TickArgs* table, const uint16_t* map, int ncells, uint32_t* work,
+                             uint32_t* work_count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect_batch, dim3(nblocks), dim3(kBlk), lds_bytes, s, table, map);
+    hipLaunchKernelGGL(k_mark_batch, dim3((ncells + kMarkBlock - 1) / kMarkBlock), dim3(kMarkBlock), 0, s, table, map,
+                       ncells, work, work_count);
     return hipGetLastError();
 }
+
+hipError_t launch_detect_list_batch(const TickArgs* table, const uint16_t* map, int ncells, const uint32_t* work,
+                                    const uint32_t* work_count, int lds_bytes, hipStream_t s)
+{
+    const int grid = ncells < 1024 ? ncells : 1024;
+    hipLaunchKernelGGL(k_detect_list_batch, dim3(grid), dim3(kBlk), lds_bytes, s, table, map, work, work_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_batch(const TickArgs* table, int n, uint32_t* work_count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact_batch, dim3(n), dim3(kCompact), 0, s, table, work_count);
+    return hipGetLastError();
+}
+
 
 }  // namespace kpd
