@@ -54,6 +54,7 @@ def lib() -> ctypes.CDLL:
     L.orc_close.restype = None
     L.orc_set_thresholds.argtypes = [P, ctypes.c_int, i32, u32]
     L.orc_reset.argtypes = [P]
+    L.orc_set_id_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.orc_push.argtypes = [P, P]
     L.orc_get.argtypes = [P, P, ctypes.c_int, P, P, P]
     _lib = L
@@ -137,6 +138,11 @@ class Stream:
 
     def reset(self):
         lib().orc_reset(self.h)
+
+    def set_id_mode(self, mode: int, layer: int = 0):
+        """0: per-cell mean difference at level 0; 1: per-pixel difference on
+        pyramid layer `layer`, Eq. 1 per feature position."""
+        assert lib().orc_set_id_mode(self.h, mode, layer) == 0
 
     def push(self, frame: np.ndarray) -> int:
         frame = np.ascontiguousarray(frame, dtype=np.uint8)

@@ -48,6 +48,21 @@
  *   R8  Eq. (1): D_n is the full-frame detection of I_n restricted to marked
  *       cells together with D_{n-1} restricted to unmarked cells, listed by
  *       cell (row-major), then octave, then y, then x.
+ *
+ * A second mask mode follows Sec. 3.1 literally (one mask for all octaves,
+ * option ii, built on a chosen pyramid layer; Sec. 4 uses the top layer):
+ *   R9  The pixel (k,l) of layer L is changed when |L_n(k,l) - L_{n-1}(k,l)|
+ *       exceeds T_I (Eq. 2 with the polarity of R7). The mask is upsampled to
+ *       level 0 by replication: level-0 pixel (X,Y) takes the value of layer
+ *       pixel (X >> L, Y >> L), clamped to the layer's last column and row
+ *       for the strip that halving by floor leaves uncovered.
+ *   R10 Eq. (1) is applied per feature: a feature at level o, (x,y), sits at
+ *       level-0 position p = (x<<o, y<<o) (R6); M_n(p) = 1 when p's layer
+ *       pixel changed or p's cell has at least T_H features of D_{n-1}
+ *       (Eq. 4, per cell as in R7). D_n holds the features of F(I_n) with
+ *       M_n(p) = 1 and those of D_{n-1} with M_n(p) = 0, in the order of R8.
+ *       The per-cell mask reported is 1 for a cell marked by T_H or holding
+ *       any level-0 pixel whose layer pixel changed.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -253,6 +268,8 @@ typedef struct {
     uint32_t TH;
     int n_frames;
     int force_all;
+    int id_mode;         /* 0: per-cell mean at level 0 (R7); 1: per-pixel on a layer (R9, R10) */
+    int id_layer;
     uint8_t* prev;       /* I_{n-1} */
     orc_kp* K;           /* D_{n-1}, then D_n */
     int nK;
@@ -294,6 +311,16 @@ int orc_set_thresholds(orc_stream* s, int t, int32_t TI, uint32_t TH)
     return 0;
 }
 
+/* Mask mode from the next frame on: 0 = R7, 1 = R9/R10 on pyramid layer
+ * `layer` (0..O-1). */
+int orc_set_id_mode(orc_stream* s, int mode, int layer)
+{
+    if (mode < 0 || mode > 1 || layer < 0 || layer >= s->O) return -1;
+    s->id_mode = mode;
+    s->id_layer = layer;
+    return 0;
+}
+
 /* A reset (a scene cut signalled by the caller) treats the next frame like
  * the first one: every cell is detected. */
 int orc_reset(orc_stream* s)
@@ -317,14 +344,48 @@ static int kp_cmp(const void* a, const void* b)
     return 0;
 }
 
-/* One frame: detection mask (Eqs. 2-4 as read in R7), full detection F(I_n),
- * and Eq. (1). */
+/* R10: M_n at the level-0 position of feature k (the cell mask of s holds
+ * the T_H test at this point). */
+static int pixel_mask(const orc_stream* s, const uint8_t* pix, int lw, int lh, const orc_kp* k)
+{
+    const int X = k->x << k->octave, Y = k->y << k->octave;
+    int kx = X >> s->id_layer, ly = Y >> s->id_layer;
+    if (kx > lw - 1) kx = lw - 1;
+    if (ly > lh - 1) ly = lh - 1;
+    if (pix[ly * lw + kx]) return 1;
+    return s->mask[orc_cell_of(k->x, k->y, k->octave, s->W, s->H, s->Nc, s->Nr)] != 0;
+}
+
+/* One frame: detection mask (Eqs. 2-4 as read in R7, or R9/R10), full
+ * detection F(I_n), and Eq. (1). */
 int orc_push(orc_stream* s, const uint8_t* frame)
 {
     const int W = s->W, H = s->H, Nc = s->Nc, Nr = s->Nr;
     const int ncell = Nc * Nr;
 
     /* detection mask M_n */
+    uint8_t* pix = NULL;     /* R9: changed pixels of the layer */
+    int lw = 0, lh = 0, L = s->id_layer;
+    if (s->id_mode == 1 && !s->force_all) {
+        int ws[32], hs[32];
+        orc_level_dims(W, H, L + 1, ws, hs);
+        lw = ws[L];
+        lh = hs[L];
+        size_t tot = 0;
+        for (int o = 0; o <= L; ++o) tot += (size_t)ws[o] * hs[o];
+        uint8_t* pc = (uint8_t*)malloc(tot);
+        uint8_t* pp = (uint8_t*)malloc(tot);
+        orc_pyramid(frame, W, H, L + 1, pc);
+        orc_pyramid(s->prev, W, H, L + 1, pp);
+        const size_t off = tot - (size_t)lw * lh;
+        pix = (uint8_t*)malloc((size_t)lw * lh);
+        for (int i = 0; i < lw * lh; ++i) {
+            int d = (int)pc[off + i] - (int)pp[off + i];
+            pix[i] = (uint8_t)((d < 0 ? -d : d) > s->TI);
+        }
+        free(pc);
+        free(pp);
+    }
     if (s->force_all) {
         for (int c = 0; c < ncell; ++c) { s->mask[c] = 1; s->sad[c] = 0; }
     } else {
@@ -346,6 +407,12 @@ int orc_push(orc_stream* s, const uint8_t* frame)
             int kb = hist[c] >= s->TH;                         /* Eq. (4) */
             s->mask[c] = (uint8_t)(id || kb);
         }
+        if (pix) {
+            /* R10: the cell mask is the T_H test; the reported mask also
+             * flags cells with a changed layer pixel */
+            for (int c = 0; c < ncell; ++c) s->mask[c] = (uint8_t)(hist[c] >= s->TH);
+            for (int c = 0; c < ncell; ++c) s->sad[c] = 0;
+        }
         free(area);
         free(hist);
     }
@@ -355,13 +422,29 @@ int orc_push(orc_stream* s, const uint8_t* frame)
     int nF = orc_detect(frame, W, H, s->t, s->O, F, s->capK);
     if (nF < 0) { free(F); return -1; }
 
-    /* Eq. (1): new features in marked cells, previous ones in the others */
+    /* Eq. (1): new features where the mask is 1, previous ones elsewhere */
     orc_kp* D = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)(nF + s->nK + 1));
     int nD = 0;
-    for (int i = 0; i < nF; ++i)
-        if (s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)]) D[nD++] = F[i];
-    for (int i = 0; i < s->nK; ++i)
-        if (!s->mask[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)]) D[nD++] = s->K[i];
+    if (pix) {
+        for (int i = 0; i < nF; ++i)
+            if (pixel_mask(s, pix, lw, lh, &F[i])) D[nD++] = F[i];
+        for (int i = 0; i < s->nK; ++i)
+            if (!pixel_mask(s, pix, lw, lh, &s->K[i])) D[nD++] = s->K[i];
+        /* reported per-cell mask: T_H, or any changed layer pixel in the cell */
+        for (int Y = 0; Y < H; ++Y)
+            for (int X = 0; X < W; ++X) {
+                int k = X >> L, l = Y >> L;
+                if (k > lw - 1) k = lw - 1;
+                if (l > lh - 1) l = lh - 1;
+                if (pix[l * lw + k]) s->mask[cell_row(Y, H, Nr) * Nc + cell_col(X, W, Nc)] = 1;
+            }
+        free(pix);
+    } else {
+        for (int i = 0; i < nF; ++i)
+            if (s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)]) D[nD++] = F[i];
+        for (int i = 0; i < s->nK; ++i)
+            if (!s->mask[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)]) D[nD++] = s->K[i];
+    }
     kp_cmp_ctx_W = W; kp_cmp_ctx_H = H; kp_cmp_ctx_Nc = Nc; kp_cmp_ctx_Nr = Nr;
     qsort(D, (size_t)nD, sizeof(orc_kp), kp_cmp);
     if (nD > s->capK) { free(F); free(D); return -1; }

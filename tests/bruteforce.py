@@ -136,9 +136,10 @@ def kp_cell(k, W: int, H: int, Nc: int, Nr: int) -> int:
 class Stream:
     """Eq. (1) over a frame sequence, by brute force."""
 
-    def __init__(self, W, H, t, O, Nc, Nr, TI, TH=0xFFFFFFFF):
+    def __init__(self, W, H, t, O, Nc, Nr, TI, TH=0xFFFFFFFF, id_mode=0, layer=0):
         self.W, self.H, self.t, self.O, self.Nc, self.Nr = W, H, t, O, Nc, Nr
         self.TI, self.TH = TI, TH
+        self.id_mode, self.layer = id_mode, layer
         self.prev = None
         self.K: List[Tuple[int, int, int, int]] = []
         self.force = True
@@ -159,7 +160,28 @@ class Stream:
             mask = (sad > self.TI * area) | (hist >= self.TH)
         F = detect(frame, self.t, self.O)
         cell = lambda k: kp_cell(k, self.W, self.H, self.Nc, self.Nr)
-        new = [k for k in F if mask[cell(k)]] + [k for k in self.K if not mask[cell(k)]]
+        if self.id_mode == 1 and not self.force:
+            # the changed pixels of one pyramid layer, replicated up to level 0
+            l = self.layer
+            cur = pyramid(frame, l + 1)[l].astype(np.int64)
+            old = pyramid(self.prev, l + 1)[l].astype(np.int64)
+            changed = np.abs(cur - old) > self.TI
+            lh, lw = changed.shape
+            ys = np.minimum(np.arange(self.H) >> l, lh - 1)
+            xs = np.minimum(np.arange(self.W) >> l, lw - 1)
+            up = changed[ys[:, None], xs[None, :]]
+            kb = hist >= self.TH
+
+            def marked(k):
+                X, Y = k[0] * 2 ** k[2], k[1] * 2 ** k[2]
+                return bool(up[Y, X]) or bool(kb[cell(k)])
+
+            new = [k for k in F if marked(k)] + [k for k in self.K if not marked(k)]
+            touched = np.zeros(nc, bool)
+            touched[np.unique(self.cells[up])] = True
+            mask = kb | touched
+        else:
+            new = [k for k in F if mask[cell(k)]] + [k for k in self.K if not mask[cell(k)]]
         new.sort(key=lambda k: (cell(k), k[2], k[1], k[0]))
         self.K = new
         self.mask = mask.astype(np.uint8)

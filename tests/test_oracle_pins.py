@@ -439,6 +439,72 @@ def test_reset_forces_full_redetection_once():
     assert not s.get()[1].any()
 
 
+# ------------------------------------- paper-literal mask on a pyramid layer
+
+@pytest.mark.parametrize("layer,TI,TH,w,h,O", [
+    (0, 8, KB_OFF, 96, 72, 3), (1, 6, KB_OFF, 96, 72, 3), (2, 4, KB_OFF, 96, 72, 3),
+    (2, 5, 3, 98, 75, 3),
+    # level-0 features in the strip that halving leaves uncovered (x >= 96)
+    # take the layer's last column
+    (3, 4, KB_OFF, 101, 77, 4),
+    (1, 0, KB_OFF, 90, 70, 3), (2, 255, 2, 96, 72, 3),
+])
+def test_layer_mask_stream_matches_bruteforce(layer, TI, TH, w, h, O):
+    frames = _scene(seed=30 + layer, frames=5, w=w, h=h, move=0.7)
+    t, Nc, Nr = 15, 6, 4
+    o = oracle.Stream(w, h, t, O, Nc, Nr, TI, TH)
+    o.set_id_mode(1, layer)
+    b = bf.Stream(w, h, t, O, Nc, Nr, TI, TH, id_mode=1, layer=layer)
+    for i, f in enumerate(frames):
+        o.push(f)
+        exp = b.push(f)
+        kps, mask, _, _ = o.get()
+        assert kps_tuples(kps) == [(k[0], k[1], k[2], k[3]) for k in exp], f"frame {i}"
+        np.testing.assert_array_equal(mask, b.mask, err_msg=f"mask frame {i}")
+
+
+def test_layer_mask_unchanged_frame_and_all_marked():
+    frames = _scene(seed=41)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, 8)
+    s.set_id_mode(1, 2)
+    s.push(frames[0])
+    first = kps_tuples(s.get()[0])
+    s.push(frames[0])                 # nothing changed: D_n = D_{n-1}, nothing marked
+    k, m, _, _ = s.get()
+    assert kps_tuples(k) == first and not m.any()
+    a = oracle.Stream(W, H, t, O, Nc, Nr, -1)
+    a.set_id_mode(1, 1)
+    for f in frames[:3]:
+        a.push(f)
+        k, m, _, _ = a.get()
+        assert m.all()
+        F = kps_tuples(oracle.detect(f, t, O))
+        key = lambda q: (bf.kp_cell(q, W, H, Nc, Nr), q[2], q[1], q[0])
+        assert kps_tuples(k) == sorted(F, key=key)
+
+
+def test_layer_mask_is_per_feature_position():
+    # one changed level-0 pixel: only features sitting on it are re-detected,
+    # every other feature of the cell is carried
+    rng = np.random.default_rng(7)
+    W, H, t, O, Nc, Nr = 64, 48, 12, 1, 1, 1
+    f0 = rng.choice(np.array([20, 200], np.uint8), size=(H, W))
+    s = oracle.Stream(W, H, t, O, Nc, Nr, 10)
+    s.set_id_mode(1, 0)
+    s.push(f0)
+    D0 = kps_tuples(s.get()[0])
+    assert len(D0) > 10
+    x, y = D0[len(D0) // 2][:2]
+    f1 = f0.copy()
+    f1[y, x] = 255 - f1[y, x]          # a dark/bright flip at one feature
+    s.push(f1)
+    D1 = kps_tuples(s.get()[0])
+    F1 = {(k[0], k[1]): k for k in kps_tuples(oracle.detect(f1, t, O))}
+    exp = [k for k in D0 if (k[0], k[1]) != (x, y)] + ([F1[(x, y)]] if (x, y) in F1 else [])
+    assert D1 == sorted(exp, key=lambda k: (k[2], k[1], k[0]))
+
+
 # ------------------------------------------------------ stored regression values
 
 @pytest.mark.parametrize("name,det", [
