@@ -80,7 +80,12 @@ extern "C" {
  *   chunk_frames
  *              most frames one push_frames call may take (0 or 1: the
  *              stream takes single frames only; at most KPD_MAX_CHUNK). It
- *              sizes the arena. */
+ *              sizes the arena.
+ *   layer_mask 1: the stream may switch to the per-pixel layer mask
+ *              (set_mask_mode). Eq. 1 per feature can then place a carried
+ *              and a new feature side by side, so D_n is sized for every
+ *              decision pixel instead of one feature per 2x2 block. 0: no.
+ *   reserved   must be 0. */
 typedef struct kpd_params {
     int32_t fast_t;
     int32_t n_octaves;
@@ -90,6 +95,8 @@ typedef struct kpd_params {
     uint32_t kb_thresh;
     int32_t tile;
     int32_t chunk_frames;
+    int32_t layer_mask;
+    int32_t reserved;
 } kpd_params;
 
 /* One feature of D_n (Sec. 3: position and scale; the integer part).
@@ -147,6 +154,20 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
  * and kpd_chunk_result every frame's. KPD_EINVAL if the stream was opened
  * without chunk_frames >= 2. */
 int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes, int n_frames);
+
+/* Mask mode from the next push_frame on (a change re-detects every cell of
+ * that frame). mode 0: the per-cell test of Sec. 3.1 Eq. 2 read as a mean
+ * absolute level-0 difference per cell (the default). mode 1: Eq. 2 per
+ * pixel of pyramid layer `layer` (0..n_octaves-1; the paper uses the top
+ * layer), one mask for all octaves, replicated to level 0 (level-0 pixel
+ * (X,Y) takes layer pixel (X >> layer, Y >> layer), clamped to the layer's
+ * last column and row), and Eq. 1 applied per feature at its level-0
+ * position (x << octave, y << octave); T_H still marks whole cells. The
+ * reported cell mask flags cells marked by T_H or holding a changed pixel.
+ * Mode 1 runs on push_frame only: push_frames and batch_push return
+ * KPD_EINVAL while it is set, and so does mode 1 on a stream opened without
+ * layer_mask. */
+int set_mask_mode(kpd_stream* s, int mode, int layer);
 
 /* Wait for the last pushed frame and copy D_n to host memory `out`, ordered
  * by cell (row-major), then octave, then y, then x. `*count` receives the

@@ -63,6 +63,8 @@
  *       M_n(p) = 1 and those of D_{n-1} with M_n(p) = 0, in the order of R8.
  *       The per-cell mask reported is 1 for a cell marked by T_H or holding
  *       any level-0 pixel whose layer pixel changed.
+ *   R11 Switching the mask mode or its layer marks every cell of the next
+ *       frame, like a change of t.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -312,12 +314,14 @@ int orc_set_thresholds(orc_stream* s, int t, int32_t TI, uint32_t TH)
 }
 
 /* Mask mode from the next frame on: 0 = R7, 1 = R9/R10 on pyramid layer
- * `layer` (0..O-1). */
+ * `layer` (0..O-1). A change marks every cell of the next frame (R11). */
 int orc_set_id_mode(orc_stream* s, int mode, int layer)
 {
     if (mode < 0 || mode > 1 || layer < 0 || layer >= s->O) return -1;
+    if (mode == s->id_mode && (mode == 0 || layer == s->id_layer)) return 0;
     s->id_mode = mode;
-    s->id_layer = layer;
+    s->id_layer = mode == 1 ? layer : 0;
+    s->force_all = 1;   /* a new mask re-detects every cell once */
     return 0;
 }
 

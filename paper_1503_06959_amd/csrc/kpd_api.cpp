@@ -68,8 +68,14 @@ struct Layout {
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
     size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0, off_work = 0;
     size_t off_cntw = 0, off_ctab = 0, off_ftab = 0;
-    size_t list_cap = 0;
+    size_t list_cap = 0;    // entries of chunk and sparse lists: one feature per 2x2 decision block
+    size_t list_cap1 = 0;   // entries of the single-frame D lists: every decision pixel with layer_mask
     int lds_bytes = 0;   // dynamic LDS of the cell pass
+    // the per-pixel layer mask (set_mask_mode): its LDS scratch past every
+    // cell's layout (changed bits, carried bits, their offsets and scores),
+    // and a second buffer for octave 1.. so the layer of I_{n-1} survives
+    int lds_bits = 0, lds_carr = 0, lds_cwoff = 0, lds_cscore = 0, lds_bytes1 = 0;
+    size_t off_lvl_alt = 0;
     size_t total = 0;
 };
 
@@ -104,6 +110,8 @@ bool valid_params(int W, int H, const kpd_params* p, std::string* why)
         *why = "chunk_frames out of range";
         return false;
     }
+    if (p->layer_mask != 0 && p->layer_mask != 1) { *why = "layer_mask must be 0 or 1"; return false; }
+    if (p->reserved != 0) { *why = "reserved must be 0"; return false; }
     return true;
 }
 
@@ -152,20 +160,41 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->csad_slots = span_max(W, L->nc, L->ctile) * span_max(H, L->nr, L->ctile);
 
     // keypoint list capacity and the detection kernel's LDS need
-    size_t cap = 0;
-    int lds = 0;
+    size_t cap = 0, dec_px = 0;
+    int lds = 0, nwords_max = 0, npx_max = 0;
+    size_t cell_cap_max = 0;
     for (int c = 0; c < L->ncell; ++c) {
         const kpd::Box r = kpd::cell_rect(c, W, H, L->nc, L->nr);
         kpd::CellLayout CL;
         kpd::cell_layout(r, L->O, L->w, L->h, &CL);
-        for (int o = 0; o < L->O; ++o) cap += kpd::decision_capacity(CL.dec[o]);
+        size_t cc = 0;
+        for (int o = 0; o < L->O; ++o) cc += kpd::decision_capacity(CL.dec[o]);
+        cap += cc;
+        dec_px += (size_t)CL.dc_start[L->O];
+        cell_cap_max = std::max(cell_cap_max, p->layer_mask ? (size_t)CL.dc_start[L->O] : cc);
+        nwords_max = std::max(nwords_max, CL.nwords);
+        for (int lv = 0; lv < L->O; ++lv) {   // layer pixels the cell maps to, on every layer
+            const int nx = std::min((r.x1 - 1) >> lv, L->w[lv] - 1) - std::min(r.x0 >> lv, L->w[lv] - 1) + 1;
+            const int ny = std::min((r.y1 - 1) >> lv, L->h[lv] - 1) - std::min(r.y0 >> lv, L->h[lv] - 1) + 1;
+            npx_max = std::max(npx_max, nx * ny);
+        }
         lds = std::max(lds, CL.bytes);
         // the detection kernel queues score-pixel indices as 16-bit values
         if (CL.sc_start[L->O] > 65535) { *why = "cell too large"; return false; }
         if (cap > 0xFFFFFFF0ull) { *why = "keypoint list too large"; return false; }
     }
     L->list_cap = std::max<size_t>(cap, 1);
+    L->list_cap1 = p->layer_mask ? std::max<size_t>(dec_px, 1) : L->list_cap;
+    if (L->list_cap1 > 0xFFFFFFF0ull) { *why = "keypoint list too large"; return false; }
     L->lds_bytes = std::max(lds, 16);
+    {
+        int o1 = kpd::round_up(lds, 16);
+        L->lds_bits = o1;   o1 += kpd::round_up(kpd::round_up(npx_max, 64) / 8, 16);
+        L->lds_carr = o1;   o1 += kpd::round_up(nwords_max * 8, 16);
+        L->lds_cwoff = o1;  o1 += kpd::round_up(nwords_max * 4, 16);
+        L->lds_cscore = o1; o1 += kpd::round_up((int)cell_cap_max * 2, 16);
+        L->lds_bytes1 = o1;
+    }
 
     L->K = std::max(1, (int)p->chunk_frames);
 
@@ -175,7 +204,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     const size_t pyr0 = off;
     for (int o = 1; o < L->O; ++o) { L->off_lvl[o] = off; off = align_up(off + (size_t)L->pitch[o] * L->h[o]); }
     L->pyr_stride = off - pyr0;
-    off += L->pyr_stride * (size_t)(L->K - 1);
+    off += L->pyr_stride * (size_t)(L->K - 1);   // octave copies of chunk frames 1..K-1
+    if (L->O > 1) { L->off_lvl_alt = off; off = align_up(off + (size_t)L->pitch[1] * L->h[1]); }
     const size_t nc4 = (size_t)L->ncell * 4;
     for (int k = 0; k < 2; ++k) { L->off_sad[k] = off; off = align_up(off + nc4); }
     for (int k = 0; k < 2; ++k) { L->off_count[k] = off; off = align_up(off + nc4); }
@@ -189,11 +219,11 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->off_layouts = off; off = align_up(off + (size_t)L->ncell * sizeof(kpd::CellLayout));
     for (int k = 0; k < 2; ++k) {
         L->off_list[k] = off;
-        off = align_up(off + L->list_cap * sizeof(kpd_keypoint));
+        off = align_up(off + L->list_cap1 * sizeof(kpd_keypoint));
     }
     L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
     L->off_own1 = off; off = align_up(off + (size_t)L->ncell * 4);
-    L->off_sparse1 = off; off = align_up(off + L->list_cap * sizeof(kpd_keypoint));
+    L->off_sparse1 = off; off = align_up(off + L->list_cap1 * sizeof(kpd_keypoint));
     if (L->K > 1) {
         const size_t kc = (size_t)L->K * L->ncell;
         L->off_csad = off; off = align_up(off + kc * 4);
@@ -254,6 +284,9 @@ struct kpd_stream {
     int prev_pitch = 0;
     int prev_dw = 0;
     int fb_last = 1;          // which of the two single-frame buffers holds the latest D_n
+    int id_mode = 0;          // 0: per-cell mean difference at level 0; 1: per-pixel on layer id_layer
+    int id_layer = 0;
+    int layer_buf = 0;        // octave id_layer >= 1 of the latest frame: 0 its usual buffer, 1 the second
     int chunk_n = 0;          // frames of the last push_frames call
     bool closed = false;
     // pinned host staging for get_keypoints: header, the first kStage
@@ -525,7 +558,15 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     const int cur_k = n & 1, prev_k = cur_k ^ 1;       // SAD accumulators go by frame parity
     const int fb_prev = s->fb_last, fb_cur = 1 - s->fb_last;  // keypoint buffers alternate
     const bool all_marked = s->force_all || s->p.id_thresh < 0 || s->p.kb_thresh == 0;
-    const bool sad_on = !all_marked && s->p.id_thresh < 255;
+    const bool sad_on = !all_marked && s->p.id_thresh < 255 && s->id_mode == 0;
+    // with the layer mask on octave lv >= 1, that octave alternates between
+    // two buffers so the previous frame's stays readable
+    const int lv = s->id_layer;
+    const bool alt_layer = s->id_mode == 1 && lv >= 1;
+    auto level_ptr = [&](int o) -> uint8_t* {
+        if (alt_layer && o == lv && s->layer_buf == 0) return s->at<uint8_t>(L.off_lvl_alt);
+        return s->at<uint8_t>(L.off_lvl[o]);
+    };
 
     *t = kpd::TickArgs{};
     kpd::FrameArgs& fa = t->f;
@@ -536,7 +577,7 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     fa.prev_pitch = sad_on ? s->prev_pitch : cur_pitch;
     fa.prev_aligned = sad_on ? s->prev_dw : cur_dw;
     for (int o = 1; o < L.O; ++o) {
-        fa.lvl[o] = s->at<uint8_t>(L.off_lvl[o]);
+        fa.lvl[o] = level_ptr(o);
         fa.pitch[o] = L.pitch[o];
     }
     for (int o = 0; o < L.O; ++o) { fa.w[o] = L.w[o]; fa.h[o] = L.h[o]; }
@@ -558,11 +599,29 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     d.lvl[0] = cur;
     d.pitch[0] = cur_pitch;
     for (int o = 1; o < L.O; ++o) {
-        d.lvl[o] = s->at<uint8_t>(L.off_lvl[o]);
+        d.lvl[o] = level_ptr(o);
         d.pitch[o] = L.pitch[o];
     }
     for (int o = 0; o < L.O; ++o) { d.w[o] = L.w[o]; d.h[o] = L.h[o]; }
     d.lvl0_aligned = cur_dw;
+    if (s->id_mode == 1) {
+        d.id_mode = 1;
+        d.id_layer = lv;
+        if (lv == 0) {
+            d.layer_cur = cur;
+            d.layer_cur_pitch = cur_pitch;
+            d.layer_prev = s->prev0 ? s->prev0 : cur;   // read only when not every cell is marked
+            d.layer_prev_pitch = s->prev0 ? s->prev_pitch : cur_pitch;
+        } else {
+            d.layer_cur = level_ptr(lv);
+            d.layer_prev = s->layer_buf == 0 ? s->at<uint8_t>(L.off_lvl[lv]) : s->at<uint8_t>(L.off_lvl_alt);
+            d.layer_cur_pitch = d.layer_prev_pitch = L.pitch[lv];
+        }
+        d.lds_bits = L.lds_bits;
+        d.lds_carr = L.lds_carr;
+        d.lds_cwoff = L.lds_cwoff;
+        d.lds_cscore = L.lds_cscore;
+    }
     d.W = L.W; d.H = L.H; d.O = L.O; d.nc = L.nc; d.nr = L.nr;
     d.t = s->p.fast_t;
     d.all_marked = all_marked ? 1 : 0;
@@ -579,7 +638,7 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     d.off_cur = s->at<uint32_t>(L.off_offs[fb_cur]);
     d.list_cur = s->at<kpd_keypoint>(L.off_list[fb_cur]);
     d.total_cur = s->at<uint32_t>(L.off_hdr) + (fb_cur ? kHdrTotal1 : kHdrTotal0);
-    d.list_cap = (uint32_t)L.list_cap;
+    d.list_cap = (uint32_t)L.list_cap1;
     d.layouts = s->at<kpd::CellLayout>(L.off_layouts);
     d.col_w = s->at<uint16_t>(L.off_colw);
     d.row_h = s->at<uint16_t>(L.off_rowh);
@@ -602,6 +661,7 @@ void advance_frame(kpd_stream* s, const kpd::TickArgs& t)
     s->n_pushed += 1;
     s->fb_last = 1 - s->fb_last;
     s->chunk_n = 0;
+    if (s->id_mode == 1 && s->id_layer >= 1) s->layer_buf ^= 1;
 }
 
 }  // namespace
@@ -616,8 +676,24 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
     const Layout& L = s->L;
     if (t.f_on)
         KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(t.f, s->stream); }));
-    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, L.lds_bytes, s->stream); }));
+    const int lds = s->id_mode == 1 ? L.lds_bytes1 : L.lds_bytes;
+    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, lds, s->stream); }));
     advance_frame(s, t);
+    return KPD_OK;
+}
+
+int set_mask_mode(kpd_stream* s, int mode, int layer)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (mode < 0 || mode > 1) return fail(KPD_EINVAL, "mode must be 0 or 1");
+    if (layer < 0 || layer >= s->L.O) return fail(KPD_EINVAL, "layer must be an octave of the stream");
+    if (mode == 1 && !s->p.layer_mask) return fail(KPD_EINVAL, "stream opened without layer_mask");
+    if (mode == s->id_mode && (mode == 0 || layer == s->id_layer)) return KPD_OK;
+    if (mode == 1) KPD_HIP(kpd::set_detect_lds_limit(s->L.lds_bytes1));
+    s->id_mode = mode;
+    s->id_layer = mode == 1 ? layer : 0;
+    s->layer_buf = 0;
+    s->force_all = true;   // the previous frame's layer may not be kept: re-detect every cell once
     return KPD_OK;
 }
 
@@ -626,6 +702,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     const Layout& L = s->L;
     if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
+    if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
     if (!frames) return fail(KPD_EINVAL, "frames is NULL");
     if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
@@ -763,7 +840,7 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
     const Layout& L = s->L;
     const int k = s->fb_last;
     // one round trip: the header, the first entries of D_n and the mask
-    const size_t pre = std::min(L.list_cap, kStage);
+    const size_t pre = std::min(L.list_cap1, kStage);
     uint8_t* st_list = s->stage + 64;
     uint8_t* st_mask = st_list + kStage * sizeof(kpd_keypoint);
     KPD_HIP(hipMemcpyAsync(s->stage, s->at<uint32_t>(L.off_hdr), 16, hipMemcpyDeviceToHost, s->stream));
@@ -1050,6 +1127,7 @@ int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_b
     if (it == b->streams.end()) return fail(KPD_EINVAL, "stream not attached");
     const size_t i = (size_t)(it - b->streams.begin());
     if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
+    if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
     if (rc != KPD_OK) return rc;
     b->has_frame[i] = 1;
@@ -1140,8 +1218,10 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out)
     if (octave < 1 || octave >= s->L.O || !out) return fail(KPD_EINVAL, "bad octave or NULL output");
     const Layout& L = s->L;
     const size_t copy = s->chunk_n > 0 ? (size_t)(s->chunk_n - 1) : 0;   // the last frame's octaves
-    KPD_HIP(hipMemcpy2DAsync(out, L.w[octave], s->arena + L.pyr_stride * copy + L.off_lvl[octave], L.pitch[octave],
-                             L.w[octave], L.h[octave], hipMemcpyDeviceToHost, s->stream));
+    const uint8_t* src = s->arena + L.pyr_stride * copy + L.off_lvl[octave];
+    if (s->id_mode == 1 && octave == s->id_layer && s->layer_buf == 1) src = s->arena + L.off_lvl_alt;
+    KPD_HIP(hipMemcpy2DAsync(out, L.w[octave], src, L.pitch[octave], L.w[octave], L.h[octave], hipMemcpyDeviceToHost,
+                             s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
     return KPD_OK;
 }

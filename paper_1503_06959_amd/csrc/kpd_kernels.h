@@ -68,6 +68,15 @@ struct DetectArgs {
     unsigned long long* status;  // per-cell count words of marked cells
     uint32_t epoch;              // frame number + 1
     uint32_t* err;               // set when a wait for an earlier cell gives up
+    // per-pixel mask on one pyramid layer (id_mode 1, single frames): the
+    // layer of I_n and of I_{n-1}, and where its per-cell scratch lives in
+    // LDS (changed-pixel bits, carried-entry bits, their word offsets and
+    // scores), past every cell's detection layout
+    int id_mode, id_layer;
+    const uint8_t* layer_cur;
+    const uint8_t* layer_prev;
+    int layer_cur_pitch, layer_prev_pitch;
+    int lds_bits, lds_carr, lds_cwoff, lds_cscore;
 };
 
 // Everything one stream needs for one batch tick. tile_base and cell_base

@@ -39,6 +39,8 @@
 // marking waits, on the same cell's count word of the previous frame.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "kpd_geom.h"
 #include "kpd_kernels.h"
 
@@ -450,9 +452,45 @@ __device__ __forceinline__ bool cell_marked(const DetectArgs& a, int c)
 // Steps 0-4 for a marked cell c: stage the octave tiles, score, suppress and
 // rank. Leaves the keep bitmask and word offsets in LDS and the cell's number
 // of keypoints in *s_n (valid after the final barrier).
+// Exclusive popcount prefix of nw bitmask words into offs (wave 0 calls it;
+// returns the total in lane 63).
+__device__ __forceinline__ uint32_t prefix_words(const uint64_t* words, uint32_t* offs, int nw, int lane)
+{
+    const int per = (nw + 63) / 64;
+    const int w0 = lane * per, w1 = min(w0 + per, nw);
+    uint32_t sum = 0;
+    for (int w = w0; w < w1; ++w) sum += (uint32_t)__popcll(words[w]);
+    uint32_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t up = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += up;
+    }
+    uint32_t run = incl - sum;
+    for (int w = w0; w < w1; ++w) {
+        offs[w] = run;
+        run += (uint32_t)__popcll(words[w]);
+    }
+    return incl;
+}
+
+// Step 4: rank the keep words (word offsets into LDS, the count into *s_n);
+// with `carr`, also the word offsets of the carried-entry bits.
+__device__ __forceinline__ void rank_words(const CellLayout& L, uint8_t* sm, uint32_t* s_n,
+                                           const uint64_t* carr = nullptr, uint32_t* cwoff = nullptr)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        const uint32_t n = prefix_words(reinterpret_cast<const uint64_t*>(sm),
+                                        reinterpret_cast<uint32_t*>(sm + L.woff_off), L.nwords, lane);
+        if (carr) prefix_words(carr, cwoff, L.nwords, lane);
+        if (lane == 63) *s_n = n;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lvl0_aligned, int c, uint8_t* sm,
                                               CellLayout& L, const uint8_t* const* s_lvl, const int* s_pitch,
-                                              uint32_t* s_n)
+                                              uint32_t* s_n, bool rank = true)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -657,26 +695,7 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
     __syncthreads();
 
     // 4) rank: exclusive popcount prefix over the keep words (wave 0)
-    if (wave == 0) {
-        const int nw = L.nwords;
-        uint32_t* woff = reinterpret_cast<uint32_t*>(sm + L.woff_off);
-        const int per = (nw + 63) / 64;
-        const int w0 = lane * per, w1 = min(w0 + per, nw);
-        uint32_t sum = 0;
-        for (int w = w0; w < w1; ++w) sum += (uint32_t)__popcll(keepw[w]);
-        uint32_t incl = sum;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t up = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += up;
-        }
-        uint32_t run = incl - sum;
-        for (int w = w0; w < w1; ++w) {
-            woff[w] = run;
-            run += (uint32_t)__popcll(keepw[w]);
-        }
-        if (lane == 63) *s_n = incl;
-    }
-    __syncthreads();
+    if (rank) rank_words(L, sm, s_n);
 }
 
 // Step 6 for a marked cell: write its ranked maxima from position excl on.
@@ -706,6 +725,42 @@ __device__ __forceinline__ void emit_marked(const DetectArgs& a, const CellLayou
             k.pad = 0;
             k.score = (uint16_t)vget(sm, L, o, x, y);
             // at most one keypoint per 2x2 block keeps pos below the capacity
+            if (pos < cap) list[pos] = k;
+            ++pos;
+        }
+    }
+}
+
+// Step 6 for a cell that keeps some new maxima and carries some D_{n-1}
+// entries: the ranked union in decision order, carried entries with their
+// previous scores (the k-th carried bit takes cscore[k]).
+__device__ __forceinline__ void emit_merged(const DetectArgs& a, const CellLayout& L, const uint8_t* sm,
+                                            uint32_t excl, kpd_keypoint* list, uint32_t cap, const uint64_t* carr,
+                                            const uint32_t* cwoff, const uint16_t* cscore)
+{
+    const int O = a.O;
+    const uint64_t* keepw = reinterpret_cast<const uint64_t*>(sm);
+    const uint32_t* woff = reinterpret_cast<const uint32_t*>(sm + L.woff_off);
+    for (int w = threadIdx.x; w < L.nwords; w += kBlk) {
+        uint64_t bits = keepw[w];
+        const uint64_t cb = carr[w];
+        uint32_t pos = excl + woff[w];
+        while (bits) {
+            const int b = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const int i = w * 64 + b;
+            const int o = level_of(L.dc_start, O, i);
+            const unsigned j = i - L.dc_start[o];
+            const Box d = L.dec[o];
+            const int ry = fast_div(j, L.dcm[o]);
+            const int x = d.x0 + (int)(j - ry * box_w(d)), y = d.y0 + ry;
+            kpd_keypoint k;
+            k.x = (uint16_t)x;
+            k.y = (uint16_t)y;
+            k.octave = (uint8_t)o;
+            k.pad = 0;
+            k.score = ((cb >> b) & 1) ? cscore[cwoff[w] + __popcll(cb & ((1ull << b) - 1))]
+                                      : (uint16_t)vget(sm, L, o, x, y);
             if (pos < cap) list[pos] = k;
             ++pos;
         }
@@ -767,9 +822,161 @@ __device__ void load_level_ptrs(const DetectArgs& a, const uint8_t** s_lvl, int*
     }
 }
 
+// One frame of one stream with the mask on a pyramid layer (Sec. 3.1 read
+// per pixel, one mask for all octaves): cell c compares its layer pixels of
+// I_n and I_{n-1}. A cell with no changed pixel carries D_{n-1}; a cell
+// marked by T_H detects everything; otherwise it keeps the new maxima whose
+// level-0 position maps to a changed pixel and the D_{n-1} entries whose
+// position does not (Eq. 1 per feature), merged in decision order. Every
+// cell publishes its count word, and offsets wait on all earlier cells.
+__device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
+{
+    __shared__ CellLayout L;
+    __shared__ int s_touched;
+    __shared__ uint32_t s_n, s_base, s_part[kDetWaves];
+    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
+    __shared__ int s_pitch[KPD_MAX_OCTAVES];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lv = a.id_layer;
+    const int lw = a.w[lv], lh = a.h[lv];
+    const Box r = cell_rect(c, a.W, a.H, a.nc, a.nr);
+    // the layer pixels the cell's level-0 pixels map to (clamped into the layer)
+    const int kx0 = min(r.x0 >> lv, lw - 1), kx1 = min((r.x1 - 1) >> lv, lw - 1);
+    const int ky0 = min(r.y0 >> lv, lh - 1), ky1 = min((r.y1 - 1) >> lv, lh - 1);
+    const int nx = kx1 - kx0 + 1, npx = nx * (ky1 - ky0 + 1);
+    uint32_t* bits = reinterpret_cast<uint32_t*>(sm + a.lds_bits);
+    if (tid == 0) {
+        load_level_ptrs(a, s_lvl, s_pitch);
+        s_touched = 0;
+    }
+    __syncthreads();
+    const bool kb = a.count_prev[c] >= a.kb_thresh;
+    if (!kb) {
+        for (int base = 0; base < npx; base += kBlk) {
+            const int i = base + tid;
+            bool ch = false;
+            if (i < npx) {
+                const int ry = i / nx, rx = i - ry * nx;
+                const int cur = a.layer_cur[(size_t)(ky0 + ry) * a.layer_cur_pitch + kx0 + rx];
+                const int prv = a.layer_prev[(size_t)(ky0 + ry) * a.layer_prev_pitch + kx0 + rx];
+                ch = abs(cur - prv) > a.id_thresh;
+            }
+            const uint64_t bal = __ballot(ch);
+            if (lane == 0 && base + wave * 64 < npx) {   // the bit map holds npx bits rounded up to 64
+                const int w0 = (base + wave * 64) >> 5;
+                bits[w0] = (uint32_t)bal;
+                bits[w0 + 1] = (uint32_t)(bal >> 32);
+                if (bal) s_touched = 1;
+            }
+        }
+    }
+    __syncthreads();
+    const int state = kb ? 2 : (s_touched ? 1 : 0);   // full, partial, carried
+    if (tid == 0) {
+        a.mask[c] = (uint8_t)(state != 0);
+        a.sad_next[c] = 0;
+    }
+    if (state) detect_marked(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n, state == 2);
+    uint64_t* carr = reinterpret_cast<uint64_t*>(sm + a.lds_carr);
+    uint32_t* cwoff = reinterpret_cast<uint32_t*>(sm + a.lds_cwoff);
+    uint16_t* cscore = reinterpret_cast<uint16_t*>(sm + a.lds_cscore);
+    if (state == 1) {
+        uint64_t* keepw = reinterpret_cast<uint64_t*>(sm);
+        auto changed_at = [&](int o, int x, int y) -> bool {
+            const int kx = min((x << o) >> lv, lw - 1) - kx0, ky = min((y << o) >> lv, lh - 1) - ky0;
+            const int i = ky * nx + kx;
+            return (bits[i >> 5] >> (i & 31)) & 1u;
+        };
+        // new maxima only where the mask is 1
+        for (int w = tid; w < L.nwords; w += kBlk) {
+            uint64_t k = keepw[w], out = k;
+            while (k) {
+                const int b = __builtin_ctzll(k);
+                k &= k - 1;
+                const int i = w * 64 + b;
+                const int o = level_of(L.dc_start, a.O, i);
+                const unsigned j = i - L.dc_start[o];
+                const Box d = L.dec[o];
+                const int ry = fast_div(j, L.dcm[o]);
+                if (!changed_at(o, d.x0 + (int)(j - ry * box_w(d)), d.y0 + ry)) out &= ~(1ull << b);
+            }
+            keepw[w] = out;
+            carr[w] = 0;
+        }
+        if (tid == 0) s_base = 0;
+        __syncthreads();
+        // D_{n-1}'s entries of the cell where the mask is 0, in order
+        const uint32_t n0 = a.count_prev[c], src0 = a.off_prev[c];
+        for (uint32_t b0 = 0; b0 < n0; b0 += kBlk) {
+            const uint32_t jj = b0 + tid;
+            bool keep = false;
+            kpd_keypoint e{};
+            if (jj < n0 && src0 + jj < a.list_cap) {
+                e = a.list_prev[src0 + jj];
+                const Box d = L.dec[e.octave < a.O ? e.octave : 0];
+                keep = e.octave < a.O && e.x >= d.x0 && e.x < d.x1 && e.y >= d.y0 && e.y < d.y1 &&
+                       !changed_at(e.octave, e.x, e.y);
+            }
+            const uint64_t bal = __ballot(keep);
+            if (lane == 0) s_part[wave] = (uint32_t)__popcll(bal);
+            __syncthreads();
+            uint32_t before = s_base, total = 0;
+            for (int w = 0; w < kDetWaves; ++w) {
+                if (w < wave) before += s_part[w];
+                total += s_part[w];
+            }
+            if (keep) {
+                const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                cscore[before + below] = e.score;
+                const int o = e.octave;
+                const Box d = L.dec[o];
+                const int i = L.dc_start[o] + (e.y - d.y0) * box_w(d) + (e.x - d.x0);
+                atomicOr(&carr[i >> 6], 1ull << (i & 63));
+            }
+            __syncthreads();
+            if (tid == 0) s_base += total;
+            __syncthreads();
+        }
+        for (int w = tid; w < L.nwords; w += kBlk) keepw[w] |= carr[w];
+        __syncthreads();
+        rank_words(L, sm, &s_n, carr, cwoff);
+    }
+
+    // offsets: every cell publishes its count word
+    if (tid == 0) {
+        const uint32_t own = state ? s_n : a.count_prev[c];
+        s_n = own;
+        __hip_atomic_store(&a.status[c], ((uint64_t)a.epoch << 32) | own, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t excl = sum_count_words(a.status, c, a.epoch, a.err, s_part);
+    const uint32_t n = s_n;
+    if (tid == 0) {
+        a.count_cur[c] = n;
+        a.off_cur[c] = excl;
+        if (c == a.nc * a.nr - 1) *a.total_cur = excl + n;
+    }
+    if (state == 2) {
+        emit_marked(a, L, sm, excl, a.list_cur, a.list_cap);
+    } else if (state == 1) {
+        emit_merged(a, L, sm, excl, a.list_cur, a.list_cap, carr, cwoff, cscore);
+    } else {
+        const uint32_t src0 = a.off_prev[c];
+        for (uint32_t j = tid; j < n; j += kBlk)
+            if (src0 + j < a.list_cap && excl + j < a.list_cap) a.list_cur[excl + j] = a.list_prev[src0 + j];
+    }
+}
+
 // One frame of one stream: cell c's mark, detection, offset and output.
 __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
 {
+    if (a.id_mode == 1 && !a.all_marked) {
+        detect_cell_layer(a, c, sm);
+        return;
+    }
     __shared__ CellLayout L;
     __shared__ int s_mark;
     __shared__ uint32_t s_n, s_excl, s_part[kDetWaves];
@@ -1309,7 +1516,12 @@ int frame_lds_bytes(int tile, int O, int sad_slots)
 
 hipError_t set_detect_lds_limit(int lds_bytes)
 {
-    if (lds_bytes <= 65536) return hipSuccess;
+    // the limit is a property of the kernels, shared by every stream: only raise it
+    static std::atomic<int> g_limit{65536};
+    int cur = g_limit.load();
+    while (lds_bytes > cur && !g_limit.compare_exchange_weak(cur, lds_bytes)) {
+    }
+    if (lds_bytes <= cur) return hipSuccess;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect1),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;

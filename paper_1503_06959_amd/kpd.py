@@ -35,7 +35,7 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "close_stream", "reset_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats",
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
             "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
-            "push_frames", "kpd_chunk_result", "get_chunk_keypoints")
+            "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode")
 KERNEL_NAMES = ("k_frame", "k_detect", "k_compact", "k_mark")
 
 
@@ -43,7 +43,8 @@ class KpdParams(ctypes.Structure):
     _fields_ = [("fast_t", ctypes.c_int32), ("n_octaves", ctypes.c_int32),
                 ("grid_cols", ctypes.c_int32), ("grid_rows", ctypes.c_int32),
                 ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32),
-                ("tile", ctypes.c_int32), ("chunk_frames", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("chunk_frames", ctypes.c_int32),
+                ("layer_mask", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KpdError(RuntimeError):
@@ -86,6 +87,7 @@ def _load() -> ctypes.CDLL:
     L.push_frames.argtypes = [P, P, sz, sz, ctypes.c_int]
     L.kpd_chunk_result.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P)]
     L.get_chunk_keypoints.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
+    L.set_mask_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
     return L
 
 
@@ -99,8 +101,10 @@ def _check(rc: int) -> int:
 
 
 def make_params(fast_t: int, n_octaves: int, grid_cols: int, grid_rows: int,
-                id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0, chunk_frames: int = 0) -> KpdParams:
-    return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, chunk_frames)
+                id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0, chunk_frames: int = 0,
+                layer_mask: int = 0) -> KpdParams:
+    return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, chunk_frames,
+                     layer_mask, 0)
 
 
 def stream_bytes(width: int, height: int, params: KpdParams) -> int:
@@ -183,6 +187,12 @@ def chunk_result(handle: int, i: int) -> Tuple[int, int]:
     lst, cnt = ctypes.c_void_p(), ctypes.c_void_p()
     _check(lib.kpd_chunk_result(handle, i, ctypes.byref(lst), ctypes.byref(cnt)))
     return lst.value, cnt.value
+
+
+def set_mask_mode(handle: int, mode: int, layer: int = 0) -> None:
+    """0: per-cell mean difference at level 0; 1: per-pixel difference on
+    pyramid layer `layer`, Eq. 1 per feature position (single-frame pushes)."""
+    _check(lib.set_mask_mode(handle, mode, layer))
 
 
 def close_stream(handle: int) -> None:
@@ -302,6 +312,9 @@ class Stream:
 
     def set_thresholds(self, fast_t: int, id_thresh: int, kb_thresh: int = KPD_KB_OFF) -> None:
         set_thresholds(self.handle, fast_t, id_thresh, kb_thresh)
+
+    def set_mask_mode(self, mode: int, layer: int = 0) -> None:
+        set_mask_mode(self.handle, mode, layer)
 
     def keypoints(self) -> Tuple[np.ndarray, np.ndarray]:
         """D_n (a copy) and M_n of the last push."""

@@ -52,7 +52,7 @@ def test_library_exports_every_declared_symbol(kpd):
 
 
 def test_struct_layouts_match_header(kpd):
-    assert ctypes.sizeof(kpd.KpdParams) == 32
+    assert ctypes.sizeof(kpd.KpdParams) == 40
     assert kpd.KEYPOINT_DTYPE.itemsize == 8
     assert kpd.KEYPOINT_DTYPE.fields["octave"][1] == 4
     assert kpd.KEYPOINT_DTYPE.fields["score"][1] == 6
