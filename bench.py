@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--mode", choices=("both", "masked", "full"), default="both",
                     help="masked or full: run only that pass of --workload and print its line (for profiling)")
     ap.add_argument("--chunked", action="store_true", help="with --mode: push --chunk frames per call")
+    ap.add_argument("--layer", type=int, default=None,
+                    help="with --mode masked: the per-pixel mask on this pyramid layer (single-frame pushes)")
     ap.add_argument("--tile", type=int, default=0, help="level-0 tile of the tile pass (0: the library default)")
     ap.add_argument("--profile-script", metavar="OUTDIR", help="print the rocprofv3 script for the profiles")
     ap.add_argument("--summarize-profiles", metavar="OUTDIR", help="write profiles/ from that script's output")
@@ -105,10 +107,11 @@ class Workload:
 TILE = 0
 
 
-def open_stream(wl: Workload, id_thresh: int, chunk: int = 0):
+def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool = False):
     from paper_1503_06959_amd import kpd
     d = wl.det
-    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh, TILE, chunk)
+    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh, TILE, chunk,
+                             int(layer_mask))
     s = kpd.Stream(wl.W, wl.H, params)
     s.chunk = chunk
     return s
@@ -241,7 +244,8 @@ def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> 
     lv = level_sizes(wl.W, wl.H, d.n_octaves)
     P = sum(lv[1:])
     F = wl.F
-    sad_frames = (F - 1) if masked else 0
+    layer = st.get("layer")
+    sad_frames = (F - 1) if masked and layer is None else 0
     frac = [m / wl.ncell for m in st["marked"]]
     carried = sum(t - n for t, n in zip(st["total_kp"], st["new_kp"]))
     meta = 24 * wl.ncell * F
@@ -253,13 +257,20 @@ def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> 
         out["k_mark"] = 8 * wl.ncell * F
     else:
         out["k_detect"] = scan + 16 * carried + meta
+        if layer is not None:   # the per-pixel test reads layer `layer` of I_n and I_{n-1}
+            out["k_detect"] += 2 * lv[layer] * (F - 1)
     return out
 
 
-def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True, chunk=0):
-    s = open_stream(wl, id_thresh, chunk)
+def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True, chunk=0,
+                 layer=None):
+    """layer: None for the per-cell mean-difference mask, else the pyramid
+    layer of the per-pixel mask (single-frame pushes only)."""
+    s = open_stream(wl, id_thresh, chunk, layer_mask=layer is not None)
+    if layer is not None:
+        s.set_mask_mode(1, layer)
     sec = timed_passes(kpd, s, wl, args.steps, args.warmup)
-    res = {"sec_per_pass": sec, "frames": wl.F, "chunk": chunk,
+    res = {"sec_per_pass": sec, "frames": wl.F, "chunk": chunk, "layer": layer,
            "mpix_per_s": wl.F * wl.W * wl.H / sec / 1e6, "frames_per_s": wl.F / sec}
     if want_latency:
         if chunk > 1:
@@ -278,6 +289,7 @@ def roofline_of(wl: Workload, res, masked: bool, traffic=None, stats=None):
     keypoint counts per frame) default to the run's own."""
     st = dict(stats or res)
     st["chunk"] = res.get("chunk", 0)
+    st["layer"] = res.get("layer")
     ab = algorithmic_bytes(wl, st, masked, chunked=res.get("chunk", 0) > 1)
     kern = {k: v for k, v in res["kernels"].items() if k != "passes"}
     passes = res["kernels"]["passes"]
@@ -287,7 +299,7 @@ def roofline_of(wl: Workload, res, masked: bool, traffic=None, stats=None):
     avg_s = ms / 1e3 / max(n, 1)
     achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
     if traffic is None:
-        traffic = traffic_for(wl.name, masked, res.get("chunk", 0), dom)
+        traffic = traffic_for(wl.name, masked, res.get("chunk", 0), dom, res.get("layer"))
     return {
         "kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
@@ -454,12 +466,19 @@ PROFILE_CASES = {
     "kt_c2_640x480_bench": ("trace", "--no-hd --no-batch --no-serve --no-cpu-baseline --steps 10 --warmup 2"),
     "kt_c2_640x480_masked_chunked": ("trace", "--workload c2_640x480 --mode masked --chunked --steps 20 --warmup 2"),
     "kt_c3_1920x1080_full_chunked": ("trace", "--workload c3_1920x1080 --mode full --chunked --steps 10 --warmup 2"),
+    "kt_c2_640x480_layer3_frame": ("trace", "--workload c2_640x480 --mode masked --layer 3 --steps 10 --warmup 2"),
     "pmc_c2_640x480_masked_chunked": ("pmc", "--workload c2_640x480 --mode masked --chunked --steps 2 --warmup 0"),
     "pmc_c2_640x480_full_chunked": ("pmc", "--workload c2_640x480 --mode full --chunked --steps 2 --warmup 0"),
     "pmc_c3_1920x1080_full_chunked": ("pmc", "--workload c3_1920x1080 --mode full --chunked --steps 2 --warmup 0"),
+    "pmc_c2_640x480_layer3_frame": ("pmc", "--workload c2_640x480 --mode masked --layer 3 --steps 2 --warmup 0"),
     "pmc_copy_256MiB": ("pmc", "--copy-calibration 256"),
 }
 PMC_COUNTERS = ("FETCH_SIZE", "WRITE_SIZE")
+# kernel -> (push path, the timed kernel id its launches count under)
+KERNEL_IDS = {"k_frame1": ("frame", "k_frame"), "k_detect1": ("frame", "k_detect"),
+              "k_frame_chunk": ("chunk", "k_frame"), "k_detect_chunk": ("chunk", "k_detect"),
+              "k_detect_list": ("chunk", "k_detect"), "k_mark_chunk": ("chunk", "k_mark"),
+              "k_compact_chunk": ("chunk", "k_compact")}
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ("kpd_kernels.hip", "kpd_kernels.h", "kpd_geom.h")
 
@@ -551,21 +570,23 @@ def summarize_profiles(out: str) -> None:
             continue
         f, w = pmc(case, "FETCH_SIZE"), pmc(case, "WRITE_SIZE")
         wl, mode = case[4:].rsplit("_", 2)[0], case[4:].rsplit("_", 2)[1]
+        acc = defaultdict(lambda: [0.0, 0])   # timed kernel id -> summed bytes, dispatches
         for k in sorted(f):
-            if not k.startswith("k_") or k not in w:
+            if k not in KERNEL_IDS or k not in w:
                 continue
             b = f[k][0] * 1024 * f_scale + w[k][0] * 1024 * w_scale
-            name = {"k_frame_chunk": "k_frame", "k_detect_chunk": "k_detect", "k_compact_chunk": "k_compact",
-                    "k_frame1": "k_frame", "k_detect1": "k_detect"}.get(k, k)
-            key = f"{wl}/{mode}/{'chunk' if k.endswith('_chunk') else 'frame'}/{name}"
-            traffic["per_launch_bytes"][key] = int(b)
+            key = f"{wl}/{mode}/{KERNEL_IDS[k][0]}/{KERNEL_IDS[k][1]}"
+            acc[key][0] += b * f[k][1]
+            acc[key][1] += f[k][1]
             lines.append(f"{case[4:]:34s} {k:16s} {f[k][1]:10d} {f[k][0]:11.2f} {w[k][0]:11.2f} {int(b):13d}")
+        for key, (b, n) in acc.items():
+            traffic["per_launch_bytes"][key] = int(b / n)
     open(os.path.join(pdir, "hbm_traffic_chunked_and_single.txt"), "w").write("\n".join(lines) + "\n")
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump(traffic, fh, indent=1, sort_keys=True)
 
 
-def traffic_for(wl_name: str, masked: bool, chunk: int, kernel: str):
+def traffic_for(wl_name: str, masked: bool, chunk: int, kernel: str, layer=None):
     """Counter-measured HBM bytes per launch of this kernel on this workload,
     or None when not measured or when the kernels changed since."""
     try:
@@ -575,7 +596,8 @@ def traffic_for(wl_name: str, masked: bool, chunk: int, kernel: str):
         return None
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    key = f"{wl_name}/{'masked' if masked else 'full'}/{'chunk' if chunk > 1 else 'frame'}/{kernel}"
+    mode = f"layer{layer}" if layer is not None else ("masked" if masked else "full")
+    key = f"{wl_name}/{mode}/{'chunk' if chunk > 1 else 'frame'}/{kernel}"
     return t["per_launch_bytes"].get(key)
 
 
@@ -617,11 +639,15 @@ def main():
     if args.mode != "both":
         masked = args.mode == "masked"
         chunk = args.chunk if args.chunked else 0
-        log(f"[bench] {args.mode} pass only, chunk {chunk}")
-        r = run_workload(kpd, wl, wl.det.id_thresh if masked else -1, args, chunk=chunk)
+        layer = args.layer if masked else None
+        if layer is not None and chunk:
+            sys.exit("--layer runs on single-frame pushes: leave out --chunked")
+        log(f"[bench] {args.mode} pass only, chunk {chunk}, layer {layer}")
+        r = run_workload(kpd, wl, wl.det.id_thresh if masked else -1, args, chunk=chunk, layer=layer)
         stats = r if chunk <= 1 else run_workload(kpd, wl, wl.det.id_thresh if masked else -1, args,
                                                   want_profile=False)
         print(json.dumps({"workload": wl.describe(wl.det.id_thresh if masked else -1), "chunk": chunk,
+                          "layer": layer,
                           "value": round(r["mpix_per_s"], 2), "unit": "Mpixel/s",
                           "frames_per_s": round(r["frames_per_s"], 1),
                           "latency_ms": {"p50": round(r["lat_p50"], 4), "p99": round(r["lat_p99"], 4)},
@@ -682,6 +708,18 @@ def main():
                            "roofline": roofline_of(wl, full, False)},
             "masked_over_full": round(masked["mpix_per_s"] / full["mpix_per_s"], 3),
         },
+    }
+    top = wl.det.n_octaves - 1
+    log(f"[bench] per-pixel mask on layer {top}")
+    lm = run_workload(kpd, wl, wl.det.id_thresh, args, layer=top)
+    out["layer_mask"] = {
+        "what": f"per-pixel |I_n - I_(n-1)| > T_I on pyramid layer {top} (the top octave), Eq. 1 per feature "
+                "position, one push_frame per frame",
+        "value": round(lm["mpix_per_s"], 2), "unit": "Mpixel/s", "frames_per_s": round(lm["frames_per_s"], 1),
+        "ms_per_step": round(lm["sec_per_pass"] * 1e3, 4),
+        "latency_ms": {"p50": round(lm["lat_p50"], 4), "p99": round(lm["lat_p99"], 4)},
+        "touched_cell_frac": round(sum(lm["marked"][1:]) / max(1, (wl.F - 1) * wl.ncell), 4),
+        "roofline": roofline_of(wl, lm, True),
     }
     out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:

@@ -141,7 +141,9 @@ class Stream:
 
     def set_id_mode(self, mode: int, layer: int = 0):
         """0: per-cell mean difference at level 0; 1: per-pixel difference on
-        pyramid layer `layer`, Eq. 1 per feature position."""
+        pyramid layer `layer`, Eq. 1 per feature position; 2: per-pixel
+        difference on every level, each octave's features tested on their own
+        level (layer 0)."""
         assert lib().orc_set_id_mode(self.h, mode, layer) == 0
 
     def push(self, frame: np.ndarray) -> int:

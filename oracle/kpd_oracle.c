@@ -65,6 +65,13 @@
  *       any level-0 pixel whose layer pixel changed.
  *   R11 Switching the mask mode or its layer marks every cell of the next
  *       frame, like a change of t.
+ * A third mode takes Sec. 3.1's option i, one mask per octave:
+ *   R12 The feature at level o, (x,y), is new when |L_{n,o}(x,y) -
+ *       L_{n-1,o}(x,y)| exceeds T_I (the mask built on its own layer, so no
+ *       upsampling is involved) or its cell passes the T_H test; otherwise
+ *       D_{n-1}'s feature there is kept (Eq. 1 per feature, as in R10). The
+ *       per-cell mask reported is 1 for a cell marked by T_H or holding a
+ *       level-0 pixel that the upsampled mask of any level (R9) sets.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -270,7 +277,8 @@ typedef struct {
     uint32_t TH;
     int n_frames;
     int force_all;
-    int id_mode;         /* 0: per-cell mean at level 0 (R7); 1: per-pixel on a layer (R9, R10) */
+    int id_mode;         /* 0: per-cell mean at level 0 (R7); 1: per-pixel on a layer (R9, R10);
+                            2: per-pixel on every level, one mask per octave (R12) */
     int id_layer;
     uint8_t* prev;       /* I_{n-1} */
     orc_kp* K;           /* D_{n-1}, then D_n */
@@ -314,10 +322,11 @@ int orc_set_thresholds(orc_stream* s, int t, int32_t TI, uint32_t TH)
 }
 
 /* Mask mode from the next frame on: 0 = R7, 1 = R9/R10 on pyramid layer
- * `layer` (0..O-1). A change marks every cell of the next frame (R11). */
+ * `layer` (0..O-1), 2 = R12 (layer must be 0). A change marks every cell of
+ * the next frame (R11). */
 int orc_set_id_mode(orc_stream* s, int mode, int layer)
 {
-    if (mode < 0 || mode > 1 || layer < 0 || layer >= s->O) return -1;
+    if (mode < 0 || mode > 2 || layer < 0 || layer >= s->O || (mode == 2 && layer != 0)) return -1;
     if (mode == s->id_mode && (mode == 0 || layer == s->id_layer)) return 0;
     s->id_mode = mode;
     s->id_layer = mode == 1 ? layer : 0;
@@ -348,15 +357,18 @@ static int kp_cmp(const void* a, const void* b)
     return 0;
 }
 
-/* R10: M_n at the level-0 position of feature k (the cell mask of s holds
- * the T_H test at this point). */
-static int pixel_mask(const orc_stream* s, const uint8_t* pix, int lw, int lh, const orc_kp* k)
+/* R10 and R12: M_n for feature k, read on layer id_layer at k's level-0
+ * position (mode 1) or on k's own level at (x,y) (mode 2); pix[l], lw[l],
+ * lh[l] are layer l's changed pixels and size. The cell mask of s holds the
+ * T_H test at this point. */
+static int pixel_mask(const orc_stream* s, uint8_t* const* pix, const int* lw, const int* lh, const orc_kp* k)
 {
+    const int l = s->id_mode == 1 ? s->id_layer : k->octave;
     const int X = k->x << k->octave, Y = k->y << k->octave;
-    int kx = X >> s->id_layer, ly = Y >> s->id_layer;
-    if (kx > lw - 1) kx = lw - 1;
-    if (ly > lh - 1) ly = lh - 1;
-    if (pix[ly * lw + kx]) return 1;
+    int kx = X >> l, ly = Y >> l;
+    if (kx > lw[l] - 1) kx = lw[l] - 1;
+    if (ly > lh[l] - 1) ly = lh[l] - 1;
+    if (pix[l][ly * lw[l] + kx]) return 1;
     return s->mask[orc_cell_of(k->x, k->y, k->octave, s->W, s->H, s->Nc, s->Nr)] != 0;
 }
 
@@ -368,24 +380,28 @@ int orc_push(orc_stream* s, const uint8_t* frame)
     const int ncell = Nc * Nr;
 
     /* detection mask M_n */
-    uint8_t* pix = NULL;     /* R9: changed pixels of the layer */
-    int lw = 0, lh = 0, L = s->id_layer;
-    if (s->id_mode == 1 && !s->force_all) {
-        int ws[32], hs[32];
-        orc_level_dims(W, H, L + 1, ws, hs);
-        lw = ws[L];
-        lh = hs[L];
+    uint8_t* pix[32] = {0};  /* R9: changed pixels of layer l (mode 1: l = id_layer; mode 2: every l) */
+    int lw[32] = {0}, lh[32] = {0};
+    const int per_pixel = s->id_mode != 0 && !s->force_all;
+    const int l0 = s->id_mode == 1 ? s->id_layer : 0, l1 = s->id_mode == 1 ? s->id_layer : s->O - 1;
+    if (per_pixel) {
+        orc_level_dims(W, H, l1 + 1, lw, lh);
         size_t tot = 0;
-        for (int o = 0; o <= L; ++o) tot += (size_t)ws[o] * hs[o];
+        for (int o = 0; o <= l1; ++o) tot += (size_t)lw[o] * lh[o];
         uint8_t* pc = (uint8_t*)malloc(tot);
         uint8_t* pp = (uint8_t*)malloc(tot);
-        orc_pyramid(frame, W, H, L + 1, pc);
-        orc_pyramid(s->prev, W, H, L + 1, pp);
-        const size_t off = tot - (size_t)lw * lh;
-        pix = (uint8_t*)malloc((size_t)lw * lh);
-        for (int i = 0; i < lw * lh; ++i) {
-            int d = (int)pc[off + i] - (int)pp[off + i];
-            pix[i] = (uint8_t)((d < 0 ? -d : d) > s->TI);
+        orc_pyramid(frame, W, H, l1 + 1, pc);
+        orc_pyramid(s->prev, W, H, l1 + 1, pp);
+        size_t off = 0;
+        for (int l = 0; l <= l1; ++l) {
+            if (l >= l0) {
+                pix[l] = (uint8_t*)malloc((size_t)lw[l] * lh[l]);
+                for (int i = 0; i < lw[l] * lh[l]; ++i) {
+                    int d = (int)pc[off + i] - (int)pp[off + i];
+                    pix[l][i] = (uint8_t)((d < 0 ? -d : d) > s->TI);
+                }
+            }
+            off += (size_t)lw[l] * lh[l];
         }
         free(pc);
         free(pp);
@@ -411,9 +427,9 @@ int orc_push(orc_stream* s, const uint8_t* frame)
             int kb = hist[c] >= s->TH;                         /* Eq. (4) */
             s->mask[c] = (uint8_t)(id || kb);
         }
-        if (pix) {
-            /* R10: the cell mask is the T_H test; the reported mask also
-             * flags cells with a changed layer pixel */
+        if (per_pixel) {
+            /* R10, R12: the cell mask is the T_H test; the reported mask
+             * also flags cells with a changed layer pixel */
             for (int c = 0; c < ncell; ++c) s->mask[c] = (uint8_t)(hist[c] >= s->TH);
             for (int c = 0; c < ncell; ++c) s->sad[c] = 0;
         }
@@ -429,20 +445,22 @@ int orc_push(orc_stream* s, const uint8_t* frame)
     /* Eq. (1): new features where the mask is 1, previous ones elsewhere */
     orc_kp* D = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)(nF + s->nK + 1));
     int nD = 0;
-    if (pix) {
+    if (per_pixel) {
         for (int i = 0; i < nF; ++i)
             if (pixel_mask(s, pix, lw, lh, &F[i])) D[nD++] = F[i];
         for (int i = 0; i < s->nK; ++i)
             if (!pixel_mask(s, pix, lw, lh, &s->K[i])) D[nD++] = s->K[i];
-        /* reported per-cell mask: T_H, or any changed layer pixel in the cell */
-        for (int Y = 0; Y < H; ++Y)
-            for (int X = 0; X < W; ++X) {
-                int k = X >> L, l = Y >> L;
-                if (k > lw - 1) k = lw - 1;
-                if (l > lh - 1) l = lh - 1;
-                if (pix[l * lw + k]) s->mask[cell_row(Y, H, Nr) * Nc + cell_col(X, W, Nc)] = 1;
-            }
-        free(pix);
+        /* reported per-cell mask: T_H, or a changed pixel of a layer, upsampled, in the cell */
+        for (int l = l0; l <= l1; ++l) {
+            for (int Y = 0; Y < H; ++Y)
+                for (int X = 0; X < W; ++X) {
+                    int k = X >> l, m = Y >> l;
+                    if (k > lw[l] - 1) k = lw[l] - 1;
+                    if (m > lh[l] - 1) m = lh[l] - 1;
+                    if (pix[l][m * lw[l] + k]) s->mask[cell_row(Y, H, Nr) * Nc + cell_col(X, W, Nc)] = 1;
+                }
+            free(pix[l]);
+        }
     } else {
         for (int i = 0; i < nF; ++i)
             if (s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)]) D[nD++] = F[i];

@@ -160,25 +160,28 @@ class Stream:
             mask = (sad > self.TI * area) | (hist >= self.TH)
         F = detect(frame, self.t, self.O)
         cell = lambda k: kp_cell(k, self.W, self.H, self.Nc, self.Nr)
-        if self.id_mode == 1 and not self.force:
-            # the changed pixels of one pyramid layer, replicated up to level 0
-            l = self.layer
-            cur = pyramid(frame, l + 1)[l].astype(np.int64)
-            old = pyramid(self.prev, l + 1)[l].astype(np.int64)
-            changed = np.abs(cur - old) > self.TI
-            lh, lw = changed.shape
-            ys = np.minimum(np.arange(self.H) >> l, lh - 1)
-            xs = np.minimum(np.arange(self.W) >> l, lw - 1)
-            up = changed[ys[:, None], xs[None, :]]
+        if self.id_mode in (1, 2) and not self.force:
+            # the changed pixels of pyramid layers, each replicated up to level 0
+            layers = [self.layer] if self.id_mode == 1 else list(range(self.O))
+            pc, pp = pyramid(frame, max(layers) + 1), pyramid(self.prev, max(layers) + 1)
+            up = {}
+            for l in layers:
+                changed = np.abs(pc[l].astype(np.int64) - pp[l].astype(np.int64)) > self.TI
+                lh, lw = changed.shape
+                ys = np.minimum(np.arange(self.H) >> l, lh - 1)
+                xs = np.minimum(np.arange(self.W) >> l, lw - 1)
+                up[l] = changed[ys[:, None], xs[None, :]]
             kb = hist >= self.TH
 
             def marked(k):
                 X, Y = k[0] * 2 ** k[2], k[1] * 2 ** k[2]
-                return bool(up[Y, X]) or bool(kb[cell(k)])
+                l = self.layer if self.id_mode == 1 else k[2]   # one mask, or the feature's own octave's
+                return bool(up[l][Y, X]) or bool(kb[cell(k)])
 
             new = [k for k in F if marked(k)] + [k for k in self.K if not marked(k)]
             touched = np.zeros(nc, bool)
-            touched[np.unique(self.cells[up])] = True
+            for u in up.values():
+                touched[np.unique(self.cells[u])] = True
             mask = kb | touched
         else:
             new = [k for k in F if mask[cell(k)]] + [k for k in self.K if not mask[cell(k)]]

@@ -505,6 +505,72 @@ def test_layer_mask_is_per_feature_position():
     assert D1 == sorted(exp, key=lambda k: (k[2], k[1], k[0]))
 
 
+# ------------------------------------------ one mask per octave (option i)
+
+@pytest.mark.parametrize("TI,TH,w,h,O", [
+    (6, KB_OFF, 96, 72, 3), (4, KB_OFF, 101, 77, 4), (5, 3, 98, 75, 3), (0, KB_OFF, 90, 70, 2),
+])
+def test_octave_masks_stream_matches_bruteforce(TI, TH, w, h, O):
+    frames = _scene(seed=60 + O, frames=5, w=w, h=h, move=0.7)
+    t, Nc, Nr = 15, 6, 4
+    o = oracle.Stream(w, h, t, O, Nc, Nr, TI, TH)
+    o.set_id_mode(2, 0)
+    b = bf.Stream(w, h, t, O, Nc, Nr, TI, TH, id_mode=2)
+    for i, f in enumerate(frames):
+        o.push(f)
+        exp = b.push(f)
+        kps, mask, _, _ = o.get()
+        assert kps_tuples(kps) == [(k[0], k[1], k[2], k[3]) for k in exp], f"frame {i}"
+        np.testing.assert_array_equal(mask, b.mask, err_msg=f"mask frame {i}")
+
+
+def test_octave_masks_test_each_octave_on_its_own_level():
+    # a level-0 change of 30 at one octave-0 feature moves its level-1 box
+    # mean by at most 8 <= T_I: under one mask per octave only that octave-0
+    # feature is re-detected and every octave-1 feature is carried; under one
+    # mask built on layer 1 nothing is re-detected at all
+    rng = np.random.default_rng(11)
+    W, H, t, O, Nc, Nr, TI = 64, 48, 12, 2, 1, 1, 10
+    f0 = rng.choice(np.array([20, 200], np.uint8), size=(H, W))
+    s2 = oracle.Stream(W, H, t, O, Nc, Nr, TI)
+    s2.set_id_mode(2, 0)
+    s1 = oracle.Stream(W, H, t, O, Nc, Nr, TI)
+    s1.set_id_mode(1, 1)
+    s2.push(f0)
+    s1.push(f0)
+    D0 = kps_tuples(s2.get()[0])
+    assert kps_tuples(s1.get()[0]) == D0
+    assert any(k[2] == 1 for k in D0) and sum(k[2] == 0 for k in D0) > 10
+    x, y = next(k for k in D0[len(D0) // 3:] if k[2] == 0)[:2]
+    f1 = f0.copy()
+    f1[y, x] = f0[y, x] + 30 if f0[y, x] == 20 else f0[y, x] - 30
+    lv0, lv1 = oracle.pyramid(f0, 2)[1].astype(int), oracle.pyramid(f1, 2)[1].astype(int)
+    assert np.abs(lv0 - lv1).max() <= TI          # level 1 sees no change
+    s2.push(f1)
+    s1.push(f1)
+    F1 = {(k[0], k[1]): k for k in kps_tuples(oracle.detect(f1, t, O)) if k[2] == 0}
+    exp = [k for k in D0 if not (k[2] == 0 and (k[0], k[1]) == (x, y))] + ([F1[(x, y)]] if (x, y) in F1 else [])
+    assert kps_tuples(s2.get()[0]) == sorted(exp, key=lambda k: (k[2], k[1], k[0]))
+    assert kps_tuples(s1.get()[0]) == D0
+    assert s2.get()[1].all() and not s1.get()[1].any()
+
+
+def test_octave_masks_unchanged_frame_and_mode_errors():
+    frames = _scene(seed=43)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, 8)
+    s.set_id_mode(2, 0)
+    s.push(frames[0])
+    first = kps_tuples(s.get()[0])
+    s.push(frames[0])
+    k, m, _, _ = s.get()
+    assert kps_tuples(k) == first and not m.any()
+    with pytest.raises(AssertionError):
+        s.set_id_mode(2, 1)                        # option i has no layer to choose
+    with pytest.raises(AssertionError):
+        s.set_id_mode(3, 0)
+
+
 # ------------------------------------------------------ stored regression values
 
 @pytest.mark.parametrize("name,det", [
