@@ -81,8 +81,9 @@ extern "C" {
  *              most frames one push_frames call may take (0 or 1: the
  *              stream takes single frames only; at most KPD_MAX_CHUNK). It
  *              sizes the arena.
- *   layer_mask 1: the stream may switch to the per-pixel layer mask
- *              (set_mask_mode). Eq. 1 per feature can then place a carried
+ *   layer_mask 1: the stream may switch to the per-pixel masks
+ *              (set_mask_mode); a second copy of octaves 1..O-1 keeps the
+ *              previous frame's readable. Eq. 1 per feature can then place a carried
  *              and a new feature side by side, so D_n is sized for every
  *              decision pixel instead of one feature per 2x2 block. 0: no.
  *   reserved   must be 0. */
@@ -162,11 +163,13 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
  * layer), one mask for all octaves, replicated to level 0 (level-0 pixel
  * (X,Y) takes layer pixel (X >> layer, Y >> layer), clamped to the layer's
  * last column and row), and Eq. 1 applied per feature at its level-0
- * position (x << octave, y << octave); T_H still marks whole cells. The
- * reported cell mask flags cells marked by T_H or holding a changed pixel.
- * Mode 1 runs on push_frame only: push_frames and batch_push return
- * KPD_EINVAL while it is set, and so does mode 1 on a stream opened without
- * layer_mask. */
+ * position (x << octave, y << octave); T_H still marks whole cells. mode 2
+ * (layer must be 0): Sec. 3.1's one mask per octave, Eq. 2 per pixel of
+ * every level, a feature at level o tested on level o's pixel (x, y). The
+ * reported cell mask flags cells marked by T_H or holding a changed pixel
+ * (of any level, replicated to level 0, in mode 2). Modes 1 and 2 run on
+ * push_frame only: push_frames and batch_push return KPD_EINVAL while one
+ * is set, and so does either mode on a stream opened without layer_mask. */
 int set_mask_mode(kpd_stream* s, int mode, int layer);
 
 /* Wait for the last pushed frame and copy D_n to host memory `out`, ordered

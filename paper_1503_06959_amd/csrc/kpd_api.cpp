@@ -173,11 +173,13 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         dec_px += (size_t)CL.dc_start[L->O];
         cell_cap_max = std::max(cell_cap_max, p->layer_mask ? (size_t)CL.dc_start[L->O] : cc);
         nwords_max = std::max(nwords_max, CL.nwords);
-        for (int lv = 0; lv < L->O; ++lv) {   // layer pixels the cell maps to, on every layer
+        int npx_sum = 0;   // layer pixels the cell maps to, summed over the layers, each rounded up to 64
+        for (int lv = 0; lv < L->O; ++lv) {
             const int nx = std::min((r.x1 - 1) >> lv, L->w[lv] - 1) - std::min(r.x0 >> lv, L->w[lv] - 1) + 1;
             const int ny = std::min((r.y1 - 1) >> lv, L->h[lv] - 1) - std::min(r.y0 >> lv, L->h[lv] - 1) + 1;
-            npx_max = std::max(npx_max, nx * ny);
+            npx_sum += kpd::round_up(nx * ny, 64);
         }
+        npx_max = std::max(npx_max, npx_sum);
         lds = std::max(lds, CL.bytes);
         // the detection kernel queues score-pixel indices as 16-bit values
         if (CL.sc_start[L->O] > 65535) { *why = "cell too large"; return false; }
@@ -189,7 +191,7 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->lds_bytes = std::max(lds, 16);
     {
         int o1 = kpd::round_up(lds, 16);
-        L->lds_bits = o1;   o1 += kpd::round_up(kpd::round_up(npx_max, 64) / 8, 16);
+        L->lds_bits = o1;   o1 += kpd::round_up(npx_max / 8, 16);
         L->lds_carr = o1;   o1 += kpd::round_up(nwords_max * 8, 16);
         L->lds_cwoff = o1;  o1 += kpd::round_up(nwords_max * 4, 16);
         L->lds_cscore = o1; o1 += kpd::round_up((int)cell_cap_max * 2, 16);
@@ -205,7 +207,9 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     for (int o = 1; o < L->O; ++o) { L->off_lvl[o] = off; off = align_up(off + (size_t)L->pitch[o] * L->h[o]); }
     L->pyr_stride = off - pyr0;
     off += L->pyr_stride * (size_t)(L->K - 1);   // octave copies of chunk frames 1..K-1
-    if (L->O > 1) { L->off_lvl_alt = off; off = align_up(off + (size_t)L->pitch[1] * L->h[1]); }
+    // a second copy of octaves 1..O-1 for the per-pixel masks, which read the
+    // previous frame's levels while the current frame's are written
+    if (L->O > 1 && p->layer_mask) { L->off_lvl_alt = off; off = align_up(off + L->pyr_stride); }
     const size_t nc4 = (size_t)L->ncell * 4;
     for (int k = 0; k < 2; ++k) { L->off_sad[k] = off; off = align_up(off + nc4); }
     for (int k = 0; k < 2; ++k) { L->off_count[k] = off; off = align_up(off + nc4); }
@@ -284,9 +288,10 @@ struct kpd_stream {
     int prev_pitch = 0;
     int prev_dw = 0;
     int fb_last = 1;          // which of the two single-frame buffers holds the latest D_n
-    int id_mode = 0;          // 0: per-cell mean difference at level 0; 1: per-pixel on layer id_layer
+    int id_mode = 0;          // 0: per-cell mean difference at level 0; 1: per-pixel on layer id_layer;
+                              // 2: per-pixel on every level, one mask per octave
     int id_layer = 0;
-    int layer_buf = 0;        // octave id_layer >= 1 of the latest frame: 0 its usual buffer, 1 the second
+    int layer_buf = 0;        // the mask's octaves >= 1 of the latest frame: 0 their usual buffers, 1 the second copy
     int chunk_n = 0;          // frames of the last push_frames call
     bool closed = false;
     // pinned host staging for get_keypoints: header, the first kStage
@@ -527,6 +532,18 @@ namespace {
 // Validate and stage the next frame of `s`: copy it into an arena slot when
 // asked to, and fill the tick arguments of both passes. The stream state
 // advances only in advance_frame, once the work is enqueued.
+// Octave o >= 1 is read by the per-pixel mask and so alternates between its
+// usual buffer and a second copy, frame by frame.
+bool alternates(const kpd_stream* s, int o)
+{
+    return o >= 1 && ((s->id_mode == 1 && o == s->id_layer) || s->id_mode == 2);
+}
+
+uint8_t* alt_level(kpd_stream* s, int o)
+{
+    return s->arena + s->L.off_lvl_alt + (s->L.off_lvl[o] - s->L.off_lvl[1]);
+}
+
 int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags, kpd::TickArgs* t)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
@@ -559,12 +576,11 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     const int fb_prev = s->fb_last, fb_cur = 1 - s->fb_last;  // keypoint buffers alternate
     const bool all_marked = s->force_all || s->p.id_thresh < 0 || s->p.kb_thresh == 0;
     const bool sad_on = !all_marked && s->p.id_thresh < 255 && s->id_mode == 0;
-    // with the layer mask on octave lv >= 1, that octave alternates between
-    // two buffers so the previous frame's stays readable
+    // the octaves >= 1 a per-pixel mask reads alternate between two buffers
+    // so the previous frame's stay readable
     const int lv = s->id_layer;
-    const bool alt_layer = s->id_mode == 1 && lv >= 1;
     auto level_ptr = [&](int o) -> uint8_t* {
-        if (alt_layer && o == lv && s->layer_buf == 0) return s->at<uint8_t>(L.off_lvl_alt);
+        if (alternates(s, o) && s->layer_buf == 0) return alt_level(s, o);
         return s->at<uint8_t>(L.off_lvl[o]);
     };
 
@@ -604,18 +620,16 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     }
     for (int o = 0; o < L.O; ++o) { d.w[o] = L.w[o]; d.h[o] = L.h[o]; }
     d.lvl0_aligned = cur_dw;
-    if (s->id_mode == 1) {
-        d.id_mode = 1;
-        d.id_layer = lv;
-        if (lv == 0) {
-            d.layer_cur = cur;
-            d.layer_cur_pitch = cur_pitch;
-            d.layer_prev = s->prev0 ? s->prev0 : cur;   // read only when not every cell is marked
-            d.layer_prev_pitch = s->prev0 ? s->prev_pitch : cur_pitch;
-        } else {
-            d.layer_cur = level_ptr(lv);
-            d.layer_prev = s->layer_buf == 0 ? s->at<uint8_t>(L.off_lvl[lv]) : s->at<uint8_t>(L.off_lvl_alt);
-            d.layer_cur_pitch = d.layer_prev_pitch = L.pitch[lv];
+    if (s->id_mode != 0) {
+        d.id_mode = s->id_mode;
+        d.id_layer = s->id_mode == 1 ? lv : 0;
+        // I_{n-1}: level 0 is the previous frame (read only when not every
+        // cell is marked), the others the buffers this frame does not write
+        d.lprev[0] = s->prev0 ? s->prev0 : cur;
+        d.lprev_pitch[0] = s->prev0 ? s->prev_pitch : cur_pitch;
+        for (int o = 1; o < L.O; ++o) {
+            d.lprev[o] = alternates(s, o) && s->layer_buf == 1 ? alt_level(s, o) : s->at<uint8_t>(L.off_lvl[o]);
+            d.lprev_pitch[o] = L.pitch[o];
         }
         d.lds_bits = L.lds_bits;
         d.lds_carr = L.lds_carr;
@@ -661,7 +675,7 @@ void advance_frame(kpd_stream* s, const kpd::TickArgs& t)
     s->n_pushed += 1;
     s->fb_last = 1 - s->fb_last;
     s->chunk_n = 0;
-    if (s->id_mode == 1 && s->id_layer >= 1) s->layer_buf ^= 1;
+    if (s->id_mode != 0) s->layer_buf ^= 1;
 }
 
 }  // namespace
@@ -676,7 +690,7 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
     const Layout& L = s->L;
     if (t.f_on)
         KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(t.f, s->stream); }));
-    const int lds = s->id_mode == 1 ? L.lds_bytes1 : L.lds_bytes;
+    const int lds = s->id_mode != 0 ? L.lds_bytes1 : L.lds_bytes;
     KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, lds, s->stream); }));
     advance_frame(s, t);
     return KPD_OK;
@@ -685,11 +699,12 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
 int set_mask_mode(kpd_stream* s, int mode, int layer)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
-    if (mode < 0 || mode > 1) return fail(KPD_EINVAL, "mode must be 0 or 1");
+    if (mode < 0 || mode > 2) return fail(KPD_EINVAL, "mode must be 0, 1 or 2");
     if (layer < 0 || layer >= s->L.O) return fail(KPD_EINVAL, "layer must be an octave of the stream");
-    if (mode == 1 && !s->p.layer_mask) return fail(KPD_EINVAL, "stream opened without layer_mask");
-    if (mode == s->id_mode && (mode == 0 || layer == s->id_layer)) return KPD_OK;
-    if (mode == 1) KPD_HIP(kpd::set_detect_lds_limit(s->L.lds_bytes1));
+    if (mode == 2 && layer != 0) return fail(KPD_EINVAL, "mode 2 masks every octave on its own level: layer must be 0");
+    if (mode != 0 && !s->p.layer_mask) return fail(KPD_EINVAL, "stream opened without layer_mask");
+    if (mode == s->id_mode && (mode != 1 || layer == s->id_layer)) return KPD_OK;
+    if (mode != 0) KPD_HIP(kpd::set_detect_lds_limit(s->L.lds_bytes1));
     s->id_mode = mode;
     s->id_layer = mode == 1 ? layer : 0;
     s->layer_buf = 0;
@@ -1219,7 +1234,7 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out)
     const Layout& L = s->L;
     const size_t copy = s->chunk_n > 0 ? (size_t)(s->chunk_n - 1) : 0;   // the last frame's octaves
     const uint8_t* src = s->arena + L.pyr_stride * copy + L.off_lvl[octave];
-    if (s->id_mode == 1 && octave == s->id_layer && s->layer_buf == 1) src = s->arena + L.off_lvl_alt;
+    if (alternates(s, octave) && s->layer_buf == 1) src = alt_level(s, octave);
     KPD_HIP(hipMemcpy2DAsync(out, L.w[octave], src, L.pitch[octave], L.w[octave], L.h[octave], hipMemcpyDeviceToHost,
                              s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));

@@ -68,14 +68,15 @@ struct DetectArgs {
     unsigned long long* status;  // per-cell count words of marked cells
     uint32_t epoch;              // frame number + 1
     uint32_t* err;               // set when a wait for an earlier cell gives up
-    // per-pixel mask on one pyramid layer (id_mode 1, single frames): the
-    // layer of I_n and of I_{n-1}, and where its per-cell scratch lives in
-    // LDS (changed-pixel bits, carried-entry bits, their word offsets and
-    // scores), past every cell's detection layout
+    // per-pixel masks (single frames): id_mode 1 builds one mask on layer
+    // id_layer, id_mode 2 one per octave on its own level. lprev holds
+    // I_{n-1}'s levels that the masks read (I_n's are lvl); the lds_ fields
+    // say where the per-cell scratch lives in LDS (changed-pixel bits,
+    // carried-entry bits, their word offsets and scores), past every cell's
+    // detection layout
     int id_mode, id_layer;
-    const uint8_t* layer_cur;
-    const uint8_t* layer_prev;
-    int layer_cur_pitch, layer_prev_pitch;
+    const uint8_t* lprev[KPD_MAX_OCTAVES];
+    int lprev_pitch[KPD_MAX_OCTAVES];
     int lds_bits, lds_carr, lds_cwoff, lds_cscore;
 };
 

@@ -822,13 +822,14 @@ __device__ void load_level_ptrs(const DetectArgs& a, const uint8_t** s_lvl, int*
     }
 }
 
-// One frame of one stream with the mask on a pyramid layer (Sec. 3.1 read
-// per pixel, one mask for all octaves): cell c compares its layer pixels of
+// One frame of one stream with per-pixel masks (Sec. 3.1): one mask on a
+// chosen pyramid layer for all octaves (id_mode 1), or one mask per octave on
+// its own level (id_mode 2). Cell c compares its pixels of those layers in
 // I_n and I_{n-1}. A cell with no changed pixel carries D_{n-1}; a cell
 // marked by T_H detects everything; otherwise it keeps the new maxima whose
-// level-0 position maps to a changed pixel and the D_{n-1} entries whose
-// position does not (Eq. 1 per feature), merged in decision order. Every
-// cell publishes its count word, and offsets wait on all earlier cells.
+// mask pixel changed and the D_{n-1} entries whose mask pixel did not (Eq. 1
+// per feature), merged in decision order. Every cell publishes its count
+// word, and offsets wait on all earlier cells.
 __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
 {
     __shared__ CellLayout L;
@@ -836,38 +837,57 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
     __shared__ uint32_t s_n, s_base, s_part[kDetWaves];
     __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
     __shared__ int s_pitch[KPD_MAX_OCTAVES];
+    // per mask layer: the cell's first pixel and width on it, and where its
+    // bits start in the bit map (a multiple of 64)
+    __shared__ int s_kx0[KPD_MAX_OCTAVES], s_ky0[KPD_MAX_OCTAVES], s_nx[KPD_MAX_OCTAVES], s_npx[KPD_MAX_OCTAVES];
+    __shared__ int s_boff[KPD_MAX_OCTAVES];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int lv = a.id_layer;
-    const int lw = a.w[lv], lh = a.h[lv];
-    const Box r = cell_rect(c, a.W, a.H, a.nc, a.nr);
-    // the layer pixels the cell's level-0 pixels map to (clamped into the layer)
-    const int kx0 = min(r.x0 >> lv, lw - 1), kx1 = min((r.x1 - 1) >> lv, lw - 1);
-    const int ky0 = min(r.y0 >> lv, lh - 1), ky1 = min((r.y1 - 1) >> lv, lh - 1);
-    const int nx = kx1 - kx0 + 1, npx = nx * (ky1 - ky0 + 1);
+    const bool one = a.id_mode == 1;
+    const int l_lo = one ? a.id_layer : 0, l_hi = one ? a.id_layer : a.O - 1;
     uint32_t* bits = reinterpret_cast<uint32_t*>(sm + a.lds_bits);
     if (tid == 0) {
         load_level_ptrs(a, s_lvl, s_pitch);
         s_touched = 0;
+        // the layer pixels the cell's level-0 pixels map to (clamped into the layer)
+        const Box r = cell_rect(c, a.W, a.H, a.nc, a.nr);
+        int boff = 0;
+        for (int l = l_lo; l <= l_hi; ++l) {
+            const int lw = a.w[l], lh = a.h[l];
+            const int kx0 = min(r.x0 >> l, lw - 1), kx1 = min((r.x1 - 1) >> l, lw - 1);
+            const int ky0 = min(r.y0 >> l, lh - 1), ky1 = min((r.y1 - 1) >> l, lh - 1);
+            s_kx0[l] = kx0;
+            s_ky0[l] = ky0;
+            s_nx[l] = kx1 - kx0 + 1;
+            s_npx[l] = s_nx[l] * (ky1 - ky0 + 1);
+            s_boff[l] = boff;
+            boff += (s_npx[l] + 63) & ~63;
+        }
     }
     __syncthreads();
     const bool kb = a.count_prev[c] >= a.kb_thresh;
     if (!kb) {
-        for (int base = 0; base < npx; base += kBlk) {
-            const int i = base + tid;
-            bool ch = false;
-            if (i < npx) {
-                const int ry = i / nx, rx = i - ry * nx;
-                const int cur = a.layer_cur[(size_t)(ky0 + ry) * a.layer_cur_pitch + kx0 + rx];
-                const int prv = a.layer_prev[(size_t)(ky0 + ry) * a.layer_prev_pitch + kx0 + rx];
-                ch = abs(cur - prv) > a.id_thresh;
-            }
-            const uint64_t bal = __ballot(ch);
-            if (lane == 0 && base + wave * 64 < npx) {   // the bit map holds npx bits rounded up to 64
-                const int w0 = (base + wave * 64) >> 5;
-                bits[w0] = (uint32_t)bal;
-                bits[w0 + 1] = (uint32_t)(bal >> 32);
-                if (bal) s_touched = 1;
+        for (int l = l_lo; l <= l_hi; ++l) {
+            const int nx = s_nx[l], npx = s_npx[l], kx0 = s_kx0[l], ky0 = s_ky0[l], boff = s_boff[l];
+            const uint8_t* cur = s_lvl[l];
+            const uint8_t* prv = a.lprev[l];
+            const int cp = s_pitch[l], pp = a.lprev_pitch[l];
+            for (int base = 0; base < npx; base += kBlk) {
+                const int i = base + tid;
+                bool ch = false;
+                if (i < npx) {
+                    const int ry = i / nx, rx = i - ry * nx;
+                    const int vc = cur[(size_t)(ky0 + ry) * cp + kx0 + rx];
+                    const int vp = prv[(size_t)(ky0 + ry) * pp + kx0 + rx];
+                    ch = abs(vc - vp) > a.id_thresh;
+                }
+                const uint64_t bal = __ballot(ch);
+                if (lane == 0 && base + wave * 64 < npx) {   // the layer's bits are npx rounded up to 64
+                    const int w0 = (boff + base + wave * 64) >> 5;
+                    bits[w0] = (uint32_t)bal;
+                    bits[w0 + 1] = (uint32_t)(bal >> 32);
+                    if (bal) s_touched = 1;
+                }
             }
         }
     }
@@ -883,9 +903,13 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
     uint16_t* cscore = reinterpret_cast<uint16_t*>(sm + a.lds_cscore);
     if (state == 1) {
         uint64_t* keepw = reinterpret_cast<uint64_t*>(sm);
+        // the mask pixel of the feature at level o, (x,y): on the chosen
+        // layer at its level-0 position, or on level o itself
         auto changed_at = [&](int o, int x, int y) -> bool {
-            const int kx = min((x << o) >> lv, lw - 1) - kx0, ky = min((y << o) >> lv, lh - 1) - ky0;
-            const int i = ky * nx + kx;
+            const int l = one ? l_lo : o;
+            const int kx = min((x << o) >> l, a.w[l] - 1) - s_kx0[l];
+            const int ky = min((y << o) >> l, a.h[l] - 1) - s_ky0[l];
+            const int i = s_boff[l] + ky * s_nx[l] + kx;
             return (bits[i >> 5] >> (i & 31)) & 1u;
         };
         // new maxima only where the mask is 1
@@ -973,7 +997,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
 // One frame of one stream: cell c's mark, detection, offset and output.
 __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
 {
-    if (a.id_mode == 1 && !a.all_marked) {
+    if (a.id_mode != 0 && !a.all_marked) {
         detect_cell_layer(a, c, sm);
         return;
     }

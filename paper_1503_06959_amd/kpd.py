@@ -191,7 +191,9 @@ def chunk_result(handle: int, i: int) -> Tuple[int, int]:
 
 def set_mask_mode(handle: int, mode: int, layer: int = 0) -> None:
     """0: per-cell mean difference at level 0; 1: per-pixel difference on
-    pyramid layer `layer`, Eq. 1 per feature position (single-frame pushes)."""
+    pyramid layer `layer`, Eq. 1 per feature position; 2: per-pixel
+    difference on every level, each octave's features tested on their own
+    level (layer 0). Modes 1 and 2 run on single-frame pushes."""
     _check(lib.set_mask_mode(handle, mode, layer))
 
 

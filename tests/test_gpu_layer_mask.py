@@ -1,7 +1,8 @@
-"""GPU parity of the per-pixel intensity-difference mask on a pyramid layer
-(Sec. 3.1 read per pixel, one mask for all octaves, Eq. 1 per feature
-position): every frame's D_n and cell mask against the oracle's, bit for
-bit, on every layer, with T_H, odd sizes, mode switches and frame modes."""
+"""GPU parity of the per-pixel intensity-difference masks of Sec. 3.1 with
+Eq. 1 per feature position: one mask on a pyramid layer for all octaves
+(mode 1) and one mask per octave on its own level (mode 2). Every frame's
+D_n and cell mask against the oracle's, bit for bit, on every layer, with
+T_H, odd sizes, mode switches and frame modes."""
 import numpy as np
 import pytest
 
@@ -94,9 +95,37 @@ def test_layer_shapes(kpd, W, H, det, layer):
     run_layer(kpd, synth.make_video(sc), det, {0: (1, layer)})
 
 
+def test_c1_octave_masks(kpd):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 16)
+    run_layer(kpd, frames, det_of("c1_320x240"), {0: (2, 0)})
+
+
+def test_c2_octave_masks_60_frames(kpd):
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 60)
+    run_layer(kpd, frames, det_of("c2_640x480"), {0: (2, 0)})
+    run_layer(kpd, frames[:20], det_of("c2_640x480", TH=3), {0: (2, 0)})
+
+
+def test_c3_octave_masks(kpd):
+    frames = synth.make_video(synth.SCENES["c3_1920x1080"], 8)
+    run_layer(kpd, frames, det_of("c3_1920x1080"), {0: (2, 0)}, mode="device")
+
+
+@pytest.mark.parametrize("W,H,det", [
+    (333, 251, (25, 4, 7, 5, 4, KB_OFF)),
+    (127, 255, (15, 7, 1, 2, 8, KB_OFF)),
+    (101, 77, (15, 4, 6, 4, 4, 3)),
+    (9, 13, (10, 2, 3, 2, 2, 3)),
+    (64, 48, (12, 1, 2, 2, 6, KB_OFF)),        # one octave: the same as one mask on level 0
+])
+def test_octave_mask_shapes(kpd, W, H, det):
+    sc = synth.Scene(W, H, 6, 6, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 970 + W)
+    run_layer(kpd, synth.make_video(sc), det, {0: (2, 0)})
+
+
 def test_mode_switches_and_frame_modes(kpd):
-    frames = synth.make_video(synth.SCENES["c1_320x240"], 14)
-    plan = {0: (1, 2), 4: (0, 0), 7: (1, 0), 10: (1, 1)}
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 18)
+    plan = {0: (1, 2), 4: (0, 0), 7: (1, 0), 10: (2, 0), 13: (1, 1), 15: (2, 0)}
     for mode in ("retain", "host", "device"):
         run_layer(kpd, frames, det_of("c1_320x240"), plan, mode=mode)
 
@@ -113,12 +142,15 @@ def test_layer_readback_and_errors(kpd):
                                              layer_mask=1))
     with pytest.raises(kpd.KpdError):
         g.set_mask_mode(1, d.n_octaves)                 # no such layer
-    g.set_mask_mode(1, 1)
-    for f in frames:
-        g.push(f)
-        ref = oracle.pyramid(f, d.n_octaves)
-        for o in range(1, d.n_octaves):
-            np.testing.assert_array_equal(g.level(o), ref[o])   # octave 1 alternates buffers
+    with pytest.raises(kpd.KpdError):
+        g.set_mask_mode(2, 1)                           # mode 2 takes no layer
+    for mode, layer in ((1, 1), (2, 0)):
+        g.set_mask_mode(mode, layer)
+        for f in frames:
+            g.push(f)
+            ref = oracle.pyramid(f, d.n_octaves)
+            for o in range(1, d.n_octaves):
+                np.testing.assert_array_equal(g.level(o), ref[o])   # the masked octaves alternate buffers
     with pytest.raises(kpd.KpdError):
         g.push_chunk(torch.from_numpy(frames).cuda())   # chunks keep the per-cell mask
     g.close()
