@@ -262,6 +262,51 @@ def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> 
     return out
 
 
+def layer_study(kpd, wl: Workload, args) -> dict:
+    """The mask variants side by side on one workload (the paper tries every
+    layer and keeps the top one since results are alike): per-frame push
+    throughput, the share of cells whose mask is set, and how much of each
+    frame's full detection F(I_n) the carried set D_n reproduces exactly
+    (same position, octave and score)."""
+    import numpy as np
+    import torch
+    full = open_stream(wl, -1)
+    ref = []
+    for i in range(wl.F):
+        kpd.push_frame(full.handle, wl.dev[i], retain=True)
+        ref.append(np.sort(full.keypoints()[0].view(np.uint64)))
+    full.close()
+    variants = [("cell_mean_level0", None)] + [(f"layer{l}", (1, l)) for l in range(wl.det.n_octaves)] + \
+               [("per_octave", (2, 0))]
+    out = {}
+    for name, mode in variants:
+        s = open_stream(wl, wl.det.id_thresh, layer_mask=mode is not None)
+        if mode is not None:
+            s.set_mask_mode(*mode)
+        sec = timed_passes(kpd, s, wl, max(1, args.steps // 5), 1)
+        kpd.reset_stream(s.handle)
+        hit = tot_ref = tot_d = marked = 0
+        for i in range(wl.F):
+            kpd.push_frame(s.handle, wl.dev[i], retain=True)
+            k, m = s.keypoints()
+            d = np.sort(k.view(np.uint64))
+            hit += len(np.intersect1d(d, ref[i], assume_unique=True))
+            tot_ref += len(ref[i])
+            tot_d += len(d)
+            if i:
+                marked += int(m.sum())
+        s.close()
+        out[name] = {"mpix_per_s": round(wl.F * wl.W * wl.H / sec / 1e6, 1),
+                     "marked_cell_frac": round(marked / max(1, (wl.F - 1) * wl.ncell), 4),
+                     "recall_of_full_detection": round(hit / max(1, tot_ref), 4),
+                     "precision_vs_full_detection": round(hit / max(1, tot_d), 4),
+                     "keypoints_per_frame": round(tot_d / wl.F, 1)}
+    torch.cuda.synchronize()
+    return {"what": f"{wl.name}, T_I={wl.det.id_thresh}, T_H off, one push_frame per frame; recall = share of "
+                    "F(I_n) found unchanged in D_n, precision = share of D_n that is in F(I_n)",
+            "full_detection_keypoints_per_frame": round(sum(len(r) for r in ref) / wl.F, 1), "variants": out}
+
+
 def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True, chunk=0,
                  layer=None):
     """layer: None for the per-cell mean-difference mask, else the pyramid
@@ -721,6 +766,8 @@ def main():
         "touched_cell_frac": round(sum(lm["marked"][1:]) / max(1, (wl.F - 1) * wl.ncell), 4),
         "roofline": roofline_of(wl, lm, True),
     }
+    log("[bench] layer study")
+    out["layer_study"] = layer_study(kpd, wl, args)
     out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:
         del wl
