@@ -67,7 +67,7 @@ struct Layout {
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
     size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0, off_work = 0;
-    size_t off_cntw = 0, off_ctab = 0, off_ftab = 0;
+    size_t off_cntw = 0, off_ctab = 0;
     size_t list_cap = 0;    // entries of chunk and sparse lists: one feature per 2x2 decision block
     size_t list_cap1 = 0;   // entries of the single-frame D lists: every decision pixel with layer_mask
     int lds_bytes = 0;   // dynamic LDS of the cell pass
@@ -243,7 +243,6 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
         L->off_clist = off; off += L->clist_stride * (size_t)(L->K - 1);   // the last frame's D goes to D_n
         L->off_ctab = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs));
-        L->off_ftab = off; off = align_up(off + (size_t)L->K * sizeof(kpd::FrameArgs));
     }
     L->total = off;
     return true;
@@ -293,6 +292,7 @@ struct kpd_stream {
     int id_layer = 0;
     int layer_buf = 0;        // the mask's octaves >= 1 of the latest frame: 0 their usual buffers, 1 the second copy
     int chunk_n = 0;          // frames of the last push_frames call
+    kpd::FrameArgs chunk_fa{};  // tile-pass arguments of chunk frame 0
     bool closed = false;
     // pinned host staging for get_keypoints: header, the first kStage
     // entries of D_n and the mask come back in one round trip
@@ -357,7 +357,8 @@ namespace {
 
 // Fixed per-frame arguments of the chunk passes: frame j's octave copy, SAD
 // accumulators, sparse list, count words and marks. What changes between
-// chunks travels in the ChunkHead kernel argument.
+// chunks travels in the ChunkHead kernel argument. The tile pass takes
+// frame 0's FrameArgs and steps to frame j's octaves and SAD itself.
 void chunk_tables(kpd_stream* s, std::vector<kpd::ChunkArgs>* ctab, std::vector<kpd::FrameArgs>* ftab)
 {
     const Layout& L = s->L;
@@ -498,9 +499,7 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->arena + L.off_ctab, ctab.data(), ctab.size() * sizeof(kpd::ChunkArgs),
                                hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->arena + L.off_ftab, ftab.data(), ftab.size() * sizeof(kpd::FrameArgs),
-                               hipMemcpyHostToDevice, s->stream);
+        s->chunk_fa = ftab[0];   // later frames' octaves and SAD follow at fixed strides
     }
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&s->stage), 64 + kStage * sizeof(kpd_keypoint) + (size_t)L.ncell,
@@ -760,10 +759,10 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     const bool any_tiles = L.O > 1 || (s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
                                        (n_frames > 1 || !h.force0));
     const kpd::ChunkArgs* ctab = s->at<kpd::ChunkArgs>(L.off_ctab);
-    const kpd::FrameArgs* ftab = s->at<kpd::FrameArgs>(L.off_ftab);
     if (any_tiles)
         KPD_HIP(timed(s, KPD_K_FRAME, [&] {
-            return kpd::launch_frame_chunk(ftab, h, kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots), s->stream);
+            return kpd::launch_frame_chunk(s->chunk_fa, L.pyr_stride, h, kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots),
+                                           s->stream);
         }));
     if (h.all_marked || h.kb_chain) {
         // every cell, or marks that wait on the previous frame's counts:

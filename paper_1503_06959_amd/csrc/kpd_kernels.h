@@ -30,13 +30,16 @@ struct FrameArgs {
     const uint16_t* rowmap;   // cell row of every level-0 row (H entries)
 };
 
-// The frame-dependent inputs of one tile pass.
+// The frame-dependent inputs of one tile pass: the frames, and where this
+// frame's octaves (FrameArgs::lvl + lvl_off) and SAD accumulators go.
 struct FrameSrc {
     const uint8_t* cur;
     const uint8_t* prev;
     int cur_pitch, prev_pitch;
     int cur_aligned, prev_aligned;
     int sad_on;
+    size_t lvl_off;
+    uint32_t* sad;
 };
 
 // k_detect: per-cell mark, detection, look-back offsets and output.
@@ -169,7 +172,7 @@ struct CompactArgs {
     uint32_t* work_count;            // cleared for the next chunk
 };
 
-hipError_t launch_frame_chunk(const FrameArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
+hipError_t launch_frame_chunk(const FrameArgs& a, size_t pyr_stride, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s);
 hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);

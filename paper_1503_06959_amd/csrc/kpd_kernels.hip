@@ -40,6 +40,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <type_traits>
 
 #include "kpd_geom.h"
 #include "kpd_kernels.h"
@@ -47,6 +48,7 @@
 namespace kpd {
 
 constexpr int kFrameBlock = 256;
+constexpr int kRegOctaves = 6;   // 128-px tiles build up to this many levels in registers
 constexpr int kBlk = kDetectBlock;
 constexpr int kDetWaves = kDetectWaves;
 
@@ -58,6 +60,88 @@ __device__ __forceinline__ unsigned fast_div(unsigned i, uint64_t magic)
 
 // ------------------------------------------------------------------ k_frame
 
+// 2x2 mean with round-half-up ((a+b+c+d+2)>>2) of two rows of eight
+// pixels, rows a and b as two dwords each (pixel k in byte k % 4 of dword
+// k / 4): the four outputs, packed. Pair sums are formed in 16-bit lanes, so
+// no lane carries into the next.
+__device__ __forceinline__ uint32_t mean2x2(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1)
+{
+    constexpr uint32_t m = 0x00FF00FFu;
+    const uint32_t s0 = (((a0 & m) + ((a0 >> 8) & m) + (b0 & m) + ((b0 >> 8) & m) + 0x00020002u) >> 2) & m;
+    const uint32_t s1 = (((a1 & m) + ((a1 >> 8) & m) + (b1 & m) + ((b1 >> 8) & m) + 0x00020002u) >> 2) & m;
+    return ((s0 | (s0 >> 8)) & 0xFFFFu) | ((s1 | (s1 >> 8)) << 16);
+}
+
+// Store the first n bytes of packed pixels at level position (gx, gy) of
+// `out`, clipped to the level's w x h; one wide store when the run is whole.
+template <int N>
+__device__ __forceinline__ void store_px(uint8_t* out, int pitch, int w, int h, int gx, int gy, uint32_t lo,
+                                         uint32_t hi)
+{
+    if (gy >= h || gx >= w) return;
+    uint8_t* p = out + (size_t)gy * pitch + gx;
+    if (gx + N - 1 < w) {
+        if constexpr (N == 8) *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
+        else if constexpr (N == 4) *reinterpret_cast<uint32_t*>(p) = lo;
+        else if constexpr (N == 2) *reinterpret_cast<uint16_t*>(p) = (uint16_t)lo;
+        else *p = (uint8_t)lo;
+        return;
+    }
+    for (int k = 0; k < N && gx + k < w; ++k) p[k] = (uint8_t)((k < 4 ? lo : hi) >> (8 * (k & 3)));
+}
+
+// Octaves 1..O-1 (O <= 6) of a 128-px tile from registers: thread (rb, seg)
+// holds level-0 rows 4rb..4rb+3, columns 16seg..16seg+15 (rows[u], one
+// uint4 each), so its level-1 block (2 x 8) and level-2 block (1 x 4) are
+// its own; level 3 pairs it with the thread one row block down (8 lanes
+// on), level 4 with the threads 16 and 24 lanes on, and level 5 with the
+// thread 32 lanes on and the next segment. Outputs go straight to the
+// level buffers.
+__device__ __forceinline__ void pyramid_regs(const FrameArgs& a, const FrameSrc& f, const uint4* rows, int x0,
+                                             int y0, int rb, int seg)
+{
+    if (a.O <= 1) return;
+    const uint32_t r[4][4] = {{rows[0].x, rows[0].y, rows[0].z, rows[0].w},
+                              {rows[1].x, rows[1].y, rows[1].z, rows[1].w},
+                              {rows[2].x, rows[2].y, rows[2].z, rows[2].w},
+                              {rows[3].x, rows[3].y, rows[3].z, rows[3].w}};
+    uint32_t l1[2][2];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) l1[y][k] = mean2x2(r[2 * y][2 * k], r[2 * y][2 * k + 1], r[2 * y + 1][2 * k],
+                                                       r[2 * y + 1][2 * k + 1]);
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+        store_px<8>(a.lvl[1] + f.lvl_off, a.pitch[1], a.w[1], a.h[1], (x0 >> 1) + 8 * seg, (y0 >> 1) + 2 * rb + y,
+                    l1[y][0], l1[y][1]);
+    if (a.O <= 2) return;
+    const uint32_t l2 = mean2x2(l1[0][0], l1[0][1], l1[1][0], l1[1][1]);
+    store_px<4>(a.lvl[2] + f.lvl_off, a.pitch[2], a.w[2], a.h[2], (x0 >> 2) + 4 * seg, (y0 >> 2) + rb, l2, 0u);
+    if (a.O <= 3) return;
+    // level 3: rows rb (even) and rb + 1, four pixels each -> two pixels
+    const uint32_t l2d = (uint32_t)__shfl_down((int)l2, 8);
+    const uint32_t l3 = mean2x2(l2, 0u, l2d, 0u) & 0xFFFFu;
+    if ((rb & 1) == 0)
+        store_px<2>(a.lvl[3] + f.lvl_off, a.pitch[3], a.w[3], a.h[3], (x0 >> 3) + 2 * seg, (y0 >> 3) + rb / 2, l3,
+                    0u);
+    if (a.O <= 4) return;
+    // level 4: level-3 rows rb/2 and rb/2 + 1 (threads rb and rb + 2) -> one pixel
+    const uint32_t l3d = (uint32_t)__shfl_down((int)l3, 16);
+    const uint32_t l4 = mean2x2(l3, 0u, l3d, 0u) & 0xFFu;
+    if ((rb & 3) == 0)
+        store_px<1>(a.lvl[4] + f.lvl_off, a.pitch[4], a.w[4], a.h[4], (x0 >> 4) + seg, (y0 >> 4) + rb / 4, l4, 0u);
+    if (a.O <= 5) return;
+    // level 5: level-4 pixels of (rb, seg), (rb, seg + 1), (rb + 4, seg), (rb + 4, seg + 1)
+    const uint32_t l4r = (uint32_t)__shfl_down((int)l4, 1);
+    const uint32_t l4d = (uint32_t)__shfl_down((int)l4, 32);
+    const uint32_t l4dr = (uint32_t)__shfl_down((int)l4, 33);
+    const uint32_t l5 = (l4 + l4r + l4d + l4dr + 2) >> 2;
+    if ((rb & 7) == 0 && (seg & 1) == 0)
+        store_px<1>(a.lvl[5] + f.lvl_off, a.pitch[5], a.w[5], a.h[5], (x0 >> 5) + seg / 2, (y0 >> 5) + rb / 8, l5,
+                    0u);
+}
+
 template <int B>
 __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int by, uint8_t* sm)
 {
@@ -66,28 +150,91 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
     const int x0 = bx * T, y0 = by * T;
     const int lgq = __builtin_ctz(T / 4);
 
-    // per-level output pointers and sizes, with static indices only
+    // 1) level-0 loads (and I_{n-1}'s for the SAD), issued first: nothing
+    //    they need comes from memory, so their latency overlaps the table
+    //    set-up below. 128-px tiles (B = 0): thread (rb, seg) holds rows
+    //    4rb..4rb+3, columns 16seg..16seg+15, so eight lanes read a whole
+    //    128-byte row; a row segment inside the frame and 16-byte aligned is
+    //    one 16-byte load. Smaller tiles: each thread holds one dword column
+    //    of the tile, B rows kFrameBlock*4/T apart (T*T/4 <= B*kFrameBlock).
+    constexpr int NV = B == 0 ? 4 : B;
+    using Word = typename std::conditional<B == 0, uint4, uint32_t>::type;
+    Word v[NV], pv[NV];
+    const int rb = tid >> 3, seg = tid & 7;   // B = 0
+    const int cx = 16 * seg, gxs = x0 + cx;
+    const int cq = tid & (T / 4 - 1), gx = x0 + 4 * cq;   // B > 0
+    const int ry0 = tid >> lgq, rstep = kFrameBlock >> lgq;
+    if constexpr (B == 0) {
+        auto load = [&](const uint8_t* row, bool al) -> uint4 {
+            const uint8_t* src = row + gxs;
+            if (al && gxs + 15 < a.W && (reinterpret_cast<uintptr_t>(src) & 15) == 0)
+                return *reinterpret_cast<const uint4*>(src);
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int g = gxs + 4 * d;
+                if (al && g + 3 < a.W) {
+                    w[d] = *reinterpret_cast<const uint32_t*>(src + 4 * d);
+                } else {
+                    for (int k = 0; k < 4; ++k)
+                        if (g + k < a.W) w[d] |= (uint32_t)src[4 * d + k] << (8 * k);
+                }
+            }
+            return make_uint4(w[0], w[1], w[2], w[3]);
+        };
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int gy = y0 + 4 * rb + u;
+            v[u] = make_uint4(0u, 0u, 0u, 0u);
+            pv[u] = v[u];
+            if (gy < a.H && gxs < a.W) {
+                v[u] = load(f.cur + (size_t)gy * f.cur_pitch, f.cur_aligned);
+                if (f.sad_on) pv[u] = load(f.prev + (size_t)gy * f.prev_pitch, f.prev_aligned);
+            }
+        }
+        if (a.O <= kRegOctaves) pyramid_regs(a, f, v, x0, y0, rb, seg);
+    } else {
+        auto load = [&](const uint8_t* src, bool al) -> uint32_t {
+            if (al) return *reinterpret_cast<const uint32_t*>(src);
+            uint32_t w = 0;
+            for (int k = 0; k < 4; ++k)
+                if (gx + k < a.W) w |= (uint32_t)src[k] << (8 * k);
+            return w;
+        };
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int ry = ry0 + u * rstep;
+            const int gy = y0 + ry;
+            v[u] = 0;
+            pv[u] = 0;
+            if (ry < T && gy < a.H && gx < a.W) {
+                v[u] = load(f.cur + (size_t)gy * f.cur_pitch + gx, f.cur_aligned);
+                if (f.sad_on) pv[u] = load(f.prev + (size_t)gy * f.prev_pitch + gx, f.prev_aligned);
+            }
+        }
+    }
+
+    // 2) per-level output pointers and sizes (static indices only), and the
+    //    tile's column/row -> local cell tables from the stream's maps
+    //    (column X is in cell column floor(X * Nc / W)). LDS: level buffers
+    //    (T^2, (T/2)^2, ...), then the per-cell SAD partials and the tables.
     __shared__ uint8_t* s_out[KPD_MAX_OCTAVES];
     __shared__ int s_pitch[KPD_MAX_OCTAVES], s_w[KPD_MAX_OCTAVES], s_h[KPD_MAX_OCTAVES];
     if (tid == 0) {
 #pragma unroll
         for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
-            s_out[o] = a.lvl[o];
+            s_out[o] = a.lvl[o] + f.lvl_off;
             s_pitch[o] = a.pitch[o];
             s_w[o] = a.w[o];
             s_h[o] = a.h[o];
         }
     }
-    // LDS: level buffers (T^2, (T/2)^2, ...), then the per-cell SAD partials
-    // and the tile's column/row -> local cell tables.
     uint32_t* sadl = reinterpret_cast<uint32_t*>(sm + a.sad_lds_off);
     uint16_t* colcell = reinterpret_cast<uint16_t*>(sm + a.sad_lds_off + 4 * a.sad_slots);
     uint16_t* rowcell = colcell + T;
     const int xe = min(x0 + T, a.W), ye = min(y0 + T, a.H);
     int cx0 = 0, cy0 = 0, ncx = 1, ncy = 1;
     if (f.sad_on) {
-        // cells of the tile's columns and rows from the stream's maps
-        // (column X is in cell column floor(X * Nc / W))
         cx0 = a.colmap[x0];
         cy0 = a.rowmap[y0];
         ncx = a.colmap[xe - 1] - cx0 + 1;
@@ -100,25 +247,16 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
     }
     __syncthreads();
 
-    // level 0 tile (and the SAD against I_{n-1}). Each thread keeps one
-    // dword column of the tile (T/4 <= kFrameBlock) and walks down rows
-    // kFrameBlock*4/T apart, loading B rows per step (all of them) so that the
-    // loads are in flight together. The SAD of consecutive dwords of one
-    // cell is summed in a register and added to the cell's LDS slot when
-    // the cell changes; dwords straddling a cell column border go byte by
-    // byte.
+    // 3) the level-0 tile into LDS, and the SAD against I_{n-1}: the SAD of
+    //    consecutive dwords of one cell is summed in a register and added to
+    //    the cell's LDS slot when the cell changes; dwords straddling a cell
+    //    column border go byte by byte.
     uint8_t* L0 = sm;
     uint32_t acc = 0;
     int acc_slot = -1;
     if constexpr (B == 0) {
-        // 128-px tiles: thread (rb, seg) holds rows 4rb..4rb+3, columns
-        // 16seg..16seg+15, so eight lanes read a whole 128-byte row; a row
-        // segment inside the frame and 16-byte aligned is one 16-byte load.
         // A segment's SAD goes to at most two cells (its first dword's and
         // its last dword's), summed in registers while the row cell stays.
-        const int rb = tid >> 3, seg = tid & 7;
-        const int cx = 16 * seg;
-        const int gxs = x0 + cx;
         int cc[4];
         bool two = true;   // every dword in one cell, the first's or the last's
         if (f.sad_on) {
@@ -129,42 +267,12 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
             }
             two = two && (cc[1] == cc[0] || cc[1] == cc[3]) && (cc[2] == cc[0] || cc[2] == cc[3]);
         }
-        uint4 v[4], pv[4];
-        auto load = [&](const uint8_t* row, bool al) -> uint4 {
-            uint4 r = make_uint4(0u, 0u, 0u, 0u);
-            const uint8_t* src = row + gxs;
-            if (al && gxs + 15 < a.W && (reinterpret_cast<uintptr_t>(src) & 15) == 0)
-                return *reinterpret_cast<const uint4*>(src);
-            uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const int gx = gxs + 4 * d;
-                if (al && gx + 3 < a.W) {
-                    w[d] = *reinterpret_cast<const uint32_t*>(src + 4 * d);
-                } else {
-                    for (int k = 0; k < 4; ++k)
-                        if (gx + k < a.W) w[d] |= (uint32_t)src[4 * d + k] << (8 * k);
-                }
-            }
-            r.x = w[0]; r.y = w[1]; r.z = w[2]; r.w = w[3];
-            return r;
-        };
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int gy = y0 + 4 * rb + u;
-            v[u] = make_uint4(0u, 0u, 0u, 0u);
-            pv[u] = v[u];
-            if (gy < a.H && gxs < a.W) {
-                v[u] = load(f.cur + (size_t)gy * f.cur_pitch, f.cur_aligned);
-                if (f.sad_on) pv[u] = load(f.prev + (size_t)gy * f.prev_pitch, f.prev_aligned);
-            }
-        }
         uint32_t accr = 0;   // the segment's second cell
         int row_slot = -1;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int ry = 4 * rb + u;
-            *reinterpret_cast<uint4*>(L0 + ry * T + cx) = v[u];
+            if (a.O > kRegOctaves) *reinterpret_cast<uint4*>(L0 + ry * T + cx) = v[u];
             const int gy = y0 + ry;
             if (!f.sad_on || gy >= a.H || gxs >= a.W) continue;
             const int rc = rowcell[ry] * ncx;
@@ -198,60 +306,28 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
             if (accr) atomicAdd(&sadl[row_slot + cc[3]], accr);
         }
     } else {
-        const int ndw = T * T / 4;
-        const int cq = tid & (T / 4 - 1);
-        const int gx = x0 + 4 * cq;
-        const int rstep = kFrameBlock >> lgq;   // rows between a thread's dwords
         const bool straddle = f.sad_on && (gx + 3 >= a.W || colcell[4 * cq] != colcell[4 * cq + 3]);
-        for (int i0 = tid; i0 < ndw; i0 += B * kFrameBlock) {
-            uint32_t v[B], pv[B];
-    #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int ry = (i0 >> lgq) + u * rstep;
-                const int gy = y0 + ry;
-                v[u] = 0;
-                pv[u] = 0;
-                if (ry < T && gy < a.H && gx < a.W) {
-                    const uint8_t* src = f.cur + (size_t)gy * f.cur_pitch + gx;
-                    if (f.cur_aligned) {
-                        v[u] = *reinterpret_cast<const uint32_t*>(src);
-                    } else {
-                        for (int k = 0; k < 4; ++k)
-                            if (gx + k < a.W) v[u] |= (uint32_t)src[k] << (8 * k);
-                    }
-                    if (f.sad_on) {
-                        const uint8_t* ps = f.prev + (size_t)gy * f.prev_pitch + gx;
-                        if (f.prev_aligned) {
-                            pv[u] = *reinterpret_cast<const uint32_t*>(ps);
-                        } else {
-                            for (int k = 0; k < 4; ++k)
-                                if (gx + k < a.W) pv[u] |= (uint32_t)ps[k] << (8 * k);
-                        }
-                    }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int ry = ry0 + u * rstep;
+            if (ry >= T) continue;
+            *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v[u];
+            const int gy = y0 + ry;
+            if (!f.sad_on || gy >= a.H || gx >= a.W) continue;
+            const int rc = rowcell[ry] * ncx;
+            if (!straddle) {
+                const int slot = rc + colcell[4 * cq];
+                const uint32_t d = __builtin_amdgcn_sad_u8(v[u], pv[u], 0u);
+                if (slot != acc_slot) {
+                    if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
+                    acc_slot = slot;
+                    acc = 0;
                 }
-            }
-    #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int ry = (i0 >> lgq) + u * rstep;
-                if (ry >= T) continue;
-                *reinterpret_cast<uint32_t*>(L0 + ry * T + 4 * cq) = v[u];
-                const int gy = y0 + ry;
-                if (!f.sad_on || gy >= a.H || gx >= a.W) continue;
-                const int rc = rowcell[ry] * ncx;
-                if (!straddle) {
-                    const int slot = rc + colcell[4 * cq];
-                    const uint32_t d = __builtin_amdgcn_sad_u8(v[u], pv[u], 0u);
-                    if (slot != acc_slot) {
-                        if (acc_slot >= 0 && acc) atomicAdd(&sadl[acc_slot], acc);
-                        acc_slot = slot;
-                        acc = 0;
-                    }
-                    acc += d;
-                } else {
-                    for (int k = 0; k < 4 && gx + k < a.W; ++k) {
-                        const uint32_t m = 0xFFu << (8 * k);
-                        atomicAdd(&sadl[rc + colcell[4 * cq + k]], __builtin_amdgcn_sad_u8(v[u] & m, pv[u] & m, 0u));
-                    }
+                acc += d;
+            } else {
+                for (int k = 0; k < 4 && gx + k < a.W; ++k) {
+                    const uint32_t m = 0xFFu << (8 * k);
+                    atomicAdd(&sadl[rc + colcell[4 * cq + k]], __builtin_amdgcn_sad_u8(v[u] & m, pv[u] & m, 0u));
                 }
             }
         }
@@ -261,9 +337,11 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
     if (f.sad_on) {
         for (int i = tid; i < ncx * ncy; i += kFrameBlock) {
             const uint32_t s = sadl[i];
-            if (s) atomicAdd(&a.sad[(cy0 + i / ncx) * a.nc + cx0 + i % ncx], s);
+            if (s) atomicAdd(&f.sad[(cy0 + i / ncx) * a.nc + cx0 + i % ncx], s);
         }
     }
+
+    if (B == 0 && a.O <= kRegOctaves) return;   // octaves already written from registers
 
     // coarser octaves, four outputs per thread while a level row holds >= 4
     int src_off = 0;
@@ -1174,7 +1252,7 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame1(FrameArgs a)
     extern __shared__ __align__(16) uint8_t sm[];
     const int tile = xcd_band_tile(blockIdx.x, a.ntiles);
     if (tile >= a.ntiles) return;
-    const FrameSrc f{a.cur, a.prev, a.cur_pitch, a.prev_pitch, a.cur_aligned, a.prev_aligned, a.sad_on};
+    const FrameSrc f{a.cur, a.prev, a.cur_pitch, a.prev_pitch, a.cur_aligned, a.prev_aligned, a.sad_on, 0, a.sad};
     frame_tile(a, f, tile % a.tiles_x, tile / a.tiles_x, sm);
 }
 
@@ -1185,15 +1263,16 @@ __global__ __launch_bounds__(kBlk) void k_detect1(DetectArgs a)
 }
 
 // Tile pass of a chunk: tiles of all its frames banded over the XCDs;
-// frame j's tile source is frame j of the chunk and its predecessor.
-__global__ __launch_bounds__(kFrameBlock) void k_frame_chunk(const FrameArgs* table, ChunkHead h)
+// frame j's tile source is frame j of the chunk and its predecessor, its
+// octaves go pyr_stride * j bytes past frame 0's and its SAD accumulators
+// one cell grid past frame j-1's. Every workgroup reads the same arguments.
+__global__ __launch_bounds__(kFrameBlock) void k_frame_chunk(FrameArgs a, ChunkHead h, size_t pyr_stride)
 {
     extern __shared__ __align__(16) uint8_t sm[];
     const int nblocks = h.n_frames * h.ntiles;
     const int b = xcd_band_tile(blockIdx.x, nblocks);
     if (b >= nblocks) return;
     const int j = b / h.ntiles, local = b - j * h.ntiles;
-    const FrameArgs& a = table[j];
     const bool sad_on = !chunk_all_marked(h, j) && h.id_thresh < 255;
     if (a.O == 1 && !sad_on) return;
     FrameSrc f;
@@ -1204,6 +1283,8 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame_chunk(const FrameArgs* ta
     f.prev_pitch = j == 0 ? h.prev0_pitch : h.pitch;
     f.prev_aligned = j == 0 ? h.prev0_aligned : h.aligned;
     f.sad_on = sad_on ? 1 : 0;
+    f.lvl_off = pyr_stride * (size_t)j;
+    f.sad = a.sad + (size_t)j * (a.nc * a.nr);
     frame_tile(a, f, local % a.tiles_x, local / a.tiles_x, sm);
 }
 
@@ -1409,7 +1490,7 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame_batch(const TickArgs* tab
     const int local = b - t.tile_base;
     if (!t.active || !t.f_on) return;
     const FrameArgs& a = t.f;
-    const FrameSrc f{a.cur, a.prev, a.cur_pitch, a.prev_pitch, a.cur_aligned, a.prev_aligned, a.sad_on};
+    const FrameSrc f{a.cur, a.prev, a.cur_pitch, a.prev_pitch, a.cur_aligned, a.prev_aligned, a.sad_on, 0, a.sad};
     frame_tile(a, f, local % a.tiles_x, local / a.tiles_x, sm);
 }
 
@@ -1528,6 +1609,7 @@ hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, 
 
 int frame_sad_lds_off(int tile, int O)
 {
+    if (tile == 128 && O <= kRegOctaves) return 0;   // no level buffers in LDS
     int lv = 0;
     for (int o = 0; o < O; ++o) lv += (tile >> o) * (tile >> o);
     return round_up(lv, 16);
@@ -1572,11 +1654,11 @@ hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_frame_chunk(const FrameArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
+hipError_t launch_frame_chunk(const FrameArgs& a, size_t pyr_stride, const ChunkHead& h, int lds_bytes, hipStream_t s)
 {
     const int nblocks = h.n_frames * h.ntiles;
     const int grid = (nblocks + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(k_frame_chunk, dim3(grid), dim3(kFrameBlock), lds_bytes, s, table, h);
+    hipLaunchKernelGGL(k_frame_chunk, dim3(grid), dim3(kFrameBlock), lds_bytes, s, a, h, pyr_stride);
     return hipGetLastError();
 }
 

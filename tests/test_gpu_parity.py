@@ -29,13 +29,13 @@ def orc_tuples(arr):
     return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
 
 
-def run_pair(kpd, frames, det, mode="host", thresholds=None, check_sad=True):
+def run_pair(kpd, frames, det, mode="host", thresholds=None, check_sad=True, tile=0):
     """Push frames through a GPU stream and an oracle stream, compare every
     frame. thresholds: {frame_index: (t, TI, TH)} applied before that frame."""
     import torch
     F, H, W = frames.shape
     t, O, Nc, Nr, TI, TH = det
-    params = kpd.make_params(t, O, Nc, Nr, TI, TH)
+    params = kpd.make_params(t, O, Nc, Nr, TI, TH, tile)
     g = kpd.Stream(W, H, params)
     o = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
     dev = torch.from_numpy(frames).cuda() if mode != "host" else None
@@ -236,6 +236,39 @@ def test_pyramid_levels_match_oracle(kpd):
     for o in range(1, 7):
         np.testing.assert_array_equal(g.level(o), ref[o])
     g.close()
+
+
+@pytest.mark.parametrize("W,H", [(333, 201), (129, 127), (640, 480)])
+def test_pyramid_every_tile_and_depth(kpd, W, H):
+    # noise exercises the rounding; odd sizes the dropped last row and column
+    rng = np.random.default_rng(W)
+    frames = rng.integers(0, 256, size=(2, H, W), dtype=np.uint8)
+    for O in range(1, 9):
+        if (1 << (O - 1)) > min(W, H):
+            continue
+        ref = oracle.pyramid(frames[1], O)
+        for tile in (32, 64, 128):
+            if tile < (1 << (O - 1)):
+                continue
+            g = kpd.Stream(W, H, kpd.make_params(20, O, max(3, W // 40), max(2, H // 40), 8, 0xFFFFFFFF, tile))
+            for f in frames:
+                g.push(f)
+            for o in range(1, O):
+                np.testing.assert_array_equal(g.level(o), ref[o], err_msg=f"O={O} tile={tile} level {o}")
+            g.close()
+
+
+@pytest.mark.parametrize("W,H,det,tile", [
+    (333, 251, (25, 4, 7, 5, 4, 0xFFFFFFFF), 128),
+    (640, 480, (20, 4, 16, 12, 8, 0xFFFFFFFF), 128),
+    (1920, 1080, (20, 5, 32, 18, 8, 0xFFFFFFFF), 128),
+    (321, 243, (15, 6, 5, 4, 6, 3), 128),
+    (200, 150, (15, 1, 4, 3, 6, 0xFFFFFFFF), 128),
+])
+def test_wide_tiles_match_oracle(kpd, W, H, det, tile):
+    sc = synth.Scene(W, H, 10, 8, 3, max(4, min(W, H) // 4), 1.0, 2.0, False, 880 + W)
+    frames = synth.make_video(sc, 6)
+    run_pair(kpd, frames, det, mode="retain", tile=tile)
 
 
 # ----------------------------------------------------------------- ABI errors
