@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--serve-budget-mib", type=int, default=1024)
     ap.add_argument("--batch-ticks", type=int, default=120)
     ap.add_argument("--batch-clip", type=int, default=40)
-    ap.add_argument("--chunk", type=int, default=256, help="frames per push_frames call (at most 256)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="frames per push_frames call (at most 512; 0: the whole video in one call)")
     ap.add_argument("--mode", choices=("both", "masked", "full"), default="both",
                     help="masked or full: run only that pass of --workload and print its line (for profiling)")
     ap.add_argument("--chunked", action="store_true", help="with --mode: push --chunk frames per call")
@@ -305,6 +306,11 @@ def layer_study(kpd, wl: Workload, args) -> dict:
     return {"what": f"{wl.name}, T_I={wl.det.id_thresh}, T_H off, one push_frame per frame; recall = share of "
                     "F(I_n) found unchanged in D_n, precision = share of D_n that is in F(I_n)",
             "full_detection_keypoints_per_frame": round(sum(len(r) for r in ref) / wl.F, 1), "variants": out}
+
+
+def chunk_of(args, wl: Workload) -> int:
+    """Frames per push_frames call: --chunk, or the whole video (at most 512)."""
+    return args.chunk if args.chunk > 0 else min(wl.F, 512)
 
 
 def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True, chunk=0,
@@ -683,7 +689,7 @@ def main():
     wl = Workload(args.workload)
     if args.mode != "both":
         masked = args.mode == "masked"
-        chunk = args.chunk if args.chunked else 0
+        chunk = chunk_of(args, wl) if args.chunked else 0
         layer = args.layer if masked else None
         if layer is not None and chunk:
             sys.exit("--layer runs on single-frame pushes: leave out --chunked")
@@ -698,7 +704,7 @@ def main():
                           "latency_ms": {"p50": round(r["lat_p50"], 4), "p99": round(r["lat_p99"], 4)},
                           "roofline": roofline_of(wl, r, masked, stats=stats)}), flush=True)
         return
-    K = args.chunk
+    K = chunk_of(args, wl)
     log(f"[bench] masked pass, chunks of {K}")
     masked_c = run_workload(kpd, wl, wl.det.id_thresh, args, chunk=K)
     log(f"[bench] masked {masked_c['mpix_per_s']:.1f} Mpx/s; full-frame pass")

@@ -52,7 +52,7 @@ extern "C" {
 #define KPD_MAX_OCTAVES 8
 #define KPD_MAX_CELL 128        /* largest cell side, in level-0 pixels */
 #define KPD_MAX_DIM 16384       /* largest frame side */
-#define KPD_MAX_CHUNK 256       /* most frames per push_frames call */
+#define KPD_MAX_CHUNK 512       /* most frames per push_frames call */
 
 /* push_frame flags */
 #define KPD_FRAME_HOST 0          /* host pointer; copied into the arena */

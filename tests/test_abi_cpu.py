@@ -76,14 +76,14 @@ def test_chunk_frames_sizes_the_arena(kpd):
     base = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12))
     assert kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, chunk_frames=1)) == base
     prev = base
-    for K in (2, 8, 64, 256):
+    for K in (2, 8, 64, 256, 512):
         n = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, chunk_frames=K))
         # per chunk frame at least its octaves 1.. and one keypoint list
         pyr = sum((640 >> o) * (480 >> o) for o in range(1, 4))
         assert n >= base + (K - 1) * pyr + K * 8 * (317 // 2) * (237 // 2)
         assert n > prev
         prev = n
-    for K in (-1, 257):
+    for K in (-1, 513):
         p = kpd.make_params(20, 4, 16, 12, chunk_frames=K)
         assert kpd.lib.stream_bytes(640, 480, ctypes.byref(p)) == 0
 

@@ -194,24 +194,35 @@ def test_c1_chunk_of_256_frames(kpd):
 # ------------------------------------------- the launch configuration bench.py times
 
 def test_c2_300_frames_in_bench_chunks(kpd):
-    # the 640x480 video as the bench pushes it: one chunk of 256, one of 44
+    # the 640x480 video as the bench pushes it: all 300 frames in one call;
+    # and as one chunk of 256 and one of 44
     frames = synth.make_video(synth.SCENES["c2_640x480"], 300)
+    run_chunks(kpd, frames, det_of("c2_640x480"), [300], K=300)
     run_chunks(kpd, frames, det_of("c2_640x480"), [256, 44], K=256)
 
 
-def test_c3_300_frames_in_bench_chunks_sampled(kpd):
-    # 1920x1080 at full length through 256 + 44 frame chunks: every 10th
-    # frame and the last compared with the oracle stream; in full-frame mode
-    # sampled frames are compared with a fresh oracle stream's first frame
+def test_chunk_of_512_frames(kpd):
+    # the largest chunk: the compaction scans up to 512 mark bytes per cell
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 520)
+    run_chunks(kpd, frames, det_of("c1_320x240"), [512, 0, 8], K=512)
+
+
+@pytest.mark.parametrize("chunks", [((0, 300),), ((0, 256), (256, 44))])
+def test_c3_300_frames_in_bench_chunks_sampled(kpd, chunks):
+    # 1920x1080 at full length in one call (as the bench pushes it) or in
+    # 256 + 44 frame chunks: every 10th frame and the last compared with the
+    # oracle stream; in full-frame mode sampled frames are compared with a
+    # fresh oracle stream's first frame
     import torch
     sc = synth.SCENES["c3_1920x1080"]
     frames = synth.make_video(sc, 300)
     dev = torch.from_numpy(frames).cuda()
+    K = max(n for _, n in chunks)
     for TI in (8, -1):
         det = det_of("c3_1920x1080", TI=TI)
-        g = kpd.Stream(1920, 1080, kpd.make_params(*det, 0, 256))
+        g = kpd.Stream(1920, 1080, kpd.make_params(*det, 0, K))
         got = {}
-        for start, n in ((0, 256), (256, 44)):
+        for start, n in chunks:
             g.push_chunk(dev[start:start + n])
             for j in range(n):
                 i = start + j
