@@ -267,8 +267,9 @@ struct KernelTimer {
     }
     ~KernelTimer()
     {
-        for (auto& p : pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
-        for (auto e : free_events) hipEventDestroy(e);
+        // teardown: nothing to report a failure to
+        for (auto& p : pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
+        for (auto e : free_events) (void)hipEventDestroy(e);
     }
 };
 
@@ -300,7 +301,7 @@ struct kpd_stream {
 
     ~kpd_stream()
     {
-        if (stage) hipHostFree(stage);
+        if (stage) (void)hipHostFree(stage);
     }
 
     template <typename T>
@@ -1001,7 +1002,7 @@ size_t batch_layout(int max_streams, int max_blocks, size_t* off_table, size_t* 
 void drop_graphs(kpd_batch* b)
 {
     for (int k = 0; k < 2; ++k)
-        if (b->graph[k]) { hipGraphExecDestroy(b->graph[k]); b->graph[k] = nullptr; }
+        if (b->graph[k]) { (void)hipGraphExecDestroy(b->graph[k]); b->graph[k] = nullptr; }
 }
 
 // Rebuild the workgroup -> stream maps after the attached set changed.
@@ -1178,10 +1179,10 @@ int batch_tick(kpd_batch* b)
             KPD_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             const hipError_t ce = enqueue_tick(b, k);
             const hipError_t ee = hipStreamEndCapture(b->stream, &g);
-            if (ce != hipSuccess) { if (g) hipGraphDestroy(g); return hip_fail(ce, "batch tick capture"); }
+            if (ce != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(ce, "batch tick capture"); }
             if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
             const hipError_t ie = hipGraphInstantiate(&b->graph[k], g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             if (ie != hipSuccess) { b->graph[k] = nullptr; return hip_fail(ie, "hipGraphInstantiate"); }
         }
         KPD_HIP(hipGraphLaunch(b->graph[k], b->stream));
@@ -1217,8 +1218,8 @@ int close_batch(kpd_batch* b)
     const hipError_t e = hipStreamSynchronize(b->stream);
     drop_graphs(b);
     for (int k = 0; k < 2; ++k) {
-        if (b->host_table[k]) hipHostFree(b->host_table[k]);
-        if (b->table_free[k]) hipEventDestroy(b->table_free[k]);
+        if (b->host_table[k]) (void)hipHostFree(b->host_table[k]);
+        if (b->table_free[k]) (void)hipEventDestroy(b->table_free[k]);
     }
     delete b;
     if (e != hipSuccess) return hip_fail(e, "close_batch");
