@@ -562,12 +562,19 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
         cur_dw = dword_readable(cur, cur_pitch, L.W, false);
     } else {
         uint8_t* dst = s->at<uint8_t>(L.off_slot[s->cur_slot]);
-        KPD_HIP(hipMemcpy2DAsync(dst, L.slot_pitch, frame, pitch_bytes, L.W, L.H,
-                                 flags == KPD_FRAME_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                                 s->stream));
+        const hipMemcpyKind kind = flags == KPD_FRAME_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        if (pitch_bytes <= (size_t)L.slot_pitch) {
+            // one linear copy that keeps the caller's pitch: the rows fit the
+            // slot, and dword reads past a row's end stay inside it
+            KPD_HIP(hipMemcpyAsync(dst, frame, pitch_bytes * (L.H - 1) + L.W, kind, s->stream));
+            cur_pitch = (int)pitch_bytes;
+            cur_dw = pitch_bytes % 4 == 0 ? 1 : 0;
+        } else {
+            KPD_HIP(hipMemcpy2DAsync(dst, L.slot_pitch, frame, pitch_bytes, L.W, L.H, kind, s->stream));
+            cur_pitch = L.slot_pitch;
+            cur_dw = 1;
+        }
         cur = dst;
-        cur_pitch = L.slot_pitch;
-        cur_dw = 1;
         s->cur_slot ^= 1;
     }
 

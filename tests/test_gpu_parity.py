@@ -149,6 +149,37 @@ def test_padded_pitch_frames(kpd):
     g.close()
 
 
+@pytest.mark.parametrize("pitch", [333, 336, 340, 384, 400])
+def test_copied_frames_every_pitch(kpd, pitch):
+    # copied frames keep the caller's pitch when their rows fit the 384-byte
+    # slot rows (one linear copy; odd pitches are read bytewise), else they
+    # are re-pitched by a 2D copy
+    import torch
+    sc = synth.Scene(333, 251, 8, 8, 3, 60, 1.0, 2.0, False, 4242)
+    frames = synth.make_video(sc)
+    buf = np.zeros((len(frames), 251 * pitch), np.uint8)
+    for i, f in enumerate(frames):
+        buf[i].reshape(251, pitch)[:, :333] = f
+    host = [buf[i].reshape(251, pitch)[:, :333] for i in range(len(frames))]
+    dev = torch.from_numpy(buf).cuda()
+    det = (25, 4, 7, 5, 4, KB_OFF)
+    g = kpd.Stream(333, 251, kpd.make_params(*det))
+    o = oracle.Stream(333, 251, *det)
+    for i in range(len(frames)):
+        if i % 2 == 0:
+            assert host[i].strides[0] == pitch
+            g.push(host[i])
+        else:
+            view = torch.as_strided(dev[i], (251, 333), (pitch, 1))
+            g.push(view, retain=False)
+        o.push(frames[i])
+        gk, gm = g.keypoints()
+        ok, om, _, _ = o.get()
+        assert gpu_tuples(gk) == orc_tuples(ok), f"frame {i}"
+        np.testing.assert_array_equal(gm, om, err_msg=f"mask frame {i}")
+    g.close()
+
+
 # ------------------------------------------------------------ special inputs
 
 def test_constant_frames_give_no_keypoints(kpd):
