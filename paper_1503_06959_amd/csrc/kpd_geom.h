@@ -135,9 +135,10 @@ KPD_HD uint64_t div_magic(unsigned d) { return (0x100000000ull + d - 1) / d; }
 // and where each level's pixel tile, score map and the bitmasks live in LDS.
 //
 // LDS layout (bytes): [keep bitmask: nwords x u64][candidate bitmask: nwords
-// x u64][word offsets: nwords x u32][wave queues: waves x kQueue x u16]
-// [score maps: u16 per level, each over its query box, zero outside the
-// score box][pixel tiles: u8 per level]. A level's pixel tile covers its score
+// x u64][word offsets: nwords x u32][score maps: u16 per level, each over its
+// query box, zero outside the score box][pixel tiles: u8 per level][wave
+// queues: waves x kQueue x u16]. The queues come last, so a workgroup of
+// fewer than kDetectWaves waves needs base_bytes + its waves' queues only. A level's pixel tile covers its score
 // box plus the 3-pixel ring apron; its first column is rounded down to a
 // multiple of 4 and its row pitch up to one, so that 4-byte aligned rows can
 // be loaded a dword at a time. Score pixels are tested in groups of four
@@ -165,7 +166,8 @@ struct CellLayout {
     int O;
     int nwords;                          // words of each bitmask
     int cand_off, woff_off, queue_off;
-    int bytes;
+    int base_bytes;                      // bytes before the queues (= queue_off)
+    int bytes;                           // with kDetectWaves queues
 };
 
 KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, CellLayout* L)
@@ -195,8 +197,6 @@ KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, Cell
     off += L->nwords * 8;
     L->woff_off = off;
     off += round_up(L->nwords * 4, 8);
-    L->queue_off = off;
-    off += kDetectWaves * kQueue * 2;
     int sc = 0, ck = 0;
     const int v0 = off;
     for (int o = 0; o < O; ++o) {
@@ -235,7 +235,13 @@ KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, Cell
         L->dcm[o] = div_magic(imax(box_w(L->dec[o]), 1));
         L->gcm[o] = div_magic(imax(L->ngx[o], 1));
     }
-    L->bytes = off;
+    L->queue_off = round_up(off, 16);
+    L->base_bytes = L->queue_off;
+    L->bytes = L->queue_off + kDetectWaves * kQueue * 2;
 }
+
+// Dynamic LDS of a detection workgroup of `waves` waves for cells whose
+// largest layout takes `bytes` (with kDetectWaves queues).
+KPD_HD int detect_lds_for(int bytes, int waves) { return bytes - (kDetectWaves - waves) * kQueue * 2; }
 
 }  // namespace kpd

@@ -48,9 +48,14 @@
 namespace kpd {
 
 constexpr int kFrameBlock = 256;
+// Detection workgroup sizes: 512 threads where one cell's latency decides
+// (single frames, chunks with few cells to detect), 256 where many cells are
+// in flight at once (more, smaller workgroups keep the CUs busier).
+constexpr int kDetLatency = kDetectBlock;
+constexpr int kDetThroughput = 256;
+// A chunk list pass takes the latency size up to this many (frame, cell) items.
+constexpr int kListLatencyItems = 65536;
 constexpr int kRegOctaves = 6;   // 128-px tiles build up to this many levels in registers
-constexpr int kBlk = kDetectBlock;
-constexpr int kDetWaves = kDetectWaves;
 
 // floor(i / d) with magic = div_magic(d) (see kpd_geom.h)
 __device__ __forceinline__ unsigned fast_div(unsigned i, uint64_t magic)
@@ -566,6 +571,7 @@ __device__ __forceinline__ void rank_words(const CellLayout& L, uint8_t* sm, uin
     __syncthreads();
 }
 
+template <int NT>
 __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lvl0_aligned, int c, uint8_t* sm,
                                               CellLayout& L, const uint8_t* const* s_lvl, const int* s_pitch,
                                               uint32_t* s_n, bool rank = true)
@@ -578,27 +584,27 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
-        for (int i = tid; i < (int)(sizeof(CellLayout) / 4); i += kBlk) dst[i] = src[i];
+        for (int i = tid; i < (int)(sizeof(CellLayout) / 4); i += NT) dst[i] = src[i];
     }
     __syncthreads();
     uint64_t* candw = reinterpret_cast<uint64_t*>(sm + L.cand_off);
-    for (int i = tid; i < L.nwords; i += kBlk) {
+    for (int i = tid; i < L.nwords; i += NT) {
         candw[i] = 0;
         keepw[i] = 0;
     }
     {
         uint32_t* v = reinterpret_cast<uint32_t*>(sm + L.voff[0]);
-        for (int i = tid; i < L.vbytes / 4; i += kBlk) v[i] = 0;
+        for (int i = tid; i < L.vbytes / 4; i += NT) v[i] = 0;
     }
 
     // 1) pixel tiles of every octave, a dword per load, four loads in flight
     const int nld = L.ld_start[O];
-    for (int base = tid; base < nld; base += 4 * kBlk) {
+    for (int base = tid; base < nld; base += 4 * NT) {
         uint32_t val[4];
         int dst[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int i = base + u * kBlk;
+            const int i = base + u * NT;
             dst[u] = -1;
             val[u] = 0;
             if (i < nld) {
@@ -657,7 +663,7 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
             q_head += count;
         };
         const int nck = L.ck_start[O];
-        for (int ck = wave; ck < nck; ck += kDetWaves) {
+        for (int ck = wave; ck < nck; ck += (NT / 64)) {
             const int o = level_of(L.ck_start, O, ck);
             const Box sb = L.sb[o];
             const int tp = L.tpitch[o], tx0 = L.tx0[o];
@@ -737,7 +743,7 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
         };
         constexpr uint32_t kWindow = kQueue - 64;   // entries added between drains
         const int nw = L.nwords;
-        for (int w0 = wave * 64; w0 < nw; w0 += kDetWaves * 64) {
+        for (int w0 = wave * 64; w0 < nw; w0 += (NT / 64) * 64) {
             const int w = w0 + lane;
             const uint64_t word = w < nw ? candw[w] : 0ull;
             const uint32_t cnt = (uint32_t)__popcll(word);
@@ -777,6 +783,7 @@ __device__ __forceinline__ void detect_marked(const DetectArgs& a, int t, int lv
 }
 
 // Step 6 for a marked cell: write its ranked maxima from position excl on.
+template <int NT>
 __device__ __forceinline__ void emit_marked(const DetectArgs& a, const CellLayout& L, const uint8_t* sm, uint32_t excl,
                             kpd_keypoint* list, uint32_t cap)
 {
@@ -784,7 +791,7 @@ __device__ __forceinline__ void emit_marked(const DetectArgs& a, const CellLayou
     const int O = a.O;
     const uint64_t* keepw = reinterpret_cast<const uint64_t*>(sm);
     const uint32_t* woff = reinterpret_cast<const uint32_t*>(sm + L.woff_off);
-    for (int w = tid; w < L.nwords; w += kBlk) {
+    for (int w = tid; w < L.nwords; w += NT) {
         uint64_t bits = keepw[w];
         uint32_t pos = excl + woff[w];
         while (bits) {
@@ -812,6 +819,7 @@ __device__ __forceinline__ void emit_marked(const DetectArgs& a, const CellLayou
 // Step 6 for a cell that keeps some new maxima and carries some D_{n-1}
 // entries: the ranked union in decision order, carried entries with their
 // previous scores (the k-th carried bit takes cscore[k]).
+template <int NT>
 __device__ __forceinline__ void emit_merged(const DetectArgs& a, const CellLayout& L, const uint8_t* sm,
                                             uint32_t excl, kpd_keypoint* list, uint32_t cap, const uint64_t* carr,
                                             const uint32_t* cwoff, const uint16_t* cscore)
@@ -819,7 +827,7 @@ __device__ __forceinline__ void emit_merged(const DetectArgs& a, const CellLayou
     const int O = a.O;
     const uint64_t* keepw = reinterpret_cast<const uint64_t*>(sm);
     const uint32_t* woff = reinterpret_cast<const uint32_t*>(sm + L.woff_off);
-    for (int w = threadIdx.x; w < L.nwords; w += kBlk) {
+    for (int w = threadIdx.x; w < L.nwords; w += NT) {
         uint64_t bits = keepw[w];
         const uint64_t cb = carr[w];
         uint32_t pos = excl + woff[w];
@@ -847,6 +855,7 @@ __device__ __forceinline__ void emit_merged(const DetectArgs& a, const CellLayou
 
 // Sum over cells [0, c) of their count words for `epoch`, spinning on each
 // until it is published (block-wide; the result is valid in every thread).
+template <int NT>
 __device__ uint32_t sum_count_words(const unsigned long long* words, int c, uint32_t epoch, uint32_t* err,
                                     uint32_t* s_part)
 {
@@ -854,7 +863,7 @@ __device__ uint32_t sum_count_words(const unsigned long long* words, int c, uint
     const int lane = tid & 63, wave = tid >> 6;
     uint32_t acc = 0;
     bool ok = true;
-    for (int p = tid; p < c; p += kBlk) {
+    for (int p = tid; p < c; p += NT) {
         int spins = 0;
         while (true) {
             const uint64_t st = __hip_atomic_load(&words[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -872,7 +881,7 @@ __device__ uint32_t sum_count_words(const unsigned long long* words, int c, uint
     if (lane == 0) s_part[wave] = acc;
     __syncthreads();
     uint32_t sum = 0;
-    for (int w = 0; w < kDetWaves; ++w) sum += s_part[w];
+    for (int w = 0; w < (NT / 64); ++w) sum += s_part[w];
     return sum;
 }
 
@@ -908,11 +917,12 @@ __device__ void load_level_ptrs(const DetectArgs& a, const uint8_t** s_lvl, int*
 // mask pixel changed and the D_{n-1} entries whose mask pixel did not (Eq. 1
 // per feature), merged in decision order. Every cell publishes its count
 // word, and offsets wait on all earlier cells.
+template <int NT>
 __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
 {
     __shared__ CellLayout L;
     __shared__ int s_touched;
-    __shared__ uint32_t s_n, s_base, s_part[kDetWaves];
+    __shared__ uint32_t s_n, s_base, s_part[(NT / 64)];
     __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
     __shared__ int s_pitch[KPD_MAX_OCTAVES];
     // per mask layer: the cell's first pixel and width on it, and where its
@@ -950,7 +960,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
             const uint8_t* cur = s_lvl[l];
             const uint8_t* prv = a.lprev[l];
             const int cp = s_pitch[l], pp = a.lprev_pitch[l];
-            for (int base = 0; base < npx; base += kBlk) {
+            for (int base = 0; base < npx; base += NT) {
                 const int i = base + tid;
                 bool ch = false;
                 if (i < npx) {
@@ -975,7 +985,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
         a.mask[c] = (uint8_t)(state != 0);
         a.sad_next[c] = 0;
     }
-    if (state) detect_marked(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n, state == 2);
+    if (state) detect_marked<NT>(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n, state == 2);
     uint64_t* carr = reinterpret_cast<uint64_t*>(sm + a.lds_carr);
     uint32_t* cwoff = reinterpret_cast<uint32_t*>(sm + a.lds_cwoff);
     uint16_t* cscore = reinterpret_cast<uint16_t*>(sm + a.lds_cscore);
@@ -991,7 +1001,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
             return (bits[i >> 5] >> (i & 31)) & 1u;
         };
         // new maxima only where the mask is 1
-        for (int w = tid; w < L.nwords; w += kBlk) {
+        for (int w = tid; w < L.nwords; w += NT) {
             uint64_t k = keepw[w], out = k;
             while (k) {
                 const int b = __builtin_ctzll(k);
@@ -1010,7 +1020,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
         __syncthreads();
         // D_{n-1}'s entries of the cell where the mask is 0, in order
         const uint32_t n0 = a.count_prev[c], src0 = a.off_prev[c];
-        for (uint32_t b0 = 0; b0 < n0; b0 += kBlk) {
+        for (uint32_t b0 = 0; b0 < n0; b0 += NT) {
             const uint32_t jj = b0 + tid;
             bool keep = false;
             kpd_keypoint e{};
@@ -1024,7 +1034,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
             if (lane == 0) s_part[wave] = (uint32_t)__popcll(bal);
             __syncthreads();
             uint32_t before = s_base, total = 0;
-            for (int w = 0; w < kDetWaves; ++w) {
+            for (int w = 0; w < (NT / 64); ++w) {
                 if (w < wave) before += s_part[w];
                 total += s_part[w];
             }
@@ -1041,7 +1051,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
             if (tid == 0) s_base += total;
             __syncthreads();
         }
-        for (int w = tid; w < L.nwords; w += kBlk) keepw[w] |= carr[w];
+        for (int w = tid; w < L.nwords; w += NT) keepw[w] |= carr[w];
         __syncthreads();
         rank_words(L, sm, &s_n, carr, cwoff);
     }
@@ -1054,7 +1064,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    const uint32_t excl = sum_count_words(a.status, c, a.epoch, a.err, s_part);
+    const uint32_t excl = sum_count_words<NT>(a.status, c, a.epoch, a.err, s_part);
     const uint32_t n = s_n;
     if (tid == 0) {
         a.count_cur[c] = n;
@@ -1062,26 +1072,27 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
         if (c == a.nc * a.nr - 1) *a.total_cur = excl + n;
     }
     if (state == 2) {
-        emit_marked(a, L, sm, excl, a.list_cur, a.list_cap);
+        emit_marked<NT>(a, L, sm, excl, a.list_cur, a.list_cap);
     } else if (state == 1) {
-        emit_merged(a, L, sm, excl, a.list_cur, a.list_cap, carr, cwoff, cscore);
+        emit_merged<NT>(a, L, sm, excl, a.list_cur, a.list_cap, carr, cwoff, cscore);
     } else {
         const uint32_t src0 = a.off_prev[c];
-        for (uint32_t j = tid; j < n; j += kBlk)
+        for (uint32_t j = tid; j < n; j += NT)
             if (src0 + j < a.list_cap && excl + j < a.list_cap) a.list_cur[excl + j] = a.list_prev[src0 + j];
     }
 }
 
 // One frame of one stream: cell c's mark, detection, offset and output.
+template <int NT>
 __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
 {
     if (a.id_mode != 0 && !a.all_marked) {
-        detect_cell_layer(a, c, sm);
+        detect_cell_layer<NT>(a, c, sm);
         return;
     }
     __shared__ CellLayout L;
     __shared__ int s_mark;
-    __shared__ uint32_t s_n, s_excl, s_part[kDetWaves];
+    __shared__ uint32_t s_n, s_excl, s_part[(NT / 64)];
     __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
     __shared__ int s_pitch[KPD_MAX_OCTAVES];
     const int tid = threadIdx.x;
@@ -1096,7 +1107,7 @@ __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
     }
     __syncthreads();
     const bool mark = s_mark != 0;
-    if (mark) detect_marked(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n);
+    if (mark) detect_marked<NT>(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n);
 
     // 5) this cell's offset in D_n: the counts of all earlier cells, carried
     //    ones read from D_{n-1}'s counts, marked ones from their count words
@@ -1109,7 +1120,7 @@ __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
     }
     uint32_t acc = 0;
     bool ok = true;
-    for (int p = tid; p < c; p += kBlk) {
+    for (int p = tid; p < c; p += NT) {
         if (!cell_marked(a, p)) {
             acc += a.count_prev[p];
             continue;
@@ -1131,7 +1142,7 @@ __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
     __syncthreads();
     if (tid == 0) {
         uint32_t excl = 0;
-        for (int w = 0; w < kDetWaves; ++w) excl += s_part[w];
+        for (int w = 0; w < (NT / 64); ++w) excl += s_part[w];
         a.count_cur[c] = s_n;
         a.off_cur[c] = excl;
         if (c == a.nc * a.nr - 1) *a.total_cur = excl + s_n;
@@ -1142,10 +1153,10 @@ __device__ void detect_cell(const DetectArgs& a, int c, uint8_t* sm)
 
     // 6) write D_n entries of this cell: the ranked maxima, or D_{n-1}'s
     if (mark) {
-        emit_marked(a, L, sm, excl, a.list_cur, a.list_cap);
+        emit_marked<NT>(a, L, sm, excl, a.list_cur, a.list_cap);
     } else {
         const uint32_t src0 = a.off_prev[c];
-        for (uint32_t j = tid; j < n; j += kBlk)
+        for (uint32_t j = tid; j < n; j += NT)
             if (src0 + j < a.list_cap && excl + j < a.list_cap) a.list_cur[excl + j] = a.list_prev[src0 + j];
     }
 }
@@ -1161,6 +1172,7 @@ __device__ __forceinline__ bool chunk_all_marked(const ChunkHead& h, int j)
 // mark and, when marked, its keypoints at the cell's fixed base in frame j's
 // sparse list. With T_H active the mark needs the cell's count in frame
 // j-1, published by that frame's workgroup for the cell as a count word.
+template <int NT>
 __device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c, uint8_t* sm)
 {
     __shared__ CellLayout L;
@@ -1201,7 +1213,7 @@ __device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c,
                                __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    detect_marked(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
+    detect_marked<NT>(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
     __syncthreads();
     if (tid == 0) {
         t.own_count[c] = s_n;
@@ -1209,10 +1221,11 @@ __device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c,
             __hip_atomic_store(&t.cnt_words[c], ((uint64_t)epoch << 32) | s_n, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
-    emit_marked(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
+    emit_marked<NT>(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
 }
 
 // Detection of marked cell c of chunk frame j (mark known, no count word).
+template <int NT>
 __device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8_t* sm)
 {
     __shared__ CellLayout L;
@@ -1226,9 +1239,9 @@ __device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8
         s_pitch[0] = h.pitch;
     }
     __syncthreads();
-    detect_marked(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
+    detect_marked<NT>(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
     if (threadIdx.x == 0) t.own_count[c] = s_n;
-    emit_marked(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
+    emit_marked<NT>(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
     __syncthreads();   // L and the LDS maps are reused by the next item
 }
 
@@ -1256,10 +1269,11 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame1(FrameArgs a)
     frame_tile(a, f, tile % a.tiles_x, tile / a.tiles_x, sm);
 }
 
-__global__ __launch_bounds__(kBlk) void k_detect1(DetectArgs a)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_detect1(DetectArgs a)
 {
     extern __shared__ __align__(16) uint8_t sm[];
-    detect_cell(a, blockIdx.x, sm);
+    detect_cell<NT>(a, blockIdx.x, sm);
 }
 
 // Tile pass of a chunk: tiles of all its frames banded over the XCDs;
@@ -1290,11 +1304,12 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame_chunk(FrameArgs a, ChunkH
 
 // Detection pass of a chunk: workgroup b is cell b % ncell of frame
 // b / ncell (frames in order, cells in order).
-__global__ __launch_bounds__(kBlk) void k_detect_chunk(const ChunkArgs* table, ChunkHead h)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_detect_chunk(const ChunkArgs* table, ChunkHead h)
 {
     extern __shared__ __align__(16) uint8_t sm[];
     const int j = blockIdx.x / h.ncell;
-    detect_cell_chunk(table[j], h, (int)blockIdx.x - j * h.ncell, sm);
+    detect_cell_chunk<NT>(table[j], h, (int)blockIdx.x - j * h.ncell, sm);
 }
 
 // Mark pass of a chunk whose marks need no counts: one thread per (frame,
@@ -1339,14 +1354,15 @@ __global__ __launch_bounds__(kMarkBlock) void k_mark_chunk(ChunkHead h)
 }
 
 // Detection pass over the work list: workgroup b takes items b, b + grid, ...
-__global__ __launch_bounds__(kBlk) void k_detect_list(const ChunkArgs* table, ChunkHead h)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_detect_list(const ChunkArgs* table, ChunkHead h)
 {
     extern __shared__ __align__(16) uint8_t sm[];
     const uint32_t n = *h.work_count;
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const uint32_t item = h.work[it];
         const int j = (int)(item / (uint32_t)h.ncell);
-        detect_item(table[j], h, (int)(item - (uint32_t)j * h.ncell), sm);
+        detect_item<NT>(table[j], h, (int)(item - (uint32_t)j * h.ncell), sm);
     }
 }
 
@@ -1533,7 +1549,8 @@ __global__ __launch_bounds__(kMarkBlock) void k_mark_batch(const TickArgs* table
     }
 }
 
-__global__ __launch_bounds__(kBlk) void k_detect_list_batch(const TickArgs* table, const uint16_t* map,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_detect_list_batch(const TickArgs* table, const uint16_t* map,
                                                             const uint32_t* work, const uint32_t* work_count)
 {
     extern __shared__ __align__(16) uint8_t sm[];
@@ -1549,9 +1566,9 @@ __global__ __launch_bounds__(kBlk) void k_detect_list_batch(const TickArgs* tabl
         const int c = g - t.cell_base;
         if (threadIdx.x == 0) load_level_ptrs(a, s_lvl, s_pitch);
         __syncthreads();
-        detect_marked(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n);
+        detect_marked<NT>(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n);
         if (threadIdx.x == 0) t.own_count[c] = s_n;
-        emit_marked(a, L, sm, t.sparse_base[c], t.sparse, a.list_cap);
+        emit_marked<NT>(a, L, sm, t.sparse_base[c], t.sparse, a.list_cap);
         __syncthreads();   // L and the LDS maps are reused by the next item
     }
 }
@@ -1628,17 +1645,18 @@ hipError_t set_detect_lds_limit(int lds_bytes)
     while (lds_bytes > cur && !g_limit.compare_exchange_weak(cur, lds_bytes)) {
     }
     if (lds_bytes <= cur) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect1),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_list), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lds_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_list_batch),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_detect_chunk),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    const void* kernels[] = {
+        reinterpret_cast<const void*>(k_detect1<kDetLatency>),
+        reinterpret_cast<const void*>(k_detect_list<kDetLatency>),
+        reinterpret_cast<const void*>(k_detect_list<kDetThroughput>),
+        reinterpret_cast<const void*>(k_detect_list_batch<kDetThroughput>),
+        reinterpret_cast<const void*>(k_detect_chunk<kDetThroughput>),
+    };
+    for (const void* k : kernels) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
@@ -1650,7 +1668,7 @@ hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
 
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect1, dim3(ncell), dim3(kBlk), lds_bytes, s, a);
+    hipLaunchKernelGGL(k_detect1<kDetLatency>, dim3(ncell), dim3(kDetLatency), lds_bytes, s, a);
     return hipGetLastError();
 }
 
@@ -1664,7 +1682,8 @@ hipError_t launch_frame_chunk(const FrameArgs& a, size_t pyr_stride, const Chunk
 
 hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_detect_chunk, dim3(h.n_frames * h.ncell), dim3(kBlk), lds_bytes, s, table, h);
+    hipLaunchKernelGGL(k_detect_chunk<kDetThroughput>, dim3(h.n_frames * h.ncell), dim3(kDetThroughput),
+                       detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, h);
     return hipGetLastError();
 }
 
@@ -1679,7 +1698,11 @@ hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int ld
 {
     const int items = h.n_frames * h.ncell;
     const int grid = items < 1024 ? items : 1024;
-    hipLaunchKernelGGL(k_detect_list, dim3(grid), dim3(kBlk), lds_bytes, s, table, h);
+    if (items <= kListLatencyItems)
+        hipLaunchKernelGGL(k_detect_list<kDetLatency>, dim3(grid), dim3(kDetLatency), lds_bytes, s, table, h);
+    else
+        hipLaunchKernelGGL(k_detect_list<kDetThroughput>, dim3(grid), dim3(kDetThroughput),
+                           detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, h);
     return hipGetLastError();
 }
 
@@ -1708,7 +1731,8 @@ hipError_t launch_detect_list_batch(const TickArgs* table, const uint16_t* map, 
                                     const uint32_t* work_count, int lds_bytes, hipStream_t s)
 {
     const int grid = ncells < 1024 ? ncells : 1024;
-    hipLaunchKernelGGL(k_detect_list_batch, dim3(grid), dim3(kBlk), lds_bytes, s, table, map, work, work_count);
+    hipLaunchKernelGGL(k_detect_list_batch<kDetThroughput>, dim3(grid), dim3(kDetThroughput),
+                       detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, map, work, work_count);
     return hipGetLastError();
 }
 
