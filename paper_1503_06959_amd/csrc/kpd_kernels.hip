@@ -260,55 +260,67 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
     uint32_t acc = 0;
     int acc_slot = -1;
     if constexpr (B == 0) {
-        // A segment's SAD goes to at most two cells (its first dword's and
-        // its last dword's), summed in registers while the row cell stays.
-        int cc[4];
-        bool two = true;   // every dword in one cell, the first's or the last's
+        if (a.O > kRegOctaves) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) *reinterpret_cast<uint4*>(L0 + (4 * rb + u) * T + cx) = v[u];
+        }
         if (f.sad_on) {
+            // The thread's 4 x 16 block usually lies in at most two cell
+            // columns (its first dword's and its last dword's, each dword in
+            // one of them) and two cell rows (its first row's and its last
+            // row's): then four register sums, without branches, one LDS
+            // atomic each. Pixels outside the frame are zero in both frames
+            // and add nothing. Other blocks go pixel by pixel.
+            int cc[4];
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                cc[d] = colcell[cx + 4 * d];
-                two = two && gxs + 4 * d + 3 < a.W && colcell[cx + 4 * d + 3] == cc[d];
-            }
+            for (int d = 0; d < 4; ++d) cc[d] = colcell[cx + 4 * d];
+            bool two = true;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) two = two && colcell[cx + 4 * d + 3] == cc[d];
             two = two && (cc[1] == cc[0] || cc[1] == cc[3]) && (cc[2] == cc[0] || cc[2] == cc[3]);
-        }
-        uint32_t accr = 0;   // the segment's second cell
-        int row_slot = -1;
+            int rr[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int ry = 4 * rb + u;
-            if (a.O > kRegOctaves) *reinterpret_cast<uint4*>(L0 + ry * T + cx) = v[u];
-            const int gy = y0 + ry;
-            if (!f.sad_on || gy >= a.H || gxs >= a.W) continue;
-            const int rc = rowcell[ry] * ncx;
-            const uint32_t cw[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-            const uint32_t pw[4] = {pv[u].x, pv[u].y, pv[u].z, pv[u].w};
+            for (int u = 0; u < 4; ++u) rr[u] = rowcell[4 * rb + u];
+            two = two && (rr[1] == rr[0] || rr[1] == rr[3]) && (rr[2] == rr[0] || rr[2] == rr[3]);
             if (two) {
-                if (rc != row_slot) {
-                    if (row_slot >= 0) {
-                        if (acc) atomicAdd(&sadl[row_slot + cc[0]], acc);
-                        if (accr) atomicAdd(&sadl[row_slot + cc[3]], accr);
-                    }
-                    row_slot = rc;
-                    acc = accr = 0;
-                }
+                uint32_t s00 = 0, s01 = 0, s10 = 0, s11 = 0;   // (first/last row cell, first/last column cell)
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const uint32_t sd = __builtin_amdgcn_sad_u8(cw[d], pw[d], 0u);
-                    if (cc[d] == cc[0]) acc += sd;
-                    else accr += sd;
-                }
-            } else {
-                for (int d = 0; d < 4; ++d)
-                    for (int k = 0; k < 4 && gxs + 4 * d + k < a.W; ++k) {
-                        const uint32_t m = 0xFFu << (8 * k);
-                        atomicAdd(&sadl[rc + colcell[cx + 4 * d + k]], __builtin_amdgcn_sad_u8(cw[d] & m, pw[d] & m, 0u));
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t cw[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                    const uint32_t pw[4] = {pv[u].x, pv[u].y, pv[u].z, pv[u].w};
+                    uint32_t sl = 0, sr = 0;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const uint32_t sd = __builtin_amdgcn_sad_u8(cw[d], pw[d], 0u);
+                        const bool left = cc[d] == cc[0];
+                        sl += left ? sd : 0u;
+                        sr += left ? 0u : sd;
                     }
+                    const bool top = rr[u] == rr[0];
+                    s00 += top ? sl : 0u;
+                    s01 += top ? sr : 0u;
+                    s10 += top ? 0u : sl;
+                    s11 += top ? 0u : sr;
+                }
+                const int t0 = rr[0] * ncx, t1 = rr[3] * ncx;
+                if (s00) atomicAdd(&sadl[t0 + cc[0]], s00);
+                if (s01) atomicAdd(&sadl[t0 + cc[3]], s01);
+                if (s10) atomicAdd(&sadl[t1 + cc[0]], s10);
+                if (s11) atomicAdd(&sadl[t1 + cc[3]], s11);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int rc = rr[u] * ncx;
+                    const uint32_t cw[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                    const uint32_t pw[4] = {pv[u].x, pv[u].y, pv[u].z, pv[u].w};
+                    for (int d = 0; d < 4; ++d)
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t m = 0xFFu << (8 * k);
+                            const uint32_t sd = __builtin_amdgcn_sad_u8(cw[d] & m, pw[d] & m, 0u);
+                            if (sd) atomicAdd(&sadl[rc + colcell[cx + 4 * d + k]], sd);
+                        }
+                }
             }
-        }
-        if (row_slot >= 0) {
-            if (acc) atomicAdd(&sadl[row_slot + cc[0]], acc);
-            if (accr) atomicAdd(&sadl[row_slot + cc[3]], accr);
         }
     } else {
         const bool straddle = f.sad_on && (gx + 3 >= a.W || colcell[4 * cq] != colcell[4 * cq + 3]);
