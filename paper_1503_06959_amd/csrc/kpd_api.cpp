@@ -59,10 +59,10 @@ struct Layout {
     size_t off_sparse1 = 0, off_own1 = 0;
     // chunks of consecutive frames (push_frames): K copies of the octaves,
     // per-frame SAD, sparse lists with per-cell counts, count words, marks
-    // (cell-major, Kp bytes per cell), dense lists with counts, offsets and
+    // (cell-major, Kw 64-bit words per cell), dense lists with counts, offsets and
     // totals, the cells' sparse bases, and the fixed per-frame argument
     // tables of the tile and detection passes
-    int K = 1, Kp = 4;
+    int K = 1, Kw = 1;
     int ctile = 32, ctiles_x = 0, ctiles_y = 0, csad_slots = 1;   // tile pass of chunks
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
@@ -235,8 +235,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_coffs = off; off = align_up(off + kc * 4);
         L->off_ctotal = off; off = align_up(off + (size_t)L->K * 4);
         L->off_cntw = off; off = align_up(off + kc * 8);
-        L->Kp = (L->K + 15) / 16 * 16;
-        L->off_marks = off; off = align_up(off + (size_t)L->ncell * L->Kp);
+        L->Kw = (L->K + 63) / 64;
+        L->off_marks = off; off = align_up(off + (size_t)L->ncell * L->Kw * 8);
         L->off_own = off; off = align_up(off + kc * 4);
         L->off_work = off; off = align_up(off + kc * 4);
         L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
@@ -401,9 +401,9 @@ void chunk_tables(kpd_stream* s, std::vector<kpd::ChunkArgs>* ctab, std::vector<
         d.row_h = s->at<uint16_t>(L.off_rowh);
         d.err = s->at<uint32_t>(L.off_hdr) + kHdrErr;
         c.j = j;
-        c.K = L.Kp;
+        c.Kw = L.Kw;
         c.cell_base = s->at<uint32_t>(L.off_cbase);
-        c.marks = s->at<uint8_t>(L.off_marks);
+        c.marks = s->at<unsigned long long>(L.off_marks);
         c.own_count = s->at<uint32_t>(L.off_own) + (size_t)j * kc;
         c.cnt_words = s->at<unsigned long long>(L.off_cntw) + (size_t)j * kc;
         c.cnt_words_prev = j ? c.cnt_words - kc : nullptr;
@@ -495,7 +495,7 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         if (e == hipSuccess)
             e = hipMemsetAsync(s->arena + L.off_csad, 0, (size_t)L.K * L.ncell * 4, s->stream);
         if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_cntw, 0, (size_t)L.K * L.ncell * 8, s->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_marks, 0, (size_t)L.ncell * L.Kp, s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_marks, 0, (size_t)L.ncell * L.Kw * 8, s->stream);
         chunk_tables(s, &ctab, &ftab);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->arena + L.off_ctab, ctab.data(), ctab.size() * sizeof(kpd::ChunkArgs),
@@ -758,9 +758,9 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     h.sad0 = s->at<uint32_t>(L.off_csad);
     h.col_w = s->at<uint16_t>(L.off_colw);
     h.row_h = s->at<uint16_t>(L.off_rowh);
-    h.marks = s->at<uint8_t>(L.off_marks);
+    h.marks = s->at<unsigned long long>(L.off_marks);
     h.mask = s->at<uint8_t>(L.off_mask);
-    h.Kp = L.Kp;
+    h.Kw = L.Kw;
     h.work = s->at<uint32_t>(L.off_work);
     h.work_count = s->at<uint32_t>(L.off_hdr) + kHdrWork;
     // the tile pass is needed for coarser octaves or intensity differences
@@ -784,12 +784,12 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     kpd::CompactArgs ca{};
     ca.ncell = L.ncell;
     ca.last = n_frames - 1;
-    ca.K = L.Kp;
+    ca.Kw = L.Kw;
     ca.list_cap = (uint32_t)L.list_cap;
     ca.list_stride = L.clist_stride / sizeof(kpd_keypoint);
     ca.sparse = reinterpret_cast<const kpd_keypoint*>(s->arena + L.off_sparse);
     ca.cell_base = s->at<uint32_t>(L.off_cbase);
-    ca.marks = s->at<uint8_t>(L.off_marks);
+    ca.marks = s->at<unsigned long long>(L.off_marks);
     ca.own_count = s->at<uint32_t>(L.off_own);
     ca.prev_list = s->at<kpd_keypoint>(L.off_list[fb_prev]);
     ca.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);

@@ -108,9 +108,9 @@ struct TickArgs {
 struct ChunkArgs {
     DetectArgs d;                               // frame j's fixed detection arguments (list_cur = sparse list j)
     int j;                                      // frame index in the chunk
-    int K;                                      // mark bytes per cell
+    int Kw;                                     // mark words per cell
     const uint32_t* cell_base;                  // each cell's first index in a sparse list
-    uint8_t* marks;                             // cells x K mark bytes (cell-major)
+    unsigned long long* marks;                  // cells x Kw mark words: bit j of a cell = frame j marked
     uint32_t* own_count;                        // frame j's per-cell counts of marked cells
     unsigned long long* cnt_words;              // frame j's count words ([63:32] epoch)
     const unsigned long long* cnt_words_prev;   // frame j-1's
@@ -140,20 +140,20 @@ struct ChunkHead {
     const uint32_t* sad0;       // frame j's SAD at sad0 + j * ncell
     const uint16_t* col_w;
     const uint16_t* row_h;
-    uint8_t* marks;             // cells x Kp mark bytes
+    unsigned long long* marks;  // cells x Kw mark words (bit j = frame j)
     uint8_t* mask;              // M of the last frame
-    int Kp;
+    int Kw;
     uint32_t* work;             // marked items j * ncell + c
     uint32_t* work_count;       // their number; cleared by the compaction pass
 };
 
 struct CompactArgs {
-    int ncell, last, K;
+    int ncell, last, Kw;
     uint32_t list_cap;
     size_t list_stride;              // entries between consecutive chunk lists
     const kpd_keypoint* sparse;      // chunk frames' sparse lists
     const uint32_t* cell_base;
-    const uint8_t* marks;
+    const unsigned long long* marks; // cells x Kw mark words
     const uint32_t* own_count;       // chunk frames x cells
     const kpd_keypoint* prev_list;   // D before the chunk, its counts and offsets
     const uint32_t* prev_count;

@@ -1213,7 +1213,11 @@ __device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c,
             cprev = j == 0 ? h.prev_count[c] : (uint32_t)wait_word(&t.cnt_words_prev[c], epoch - 1, a.err);
             mark = cprev >= h.kb_thresh;
         }
-        t.marks[(size_t)c * t.K + j] = (uint8_t)mark;
+        // every frame sets or clears its own bit, so the words need no clearing
+        unsigned long long* mw = &t.marks[(size_t)c * t.Kw + (j >> 6)];
+        const unsigned long long bit = 1ull << (j & 63);
+        if (mark) atomicOr(mw, bit);
+        else atomicAnd(mw, ~bit);
         if (j == h.n_frames - 1) a.mask[c] = (uint8_t)mark;
         s_mark = mark;
         s_cprev = cprev;
@@ -1324,44 +1328,46 @@ __global__ __launch_bounds__(NT) void k_detect_chunk(const ChunkArgs* table, Chu
     detect_cell_chunk<NT>(table[j], h, (int)blockIdx.x - j * h.ncell, sm);
 }
 
-// Mark pass of a chunk whose marks need no counts: one thread per (frame,
-// cell) decides the mark, records it and appends marked items to the work
-// list (one atomic per wave).
+// Mark pass of a chunk whose marks need no counts: one wave per cell and 64
+// consecutive frames, one lane per frame. The wave's ballot is the cell's
+// mark word for those frames; marked items are appended to the work list
+// (one LDS atomic per wave, one global atomic per workgroup).
 constexpr int kMarkBlock = 1024;
 
 __global__ __launch_bounds__(kMarkBlock) void k_mark_chunk(ChunkHead h)
 {
     __shared__ uint32_t s_count, s_base;
-    const int n = h.n_frames * h.ncell;
-    const int i = blockIdx.x * kMarkBlock + threadIdx.x;
+    const int nw = (h.n_frames + 63) >> 6;
+    const int g = blockIdx.x * kMarkBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int cw = g >> 6;               // (cell, word) of this wave
+    const int c = cw / nw, w = cw - c * nw;
+    const int j = w * 64 + lane;
     if (threadIdx.x == 0) s_count = 0;
     __syncthreads();
     bool mark = false;
-    if (i < n) {
-        const int j = i / h.ncell, c = i - j * h.ncell;
+    if (c < h.ncell && j < h.n_frames) {
         mark = chunk_all_marked(h, j);
         if (!mark && h.id_thresh < 255) {
             const int cx = c % h.nc, cy = c / h.nc;
             const int64_t area = (int64_t)h.col_w[cx] * h.row_h[cy];
             mark = (int64_t)h.sad0[(size_t)j * h.ncell + c] > (int64_t)h.id_thresh * area;
         }
-        h.marks[(size_t)c * h.Kp + j] = (uint8_t)mark;
         if (j == h.n_frames - 1) h.mask[c] = (uint8_t)mark;
     }
-    // workgroup-local slots first, then one global atomic per workgroup
     const uint64_t bal = __ballot(mark);
-    const int lane = threadIdx.x & 63;
-    const int leader = bal ? __builtin_ctzll(bal) : 0;
+    if (lane == 0 && c < h.ncell) h.marks[(size_t)c * h.Kw + w] = bal;
+    // workgroup-local slots first, then one global atomic per workgroup
     uint32_t wbase = 0;
-    if (bal && lane == leader) wbase = atomicAdd(&s_count, (uint32_t)__popcll(bal));
-    wbase = __shfl(wbase, leader);
+    if (bal && lane == 0) wbase = atomicAdd(&s_count, (uint32_t)__popcll(bal));
+    wbase = __shfl(wbase, 0);
     __syncthreads();
     if (threadIdx.x == 0) s_base = s_count ? atomicAdd(h.work_count, s_count) : 0;
     __syncthreads();
     if (mark) {
         const unsigned below =
             __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-        h.work[s_base + wbase + below] = (uint32_t)i;
+        h.work[s_base + wbase + below] = (uint32_t)(j * h.ncell + c);
     }
 }
 
@@ -1464,29 +1470,19 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
     uint32_t* off_out = last ? a.next_offs : a.offs + jc;
     compact_frame(a.ncell, a.list_cap, dst, cnt_out, off_out, last ? a.next_total : a.totals + j,
                   [&](int c, uint32_t* n, const kpd_keypoint** src) {
-        // the newest frame <= j that marked this cell: mark bytes (0 or 1)
-        // 16 frames per load, all loads issued before any is used
-        const uint4* m16 = reinterpret_cast<const uint4*>(a.marks + (size_t)c * a.K);
-        const int qj = j >> 4;
+        // the newest frame <= j that marked this cell: its mark words up
+        // to frame j, all loads issued before any is used
+        const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
+        const int qj = j >> 6;
+        const unsigned long long upto = (j & 63) == 63 ? ~0ull : (2ull << (j & 63)) - 1ull;   // frames <= j
+        unsigned long long m[kMaxChunk / 64];
+#pragma unroll
+        for (int q = 0; q < kMaxChunk / 64; ++q) m[q] = q <= qj ? mw[q] : 0ull;
         int f = -1;
 #pragma unroll
-        for (int q0 = 0; q0 < kMaxChunk / 16; q0 += 4) {
-            if (q0 > qj) break;
-            uint4 w[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (q0 + u <= qj) w[u] = m16[q0 + u];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (q0 + u > qj) break;
-                const uint32_t d[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
-                uint32_t b = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    b |= ((d[k] & 1u) | ((d[k] >> 7) & 2u) | ((d[k] >> 14) & 4u) | ((d[k] >> 21) & 8u)) << (4 * k);
-                if (q0 + u == qj) b &= (2u << (j & 15)) - 1u;
-                if (b) f = 16 * (q0 + u) + 31 - __clz(b);
-            }
+        for (int q = 0; q < kMaxChunk / 64; ++q) {
+            const unsigned long long x = q == qj ? m[q] & upto : m[q];
+            if (q <= qj && x) f = 64 * q + 63 - __clzll(x);
         }
         if (f >= 0) {
             const uint32_t off = a.cell_base[c];
@@ -1701,7 +1697,7 @@ hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int l
 
 hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s)
 {
-    const int n = h.n_frames * h.ncell;
+    const int n = (h.n_frames + 63) / 64 * 64 * h.ncell;   // a wave per cell and 64 frames
     hipLaunchKernelGGL(k_mark_chunk, dim3((n + kMarkBlock - 1) / kMarkBlock), dim3(kMarkBlock), 0, s, h);
     return hipGetLastError();
 }
