@@ -108,10 +108,11 @@ class Workload:
 TILE = 0
 
 
-def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool = False):
+def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool = False, kb_thresh=None):
     from paper_1503_06959_amd import kpd
     d = wl.det
-    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh, TILE, chunk,
+    kb = d.kb_thresh if kb_thresh is None else kb_thresh
+    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, kb, TILE, chunk,
                              int(layer_mask))
     s = kpd.Stream(wl.W, wl.H, params)
     s.chunk = chunk
@@ -314,10 +315,11 @@ def chunk_of(args, wl: Workload) -> int:
 
 
 def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True, chunk=0,
-                 layer=None):
+                 layer=None, kb_thresh=None):
     """layer: None for the per-cell mean-difference mask, else the pyramid
-    layer of the per-pixel mask (single-frame pushes only)."""
-    s = open_stream(wl, id_thresh, chunk, layer_mask=layer is not None)
+    layer of the per-pixel mask (single-frame pushes only). kb_thresh: T_H
+    (default: the workload's)."""
+    s = open_stream(wl, id_thresh, chunk, layer_mask=layer is not None, kb_thresh=kb_thresh)
     if layer is not None:
         s.set_mask_mode(1, layer)
     sec = timed_passes(kpd, s, wl, args.steps, args.warmup)
@@ -388,6 +390,46 @@ def _gen_clip(args):
     from paper_1503_06959_amd import synth
     sc, n = args
     return synth.make_video(sc, n)
+
+
+def _oracle_streams(args):
+    """One host worker of the all-cores oracle baseline: its share of the
+    batched streams, each through its own oracle stream, one frame per stream
+    per tick until `seconds` have passed. Returns (level-0 pixels, seconds)."""
+    import oracle
+    from paper_1503_06959_amd import synth
+    idx, clip, seconds = args
+    specs = synth.batch_streams(clip)
+    mine = [(specs[i][0], specs[i][1], synth.make_video(specs[i][0], clip)) for i in idx]
+    streams = [oracle.Stream(sc.width, sc.height, d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, d.id_thresh,
+                             d.kb_thresh) for sc, d, _ in mine]
+    px, k = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        i = pingpong(k, clip)
+        for s, (sc, _, frames) in zip(streams, mine):
+            s.push(frames[i])
+            px += sc.width * sc.height
+        k += 1
+    dt = time.perf_counter() - t0
+    for s in streams:
+        s.close()
+    return px, dt
+
+
+def oracle_all_cores(clip: int, seconds: float) -> dict:
+    """The oracle on every host core for the 64-stream batched workload:
+    streams dealt round-robin to one worker process per core."""
+    from concurrent.futures import ProcessPoolExecutor
+    n = min(16, os.cpu_count() or 1)
+    parts = [(list(range(w, 64, n)), clip, seconds) for w in range(n)]
+    with ProcessPoolExecutor(max_workers=n) as ex:
+        res = list(ex.map(_oracle_streams, parts))
+    px = sum(p for p, _ in res)
+    dt = max(d for _, d in res)
+    return {"value": round(px / dt / 1e6, 3), "unit": "Mpixel/s", "cores": n, "kind": "oracle",
+            "sample": f"the 64 batched streams dealt to {n} worker processes, one oracle stream per video stream, "
+                      f"about {seconds:.0f}s each, {cpu_model()}"}
 
 
 def pingpong(k: int, n: int) -> int:
@@ -477,6 +519,7 @@ def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
                              "frames_per_s": round(64 / sec_p, 1), "ms_per_tick": round(sec_p * 1e3, 4),
                              "launches_per_tick": 128},
         "batched_over_plain": round(sec_p / sec_b, 3),
+        "cpu_all_cores": oracle_all_cores(clip, 10.0),
     }
 
 
@@ -771,6 +814,19 @@ def main():
         "latency_ms": {"p50": round(lm["lat_p50"], 4), "p99": round(lm["lat_p99"], 4)},
         "touched_cell_frac": round(sum(lm["marked"][1:]) / max(1, (wl.F - 1) * wl.ncell), 4),
         "roofline": roofline_of(wl, lm, True),
+    }
+    log("[bench] keypoint-binning mask only (T_I off, T_H = 2)")
+    kbc = run_workload(kpd, wl, 255, args, chunk=K, kb_thresh=2, want_profile=False)
+    kbf = run_workload(kpd, wl, 255, args, kb_thresh=2, want_profile=False)
+    out["kb_only"] = {
+        "what": "the keypoint-binning mask alone (Sec. 3.2, Eqs. 3-4): T_I off (255), T_H = 2; marks need the "
+                "previous frame's counts, so chunks run the chained detection pass",
+        "chunked": {"value": round(kbc["mpix_per_s"], 2), "unit": "Mpixel/s", "frames_per_s": round(kbc["frames_per_s"], 1),
+                    "ms_per_step": round(kbc["sec_per_pass"] * 1e3, 4)},
+        "per_frame_push": {"value": round(kbf["mpix_per_s"], 2), "unit": "Mpixel/s",
+                           "frames_per_s": round(kbf["frames_per_s"], 1),
+                           "latency_ms": {"p50": round(kbf["lat_p50"], 4), "p99": round(kbf["lat_p99"], 4)}},
+        "marked_cell_frac": round(sum(kbf["marked"][1:]) / max(1, (wl.F - 1) * wl.ncell), 4),
     }
     log("[bench] layer study")
     out["layer_study"] = layer_study(kpd, wl, args)
