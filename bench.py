@@ -566,8 +566,12 @@ PROFILE_CASES = {
     "pmc_c3_1920x1080_full_chunked": ("pmc", "--workload c3_1920x1080 --mode full --chunked --steps 2 --warmup 0"),
     "pmc_c2_640x480_layer3_frame": ("pmc", "--workload c2_640x480 --mode masked --layer 3 --steps 2 --warmup 0"),
     "pmc_copy_256MiB": ("pmc", "--copy-calibration 256"),
+    "valu_c3_1920x1080_full_chunked": ("valu", "--workload c3_1920x1080 --mode full --chunked --steps 2 --warmup 0"),
 }
 PMC_COUNTERS = ("FETCH_SIZE", "WRITE_SIZE")
+# counter sets of the VALU study, one rocprofv3 run each
+VALU_SETS = (("VALUBusy",), ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY",
+                             "GRBM_GUI_ACTIVE"))
 # kernel -> (push path, the timed kernel id its launches count under)
 KERNEL_IDS = {"k_frame1": ("frame", "k_frame"), "k_detect1": ("frame", "k_detect"),
               "k_frame_chunk": ("chunk", "k_frame"), "k_detect_chunk": ("chunk", "k_detect"),
@@ -591,7 +595,8 @@ def profile_command(case: str, out: str, counter: str = "", root: str = "$R") ->
     if kind == "trace":
         return (f"rocprofv3 --kernel-trace --stats --output-format csv -d {out}/{case} -o kt -- "
                 f"python3 {root}/bench.py {args}")
-    return (f"rocprofv3 --pmc {counter} --output-format csv -d {out}/{case}_{counter} -o p -- "
+    tag = counter.split()[0]
+    return (f"rocprofv3 --pmc {counter} --output-format csv -d {out}/{case}_{tag} -o p -- "
             f"python3 {root}/bench.py {args}")
 
 
@@ -606,9 +611,11 @@ def profile_script(out: str) -> str:
             lines.append(f"timeout -k 10 300 {profile_command(case, out)} > {out}/{case}.out 2> {out}/{case}.log "
                          f"|| exit $?")
         else:
-            for c in PMC_COUNTERS:
-                lines.append(f"timeout -s KILL 90 {profile_command(case, out, c)} > {out}/{case}_{c}.out "
-                             f"2> {out}/{case}_{c}.log || exit $?")
+            sets = PMC_COUNTERS if kind == "pmc" else [" ".join(v) for v in VALU_SETS]
+            for c in sets:
+                tag = c.split()[0]
+                lines.append(f"timeout -s KILL 90 {profile_command(case, out, c)} > {out}/{case}_{tag}.out "
+                             f"2> {out}/{case}_{tag}.log || exit $?")
         lines.append(f"echo {case} done")
     return "\n".join(lines) + "\n"
 
@@ -620,7 +627,11 @@ def summarize_profiles(out: str) -> None:
     from collections import defaultdict
     pdir = os.path.join(ROOT, "profiles")
     os.makedirs(pdir, exist_ok=True)
-    short = lambda n: n.split("(")[0].replace("kpd::", "")
+    def short(n):
+        n = n.split("(")[0].replace("kpd::", "")
+        if n.startswith("void "):
+            n = n[5:]
+        return n.split("<")[0]
     for case, (kind, _) in PROFILE_CASES.items():
         if kind != "trace":
             continue
@@ -635,11 +646,12 @@ def summarize_profiles(out: str) -> None:
                          f"{float(r['Percentage']):6.2f}%")
         open(os.path.join(pdir, f"kernel_trace_{case[3:]}.txt"), "w").write("\n".join(lines) + "\n")
 
-    def pmc(case, counter):
+    def pmc(case, counter, name=None):
         path = os.path.join(out, f"{case}_{counter}", "p_counter_collection.csv")
         agg = defaultdict(list)
         for r in csv.DictReader(open(path)):
-            agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+            if name is None or r["Counter_Name"] == name:
+                agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
         return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
     copy_bytes = 256 << 20
@@ -676,6 +688,30 @@ def summarize_profiles(out: str) -> None:
         for key, (b, n) in acc.items():
             traffic["per_launch_bytes"][key] = int(b / n)
     open(os.path.join(pdir, "hbm_traffic_chunked_and_single.txt"), "w").write("\n".join(lines) + "\n")
+
+    # VALU study of the full-frame 1920x1080 chunk passes
+    case = "valu_c3_1920x1080_full_chunked"
+    busy = pmc(case, "VALUBusy", "VALUBusy")
+    cnt = {c: pmc(case, "SQ_INSTS_VALU", c) for c in VALU_SETS[1]}
+    lv = level_sizes(1920, 1080, 5)
+    px_oct = 300 * sum(lv)   # pixel-octaves one chunk launch covers (the whole video)
+    lines = ["# VALU study, 1920x1080 full-frame chunks (300 frames per launch), one counter set per run", "",
+             "commands (R = the repository root, run from /tmp):"]
+    for c in VALU_SETS:
+        lines.append("  " + profile_command(case, "$R/gpurun_out/prof", " ".join(c)))
+    lines += ["", f"{'kernel':16s} {'dispatches':>10s} {'VALUBusy%':>10s} {'VALU insts':>14s} {'waves':>10s} "
+                  f"{'wait/wave cyc':>13s} {'lane-ops/px-oct':>16s}"]
+    for k in ("k_frame_chunk", "k_detect_chunk", "k_compact_chunk"):
+        if k not in busy or k not in cnt["SQ_INSTS_VALU"]:
+            continue
+        insts, n = cnt["SQ_INSTS_VALU"][k]
+        waves = cnt["SQ_WAVES"][k][0]
+        wait = cnt["SQ_WAIT_ANY"][k][0] / max(cnt["SQ_WAVE_CYCLES"][k][0], 1)
+        per = insts * 64 / px_oct if k == "k_detect_chunk" else float("nan")
+        lines.append(f"{k:16s} {n:10d} {busy[k][0]:10.1f} {insts:14.0f} {waves:10.0f} {wait:13.3f} {per:16.1f}")
+    lines += ["", "lane-ops/px-oct: VALU instructions x 64 lanes per pixel-octave of the launch "
+                  f"({px_oct} = 300 frames x {sum(lv)})"]
+    open(os.path.join(pdir, "valu_c3_1920x1080_full_chunked.txt"), "w").write("\n".join(lines) + "\n")
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump(traffic, fh, indent=1, sort_keys=True)
 
