@@ -67,7 +67,7 @@ struct Layout {
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
     size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0, off_work = 0;
-    size_t off_cntw = 0, off_ctab = 0;
+    size_t off_ctab = 0;
     size_t list_cap = 0;    // entries of chunk and sparse lists: one feature per 2x2 decision block
     size_t list_cap1 = 0;   // entries of the single-frame D lists: every decision pixel with layer_mask
     int lds_bytes = 0;   // dynamic LDS of the cell pass
@@ -80,7 +80,7 @@ struct Layout {
 };
 
 // header words
-constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrErr = 3, kHdrWork = 4;
+constexpr int kHdrTotal0 = 0, kHdrTotal1 = 1, kHdrErr = 3, kHdrWork = 4;   // kHdrWork + 1: a chunk's second work count
 constexpr size_t kStage = 4096;   // D_n entries staged by get_keypoints
 
 bool valid_params(int W, int H, const kpd_params* p, std::string* why)
@@ -234,7 +234,6 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_ccount = off; off = align_up(off + kc * 4);
         L->off_coffs = off; off = align_up(off + kc * 4);
         L->off_ctotal = off; off = align_up(off + (size_t)L->K * 4);
-        L->off_cntw = off; off = align_up(off + kc * 8);
         L->Kw = (L->K + 63) / 64;
         L->off_marks = off; off = align_up(off + (size_t)L->ncell * L->Kw * 8);
         L->off_own = off; off = align_up(off + kc * 4);
@@ -405,8 +404,6 @@ void chunk_tables(kpd_stream* s, std::vector<kpd::ChunkArgs>* ctab, std::vector<
         c.cell_base = s->at<uint32_t>(L.off_cbase);
         c.marks = s->at<unsigned long long>(L.off_marks);
         c.own_count = s->at<uint32_t>(L.off_own) + (size_t)j * kc;
-        c.cnt_words = s->at<unsigned long long>(L.off_cntw) + (size_t)j * kc;
-        c.cnt_words_prev = j ? c.cnt_words - kc : nullptr;
     }
 }
 
@@ -494,7 +491,6 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (L.K > 1) {
         if (e == hipSuccess)
             e = hipMemsetAsync(s->arena + L.off_csad, 0, (size_t)L.K * L.ncell * 4, s->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_cntw, 0, (size_t)L.K * L.ncell * 8, s->stream);
         if (e == hipSuccess) e = hipMemsetAsync(s->arena + L.off_marks, 0, (size_t)L.ncell * L.Kw * 8, s->stream);
         chunk_tables(s, &ctab, &ftab);
         if (e == hipSuccess)
@@ -742,7 +738,6 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     h.prev0_pitch = s->prev0 ? s->prev_pitch : pitch;
     h.prev0_aligned = s->prev0 ? s->prev_dw : h.aligned;
     h.n_frames = n_frames;
-    h.epoch0 = n0 + 1;
     h.force0 = s->force_all ? 1 : 0;
     h.all_marked = (s->p.id_thresh < 0 || s->p.kb_thresh == 0) ? 1 : 0;
     h.t = s->p.fast_t;
@@ -772,10 +767,18 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
             return kpd::launch_frame_chunk(s->chunk_fa, L.pyr_stride, h, kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots),
                                            s->stream);
         }));
-    if (h.all_marked || h.kb_chain) {
-        // every cell, or marks that wait on the previous frame's counts:
-        // one workgroup per (frame, cell)
+    if (h.all_marked) {
+        // every cell of every frame: one workgroup per (frame, cell)
         KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_chunk(ctab, h, L.lds_bytes, s->stream); }));
+    } else if (h.kb_chain) {
+        // marks that depend on the counts: detect every frame a cell's chain
+        // can mark, then walk each cell's frames to keep the marks
+        const uint32_t* own = s->at<uint32_t>(L.off_own);
+        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_spec_chunk(h, s->stream); }));
+        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_list(ctab, h, L.lds_bytes, s->stream, 0); }));
+        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_spec2_chunk(h, own, s->stream); }));
+        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_list(ctab, h, L.lds_bytes, s->stream, 1); }));
+        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_resolve_chunk(h, own, s->stream); }));
     } else {
         // marks from the SAD alone: list the marked cells, detect only those
         KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(h, s->stream); }));

@@ -111,9 +111,7 @@ struct ChunkArgs {
     int Kw;                                     // mark words per cell
     const uint32_t* cell_base;                  // each cell's first index in a sparse list
     unsigned long long* marks;                  // cells x Kw mark words: bit j of a cell = frame j marked
-    uint32_t* own_count;                        // frame j's per-cell counts of marked cells
-    unsigned long long* cnt_words;              // frame j's count words ([63:32] epoch)
-    const unsigned long long* cnt_words_prev;   // frame j-1's
+    uint32_t* own_count;                        // frame j's per-cell counts of detected cells
 };
 
 // What changes from one chunk to the next, passed by value: the frames, the
@@ -125,13 +123,12 @@ struct ChunkHead {
     int pitch, prev0_pitch;
     int aligned, prev0_aligned; // rows dword-readable
     int n_frames;
-    uint32_t epoch0;            // epoch of frame 0 (frame number + 1)
     int force0;                 // frame 0 marks every cell (first frame, reset, new t)
     int all_marked;             // the parameters mark every cell
     int t;
     int32_t id_thresh;
     uint32_t kb_thresh;
-    int kb_chain;               // marks read the previous frame's counts (T_H active)
+    int kb_chain;               // marks depend on the previous frame's counts (T_H active)
     const uint32_t* prev_count; // counts of the frame before the chunk
     int ntiles, ncell;          // tiles and cells per frame
     int nc;                     // cell columns
@@ -144,7 +141,8 @@ struct ChunkHead {
     uint8_t* mask;              // M of the last frame
     int Kw;
     uint32_t* work;             // marked items j * ncell + c
-    uint32_t* work_count;       // their number; cleared by the compaction pass
+    uint32_t* work_count;       // their number (two: a second round of items follows the first);
+                                // cleared by the compaction pass
 };
 
 struct CompactArgs {
@@ -169,13 +167,17 @@ struct CompactArgs {
     uint32_t* sad_chunk;             // chunk frames x cells, cleared here
     uint32_t* sad_stats;             // receives the last frame's SAD
     uint32_t* sad_single_next;       // cleared for the next single frame
-    uint32_t* work_count;            // cleared for the next chunk
+    uint32_t* work_count;            // both words cleared for the next chunk
 };
 
 hipError_t launch_frame_chunk(const FrameArgs& a, size_t pyr_stride, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s);
-hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
+hipError_t launch_spec_chunk(const ChunkHead& h, hipStream_t s);
+hipError_t launch_spec2_chunk(const ChunkHead& h, const uint32_t* own, hipStream_t s);
+hipError_t launch_resolve_chunk(const ChunkHead& h, const uint32_t* own, hipStream_t s);
+hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s,
+                              int round = 0);
 hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t s);
 
 int frame_sad_lds_off(int tile, int O);

@@ -897,21 +897,6 @@ __device__ uint32_t sum_count_words(const unsigned long long* words, int c, uint
     return sum;
 }
 
-// Spin on one word until it carries `epoch` (one thread).
-__device__ uint64_t wait_word(const unsigned long long* w, uint32_t epoch, uint32_t* err)
-{
-    int spins = 0;
-    while (true) {
-        const uint64_t st = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)(st >> 32) == epoch) return st;
-        if (++spins > kSpinLimit) {
-            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return st;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-}
-
 __device__ void load_level_ptrs(const DetectArgs& a, const uint8_t** s_lvl, int* s_pitch)
 {
 #pragma unroll
@@ -1180,63 +1165,30 @@ __device__ __forceinline__ bool chunk_all_marked(const ChunkHead& h, int j)
     return h.all_marked || (j == 0 && h.force0);
 }
 
-// One frame j of a chunk of consecutive frames of one stream: cell c's
-// mark and, when marked, its keypoints at the cell's fixed base in frame j's
-// sparse list. With T_H active the mark needs the cell's count in frame
-// j-1, published by that frame's workgroup for the cell as a count word.
+// Cell c of frame j of a chunk whose parameters mark every cell: its mark
+// bit, and its keypoints at the cell's fixed base in frame j's sparse list.
 template <int NT>
 __device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c, uint8_t* sm)
 {
     __shared__ CellLayout L;
-    __shared__ int s_mark;
-    __shared__ uint32_t s_n, s_cprev;
+    __shared__ uint32_t s_n;
     __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
     __shared__ int s_pitch[KPD_MAX_OCTAVES];
     const DetectArgs& a = t.d;
     const int tid = threadIdx.x;
     const int j = t.j;
-    const uint32_t epoch = h.epoch0 + (uint32_t)j;
-    const bool all = chunk_all_marked(h, j);
-
     if (tid == 0) {
         load_level_ptrs(a, s_lvl, s_pitch);
         s_lvl[0] = h.frames + (size_t)j * h.stride;
         s_pitch[0] = h.pitch;
-        bool mark = all;
-        uint32_t cprev = 0;
-        if (!mark && h.id_thresh < 255) {
-            const int cx = c % a.nc, cy = c / a.nc;
-            const int64_t area = (int64_t)a.col_w[cx] * a.row_h[cy];
-            mark = (int64_t)a.sad[c] > (int64_t)h.id_thresh * area;
-        }
-        if (!mark && h.kb_chain) {
-            cprev = j == 0 ? h.prev_count[c] : (uint32_t)wait_word(&t.cnt_words_prev[c], epoch - 1, a.err);
-            mark = cprev >= h.kb_thresh;
-        }
-        // every frame sets or clears its own bit, so the words need no clearing
-        unsigned long long* mw = &t.marks[(size_t)c * t.Kw + (j >> 6)];
-        const unsigned long long bit = 1ull << (j & 63);
-        if (mark) atomicOr(mw, bit);
-        else atomicAnd(mw, ~bit);
-        if (j == h.n_frames - 1) a.mask[c] = (uint8_t)mark;
-        s_mark = mark;
-        s_cprev = cprev;
+        // frames of one cell share a mark word: each sets its own bit
+        atomicOr(&t.marks[(size_t)c * t.Kw + (j >> 6)], 1ull << (j & 63));
+        if (j == h.n_frames - 1) a.mask[c] = 1;
     }
     __syncthreads();
-    if (!s_mark) {
-        if (h.kb_chain && tid == 0)
-            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)epoch << 32) | s_cprev, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        return;
-    }
     detect_marked<NT>(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
     __syncthreads();
-    if (tid == 0) {
-        t.own_count[c] = s_n;
-        if (h.kb_chain)
-            __hip_atomic_store(&t.cnt_words[c], ((uint64_t)epoch << 32) | s_n, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (tid == 0) t.own_count[c] = s_n;
     emit_marked<NT>(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
 }
 
@@ -1371,13 +1323,125 @@ __global__ __launch_bounds__(kMarkBlock) void k_mark_chunk(ChunkHead h)
     }
 }
 
+// With T_H active, cell c is marked in frame j when the intensity test or
+// a forced frame marks it (a root) or when its count in D_{j-1} reaches T_H
+// (Eqs. 3-4); that count is its detection count in the newest marked frame
+// before j. Instead of detecting frame after frame, a chunk detects in two
+// rounds: first every root, then, speculatively, every other frame of a
+// cell that follows a root whose count reaches T_H (or, from frame 0, a
+// count before the chunk that does) up to the cell's next root: these are
+// all the frames a chain of counts can mark. The resolve pass then walks
+// each cell's frames in order and keeps the marks. One wave per cell, 64
+// frames per step; both rounds append to the work list, the second after
+// the first's items.
+constexpr int kWaveCells = 4;   // cells (waves) per workgroup of these passes
+
+__device__ __forceinline__ bool chunk_root(const ChunkHead& h, int j, int c, int64_t thr)
+{
+    return chunk_all_marked(h, j) || (h.id_thresh < 255 && (int64_t)h.sad0[(size_t)j * h.ncell + c] > thr);
+}
+
+__device__ __forceinline__ int64_t chunk_sad_thresh(const ChunkHead& h, int c)
+{
+    return (int64_t)h.id_thresh * h.col_w[c % h.nc] * h.row_h[c / h.nc];
+}
+
+// Append the frames in `bits` (frames w*64 + k) of cell c to the work list
+// after *count, at base + the items before them (one atomic per wave).
+__device__ __forceinline__ void append_frames(const ChunkHead& h, uint64_t bits, int w, int c, uint32_t base,
+                                              uint32_t* count)
+{
+    if (!bits) return;
+    const int lane = threadIdx.x & 63;
+    uint32_t at = 0;
+    if (lane == 0) at = atomicAdd(count, (uint32_t)__popcll(bits));
+    at = base + __shfl(at, 0);
+    if ((bits >> lane) & 1) {
+        const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(bits >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)bits, 0u));
+        h.work[at + below] = (uint32_t)((w * 64 + lane) * h.ncell + c);
+    }
+}
+
+// Round 1: every root of every cell.
+__global__ __launch_bounds__(kWaveCells * 64) void k_spec_chunk(ChunkHead h)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * kWaveCells + (int)(threadIdx.x >> 6);
+    if (c >= h.ncell) return;   // the whole wave
+    const int64_t thr = chunk_sad_thresh(h, c);
+    for (int w = 0; w * 64 < h.n_frames; ++w) {
+        const int j = w * 64 + lane;
+        append_frames(h, __ballot(j < h.n_frames && chunk_root(h, j, c, thr)), w, c, 0u, h.work_count);
+    }
+}
+
+// Round 2: the non-root frames a chain can reach, after round 1's items.
+__global__ __launch_bounds__(kWaveCells * 64) void k_spec2_chunk(ChunkHead h, const uint32_t* own)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * kWaveCells + (int)(threadIdx.x >> 6);
+    if (c >= h.ncell) return;   // the whole wave
+    const int64_t thr = chunk_sad_thresh(h, c);
+    const uint32_t base = *h.work_count;
+    bool chain = h.prev_count[c] >= h.kb_thresh;
+    for (int w = 0; w * 64 < h.n_frames; ++w) {
+        const int j = w * 64 + lane;
+        bool root = false, g = false;
+        if (j < h.n_frames) {
+            root = chunk_root(h, j, c, thr);
+            g = root && own[(size_t)j * h.ncell + c] >= h.kb_thresh;
+        }
+        const uint64_t R = __ballot(root), G = __ballot(g);
+        const int nj = min(64, h.n_frames - w * 64);
+        uint64_t S = 0;
+        for (int k = 0; k < nj; ++k) {
+            if ((R >> k) & 1) chain = (G >> k) & 1;
+            else if (chain) S |= 1ull << k;
+        }
+        append_frames(h, S, w, c, base, h.work_count + 1);
+    }
+}
+
+__global__ __launch_bounds__(kWaveCells * 64) void k_resolve_chunk(ChunkHead h, const uint32_t* own)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * kWaveCells + (int)(threadIdx.x >> 6);
+    if (c >= h.ncell) return;   // the whole wave
+    const int64_t thr = chunk_sad_thresh(h, c);
+    bool pass = h.prev_count[c] >= h.kb_thresh;   // the running count reaches T_H
+    bool m = false;
+    for (int w = 0; w * 64 < h.n_frames; ++w) {
+        const int j = w * 64 + lane;
+        bool root = false, g = false;
+        if (j < h.n_frames) {
+            root = chunk_root(h, j, c, thr);
+            g = own[(size_t)j * h.ncell + c] >= h.kb_thresh;   // used only where frame j was detected
+        }
+        const uint64_t R = __ballot(root), G = __ballot(g);
+        const int nj = min(64, h.n_frames - w * 64);
+        uint64_t M = 0;
+        for (int k = 0; k < nj; ++k) {
+            m = ((R >> k) & 1) || pass;
+            if (m) {
+                M |= 1ull << k;
+                pass = (G >> k) & 1;
+            }
+        }
+        if (lane == 0) h.marks[(size_t)c * h.Kw + w] = M;
+    }
+    if (lane == 0) h.mask[c] = (uint8_t)m;
+}
+
 // Detection pass over the work list: workgroup b takes items b, b + grid, ...
 template <int NT>
-__global__ __launch_bounds__(NT) void k_detect_list(const ChunkArgs* table, ChunkHead h)
+__global__ __launch_bounds__(NT) void k_detect_list(const ChunkArgs* table, ChunkHead h, int round)
 {
     extern __shared__ __align__(16) uint8_t sm[];
-    const uint32_t n = *h.work_count;
-    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    // round 0: items [0, count 0); round 1: [count 0, count 0 + count 1)
+    const uint32_t b = round ? h.work_count[0] : 0u;
+    const uint32_t n = b + h.work_count[round];
+    for (uint32_t it = b + blockIdx.x; it < n; it += gridDim.x) {
         const uint32_t item = h.work[it];
         const int j = (int)(item / (uint32_t)h.ncell);
         detect_item<NT>(table[j], h, (int)(item - (uint32_t)j * h.ncell), sm);
@@ -1499,7 +1563,7 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
         }
         a.sad_chunk[jc + c] = 0;
     });
-    if (j == 0 && threadIdx.x == 0) *a.work_count = 0;
+    if (j == 0 && threadIdx.x == 0) a.work_count[0] = a.work_count[1] = 0;
 }
 
 // One batch tick: workgroup b works for stream map[b] (streams' workgroups
@@ -1695,6 +1759,26 @@ hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int l
     return hipGetLastError();
 }
 
+hipError_t launch_spec_chunk(const ChunkHead& h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_spec_chunk, dim3((h.ncell + kWaveCells - 1) / kWaveCells), dim3(kWaveCells * 64), 0, s, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec2_chunk(const ChunkHead& h, const uint32_t* own, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_spec2_chunk, dim3((h.ncell + kWaveCells - 1) / kWaveCells), dim3(kWaveCells * 64), 0, s,
+                       h, own);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve_chunk(const ChunkHead& h, const uint32_t* own, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resolve_chunk, dim3((h.ncell + kWaveCells - 1) / kWaveCells), dim3(kWaveCells * 64), 0, s,
+                       h, own);
+    return hipGetLastError();
+}
+
 hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s)
 {
     const int n = (h.n_frames + 63) / 64 * 64 * h.ncell;   // a wave per cell and 64 frames
@@ -1702,15 +1786,15 @@ hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
+hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s, int round)
 {
     const int items = h.n_frames * h.ncell;
     const int grid = items < 1024 ? items : 1024;
     if (items <= kListLatencyItems)
-        hipLaunchKernelGGL(k_detect_list<kDetLatency>, dim3(grid), dim3(kDetLatency), lds_bytes, s, table, h);
+        hipLaunchKernelGGL(k_detect_list<kDetLatency>, dim3(grid), dim3(kDetLatency), lds_bytes, s, table, h, round);
     else
         hipLaunchKernelGGL(k_detect_list<kDetThroughput>, dim3(grid), dim3(kDetThroughput),
-                           detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, h);
+                           detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, h, round);
     return hipGetLastError();
 }
 
