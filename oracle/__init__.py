@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kpd_oracle.c")
 LIB = os.path.join(HERE, "libkpd_oracle.so")
-GCC_CMD = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, SRC]
+GCC_CMD = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, SRC, "-lm"]
 
 KP_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("octave", "<i4"), ("score", "<i4")])
 KB_OFF = 0xFFFFFFFF
@@ -57,6 +57,10 @@ def lib() -> ctypes.CDLL:
     L.orc_set_id_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.orc_push.argtypes = [P, P]
     L.orc_get.argtypes = [P, P, ctypes.c_int, P, P, P]
+    L.orc_set_descriptors.argtypes = [P, ctypes.c_int]
+    L.orc_get_desc.argtypes = [P, P, P, ctypes.c_int]
+    L.orc_describe.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+    L.orc_desc_point.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
     _lib = L
     return L
 
@@ -119,6 +123,26 @@ def detect(img: np.ndarray, t: int, O: int) -> np.ndarray:
     return out[:n].copy()
 
 
+def describe(level: np.ndarray, x: int, y: int):
+    """Orientation sector and 512-bit descriptor (8 uint64 words) of the
+    keypoint at (x, y) of a level image (R13-R15)."""
+    level = np.ascontiguousarray(level, dtype=np.uint8)
+    bits = np.zeros(8, np.uint64)
+    b = lib().orc_describe(_ptr(level), level.shape[1], level.shape[0], x, y, _ptr(bits))
+    return b, bits
+
+
+def desc_pattern(b: int):
+    """Rounded offsets (dx, dy) and box half-sizes of the 60 pattern points
+    turned to sector b."""
+    out = np.zeros((60, 3), np.int32)
+    dx, dy = ctypes.c_int(), ctypes.c_int()
+    for i in range(60):
+        out[i, 2] = lib().orc_desc_point(b, i, ctypes.byref(dx), ctypes.byref(dy))
+        out[i, 0], out[i, 1] = dx.value, dy.value
+    return out
+
+
 def cell_of(x: int, y: int, o: int, W: int, H: int, Nc: int, Nr: int) -> int:
     return lib().orc_cell_of(x, y, o, W, H, Nc, Nr)
 
@@ -163,6 +187,18 @@ class Stream:
         n2 = lib().orc_get(self.h, _ptr(kps), len(kps), _ptr(mask), _ptr(sad), _ptr(cnt))
         assert n2 == n
         return kps[:n].copy(), mask, sad, cnt
+
+    def set_descriptors(self, on: bool = True):
+        """Keep a descriptor with every feature of D_n (R13-R16)."""
+        lib().orc_set_descriptors(self.h, 1 if on else 0)
+
+    def descriptors(self):
+        """(sectors int32 [n], descriptors uint64 [n, 8]) of D_n, in D_n's order."""
+        n = lib().orc_get(self.h, None, 0, None, None, None)
+        bits = np.zeros((max(n, 1), 8), np.uint64)
+        bins = np.zeros(max(n, 1), np.int32)
+        assert lib().orc_get_desc(self.h, _ptr(bits), _ptr(bins), max(n, 1)) == n
+        return bins[:n].copy(), bits[:n].copy()
 
     def close(self):
         if self.h:

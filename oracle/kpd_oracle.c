@@ -72,7 +72,32 @@
  *       D_{n-1}'s feature there is kept (Eq. 1 per feature, as in R10). The
  *       per-cell mask reported is 1 for a cell marked by T_H or holding a
  *       level-0 pixel that the upsampled mask of any level (R9) sets.
+ *
+ * Sec. 3 models a feature as position, scale, orientation and a binary
+ * descriptor computed on the patch around the keypoint, and Eq. (1) carries
+ * whole features; the paper takes both from BRISK and fixes no parameter.
+ * With descriptors switched on (orc_set_descriptors):
+ *   R13 Pattern: 60 points in pixels of the keypoint's own level: the
+ *       centre and rings of (radius, points) (3, 10), (5, 14), (7.5, 15),
+ *       (11, 20); point i of a ring of n points sits at angle 2*pi*i/n, its
+ *       offset rounded half away from zero. Each point is smoothed by a box
+ *       of half-size 1 (centre and the two inner rings) or 2 (outer rings);
+ *       V = box sum * 225 / box area, an exact integer. Pixels outside the
+ *       level take the nearest edge pixel.
+ *   R14 Orientation: G = sum over long pairs (squared distance >= 169
+ *       between the unrotated rounded points) of (p_j - p_i)(V_j - V_i),
+ *       unweighted; its angle falls in one of 32 equal sectors, found
+ *       exactly against the integer boundary vectors round(2^20 (cos, sin)
+ *       (2*pi*b/32)); G = 0 takes sector 0.
+ *   R15 Descriptor: the pattern turned by 2*pi*b/32 for sector b (offsets
+ *       recomputed from the angles and rounded), smoothed again; bit k is
+ *       V_a > V_b for the k-th of the 512 shortest pairs (squared distance
+ *       of the unrotated points below 96; ordered by that distance, then a,
+ *       then b).
+ *   R16 Eq. (1) carries a feature whole: only the keypoints that are new in
+ *       D_n get a descriptor computed; carried ones keep theirs.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -270,6 +295,128 @@ int orc_cell_of(int x, int y, int o, int W, int H, int Nc, int Nr)
 
 /* ----------------------------------------------------------------- stream */
 
+/* ------------------------------------------------- descriptors (R13-R16) */
+
+#define ORC_NPTS 60
+#define ORC_BINS 32
+#define ORC_NBITS 512
+
+static const double ORC_PI = 3.14159265358979323846;
+static const double RING_R[5] = {0.0, 3.0, 5.0, 7.5, 11.0};
+static const int RING_N[5] = {1, 10, 14, 15, 20};
+static const int RING_H[5] = {1, 1, 1, 2, 2};
+
+static int d_ready = 0;
+static int d_pt[ORC_BINS][ORC_NPTS][2];   /* rounded offsets per sector (R13, R15) */
+static int d_half[ORC_NPTS];
+static int d_long[ORC_NPTS * ORC_NPTS][2], d_nlong = 0;
+static int d_short[ORC_NBITS][2];
+static long long d_ux[ORC_BINS], d_uy[ORC_BINS];
+
+static int round_away(double v) { return (int)lround(v); }
+
+static int pair_d2(int a, int b)
+{
+    const int dx = d_pt[0][a][0] - d_pt[0][b][0], dy = d_pt[0][a][1] - d_pt[0][b][1];
+    return dx * dx + dy * dy;
+}
+
+static void desc_tables(void)
+{
+    if (d_ready) return;
+    for (int b = 0; b < ORC_BINS; ++b) {
+        int i = 0;
+        for (int r = 0; r < 5; ++r)
+            for (int k = 0; k < RING_N[r]; ++k, ++i) {
+                const double a = (2.0 * ORC_PI * k) / RING_N[r] + (2.0 * ORC_PI * b) / ORC_BINS;
+                d_pt[b][i][0] = round_away(RING_R[r] * cos(a));
+                d_pt[b][i][1] = round_away(RING_R[r] * sin(a));
+                d_half[i] = RING_H[r];
+            }
+        d_ux[b] = llround(1048576.0 * cos((2.0 * ORC_PI * b) / ORC_BINS));
+        d_uy[b] = llround(1048576.0 * sin((2.0 * ORC_PI * b) / ORC_BINS));
+    }
+    /* long pairs in (a, b) order; short pairs: the 512 shortest */
+    int ns = 0;
+    static int cand[ORC_NPTS * ORC_NPTS][3];
+    for (int a = 0; a < ORC_NPTS; ++a)
+        for (int b = a + 1; b < ORC_NPTS; ++b) {
+            const int d2 = pair_d2(a, b);
+            if (d2 >= 169) { d_long[d_nlong][0] = a; d_long[d_nlong][1] = b; ++d_nlong; }
+            if (d2 < 96) { cand[ns][0] = d2; cand[ns][1] = a; cand[ns][2] = b; ++ns; }
+        }
+    /* selection by (d2, a, b): repeated minimum, plain and obviously ordered */
+    for (int k = 0; k < ORC_NBITS; ++k) {
+        int best = -1;
+        for (int q = 0; q < ns; ++q) {
+            if (cand[q][0] < 0) continue;
+            if (best < 0 || cand[q][0] < cand[best][0] ||
+                (cand[q][0] == cand[best][0] && (cand[q][1] < cand[best][1] ||
+                                                 (cand[q][1] == cand[best][1] && cand[q][2] < cand[best][2]))))
+                best = q;
+        }
+        d_short[k][0] = cand[best][1];
+        d_short[k][1] = cand[best][2];
+        cand[best][0] = -1;
+    }
+    d_ready = 1;
+}
+
+/* R13: smoothed value of pattern point i of sector b around (x, y). */
+static int point_value(const uint8_t* L, int w, int h, int x, int y, int b, int i)
+{
+    const int cx = x + d_pt[b][i][0], cy = y + d_pt[b][i][1], r = d_half[i];
+    long sum = 0;
+    for (int yy = cy - r; yy <= cy + r; ++yy)
+        for (int xx = cx - r; xx <= cx + r; ++xx) {
+            const int px = xx < 0 ? 0 : (xx > w - 1 ? w - 1 : xx);
+            const int py = yy < 0 ? 0 : (yy > h - 1 ? h - 1 : yy);
+            sum += L[(size_t)py * w + px];
+        }
+    const int area = (2 * r + 1) * (2 * r + 1);
+    return (int)(sum * (225 / area));
+}
+
+/* Rounded offset of pattern point i in sector b (for checking tables). */
+int orc_desc_point(int b, int i, int* dx, int* dy)
+{
+    if (b < 0 || b >= ORC_BINS || i < 0 || i >= ORC_NPTS) return -1;
+    desc_tables();
+    *dx = d_pt[b][i][0];
+    *dy = d_pt[b][i][1];
+    return d_half[i];
+}
+
+/* R14-R15: sector and 512-bit descriptor of the keypoint at (x, y) of the
+ * level image L (w x h). */
+int orc_describe(const uint8_t* L, int w, int h, int x, int y, uint64_t* bits)
+{
+    desc_tables();
+    int V[ORC_NPTS];
+    for (int i = 0; i < ORC_NPTS; ++i) V[i] = point_value(L, w, h, x, y, 0, i);
+    long long gx = 0, gy = 0;
+    for (int q = 0; q < d_nlong; ++q) {
+        const int a = d_long[q][0], b = d_long[q][1];
+        const long long dv = (long long)V[b] - V[a];
+        gx += (long long)(d_pt[0][b][0] - d_pt[0][a][0]) * dv;
+        gy += (long long)(d_pt[0][b][1] - d_pt[0][a][1]) * dv;
+    }
+    int bin = 0;
+    if (gx != 0 || gy != 0) {
+        for (int b = 0; b < ORC_BINS; ++b) {
+            const int n = (b + 1) % ORC_BINS;
+            const long long c0 = d_ux[b] * gy - d_uy[b] * gx;   /* >= 0: G at or counterclockwise of boundary b */
+            const long long c1 = d_ux[n] * gy - d_uy[n] * gx;   /* < 0: G clockwise of boundary b + 1 */
+            if (c0 >= 0 && c1 < 0) { bin = b; break; }
+        }
+    }
+    for (int i = 0; i < ORC_NPTS; ++i) V[i] = point_value(L, w, h, x, y, bin, i);
+    for (int k = 0; k < ORC_NBITS / 64; ++k) bits[k] = 0;
+    for (int k = 0; k < ORC_NBITS; ++k)
+        if (V[d_short[k][0]] > V[d_short[k][1]]) bits[k >> 6] |= 1ull << (k & 63);
+    return bin;
+}
+
 typedef struct {
     int W, H, O, Nc, Nr;
     int t;
@@ -285,6 +432,9 @@ typedef struct {
     int nK;
     int capK;
     uint8_t* mask;       /* M_n per cell */
+    int desc_on;         /* R13-R16: descriptors kept with D_n */
+    uint64_t* desc;      /* 8 words per feature of D_n */
+    int32_t* bin;        /* orientation sector per feature of D_n */
     int64_t* sad;        /* per-cell summed |I_n - I_{n-1}| */
     uint32_t* count;     /* per-cell keypoint count of D_n */
 } orc_stream;
@@ -308,7 +458,7 @@ orc_stream* orc_open(int W, int H, int t, int O, int Nc, int Nr, int32_t TI, uin
 void orc_close(orc_stream* s)
 {
     if (!s) return;
-    free(s->prev); free(s->K); free(s->mask); free(s->sad); free(s->count);
+    free(s->prev); free(s->K); free(s->mask); free(s->sad); free(s->count); free(s->desc); free(s->bin);
     free(s);
 }
 
@@ -334,6 +484,29 @@ int orc_set_id_mode(orc_stream* s, int mode, int layer)
     return 0;
 }
 
+/* Keep a descriptor with every feature of D_n (R13-R16) from the next frame
+ * on; switching on re-detects every cell once, so that every feature has
+ * one. */
+int orc_set_descriptors(orc_stream* s, int on)
+{
+    if (on && !s->desc_on) {
+        s->desc = (uint64_t*)calloc((size_t)s->capK * 8, sizeof(uint64_t));
+        s->bin = (int32_t*)calloc((size_t)s->capK, sizeof(int32_t));
+        s->force_all = 1;
+    }
+    s->desc_on = on != 0;
+    return 0;
+}
+
+/* Copy out the descriptors (8 words each) and sectors of D_n. */
+int orc_get_desc(orc_stream* s, uint64_t* bits, int32_t* bins, int cap)
+{
+    if (!s->desc_on || cap < s->nK) return -1;
+    memcpy(bits, s->desc, sizeof(uint64_t) * 8 * (size_t)s->nK);
+    memcpy(bins, s->bin, sizeof(int32_t) * (size_t)s->nK);
+    return s->nK;
+}
+
 /* A reset (a scene cut signalled by the caller) treats the next frame like
  * the first one: every cell is detected. */
 int orc_reset(orc_stream* s)
@@ -355,6 +528,17 @@ static int kp_cmp(const void* a, const void* b)
     if (p->y != q->y) return p->y < q->y ? -1 : 1;
     if (p->x != q->x) return p->x < q->x ? -1 : 1;
     return 0;
+}
+
+typedef struct {
+    orc_kp k;
+    int32_t bin;
+    uint64_t bits[8];
+} orc_feat;
+
+static int feat_cmp(const void* a, const void* b)
+{
+    return kp_cmp(&((const orc_feat*)a)->k, &((const orc_feat*)b)->k);
 }
 
 /* R10 and R12: M_n for feature k, read on layer id_layer at k's level-0
@@ -442,14 +626,44 @@ int orc_push(orc_stream* s, const uint8_t* frame)
     int nF = orc_detect(frame, W, H, s->t, s->O, F, s->capK);
     if (nF < 0) { free(F); return -1; }
 
-    /* Eq. (1): new features where the mask is 1, previous ones elsewhere */
-    orc_kp* D = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)(nF + s->nK + 1));
+    /* Eq. (1): new features where the mask is 1, previous ones elsewhere;
+     * with descriptors, new features get theirs computed (R16) */
+    orc_feat* D = (orc_feat*)calloc((size_t)(nF + s->nK + 1), sizeof(orc_feat));
+    uint8_t* pyr = NULL;
+    int dws[32], dhs[32];
+    size_t doff[32];
+    if (s->desc_on) {
+        const long tot = orc_level_dims(W, H, s->O, dws, dhs);
+        pyr = (uint8_t*)malloc((size_t)tot);
+        orc_pyramid(frame, W, H, s->O, pyr);
+        size_t off = 0;
+        for (int o = 0; o < s->O; ++o) { doff[o] = off; off += (size_t)dws[o] * dhs[o]; }
+    }
     int nD = 0;
+    for (int i = 0; i < nF; ++i) {
+        const int keep = per_pixel ? pixel_mask(s, pix, lw, lh, &F[i])
+                                   : s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)] != 0;
+        if (!keep) continue;
+        D[nD].k = F[i];
+        if (pyr) {
+            const int o = F[i].octave;
+            D[nD].bin = orc_describe(pyr + doff[o], dws[o], dhs[o], F[i].x, F[i].y, D[nD].bits);
+        }
+        ++nD;
+    }
+    for (int i = 0; i < s->nK; ++i) {
+        const int keep = per_pixel ? !pixel_mask(s, pix, lw, lh, &s->K[i])
+                                   : !s->mask[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)];
+        if (!keep) continue;
+        D[nD].k = s->K[i];
+        if (pyr) {
+            D[nD].bin = s->bin[i];
+            memcpy(D[nD].bits, s->desc + (size_t)i * 8, sizeof(D[nD].bits));
+        }
+        ++nD;
+    }
+    free(pyr);
     if (per_pixel) {
-        for (int i = 0; i < nF; ++i)
-            if (pixel_mask(s, pix, lw, lh, &F[i])) D[nD++] = F[i];
-        for (int i = 0; i < s->nK; ++i)
-            if (!pixel_mask(s, pix, lw, lh, &s->K[i])) D[nD++] = s->K[i];
         /* reported per-cell mask: T_H, or a changed pixel of a layer, upsampled, in the cell */
         for (int l = l0; l <= l1; ++l) {
             for (int Y = 0; Y < H; ++Y)
@@ -461,20 +675,21 @@ int orc_push(orc_stream* s, const uint8_t* frame)
                 }
             free(pix[l]);
         }
-    } else {
-        for (int i = 0; i < nF; ++i)
-            if (s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)]) D[nD++] = F[i];
-        for (int i = 0; i < s->nK; ++i)
-            if (!s->mask[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)]) D[nD++] = s->K[i];
     }
     kp_cmp_ctx_W = W; kp_cmp_ctx_H = H; kp_cmp_ctx_Nc = Nc; kp_cmp_ctx_Nr = Nr;
-    qsort(D, (size_t)nD, sizeof(orc_kp), kp_cmp);
+    qsort(D, (size_t)nD, sizeof(orc_feat), feat_cmp);
     if (nD > s->capK) { free(F); free(D); return -1; }
-    memcpy(s->K, D, sizeof(orc_kp) * (size_t)nD);
+    for (int i = 0; i < nD; ++i) {
+        s->K[i] = D[i].k;
+        if (s->desc_on) {
+            s->bin[i] = D[i].bin;
+            memcpy(s->desc + (size_t)i * 8, D[i].bits, sizeof(D[i].bits));
+        }
+    }
     s->nK = nD;
     for (int c = 0; c < ncell; ++c) s->count[c] = 0;
     for (int i = 0; i < nD; ++i)
-        s->count[orc_cell_of(D[i].x, D[i].y, D[i].octave, W, H, Nc, Nr)] += 1;
+        s->count[orc_cell_of(D[i].k.x, D[i].k.y, D[i].k.octave, W, H, Nc, Nr)] += 1;
     free(F);
     free(D);
 

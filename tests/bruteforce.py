@@ -191,3 +191,67 @@ class Stream:
         self.prev = frame.copy()
         self.force = False
         return new
+
+
+# ------------------------------------------------- descriptors (R13-R15)
+
+_RINGS = ((0.0, 1, 1), (3.0, 10, 1), (5.0, 14, 1), (7.5, 15, 2), (11.0, 20, 2))   # radius, points, box half-size
+
+
+def _round_away(v: float) -> int:
+    return int(math.copysign(math.floor(abs(v) + 0.5), v))
+
+
+def desc_points(b: int):
+    """Pattern points turned to sector b: (dx, dy, half) per point."""
+    pts = []
+    for R, n, h in _RINGS:
+        for k in range(n):
+            a = (2.0 * math.pi * k) / n + (2.0 * math.pi * b) / 32
+            pts.append((_round_away(R * math.cos(a)), _round_away(R * math.sin(a)), h))
+    return pts
+
+
+def desc_pairs():
+    p0 = desc_points(0)
+    d2 = lambda a, b: (p0[a][0] - p0[b][0]) ** 2 + (p0[a][1] - p0[b][1]) ** 2
+    pairs = [(a, b) for a in range(60) for b in range(a + 1, 60)]
+    long_pairs = [(a, b) for a, b in pairs if d2(a, b) >= 169]
+    short = sorted(((d2(a, b), a, b) for a, b in pairs if d2(a, b) < 96))[:512]
+    return long_pairs, [(a, b) for _, a, b in short]
+
+
+def describe(level: np.ndarray, x: int, y: int):
+    """Sector and descriptor words (8 x uint64) of the keypoint at (x, y)."""
+    padded = np.pad(level.astype(np.int64), 2 + 11 + 2, mode="edge")
+    off = 2 + 11 + 2
+
+    def values(b):
+        out = []
+        for dx, dy, h in desc_points(b):
+            cx, cy = x + dx + off, y + dy + off
+            box = padded[cy - h:cy + h + 1, cx - h:cx + h + 1]
+            out.append(int(box.sum()) * (225 // box.size))
+        return out
+
+    long_pairs, short_pairs = desc_pairs()
+    p0 = desc_points(0)
+    V = values(0)
+    gx = sum((p0[b][0] - p0[a][0]) * (V[b] - V[a]) for a, b in long_pairs)
+    gy = sum((p0[b][1] - p0[a][1]) * (V[b] - V[a]) for a, b in long_pairs)
+    U = [(_round_away(1048576.0 * math.cos((2.0 * math.pi * b) / 32)),
+          _round_away(1048576.0 * math.sin((2.0 * math.pi * b) / 32))) for b in range(32)]
+    sector = 0
+    if gx or gy:
+        for b in range(32):
+            ux, uy = U[b]
+            vx, vy = U[(b + 1) % 32]
+            if ux * gy - uy * gx >= 0 and vx * gy - vy * gx < 0:
+                sector = b
+                break
+    V = values(sector)
+    words = [0] * 8
+    for k, (a, b) in enumerate(short_pairs):
+        if V[a] > V[b]:
+            words[k >> 6] |= 1 << (k & 63)
+    return sector, np.array(words, np.uint64)

@@ -571,6 +571,94 @@ def test_octave_masks_unchanged_frame_and_mode_errors():
         s.set_id_mode(3, 0)
 
 
+# ------------------------------------------------ descriptors (R13-R16)
+
+def test_descriptor_matches_bruteforce():
+    rng = np.random.default_rng(17)
+    for h, w in ((40, 56), (25, 31), (9, 13)):
+        img = rng.integers(0, 256, size=(h + 4, w + 4)).astype(np.float64)
+        img = (img[:-4, :-4] + img[2:-2, 2:-2] + img[4:, 4:] + img[4:, :-4]) / 4   # some spatial structure
+        level = np.clip(np.rint(img), 0, 255).astype(np.uint8)
+        for x, y in ((w // 2, h // 2), (0, 0), (w - 1, h - 1), (3, h - 2), (w - 4, 5)):
+            b, bits = oracle.describe(level, x, y)
+            eb, ebits = bf.describe(level, x, y)
+            assert b == eb, (h, w, x, y)
+            np.testing.assert_array_equal(bits, ebits, err_msg=f"{h}x{w} at {x},{y}")
+
+
+def test_descriptor_pattern_is_the_stated_rings():
+    # 60 points: the centre, then rings of 10, 14, 15 and 20 points at radii
+    # 3, 5, 7.5 and 11; the rounded offsets stay within half a pixel of the ring
+    for b in (0, 5, 17):
+        pat = oracle.desc_pattern(b)
+        assert pat.shape == (60, 3)
+        assert tuple(pat[0]) == (0, 0, 1)
+        starts = [1, 11, 25, 40, 60]
+        for R, h, s0, s1 in zip((3, 5, 7.5, 11), (1, 1, 2, 2), starts[:-1], starts[1:]):
+            r = np.hypot(pat[s0:s1, 0], pat[s0:s1, 1])
+            assert np.all(np.abs(r - R) <= np.sqrt(0.5) + 1e-9)
+            assert np.all(pat[s0:s1, 2] == h)
+        assert len({(int(a), int(c)) for a, c, _ in pat}) == 60
+
+
+def test_descriptor_of_constant_patch():
+    level = np.full((30, 30), 77, np.uint8)
+    b, bits = oracle.describe(level, 15, 15)
+    assert b == 0 and not bits.any()
+
+
+@pytest.mark.parametrize("direction,sector", [((1, 0), 0), ((0, 1), 8), ((-1, 0), 16), ((0, -1), 24)])
+def test_descriptor_orientation_follows_the_gradient(direction, sector):
+    # a linear ramp: the pattern's intensity gradient points along it
+    yy, xx = np.mgrid[0:64, 0:64]
+    level = np.clip(128 + 3 * (direction[0] * (xx - 32) + direction[1] * (yy - 32)), 0, 255).astype(np.uint8)
+    b, bits = oracle.describe(level, 32, 32)
+    if direction[1] == 0:
+        # the pattern is symmetric under y -> -y, so a ramp along x gives a
+        # gradient exactly on the x axis: a sector boundary, which belongs
+        # to the sector it starts
+        assert b == sector
+    else:
+        assert (b - sector) % 32 in (0, 1, 31)
+    # brighter points lie further along the ramp: bit k is set iff point a is further along than point b
+    pat = oracle.desc_pattern(b)
+    _, short_pairs = bf.desc_pairs()
+    along = lambda i: direction[0] * pat[i, 0] + direction[1] * pat[i, 1]
+    for k, (a, c) in enumerate(short_pairs):
+        if along(a) != along(c):
+            assert bool((int(bits[k >> 6]) >> (k & 63)) & 1) == (along(a) > along(c)), k
+
+
+def test_stream_descriptors_follow_eq1():
+    frames = _scene(seed=52, frames=4, w=96, h=72, move=0.8)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, 6)
+    s.set_descriptors(True)
+    s.push(frames[0])
+    k0 = kps_tuples(s.get()[0])
+    b0, d0 = s.descriptors()
+    pyr = oracle.pyramid(frames[0], O)
+    for (x, y, o, _), b, d in zip(k0, b0, d0):   # frame 0 marks every cell: every feature is new
+        eb, ed = oracle.describe(pyr[o], x, y)
+        assert b == eb and np.array_equal(d, ed)
+    s.push(frames[0])                               # unchanged: every feature and descriptor carried
+    assert kps_tuples(s.get()[0]) == k0
+    b1, d1 = s.descriptors()
+    assert np.array_equal(b1, b0) and np.array_equal(d1, d0)
+    s.push(frames[1])                               # marked cells: new descriptors; the rest carried
+    k2, m2, _, _ = s.get()
+    b2, d2 = s.descriptors()
+    old = {k: (b, tuple(d)) for k, b, d in zip(k0, b0, d0)}
+    pyr = oracle.pyramid(frames[1], O)
+    for (x, y, o, v), b, d in zip(kps_tuples(k2), b2, d2):
+        if m2[bf.kp_cell((x, y, o), W, H, Nc, Nr)]:
+            eb, ed = oracle.describe(pyr[o], x, y)
+            assert b == eb and np.array_equal(d, ed)
+        else:
+            assert old[(x, y, o, v)] == (b, tuple(d))
+    assert m2.any() and not m2.all()
+
+
 # ------------------------------------------------------ stored regression values
 
 @pytest.mark.parametrize("name,det", [
