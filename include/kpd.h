@@ -86,7 +86,11 @@ extern "C" {
  *              previous frame's readable. Eq. 1 per feature can then place a carried
  *              and a new feature side by side, so D_n is sized for every
  *              decision pixel instead of one feature per 2x2 block. 0: no.
- *   reserved   must be 0. */
+ *   descriptors
+ *              1: every feature of D_n carries an orientation sector and a
+ *              512-bit binary descriptor (get_descriptors), computed for the
+ *              keypoints new in D_n and carried with the others (Sec. 3,
+ *              Eq. 1); push_frame only, mask mode 0. 0: no. */
 typedef struct kpd_params {
     int32_t fast_t;
     int32_t n_octaves;
@@ -97,7 +101,7 @@ typedef struct kpd_params {
     int32_t tile;
     int32_t chunk_frames;
     int32_t layer_mask;
-    int32_t reserved;
+    int32_t descriptors;
 } kpd_params;
 
 /* One feature of D_n (Sec. 3: position and scale; the integer part).
@@ -171,6 +175,35 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
  * push_frame only: push_frames and batch_push return KPD_EINVAL while one
  * is set, and so does either mode on a stream opened without layer_mask. */
 int set_mask_mode(kpd_stream* s, int mode, int layer);
+
+/* Orientation and binary descriptor of one feature (Sec. 3: a feature is
+ * position, scale, orientation and a binary descriptor). The pattern is 60
+ * points in pixels of the keypoint's level: the centre and rings of
+ * (radius, points) (3, 10), (5, 14), (7.5, 15), (11, 20), point i of a ring
+ * of n at angle 2*pi*i/n, offsets rounded half away from zero, each point
+ * the mean of a box of half-size 1 (centre, inner two rings) or 2 (outer
+ * rings), edge pixels repeated outside the level. `sector` (0..31) is the
+ * angle of the sum over point pairs at squared distance >= 169 of
+ * (p_j - p_i)(V_j - V_i), in 32 equal sectors; `bits` holds, for the 512
+ * shortest pairs (squared distance < 96, by distance then indices), bit k
+ * = V_a > V_b with the pattern turned by 2*pi*sector/32 (bit k in word
+ * k / 64, bit k % 64). */
+typedef struct kpd_descriptor {
+    uint32_t sector;
+    uint32_t pad;
+    uint64_t bits[8];
+} kpd_descriptor;
+
+/* Descriptors of D_n, in get_keypoints' order (streams opened with
+ * descriptors = 1). `*count` receives the number of features; when it
+ * exceeds `capacity`, nothing is copied and KPD_ETRUNC is returned.
+ * KPD_EINVAL without descriptors, KPD_ESTATE before the first push. */
+int get_descriptors(kpd_stream* s, kpd_descriptor* out, size_t capacity, size_t* count);
+
+/* The descriptor pattern's point i (0..59) turned to `sector` (0..31):
+ * rounded offsets in level pixels and the box half-size (returned; -1 for
+ * out-of-range arguments). Host only, no stream needed. */
+int kpd_desc_point(int sector, int i, int* dx, int* dy);
 
 /* Wait for the last pushed frame and copy D_n to host memory `out`, ordered
  * by cell (row-major), then octave, then y, then x. `*count` receives the
@@ -274,8 +307,9 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
 #define KPD_K_FRAME 0
 #define KPD_K_DETECT 1
 #define KPD_K_COMPACT 2 /* compaction pass of push_frames */
-#define KPD_K_MARK 3    /* mark pass of push_frames when marks need no counts */
-#define KPD_NKERNELS 4
+#define KPD_K_MARK 3    /* mark, speculation and resolve passes of push_frames */
+#define KPD_K_DESCRIBE 4 /* descriptor pass of push_frame with descriptors */
+#define KPD_NKERNELS 5
 
 /* Switch per-kernel GPU timing on (1) or off (0). While on, every kernel
  * launch of this stream is bracketed by two HIP events recorded on the

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -57,6 +58,7 @@ struct Layout {
     size_t off_colmap = 0, off_rowmap = 0;   // cell column / row of every level-0 column / row
     // batch ticks: marked cells' keypoints at fixed per-cell bases, and counts
     size_t off_sparse1 = 0, off_own1 = 0;
+    size_t off_desc[2] = {0, 0}, off_dtab = 0;   // descriptors (streams opened with descriptors = 1)
     // chunks of consecutive frames (push_frames): K copies of the octaves,
     // per-frame SAD, sparse lists with per-cell counts, count words, marks
     // (cell-major, Kw 64-bit words per cell), dense lists with counts, offsets and
@@ -111,7 +113,7 @@ bool valid_params(int W, int H, const kpd_params* p, std::string* why)
         return false;
     }
     if (p->layer_mask != 0 && p->layer_mask != 1) { *why = "layer_mask must be 0 or 1"; return false; }
-    if (p->reserved != 0) { *why = "reserved must be 0"; return false; }
+    if (p->descriptors != 0 && p->descriptors != 1) { *why = "descriptors must be 0 or 1"; return false; }
     return true;
 }
 
@@ -228,6 +230,10 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
     L->off_own1 = off; off = align_up(off + (size_t)L->ncell * 4);
     L->off_sparse1 = off; off = align_up(off + L->list_cap1 * sizeof(kpd_keypoint));
+    if (p->descriptors) {   // descriptors of D_{n-1} and D_n, and the pattern tables
+        for (int k = 0; k < 2; ++k) { L->off_desc[k] = off; off = align_up(off + L->list_cap1 * sizeof(kpd_descriptor)); }
+        L->off_dtab = off; off = align_up(off + sizeof(kpd::DescTables));
+    }
     if (L->K > 1) {
         const size_t kc = (size_t)L->K * L->ncell;
         L->off_csad = off; off = align_up(off + kc * 4);
@@ -354,6 +360,63 @@ size_t stream_bytes(int width, int height, const kpd_params* params)
 }  // extern "C"
 
 namespace {
+
+// The descriptor pattern (the feature model of Sec. 3; kpd.h states the
+// pattern): 60 points, the centre and four rings, turned to each of 32
+// sectors and rounded half away from zero; the long pairs (squared distance
+// >= 169 between the unturned points) with their offset difference; the 512
+// shortest pairs (squared distance < 96, by distance, then indices); the
+// sector boundary vectors round(2^20 (cos, sin)).
+void build_desc_tables(kpd::DescTables* T)
+{
+    static const double kR[5] = {0.0, 3.0, 5.0, 7.5, 11.0};
+    static const int kN[5] = {1, 10, 14, 15, 20}, kH[5] = {1, 1, 1, 2, 2};
+    std::memset(T, 0, sizeof(*T));
+    for (int b = 0; b < kpd::kDescSectors; ++b) {
+        int i = 0;
+        for (int r = 0; r < 5; ++r)
+            for (int k = 0; k < kN[r]; ++k, ++i) {
+                const double a = (2.0 * M_PI * k) / kN[r] + (2.0 * M_PI * b) / kpd::kDescSectors;
+                T->pt[b][i][0] = (int8_t)std::lround(kR[r] * std::cos(a));
+                T->pt[b][i][1] = (int8_t)std::lround(kR[r] * std::sin(a));
+                T->half[i] = (uint8_t)kH[r];
+            }
+        T->ux[b] = std::llround(1048576.0 * std::cos((2.0 * M_PI * b) / kpd::kDescSectors));
+        T->uy[b] = std::llround(1048576.0 * std::sin((2.0 * M_PI * b) / kpd::kDescSectors));
+    }
+    struct Pair { int d2, a, b; };
+    std::vector<Pair> shorts;
+    for (int a = 0; a < kpd::kDescPts; ++a)
+        for (int b = a + 1; b < kpd::kDescPts; ++b) {
+            const int dx = T->pt[0][b][0] - T->pt[0][a][0], dy = T->pt[0][b][1] - T->pt[0][a][1];
+            const int d2 = dx * dx + dy * dy;
+            if (d2 >= 169) {
+                T->lp[T->nlong][0] = (uint8_t)a;
+                T->lp[T->nlong][1] = (uint8_t)b;
+                T->ld[T->nlong][0] = (int8_t)dx;
+                T->ld[T->nlong][1] = (int8_t)dy;
+                ++T->nlong;
+            }
+            if (d2 < 96) shorts.push_back({d2, a, b});
+        }
+    std::sort(shorts.begin(), shorts.end(), [](const Pair& x, const Pair& y) {
+        return x.d2 != y.d2 ? x.d2 < y.d2 : (x.a != y.a ? x.a < y.a : x.b < y.b);
+    });
+    for (int k = 0; k < kpd::kDescBits; ++k) {
+        T->sp[k][0] = (uint8_t)shorts[k].a;
+        T->sp[k][1] = (uint8_t)shorts[k].b;
+    }
+}
+
+const kpd::DescTables& desc_tables()
+{
+    static const kpd::DescTables* t = [] {
+        auto* p = new kpd::DescTables;
+        build_desc_tables(p);
+        return p;
+    }();
+    return *t;
+}
 
 // Fixed per-frame arguments of the chunk passes: frame j's octave copy, SAD
 // accumulators, sparse list, count words and marks. What changes between
@@ -486,6 +549,9 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && params->descriptors)
+        e = hipMemcpyAsync(s->arena + L.off_dtab, &desc_tables(), sizeof(kpd::DescTables), hipMemcpyHostToDevice,
+                           s->stream);
     std::vector<kpd::ChunkArgs> ctab;
     std::vector<kpd::FrameArgs> ftab;
     if (L.K > 1) {
@@ -695,6 +761,26 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
         KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(t.f, s->stream); }));
     const int lds = s->id_mode != 0 ? L.lds_bytes1 : L.lds_bytes;
     KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, lds, s->stream); }));
+    if (s->p.descriptors) {
+        const int fb_prev = s->fb_last, fb_cur = 1 - s->fb_last;
+        kpd::DescArgs da{};
+        da.tab = s->at<kpd::DescTables>(L.off_dtab);
+        for (int o = 0; o < L.O; ++o) {
+            da.lvl[o] = t.d.lvl[o];
+            da.pitch[o] = t.d.pitch[o];
+            da.w[o] = L.w[o];
+            da.h[o] = L.h[o];
+        }
+        da.mask = t.d.mask;
+        da.count_cur = t.d.count_cur;
+        da.off_cur = t.d.off_cur;
+        da.off_prev = t.d.off_prev;
+        da.list_cur = t.d.list_cur;
+        da.desc_prev = s->at<kpd_descriptor>(L.off_desc[fb_prev]);
+        da.desc_cur = s->at<kpd_descriptor>(L.off_desc[fb_cur]);
+        da.list_cap = (uint32_t)L.list_cap1;
+        KPD_HIP(timed(s, KPD_K_DESCRIBE, [&] { return kpd::launch_describe(da, L.ncell, s->stream); }));
+    }
     advance_frame(s, t);
     return KPD_OK;
 }
@@ -706,6 +792,7 @@ int set_mask_mode(kpd_stream* s, int mode, int layer)
     if (layer < 0 || layer >= s->L.O) return fail(KPD_EINVAL, "layer must be an octave of the stream");
     if (mode == 2 && layer != 0) return fail(KPD_EINVAL, "mode 2 masks every octave on its own level: layer must be 0");
     if (mode != 0 && !s->p.layer_mask) return fail(KPD_EINVAL, "stream opened without layer_mask");
+    if (mode != 0 && s->p.descriptors) return fail(KPD_EINVAL, "descriptors run with mask mode 0 only");
     if (mode == s->id_mode && (mode != 1 || layer == s->id_layer)) return KPD_OK;
     if (mode != 0) KPD_HIP(kpd::set_detect_lds_limit(s->L.lds_bytes1));
     s->id_mode = mode;
@@ -721,6 +808,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     const Layout& L = s->L;
     if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
+    if (s->p.descriptors) return fail(KPD_EINVAL, "descriptors run on single-frame pushes only");
     if (!frames) return fail(KPD_EINVAL, "frames is NULL");
     if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
@@ -893,6 +981,39 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
     }
     if (cell_mask) std::memcpy(cell_mask, st_mask, (size_t)L.ncell);
     return KPD_OK;
+}
+
+int get_descriptors(kpd_stream* s, kpd_descriptor* out, size_t capacity, size_t* count)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!count) return fail(KPD_EINVAL, "count is NULL");
+    if (!s->p.descriptors) return fail(KPD_EINVAL, "stream opened without descriptors");
+    if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
+    const Layout& L = s->L;
+    const int k = s->fb_last;
+    uint32_t hdr[4];
+    KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
+    KPD_HIP(hipStreamSynchronize(s->stream));
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
+    const uint32_t total = std::min<uint32_t>(hdr[k ? kHdrTotal1 : kHdrTotal0], (uint32_t)L.list_cap1);
+    *count = total;
+    if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the feature count");
+    if (total > 0) {
+        if (!out) return fail(KPD_EINVAL, "out is NULL");
+        KPD_HIP(hipMemcpyAsync(out, s->at<kpd_descriptor>(L.off_desc[k]), (size_t)total * sizeof(kpd_descriptor),
+                               hipMemcpyDeviceToHost, s->stream));
+        KPD_HIP(hipStreamSynchronize(s->stream));
+    }
+    return KPD_OK;
+}
+
+int kpd_desc_point(int sector, int i, int* dx, int* dy)
+{
+    if (sector < 0 || sector >= kpd::kDescSectors || i < 0 || i >= kpd::kDescPts || !dx || !dy) return -1;
+    const kpd::DescTables& T = desc_tables();
+    *dx = T.pt[sector][i][0];
+    *dy = T.pt[sector][i][1];
+    return T.half[i];
 }
 
 int close_stream(kpd_stream* s)
@@ -1116,6 +1237,7 @@ int batch_attach(kpd_batch* b, kpd_stream* s)
 {
     if (!b || !s || s->closed) return fail(KPD_ESTATE, "batch or stream is closed");
     if (s->stream != b->stream) return fail(KPD_EINVAL, "stream was opened on another HIP stream");
+    if (s->p.descriptors) return fail(KPD_EINVAL, "descriptors run on single-frame pushes only");
     if (std::find(b->streams.begin(), b->streams.end(), s) != b->streams.end())
         return fail(KPD_EINVAL, "stream already attached");
     if ((int)b->streams.size() >= b->max_streams) return fail(KPD_ENOMEM, "batch stream capacity exceeded");
@@ -1153,6 +1275,7 @@ int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_b
     const size_t i = (size_t)(it - b->streams.begin());
     if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
+    if (s->p.descriptors) return fail(KPD_EINVAL, "descriptors run on single-frame pushes only");
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
     if (rc != KPD_OK) return rc;
     b->has_frame[i] = 1;

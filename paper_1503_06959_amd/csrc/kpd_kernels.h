@@ -42,6 +42,38 @@ struct FrameSrc {
     uint32_t* sad;
 };
 
+// Descriptor pattern tables, built on the host at open: the 60 points turned
+// to each of the 32 sectors (rounded offsets in level pixels), their box
+// half-sizes, the long pairs with the unturned offset difference p_b - p_a,
+// the 512 short pairs in bit order, and the sector boundary vectors.
+constexpr int kDescPts = 60, kDescSectors = 32, kDescBits = 512, kDescLongMax = kDescPts * (kDescPts - 1) / 2;
+struct DescTables {
+    int8_t pt[kDescSectors][kDescPts][2];
+    uint8_t half[kDescPts];
+    int32_t nlong;
+    uint8_t lp[kDescLongMax][2];
+    int8_t ld[kDescLongMax][2];
+    uint8_t sp[kDescBits][2];
+    int64_t ux[kDescSectors], uy[kDescSectors];
+};
+
+// k_describe: descriptors of D_n's features, computed for the cells marked
+// this frame and carried with the keypoints of the others.
+struct DescArgs {
+    const DescTables* tab;
+    const uint8_t* lvl[KPD_MAX_OCTAVES];
+    int pitch[KPD_MAX_OCTAVES];
+    int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];
+    const uint8_t* mask;
+    const uint32_t* count_cur;
+    const uint32_t* off_cur;
+    const uint32_t* off_prev;
+    const kpd_keypoint* list_cur;
+    const kpd_descriptor* desc_prev;
+    kpd_descriptor* desc_cur;
+    uint32_t list_cap;
+};
+
 // k_detect: per-cell mark, detection, look-back offsets and output.
 struct DetectArgs {
     const uint8_t* lvl[KPD_MAX_OCTAVES];
@@ -185,6 +217,7 @@ int frame_lds_bytes(int tile, int O, int sad_slots);
 hipError_t set_detect_lds_limit(int lds_bytes);
 hipError_t launch_frame(const FrameArgs& a, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s);
+hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s);
 hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, uint32_t out_cap, uint32_t* counts,
                                hipStream_t s);

@@ -1215,6 +1215,92 @@ __device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8
 
 // ----------------------------------------------------------------- kernels
 
+// ------------------------------------------------------------ k_describe
+
+// Descriptors of one frame (Sec. 3 feature model; Eq. 1 carries whole
+// features). A workgroup per cell: an unmarked cell's features are D_{n-1}'s,
+// so their descriptors are copied in the same order; a marked cell's are new
+// and each of its four waves describes one feature at a time: a lane per
+// pattern point takes the box mean around its point, the lanes sum the long
+// pairs' gradient, 32 lanes test the sector boundaries, the points are taken
+// again turned to the sector, and eight ballots over the short pairs give the
+// bits.
+constexpr int kDescBlock = 256;
+
+__global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
+{
+    __shared__ int s_v[kDescBlock / 64][64];
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t n = a.count_cur[c], dst0 = a.off_cur[c];
+    if (!a.mask[c]) {
+        const uint32_t src0 = a.off_prev[c];
+        constexpr int kw = sizeof(kpd_descriptor) / 8;
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(a.desc_prev);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(a.desc_cur);
+        for (uint32_t i = threadIdx.x; i < n * kw; i += kDescBlock) {
+            const uint32_t e = i / kw;
+            if (src0 + e < a.list_cap && dst0 + e < a.list_cap)
+                dst[(size_t)(dst0 + e) * kw + i % kw] = src[(size_t)(src0 + e) * kw + i % kw];
+        }
+        return;
+    }
+    const DescTables& T = *a.tab;
+    int* V = s_v[wave];
+    for (uint32_t k = wave; k < n; k += kDescBlock / 64) {
+        if (dst0 + k >= a.list_cap) break;
+        const kpd_keypoint kp = a.list_cur[dst0 + k];
+        const int o = kp.octave;
+        const uint8_t* L = a.lvl[o];
+        const int pitch = a.pitch[o], w = a.w[o], h = a.h[o];
+        // box mean of point i turned to sector sct, edge pixels repeated
+        auto value = [&](int sct, int i) -> int {
+            const int cx = (int)kp.x + T.pt[sct][i][0], cy = (int)kp.y + T.pt[sct][i][1], r = T.half[i];
+            int sum = 0;
+            for (int yy = cy - r; yy <= cy + r; ++yy) {
+                const uint8_t* row = L + (size_t)min(max(yy, 0), h - 1) * pitch;
+                for (int xx = cx - r; xx <= cx + r; ++xx) sum += row[min(max(xx, 0), w - 1)];
+            }
+            return sum * (225 / ((2 * r + 1) * (2 * r + 1)));
+        };
+        if (lane < kDescPts) V[lane] = value(0, lane);
+        __builtin_amdgcn_wave_barrier();
+        long long gx = 0, gy = 0;
+        for (int q = lane; q < T.nlong; q += 64) {
+            const int dv = V[T.lp[q][1]] - V[T.lp[q][0]];
+            gx += (long long)T.ld[q][0] * dv;
+            gy += (long long)T.ld[q][1] * dv;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            gx += __shfl_xor(gx, off);
+            gy += __shfl_xor(gy, off);
+        }
+        bool in = false;
+        if (lane < kDescSectors) {
+            const int nx = (lane + 1) & (kDescSectors - 1);
+            in = T.ux[lane] * gy - T.uy[lane] * gx >= 0 && T.ux[nx] * gy - T.uy[nx] * gx < 0;
+        }
+        const uint64_t sec = __ballot(in);
+        const int sector = (gx == 0 && gy == 0) || !sec ? 0 : __builtin_ctzll(sec);
+        if (lane < kDescPts) V[lane] = value(sector, lane);
+        __builtin_amdgcn_wave_barrier();
+        uint64_t mine = 0;
+#pragma unroll
+        for (int r = 0; r < kDescBits / 64; ++r) {
+            const int q = r * 64 + lane;
+            const uint64_t b = __ballot(V[T.sp[q][0]] > V[T.sp[q][1]]);
+            if (lane == r) mine = b;
+        }
+        kpd_descriptor* D = a.desc_cur + dst0 + k;
+        if (lane < kDescBits / 64) D->bits[lane] = mine;
+        if (lane == kDescBits / 64) {
+            D->sector = (uint32_t)sector;
+            D->pad = 0;
+        }
+        __builtin_amdgcn_wave_barrier();   // V is reused by the wave's next feature
+    }
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin by index. The tile pass
 // runs on a grid rounded up to a multiple of 8 and hands XCD k the k-th
 // contiguous band of row-major tiles, so tiles that share cache lines share
@@ -1741,6 +1827,12 @@ hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s)
 {
     hipLaunchKernelGGL(k_detect1<kDetLatency>, dim3(ncell), dim3(kDetLatency), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_describe1, dim3(ncell), dim3(kDescBlock), 0, s, a);
     return hipGetLastError();
 }
 

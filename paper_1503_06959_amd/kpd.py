@@ -35,8 +35,10 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "close_stream", "reset_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats",
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
             "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
-            "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode")
-KERNEL_NAMES = ("k_frame", "k_detect", "k_compact", "k_mark")
+            "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
+            "kpd_desc_point")
+DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
+KERNEL_NAMES = ("k_frame", "k_detect", "k_compact", "k_mark", "k_describe")
 
 
 class KpdParams(ctypes.Structure):
@@ -44,7 +46,7 @@ class KpdParams(ctypes.Structure):
                 ("grid_cols", ctypes.c_int32), ("grid_rows", ctypes.c_int32),
                 ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32),
                 ("tile", ctypes.c_int32), ("chunk_frames", ctypes.c_int32),
-                ("layer_mask", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("layer_mask", ctypes.c_int32), ("descriptors", ctypes.c_int32)]
 
 
 class KpdError(RuntimeError):
@@ -88,6 +90,9 @@ def _load() -> ctypes.CDLL:
     L.kpd_chunk_result.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P)]
     L.get_chunk_keypoints.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
     L.set_mask_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    L.get_descriptors.argtypes = [P, P, sz, ctypes.POINTER(sz)]
+    L.kpd_desc_point.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int)]
     return L
 
 
@@ -102,9 +107,9 @@ def _check(rc: int) -> int:
 
 def make_params(fast_t: int, n_octaves: int, grid_cols: int, grid_rows: int,
                 id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0, chunk_frames: int = 0,
-                layer_mask: int = 0) -> KpdParams:
+                layer_mask: int = 0, descriptors: int = 0) -> KpdParams:
     return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, chunk_frames,
-                     layer_mask, 0)
+                     layer_mask, descriptors)
 
 
 def stream_bytes(width: int, height: int, params: KpdParams) -> int:
@@ -195,6 +200,28 @@ def set_mask_mode(handle: int, mode: int, layer: int = 0) -> None:
     difference on every level, each octave's features tested on their own
     level (layer 0). Modes 1 and 2 run on single-frame pushes."""
     _check(lib.set_mask_mode(handle, mode, layer))
+
+
+def get_descriptors(handle: int, capacity: int = 4096) -> np.ndarray:
+    """Descriptors of D_n (DESCRIPTOR_DTYPE), in get_keypoints' order."""
+    out = np.zeros(max(capacity, 1), DESCRIPTOR_DTYPE)
+    cnt = ctypes.c_size_t()
+    rc = lib.get_descriptors(handle, out.ctypes.data, len(out), ctypes.byref(cnt))
+    if rc == KPD_ETRUNC:
+        out = np.zeros(cnt.value, DESCRIPTOR_DTYPE)
+        rc = lib.get_descriptors(handle, out.ctypes.data, len(out), ctypes.byref(cnt))
+    _check(rc)
+    return out[:cnt.value].copy()
+
+
+def desc_point(sector: int, i: int) -> Tuple[int, int, int]:
+    """(dx, dy, box half-size) of the library's descriptor pattern point i
+    turned to `sector`."""
+    dx, dy = ctypes.c_int(), ctypes.c_int()
+    h = lib.kpd_desc_point(sector, i, ctypes.byref(dx), ctypes.byref(dy))
+    if h < 0:
+        raise KpdError(KPD_EINVAL, "sector or point out of range")
+    return dx.value, dy.value, h
 
 
 def close_stream(handle: int) -> None:
@@ -332,6 +359,10 @@ class Stream:
                                    mask.ctypes.data)
         _check(rc)
         return self._out[:cnt.value].copy(), mask
+
+    def descriptors(self) -> np.ndarray:
+        """Descriptors of D_n (streams opened with descriptors=1)."""
+        return get_descriptors(self.handle)
 
     def cell_stats(self):
         return cell_stats(self.handle, self.n_cells)

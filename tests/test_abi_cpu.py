@@ -143,3 +143,23 @@ def test_cell_geometry_partitions_and_covers_neighbourhoods(geom_check, shape):
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
     lds = int(out.stdout.split()[1])
     assert lds <= 160 * 1024
+
+
+def test_descriptor_pattern_matches_the_oracle(kpd):
+    # the library builds its pattern tables from the same stated rings as the
+    # oracle, in code of its own: every point of every sector agrees
+    import oracle
+    for sector in range(32):
+        pat = oracle.desc_pattern(sector)
+        lib_pat = [kpd.desc_point(sector, i) for i in range(60)]
+        assert [tuple(int(v) for v in row) for row in pat] == lib_pat, sector
+    with pytest.raises(kpd.KpdError):
+        kpd.desc_point(32, 0)
+
+
+def test_descriptor_flag_is_validated(kpd):
+    p = kpd.make_params(20, 4, 16, 12, descriptors=2)
+    assert kpd.lib.stream_bytes(640, 480, ctypes.byref(p)) == 0
+    base = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12))
+    with_desc = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, descriptors=1))
+    assert with_desc > base + 2 * 72 * 1000   # two descriptor lists and the tables
