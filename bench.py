@@ -108,12 +108,13 @@ class Workload:
 TILE = 0
 
 
-def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool = False, kb_thresh=None):
+def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool = False, kb_thresh=None,
+                descriptors: bool = False):
     from paper_1503_06959_amd import kpd
     d = wl.det
     kb = d.kb_thresh if kb_thresh is None else kb_thresh
     params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, kb, TILE, chunk,
-                             int(layer_mask))
+                             int(layer_mask), int(descriptors))
     s = kpd.Stream(wl.W, wl.H, params)
     s.chunk = chunk
     return s
@@ -261,6 +262,31 @@ def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> 
         out["k_detect"] = scan + 16 * carried + meta
         if layer is not None:   # the per-pixel test reads layer `layer` of I_n and I_{n-1}
             out["k_detect"] += 2 * lv[layer] * (F - 1)
+    return out
+
+
+def descriptor_workload(kpd, wl: Workload, args) -> dict:
+    """Descriptors of D_n (streaming, one push_frame per frame): masked
+    frames describe only the features of marked cells and carry the rest
+    (Eq. 1), full-frame ones describe every feature."""
+    out = {}
+    for name, ti in (("masked", wl.det.id_thresh), ("full_frame", -1)):
+        s = open_stream(wl, ti, descriptors=True)
+        sec = timed_passes(kpd, s, wl, max(1, args.steps // 5), 1)
+        prof = kernel_profile(kpd, s, wl, 2)
+        st = latency_pass(kpd, s, wl)
+        s.close()
+        out[name] = {"value": round(wl.F * wl.W * wl.H / sec / 1e6, 2), "unit": "Mpixel/s",
+                     "frames_per_s": round(wl.F / sec, 1),
+                     "latency_ms": {"p50": round(st["lat_p50"], 4), "p99": round(st["lat_p99"], 4)},
+                     "described_per_frame": round(sum(st["new_kp"]) / wl.F, 1),
+                     "features_per_frame": round(sum(st["total_kp"]) / wl.F, 1),
+                     "k_describe_avg_us": round(prof["k_describe"][0] * 1e3 / max(prof["k_describe"][1], 1), 3)
+                     if "k_describe" in prof else None}
+    out["what"] = (f"{wl.name}, one push_frame per frame with descriptors (60-point pattern, 32 sectors, 512 bits): "
+                   "masked frames describe the new features only, carried ones keep theirs")
+    out["described_masked_over_full"] = round(out["masked"]["described_per_frame"] /
+                                              max(out["full_frame"]["described_per_frame"], 1e-9), 4)
     return out
 
 
@@ -866,6 +892,8 @@ def main():
     }
     log("[bench] layer study")
     out["layer_study"] = layer_study(kpd, wl, args)
+    log("[bench] descriptors")
+    out["descriptors"] = descriptor_workload(kpd, wl, args)
     out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:
         del wl

@@ -1220,16 +1220,20 @@ __device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8
 // Descriptors of one frame (Sec. 3 feature model; Eq. 1 carries whole
 // features). A workgroup per cell: an unmarked cell's features are D_{n-1}'s,
 // so their descriptors are copied in the same order; a marked cell's are new
-// and each of its four waves describes one feature at a time: a lane per
-// pattern point takes the box mean around its point, the lanes sum the long
-// pairs' gradient, 32 lanes test the sector boundaries, the points are taken
-// again turned to the sector, and eight ballots over the short pairs give the
-// bits.
+// and each of its four waves describes one feature at a time: the wave loads
+// the feature's 27 x 27 patch (every point of the pattern, turned any way,
+// with its box) into LDS in one round of loads, a lane per pattern point
+// takes the box mean around its point, the lanes sum the long pairs'
+// gradient, 32 lanes test the sector boundaries, the points are taken again
+// turned to the sector, and eight ballots over the short pairs give the bits.
 constexpr int kDescBlock = 256;
+constexpr int kPatchR = 13;                  // pattern radius 11 plus a box half-size 2
+constexpr int kPatch = 2 * kPatchR + 1;      // patch side
 
 __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
 {
     __shared__ int s_v[kDescBlock / 64][64];
+    __shared__ uint8_t s_patch[kDescBlock / 64][kPatch * kPatch];
     const int c = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t n = a.count_cur[c], dst0 = a.off_cur[c];
@@ -1247,20 +1251,39 @@ __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
     }
     const DescTables& T = *a.tab;
     int* V = s_v[wave];
+    uint8_t* patch = s_patch[wave];
     for (uint32_t k = wave; k < n; k += kDescBlock / 64) {
         if (dst0 + k >= a.list_cap) break;
         const kpd_keypoint kp = a.list_cur[dst0 + k];
         const int o = kp.octave;
         const uint8_t* L = a.lvl[o];
         const int pitch = a.pitch[o], w = a.w[o], h = a.h[o];
-        // box mean of point i turned to sector sct, edge pixels repeated
-        auto value = [&](int sct, int i) -> int {
-            const int cx = (int)kp.x + T.pt[sct][i][0], cy = (int)kp.y + T.pt[sct][i][1], r = T.half[i];
-            int sum = 0;
-            for (int yy = cy - r; yy <= cy + r; ++yy) {
-                const uint8_t* row = L + (size_t)min(max(yy, 0), h - 1) * pitch;
-                for (int xx = cx - r; xx <= cx + r; ++xx) sum += row[min(max(xx, 0), w - 1)];
+        // the patch around the feature, edge pixels repeated
+        constexpr int kPer = (kPatch * kPatch + 63) / 64;
+        uint8_t px[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int q = u * 64 + lane;
+            px[u] = 0;
+            if (q < kPatch * kPatch) {
+                const int py = q / kPatch, pxx = q - py * kPatch;
+                const int yy = min(max((int)kp.y + py - kPatchR, 0), h - 1);
+                const int xx = min(max((int)kp.x + pxx - kPatchR, 0), w - 1);
+                px[u] = L[(size_t)yy * pitch + xx];
             }
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int q = u * 64 + lane;
+            if (q < kPatch * kPatch) patch[q] = px[u];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // box mean of point i turned to sector sct
+        auto value = [&](int sct, int i) -> int {
+            const int cx = kPatchR + T.pt[sct][i][0], cy = kPatchR + T.pt[sct][i][1], r = T.half[i];
+            int sum = 0;
+            for (int yy = cy - r; yy <= cy + r; ++yy)
+                for (int xx = cx - r; xx <= cx + r; ++xx) sum += patch[yy * kPatch + xx];
             return sum * (225 / ((2 * r + 1) * (2 * r + 1)));
         };
         if (lane < kDescPts) V[lane] = value(0, lane);
