@@ -61,6 +61,10 @@ def lib() -> ctypes.CDLL:
     L.orc_get_desc.argtypes = [P, P, P, ctypes.c_int]
     L.orc_describe.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
     L.orc_desc_point.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
+    L.orc_set_refine.argtypes = [P, ctypes.c_int]
+    L.orc_get_refined.argtypes = [P, P, ctypes.c_int]
+    L.orc_refine_kp.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+    L.orc_refine_kp.restype = None
     _lib = L
     return L
 
@@ -132,6 +136,19 @@ def describe(level: np.ndarray, x: int, y: int):
     return b, bits
 
 
+def refine(levels, t: int, x: int, y: int, o: int):
+    """Refined (x, y) in level-0 pixels, log2 scale and score of the
+    keypoint (x, y) of level o (R17-R19); `levels` is the pyramid."""
+    levels = [np.ascontiguousarray(l, dtype=np.uint8) for l in levels]
+    O = len(levels)
+    ptrs = (ctypes.c_void_p * 32)(*[l.ctypes.data for l in levels])
+    ws = np.array([l.shape[1] for l in levels] + [0] * (32 - O), np.int32)
+    hs = np.array([l.shape[0] for l in levels] + [0] * (32 - O), np.int32)
+    out = np.zeros(4, np.float32)
+    lib().orc_refine_kp(ptrs, _ptr(ws), _ptr(hs), O, t, x, y, o, _ptr(out))
+    return out
+
+
 def desc_pattern(b: int):
     """Rounded offsets (dx, dy) and box half-sizes of the 60 pattern points
     turned to sector b."""
@@ -191,6 +208,17 @@ class Stream:
     def set_descriptors(self, on: bool = True):
         """Keep a descriptor with every feature of D_n (R13-R16)."""
         lib().orc_set_descriptors(self.h, 1 if on else 0)
+
+    def set_refine(self, on: bool = True):
+        """Keep the refined position, log2 scale and score with every feature of D_n (R17-R19)."""
+        lib().orc_set_refine(self.h, 1 if on else 0)
+
+    def refined(self):
+        """float32 [n, 4]: refined x, y (level-0 pixels), log2 scale and score of D_n."""
+        n = lib().orc_get(self.h, None, 0, None, None, None)
+        out = np.zeros((max(n, 1), 4), np.float32)
+        assert lib().orc_get_refined(self.h, _ptr(out), max(n, 1)) == n
+        return out[:n].copy()
 
     def descriptors(self):
         """(sectors int32 [n], descriptors uint64 [n, 8]) of D_n, in D_n's order."""

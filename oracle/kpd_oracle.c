@@ -96,6 +96,27 @@
  *       then b).
  *   R16 Eq. (1) carries a feature whole: only the keypoints that are new in
  *       D_n get a descriptor computed; carried ones keep theirs.
+ * With refinement switched on (orc_set_refine), Sec. 2's sub-pixel and
+ * sub-scale interpolation, on the octave layers:
+ *   R17 On layer l, the 3 x 3 patch P(i, j) of FAST scores (R3; 0 outside the
+ *       candidate region) around a centre pixel is fit by a least-squares
+ *       quadratic. With integer sums A = P(1,.) - P(-1,.), B = P(.,1) -
+ *       P(.,-1), Cx = P(1,.) + P(-1,.) - 2P(0,.), Cy likewise, E = P(1,1) -
+ *       P(1,-1) - P(-1,1) + P(-1,-1), K0 = the 5/2/-1 centre stencil, and
+ *       D = 16 Cx Cy - 9 E^2: if D > 0 and Cx < 0 the maximum is at
+ *       (U/D, V/D), U = -8 Cy A + 6 E B, V = -8 Cx B + 6 E A, each clamped
+ *       to [-1, 1]; otherwise at (0, 0). Its value m follows from the fit.
+ *   R18 Layers: the keypoint's own (centre = the keypoint), the finer one
+ *       (centre (2x+1, 2y+1)) and the coarser one (centre (x>>1, y>>1)),
+ *       the pixels holding the keypoint's footprint centre; a missing layer
+ *       has m = 0 and the keypoint's own position. A parabola through the
+ *       three m along log2 scale gives t in [-1, 1] (0 when not concave), the
+ *       score at its vertex, log2 scale o + t, and the position interpolated
+ *       linearly between the own layer's maximum and the finer (t < 0) or
+ *       coarser (t > 0) one's, in level-0 pixels ((centre + 0.5 + offset) *
+ *       2^l). Every step is an IEEE double operation in a stated order, so
+ *       any implementation that keeps the order gets the same bits.
+ *   R19 Eq. (1) carries refined values with their features.
  */
 #include <math.h>
 #include <stdint.h>
@@ -417,6 +438,86 @@ int orc_describe(const uint8_t* L, int w, int h, int x, int y, uint64_t* bits)
     return bin;
 }
 
+/* ------------------------------------------------------ refinement (R17-R19) */
+
+/* R17: the quadratic fit of the 3 x 3 score patch of layer L around (cx, cy);
+ * the maximum's offsets and value. */
+static void fit_patch(const uint8_t* L, int w, int h, int t, int cx, int cy, double* u, double* v, double* m)
+{
+    long P[3][3];   /* P[i + 1][j + 1]: x offset i, y offset j */
+    for (int i = -1; i <= 1; ++i)
+        for (int j = -1; j <= 1; ++j) P[i + 1][j + 1] = score_at(L, w, h, cx + i, cy + j, t);
+    long sx[3], sy[3];
+    for (int k = 0; k < 3; ++k) {
+        sx[k] = P[k][0] + P[k][1] + P[k][2];
+        sy[k] = P[0][k] + P[1][k] + P[2][k];
+    }
+    const long A = sx[2] - sx[0], B = sy[2] - sy[0];
+    const long Cx = sx[2] + sx[0] - 2 * sx[1], Cy = sy[2] + sy[0] - 2 * sy[1];
+    const long E = P[2][2] - P[2][0] - P[0][2] + P[0][0];
+    const long K0 = -P[0][0] + 2 * P[1][0] - P[2][0] + 2 * P[0][1] + 5 * P[1][1] + 2 * P[2][1] - P[0][2] +
+                    2 * P[1][2] - P[2][2];
+    const long D = 16 * Cx * Cy - 9 * E * E;
+    long U = 0, V = 0, Dn = 1;
+    if (D > 0 && Cx < 0) {
+        U = -8 * Cy * A + 6 * E * B;
+        V = -8 * Cx * B + 6 * E * A;
+        Dn = D;
+        if (U > D) U = D;
+        if (U < -D) U = -D;
+        if (V > D) V = D;
+        if (V < -D) V = -D;
+    }
+    *u = (double)U / (double)Dn;
+    *v = (double)V / (double)Dn;
+    double f = (double)K0 / 9.0;
+    f = f + ((double)A / 6.0) * *u;
+    f = f + ((double)B / 6.0) * *v;
+    f = f + (((double)Cx / 6.0) * *u) * *u;
+    f = f + (((double)E / 4.0) * *u) * *v;
+    f = f + (((double)Cy / 6.0) * *v) * *v;
+    *m = f;
+}
+
+/* R18: refined position (level-0 pixels), log2 scale and score of the
+ * keypoint (x, y) of level o; lv[l], ws[l], hs[l] are the pyramid levels. */
+void orc_refine_kp(uint8_t* const* lv, const int* ws, const int* hs, int O, int t, int x, int y, int o, float* out)
+{
+    double m[3] = {0.0, 0.0, 0.0}, X[3], Y[3];   /* finer, own, coarser */
+    for (int k = 0; k < 3; ++k) {
+        const int l = o - 1 + k;
+        if (l < 0 || l >= O) continue;
+        const int cx = k == 0 ? 2 * x + 1 : (k == 1 ? x : x >> 1);
+        const int cy = k == 0 ? 2 * y + 1 : (k == 1 ? y : y >> 1);
+        double u, v;
+        fit_patch(lv[l], ws[l], hs[l], t, cx, cy, &u, &v, &m[k]);
+        X[k] = (((double)cx + 0.5) + u) * (double)(1 << l);
+        Y[k] = (((double)cy + 0.5) + v) * (double)(1 << l);
+    }
+    if (o == 0) { X[0] = X[1]; Y[0] = Y[1]; }
+    if (o + 1 >= O) { X[2] = X[1]; Y[2] = Y[1]; }
+    const double q = (m[0] - 2.0 * m[1]) + m[2];
+    double tt = 0.0;
+    if (q < 0.0) {
+        tt = (m[0] - m[2]) / (2.0 * q);
+        if (tt > 1.0) tt = 1.0;
+        if (tt < -1.0) tt = -1.0;
+    }
+    const double score = (m[1] + (0.5 * (m[2] - m[0])) * tt) + (0.5 * q) * (tt * tt);
+    double px, py;
+    if (tt >= 0.0) {
+        px = X[1] + tt * (X[2] - X[1]);
+        py = Y[1] + tt * (Y[2] - Y[1]);
+    } else {
+        px = X[1] + (-tt) * (X[0] - X[1]);
+        py = Y[1] + (-tt) * (Y[0] - Y[1]);
+    }
+    out[0] = (float)px;
+    out[1] = (float)py;
+    out[2] = (float)((double)o + tt);
+    out[3] = (float)score;
+}
+
 typedef struct {
     int W, H, O, Nc, Nr;
     int t;
@@ -433,6 +534,8 @@ typedef struct {
     int capK;
     uint8_t* mask;       /* M_n per cell */
     int desc_on;         /* R13-R16: descriptors kept with D_n */
+    int ref_on;          /* R17-R19: refined position, scale and score kept with D_n */
+    float* ref;          /* 4 floats per feature of D_n */
     uint64_t* desc;      /* 8 words per feature of D_n */
     int32_t* bin;        /* orientation sector per feature of D_n */
     int64_t* sad;        /* per-cell summed |I_n - I_{n-1}| */
@@ -458,7 +561,7 @@ orc_stream* orc_open(int W, int H, int t, int O, int Nc, int Nr, int32_t TI, uin
 void orc_close(orc_stream* s)
 {
     if (!s) return;
-    free(s->prev); free(s->K); free(s->mask); free(s->sad); free(s->count); free(s->desc); free(s->bin);
+    free(s->prev); free(s->K); free(s->mask); free(s->sad); free(s->count); free(s->desc); free(s->bin); free(s->ref);
     free(s);
 }
 
@@ -498,6 +601,27 @@ int orc_set_descriptors(orc_stream* s, int on)
     return 0;
 }
 
+/* Keep the refined position, log2 scale and score with every feature of
+ * D_n (R17-R19) from the next frame on; switching on re-detects every cell
+ * once. */
+int orc_set_refine(orc_stream* s, int on)
+{
+    if (on && !s->ref_on) {
+        s->ref = (float*)calloc((size_t)s->capK * 4, sizeof(float));
+        s->force_all = 1;
+    }
+    s->ref_on = on != 0;
+    return 0;
+}
+
+/* Copy out the refined values (x, y, log2 scale, score) of D_n. */
+int orc_get_refined(orc_stream* s, float* out, int cap)
+{
+    if (!s->ref_on || cap < s->nK) return -1;
+    memcpy(out, s->ref, sizeof(float) * 4 * (size_t)s->nK);
+    return s->nK;
+}
+
 /* Copy out the descriptors (8 words each) and sectors of D_n. */
 int orc_get_desc(orc_stream* s, uint64_t* bits, int32_t* bins, int cap)
 {
@@ -534,6 +658,7 @@ typedef struct {
     orc_kp k;
     int32_t bin;
     uint64_t bits[8];
+    float ref[4];
 } orc_feat;
 
 static int feat_cmp(const void* a, const void* b)
@@ -632,12 +757,13 @@ int orc_push(orc_stream* s, const uint8_t* frame)
     uint8_t* pyr = NULL;
     int dws[32], dhs[32];
     size_t doff[32];
-    if (s->desc_on) {
+    uint8_t* lvp[32];
+    if (s->desc_on || s->ref_on) {
         const long tot = orc_level_dims(W, H, s->O, dws, dhs);
         pyr = (uint8_t*)malloc((size_t)tot);
         orc_pyramid(frame, W, H, s->O, pyr);
         size_t off = 0;
-        for (int o = 0; o < s->O; ++o) { doff[o] = off; off += (size_t)dws[o] * dhs[o]; }
+        for (int o = 0; o < s->O; ++o) { doff[o] = off; lvp[o] = pyr + off; off += (size_t)dws[o] * dhs[o]; }
     }
     int nD = 0;
     for (int i = 0; i < nF; ++i) {
@@ -645,10 +771,11 @@ int orc_push(orc_stream* s, const uint8_t* frame)
                                    : s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)] != 0;
         if (!keep) continue;
         D[nD].k = F[i];
-        if (pyr) {
+        if (s->desc_on) {
             const int o = F[i].octave;
             D[nD].bin = orc_describe(pyr + doff[o], dws[o], dhs[o], F[i].x, F[i].y, D[nD].bits);
         }
+        if (s->ref_on) orc_refine_kp(lvp, dws, dhs, s->O, s->t, F[i].x, F[i].y, F[i].octave, D[nD].ref);
         ++nD;
     }
     for (int i = 0; i < s->nK; ++i) {
@@ -656,10 +783,11 @@ int orc_push(orc_stream* s, const uint8_t* frame)
                                    : !s->mask[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)];
         if (!keep) continue;
         D[nD].k = s->K[i];
-        if (pyr) {
+        if (s->desc_on) {
             D[nD].bin = s->bin[i];
             memcpy(D[nD].bits, s->desc + (size_t)i * 8, sizeof(D[nD].bits));
         }
+        if (s->ref_on) memcpy(D[nD].ref, s->ref + (size_t)i * 4, sizeof(D[nD].ref));
         ++nD;
     }
     free(pyr);
@@ -685,6 +813,7 @@ int orc_push(orc_stream* s, const uint8_t* frame)
             s->bin[i] = D[i].bin;
             memcpy(s->desc + (size_t)i * 8, D[i].bits, sizeof(D[i].bits));
         }
+        if (s->ref_on) memcpy(s->ref + (size_t)i * 4, D[i].ref, sizeof(D[i].ref));
     }
     s->nK = nD;
     for (int c = 0; c < ncell; ++c) s->count[c] = 0;

@@ -255,3 +255,47 @@ def describe(level: np.ndarray, x: int, y: int):
         if V[a] > V[b]:
             words[k >> 6] |= 1 << (k & 63)
     return sector, np.array(words, np.uint64)
+
+
+# --------------------------------------- sub-pixel and sub-scale refinement
+
+def _fit(level: np.ndarray, t: int, cx: int, cy: int):
+    """Least-squares quadratic through the 3 x 3 score patch (numpy lstsq),
+    its maximum's offsets (clamped to [-1, 1]) and value."""
+    pts, vals = [], []
+    for j in (-1, 0, 1):
+        for i in (-1, 0, 1):
+            pts.append((1.0, i, j, i * i, i * j, j * j))
+            vals.append(score(level, cx + i, cy + j, t))
+    c = np.linalg.lstsq(np.array(pts), np.array(vals, np.float64), rcond=None)[0]
+    # decide concavity on the exact integer multiples of the coefficients
+    cxx, cxy, cyy = int(round(6 * c[3])), int(round(4 * c[4])), int(round(6 * c[5]))
+    D = 16 * cxx * cyy - 9 * cxy * cxy
+    if D > 0 and cxx < 0:
+        u, v = np.linalg.solve(np.array([[2 * c[3], c[4]], [c[4], 2 * c[5]]]), -np.array([c[1], c[2]]))
+        u, v = float(np.clip(u, -1, 1)), float(np.clip(v, -1, 1))
+    else:
+        u, v = 0.0, 0.0
+    m = c[0] + c[1] * u + c[2] * v + c[3] * u * u + c[4] * u * v + c[5] * v * v
+    return u, v, float(m)
+
+
+def refine(levels, t: int, x: int, y: int, o: int):
+    """Refined (x, y), log2 scale and score: fits on the finer, own and
+    coarser layers, a parabola along log2 scale, linear interpolation."""
+    O = len(levels)
+    res = {}
+    for k, l in ((0, o - 1), (1, o), (2, o + 1)):
+        if 0 <= l < O:
+            cx, cy = ((2 * x + 1, 2 * y + 1), (x, y), (x >> 1, y >> 1))[k]
+            u, v, m = _fit(levels[l], t, cx, cy)
+            res[k] = ((cx + 0.5 + u) * 2 ** l, (cy + 0.5 + v) * 2 ** l, m)
+    own = res[1]
+    lo = res.get(0, (own[0], own[1], 0.0))
+    hi = res.get(2, (own[0], own[1], 0.0))
+    q = lo[2] - 2 * own[2] + hi[2]
+    tt = float(np.clip((lo[2] - hi[2]) / (2 * q), -1, 1)) if q < 0 else 0.0
+    score_v = own[2] + 0.5 * (hi[2] - lo[2]) * tt + 0.5 * q * tt * tt
+    other = hi if tt >= 0 else lo
+    a = abs(tt)
+    return np.array([own[0] + a * (other[0] - own[0]), own[1] + a * (other[1] - own[1]), o + tt, score_v])

@@ -659,6 +659,86 @@ def test_stream_descriptors_follow_eq1():
     assert m2.any() and not m2.all()
 
 
+# ------------------------------------- sub-pixel and sub-scale refinement
+
+def _smooth_random(seed, h, w):
+    rng = np.random.default_rng(seed)
+    img = rng.integers(0, 256, size=(h + 4, w + 4)).astype(np.float64)
+    img = (img[:-4, :-4] + img[4:, 4:] + img[2:-2, 2:-2]) / 3
+    return np.clip(np.rint(img), 0, 255).astype(np.uint8)
+
+
+@pytest.mark.parametrize("seed,h,w,O,t,noise", [(3, 72, 96, 3, 15, False), (4, 77, 101, 4, 12, False),
+                                                 (5, 40, 40, 1, 10, True), (6, 60, 80, 2, 12, False)])
+def test_refine_matches_bruteforce(seed, h, w, O, t, noise):
+    # the closed-form integer fit against a numpy least-squares fit, the
+    # parabola along scale and the interpolation written out again
+    img = _smooth_random(seed, h, w) if noise else _scene(seed=seed, frames=1, w=w, h=h)[0]
+    lv = oracle.pyramid(img, O)
+    kps = oracle.detect(img, t, O)
+    assert len(kps) > 10
+    octaves = set()
+    sample = [k for k in kps if int(k["octave"]) > 0] + list(kps[::max(1, len(kps) // 40)])
+    for k in sample:
+        x, y, o = int(k["x"]), int(k["y"]), int(k["octave"])
+        octaves.add(o)
+        got = oracle.refine(lv, t, x, y, o)
+        exp = bf.refine([np.asarray(l) for l in lv], t, x, y, o)
+        np.testing.assert_allclose(got, exp, rtol=1e-6, atol=2e-4, err_msg=f"{x},{y},{o}")
+        assert o - 1 <= got[2] <= o + 1
+        # the refined position stays within the patches it was fit on
+        assert abs(got[0] - (x + 0.5) * 2 ** o) <= 1.5 * 2 ** (o + 1)
+        assert abs(got[1] - (y + 0.5) * 2 ** o) <= 1.5 * 2 ** (o + 1)
+    assert len(octaves) >= min(O, 2)
+
+
+def test_refine_of_a_square_corner_closed_form():
+    # a single-octave bright square (contrast D, threshold t, k = D - t): a
+    # corner scores 11k, its two edge neighbours 10k and the diagonal one 9k,
+    # the outside 0 (the closed forms of the FAST score). The fit through
+    # k [[0,0,0],[0,11,10],[0,10,9]] puts the maximum at (38/65, 38/65)
+    # towards the square's inside with value k (86/9 + 2*19/6*38/65 +
+    # (-23/3 + 9/4)(38/65)^2); with one layer the scale stays (t = 0)
+    img = np.full((48, 48), 40, np.uint8)
+    img[12:36, 12:36] = 200
+    lv = oracle.pyramid(img, 1)
+    k = 200 - 40 - 30
+    u = 38 / 65
+    m = k * (86 / 9 + 2 * 19 / 6 * u + (-23 / 3 + 9 / 4) * u * u)
+    corners = {(int(q["x"]), int(q["y"])) for q in oracle.detect(img, 30, 1)}
+    assert corners == {(12, 12), (35, 12), (12, 35), (35, 35)}
+    for x, y in corners:
+        r = oracle.refine(lv, 30, x, y, 0)
+        sx = 1 if x == 12 else -1
+        sy = 1 if y == 12 else -1
+        np.testing.assert_allclose(r, [x + 0.5 + sx * u, y + 0.5 + sy * u, 0.0, m], rtol=1e-6)
+
+
+def test_stream_refinement_follows_eq1():
+    frames = _scene(seed=53, frames=3, w=96, h=72, move=0.8)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, 6)
+    s.set_refine(True)
+    s.push(frames[0])
+    k0 = kps_tuples(s.get()[0])
+    r0 = s.refined()
+    lv = oracle.pyramid(frames[0], O)
+    for (x, y, o, _), r in zip(k0, r0):
+        np.testing.assert_array_equal(r, oracle.refine(lv, t, x, y, o))
+    s.push(frames[0])
+    np.testing.assert_array_equal(s.refined(), r0)        # carried whole
+    s.push(frames[1])
+    k2, m2, _, _ = s.get()
+    r2 = s.refined()
+    old = {k: tuple(r) for k, r in zip(k0, r0)}
+    lv = oracle.pyramid(frames[1], O)
+    for (x, y, o, v), r in zip(kps_tuples(k2), r2):
+        if m2[bf.kp_cell((x, y, o), W, H, Nc, Nr)]:
+            np.testing.assert_array_equal(r, oracle.refine(lv, t, x, y, o))
+        else:
+            assert old[(x, y, o, v)] == tuple(r)
+
+
 # ------------------------------------------------------ stored regression values
 
 @pytest.mark.parametrize("name,det", [
