@@ -109,12 +109,12 @@ TILE = 0
 
 
 def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool = False, kb_thresh=None,
-                descriptors: bool = False):
+                features: int = 0):
     from paper_1503_06959_amd import kpd
     d = wl.det
     kb = d.kb_thresh if kb_thresh is None else kb_thresh
     params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, kb, TILE, chunk,
-                             int(layer_mask), int(descriptors))
+                             int(layer_mask), features)
     s = kpd.Stream(wl.W, wl.H, params)
     s.chunk = chunk
     return s
@@ -271,7 +271,7 @@ def descriptor_workload(kpd, wl: Workload, args) -> dict:
     (Eq. 1), full-frame ones describe every feature."""
     out = {}
     for name, ti in (("masked", wl.det.id_thresh), ("full_frame", -1)):
-        s = open_stream(wl, ti, descriptors=True)
+        s = open_stream(wl, ti, features=kpd.FEAT_DESCRIPTOR)
         sec = timed_passes(kpd, s, wl, max(1, args.steps // 5), 1)
         prof = kernel_profile(kpd, s, wl, 2)
         st = latency_pass(kpd, s, wl)

@@ -86,11 +86,13 @@ extern "C" {
  *              previous frame's readable. Eq. 1 per feature can then place a carried
  *              and a new feature side by side, so D_n is sized for every
  *              decision pixel instead of one feature per 2x2 block. 0: no.
- *   descriptors
- *              1: every feature of D_n carries an orientation sector and a
- *              512-bit binary descriptor (get_descriptors), computed for the
- *              keypoints new in D_n and carried with the others (Sec. 3,
- *              Eq. 1); push_frame only, mask mode 0. 0: no. */
+ *   features   what every feature of D_n carries besides its keypoint,
+ *              computed for the keypoints new in D_n and carried with the
+ *              others (Sec. 3, Eq. 1): KPD_FEAT_DESCRIPTOR, an orientation
+ *              sector and a 512-bit binary descriptor (get_descriptors);
+ *              KPD_FEAT_REFINE, the sub-pixel position and sub-scale of
+ *              Sec. 2's interpolation (get_refined). push_frame only, mask
+ *              mode 0. 0: nothing. */
 typedef struct kpd_params {
     int32_t fast_t;
     int32_t n_octaves;
@@ -101,8 +103,11 @@ typedef struct kpd_params {
     int32_t tile;
     int32_t chunk_frames;
     int32_t layer_mask;
-    int32_t descriptors;
+    int32_t features;
 } kpd_params;
+
+#define KPD_FEAT_DESCRIPTOR 1
+#define KPD_FEAT_REFINE 2
 
 /* One feature of D_n (Sec. 3: position and scale; the integer part).
  * x, y are coordinates at level `octave`; the level-0 footprint starts at
@@ -195,7 +200,7 @@ typedef struct kpd_descriptor {
 } kpd_descriptor;
 
 /* Descriptors of D_n, in get_keypoints' order (streams opened with
- * descriptors = 1). `*count` receives the number of features; when it
+ * KPD_FEAT_DESCRIPTOR). `*count` receives the number of features; when it
  * exceeds `capacity`, nothing is copied and KPD_ETRUNC is returned.
  * KPD_EINVAL without descriptors, KPD_ESTATE before the first push. */
 int get_descriptors(kpd_stream* s, kpd_descriptor* out, size_t capacity, size_t* count);
@@ -204,6 +209,29 @@ int get_descriptors(kpd_stream* s, kpd_descriptor* out, size_t capacity, size_t*
  * rounded offsets in level pixels and the box half-size (returned; -1 for
  * out-of-range arguments). Host only, no stream needed. */
 int kpd_desc_point(int sector, int i, int* dx, int* dy);
+
+/* Sub-pixel position and sub-scale of one feature (Sec. 2's interpolation,
+ * on the octave layers). On the keypoint's layer and the finer and coarser
+ * ones (centres (x, y), (2x+1, 2y+1), (x>>1, y>>1)), a least-squares
+ * quadratic through the 3 x 3 FAST scores (0 outside the candidate region)
+ * gives a maximum, clamped to one pixel and taken at the centre when the fit
+ * is not concave; a parabola through the three maxima along log2 scale gives
+ * t in [-1, 1] (0 when not concave; a missing layer counts 0); x, y (level-0
+ * pixels, pixel (X, Y) spanning [X, X+1) x [Y, Y+1)) move from the own
+ * layer's maximum towards the coarser (t > 0) or finer (t < 0) one's by |t|;
+ * log2_scale = octave + t; score = the parabola's value at t. Every
+ * floating step is an IEEE double operation in a fixed order, then rounded
+ * to float. */
+typedef struct kpd_refined {
+    float x;
+    float y;
+    float log2_scale;
+    float score;
+} kpd_refined;
+
+/* Refined values of D_n, in get_keypoints' order (streams opened with
+ * KPD_FEAT_REFINE); like get_descriptors otherwise. */
+int get_refined(kpd_stream* s, kpd_refined* out, size_t capacity, size_t* count);
 
 /* Wait for the last pushed frame and copy D_n to host memory `out`, ordered
  * by cell (row-major), then octave, then y, then x. `*count` receives the
@@ -308,7 +336,7 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
 #define KPD_K_DETECT 1
 #define KPD_K_COMPACT 2 /* compaction pass of push_frames */
 #define KPD_K_MARK 3    /* mark, speculation and resolve passes of push_frames */
-#define KPD_K_DESCRIBE 4 /* descriptor pass of push_frame with descriptors */
+#define KPD_K_DESCRIBE 4 /* feature pass of push_frame: descriptors, refinement */
 #define KPD_NKERNELS 5
 
 /* Switch per-kernel GPU timing on (1) or off (0). While on, every kernel

@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kpd_oracle.c")
 LIB = os.path.join(HERE, "libkpd_oracle.so")
-GCC_CMD = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, SRC, "-lm"]
+GCC_CMD = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", LIB, SRC, "-lm"]
 
 KP_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("octave", "<i4"), ("score", "<i4")])
 KB_OFF = 0xFFFFFFFF

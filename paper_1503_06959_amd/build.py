@@ -21,6 +21,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # floating expressions as written: no fused multiply-adds
+    "-ffp-contract=off",
 ]
 
 

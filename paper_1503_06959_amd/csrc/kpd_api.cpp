@@ -58,7 +58,8 @@ struct Layout {
     size_t off_colmap = 0, off_rowmap = 0;   // cell column / row of every level-0 column / row
     // batch ticks: marked cells' keypoints at fixed per-cell bases, and counts
     size_t off_sparse1 = 0, off_own1 = 0;
-    size_t off_desc[2] = {0, 0}, off_dtab = 0;   // descriptors (streams opened with descriptors = 1)
+    size_t off_desc[2] = {0, 0}, off_dtab = 0;   // descriptors (KPD_FEAT_DESCRIPTOR)
+    size_t off_ref[2] = {0, 0};                  // refined values (KPD_FEAT_REFINE)
     // chunks of consecutive frames (push_frames): K copies of the octaves,
     // per-frame SAD, sparse lists with per-cell counts, count words, marks
     // (cell-major, Kw 64-bit words per cell), dense lists with counts, offsets and
@@ -113,7 +114,7 @@ bool valid_params(int W, int H, const kpd_params* p, std::string* why)
         return false;
     }
     if (p->layer_mask != 0 && p->layer_mask != 1) { *why = "layer_mask must be 0 or 1"; return false; }
-    if (p->descriptors != 0 && p->descriptors != 1) { *why = "descriptors must be 0 or 1"; return false; }
+    if (p->features & ~(KPD_FEAT_DESCRIPTOR | KPD_FEAT_REFINE)) { *why = "unknown feature bits"; return false; }
     return true;
 }
 
@@ -230,10 +231,12 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
     L->off_own1 = off; off = align_up(off + (size_t)L->ncell * 4);
     L->off_sparse1 = off; off = align_up(off + L->list_cap1 * sizeof(kpd_keypoint));
-    if (p->descriptors) {   // descriptors of D_{n-1} and D_n, and the pattern tables
+    if (p->features & KPD_FEAT_DESCRIPTOR) {   // descriptors of D_{n-1} and D_n, and the pattern tables
         for (int k = 0; k < 2; ++k) { L->off_desc[k] = off; off = align_up(off + L->list_cap1 * sizeof(kpd_descriptor)); }
         L->off_dtab = off; off = align_up(off + sizeof(kpd::DescTables));
     }
+    if (p->features & KPD_FEAT_REFINE)   // refined values of D_{n-1} and D_n
+        for (int k = 0; k < 2; ++k) { L->off_ref[k] = off; off = align_up(off + L->list_cap1 * sizeof(kpd_refined)); }
     if (L->K > 1) {
         const size_t kc = (size_t)L->K * L->ncell;
         L->off_csad = off; off = align_up(off + kc * 4);
@@ -549,7 +552,7 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess && params->descriptors)
+    if (e == hipSuccess && (params->features & KPD_FEAT_DESCRIPTOR))
         e = hipMemcpyAsync(s->arena + L.off_dtab, &desc_tables(), sizeof(kpd::DescTables), hipMemcpyHostToDevice,
                            s->stream);
     std::vector<kpd::ChunkArgs> ctab;
@@ -747,6 +750,30 @@ void advance_frame(kpd_stream* s, const kpd::TickArgs& t)
     if (s->id_mode != 0) s->layer_buf ^= 1;
 }
 
+// Copies D_n's per-feature values (one T per feature, in list order) from
+// the arena buffers off[0], off[1] that alternate with the keypoint lists.
+template <class T>
+int copy_features(kpd_stream* s, const size_t* off, T* out, size_t capacity, size_t* count)
+{
+    if (!count) return fail(KPD_EINVAL, "count is NULL");
+    if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
+    const Layout& L = s->L;
+    const int k = s->fb_last;
+    uint32_t hdr[4];
+    KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
+    KPD_HIP(hipStreamSynchronize(s->stream));
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
+    const uint32_t total = std::min<uint32_t>(hdr[k ? kHdrTotal1 : kHdrTotal0], (uint32_t)L.list_cap1);
+    *count = total;
+    if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the feature count");
+    if (total > 0) {
+        if (!out) return fail(KPD_EINVAL, "out is NULL");
+        KPD_HIP(hipMemcpyAsync(out, s->at<T>(off[k]), (size_t)total * sizeof(T), hipMemcpyDeviceToHost, s->stream));
+        KPD_HIP(hipStreamSynchronize(s->stream));
+    }
+    return KPD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -761,23 +788,31 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
         KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(t.f, s->stream); }));
     const int lds = s->id_mode != 0 ? L.lds_bytes1 : L.lds_bytes;
     KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, lds, s->stream); }));
-    if (s->p.descriptors) {
+    if (s->p.features) {
         const int fb_prev = s->fb_last, fb_cur = 1 - s->fb_last;
         kpd::DescArgs da{};
-        da.tab = s->at<kpd::DescTables>(L.off_dtab);
+        if (s->p.features & KPD_FEAT_DESCRIPTOR) {
+            da.tab = s->at<kpd::DescTables>(L.off_dtab);
+            da.desc_prev = s->at<kpd_descriptor>(L.off_desc[fb_prev]);
+            da.desc_cur = s->at<kpd_descriptor>(L.off_desc[fb_cur]);
+        }
+        if (s->p.features & KPD_FEAT_REFINE) {
+            da.ref_prev = s->at<kpd_refined>(L.off_ref[fb_prev]);
+            da.ref_cur = s->at<kpd_refined>(L.off_ref[fb_cur]);
+        }
         for (int o = 0; o < L.O; ++o) {
             da.lvl[o] = t.d.lvl[o];
             da.pitch[o] = t.d.pitch[o];
             da.w[o] = L.w[o];
             da.h[o] = L.h[o];
         }
+        da.O = L.O;
+        da.t = t.d.t;
         da.mask = t.d.mask;
         da.count_cur = t.d.count_cur;
         da.off_cur = t.d.off_cur;
         da.off_prev = t.d.off_prev;
         da.list_cur = t.d.list_cur;
-        da.desc_prev = s->at<kpd_descriptor>(L.off_desc[fb_prev]);
-        da.desc_cur = s->at<kpd_descriptor>(L.off_desc[fb_cur]);
         da.list_cap = (uint32_t)L.list_cap1;
         KPD_HIP(timed(s, KPD_K_DESCRIBE, [&] { return kpd::launch_describe(da, L.ncell, s->stream); }));
     }
@@ -792,7 +827,7 @@ int set_mask_mode(kpd_stream* s, int mode, int layer)
     if (layer < 0 || layer >= s->L.O) return fail(KPD_EINVAL, "layer must be an octave of the stream");
     if (mode == 2 && layer != 0) return fail(KPD_EINVAL, "mode 2 masks every octave on its own level: layer must be 0");
     if (mode != 0 && !s->p.layer_mask) return fail(KPD_EINVAL, "stream opened without layer_mask");
-    if (mode != 0 && s->p.descriptors) return fail(KPD_EINVAL, "descriptors run with mask mode 0 only");
+    if (mode != 0 && s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run with mask mode 0 only");
     if (mode == s->id_mode && (mode != 1 || layer == s->id_layer)) return KPD_OK;
     if (mode != 0) KPD_HIP(kpd::set_detect_lds_limit(s->L.lds_bytes1));
     s->id_mode = mode;
@@ -808,7 +843,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     const Layout& L = s->L;
     if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
-    if (s->p.descriptors) return fail(KPD_EINVAL, "descriptors run on single-frame pushes only");
+    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on single-frame pushes only");
     if (!frames) return fail(KPD_EINVAL, "frames is NULL");
     if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
@@ -986,25 +1021,15 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
 int get_descriptors(kpd_stream* s, kpd_descriptor* out, size_t capacity, size_t* count)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
-    if (!count) return fail(KPD_EINVAL, "count is NULL");
-    if (!s->p.descriptors) return fail(KPD_EINVAL, "stream opened without descriptors");
-    if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
-    const Layout& L = s->L;
-    const int k = s->fb_last;
-    uint32_t hdr[4];
-    KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
-    KPD_HIP(hipStreamSynchronize(s->stream));
-    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
-    const uint32_t total = std::min<uint32_t>(hdr[k ? kHdrTotal1 : kHdrTotal0], (uint32_t)L.list_cap1);
-    *count = total;
-    if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the feature count");
-    if (total > 0) {
-        if (!out) return fail(KPD_EINVAL, "out is NULL");
-        KPD_HIP(hipMemcpyAsync(out, s->at<kpd_descriptor>(L.off_desc[k]), (size_t)total * sizeof(kpd_descriptor),
-                               hipMemcpyDeviceToHost, s->stream));
-        KPD_HIP(hipStreamSynchronize(s->stream));
-    }
-    return KPD_OK;
+    if (!(s->p.features & KPD_FEAT_DESCRIPTOR)) return fail(KPD_EINVAL, "stream opened without descriptors");
+    return copy_features(s, s->L.off_desc, out, capacity, count);
+}
+
+int get_refined(kpd_stream* s, kpd_refined* out, size_t capacity, size_t* count)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!(s->p.features & KPD_FEAT_REFINE)) return fail(KPD_EINVAL, "stream opened without refinement");
+    return copy_features(s, s->L.off_ref, out, capacity, count);
 }
 
 int kpd_desc_point(int sector, int i, int* dx, int* dy)
@@ -1237,7 +1262,7 @@ int batch_attach(kpd_batch* b, kpd_stream* s)
 {
     if (!b || !s || s->closed) return fail(KPD_ESTATE, "batch or stream is closed");
     if (s->stream != b->stream) return fail(KPD_EINVAL, "stream was opened on another HIP stream");
-    if (s->p.descriptors) return fail(KPD_EINVAL, "descriptors run on single-frame pushes only");
+    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on single-frame pushes only");
     if (std::find(b->streams.begin(), b->streams.end(), s) != b->streams.end())
         return fail(KPD_EINVAL, "stream already attached");
     if ((int)b->streams.size() >= b->max_streams) return fail(KPD_ENOMEM, "batch stream capacity exceeded");
@@ -1275,7 +1300,7 @@ int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_b
     const size_t i = (size_t)(it - b->streams.begin());
     if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
-    if (s->p.descriptors) return fail(KPD_EINVAL, "descriptors run on single-frame pushes only");
+    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on single-frame pushes only");
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
     if (rc != KPD_OK) return rc;
     b->has_frame[i] = 1;

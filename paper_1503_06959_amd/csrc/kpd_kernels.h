@@ -57,13 +57,17 @@ struct DescTables {
     int64_t ux[kDescSectors], uy[kDescSectors];
 };
 
-// k_describe: descriptors of D_n's features, computed for the cells marked
-// this frame and carried with the keypoints of the others.
+// k_describe: descriptors and refined values of D_n's features, computed for
+// the cells marked this frame and carried with the keypoints of the others.
+// A null tab (desc_*) or ref_cur leaves that part out.
 struct DescArgs {
     const DescTables* tab;
     const uint8_t* lvl[KPD_MAX_OCTAVES];
     int pitch[KPD_MAX_OCTAVES];
     int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];
+    int O, t;
+    const kpd_refined* ref_prev;
+    kpd_refined* ref_cur;
     const uint8_t* mask;
     const uint32_t* count_cur;
     const uint32_t* off_cur;

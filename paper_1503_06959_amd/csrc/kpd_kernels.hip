@@ -1217,15 +1217,94 @@ __device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8
 
 // ------------------------------------------------------------ k_describe
 
-// Descriptors of one frame (Sec. 3 feature model; Eq. 1 carries whole
+// Sub-pixel, sub-scale refinement of one feature (Sec. 2's interpolation on
+// the octave layers). S holds the FAST scores of the 3 x 3 patches on the
+// finer, own and coarser layers (S[9k + 3(i+1) + (j+1)], x offset i, y
+// offset j). Per layer, an exact integer least-squares quadratic gives its
+// maximum (clamped to a pixel; the centre when not concave) and the value
+// there; a parabola through the three values along log2 scale gives t. The
+// floating steps are IEEE double operations in a fixed order, none fused.
+struct Fit {
+    double u, v, m;
+};
+
+__device__ Fit fit_patch(const int* S)
+{
+#pragma clang fp contract(off)
+    long long sx[3], sy[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        sx[k] = (long long)S[3 * k] + S[3 * k + 1] + S[3 * k + 2];
+        sy[k] = (long long)S[k] + S[3 + k] + S[6 + k];
+    }
+    auto P = [&](int i, int j) -> long long { return S[3 * (i + 1) + (j + 1)]; };
+    const long long A = sx[2] - sx[0], B = sy[2] - sy[0];
+    const long long Cx = sx[2] + sx[0] - 2 * sx[1], Cy = sy[2] + sy[0] - 2 * sy[1];
+    const long long E = P(1, 1) - P(1, -1) - P(-1, 1) + P(-1, -1);
+    const long long K0 = 5 * P(0, 0) + 2 * (P(0, -1) + P(-1, 0) + P(1, 0) + P(0, 1)) -
+                         (P(-1, -1) + P(1, -1) + P(-1, 1) + P(1, 1));
+    const long long D = 16 * Cx * Cy - 9 * E * E;
+    long long U = 0, V = 0, Dn = 1;
+    if (D > 0 && Cx < 0) {
+        U = min(max(6 * E * B - 8 * Cy * A, -D), D);
+        V = min(max(6 * E * A - 8 * Cx * B, -D), D);
+        Dn = D;
+    }
+    Fit r;
+    r.u = (double)U / (double)Dn;
+    r.v = (double)V / (double)Dn;
+    double f = (double)K0 / 9.0;
+    f = f + ((double)A / 6.0) * r.u;
+    f = f + ((double)B / 6.0) * r.v;
+    f = f + (((double)Cx / 6.0) * r.u) * r.u;
+    f = f + (((double)E / 4.0) * r.u) * r.v;
+    f = f + (((double)Cy / 6.0) * r.v) * r.v;
+    r.m = f;
+    return r;
+}
+
+__device__ kpd_refined refine_feature(const int* S, int x, int y, int o, int O)
+{
+#pragma clang fp contract(off)
+    double m[3] = {0.0, 0.0, 0.0}, X[3] = {0.0, 0.0, 0.0}, Y[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int l = o - 1 + k;
+        if (l < 0 || l >= O) continue;
+        const int cx = k == 0 ? 2 * x + 1 : (k == 1 ? x : x >> 1);
+        const int cy = k == 0 ? 2 * y + 1 : (k == 1 ? y : y >> 1);
+        const Fit f = fit_patch(S + 9 * k);
+        m[k] = f.m;
+        X[k] = (((double)cx + 0.5) + f.u) * (double)(1 << l);
+        Y[k] = (((double)cy + 0.5) + f.v) * (double)(1 << l);
+    }
+    if (o == 0) { X[0] = X[1]; Y[0] = Y[1]; }
+    if (o + 1 >= O) { X[2] = X[1]; Y[2] = Y[1]; }
+    const double q = (m[0] - 2.0 * m[1]) + m[2];
+    double tt = 0.0;
+    if (q < 0.0) tt = fmin(fmax((m[0] - m[2]) / (2.0 * q), -1.0), 1.0);
+    const double score = (m[1] + (0.5 * (m[2] - m[0])) * tt) + (0.5 * q) * (tt * tt);
+    const int side = tt >= 0.0 ? 2 : 0;
+    const double a = tt >= 0.0 ? tt : -tt;
+    kpd_refined r;
+    r.x = (float)(X[1] + a * (X[side] - X[1]));
+    r.y = (float)(Y[1] + a * (Y[side] - Y[1]));
+    r.log2_scale = (float)((double)o + tt);
+    r.score = (float)score;
+    return r;
+}
+
+// Features of one frame (Sec. 3 feature model; Eq. 1 carries whole
 // features). A workgroup per cell: an unmarked cell's features are D_{n-1}'s,
-// so their descriptors are copied in the same order; a marked cell's are new
-// and each of its four waves describes one feature at a time: the wave loads
-// the feature's 27 x 27 patch (every point of the pattern, turned any way,
-// with its box) into LDS in one round of loads, a lane per pattern point
-// takes the box mean around its point, the lanes sum the long pairs'
-// gradient, 32 lanes test the sector boundaries, the points are taken again
-// turned to the sector, and eight ballots over the short pairs give the bits.
+// so their descriptors and refined values are copied in the same order; a
+// marked cell's are new and each of its four waves takes one feature at a
+// time. Refinement: 27 lanes score one pixel each of the three 3 x 3 patches
+// and one lane fits them. Descriptor: the wave loads the feature's 27 x 27
+// patch (every point of the pattern, turned any way, with its box) into LDS
+// in one round of loads, a lane per pattern point takes the box mean around
+// its point, the lanes sum the long pairs' gradient, 32 lanes test the
+// sector boundaries, the points are taken again turned to the sector, and
+// eight ballots over the short pairs give the bits.
 constexpr int kDescBlock = 256;
 constexpr int kPatchR = 13;                  // pattern radius 11 plus a box half-size 2
 constexpr int kPatch = 2 * kPatchR + 1;      // patch side
@@ -1239,23 +1318,47 @@ __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
     const uint32_t n = a.count_cur[c], dst0 = a.off_cur[c];
     if (!a.mask[c]) {
         const uint32_t src0 = a.off_prev[c];
-        constexpr int kw = sizeof(kpd_descriptor) / 8;
-        const uint64_t* src = reinterpret_cast<const uint64_t*>(a.desc_prev);
-        uint64_t* dst = reinterpret_cast<uint64_t*>(a.desc_cur);
-        for (uint32_t i = threadIdx.x; i < n * kw; i += kDescBlock) {
-            const uint32_t e = i / kw;
-            if (src0 + e < a.list_cap && dst0 + e < a.list_cap)
-                dst[(size_t)(dst0 + e) * kw + i % kw] = src[(size_t)(src0 + e) * kw + i % kw];
+        if (a.tab) {
+            constexpr int kw = sizeof(kpd_descriptor) / 8;
+            const uint64_t* src = reinterpret_cast<const uint64_t*>(a.desc_prev);
+            uint64_t* dst = reinterpret_cast<uint64_t*>(a.desc_cur);
+            for (uint32_t i = threadIdx.x; i < n * kw; i += kDescBlock) {
+                const uint32_t e = i / kw;
+                if (src0 + e < a.list_cap && dst0 + e < a.list_cap)
+                    dst[(size_t)(dst0 + e) * kw + i % kw] = src[(size_t)(src0 + e) * kw + i % kw];
+            }
         }
+        if (a.ref_cur)
+            for (uint32_t e = threadIdx.x; e < n; e += kDescBlock)
+                if (src0 + e < a.list_cap && dst0 + e < a.list_cap) a.ref_cur[dst0 + e] = a.ref_prev[src0 + e];
         return;
     }
-    const DescTables& T = *a.tab;
     int* V = s_v[wave];
     uint8_t* patch = s_patch[wave];
     for (uint32_t k = wave; k < n; k += kDescBlock / 64) {
         if (dst0 + k >= a.list_cap) break;
         const kpd_keypoint kp = a.list_cur[dst0 + k];
         const int o = kp.octave;
+        if (a.ref_cur) {
+            if (lane < 27) {
+                const int kl = lane / 9, r = lane - 9 * kl, i = r / 3 - 1, j = r - 3 * (r / 3) - 1;
+                const int l = o - 1 + kl;
+                int sc = 0;
+                if (l >= 0 && l < a.O) {
+                    const int x = kl == 0 ? 2 * (int)kp.x + 1 : (kl == 1 ? (int)kp.x : (int)kp.x >> 1);
+                    const int y = kl == 0 ? 2 * (int)kp.y + 1 : (kl == 1 ? (int)kp.y : (int)kp.y >> 1);
+                    const int px = x + i, py = y + j;
+                    if (px >= 3 && py >= 3 && px < a.w[l] - 3 && py < a.h[l] - 3)
+                        sc = full_score(a.lvl[l] + (size_t)py * a.pitch[l] + px, a.pitch[l], a.t);
+                }
+                V[lane] = sc;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) a.ref_cur[dst0 + k] = refine_feature(V, kp.x, kp.y, o, a.O);
+            __builtin_amdgcn_wave_barrier();   // V is reused below
+        }
+        if (!a.tab) continue;
+        const DescTables& T = *a.tab;
         const uint8_t* L = a.lvl[o];
         const int pitch = a.pitch[o], w = a.w[o], h = a.h[o];
         // the patch around the feature, edge pixels repeated

@@ -36,8 +36,10 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
             "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
-            "kpd_desc_point")
+            "kpd_desc_point", "get_refined")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
+REFINED_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("log2_scale", "<f4"), ("score", "<f4")])
+FEAT_DESCRIPTOR, FEAT_REFINE = 1, 2
 KERNEL_NAMES = ("k_frame", "k_detect", "k_compact", "k_mark", "k_describe")
 
 
@@ -46,7 +48,7 @@ class KpdParams(ctypes.Structure):
                 ("grid_cols", ctypes.c_int32), ("grid_rows", ctypes.c_int32),
                 ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32),
                 ("tile", ctypes.c_int32), ("chunk_frames", ctypes.c_int32),
-                ("layer_mask", ctypes.c_int32), ("descriptors", ctypes.c_int32)]
+                ("layer_mask", ctypes.c_int32), ("features", ctypes.c_int32)]
 
 
 class KpdError(RuntimeError):
@@ -91,6 +93,7 @@ def _load() -> ctypes.CDLL:
     L.get_chunk_keypoints.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
     L.set_mask_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.get_descriptors.argtypes = [P, P, sz, ctypes.POINTER(sz)]
+    L.get_refined.argtypes = [P, P, sz, ctypes.POINTER(sz)]
     L.kpd_desc_point.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(ctypes.c_int)]
     return L
@@ -107,9 +110,10 @@ def _check(rc: int) -> int:
 
 def make_params(fast_t: int, n_octaves: int, grid_cols: int, grid_rows: int,
                 id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0, chunk_frames: int = 0,
-                layer_mask: int = 0, descriptors: int = 0) -> KpdParams:
+                layer_mask: int = 0, features: int = 0) -> KpdParams:
+    """features: FEAT_DESCRIPTOR | FEAT_REFINE bits."""
     return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, chunk_frames,
-                     layer_mask, descriptors)
+                     layer_mask, features)
 
 
 def stream_bytes(width: int, height: int, params: KpdParams) -> int:
@@ -202,16 +206,26 @@ def set_mask_mode(handle: int, mode: int, layer: int = 0) -> None:
     _check(lib.set_mask_mode(handle, mode, layer))
 
 
-def get_descriptors(handle: int, capacity: int = 4096) -> np.ndarray:
-    """Descriptors of D_n (DESCRIPTOR_DTYPE), in get_keypoints' order."""
-    out = np.zeros(max(capacity, 1), DESCRIPTOR_DTYPE)
+def _get_features(fn, dtype, handle: int, capacity: int) -> np.ndarray:
+    out = np.zeros(max(capacity, 1), dtype)
     cnt = ctypes.c_size_t()
-    rc = lib.get_descriptors(handle, out.ctypes.data, len(out), ctypes.byref(cnt))
+    rc = fn(handle, out.ctypes.data, len(out), ctypes.byref(cnt))
     if rc == KPD_ETRUNC:
-        out = np.zeros(cnt.value, DESCRIPTOR_DTYPE)
-        rc = lib.get_descriptors(handle, out.ctypes.data, len(out), ctypes.byref(cnt))
+        out = np.zeros(cnt.value, dtype)
+        rc = fn(handle, out.ctypes.data, len(out), ctypes.byref(cnt))
     _check(rc)
     return out[:cnt.value].copy()
+
+
+def get_descriptors(handle: int, capacity: int = 4096) -> np.ndarray:
+    """Descriptors of D_n (DESCRIPTOR_DTYPE), in get_keypoints' order."""
+    return _get_features(lib.get_descriptors, DESCRIPTOR_DTYPE, handle, capacity)
+
+
+def get_refined(handle: int, capacity: int = 4096) -> np.ndarray:
+    """Refined position, log2 scale and score of D_n's features
+    (REFINED_DTYPE), in get_keypoints' order."""
+    return _get_features(lib.get_refined, REFINED_DTYPE, handle, capacity)
 
 
 def desc_point(sector: int, i: int) -> Tuple[int, int, int]:
@@ -361,8 +375,12 @@ class Stream:
         return self._out[:cnt.value].copy(), mask
 
     def descriptors(self) -> np.ndarray:
-        """Descriptors of D_n (streams opened with descriptors=1)."""
+        """Descriptors of D_n (streams opened with FEAT_DESCRIPTOR)."""
         return get_descriptors(self.handle)
+
+    def refined(self) -> np.ndarray:
+        """Refined values of D_n (streams opened with FEAT_REFINE)."""
+        return get_refined(self.handle)
 
     def cell_stats(self):
         return cell_stats(self.handle, self.n_cells)

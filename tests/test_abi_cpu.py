@@ -158,8 +158,12 @@ def test_descriptor_pattern_matches_the_oracle(kpd):
 
 
 def test_descriptor_flag_is_validated(kpd):
-    p = kpd.make_params(20, 4, 16, 12, descriptors=2)
+    p = kpd.make_params(20, 4, 16, 12, features=4)
     assert kpd.lib.stream_bytes(640, 480, ctypes.byref(p)) == 0
     base = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12))
-    with_desc = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, descriptors=1))
+    with_desc = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, features=kpd.FEAT_DESCRIPTOR))
     assert with_desc > base + 2 * 72 * 1000   # two descriptor lists and the tables
+    with_ref = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, features=kpd.FEAT_REFINE))
+    assert with_ref > base + 2 * 16 * 1000    # two lists of refined values
+    both = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, features=3))
+    assert both > max(with_desc, with_ref)

@@ -31,7 +31,7 @@ def run_desc(kpd, frames, det, mode="retain", thresholds=None, resets=()):
     import torch
     F, H, W = frames.shape
     t, O, Nc, Nr, TI, TH = det
-    g = kpd.Stream(W, H, kpd.make_params(t, O, Nc, Nr, TI, TH, descriptors=1))
+    g = kpd.Stream(W, H, kpd.make_params(t, O, Nc, Nr, TI, TH, features=kpd.FEAT_DESCRIPTOR))
     o = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
     o.set_descriptors(True)
     dev = torch.from_numpy(frames).cuda() if mode != "host" else None
@@ -105,7 +105,7 @@ def test_descriptor_errors(kpd):
     import torch
     d = synth.DETECTORS["c1_320x240"]
     frames = synth.make_video(synth.SCENES["c1_320x240"], 3)
-    g = kpd.Stream(320, 240, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, descriptors=1,
+    g = kpd.Stream(320, 240, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, features=kpd.FEAT_DESCRIPTOR,
                                              chunk_frames=4, layer_mask=1))
     with pytest.raises(kpd.KpdError):
         g.descriptors()                                # nothing pushed yet

@@ -1,0 +1,137 @@
+"""GPU parity of the feature refinement (Sec. 2: sub-pixel and sub-scale
+interpolation of the keypoints; Eq. 1 carries whole features): every
+frame's refined position, log2 scale and score of D_n against the oracle's,
+bit for bit (both take the same IEEE double steps in the same order), for
+features new in the frame and for carried ones, on the three workloads, odd
+shapes, one-octave and deep pyramids, resets and threshold changes, and
+with descriptors on the same stream."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06959_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KB_OFF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def kpd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_06959_amd import kpd as k
+    return k
+
+
+def tuples(arr):
+    return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
+
+
+def run_ref(kpd, frames, det, mode="retain", thresholds=None, resets=(), with_desc=False):
+    import torch
+    F, H, W = frames.shape
+    t, O, Nc, Nr, TI, TH = det
+    feats = kpd.FEAT_REFINE | (kpd.FEAT_DESCRIPTOR if with_desc else 0)
+    g = kpd.Stream(W, H, kpd.make_params(t, O, Nc, Nr, TI, TH, features=feats))
+    o = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    o.set_refine(True)
+    if with_desc:
+        o.set_descriptors(True)
+    dev = torch.from_numpy(frames).cuda() if mode != "host" else None
+    refined = 0
+    for i in range(F):
+        if i in resets:
+            g.reset()
+            o.reset()
+        if thresholds and i in thresholds:
+            g.set_thresholds(*thresholds[i])
+            o.set_thresholds(*thresholds[i])
+        if mode == "host":
+            g.push(frames[i])
+        else:
+            g.push(dev[i], retain=(mode == "retain"))
+        o.push(frames[i])
+        gk, _ = g.keypoints()
+        ok, _, _, _ = o.get()
+        assert tuples(gk) == tuples(ok), f"frame {i}"
+        gr = g.refined()
+        orf = o.refined()
+        assert len(gr) == len(orf)
+        got = np.stack([gr["x"], gr["y"], gr["log2_scale"], gr["score"]], axis=1).astype(np.float32)
+        bad = np.nonzero((got.view(np.uint32) != orf.view(np.uint32)).any(axis=1))[0]
+        assert len(bad) == 0, (f"frame {i}: {len(bad)} features differ, first "
+                               f"{tuples(gk[bad[:1]])} gpu {got[bad[0]]} oracle {orf[bad[0]]}")
+        if with_desc:
+            gd = g.descriptors()
+            ob, od = o.descriptors()
+            np.testing.assert_array_equal(gd["sector"].astype(np.int64), ob.astype(np.int64))
+            np.testing.assert_array_equal(gd["bits"], od)
+        refined += len(gr)
+    g.close()
+    return refined
+
+
+def det_of(name, **kw):
+    d = synth.DETECTORS[name]
+    v = dict(t=d.fast_t, O=d.n_octaves, Nc=d.grid_cols, Nr=d.grid_rows, TI=d.id_thresh, TH=d.kb_thresh)
+    v.update(kw)
+    return (v["t"], v["O"], v["Nc"], v["Nr"], v["TI"], v["TH"])
+
+
+def test_c1_masked_and_full(kpd):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 20)
+    assert run_ref(kpd, frames, det_of("c1_320x240")) > 0
+    assert run_ref(kpd, frames[:6], det_of("c1_320x240", TI=-1)) > 0
+
+
+def test_c2_masked_60_frames(kpd):
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 60)
+    run_ref(kpd, frames, det_of("c2_640x480"), mode="device")
+
+
+def test_c3_first_frames(kpd):
+    frames = synth.make_video(synth.SCENES["c3_1920x1080"], 4)
+    run_ref(kpd, frames, det_of("c3_1920x1080"))
+
+
+@pytest.mark.parametrize("W,H,det", [
+    (333, 251, (25, 4, 7, 5, 4, KB_OFF)),     # features near the right and bottom edges
+    (127, 255, (15, 7, 1, 2, 8, KB_OFF)),     # a deep pyramid: coarse layers with no candidate region
+    (101, 77, (12, 4, 6, 4, 4, 3)),
+    (64, 48, (10, 1, 2, 2, 6, KB_OFF)),       # one octave: no finer or coarser layer
+    (97, 65, (10, 2, 3, 2, 6, KB_OFF)),       # odd sizes: coarser centres past the last column
+])
+def test_shapes(kpd, W, H, det):
+    sc = synth.Scene(W, H, 6, 8, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 770 + W)
+    run_ref(kpd, synth.make_video(sc), det)
+
+
+def test_resets_thresholds_and_host_frames(kpd):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 12)
+    run_ref(kpd, frames, det_of("c1_320x240"), mode="host", thresholds={4: (25, 6, 3), 8: (25, 8, KB_OFF)},
+            resets=(6,))
+
+
+def test_with_descriptors(kpd):
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 12)
+    assert run_ref(kpd, frames, det_of("c2_640x480"), with_desc=True) > 0
+
+
+def test_refine_errors(kpd):
+    d = synth.DETECTORS["c1_320x240"]
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 3)
+    g = kpd.Stream(320, 240, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows,
+                                             features=kpd.FEAT_REFINE))
+    with pytest.raises(kpd.KpdError):
+        g.refined()                                    # nothing pushed yet
+    g.push(frames[0])
+    with pytest.raises(kpd.KpdError):
+        g.descriptors()                                # opened without descriptors
+    assert len(g.refined()) == len(g.keypoints()[0])
+    kpd.profile(g.handle, True)
+    g.push(frames[1])
+    ms, n = kpd.profile_read(g.handle)
+    assert list(n) == [1, 1, 0, 0, 1]
+    g.close()
