@@ -265,13 +265,20 @@ def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> 
     return out
 
 
-def descriptor_workload(kpd, wl: Workload, args) -> dict:
-    """Descriptors of D_n (streaming, one push_frame per frame): masked
-    frames describe only the features of marked cells and carry the rest
-    (Eq. 1), full-frame ones describe every feature."""
+FEATURE_PASSES = {
+    "descriptors": (1, "descriptors (60-point pattern, 32 sectors, 512 bits)"),
+    "refinement": (2, "sub-pixel and sub-scale refinement (3x3 score fits on three layers)"),
+}
+
+
+def feature_workload(kpd, wl: Workload, args, which: str) -> dict:
+    """Per-feature values of D_n (streaming, one push_frame per frame):
+    masked frames compute them only for the features of marked cells and
+    carry the rest (Eq. 1), full-frame ones for every feature."""
+    features, label = FEATURE_PASSES[which]
     out = {}
     for name, ti in (("masked", wl.det.id_thresh), ("full_frame", -1)):
-        s = open_stream(wl, ti, features=kpd.FEAT_DESCRIPTOR)
+        s = open_stream(wl, ti, features=features)
         sec = timed_passes(kpd, s, wl, max(1, args.steps // 5), 1)
         prof = kernel_profile(kpd, s, wl, 2)
         st = latency_pass(kpd, s, wl)
@@ -279,14 +286,14 @@ def descriptor_workload(kpd, wl: Workload, args) -> dict:
         out[name] = {"value": round(wl.F * wl.W * wl.H / sec / 1e6, 2), "unit": "Mpixel/s",
                      "frames_per_s": round(wl.F / sec, 1),
                      "latency_ms": {"p50": round(st["lat_p50"], 4), "p99": round(st["lat_p99"], 4)},
-                     "described_per_frame": round(sum(st["new_kp"]) / wl.F, 1),
+                     "computed_per_frame": round(sum(st["new_kp"]) / wl.F, 1),
                      "features_per_frame": round(sum(st["total_kp"]) / wl.F, 1),
                      "k_describe_avg_us": round(prof["k_describe"][0] * 1e3 / max(prof["k_describe"][1], 1), 3)
                      if "k_describe" in prof else None}
-    out["what"] = (f"{wl.name}, one push_frame per frame with descriptors (60-point pattern, 32 sectors, 512 bits): "
-                   "masked frames describe the new features only, carried ones keep theirs")
-    out["described_masked_over_full"] = round(out["masked"]["described_per_frame"] /
-                                              max(out["full_frame"]["described_per_frame"], 1e-9), 4)
+    out["what"] = (f"{wl.name}, one push_frame per frame with {label}: "
+                   "masked frames compute them for the new features only, carried ones keep theirs")
+    out["computed_masked_over_full"] = round(out["masked"]["computed_per_frame"] /
+                                             max(out["full_frame"]["computed_per_frame"], 1e-9), 4)
     return out
 
 
@@ -892,8 +899,9 @@ def main():
     }
     log("[bench] layer study")
     out["layer_study"] = layer_study(kpd, wl, args)
-    log("[bench] descriptors")
-    out["descriptors"] = descriptor_workload(kpd, wl, args)
+    for which in FEATURE_PASSES:
+        log(f"[bench] {which}")
+        out[which] = feature_workload(kpd, wl, args, which)
     out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:
         del wl
