@@ -65,6 +65,16 @@ def lib() -> ctypes.CDLL:
     L.orc_get_refined.argtypes = [P, P, ctypes.c_int]
     L.orc_refine_kp.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
     L.orc_refine_kp.restype = None
+    L.orc_tcd_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.orc_tcd_spiral.argtypes = [ctypes.c_int, P, P]
+    L.orc_tcd_track.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
+    L.orc_tcd_open.argtypes = [ctypes.c_int] * 9
+    L.orc_tcd_open.restype = P
+    L.orc_tcd_close.argtypes = [P]
+    L.orc_tcd_close.restype = None
+    L.orc_tcd_reset.argtypes = [P]
+    L.orc_tcd_push.argtypes = [P, P]
+    L.orc_tcd_get.argtypes = [P, P, ctypes.c_int]
     _lib = L
     return L
 
@@ -231,6 +241,74 @@ class Stream:
     def close(self):
         if self.h:
             lib().orc_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------- temporally coherent detector
+
+TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "<i4"), ("score", "<i4"), ("sad", "<i4")])
+
+
+def tcd_sample(frame: np.ndarray, X: int, Y: int) -> int:
+    """Bilinear sample of `frame` at quarter-pixel position (X, Y) (T3); -1
+    when it needs pixels outside the frame."""
+    frame = np.ascontiguousarray(frame, dtype=np.uint8)
+    return lib().orc_tcd_sample(_ptr(frame), frame.shape[1], frame.shape[0], X, Y)
+
+
+def tcd_spiral(k: int):
+    """The k-th grid offset (u, v) of the spiral search order (T6)."""
+    u, v = ctypes.c_int(), ctypes.c_int()
+    assert lib().orc_tcd_spiral(k, ctypes.byref(u), ctypes.byref(v)) == 0
+    return u.value, v.value
+
+
+def tcd_track(prev: np.ndarray, cur: np.ndarray, tracks: np.ndarray, t_bm: int, t_et: int) -> np.ndarray:
+    """One propagation step (T5-T7): the tracks of `prev` that match in `cur`."""
+    prev = np.ascontiguousarray(prev, dtype=np.uint8)
+    cur = np.ascontiguousarray(cur, dtype=np.uint8)
+    tracks = np.ascontiguousarray(tracks, dtype=TRACK_DTYPE)
+    out = np.zeros(max(len(tracks), 1), TRACK_DTYPE)
+    H, W = prev.shape
+    m = lib().orc_tcd_track(_ptr(prev), _ptr(cur), W, H, t_bm, t_et, _ptr(tracks), len(tracks), _ptr(out))
+    return out[:m].copy()
+
+
+class Tcd:
+    """The oracle's temporally coherent detector (T1-T7): full-frame
+    detection on the first frame of every group of `gop`, block-matching
+    propagation on the others."""
+
+    def __init__(self, W: int, H: int, t: int, O: int, Nc: int, Nr: int, gop: int = 10, t_bm: int = 1800,
+                 t_et: int = 1000):
+        self.W, self.H = W, H
+        self.h = lib().orc_tcd_open(W, H, t, O, Nc, Nr, gop, t_bm, t_et)
+        if not self.h:
+            raise ValueError("bad oracle tracker parameters")
+
+    def reset(self):
+        lib().orc_tcd_reset(self.h)
+
+    def push(self, frame: np.ndarray) -> int:
+        frame = np.ascontiguousarray(frame, dtype=np.uint8)
+        assert frame.shape == (self.H, self.W)
+        return lib().orc_tcd_push(self.h, _ptr(frame))
+
+    def tracks(self) -> np.ndarray:
+        n = lib().orc_tcd_get(self.h, None, 0)
+        out = np.zeros(max(n, 1), TRACK_DTYPE)
+        assert lib().orc_tcd_get(self.h, _ptr(out), len(out)) == n
+        return out[:n].copy()
+
+    def close(self):
+        if self.h:
+            lib().orc_tcd_close(self.h)
             self.h = None
 
     def __del__(self):

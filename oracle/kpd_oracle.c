@@ -117,6 +117,40 @@
  *       2^l). Every step is an IEEE double operation in a stated order, so
  *       any implementation that keeps the order gets the same bits.
  *   R19 Eq. (1) carries refined values with their features.
+ *
+ * The comparison system of Sec. 4, the temporally coherent detector (block
+ * matching of keypoint patches from frame to frame), as read here:
+ *   T1  Groups of Delta frames, counted from the first frame (and from a
+ *       reset): the first frame of a group takes the full-frame detection
+ *       F(I_n) (R1-R5, in the order of R8, every cell marked); every other
+ *       frame propagates the previous frame's keypoints by block matching
+ *       and detects nothing.
+ *   T2  Positions are in quarter pixels of level 0. A level-o keypoint (x,y)
+ *       starts at the centre of its level-0 footprint: 4(x << o) + 2(2^o - 1)
+ *       (likewise y). Octave and score travel with it.
+ *   T3  A sample at quarter-pixel position (X, Y) (X = 4x + a, Y = 4y + b,
+ *       0 <= a, b < 4) is the bilinear mix ((4-a)(4-b)I(x,y) + a(4-b)I(x+1,y)
+ *       + (4-a)b I(x,y+1) + ab I(x+1,y+1) + 8) >> 4, exact in integers.
+ *   T4  The 16 x 16 patch at (X, Y) holds the samples at (X + 4(i-8),
+ *       Y + 4(j-8)), i, j = 0..15. A position is usable when every sample
+ *       and its right and lower neighbours lie in the frame: X >= 32,
+ *       Y >= 32, X + 28 <= 4(W-2), Y + 28 <= 4(H-2).
+ *   T5  Matching cost: the SAD between the keypoint's patch in I_{n-1}, at
+ *       its position there, and a candidate patch in I_n. A keypoint whose
+ *       own patch is not usable is dropped.
+ *   T6  Coarse step: candidates at displacements (2u, 2v) pixels, u, v in
+ *       -6..6 (the 24 x 24 window at a precision of 2); fine step: around
+ *       the coarse winner, displacements (u/4, v/4), u, v in -7..7 (quarter
+ *       pixels up to 1.75 away on each side, so the pixels that the step of
+ *       2 skipped are reached). Each step visits its grid in spiral order:
+ *       ring r = max(|u|, |v|) outwards; ring r starts at (-r, -r) and walks
+ *       clockwise (y down): along the top row to the right, down the right
+ *       column, left along the bottom row, up the left column. Unusable
+ *       candidates are skipped. The step keeps the lowest SAD, the earliest
+ *       on ties, and stops at the first candidate whose SAD is below T_ET.
+ *   T7  The keypoint moves to the fine winner when its SAD is below T_BM;
+ *       otherwise (or with no usable coarse candidate) it is dropped. The
+ *       survivors keep the previous frame's order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -840,4 +874,186 @@ int orc_get(orc_stream* s, orc_kp* out, int cap, uint8_t* mask, int64_t* sad, ui
     if (sad) memcpy(sad, s->sad, sizeof(int64_t) * (size_t)ncell);
     if (count) memcpy(count, s->count, sizeof(uint32_t) * (size_t)ncell);
     return s->nK;
+}
+
+/* ------------------------------------------ temporally coherent detector */
+
+typedef struct {
+    int32_t x4, y4, octave, score, sad;
+} orc_track;
+
+/* T3 */
+static int tcd_sample(const uint8_t* I, int W, int X, int Y)
+{
+    const int x = X >> 2, y = Y >> 2, a = X & 3, b = Y & 3;
+    const int p00 = I[y * W + x];
+    const int p10 = a ? I[y * W + x + 1] : 0;
+    const int p01 = b ? I[(y + 1) * W + x] : 0;
+    const int p11 = (a && b) ? I[(y + 1) * W + x + 1] : 0;
+    return ((4 - a) * (4 - b) * p00 + a * (4 - b) * p10 + (4 - a) * b * p01 + a * b * p11 + 8) >> 4;
+}
+
+int orc_tcd_sample(const uint8_t* I, int W, int H, int X, int Y)
+{
+    if (X < 0 || Y < 0 || (X >> 2) + ((X & 3) != 0) >= W || (Y >> 2) + ((Y & 3) != 0) >= H) return -1;
+    return tcd_sample(I, W, X, Y);
+}
+
+/* T4 */
+static int tcd_usable(int W, int H, int X, int Y)
+{
+    return X >= 32 && Y >= 32 && X + 28 <= 4 * (W - 2) && Y + 28 <= 4 * (H - 2);
+}
+
+static void tcd_patch(const uint8_t* I, int W, int X, int Y, int* P)
+{
+    for (int j = 0; j < 16; ++j)
+        for (int i = 0; i < 16; ++i) P[j * 16 + i] = tcd_sample(I, W, X + 4 * (i - 8), Y + 4 * (j - 8));
+}
+
+/* T6: the k-th grid offset in spiral order, found by walking the rings */
+static void tcd_spiral(int k, int* u, int* v)
+{
+    int cu = 0, cv = 0, n = 0;
+    if (k == 0) { *u = 0; *v = 0; return; }
+    n = 1;
+    for (int r = 1;; ++r) {
+        /* the walk: start at the ring's top-left corner */
+        cu = -r; cv = -r;
+        static const int du[4] = {1, 0, -1, 0}, dv[4] = {0, 1, 0, -1};
+        for (int side = 0; side < 4; ++side)
+            for (int step = 0; step < 2 * r; ++step) {
+                if (n == k) { *u = cu; *v = cv; return; }
+                ++n;
+                cu += du[side];
+                cv += dv[side];
+            }
+    }
+}
+
+int orc_tcd_spiral(int k, int* u, int* v)
+{
+    if (k < 0) return -1;
+    tcd_spiral(k, u, v);
+    return 0;
+}
+
+/* one step of T6 around (X, Y): grid of (2R+1)^2 offsets scaled by `scale`
+ * quarter pixels; returns the winner's SAD (or -1 with no usable candidate)
+ * and its position */
+static int tcd_step(const uint8_t* I, int W, int H, const int* ref, int X, int Y, int R, int scale, int t_et,
+                    int* bx, int* by)
+{
+    int best = -1;
+    const int n = (2 * R + 1) * (2 * R + 1);
+    for (int k = 0; k < n; ++k) {
+        int u, v;
+        tcd_spiral(k, &u, &v);
+        const int cx = X + scale * u, cy = Y + scale * v;
+        if (!tcd_usable(W, H, cx, cy)) continue;
+        int sad = 0;
+        for (int j = 0; j < 16; ++j)
+            for (int i = 0; i < 16; ++i) {
+                const int d = ref[j * 16 + i] - tcd_sample(I, W, cx + 4 * (i - 8), cy + 4 * (j - 8));
+                sad += d < 0 ? -d : d;
+            }
+        if (best < 0 || sad < best) { best = sad; *bx = cx; *by = cy; }
+        if (sad < t_et) break;
+    }
+    return best;
+}
+
+/* T5-T7: propagate n tracks from prev to cur; returns the survivors */
+int orc_tcd_track(const uint8_t* prev, const uint8_t* cur, int W, int H, int t_bm, int t_et, const orc_track* in,
+                  int n, orc_track* out)
+{
+    int ref[256], m = 0;
+    for (int k = 0; k < n; ++k) {
+        const orc_track t = in[k];
+        if (!tcd_usable(W, H, t.x4, t.y4)) continue;
+        tcd_patch(prev, W, t.x4, t.y4, ref);
+        int cx, cy, fx, fy;
+        if (tcd_step(cur, W, H, ref, t.x4, t.y4, 6, 8, t_et, &cx, &cy) < 0) continue;
+        const int sad = tcd_step(cur, W, H, ref, cx, cy, 7, 1, t_et, &fx, &fy);
+        if (sad < 0 || sad >= t_bm) continue;
+        out[m] = t;
+        out[m].x4 = fx;
+        out[m].y4 = fy;
+        out[m].sad = sad;
+        ++m;
+    }
+    return m;
+}
+
+typedef struct {
+    int W, H, gop, t_bm, t_et;
+    int n_frames;        /* frames since open or reset */
+    orc_stream* det;     /* full-frame detection of the group's first frame (T1) */
+    uint8_t* prev;
+    orc_track* T;
+    orc_track* T2;
+    int nT, capT;
+} orc_tcd;
+
+orc_tcd* orc_tcd_open(int W, int H, int t, int O, int Nc, int Nr, int gop, int t_bm, int t_et)
+{
+    if (gop < 1) return NULL;
+    orc_stream* det = orc_open(W, H, t, O, Nc, Nr, -1, 0xFFFFFFFFu);
+    if (!det) return NULL;
+    orc_tcd* s = (orc_tcd*)calloc(1, sizeof(orc_tcd));
+    s->W = W; s->H = H; s->gop = gop; s->t_bm = t_bm; s->t_et = t_et;
+    s->det = det;
+    s->prev = (uint8_t*)malloc((size_t)W * H);
+    s->capT = W * H + 16;
+    s->T = (orc_track*)malloc(sizeof(orc_track) * (size_t)s->capT);
+    s->T2 = (orc_track*)malloc(sizeof(orc_track) * (size_t)s->capT);
+    return s;
+}
+
+void orc_tcd_close(orc_tcd* s)
+{
+    if (!s) return;
+    orc_close(s->det);
+    free(s->prev); free(s->T); free(s->T2);
+    free(s);
+}
+
+int orc_tcd_reset(orc_tcd* s)
+{
+    s->n_frames = 0;
+    return 0;
+}
+
+int orc_tcd_push(orc_tcd* s, const uint8_t* frame)
+{
+    if (s->n_frames % s->gop == 0) {   /* T1, T2 */
+        orc_reset(s->det);
+        orc_push(s->det, frame);
+        s->nT = 0;
+        for (int k = 0; k < s->det->nK; ++k) {
+            const orc_kp p = s->det->K[k];
+            orc_track* t = &s->T[s->nT++];
+            t->x4 = 4 * (p.x << p.octave) + 2 * ((1 << p.octave) - 1);
+            t->y4 = 4 * (p.y << p.octave) + 2 * ((1 << p.octave) - 1);
+            t->octave = p.octave;
+            t->score = p.score;
+            t->sad = 0;
+        }
+    } else {
+        const int m = orc_tcd_track(s->prev, frame, s->W, s->H, s->t_bm, s->t_et, s->T, s->nT, s->T2);
+        orc_track* x = s->T; s->T = s->T2; s->T2 = x;
+        s->nT = m;
+    }
+    memcpy(s->prev, frame, (size_t)s->W * s->H);
+    s->n_frames += 1;
+    return s->nT;
+}
+
+int orc_tcd_get(orc_tcd* s, orc_track* out, int cap)
+{
+    if (out) {
+        if (cap < s->nT) return -1;
+        memcpy(out, s->T, sizeof(orc_track) * (size_t)s->nT);
+    }
+    return s->nT;
 }

@@ -299,3 +299,80 @@ def refine(levels, t: int, x: int, y: int, o: int):
     other = hi if tt >= 0 else lo
     a = abs(tt)
     return np.array([own[0] + a * (other[0] - own[0]), own[1] + a * (other[1] - own[1]), o + tt, score_v])
+
+
+# ------------------------------------------- temporally coherent detector
+
+def spiral_offsets(R: int):
+    """Grid offsets |u|, |v| <= R in spiral order, by sorting on (ring,
+    position along the ring's clockwise perimeter from its top-left corner)."""
+    def key(uv):
+        u, v = uv
+        r = max(abs(u), abs(v))
+        if r == 0:
+            return (0, 0)
+        if v == -r and u < r:
+            p = u + r                 # top row, left to right
+        elif u == r and v < r:
+            p = 2 * r + (v + r)       # right column, downwards
+        elif v == r and u > -r:
+            p = 4 * r + (r - u)       # bottom row, right to left
+        else:
+            p = 6 * r + (r - v)       # left column, upwards
+        return (r, p)
+    return sorted(((u, v) for u in range(-R, R + 1) for v in range(-R, R + 1)), key=key)
+
+
+def quarter_samples(img: np.ndarray, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Bilinear samples at quarter-pixel positions, exact integers."""
+    img = img.astype(np.int64)
+    x, y, a, b = X // 4, Y // 4, X % 4, Y % 4
+    H, W = img.shape
+    x1, y1 = np.minimum(x + 1, W - 1), np.minimum(y + 1, H - 1)
+    v = ((4 - a) * (4 - b) * img[y, x] + a * (4 - b) * img[y, x1] + (4 - a) * b * img[y1, x] +
+         a * b * img[y1, x1] + 8)
+    return v >> 4
+
+
+def _patch(img, X, Y):
+    off = 4 * (np.arange(16) - 8)
+    return quarter_samples(img, X + off[None, :], Y + off[:, None])
+
+
+def _usable(W, H, X, Y):
+    return X >= 32 and Y >= 32 and X + 28 <= 4 * (W - 2) and Y + 28 <= 4 * (H - 2)
+
+
+def _search(cur, ref, X, Y, R, scale, t_et):
+    H, W = cur.shape
+    best = None
+    for u, v in spiral_offsets(R):
+        cx, cy = X + scale * u, Y + scale * v
+        if not _usable(W, H, cx, cy):
+            continue
+        sad = int(np.abs(_patch(cur, cx, cy) - ref).sum())
+        if best is None or sad < best[0]:
+            best = (sad, cx, cy)
+        if sad < t_et:
+            break
+    return best
+
+
+def track_step(prev: np.ndarray, cur: np.ndarray, tracks, t_bm: int, t_et: int):
+    """Block-matching propagation of (x4, y4, octave, score, sad) tracks:
+    coarse search over 2-pixel steps within 12 pixels, fine search over
+    quarter pixels within 1.75 pixels, both in spiral order with early
+    termination; a track survives when the fine SAD is below t_bm."""
+    H, W = prev.shape
+    out = []
+    for x4, y4, o, sc, _ in tracks:
+        if not _usable(W, H, x4, y4):
+            continue
+        ref = _patch(prev, x4, y4)
+        c = _search(cur, ref, x4, y4, 6, 8, t_et)
+        if c is None:
+            continue
+        f = _search(cur, ref, c[1], c[2], 7, 1, t_et)
+        if f[0] < t_bm:
+            out.append((f[1], f[2], o, sc, f[0]))
+    return out

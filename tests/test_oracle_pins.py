@@ -758,3 +758,144 @@ def test_oracle_reproduces_stored_fixture(name, det):
         got, mask, _, _ = s.get()
         assert "".join(str(int(m)) for m in mask) == mask_bits
         assert kps_tuples(got) == kps
+
+
+# ------------------------------------------- temporally coherent detector
+
+def _texture(seed, h, w, passes=3, width=5):
+    """Smooth random texture: box-blurred noise stretched to 10..245."""
+    rng = np.random.default_rng(seed)
+    img = rng.random((h, w))
+    k = np.ones(width) / width
+    for _ in range(passes):
+        img = np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), 1, img)
+        img = np.apply_along_axis(lambda c: np.convolve(c, k, mode="same"), 0, img)
+    img = (img - img.min()) / (img.max() - img.min())
+    return np.rint(10 + 235 * img).astype(np.uint8)
+
+
+def test_tcd_spiral_order():
+    # the walk of the oracle against a sort on (ring, clockwise perimeter
+    # position); every ring of radius r holds 8r offsets
+    order = bf.spiral_offsets(7)
+    assert [oracle.tcd_spiral(k) for k in range(len(order))] == order
+    assert len(set(order)) == 225
+    for r in range(1, 8):
+        start = (2 * r - 1) ** 2
+        assert order[start] == (-r, -r)
+        ring = order[start:(2 * r + 1) ** 2]
+        assert len(ring) == 8 * r and all(max(abs(u), abs(v)) == r for u, v in ring)
+        # consecutive offsets on a ring are 4-neighbours (a walk)
+        assert all(abs(a[0] - b[0]) + abs(a[1] - b[1]) == 1 for a, b in zip(ring, ring[1:]))
+        assert ring[1] == (-r + 1, -r)   # first step to the right along the top row (y down)
+
+
+def test_tcd_sample_closed_forms():
+    # bilinear sampling is exact on a linear ramp: the sample at quarter
+    # position (X, Y) of I = 2x + 3y is round-half-up((2X + 3Y) / 4)
+    H, W = 30, 40
+    ys, xs = np.mgrid[0:H, 0:W]
+    ramp = (2 * xs + 3 * ys).astype(np.uint8)
+    for X in range(0, 4 * (W - 1) + 1, 3):
+        for Y in range(0, 4 * (H - 1) + 1, 5):
+            assert oracle.tcd_sample(ramp, X, Y) == (2 * X + 3 * Y + 2) >> 2, (X, Y)
+    img = _texture(3, H, W)
+    assert oracle.tcd_sample(img, 4 * 7, 4 * 9) == img[9, 7]            # whole pixels read the pixel
+    assert oracle.tcd_sample(img, 4 * 7 + 2, 4 * 9) == (int(img[9, 7]) + int(img[9, 8]) + 1) >> 1
+    assert oracle.tcd_sample(img, 4 * (W - 1), 0) == img[0, W - 1]      # last column, no right neighbour
+    assert oracle.tcd_sample(img, 4 * (W - 1) + 1, 0) == -1
+    assert oracle.tcd_sample(img, -1, 0) == -1
+
+
+@pytest.mark.parametrize("dx,dy", [(0, 0), (2, -4), (3, 1), (-5, 7), (12, -12), (13, -1), (-1, 0)])
+def test_tcd_integer_translation_is_found_exactly(dx, dy):
+    # the content moves by (dx, dy) whole pixels (up to 13.75 is reachable:
+    # 12 by the coarse step, 1.75 more by the fine one): every track whose
+    # patches stay in the frame moves by exactly (4dx, 4dy) with SAD 0
+    H, W = 120, 140
+    big = _texture(11 + dx, H + 40, W + 40)
+    prev = big[20:20 + H, 20:20 + W]
+    cur = big[20 - dy:20 - dy + H, 20 - dx:20 - dx + W]
+    pts = [(x, y) for x in range(36, W - 36, 9) for y in range(36, H - 36, 11)]
+    tr = np.array([(4 * x, 4 * y, 0, 50, 0) for x, y in pts], oracle.TRACK_DTYPE)
+    out = oracle.tcd_track(prev, cur, tr, t_bm=1, t_et=0)
+    assert len(out) == len(tr)
+    np.testing.assert_array_equal(out["x4"], tr["x4"] + 4 * dx)
+    np.testing.assert_array_equal(out["y4"], tr["y4"] + 4 * dy)
+    assert (out["sad"] == 0).all()
+    np.testing.assert_array_equal(out["score"], tr["score"])
+
+
+@pytest.mark.parametrize("t_bm,t_et,seed", [(1800, 1000, 1), (1800, 0, 2), (4000, 2500, 3), (600, 1000, 4),
+                                            (100000, 100000, 5)])
+def test_tcd_track_matches_bruteforce(t_bm, t_et, seed):
+    # moving scenes on a small frame, so that many candidates and tracks
+    # meet the border: every survivor, position, SAD and the order
+    frames = _scene(seed=40 + seed, frames=3, w=72, h=56, move=1.5)
+    kps = oracle.detect(frames[0], 12, 2)
+    tr = np.array([(4 * (k["x"] << k["octave"]) + 2 * ((1 << k["octave"]) - 1),
+                    4 * (k["y"] << k["octave"]) + 2 * ((1 << k["octave"]) - 1), k["octave"], k["score"], 0)
+                   for k in kps], oracle.TRACK_DTYPE)
+    assert len(tr) > 10
+    for i in (1, 2):
+        got = oracle.tcd_track(frames[i - 1], frames[i], tr, t_bm, t_et)
+        exp = bf.track_step(frames[i - 1], frames[i], [tuple(int(v) for v in r) for r in tr], t_bm, t_et)
+        assert [tuple(int(v) for v in r) for r in got] == exp
+        tr = got
+
+
+def test_tcd_stream_groups_and_drops():
+    # T1: the first frame of every group is F(I_n) in the detector's order,
+    # the others propagate the previous frame's tracks; a reset starts a new
+    # group; an unrelated frame drops every track
+    frames = _scene(seed=61, frames=7, w=96, h=72, move=0.8)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    tc = oracle.Tcd(W, H, t, O, Nc, Nr, gop=3, t_bm=1800, t_et=1000)
+    prev, prev_tr = None, None
+    for i, f in enumerate(frames):
+        if i == 5:
+            tc.reset()
+        n = tc.push(f)
+        got = tc.tracks()
+        assert n == len(got)
+        if i in (0, 3, 5):   # groups of 3 from the first frame and from the reset
+            det = oracle.Stream(W, H, t, O, Nc, Nr, -1)
+            det.push(f)
+            kps = det.get()[0]
+            seeded = [(4 * (int(k["x"]) << int(k["octave"])) + 2 * ((1 << int(k["octave"])) - 1),
+                       4 * (int(k["y"]) << int(k["octave"])) + 2 * ((1 << int(k["octave"])) - 1),
+                       int(k["octave"]), int(k["score"]), 0) for k in kps]
+            assert [tuple(int(v) for v in r) for r in got] == seeded, i
+        else:
+            exp = oracle.tcd_track(prev, f, prev_tr, 1800, 1000)
+            np.testing.assert_array_equal(got, exp)
+            assert len(got) > 0
+        prev, prev_tr = f, got
+    noise = np.random.default_rng(9).integers(0, 256, (H, W)).astype(np.uint8)
+    tc.push(noise)   # the third frame of the group that the reset started
+    assert len(tc.tracks()) == 0
+    tc.close()
+
+
+def test_tcd_thresholds_are_strict():
+    # T_ET and T_BM compare with "below": a SAD equal to T_ET does not stop
+    # the search, and a match whose SAD equals T_BM is dropped
+    H, W = 100, 120
+    big = _texture(77, H + 20, W + 20)
+    prev = big[10:10 + H, 10:10 + W]
+    cur = big[10 - 3:10 - 3 + H, 10 - 4:10 - 4 + W].astype(np.int64)
+    cur = np.clip(cur + np.random.default_rng(5).integers(-3, 4, cur.shape), 0, 255).astype(np.uint8)
+    for x, y in ((40, 40), (60, 52), (75, 45)):
+        tr = np.array([(4 * x, 4 * y, 0, 30, 0)], oracle.TRACK_DTYPE)
+        ref = bf._patch(prev, 4 * x, 4 * y)
+        sad0 = int(np.abs(bf._patch(cur, 4 * x, 4 * y) - ref).sum())   # the first coarse candidate
+        row = [tuple(int(v) for v in r) for r in tr]
+        for t_et in (sad0, sad0 + 1):
+            got = oracle.tcd_track(prev, cur, tr, 10 ** 6, t_et)
+            assert [tuple(int(v) for v in r) for r in got] == bf.track_step(prev, cur, row, 10 ** 6, t_et)
+        stopped = oracle.tcd_track(prev, cur, tr, 10 ** 6, sad0 + 1)[0]
+        full = oracle.tcd_track(prev, cur, tr, 10 ** 6, sad0)[0]
+        assert (stopped["x4"], stopped["y4"]) != (full["x4"], full["y4"])   # the threshold decided
+        s = int(full["sad"])
+        assert len(oracle.tcd_track(prev, cur, tr, s, sad0)) == 0
+        assert len(oracle.tcd_track(prev, cur, tr, s + 1, sad0)) == 1
