@@ -297,6 +297,58 @@ def feature_workload(kpd, wl: Workload, args, which: str) -> dict:
     return out
 
 
+def tcd_workload(kpd, wl: Workload, args) -> dict:
+    """The comparison system of Sec. 4 on the same video: full-frame
+    detection on the first frame of every group of 10, quarter-pixel block
+    matching of the keypoints' 16 x 16 patches on the others (T_BM = 1800,
+    T_ET = 1000). Whole-video throughput, per-frame GPU time of detected and
+    propagated frames (events on the tracker's stream), tracks per frame."""
+    import numpy as np
+    import torch
+    d = wl.det
+    gop = 10
+    g = kpd.Tcd(wl.W, wl.H, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows), gop, 1800, 1000)
+    ptrs = [wl.dev[i].data_ptr() for i in range(wl.F)]
+
+    def one_pass():
+        g.reset()
+        for p in ptrs:
+            kpd._check(kpd.lib.tcd_push(g.handle, p, wl.W, kpd.FRAME_DEVICE_RETAIN))
+
+    one_pass()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 5)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_pass()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(wl.F + 1)]
+    g.reset()
+    ev[0].record()
+    for i, p in enumerate(ptrs):
+        kpd._check(kpd.lib.tcd_push(g.handle, p, wl.W, kpd.FRAME_DEVICE_RETAIN))
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(wl.F)])
+    first = np.arange(wl.F) % gop == 0
+    g.reset()
+    counts = []
+    for p in ptrs:
+        kpd._check(kpd.lib.tcd_push(g.handle, p, wl.W, kpd.FRAME_DEVICE_RETAIN))
+        counts.append(len(g.tracks()))
+    g.close()
+    counts = np.array(counts)
+    return {"value": round(wl.F * wl.W * wl.H / dt / 1e6, 2), "unit": "Mpixel/s", "frames_per_s": round(wl.F / dt, 1),
+            "gpu_ms_per_frame": {"detected": round(float(ms[first].mean()), 4),
+                                 "propagated": round(float(ms[~first].mean()), 4)},
+            "tracks_per_frame": {"detected": round(float(counts[first].mean()), 1),
+                                 "propagated": round(float(counts[~first].mean()), 1)},
+            "what": f"{wl.name}, temporally coherent detector: groups of {gop}, 16x16 patches, coarse spiral "
+                    "search (2-pixel steps, 24-pixel window), quarter-pixel refinement within 1.75 pixels, "
+                    "T_BM=1800, T_ET=1000; one tcd_push per frame"}
+
+
 def layer_study(kpd, wl: Workload, args) -> dict:
     """The mask variants side by side on one workload (the paper tries every
     layer and keeps the top one since results are alike): per-frame push
@@ -902,6 +954,8 @@ def main():
     for which in FEATURE_PASSES:
         log(f"[bench] {which}")
         out[which] = feature_workload(kpd, wl, args, which)
+    log("[bench] temporally coherent detector")
+    out["tcd"] = tcd_workload(kpd, wl, args)
     out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:
         del wl

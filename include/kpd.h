@@ -350,6 +350,81 @@ int kpd_profile(kpd_stream* s, int enable);
  * the number of launches (arrays of KPD_NKERNELS; either may be NULL). */
 int kpd_profile_read(kpd_stream* s, double* ms, uint64_t* launches);
 
+/* ------------------------------------------ temporally coherent detector */
+
+/* The comparison system of Sec. 4: keypoints propagated from frame to frame
+ * by block matching instead of being detected. Frames come in groups of
+ * `gop` (Delta), counted from the first push and from tcd_reset. The first
+ * frame of a group takes the full-frame detection F(I_n) (as push_frame with
+ * T_I < 0, in D_n's order); every keypoint becomes a track at the centre of
+ * its level-0 footprint, 4(x << o) + 2(2^o - 1) in quarter pixels (likewise
+ * y). Every other frame moves each track of the previous frame:
+ *   - a sample at quarter position (X, Y) = (4x + a, 4y + b) is the exact
+ *     bilinear mix ((4-a)(4-b) I(x,y) + a(4-b) I(x+1,y) + (4-a)b I(x,y+1)
+ *     + ab I(x+1,y+1) + 8) >> 4;
+ *   - a patch is the 16 x 16 samples at (X + 4(i-8), Y + 4(j-8)); a
+ *     position is usable when X >= 32, Y >= 32, X + 28 <= 4(W-2) and
+ *     Y + 28 <= 4(H-2); a track whose patch in I_{n-1} is not usable is
+ *     dropped;
+ *   - the coarse step tries displacements of (2u, 2v) pixels, |u|, |v| <= 6
+ *     (the 24-pixel window at a precision of 2), the fine step, around the
+ *     coarse winner, (u/4, v/4) pixels, |u|, |v| <= 7 (quarter pixels up to
+ *     1.75 away). Each step visits its grid in spiral order (ring
+ *     max(|u|,|v|) outwards, each ring clockwise from its top-left corner,
+ *     y down), skips unusable candidates, keeps the lowest SAD against the
+ *     track's patch in I_{n-1} (the earliest on ties) and stops at the first
+ *     SAD below t_et;
+ *   - the track moves to the fine winner when its SAD is below t_bm, and is
+ *     dropped otherwise. Survivors keep their order.
+ * Integer arithmetic throughout. The tracker owns an inner stream (tcd_bytes
+ * includes it) and two frame slots in its arena. */
+typedef struct kpd_tcd_params {
+    int32_t gop;    /* frames per group (Delta), >= 1; the paper uses 10 */
+    int32_t t_bm;   /* a match needs SAD < t_bm (the paper's T_BM = 1800) */
+    int32_t t_et;   /* a step stops at the first SAD < t_et (T_ET = 1000; 0: never) */
+    int32_t pad;    /* 0 */
+} kpd_tcd_params;
+
+typedef struct kpd_track {
+    int32_t x4, y4;   /* position in quarter pixels of level 0 */
+    uint8_t octave;   /* of the detection the track started from */
+    uint8_t pad;
+    uint16_t score;   /* FAST score at detection */
+    uint32_t sad;     /* SAD of the last match (0 on the group's first frame) */
+} kpd_track;
+
+typedef struct kpd_tcd kpd_tcd;
+
+/* Arena bytes for a tracker on width x height frames. `det` holds the
+ * detector's fast_t, n_octaves, grid and tile (its id_thresh, kb_thresh,
+ * chunk_frames, layer_mask and features are ignored: the group's first
+ * frame is detected whole). 0 when invalid (see kpd_last_error). */
+size_t tcd_bytes(int width, int height, const kpd_params* det, const kpd_tcd_params* tp);
+
+/* Open a tracker on a caller-owned, 256-byte-aligned device arena of at
+ * least tcd_bytes() bytes and a HIP stream; like open_stream. */
+int tcd_open(int width, int height, const kpd_params* det, const kpd_tcd_params* tp, void* dev_arena,
+             size_t arena_bytes, void* hip_stream, kpd_tcd** out);
+
+/* Process the next frame (flags and pitch as push_frame; with
+ * KPD_FRAME_DEVICE_RETAIN the frame must stay unchanged until the next
+ * push, which matches against it). Asynchronous. */
+int tcd_push(kpd_tcd* s, const uint8_t* frame, size_t pitch_bytes, int flags);
+
+/* Copy the current tracks (synchronises): *count receives their number;
+ * KPD_ETRUNC, copying nothing, when it exceeds capacity. */
+int tcd_get(kpd_tcd* s, kpd_track* out, size_t capacity, size_t* count);
+
+/* Device pointers to the current tracks and their uint32 count, valid until
+ * the next push. Does not synchronise. */
+int tcd_device_result(kpd_tcd* s, const kpd_track** d_tracks, const uint32_t** d_count);
+
+/* Start a new group with the next frame. */
+int tcd_reset(kpd_tcd* s);
+
+/* Wait for the tracker's work and release it (the inner stream too). */
+int tcd_close(kpd_tcd* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -776,6 +776,12 @@ int copy_features(kpd_stream* s, const size_t* off, T* out, size_t capacity, siz
 
 }  // namespace
 
+namespace kpd {
+// error reporting for the other host files of the library
+int api_fail(int code, const std::string& msg) { return fail(code, msg); }
+int api_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace kpd
+
 extern "C" {
 
 int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)

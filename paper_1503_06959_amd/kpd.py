@@ -36,8 +36,11 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
             "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
-            "kpd_desc_point", "get_refined")
+            "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
+            "tcd_device_result", "tcd_reset", "tcd_close")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
+TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2"),
+                        ("sad", "<u4")])
 REFINED_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("log2_scale", "<f4"), ("score", "<f4")])
 FEAT_DESCRIPTOR, FEAT_REFINE = 1, 2
 KERNEL_NAMES = ("k_frame", "k_detect", "k_compact", "k_mark", "k_describe")
@@ -49,6 +52,11 @@ class KpdParams(ctypes.Structure):
                 ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32),
                 ("tile", ctypes.c_int32), ("chunk_frames", ctypes.c_int32),
                 ("layer_mask", ctypes.c_int32), ("features", ctypes.c_int32)]
+
+
+class KpdTcdParams(ctypes.Structure):
+    _fields_ = [("gop", ctypes.c_int32), ("t_bm", ctypes.c_int32), ("t_et", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class KpdError(RuntimeError):
@@ -94,6 +102,15 @@ def _load() -> ctypes.CDLL:
     L.set_mask_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.get_descriptors.argtypes = [P, P, sz, ctypes.POINTER(sz)]
     L.get_refined.argtypes = [P, P, sz, ctypes.POINTER(sz)]
+    TP = ctypes.POINTER(KpdTcdParams)
+    L.tcd_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), TP]
+    L.tcd_bytes.restype = sz
+    L.tcd_open.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), TP, P, sz, P, ctypes.POINTER(P)]
+    L.tcd_push.argtypes = [P, P, sz, ctypes.c_int]
+    L.tcd_get.argtypes = [P, P, sz, ctypes.POINTER(sz)]
+    L.tcd_device_result.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P)]
+    L.tcd_reset.argtypes = [P]
+    L.tcd_close.argtypes = [P]
     L.kpd_desc_point.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(ctypes.c_int)]
     return L
@@ -396,6 +413,83 @@ class Stream:
             close_stream(self.handle)
             self.handle = None
             self._held = [None, None]
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------- temporally coherent detector
+
+def tcd_bytes(width: int, height: int, params: KpdParams, tp: KpdTcdParams) -> int:
+    n = lib.tcd_bytes(width, height, ctypes.byref(params), ctypes.byref(tp))
+    if n == 0:
+        raise KpdError(KPD_EINVAL, lib.kpd_last_error().decode())
+    return n
+
+
+class Tcd:
+    """The temporally coherent detector (the comparison system of Sec. 4):
+    full-frame detection on the first frame of every group of `gop` frames,
+    block-matching propagation of the keypoints on the others."""
+
+    def __init__(self, width: int, height: int, params: KpdParams, gop: int = 10, t_bm: int = 1800,
+                 t_et: int = 1000, stream=None, device="cuda"):
+        self.width, self.height = width, height
+        self.tp = KpdTcdParams(gop, t_bm, t_et, 0)
+        self.params = params
+        self.nbytes = tcd_bytes(width, height, params, self.tp)
+        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        if self.arena.data_ptr() % 256:
+            raise ValueError("arena not 256-byte aligned")
+        h = ctypes.c_void_p()
+        _check(lib.tcd_open(width, height, ctypes.byref(params), ctypes.byref(self.tp), self.arena.data_ptr(),
+                            self.arena.numel(), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h.value
+        self._held = [None, None]
+
+    def push(self, frame, retain: bool = False) -> None:
+        """frame: as push_frame (host array, or CUDA tensor copied or read in
+        place when `retain`; a retained frame is kept alive until the next
+        push, which matches against it)."""
+        if isinstance(frame, np.ndarray):
+            if frame.dtype != np.uint8 or frame.ndim != 2 or frame.strides[1] != 1:
+                raise ValueError("host frame must be a uint8 [H, W] array with unit column stride")
+            _check(lib.tcd_push(self.handle, frame.ctypes.data, frame.strides[0], FRAME_HOST))
+            return
+        if not (isinstance(frame, torch.Tensor) and frame.device.type == "cuda" and frame.dtype == torch.uint8
+                and frame.dim() == 2 and frame.stride(1) == 1):
+            raise ValueError("device frame must be a CUDA uint8 [H, W] tensor with unit column stride")
+        _check(lib.tcd_push(self.handle, frame.data_ptr(), frame.stride(0),
+                            FRAME_DEVICE_RETAIN if retain else FRAME_DEVICE))
+        if retain:
+            self._held = [self._held[1], frame]
+
+    def tracks(self, capacity: int = 4096) -> np.ndarray:
+        out = np.zeros(max(capacity, 1), TRACK_DTYPE)
+        cnt = ctypes.c_size_t()
+        rc = lib.tcd_get(self.handle, out.ctypes.data, len(out), ctypes.byref(cnt))
+        if rc == KPD_ETRUNC:
+            out = np.zeros(cnt.value, TRACK_DTYPE)
+            rc = lib.tcd_get(self.handle, out.ctypes.data, len(out), ctypes.byref(cnt))
+        _check(rc)
+        return out[:cnt.value].copy()
+
+    def device_result(self):
+        """(device pointer to the tracks, device pointer to their uint32 count)."""
+        t, c = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib.tcd_device_result(self.handle, ctypes.byref(t), ctypes.byref(c)))
+        return t.value, c.value
+
+    def reset(self) -> None:
+        _check(lib.tcd_reset(self.handle))
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib.tcd_close(self.handle))
+            self.handle = None
 
     def __del__(self):
         try:

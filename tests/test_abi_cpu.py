@@ -167,3 +167,19 @@ def test_descriptor_flag_is_validated(kpd):
     assert with_ref > base + 2 * 16 * 1000    # two lists of refined values
     both = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, features=3))
     assert both > max(with_desc, with_ref)
+
+
+def test_tcd_structs_and_sizes(kpd):
+    # the tracker's records and parameter block match the header, and its
+    # arena holds the inner stream plus two frame slots and three track lists
+    assert kpd.TRACK_DTYPE.itemsize == 16 and ctypes.sizeof(kpd.KpdTcdParams) == 16
+    p = kpd.make_params(20, 4, 16, 12)
+    tp = kpd.KpdTcdParams(10, 1800, 1000, 0)
+    n = kpd.tcd_bytes(640, 480, p, tp)
+    inner = kpd.stream_bytes(640, 480, kpd.make_params(20, 4, 16, 12, id_thresh=-1))
+    cap = sum(((640 >> o) + 1) // 2 * (((480 >> o) + 1) // 2) for o in range(4)) + 16
+    assert n >= inner + 2 * 640 * 480 + 3 * 16 * cap
+    for bad in (kpd.KpdTcdParams(0, 1800, 1000, 0), kpd.KpdTcdParams(10, -1, 1000, 0),
+                kpd.KpdTcdParams(10, 1800, -5, 0), kpd.KpdTcdParams(10, 1800, 1000, 1)):
+        assert kpd.lib.tcd_bytes(640, 480, ctypes.byref(p), ctypes.byref(bad)) == 0
+    assert kpd.lib.tcd_bytes(640, 480, ctypes.byref(kpd.make_params(20, 0, 16, 12)), ctypes.byref(tp)) == 0
