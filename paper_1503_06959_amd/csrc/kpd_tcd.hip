@@ -17,7 +17,7 @@ constexpr int kCoarseR = 6, kCoarseScale = 8;   // (2u, 2v) pixels, |u|, |v| <= 
 constexpr int kFineR = 7, kFineScale = 1;       // (u/4, v/4) pixels, |u|, |v| <= 7
 // Every sample a track's searches read lies within 22 pixels of the track's
 // position in I_{n-1} (displacements up to 12 + 1.75 pixels, the patch's
-// 8 pixels, the bilinear neighbour), so each wave stages that 45 x 45
+// 8 pixels, the bilinear neighbour), so each workgroup stages that 45 x 45
 // region of I_n in LDS once.
 constexpr int kReach = 22;
 constexpr int kRegion = 2 * kReach + 1;
@@ -73,86 +73,104 @@ struct Best {
     int x, y, sad;
 };
 
-// One search step around (X, Y): the lanes take 64 spiral candidates at a
-// time; the first round with a SAD below t_et ends the step at its earliest
-// such candidate (every earlier one had a SAD of at least t_et, so it is
-// also the lowest so far), otherwise the lowest SAD, earliest on ties, wins.
-// sad < 0 when no candidate is usable.
+// One search step around (X, Y), by the whole workgroup: thread i takes
+// the i-th candidate of the spiral order (256 threads cover both grids). In
+// each wave a ballot finds its earliest candidate with a SAD below t_et and
+// a min-reduction its lowest (SAD, index) key; the waves' results meet in
+// LDS. The earliest candidate below t_et over all waves is the step's
+// result when there is one (every earlier candidate had a SAD of at least
+// t_et, so a sequential search would have stopped there with it as the
+// lowest so far); otherwise the lowest SAD, earliest on ties. sad < 0 when
+// no candidate is usable.
 __device__ Best search(const uint8_t* ref, const uint8_t* reg, int ox, int oy, int W, int H, int X, int Y, int R,
-                       int scale, int t_et, int lane)
+                       int scale, int t_et, int* s_et, int* s_min)
 {
     const int n = (2 * R + 1) * (2 * R + 1);
-    int best_key = 0x7FFFFFFF;
-    for (int base = 0; base < n; base += 64) {
-        const int k = base + lane;
-        int cx = 0, cy = 0, sad = 0;
-        bool ok = k < n;
-        if (ok) {
-            int u, v;
-            spiral_uv(k, u, v);
-            cx = X + scale * u;
-            cy = Y + scale * v;
-            ok = usable(W, H, cx, cy);
-        }
-        if (ok) sad = patch_sad(ref, reg, (cx >> 2) - 8 - ox, (cy >> 2) - 8 - oy, cx & 3, cy & 3);
-        const uint64_t et = __ballot(ok && sad < t_et);
-        if (et) {
-            const int first = __builtin_ctzll(et);
-            return Best{__shfl(cx, first), __shfl(cy, first), __shfl(sad, first)};
-        }
-        int key = ok ? (sad << 8) | k : 0x7FFFFFFF;   // sad <= 65280, k < 256
-        for (int off = 32; off > 0; off >>= 1) key = min(key, __shfl_xor(key, off));
-        best_key = min(best_key, key);
+    const int k = threadIdx.x, lane = k & 63, wave = k >> 6;
+    int cx = 0, cy = 0, sad = 0;
+    bool ok = k < n;
+    if (ok) {
+        int u, v;
+        spiral_uv(k, u, v);
+        cx = X + scale * u;
+        cy = Y + scale * v;
+        ok = usable(W, H, cx, cy);
     }
-    if (best_key == 0x7FFFFFFF) return Best{0, 0, -1};
+    if (ok) sad = patch_sad(ref, reg, (cx >> 2) - 8 - ox, (cy >> 2) - 8 - oy, cx & 3, cy & 3);
+    const uint64_t et = __ballot(ok && sad < t_et);
+    int et_key = 0x7FFFFFFF;   // (index, SAD) of the wave's earliest candidate below t_et
+    if (et) {
+        const int first = __builtin_ctzll(et);
+        et_key = ((wave * 64 + first) << 16) | __shfl(sad, first);   // sad <= 65280 < 2^16
+    }
+    int key = ok ? (sad << 8) | k : 0x7FFFFFFF;   // sad <= 65280, k < 256
+    for (int off = 32; off > 0; off >>= 1) key = min(key, __shfl_xor(key, off));
+    if (lane == 0) {
+        s_et[wave] = et_key;
+        s_min[wave] = key;
+    }
+    __syncthreads();
+    int e = 0x7FFFFFFF, m = 0x7FFFFFFF;
+#pragma unroll
+    for (int w = 0; w < kTcdWaves; ++w) {
+        e = min(e, s_et[w]);
+        m = min(m, s_min[w]);
+    }
+    __syncthreads();   // s_et and s_min are rewritten by the next step
+    int idx, bs;
+    if (e != 0x7FFFFFFF) {
+        idx = e >> 16;
+        bs = e & 0xFFFF;
+    } else if (m != 0x7FFFFFFF) {
+        idx = m & 255;
+        bs = m >> 8;
+    } else {
+        return Best{0, 0, -1};
+    }
     int u, v;
-    spiral_uv(best_key & 255, u, v);
-    return Best{X + scale * u, Y + scale * v, best_key >> 8};
+    spiral_uv(idx, u, v);
+    return Best{X + scale * u, Y + scale * v, bs};
 }
 
-// One wave per track (grid-stride over the device-side count): the patch
-// in I_{n-1} and the region of I_n go to LDS, then the coarse and the fine
-// step.
+// One workgroup per track (grid-stride over the device-side count): the
+// patch in I_{n-1} and the region of I_n go to LDS, then the coarse and the
+// fine step, each with one candidate per thread.
 __global__ __launch_bounds__(kTcdBlock) void k_tcd_track(TcdTrackArgs a)
 {
-    __shared__ uint8_t s_ref[kTcdWaves][256];
-    __shared__ uint8_t s_reg[kTcdWaves][kRegion * kRegionPitch];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint8_t* ref = s_ref[wave];
-    uint8_t* reg = s_reg[wave];
+    __shared__ uint8_t s_ref[256];
+    __shared__ uint8_t s_reg[kRegion * kRegionPitch];
+    __shared__ int s_et[kTcdWaves], s_min[kTcdWaves];
+    static_assert(kTcdBlock >= (2 * kFineR + 1) * (2 * kFineR + 1), "one candidate per thread");
+    static_assert(kTcdBlock >= (2 * kCoarseR + 1) * (2 * kCoarseR + 1), "one candidate per thread");
     const uint32_t n = min(*a.in_count, a.cap);
-    for (uint32_t k = blockIdx.x * kTcdWaves + wave; k < n; k += gridDim.x * kTcdWaves) {
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
         const kpd_track t = a.in[k];
         if (!usable(a.W, a.H, t.x4, t.y4)) {
-            if (lane == 0) a.keep[k] = 0;
+            if (threadIdx.x == 0) a.keep[k] = 0;
             continue;
         }
-        // the reference patch: 4 bilinear samples per lane, all in the frame
+        // the reference patch: one bilinear sample per thread, all in the frame
         {
             const int fa = t.x4 & 3, fb = t.y4 & 3;
             const int w00 = (4 - fa) * (4 - fb), w10 = fa * (4 - fb), w01 = (4 - fa) * fb, w11 = fa * fb;
-            const int x0 = (t.x4 >> 2) - 8, y0 = (t.y4 >> 2) - 8;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int q = m * 64 + lane, i = q & 15, j = q >> 4;
-                const uint8_t* p = a.prev + (size_t)(y0 + j) * a.prev_pitch + (x0 + i);
-                ref[q] = (uint8_t)((w00 * p[0] + w10 * p[1] + w01 * p[a.prev_pitch] + w11 * p[a.prev_pitch + 1] + 8) >> 4);
-            }
+            const int q = threadIdx.x, i = q & 15, j = q >> 4;
+            const uint8_t* p = a.prev + (size_t)((t.y4 >> 2) - 8 + j) * a.prev_pitch + ((t.x4 >> 2) - 8 + i);
+            s_ref[q] = (uint8_t)((w00 * p[0] + w10 * p[1] + w01 * p[a.prev_pitch] + w11 * p[a.prev_pitch + 1] + 8) >> 4);
         }
         // the region of I_n around the track, coordinates clamped to the
         // frame (clamped pixels are read only by unusable candidates, which
         // are skipped)
         const int ox = (t.x4 >> 2) - kReach, oy = (t.y4 >> 2) - kReach;
-        for (int q = lane; q < kRegion * kRegion; q += 64) {
+        for (int q = threadIdx.x; q < kRegion * kRegion; q += kTcdBlock) {
             const int yy = q / kRegion, xx = q - yy * kRegion;
             const int gx = min(max(ox + xx, 0), a.W - 1), gy = min(max(oy + yy, 0), a.H - 1);
-            reg[yy * kRegionPitch + xx] = a.cur[(size_t)gy * a.cur_pitch + gx];
+            s_reg[yy * kRegionPitch + xx] = a.cur[(size_t)gy * a.cur_pitch + gx];
         }
-        __builtin_amdgcn_wave_barrier();
-        const Best c = search(ref, reg, ox, oy, a.W, a.H, t.x4, t.y4, kCoarseR, kCoarseScale, a.t_et, lane);
+        __syncthreads();
+        const Best c = search(s_ref, s_reg, ox, oy, a.W, a.H, t.x4, t.y4, kCoarseR, kCoarseScale, a.t_et, s_et, s_min);
         Best f = c;
-        if (c.sad >= 0) f = search(ref, reg, ox, oy, a.W, a.H, c.x, c.y, kFineR, kFineScale, a.t_et, lane);
-        if (lane == 0) {
+        if (c.sad >= 0) f = search(s_ref, s_reg, ox, oy, a.W, a.H, c.x, c.y, kFineR, kFineScale, a.t_et, s_et, s_min);
+        if (threadIdx.x == 0) {
             const bool kept = c.sad >= 0 && f.sad < a.t_bm;
             a.keep[k] = kept ? 1u : 0u;
             if (kept) {
@@ -163,7 +181,7 @@ __global__ __launch_bounds__(kTcdBlock) void k_tcd_track(TcdTrackArgs a)
                 a.moved[k] = o;
             }
         }
-        __builtin_amdgcn_wave_barrier();   // the LDS patch and region are reused by the next track
+        __syncthreads();   // the LDS patch and region are reused by the next track
     }
 }
 
@@ -229,7 +247,7 @@ hipError_t launch_tcd_seed(const TcdSeedArgs& a, hipStream_t s)
 
 hipError_t launch_tcd_track(const TcdTrackArgs& a, hipStream_t s)
 {
-    const uint32_t blocks = a.cap == 0 ? 1u : std::min<uint32_t>((a.cap + kTcdWaves - 1) / kTcdWaves, 2048u);
+    const uint32_t blocks = a.cap == 0 ? 1u : std::min<uint32_t>(a.cap, 4096u);
     hipLaunchKernelGGL(k_tcd_track, dim3(blocks), dim3(kTcdBlock), 0, s, a);
     return hipGetLastError();
 }
