@@ -713,7 +713,7 @@ def summarize_profiles(out: str) -> None:
     pdir = os.path.join(ROOT, "profiles")
     os.makedirs(pdir, exist_ok=True)
     def short(n):
-        n = n.split("(")[0].replace("kpd::", "")
+        n = n.replace("(anonymous namespace)::", "").split("(")[0].replace("kpd::", "")
         if n.startswith("void "):
             n = n[5:]
         return n.split("<")[0]
