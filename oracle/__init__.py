@@ -65,6 +65,12 @@ def lib() -> ctypes.CDLL:
     L.orc_get_refined.argtypes = [P, P, ctypes.c_int]
     L.orc_refine_kp.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
     L.orc_refine_kp.restype = None
+    L.orc_layer_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
+    L.orc_layer_dims.restype = ctypes.c_long
+    L.orc_twothirds.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
+    L.orc_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+    L.orc_layer_range.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+    L.orc_detect_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int]
     L.orc_tcd_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.orc_tcd_spiral.argtypes = [ctypes.c_int, P, P]
     L.orc_tcd_track.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
@@ -316,3 +322,53 @@ class Tcd:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------ intra-octave layers
+
+def layer_dims(W: int, H: int, O: int):
+    """[(w, h, pixel size in half level-0 pixels)] of the 2O layers c_0, d_0,
+    c_1, d_1, ... (L1)."""
+    ws, hs, S = (np.zeros(64, np.int32) for _ in range(3))
+    lib().orc_layer_dims(W, H, O, _ptr(ws), _ptr(hs), _ptr(S))
+    return [(int(ws[l]), int(hs[l]), int(S[l])) for l in range(2 * O)]
+
+
+def twothirds(img: np.ndarray) -> np.ndarray:
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    h, w = img.shape
+    out = np.zeros(((h // 3) * 2, (w // 3) * 2), np.uint8)
+    lib().orc_twothirds(_ptr(img), w, h, _ptr(out))
+    return out
+
+
+def layers(img: np.ndarray, O: int):
+    """The 2O layers (L1) as arrays, in scale order."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    dims = layer_dims(W, H, O)
+    buf = np.zeros(sum(w * h for w, h, _ in dims) + 1, np.uint8)
+    assert lib().orc_layers(_ptr(img), W, H, O, _ptr(buf)) == 0
+    out, off = [], 0
+    for w, h, _ in dims:
+        out.append(buf[off:off + w * h].reshape(h, w).copy())
+        off += w * h
+    return out
+
+
+def layer_range(S1: int, S2: int, x: int):
+    lo, hi = ctypes.c_int(), ctypes.c_int()
+    lib().orc_layer_range(S1, S2, x, ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def detect_layers(img: np.ndarray, t: int, O: int) -> np.ndarray:
+    """Full-frame detection over octaves and intra-octaves (L1-L3); the
+    `octave` field holds the layer index (2i: c_i, 2i+1: d_i)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    cap = W * H + 16
+    out = np.zeros(cap, KP_DTYPE)
+    n = lib().orc_detect_layers(_ptr(img), W, H, t, O, _ptr(out), cap)
+    assert n >= 0
+    return out[:n].copy()

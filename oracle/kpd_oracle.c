@@ -151,6 +151,26 @@
  *   T7  The keypoint moves to the fine winner when its SAD is below T_BM;
  *       otherwise (or with no usable coarse candidate) it is dropped. The
  *       survivors keep the previous frame's order.
+ *
+ * BRISK's intra-octave layers (Sec. 2: layers between the octaves, the
+ * first one made by downsampling the image by 1.5), for full-frame
+ * detection of one image:
+ *   L1  Layers in scale order c_0, d_0, c_1, d_1, ..., c_{O-1}, d_{O-1}
+ *       (layer index 2i for c_i, 2i+1 for d_i). c_i are the octaves (R1).
+ *       d_0 takes every 3 x 3 block of c_0 (only whole blocks) to a 2 x 2
+ *       block: output (2a+p, 2b+q) = (sum over i, j of w_p(i) w_q(j)
+ *       c_0(3a+i, 3b+j) + 4) / 9 (floor), w_0 = (2, 1, 0), w_1 = (0, 1, 2),
+ *       the mean over the 1.5 x 1.5 area the output pixel covers, rounded to
+ *       nearest; d_{i+1} halves d_i as R1 does. A pixel of c_i covers 2^i
+ *       level-0 pixels a side, one of d_i 1.5 * 2^i.
+ *   L2  Every layer is scored as R2, R3, R5.
+ *   L3  Two pixels of the same layer, or of layers adjacent in the scale
+ *       order, are neighbours when their closed level-0 footprints
+ *       [x s, (x+1) s] x [y s, (y+1) s] intersect (s the pixel size); on
+ *       one layer these are the 8 neighbours and between octaves exactly
+ *       the neighbourhood of R4. A pixel with V > 0 is a keypoint when no
+ *       neighbour ranks above it (higher V, then the lower layer index, then
+ *       the smaller (y, x)). Keypoints are listed by layer, then y, then x.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1056,4 +1076,122 @@ int orc_tcd_get(orc_tcd* s, orc_track* out, int cap)
         memcpy(out, s->T, sizeof(orc_track) * (size_t)s->nT);
     }
     return s->nT;
+}
+
+/* ------------------------------------------------ intra-octave layers */
+
+/* L1: sizes of the 2O layers in scale order and their pixel sizes in
+ * half level-0 pixels; returns the total byte count */
+long orc_layer_dims(int W, int H, int O, int* ws, int* hs, int* S)
+{
+    long total = 0;
+    for (int i = 0; i < O; ++i) {
+        ws[2 * i] = W >> i;
+        hs[2 * i] = H >> i;
+        S[2 * i] = 2 << i;
+        ws[2 * i + 1] = ((W / 3) * 2) >> i;
+        hs[2 * i + 1] = ((H / 3) * 2) >> i;
+        S[2 * i + 1] = 3 << i;
+        total += (long)ws[2 * i] * hs[2 * i] + (long)ws[2 * i + 1] * hs[2 * i + 1];
+    }
+    return total;
+}
+
+/* L1: the 1.5x downsampling of c_0 into d_0 */
+int orc_twothirds(const uint8_t* src, int w, int h, uint8_t* dst)
+{
+    static const int wt[2][3] = {{2, 1, 0}, {0, 1, 2}};
+    const int dw = (w / 3) * 2, dh = (h / 3) * 2;
+    for (int Y = 0; Y < dh; ++Y)
+        for (int X = 0; X < dw; ++X) {
+            const int a = X / 2, p = X % 2, b = Y / 2, q = Y % 2;
+            int sum = 0;
+            for (int j = 0; j < 3; ++j)
+                for (int i = 0; i < 3; ++i) sum += wt[p][i] * wt[q][j] * src[(3 * b + j) * w + 3 * a + i];
+            dst[Y * dw + X] = (uint8_t)((sum + 4) / 9);
+        }
+    return 0;
+}
+
+static void halve(const uint8_t* src, int w, int h, uint8_t* dst)
+{
+    const int dw = w / 2, dh = h / 2;
+    for (int y = 0; y < dh; ++y)
+        for (int x = 0; x < dw; ++x) {
+            const int s = src[2 * y * w + 2 * x] + src[2 * y * w + 2 * x + 1] + src[(2 * y + 1) * w + 2 * x] +
+                          src[(2 * y + 1) * w + 2 * x + 1];
+            dst[y * dw + x] = (uint8_t)((s + 2) >> 2);
+        }
+}
+
+/* all 2O layers, concatenated in scale order */
+int orc_layers(const uint8_t* img, int W, int H, int O, uint8_t* out)
+{
+    int ws[64], hs[64], S[64];
+    if (O < 1 || O > 16) return -1;
+    orc_layer_dims(W, H, O, ws, hs, S);
+    long off[65];
+    off[0] = 0;
+    for (int l = 0; l < 2 * O; ++l) off[l + 1] = off[l] + (long)ws[l] * hs[l];
+    memcpy(out, img, (size_t)W * H);
+    for (int i = 1; i < O; ++i) halve(out + off[2 * i - 2], ws[2 * i - 2], hs[2 * i - 2], out + off[2 * i]);
+    orc_twothirds(img, W, H, out + off[1]);
+    for (int i = 1; i < O; ++i) halve(out + off[2 * i - 1], ws[2 * i - 1], hs[2 * i - 1], out + off[2 * i + 1]);
+    return 0;
+}
+
+static long floor_div(long a, long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+/* L3: the pixels x' of a layer with pixel size S2 whose footprints meet
+ * that of pixel x of pixel size S1: x' S2 <= (x+1) S1 and (x'+1) S2 >= x S1 */
+int orc_layer_range(int S1, int S2, int x, int* lo, int* hi)
+{
+    *lo = (int)(-floor_div(-(long)x * S1, S2)) - 1;   /* ceil(x S1 / S2) - 1 */
+    *hi = (int)floor_div((long)(x + 1) * S1, S2);
+    return 0;
+}
+
+int orc_detect_layers(const uint8_t* img, int W, int H, int t, int O, orc_kp* out, int cap)
+{
+    int ws[64], hs[64], S[64];
+    if (O < 1 || O > 16 || W < 1 || H < 1) return -2;
+    const int L = 2 * O;
+    long total = orc_layer_dims(W, H, O, ws, hs, S);
+    uint8_t* lay = (uint8_t*)malloc((size_t)total + 1);
+    uint16_t* V = (uint16_t*)malloc(((size_t)total + 1) * sizeof(uint16_t));
+    long off[65];
+    off[0] = 0;
+    for (int l = 0; l < L; ++l) off[l + 1] = off[l] + (long)ws[l] * hs[l];
+    orc_layers(img, W, H, O, lay);
+    for (int l = 0; l < L; ++l) orc_score_level(lay + off[l], ws[l], hs[l], t, V + off[l]);
+    int n = 0;
+    for (int l = 0; l < L; ++l)
+        for (int y = 0; y < hs[l]; ++y)
+            for (int x = 0; x < ws[l]; ++x) {
+                const int v = V[off[l] + (long)y * ws[l] + x];
+                if (v == 0) continue;
+                int keep = 1;
+                for (int m = l - 1; m <= l + 1 && keep; ++m) {
+                    if (m < 0 || m >= L) continue;
+                    int x0, x1, y0, y1;
+                    orc_layer_range(S[l], S[m], x, &x0, &x1);
+                    orc_layer_range(S[l], S[m], y, &y0, &y1);
+                    for (int qy = y0; qy <= y1 && keep; ++qy)
+                        for (int qx = x0; qx <= x1 && keep; ++qx) {
+                            if (qx < 0 || qy < 0 || qx >= ws[m] || qy >= hs[m]) continue;
+                            if (m == l && qx == x && qy == y) continue;
+                            if (beats(V[off[m] + (long)qy * ws[m] + qx], m, qy, qx, v, l, y, x)) keep = 0;
+                        }
+                }
+                if (!keep) continue;
+                if (n >= cap) { free(lay); free(V); return -1; }
+                out[n].x = x;
+                out[n].y = y;
+                out[n].octave = l;
+                out[n].score = v;
+                ++n;
+            }
+    free(lay);
+    free(V);
+    return n;
 }

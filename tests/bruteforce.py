@@ -376,3 +376,64 @@ def track_step(prev: np.ndarray, cur: np.ndarray, tracks, t_bm: int, t_et: int):
         if f[0] < t_bm:
             out.append((f[1], f[2], o, sc, f[0]))
     return out
+
+
+# ------------------------------------------------ intra-octave layers
+
+def twothirds(img: np.ndarray) -> np.ndarray:
+    """1.5x downsampling: every whole 3x3 block to a 2x2 block, each output
+    the rounded mean over the 1.5 x 1.5 area it covers."""
+    h, w = img.shape
+    bh, bw = h // 3, w // 3
+    blocks = img[:3 * bh, :3 * bw].astype(np.int64).reshape(bh, 3, bw, 3)
+    wt = np.array([[2, 1, 0], [0, 1, 2]], np.int64)
+    s = np.einsum("qj,pi,bjai->bqap", wt, wt, blocks)
+    return ((s + 4) // 9).reshape(2 * bh, 2 * bw).astype(np.uint8)
+
+
+def layer_stack(img: np.ndarray, O: int):
+    """[(layer, pixel size in level-0 pixels)] in scale order c0, d0, c1, ..."""
+    from fractions import Fraction
+    cs = pyramid(img, O)
+    ds = [twothirds(img)]
+    for _ in range(1, O):
+        d = ds[-1]
+        h, w = d.shape[0] // 2, d.shape[1] // 2
+        q = d[:2 * h, :2 * w].astype(np.int64)
+        ds.append(((q[0::2, 0::2] + q[0::2, 1::2] + q[1::2, 0::2] + q[1::2, 1::2] + 2) >> 2).astype(np.uint8))
+    out = []
+    for i in range(O):
+        out.append((cs[i], Fraction(2 ** i)))
+        out.append((ds[i], Fraction(3, 2) * 2 ** i))
+    return out
+
+
+def detect_layers(img: np.ndarray, t: int, O: int):
+    """Detection over octaves and intra-octaves as tuples (x, y, layer, V) by
+    layer, y, x: neighbours on the same or adjacent layers are the pixels
+    whose closed level-0 footprints intersect."""
+    stack = layer_stack(img, O)
+    cands = {}
+    for l, (lv, s) in enumerate(stack):
+        h, w = lv.shape
+        for y in range(h):
+            for x in range(w):
+                v = score(lv, x, y, t)
+                if v > 0:
+                    cands[(l, x, y)] = v
+
+    def meet(p, q):
+        (lp, xp, yp), (lq, xq, yq) = p, q
+        if p == q or abs(lp - lq) > 1:
+            return False
+        sp, sq = stack[lp][1], stack[lq][1]
+        return (max(xp * sp, xq * sq) <= min((xp + 1) * sp, (xq + 1) * sq) and
+                max(yp * sp, yq * sq) <= min((yp + 1) * sp, (yq + 1) * sq))
+
+    out = []
+    for p, v in cands.items():
+        if not any(meet(p, q) and precedes((vq, q[0], q[2], q[1]), (v, p[0], p[2], p[1]))
+                   for q, vq in cands.items()):
+            out.append((p[1], p[2], p[0], v))
+    out.sort(key=lambda k: (k[2], k[1], k[0]))
+    return out

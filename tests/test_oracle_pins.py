@@ -899,3 +899,106 @@ def test_tcd_thresholds_are_strict():
         s = int(full["sad"])
         assert len(oracle.tcd_track(prev, cur, tr, s, sad0)) == 0
         assert len(oracle.tcd_track(prev, cur, tr, s + 1, sad0)) == 1
+
+
+# ------------------------------------------------ intra-octave layers
+
+def test_twothirds_closed_forms():
+    rng = np.random.default_rng(31)
+    img = rng.integers(0, 256, (61, 47)).astype(np.uint8)   # partial blocks dropped
+    np.testing.assert_array_equal(oracle.twothirds(img), bf.twothirds(img))
+    assert oracle.twothirds(img).shape == (40, 30)
+    for v in (0, 1, 128, 255):   # a constant stays constant
+        assert (oracle.twothirds(np.full((9, 12), v, np.uint8)) == v).all()
+    # one bright pixel per block position: its weight over 9 at each output
+    for j in range(3):
+        for i in range(3):
+            img = np.zeros((3, 3), np.uint8)
+            img[j, i] = 90
+            w = [[2, 1, 0], [0, 1, 2]]
+            exp = [[(90 * w[q][j] * w[p][i] + 4) // 9 for p in range(2)] for q in range(2)]
+            np.testing.assert_array_equal(oracle.twothirds(img), np.array(exp, np.uint8))
+    # columns c, c + 3, c + 6 (constant down each column): the outputs are
+    # the area means c + 1 and c + 5 exactly
+    img = np.tile(np.array([30, 33, 36, 60, 63, 66], np.uint8), (3, 1))
+    np.testing.assert_array_equal(oracle.twothirds(img), np.array([[31, 35, 61, 65]] * 2, np.uint8))
+
+
+def test_layers_and_their_sizes():
+    img = _smooth_random(5, 100, 131)
+    L = oracle.layers(img, 4)
+    ref = bf.layer_stack(img, 4)
+    assert len(L) == 8
+    for got, (exp, s) in zip(L, ref):
+        np.testing.assert_array_equal(got, exp)
+    dims = oracle.layer_dims(131, 100, 4)
+    # pixel sizes (half level-0 pixels): 2^(i+1) for octaves, 3 * 2^i between
+    assert [d[2] for d in dims] == [2, 3, 4, 6, 8, 12, 16, 24]
+    assert [(d[0], d[1]) for d in dims] == [(a.shape[1], a.shape[0]) for a in L]
+
+
+def test_layer_neighbourhood_between_octaves_is_r4():
+    # the footprint rule reproduces R4 between octaves: 4x4 finer, 2x2 coarser
+    for x in range(0, 40):
+        assert oracle.layer_range(4, 2, x) == (2 * x - 1, 2 * x + 2)
+        lo = min(X for X in range(-2, 40) if 2 * X - 1 <= x <= 2 * X + 2)
+        hi = max(X for X in range(-2, 40) if 2 * X - 1 <= x <= 2 * X + 2)
+        assert oracle.layer_range(2, 4, x) == (lo, hi)
+        assert oracle.layer_range(2, 2, x) == (x - 1, x + 1)
+        # octave <-> intra-octave: closed intervals [x s, (x+1) s] meet
+        for S1, S2 in ((2, 3), (3, 2), (3, 4), (4, 3), (6, 8), (12, 8)):
+            exp = [q for q in range(-3, 80) if max(x * S1, q * S2) <= min((x + 1) * S1, (q + 1) * S2)]
+            assert oracle.layer_range(S1, S2, x) == (exp[0], exp[-1])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_detect_layers_matches_bruteforce(seed):
+    rng = np.random.default_rng(300 + seed)
+    h, w = int(rng.integers(18, 40)), int(rng.integers(18, 40))
+    img = rng.choice(np.array([0, 60, 120, 200, 255], np.uint8), size=(h, w))
+    for O in (1, 2, 3):
+        for t in (10, 50):
+            assert kps_tuples(oracle.detect_layers(img, t, O)) == bf.detect_layers(img, t, O), (O, t)
+
+
+def test_detect_layers_matches_bruteforce_scene():
+    frames = _scene(seed=88, frames=1, w=64, h=52)
+    for O in (2, 3):
+        assert kps_tuples(oracle.detect_layers(frames[0], 12, O)) == bf.detect_layers(frames[0], 12, O)
+
+
+def test_detect_layers_invariants():
+    # on a scene at three octaves: keypoints on octave and intra-octave
+    # layers alike; a candidate is kept exactly when no neighbour (by the
+    # footprint rule) ranks above it, and no two keypoints are neighbours
+    img = _scene(seed=91, frames=1, w=160, h=120)[0]
+    t, O = 15, 3
+    kps = kps_tuples(oracle.detect_layers(img, t, O))
+    assert any(k[2] % 2 == 1 for k in kps) and any(k[2] % 2 == 0 for k in kps)
+    L = oracle.layers(img, O)
+    dims = oracle.layer_dims(160, 120, O)
+    V = [oracle.score_level(l, t).astype(np.int64) for l in L]
+    kept = {(k[2], k[0], k[1]) for k in kps}
+
+    def nbrs(l, x, y):
+        for m in (l - 1, l, l + 1):
+            if m < 0 or m >= len(L):
+                continue
+            x0, x1 = oracle.layer_range(dims[l][2], dims[m][2], x)
+            y0, y1 = oracle.layer_range(dims[l][2], dims[m][2], y)
+            for qy in range(max(y0, 0), min(y1, dims[m][1] - 1) + 1):
+                for qx in range(max(x0, 0), min(x1, dims[m][0] - 1) + 1):
+                    if (m, qx, qy) != (l, x, y):
+                        yield m, qx, qy
+
+    def ranks_above(q, p):
+        return (-V[q[0]][q[2], q[1]], q[0], q[2], q[1]) < (-V[p[0]][p[2], p[1]], p[0], p[2], p[1])
+
+    for l in range(len(L)):
+        ys, xs = np.nonzero(V[l])
+        for y, x in zip(ys.tolist(), xs.tolist()):
+            p = (l, x, y)
+            above = [q for q in nbrs(l, x, y) if ranks_above(q, p)]
+            assert (p in kept) == (len(above) == 0), p
+            if p in kept:
+                assert not any(q in kept for q in nbrs(l, x, y))
