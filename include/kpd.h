@@ -350,6 +350,41 @@ int kpd_profile(kpd_stream* s, int enable);
  * the number of launches (arrays of KPD_NKERNELS; either may be NULL). */
 int kpd_profile_read(kpd_stream* s, double* ms, uint64_t* launches);
 
+/* ------------------------------------------ octaves and intra-octaves */
+
+/* Full-frame detection of one frame over BRISK's scale space with the
+ * layers between the octaves (Sec. 2). Layers in scale order c_0, d_0,
+ * c_1, d_1, ..., c_{O-1}, d_{O-1} (layer index 2i for c_i, 2i+1 for d_i):
+ * c_i are the octaves of push_frame (2x2 means, round half up, sizes
+ * halved by floor); d_0 takes every whole 3x3 block of the frame to a 2x2
+ * block, output (2a+p, 2b+q) = (sum of w_p(i) w_q(j) I(3a+i, 3b+j) + 4) / 9
+ * with w_0 = (2,1,0), w_1 = (0,1,2) (the rounded mean over the 1.5 x 1.5
+ * area it covers; size floor(W/3)*2 x floor(H/3)*2); d_{i+1} halves d_i.
+ * A pixel of c_i spans 2^i level-0 pixels a side, one of d_i 1.5 * 2^i.
+ * Every layer is scored like the octaves (FAST-9/16 score, no candidates
+ * within 3 pixels of a layer's border). Two pixels of one layer, or of
+ * layers adjacent in the scale order, are neighbours when their closed
+ * level-0 footprints [x s, (x+1) s] x [y s, (y+1) s] intersect; between
+ * two octaves this is push_frame's neighbourhood. A pixel with score > 0 is
+ * a keypoint when no neighbour ranks above it (higher score, then the lower
+ * layer, then the smaller (y, x)).
+ *
+ * frame: device, `pitch_bytes` per row; workspace: device, 256-byte
+ * aligned, at least kpd_layers_bytes() bytes, used by one call at a time;
+ * out: device, `capacity` kpd_keypoint records in (layer, y, x) order, the
+ * `octave` field holding the layer index (entries past capacity are
+ * dropped); count: device uint32 receiving the keypoint total. All work is
+ * queued on `hip_stream`; nothing is read back. */
+size_t kpd_layers_bytes(int width, int height, int n_octaves);
+int kpd_detect_layers(const uint8_t* frame, size_t pitch_bytes, int width, int height, int fast_t, int n_octaves,
+                      void* workspace, size_t workspace_bytes, kpd_keypoint* out, uint32_t capacity, uint32_t* count,
+                      void* hip_stream);
+
+/* Where layer `layer` (1 .. 2 n_octaves - 1; layer 0 is the frame) lies in
+ * the workspace after kpd_detect_layers: byte offset, width and height,
+ * rows packed (pitch = width). */
+int kpd_layer_plane(int width, int height, int n_octaves, int layer, size_t* offset, int* w, int* h);
+
 /* ------------------------------------------ temporally coherent detector */
 
 /* The comparison system of Sec. 4: keypoints propagated from frame to frame

@@ -1,0 +1,54 @@
+// Geometry, kernel arguments and launchers of detection over octaves and
+// intra-octaves (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/kpd.h"
+
+namespace kpd {
+
+constexpr int kMaxLayers = 2 * KPD_MAX_OCTAVES;
+
+// The 2O layers in scale order c_0, d_0, c_1, d_1, ...: sizes, pixel sizes
+// in half level-0 pixels, where each plane lives in the workspace (layer 0
+// is the caller's frame) and where each layer's pixels start in the
+// flattened index space that the score, suppression and output passes
+// share.
+struct LayerGeom {
+    int L = 0;
+    int w[kMaxLayers] = {}, h[kMaxLayers] = {}, S[kMaxLayers] = {};
+    size_t plane_off[kMaxLayers] = {};
+    uint32_t base[kMaxLayers + 1] = {};
+    uint32_t N = 0;        // pixels of all layers
+    uint32_t nblocks = 0;  // blocks of the flattened passes
+    size_t off_score = 0, off_flag = 0, off_bcount = 0, off_boff = 0;
+    size_t total = 0;
+};
+
+constexpr int kLayBlock = 256;
+
+struct LayArgs {
+    const uint8_t* plane[kMaxLayers];
+    int pitch[kMaxLayers];
+    int w[kMaxLayers], h[kMaxLayers], S[kMaxLayers];
+    uint32_t base[kMaxLayers + 1];
+    int L, t;
+    uint32_t N;
+    uint16_t* score;
+    uint8_t* flag;
+    uint32_t* bcount;
+    uint32_t* boff;
+    uint32_t nblocks;
+    kpd_keypoint* out;
+    uint32_t cap;
+    uint32_t* count;
+};
+
+hipError_t launch_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
+hipError_t launch_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
+hipError_t launch_lay_detect(const LayArgs& a, hipStream_t s);
+
+}  // namespace kpd

@@ -1,0 +1,217 @@
+// Detection over octaves and intra-octaves (Sec. 2's scale space with the
+// layers between the octaves) for one frame: the layers, the FAST score of
+// every layer pixel, suppression among same-layer and adjacent-layer
+// pixels whose level-0 footprints meet, and the keypoints in (layer, y, x)
+// order by a block-count / scan / write pass over the flattened layers.
+#include <hip/hip_runtime.h>
+
+#include "kpd_layers.h"
+
+namespace kpd {
+namespace {
+
+__constant__ int8_t kLayRingDx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+__constant__ int8_t kLayRingDy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+
+// 2x2 blocks, round half up (the octaves' halving).
+__global__ __launch_bounds__(256) void k_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh)
+{
+    const int x = blockIdx.x * 16 + (threadIdx.x & 15), y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (x >= dw || y >= dh) return;
+    const uint8_t* p = src + (size_t)(2 * y) * spitch + 2 * x;
+    dst[(size_t)y * dw + x] = (uint8_t)((p[0] + p[1] + p[spitch] + p[spitch + 1] + 2) >> 2);
+}
+
+// Whole 3x3 blocks to 2x2 blocks: the output pixel (2a+p, 2b+q) is the
+// rounded mean over the 1.5 x 1.5 area it covers, weights (2, 1, 0) or
+// (0, 1, 2) along each axis, over 9.
+__global__ __launch_bounds__(256) void k_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh)
+{
+    const int X = blockIdx.x * 16 + (threadIdx.x & 15), Y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (X >= dw || Y >= dh) return;
+    const int a = X >> 1, p = X & 1, b = Y >> 1, q = Y & 1;
+    const uint8_t* s = src + (size_t)(3 * b) * spitch + 3 * a;
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int wy = q ? j : 2 - j;
+        const uint8_t* r = s + (size_t)j * spitch;
+        sum += wy * ((p ? 0 : 2) * r[0] + r[1] + (p ? 2 : 0) * r[2]);
+    }
+    dst[(size_t)Y * dw + X] = (uint8_t)((sum + 4) / 9);
+}
+
+__device__ __forceinline__ bool arc9(unsigned m)
+{
+    const unsigned d = m | (m << 16);
+    unsigned r = d & (d >> 1);
+    r &= r >> 2;
+    r &= r >> 4;
+    r &= d >> 8;
+    return (r & 0xFFFFu) != 0;
+}
+
+// FAST score of the pixel at P (0 for non-corners).
+__device__ int layer_score(const uint8_t* P, int pw, int t)
+{
+    const int p = P[0], hi = p + t, lo = p - t;
+    unsigned bm = 0, dm = 0;
+    int sb = 0, sd = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int c = P[kLayRingDy[k] * pw + kLayRingDx[k]];
+        if (c > hi) { bm |= 1u << k; sb += c - hi; }
+        if (c < lo) { dm |= 1u << k; sd += lo - c; }
+    }
+    if (!arc9(bm) && !arc9(dm)) return 0;
+    return max(sb, sd);
+}
+
+__device__ __forceinline__ int layer_of(const LayArgs& a, uint32_t i)
+{
+    int l = 0;
+    while (l + 1 < a.L && i >= a.base[l + 1]) ++l;
+    return l;
+}
+
+__global__ __launch_bounds__(kLayBlock) void k_lay_score(LayArgs a)
+{
+    const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
+    if (i >= a.N) return;
+    const int l = layer_of(a, i);
+    const uint32_t r = i - a.base[l];
+    const int w = a.w[l], h = a.h[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
+    int v = 0;
+    if (x >= 3 && y >= 3 && x < w - 3 && y < h - 3) v = layer_score(a.plane[l] + (size_t)y * a.pitch[l] + x, a.pitch[l], a.t);
+    a.score[i] = (uint16_t)v;
+}
+
+// A pixel with V > 0 is kept when no pixel of its own layer or an adjacent
+// one whose closed footprint meets its own ranks above it: higher V, then
+// the lower layer, then the smaller (y, x). The range of pixels x' of a
+// layer of pixel size S2 meeting pixel x of pixel size S1 is
+// ceil(x S1 / S2) - 1 .. floor((x + 1) S1 / S2).
+__global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
+{
+    __shared__ uint32_t s_cnt[kLayBlock / 64];
+    const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
+    bool keep = false;
+    if (i < a.N) {
+        const int v = a.score[i];
+        if (v > 0) {
+            const int l = layer_of(a, i);
+            const uint32_t r = i - a.base[l];
+            const int w = a.w[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
+            keep = true;
+            for (int m = max(l - 1, 0); m <= min(l + 1, a.L - 1) && keep; ++m) {
+                const int S1 = a.S[l], S2 = a.S[m], wm = a.w[m], hm = a.h[m];
+                const int x0 = max((x * S1 + S2 - 1) / S2 - 1, 0), x1 = min(((x + 1) * S1) / S2, wm - 1);
+                const int y0 = max((y * S1 + S2 - 1) / S2 - 1, 0), y1 = min(((y + 1) * S1) / S2, hm - 1);
+                const uint16_t* sc = a.score + a.base[m];
+                for (int qy = y0; qy <= y1 && keep; ++qy)
+                    for (int qx = x0; qx <= x1; ++qx) {
+                        const int vq = sc[(size_t)qy * wm + qx];
+                        const bool above = vq > v || (vq == v && (m < l || (m == l && (qy < y || (qy == y && qx < x)))));
+                        if (above) {
+                            keep = false;
+                            break;
+                        }
+                    }
+            }
+        }
+        a.flag[i] = keep ? 1 : 0;
+    }
+    const uint64_t b = __ballot(keep);
+    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = 0;
+        for (int k = 0; k < kLayBlock / 64; ++k) c += s_cnt[k];
+        a.bcount[blockIdx.x] = c;
+    }
+}
+
+// Exclusive prefix of the block counts (one workgroup) and the total.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_lay_scan(LayArgs a)
+{
+    __shared__ uint32_t s_wave[kScanBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < a.nblocks; base += kScanBlock) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t c = i < a.nblocks ? a.bcount[i] : 0;
+        uint32_t incl = c;   // inclusive prefix within the wave
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, round = 0;
+        for (int k = 0; k < kScanBlock / 64; ++k) {
+            before += k < wave ? s_wave[k] : 0;
+            round += s_wave[k];
+        }
+        if (i < a.nblocks) a.boff[i] = carry + before + incl - c;
+        carry += round;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *a.count = carry;
+}
+
+__global__ __launch_bounds__(kLayBlock) void k_lay_write(LayArgs a)
+{
+    __shared__ uint32_t s_cnt[kLayBlock / 64];
+    const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool f = i < a.N && a.flag[i] != 0;
+    const uint64_t b = __ballot(f);
+    if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (!f) return;
+    uint32_t pos = a.boff[blockIdx.x] + (uint32_t)__popcll(b & ((1ull << lane) - 1));
+    for (int k = 0; k < wave; ++k) pos += s_cnt[k];
+    if (pos >= a.cap) return;
+    const int l = layer_of(a, i);
+    const uint32_t r = i - a.base[l];
+    const int w = a.w[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
+    kpd_keypoint k;
+    k.x = (uint16_t)x;
+    k.y = (uint16_t)y;
+    k.octave = (uint8_t)l;
+    k.pad = 0;
+    k.score = a.score[i];
+    a.out[pos] = k;
+}
+
+}  // namespace
+
+hipError_t launch_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s)
+{
+    if (dw <= 0 || dh <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lay_half, dim3((dw + 15) / 16, (dh + 15) / 16), dim3(256), 0, s, src, spitch, dst, dw, dh);
+    return hipGetLastError();
+}
+
+hipError_t launch_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s)
+{
+    if (dw <= 0 || dh <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lay_twothirds, dim3((dw + 15) / 16, (dh + 15) / 16), dim3(256), 0, s, src, spitch, dst, dw,
+                       dh);
+    return hipGetLastError();
+}
+
+hipError_t launch_lay_detect(const LayArgs& a, hipStream_t s)
+{
+    if (a.nblocks > 0) {
+        hipLaunchKernelGGL(k_lay_score, dim3(a.nblocks), dim3(kLayBlock), 0, s, a);
+        hipLaunchKernelGGL(k_lay_nms, dim3(a.nblocks), dim3(kLayBlock), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_lay_scan, dim3(1), dim3(kScanBlock), 0, s, a);
+    if (a.nblocks > 0) hipLaunchKernelGGL(k_lay_write, dim3(a.nblocks), dim3(kLayBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace kpd

@@ -37,7 +37,8 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
             "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
-            "tcd_device_result", "tcd_reset", "tcd_close")
+            "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
+            "kpd_layer_plane")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
 TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2"),
                         ("sad", "<u4")])
@@ -102,6 +103,11 @@ def _load() -> ctypes.CDLL:
     L.set_mask_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.get_descriptors.argtypes = [P, P, sz, ctypes.POINTER(sz)]
     L.get_refined.argtypes = [P, P, sz, ctypes.POINTER(sz)]
+    L.kpd_layers_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.kpd_layers_bytes.restype = sz
+    L.kpd_detect_layers.argtypes = [P, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, u32, P, P]
+    L.kpd_layer_plane.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz),
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     TP = ctypes.POINTER(KpdTcdParams)
     L.tcd_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), TP]
     L.tcd_bytes.restype = sz
@@ -496,3 +502,65 @@ class Tcd:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------ octaves and intra-octaves
+
+def layers_bytes(width: int, height: int, n_octaves: int) -> int:
+    n = lib.kpd_layers_bytes(width, height, n_octaves)
+    if n == 0:
+        raise KpdError(KPD_EINVAL, lib.kpd_last_error().decode())
+    return n
+
+
+def layer_plane(width: int, height: int, n_octaves: int, layer: int) -> Tuple[int, int, int]:
+    """(byte offset in the workspace, width, height) of layer `layer` >= 1."""
+    off, w, h = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_int()
+    _check(lib.kpd_layer_plane(width, height, n_octaves, layer, ctypes.byref(off), ctypes.byref(w), ctypes.byref(h)))
+    return off.value, w.value, h.value
+
+
+class LayerDetector:
+    """Full-frame detection over octaves and intra-octaves (Sec. 2) for
+    frames of one size: owns the workspace, the output list and its count
+    on the device."""
+
+    def __init__(self, width: int, height: int, fast_t: int, n_octaves: int, capacity: int = 0,
+                 stream=None, device="cuda"):
+        self.width, self.height, self.fast_t, self.n_octaves = width, height, fast_t, n_octaves
+        self.workspace = torch.empty(layers_bytes(width, height, n_octaves), dtype=torch.uint8, device=device)
+        if capacity <= 0:   # at most one keypoint per 2 x 2 block of every layer
+            capacity = 16
+            for l in range(2 * n_octaves):
+                w = (width >> (l // 2)) if l % 2 == 0 else (((width // 3) * 2) >> (l // 2))
+                h = (height >> (l // 2)) if l % 2 == 0 else (((height // 3) * 2) >> (l // 2))
+                capacity += ((w + 1) // 2) * ((h + 1) // 2)
+        self.capacity = capacity
+        self.out = torch.empty(capacity * KEYPOINT_DTYPE.itemsize, dtype=torch.uint8, device=device)
+        self.count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.stream = stream
+
+    def detect_async(self, frame: torch.Tensor) -> None:
+        """Queue detection of a CUDA uint8 [H, W] frame (unit column stride)."""
+        if not (isinstance(frame, torch.Tensor) and frame.device.type == "cuda" and frame.dtype == torch.uint8
+                and frame.dim() == 2 and frame.stride(1) == 1
+                and tuple(frame.shape) == (self.height, self.width)):
+            raise ValueError("frame must be a CUDA uint8 [H, W] tensor with unit column stride")
+        _check(lib.kpd_detect_layers(frame.data_ptr(), frame.stride(0), self.width, self.height, self.fast_t,
+                                     self.n_octaves, self.workspace.data_ptr(), self.workspace.numel(),
+                                     self.out.data_ptr(), self.capacity, self.count.data_ptr(),
+                                     _stream_ptr(self.stream)))
+
+    def detect(self, frame) -> np.ndarray:
+        """Keypoints (KEYPOINT_DTYPE, `octave` = layer index) of one frame."""
+        if isinstance(frame, np.ndarray):
+            frame = torch.from_numpy(np.ascontiguousarray(frame)).cuda()
+        self.detect_async(frame)
+        n = min(int(self.count.item()), self.capacity)
+        raw = self.out[:n * KEYPOINT_DTYPE.itemsize].cpu().numpy()
+        return raw.view(KEYPOINT_DTYPE).copy()
+
+    def layer(self, l: int) -> np.ndarray:
+        """Layer l >= 1 of the last frame, as computed on the device."""
+        off, w, h = layer_plane(self.width, self.height, self.n_octaves, l)
+        return self.workspace[off:off + w * h].cpu().numpy().reshape(h, w)

@@ -183,3 +183,26 @@ def test_tcd_structs_and_sizes(kpd):
                 kpd.KpdTcdParams(10, 1800, -5, 0), kpd.KpdTcdParams(10, 1800, 1000, 1)):
         assert kpd.lib.tcd_bytes(640, 480, ctypes.byref(p), ctypes.byref(bad)) == 0
     assert kpd.lib.tcd_bytes(640, 480, ctypes.byref(kpd.make_params(20, 0, 16, 12)), ctypes.byref(tp)) == 0
+
+
+def test_layer_workspace_sizes(kpd):
+    # the workspace holds every layer past the frame, 2-byte scores and a
+    # flag per layer pixel, and two words per block of 256 layer pixels
+    import oracle
+    for W, H, O in ((640, 480, 4), (101, 77, 6), (1, 1, 1)):
+        dims = oracle.layer_dims(W, H, O)
+        N = sum(w * h for w, h, _ in dims)
+        n = kpd.layers_bytes(W, H, O)
+        assert n >= sum(w * h for w, h, _ in dims[1:]) + 3 * N + 8 * ((N + 255) // 256)
+        end = 0
+        for l in range(1, 2 * O):
+            off, w, h = kpd.layer_plane(W, H, O, l)
+            assert (w, h) == dims[l][:2] and off >= end and off % 256 == 0
+            end = off + w * h
+    assert kpd.lib.kpd_layers_bytes(640, 480, 0) == 0
+    assert kpd.lib.kpd_layers_bytes(640, 480, 9) == 0
+    assert kpd.lib.kpd_layers_bytes(0, 480, 4) == 0
+    with pytest.raises(kpd.KpdError):
+        kpd.layer_plane(640, 480, 4, 0)
+    with pytest.raises(kpd.KpdError):
+        kpd.layer_plane(640, 480, 4, 8)

@@ -1,0 +1,100 @@
+"""GPU parity of detection over octaves and intra-octaves (Sec. 2's scale
+space with the layers between the octaves): every layer and every keypoint
+(position, layer, score, order) against the oracle, exactly, on the three
+workload scenes, random images with few grey levels (every tie-break), odd
+and tiny sizes where some layers are empty, padded frames and a short
+output list."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06959_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kpd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_06959_amd import kpd as k
+    return k
+
+
+def tuples(arr):
+    return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
+
+
+def check(kpd, img, t, O, layers=True):
+    H, W = img.shape
+    det = kpd.LayerDetector(W, H, t, O)
+    got = det.detect(img)
+    exp = oracle.detect_layers(img, t, O)
+    assert tuples(got) == tuples(exp), (W, H, t, O, len(got), len(exp))
+    if layers:
+        ref = oracle.layers(img, O)
+        for l in range(1, 2 * O):
+            if ref[l].size:
+                np.testing.assert_array_equal(det.layer(l), ref[l], err_msg=f"layer {l}")
+    return len(got)
+
+
+@pytest.mark.parametrize("name", ["c1_320x240", "c2_640x480", "c3_1920x1080"])
+def test_workload_scenes(kpd, name):
+    d = synth.DETECTORS[name]
+    frames = synth.make_video(synth.SCENES[name], 2)
+    for f in frames:
+        assert check(kpd, f, d.fast_t, d.n_octaves) > 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_few_grey_levels(kpd, seed):
+    rng = np.random.default_rng(500 + seed)
+    h, w = int(rng.integers(20, 200)), int(rng.integers(20, 200))
+    img = rng.choice(np.array([0, 60, 120, 200, 255], np.uint8), size=(h, w))
+    for O in (1, 2, 4):
+        for t in (10, 50):
+            check(kpd, img, t, O)
+
+
+@pytest.mark.parametrize("W,H,O", [(1, 1, 1), (2, 5, 2), (7, 7, 3), (8, 9, 8), (37, 23, 5), (101, 77, 6),
+                                   (255, 17, 4), (640, 480, 8)])
+def test_shapes_and_depths(kpd, W, H, O):
+    sc = synth.Scene(max(W, 8), max(H, 8), 1, 6, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 600 + W)
+    img = np.ascontiguousarray(synth.make_video(sc)[0][:H, :W])
+    check(kpd, img, 12, O)
+
+
+def test_padded_frame_and_short_list(kpd):
+    import torch
+    img = synth.make_video(synth.SCENES["c2_640x480"], 1)[0]
+    wide = torch.zeros((480, 704), dtype=torch.uint8, device="cuda")
+    wide[:, :640] = torch.from_numpy(img).cuda()
+    det = kpd.LayerDetector(640, 480, 20, 4)
+    det.detect_async(wide[:, :640])
+    exp = tuples(oracle.detect_layers(img, 20, 4))
+    n = int(det.count.item())
+    got = det.out[:n * kpd.KEYPOINT_DTYPE.itemsize].cpu().numpy().view(kpd.KEYPOINT_DTYPE)
+    assert tuples(got) == exp
+    short = kpd.LayerDetector(640, 480, 20, 4, capacity=25)
+    short.detect_async(wide[:, :640])
+    assert int(short.count.item()) == len(exp)   # the count reports every keypoint
+    got = short.out[:25 * kpd.KEYPOINT_DTYPE.itemsize].cpu().numpy().view(kpd.KEYPOINT_DTYPE)
+    assert tuples(got) == exp[:25]
+
+
+def test_errors(kpd):
+    import ctypes
+    import torch
+    det = kpd.LayerDetector(64, 48, 20, 3)
+    f = torch.zeros((48, 64), dtype=torch.uint8, device="cuda")
+    L = kpd.lib
+    args = (f.data_ptr(), 64, 64, 48)
+    ws, out, cnt = det.workspace, det.out, det.count
+    assert L.kpd_detect_layers(*args, 0, 3, ws.data_ptr(), ws.numel(), out.data_ptr(), 10, cnt.data_ptr(), None) != 0
+    assert L.kpd_detect_layers(*args, 20, 9, ws.data_ptr(), ws.numel(), out.data_ptr(), 10, cnt.data_ptr(), None) != 0
+    assert L.kpd_detect_layers(*args, 20, 3, ws.data_ptr(), 100, out.data_ptr(), 10, cnt.data_ptr(), None) \
+        == kpd.KPD_ENOMEM
+    assert L.kpd_detect_layers(f.data_ptr(), 32, 64, 48, 20, 3, ws.data_ptr(), ws.numel(), out.data_ptr(), 10,
+                               cnt.data_ptr(), None) != 0   # pitch below the width
