@@ -349,6 +349,45 @@ def tcd_workload(kpd, wl: Workload, args) -> dict:
                     "T_BM=1800, T_ET=1000; one tcd_push per frame"}
 
 
+def intra_octave_workload(kpd, wl: Workload, args) -> dict:
+    """Full-frame detection over octaves and intra-octaves (Sec. 2's BRISK
+    scale space, 2O layers), one call per frame of the video, frames in
+    place; keypoints per frame on octave and intra-octave layers."""
+    import numpy as np
+    import torch
+    d = wl.det
+    det = kpd.LayerDetector(wl.W, wl.H, d.fast_t, d.n_octaves)
+
+    def one_pass():
+        for i in range(wl.F):
+            det.detect_async(wl.dev[i])
+
+    one_pass()
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_pass()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    one_pass()
+    e1.record()
+    torch.cuda.synchronize()
+    oct_kp, intra_kp = [], []
+    for i in range(0, wl.F, max(1, wl.F // 30)):
+        k = det.detect(wl.dev[i])
+        oct_kp.append(int((k["octave"] % 2 == 0).sum()))
+        intra_kp.append(int((k["octave"] % 2 == 1).sum()))
+    return {"value": round(wl.F * wl.W * wl.H / dt / 1e6, 2), "unit": "Mpixel/s", "frames_per_s": round(wl.F / dt, 1),
+            "gpu_us_per_frame": round(e0.elapsed_time(e1) * 1e3 / wl.F, 3),
+            "keypoints_per_frame": {"octave_layers": round(float(np.mean(oct_kp)), 1),
+                                    "intra_octave_layers": round(float(np.mean(intra_kp)), 1)},
+            "what": f"{wl.name}, full-frame detection over {2 * d.n_octaves} layers (octaves and intra-octaves), "
+                    f"one kpd_detect_layers call per frame ({2 * d.n_octaves + 3} launches)"}
+
+
 def layer_study(kpd, wl: Workload, args) -> dict:
     """The mask variants side by side on one workload (the paper tries every
     layer and keeps the top one since results are alike): per-frame push
@@ -956,6 +995,8 @@ def main():
         out[which] = feature_workload(kpd, wl, args, which)
     log("[bench] temporally coherent detector")
     out["tcd"] = tcd_workload(kpd, wl, args)
+    log("[bench] intra-octave layers")
+    out["intra_octaves"] = intra_octave_workload(kpd, wl, args)
     out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:
         del wl
