@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libkpd.so")
 SOURCES = [os.path.join(CSRC, "kpd_api.cpp"), os.path.join(CSRC, "kpd_kernels.hip"),
            os.path.join(CSRC, "kpd_tcd.cpp"), os.path.join(CSRC, "kpd_tcd.hip"),
            os.path.join(CSRC, "kpd_layers.cpp"), os.path.join(CSRC, "kpd_layers.hip")]
-HEADERS = [os.path.join(CSRC, "kpd_geom.h"), os.path.join(CSRC, "kpd_kernels.h"), os.path.join(CSRC, "kpd_tcd.h"),
+HEADERS = [os.path.join(CSRC, "kpd_geom.h"), os.path.join(CSRC, "kpd_kernels.h"), os.path.join(CSRC, "kpd_tcd.h"), os.path.join(CSRC, "kpd_errors.h"),
            os.path.join(CSRC, "kpd_layers.h"),
            os.path.join(os.path.dirname(HERE), "include", "kpd.h")]
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/kpd.h"
+#include "kpd_errors.h"
 #include "kpd_geom.h"
 #include "kpd_kernels.h"
 

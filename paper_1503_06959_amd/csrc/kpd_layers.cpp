@@ -7,8 +7,8 @@
 #include <string>
 
 #include "../../include/kpd.h"
+#include "kpd_errors.h"
 #include "kpd_layers.h"
-#include "kpd_tcd.h"   // api_fail, api_hip_fail
 
 namespace {
 

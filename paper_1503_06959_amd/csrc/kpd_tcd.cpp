@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/kpd.h"
+#include "kpd_errors.h"
 #include "kpd_tcd.h"
 
 namespace {

@@ -5,8 +5,6 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
-#include <string>
-
 #include "../../include/kpd.h"
 
 namespace kpd {
@@ -48,8 +46,5 @@ struct TcdCompactArgs {
 hipError_t launch_tcd_seed(const TcdSeedArgs& a, hipStream_t s);
 hipError_t launch_tcd_track(const TcdTrackArgs& a, hipStream_t s);
 hipError_t launch_tcd_compact(const TcdCompactArgs& a, hipStream_t s);
-
-int api_fail(int code, const std::string& msg);
-int api_hip_fail(hipError_t e, const char* what);
 
 }  // namespace kpd
