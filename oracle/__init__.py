@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
     L.orc_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
     L.orc_layer_range.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
     L.orc_detect_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int]
+    L.orc_refine_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
     L.orc_tcd_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.orc_tcd_spiral.argtypes = [ctypes.c_int, P, P]
     L.orc_tcd_track.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
@@ -372,3 +373,14 @@ def detect_layers(img: np.ndarray, t: int, O: int) -> np.ndarray:
     n = lib().orc_detect_layers(_ptr(img), W, H, t, O, _ptr(out), cap)
     assert n >= 0
     return out[:n].copy()
+
+
+def refine_layers(img: np.ndarray, t: int, O: int, kps: np.ndarray) -> np.ndarray:
+    """float32 [n, 4]: refined x, y (level-0 pixels), log2 scale and score of
+    keypoints of detect_layers (L4)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    kps = np.ascontiguousarray(kps, dtype=KP_DTYPE)
+    H, W = img.shape
+    out = np.zeros((max(len(kps), 1), 4), np.float32)
+    assert lib().orc_refine_layers(_ptr(img), W, H, t, O, _ptr(kps), len(kps), _ptr(out)) == 0
+    return out[:len(kps)].copy()

@@ -171,6 +171,22 @@
  *       the neighbourhood of R4. A pixel with V > 0 is a keypoint when no
  *       neighbour ranks above it (higher V, then the lower layer index, then
  *       the smaller (y, x)). Keypoints are listed by layer, then y, then x.
+ *   L4  Refinement on these layers (R17's fits, R18 generalised): for a
+ *       keypoint (x, y) on layer l, the layers l-1, l, l+1 are fitted at the
+ *       pixel that holds the keypoint's footprint centre, floor((2x+1) S_l /
+ *       (2 S_m)) (S in half level-0 pixels; between octaves this is R18's
+ *       (2x+1, 2y+1) and (x>>1, y>>1)). Layer m sits at log2 scale
+ *       sigma_m = m/2 for octaves, (m-1)/2 + log2(1.5) for intra-octaves
+ *       (log2(1.5) taken as the double nearest to it), extended the same way
+ *       to a missing layer, which has value 0 and the keypoint's position.
+ *       The parabola through (sigma_k, m_k) in Newton form, d1 = (m_1 -
+ *       m_0)/(sigma_1 - sigma_0), d2 likewise, a = (d2 - d1)/(sigma_2 -
+ *       sigma_0), has its vertex at sigma* = (sigma_0 + sigma_1)/2 -
+ *       d1/(2a) when a < 0, clamped to [sigma_0, sigma_2], else sigma_1; the
+ *       score is its value there and the position moves from the own
+ *       layer's maximum towards the coarser (sigma* > sigma_1) or finer one's
+ *       by the fraction of the way in sigma. Every step is a double
+ *       operation in a stated order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1194,4 +1210,76 @@ int orc_detect_layers(const uint8_t* img, int W, int H, int t, int O, orc_kp* ou
     free(lay);
     free(V);
     return n;
+}
+
+/* L4: refined (x, y) in level-0 pixels, log2 scale and score of the
+ * keypoint (x, y) of layer l; lay[m], ws[m], hs[m], S[m] describe the
+ * 2O layers */
+static const double ORC_LOG2_1P5 = 0.58496250072115618;
+
+static double layer_sigma(int m)
+{
+    /* m = -1 is the intra-octave below c_0, m = L the layer past the last */
+    return m % 2 == 0 ? (double)(m / 2) : (double)((m - 1) / 2) + ORC_LOG2_1P5;
+}
+
+void orc_refine_layer_kp(uint8_t* const* lay, const int* ws, const int* hs, const int* S, int L, int t, int x, int y,
+                         int l, float* out)
+{
+    double m[3] = {0.0, 0.0, 0.0}, X[3], Y[3], sg[3];
+    for (int k = 0; k < 3; ++k) {
+        const int ll = l - 1 + k;
+        sg[k] = layer_sigma(ll);
+        if (ll < 0 || ll >= L) continue;
+        const int cx = (int)(((long)(2 * x + 1) * S[l]) / (2L * S[ll]));
+        const int cy = (int)(((long)(2 * y + 1) * S[l]) / (2L * S[ll]));
+        double u, v;
+        fit_patch(lay[ll], ws[ll], hs[ll], t, cx, cy, &u, &v, &m[k]);
+        X[k] = (((double)cx + 0.5) + u) * ((double)S[ll] / 2.0);
+        Y[k] = (((double)cy + 0.5) + v) * ((double)S[ll] / 2.0);
+    }
+    if (l == 0) { X[0] = X[1]; Y[0] = Y[1]; }
+    if (l + 1 >= L) { X[2] = X[1]; Y[2] = Y[1]; }
+    const double d1 = (m[1] - m[0]) / (sg[1] - sg[0]);
+    const double d2 = (m[2] - m[1]) / (sg[2] - sg[1]);
+    const double a = (d2 - d1) / (sg[2] - sg[0]);
+    double sig = sg[1];
+    if (a < 0.0) {
+        sig = (sg[0] + sg[1]) / 2.0 - d1 / (2.0 * a);
+        if (sig > sg[2]) sig = sg[2];
+        if (sig < sg[0]) sig = sg[0];
+    }
+    const double score = (m[0] + d1 * (sig - sg[0])) + (a * (sig - sg[0])) * (sig - sg[1]);
+    double px, py;
+    if (sig >= sg[1]) {
+        const double f = (sig - sg[1]) / (sg[2] - sg[1]);
+        px = X[1] + f * (X[2] - X[1]);
+        py = Y[1] + f * (Y[2] - Y[1]);
+    } else {
+        const double f = (sg[1] - sig) / (sg[1] - sg[0]);
+        px = X[1] + f * (X[0] - X[1]);
+        py = Y[1] + f * (Y[0] - Y[1]);
+    }
+    out[0] = (float)px;
+    out[1] = (float)py;
+    out[2] = (float)sig;
+    out[3] = (float)score;
+}
+
+/* layers of img, then L4 for every keypoint of orc_detect_layers' list */
+int orc_refine_layers(const uint8_t* img, int W, int H, int t, int O, const orc_kp* kps, int n, float* out)
+{
+    int ws[64], hs[64], S[64];
+    if (O < 1 || O > 16) return -1;
+    const int L = 2 * O;
+    long total = orc_layer_dims(W, H, O, ws, hs, S);
+    uint8_t* buf = (uint8_t*)malloc((size_t)total + 1);
+    orc_layers(img, W, H, O, buf);
+    uint8_t* lay[64];
+    long off = 0;
+    for (int l = 0; l < L; ++l) { lay[l] = buf + off; off += (long)ws[l] * hs[l]; }
+    for (int i = 0; i < n; ++i)
+        orc_refine_layer_kp(lay, ws, hs, S, L, t, kps[i].x, kps[i].y, kps[i].octave, out + 4 * i);
+    free(buf);
+    return 0;
 }

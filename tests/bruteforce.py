@@ -437,3 +437,37 @@ def detect_layers(img: np.ndarray, t: int, O: int):
             out.append((p[1], p[2], p[0], v))
     out.sort(key=lambda k: (k[2], k[1], k[0]))
     return out
+
+
+def refine_layers(stack, t: int, x: int, y: int, l: int):
+    """Refinement on the layers of layer_stack: numpy least-squares fits at
+    the pixels holding the footprint centre on layers l-1, l, l+1, a
+    parabola (numpy.polyfit) through the fit values along log2 scale, its
+    clamped vertex, linear interpolation of the positions in log2 scale."""
+    import math
+    L = len(stack)
+
+    def sigma(m):
+        return m // 2 + (math.log2(1.5) if m % 2 else 0.0)
+
+    s_l = stack[l][1]
+    res = {}
+    for k, m in ((0, l - 1), (1, l), (2, l + 1)):
+        if 0 <= m < L:
+            s_m = stack[m][1]
+            cx, cy = int((x + 0.5) * s_l / s_m), int((y + 0.5) * s_l / s_m)
+            u, v, val = _fit(stack[m][0], t, cx, cy)
+            res[k] = (float((cx + 0.5 + u) * s_m), float((cy + 0.5 + v) * s_m), val)
+    own = res[1]
+    pts = [res.get(k, (own[0], own[1], 0.0)) for k in range(3)]
+    sg = [sigma(l - 1), sigma(l), sigma(l + 1)]
+    c2, c1, c0 = np.polyfit(sg, [p[2] for p in pts], 2)
+    s = sg[1]
+    if c2 < -1e-12:
+        s = float(np.clip(-c1 / (2 * c2), sg[0], sg[2]))
+    score_v = c2 * s * s + c1 * s + c0
+    if s >= sg[1]:
+        f, other = (s - sg[1]) / (sg[2] - sg[1]), pts[2]
+    else:
+        f, other = (sg[1] - s) / (sg[1] - sg[0]), pts[0]
+    return np.array([own[0] + f * (other[0] - own[0]), own[1] + f * (other[1] - own[1]), s, score_v])

@@ -1002,3 +1002,24 @@ def test_detect_layers_invariants():
             assert (p in kept) == (len(above) == 0), p
             if p in kept:
                 assert not any(q in kept for q in nbrs(l, x, y))
+
+
+@pytest.mark.parametrize("seed,h,w,O,t,noise", [(1, 60, 80, 2, 10, True), (2, 90, 70, 3, 15, False),
+                                                (3, 120, 160, 3, 12, False), (4, 64, 64, 4, 8, True)])
+def test_refine_layers_matches_bruteforce(seed, h, w, O, t, noise):
+    # the integer fits against numpy least squares and the Newton-form
+    # parabola against numpy.polyfit, on octave and intra-octave keypoints
+    img = _smooth_random(seed, h, w) if noise else _scene(seed=seed, frames=1, w=w, h=h)[0]
+    kps = oracle.detect_layers(img, t, O)
+    assert len(kps) > 5
+    got = oracle.refine_layers(img, t, O, kps)
+    stack = bf.layer_stack(img, O)
+    for k, g in zip(kps, got):
+        x, y, l = int(k["x"]), int(k["y"]), int(k["octave"])
+        exp = bf.refine_layers(stack, t, x, y, l)
+        np.testing.assert_allclose(g, exp, rtol=1e-6, atol=2e-4, err_msg=f"{x},{y},{l}")
+        # the scale stays between the neighbouring layers' scales
+        s_lo = (l - 1) // 2 + (np.log2(1.5) if (l - 1) % 2 else 0.0)
+        s_hi = (l + 1) // 2 + (np.log2(1.5) if (l + 1) % 2 else 0.0)
+        assert s_lo - 1e-6 <= g[2] <= s_hi + 1e-6
+    assert any(int(k["octave"]) % 2 for k in kps) and any(int(k["octave"]) % 2 == 0 for k in kps)
