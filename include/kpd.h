@@ -380,6 +380,31 @@ int kpd_detect_layers(const uint8_t* frame, size_t pitch_bytes, int width, int h
                       void* workspace, size_t workspace_bytes, kpd_keypoint* out, uint32_t capacity, uint32_t* count,
                       void* hip_stream);
 
+/* Refinement of keypoints on these layers (Sec. 2's sub-pixel and
+ * sub-scale interpolation over the layered scale space), from the score
+ * maps that the last kpd_detect_layers call left in `workspace`. For a
+ * keypoint (x, y) of layer l, layers l-1, l, l+1 are fitted as
+ * get_refined's layers are (3 x 3 scores, exact integer least squares,
+ * maximum clamped to a pixel) at the pixel holding the keypoint's footprint
+ * centre, floor((2x+1) S_l / (2 S_m)) with S the pixel size in half
+ * level-0 pixels. Layer m sits at log2 scale sigma_m = m/2 for octaves and
+ * (m-1)/2 + log2(1.5) for intra-octaves (log2(1.5) rounded to double; a
+ * missing layer below c_0 or past the last has value 0 and the keypoint's
+ * position). The parabola through the three values in Newton form, d1 =
+ * (m_1 - m_0)/(sigma_1 - sigma_0), d2 = (m_2 - m_1)/(sigma_2 - sigma_1),
+ * c = (d2 - d1)/(sigma_2 - sigma_0), has its vertex at (sigma_0 + sigma_1)/2
+ * - d1/(2c) when c < 0 (clamped to [sigma_0, sigma_2]), else sigma_1; the
+ * score is its value there, log2_scale the vertex, and x, y move from the
+ * own layer's maximum towards the coarser (vertex above sigma_1) or finer
+ * one's by the fraction of the way in log2 scale. IEEE double steps in a
+ * fixed order, rounded to float.
+ * list, count: device keypoints of the last detection and their device
+ * count (the out/count given to it); out: device, min(count, capacity)
+ * records written in list order. */
+int kpd_refine_layers(int width, int height, int n_octaves, void* workspace, size_t workspace_bytes,
+                      const kpd_keypoint* list, const uint32_t* count, uint32_t capacity, kpd_refined* out,
+                      void* hip_stream);
+
 /* Where layer `layer` (1 .. 2 n_octaves - 1; layer 0 is the frame) lies in
  * the workspace after kpd_detect_layers: byte offset, width and height,
  * rows packed (pitch = width). */

@@ -42,6 +42,7 @@
 #include <atomic>
 #include <type_traits>
 
+#include "kpd_fit.h"
 #include "kpd_geom.h"
 #include "kpd_kernels.h"
 
@@ -1224,45 +1225,6 @@ __device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8
 // maximum (clamped to a pixel; the centre when not concave) and the value
 // there; a parabola through the three values along log2 scale gives t. The
 // floating steps are IEEE double operations in a fixed order, none fused.
-struct Fit {
-    double u, v, m;
-};
-
-__device__ Fit fit_patch(const int* S)
-{
-#pragma clang fp contract(off)
-    long long sx[3], sy[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        sx[k] = (long long)S[3 * k] + S[3 * k + 1] + S[3 * k + 2];
-        sy[k] = (long long)S[k] + S[3 + k] + S[6 + k];
-    }
-    auto P = [&](int i, int j) -> long long { return S[3 * (i + 1) + (j + 1)]; };
-    const long long A = sx[2] - sx[0], B = sy[2] - sy[0];
-    const long long Cx = sx[2] + sx[0] - 2 * sx[1], Cy = sy[2] + sy[0] - 2 * sy[1];
-    const long long E = P(1, 1) - P(1, -1) - P(-1, 1) + P(-1, -1);
-    const long long K0 = 5 * P(0, 0) + 2 * (P(0, -1) + P(-1, 0) + P(1, 0) + P(0, 1)) -
-                         (P(-1, -1) + P(1, -1) + P(-1, 1) + P(1, 1));
-    const long long D = 16 * Cx * Cy - 9 * E * E;
-    long long U = 0, V = 0, Dn = 1;
-    if (D > 0 && Cx < 0) {
-        U = min(max(6 * E * B - 8 * Cy * A, -D), D);
-        V = min(max(6 * E * A - 8 * Cx * B, -D), D);
-        Dn = D;
-    }
-    Fit r;
-    r.u = (double)U / (double)Dn;
-    r.v = (double)V / (double)Dn;
-    double f = (double)K0 / 9.0;
-    f = f + ((double)A / 6.0) * r.u;
-    f = f + ((double)B / 6.0) * r.v;
-    f = f + (((double)Cx / 6.0) * r.u) * r.u;
-    f = f + (((double)E / 4.0) * r.u) * r.v;
-    f = f + (((double)Cy / 6.0) * r.v) * r.v;
-    r.m = f;
-    return r;
-}
-
 __device__ kpd_refined refine_feature(const int* S, int x, int y, int o, int O)
 {
 #pragma clang fp contract(off)

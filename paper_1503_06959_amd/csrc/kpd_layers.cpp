@@ -47,6 +47,28 @@ bool layer_geom(int W, int H, int O, kpd::LayerGeom* g, std::string* why)
     return true;
 }
 
+kpd::LayArgs layer_args(const kpd::LayerGeom& g, const uint8_t* frame, size_t pitch_bytes, uint8_t* ws)
+{
+    kpd::LayArgs a{};
+    a.L = g.L;
+    a.N = g.N;
+    for (int l = 0; l < g.L; ++l) {
+        a.plane[l] = l == 0 ? frame : ws + g.plane_off[l];
+        a.pitch[l] = l == 0 ? (int)pitch_bytes : g.w[l];
+        a.w[l] = g.w[l];
+        a.h[l] = g.h[l];
+        a.S[l] = g.S[l];
+        a.base[l] = g.base[l];
+    }
+    a.base[g.L] = g.base[g.L];
+    a.score = reinterpret_cast<uint16_t*>(ws + g.off_score);
+    a.flag = ws + g.off_flag;
+    a.bcount = reinterpret_cast<uint32_t*>(ws + g.off_bcount);
+    a.boff = reinterpret_cast<uint32_t*>(ws + g.off_boff);
+    a.nblocks = g.nblocks;
+    return a;
+}
+
 }  // namespace
 
 extern "C" {
@@ -90,24 +112,8 @@ int kpd_detect_layers(const uint8_t* frame, size_t pitch_bytes, int width, int h
                                              std::to_string(g.total));
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
-    kpd::LayArgs a{};
-    a.L = g.L;
+    kpd::LayArgs a = layer_args(g, frame, pitch_bytes, ws);
     a.t = fast_t;
-    a.N = g.N;
-    for (int l = 0; l < g.L; ++l) {
-        a.plane[l] = l == 0 ? frame : ws + g.plane_off[l];
-        a.pitch[l] = l == 0 ? (int)pitch_bytes : g.w[l];
-        a.w[l] = g.w[l];
-        a.h[l] = g.h[l];
-        a.S[l] = g.S[l];
-        a.base[l] = g.base[l];
-    }
-    a.base[g.L] = g.base[g.L];
-    a.score = reinterpret_cast<uint16_t*>(ws + g.off_score);
-    a.flag = ws + g.off_flag;
-    a.bcount = reinterpret_cast<uint32_t*>(ws + g.off_bcount);
-    a.boff = reinterpret_cast<uint32_t*>(ws + g.off_boff);
-    a.nblocks = g.nblocks;
     a.out = out;
     a.cap = capacity;
     a.count = count;
@@ -128,6 +134,23 @@ int kpd_detect_layers(const uint8_t* frame, size_t pitch_bytes, int width, int h
     }
     e = kpd::launch_lay_detect(a, s);
     if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_detect_layers");
+    return KPD_OK;
+}
+
+int kpd_refine_layers(int width, int height, int n_octaves, void* workspace, size_t workspace_bytes,
+                      const kpd_keypoint* list, const uint32_t* count, uint32_t capacity, kpd_refined* out,
+                      void* hip_stream)
+{
+    kpd::LayerGeom g;
+    std::string why;
+    if (!layer_geom(width, height, n_octaves, &g, &why)) return kpd::api_fail(KPD_EINVAL, why);
+    if (!workspace || !count || (capacity > 0 && (!list || !out))) return kpd::api_fail(KPD_EINVAL, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return kpd::api_fail(KPD_EINVAL, "workspace not 256-byte aligned");
+    if (workspace_bytes < g.total) return kpd::api_fail(KPD_ENOMEM, "workspace smaller than kpd_layers_bytes()");
+    // the frame is not read: the fits take the score maps of the last detection
+    const kpd::LayArgs a = layer_args(g, nullptr, (size_t)width, reinterpret_cast<uint8_t*>(workspace));
+    const hipError_t e = kpd::launch_lay_refine(a, list, count, capacity, out, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_refine_layers");
     return KPD_OK;
 }
 

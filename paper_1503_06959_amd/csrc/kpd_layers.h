@@ -50,5 +50,7 @@ struct LayArgs {
 hipError_t launch_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
 hipError_t launch_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
 hipError_t launch_lay_detect(const LayArgs& a, hipStream_t s);
+hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const uint32_t* count, uint32_t cap,
+                             kpd_refined* out, hipStream_t s);
 
 }  // namespace kpd

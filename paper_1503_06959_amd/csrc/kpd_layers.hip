@@ -5,6 +5,7 @@
 // order by a block-count / scan / write pass over the flattened layers.
 #include <hip/hip_runtime.h>
 
+#include "kpd_fit.h"
 #include "kpd_layers.h"
 
 namespace kpd {
@@ -186,7 +187,93 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_write(LayArgs a)
     a.out[pos] = k;
 }
 
+// Refinement of the keypoints on these layers: for a keypoint (x, y) of
+// layer l, the fits at the pixel holding its footprint centre on layers
+// l-1, l, l+1 (scores from the maps of the last detection; 0 outside a
+// layer), a parabola through the fit values at the layers' log2 scales in
+// Newton form with its vertex clamped between the outer two, the position
+// moved towards the coarser or finer layer's maximum by the fraction of the
+// way in log2 scale. One thread per keypoint; IEEE double steps in a fixed
+// order, none fused.
+constexpr double kLog2OneHalf = 0.58496250072115618;   // log2(1.5), the nearest double
+
+__device__ __forceinline__ double layer_sigma(int m)
+{
+    return m % 2 == 0 ? (double)(m / 2) : (double)((m - 1) / 2) + kLog2OneHalf;
+}
+
+__global__ __launch_bounds__(kLayBlock) void k_lay_refine(LayArgs a, const kpd_keypoint* list,
+                                                          const uint32_t* count, uint32_t cap, kpd_refined* out)
+{
+#pragma clang fp contract(off)
+    const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
+    if (i >= min(*count, cap)) return;
+    const kpd_keypoint kp = list[i];
+    const int x = kp.x, y = kp.y, l = kp.octave;
+    if (l >= a.L) {   // not a keypoint of these layers
+        out[i] = kpd_refined{0.0f, 0.0f, 0.0f, 0.0f};
+        return;
+    }
+    double m[3] = {0.0, 0.0, 0.0}, X[3] = {0.0, 0.0, 0.0}, Y[3] = {0.0, 0.0, 0.0}, sg[3];
+    for (int k = 0; k < 3; ++k) {
+        const int ll = l - 1 + k;
+        sg[k] = layer_sigma(ll);
+        if (ll < 0 || ll >= a.L) continue;
+        const int cx = (int)(((long long)(2 * x + 1) * a.S[l]) / (2LL * a.S[ll]));
+        const int cy = (int)(((long long)(2 * y + 1) * a.S[l]) / (2LL * a.S[ll]));
+        const int w = a.w[ll], h = a.h[ll];
+        const uint16_t* sc = a.score + a.base[ll];
+        int P[9];
+        for (int di = -1; di <= 1; ++di)
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int px = cx + di, py = cy + dj;
+                P[3 * (di + 1) + (dj + 1)] = (px >= 0 && py >= 0 && px < w && py < h) ? sc[(size_t)py * w + px] : 0;
+            }
+        const Fit f = fit_patch(P);
+        m[k] = f.m;
+        X[k] = (((double)cx + 0.5) + f.u) * ((double)a.S[ll] / 2.0);
+        Y[k] = (((double)cy + 0.5) + f.v) * ((double)a.S[ll] / 2.0);
+    }
+    if (l == 0) { X[0] = X[1]; Y[0] = Y[1]; }
+    if (l + 1 >= a.L) { X[2] = X[1]; Y[2] = Y[1]; }
+    const double d1 = (m[1] - m[0]) / (sg[1] - sg[0]);
+    const double d2 = (m[2] - m[1]) / (sg[2] - sg[1]);
+    const double c2 = (d2 - d1) / (sg[2] - sg[0]);
+    double sig = sg[1];
+    if (c2 < 0.0) {
+        sig = (sg[0] + sg[1]) / 2.0 - d1 / (2.0 * c2);
+        if (sig > sg[2]) sig = sg[2];
+        if (sig < sg[0]) sig = sg[0];
+    }
+    const double score = (m[0] + d1 * (sig - sg[0])) + (c2 * (sig - sg[0])) * (sig - sg[1]);
+    double px, py;
+    if (sig >= sg[1]) {
+        const double f = (sig - sg[1]) / (sg[2] - sg[1]);
+        px = X[1] + f * (X[2] - X[1]);
+        py = Y[1] + f * (Y[2] - Y[1]);
+    } else {
+        const double f = (sg[1] - sig) / (sg[1] - sg[0]);
+        px = X[1] + f * (X[0] - X[1]);
+        py = Y[1] + f * (Y[0] - Y[1]);
+    }
+    kpd_refined r;
+    r.x = (float)px;
+    r.y = (float)py;
+    r.log2_scale = (float)sig;
+    r.score = (float)score;
+    out[i] = r;
+}
+
 }  // namespace
+
+hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const uint32_t* count, uint32_t cap,
+                             kpd_refined* out, hipStream_t s)
+{
+    if (cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lay_refine, dim3((cap + kLayBlock - 1) / kLayBlock), dim3(kLayBlock), 0, s, a, list, count,
+                       cap, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s)
 {

@@ -38,7 +38,7 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
             "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
             "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
-            "kpd_layer_plane")
+            "kpd_layer_plane", "kpd_refine_layers")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
 TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2"),
                         ("sad", "<u4")])
@@ -106,6 +106,7 @@ def _load() -> ctypes.CDLL:
     L.kpd_layers_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.kpd_layers_bytes.restype = sz
     L.kpd_detect_layers.argtypes = [P, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, u32, P, P]
+    L.kpd_refine_layers.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, P, u32, P, P]
     L.kpd_layer_plane.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz),
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     TP = ctypes.POINTER(KpdTcdParams)
@@ -559,6 +560,18 @@ class LayerDetector:
         n = min(int(self.count.item()), self.capacity)
         raw = self.out[:n * KEYPOINT_DTYPE.itemsize].cpu().numpy()
         return raw.view(KEYPOINT_DTYPE).copy()
+
+    def refine(self) -> np.ndarray:
+        """Refined values (REFINED_DTYPE) of the last detection's keypoints,
+        in their order."""
+        if not hasattr(self, "refined_dev"):
+            self.refined_dev = torch.empty(self.capacity * REFINED_DTYPE.itemsize, dtype=torch.uint8,
+                                           device=self.out.device)
+        _check(lib.kpd_refine_layers(self.width, self.height, self.n_octaves, self.workspace.data_ptr(),
+                                     self.workspace.numel(), self.out.data_ptr(), self.count.data_ptr(),
+                                     self.capacity, self.refined_dev.data_ptr(), _stream_ptr(self.stream)))
+        n = min(int(self.count.item()), self.capacity)
+        return self.refined_dev[:n * REFINED_DTYPE.itemsize].cpu().numpy().view(REFINED_DTYPE).copy()
 
     def layer(self, l: int) -> np.ndarray:
         """Layer l >= 1 of the last frame, as computed on the device."""

@@ -98,3 +98,38 @@ def test_errors(kpd):
         == kpd.KPD_ENOMEM
     assert L.kpd_detect_layers(f.data_ptr(), 32, 64, 48, 20, 3, ws.data_ptr(), ws.numel(), out.data_ptr(), 10,
                                cnt.data_ptr(), None) != 0   # pitch below the width
+
+
+def check_refined(kpd, img, t, O):
+    H, W = img.shape
+    det = kpd.LayerDetector(W, H, t, O)
+    kps = det.detect(img)
+    got = det.refine()
+    exp = oracle.refine_layers(img, t, O, oracle.detect_layers(img, t, O))
+    assert len(got) == len(exp) == len(kps)
+    g = np.stack([got["x"], got["y"], got["log2_scale"], got["score"]], axis=1).astype(np.float32)
+    bad = np.nonzero((g.view(np.uint32) != exp.view(np.uint32)).any(axis=1))[0]
+    assert len(bad) == 0, (f"{len(bad)} of {len(g)} differ, first {tuples(kps[bad[:1]])}: gpu {g[bad[0]]} "
+                           f"oracle {exp[bad[0]]}")
+    return len(g)
+
+
+@pytest.mark.parametrize("name", ["c1_320x240", "c2_640x480", "c3_1920x1080"])
+def test_refined_workload_scenes(kpd, name):
+    d = synth.DETECTORS[name]
+    f = synth.make_video(synth.SCENES[name], 1)[0]
+    assert check_refined(kpd, f, d.fast_t, d.n_octaves) > 0
+
+
+@pytest.mark.parametrize("W,H,O,t", [(37, 23, 5, 10), (101, 77, 6, 12), (160, 120, 1, 15), (255, 17, 4, 8),
+                                     (640, 480, 8, 20)])
+def test_refined_shapes(kpd, W, H, O, t):
+    sc = synth.Scene(max(W, 8), max(H, 8), 1, 6, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 700 + W)
+    img = np.ascontiguousarray(synth.make_video(sc)[0][:H, :W])
+    check_refined(kpd, img, t, O)
+
+
+def test_refined_random(kpd):
+    rng = np.random.default_rng(77)
+    img = rng.integers(0, 256, (90, 120)).astype(np.uint8)
+    assert check_refined(kpd, img, 25, 3) > 0
