@@ -380,12 +380,25 @@ def intra_octave_workload(kpd, wl: Workload, args) -> dict:
         k = det.detect(wl.dev[i])
         oct_kp.append(int((k["octave"] % 2 == 0).sum()))
         intra_kp.append(int((k["octave"] % 2 == 1).sum()))
+    # detection followed by refinement of every keypoint, frame by frame
+    det.refine()
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record()
+    for i in range(wl.F):
+        det.detect_async(wl.dev[i])
+        kpd._check(kpd.lib.kpd_refine_layers(det.width, det.height, det.n_octaves, det.workspace.data_ptr(),
+                                             det.workspace.numel(), det.out.data_ptr(), det.count.data_ptr(),
+                                             det.capacity, det.refined_dev.data_ptr(), kpd._stream_ptr(None)))
+    r1.record()
+    torch.cuda.synchronize()
     return {"value": round(wl.F * wl.W * wl.H / dt / 1e6, 2), "unit": "Mpixel/s", "frames_per_s": round(wl.F / dt, 1),
             "gpu_us_per_frame": round(e0.elapsed_time(e1) * 1e3 / wl.F, 3),
+            "gpu_us_per_frame_with_refinement": round(r0.elapsed_time(r1) * 1e3 / wl.F, 3),
             "keypoints_per_frame": {"octave_layers": round(float(np.mean(oct_kp)), 1),
                                     "intra_octave_layers": round(float(np.mean(intra_kp)), 1)},
             "what": f"{wl.name}, full-frame detection over {2 * d.n_octaves} layers (octaves and intra-octaves), "
-                    f"one kpd_detect_layers call per frame ({2 * d.n_octaves + 3} launches)"}
+                    f"one kpd_detect_layers call per frame ({2 * d.n_octaves + 3} launches); with refinement, "
+                    "one kpd_refine_layers call after it"}
 
 
 def layer_study(kpd, wl: Workload, args) -> dict:
