@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
     L.orc_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
     L.orc_layer_range.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
     L.orc_detect_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int]
+    L.orc_set_layers.argtypes = [P, ctypes.c_int]
     L.orc_refine_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
     L.orc_tcd_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.orc_tcd_spiral.argtypes = [ctypes.c_int, P, P]
@@ -225,6 +226,10 @@ class Stream:
     def set_descriptors(self, on: bool = True):
         """Keep a descriptor with every feature of D_n (R13-R16)."""
         lib().orc_set_descriptors(self.h, 1 if on else 0)
+
+    def set_layers(self, on: bool = True):
+        """Detect over octaves and intra-octaves (L5) from the next frame on."""
+        assert lib().orc_set_layers(self.h, 1 if on else 0) == 0
 
     def set_refine(self, on: bool = True):
         """Keep the refined position, log2 scale and score with every feature of D_n (R17-R19)."""

@@ -187,6 +187,13 @@
  *       layer's maximum towards the coarser (sigma* > sigma_1) or finer one's
  *       by the fraction of the way in sigma. Every step is a double
  *       operation in a stated order.
+ *   L5  The stream over these layers (orc_set_layers): the mask is R7's and
+ *       Eq. (1) is R8's with F(I_n) the detection of L1-L3; a keypoint of
+ *       layer l at (x, y) lies in the cell of its level-0 footprint start
+ *       (floor(x S_l / 2), floor(y S_l / 2)), S_l in half pixels (R6 for
+ *       the octaves), for the mask's histogram, for Eq. (1) and for the
+ *       order (cell, layer, y, x). Switching it marks every cell of the
+ *       next frame; it runs with the per-cell mask only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -605,6 +612,7 @@ typedef struct {
     uint8_t* mask;       /* M_n per cell */
     int desc_on;         /* R13-R16: descriptors kept with D_n */
     int ref_on;          /* R17-R19: refined position, scale and score kept with D_n */
+    int layers_on;       /* L5: detection over octaves and intra-octaves */
     float* ref;          /* 4 floats per feature of D_n */
     uint64_t* desc;      /* 8 words per feature of D_n */
     int32_t* bin;        /* orientation sector per feature of D_n */
@@ -660,6 +668,17 @@ int orc_set_id_mode(orc_stream* s, int mode, int layer)
 /* Keep a descriptor with every feature of D_n (R13-R16) from the next frame
  * on; switching on re-detects every cell once, so that every feature has
  * one. */
+/* L5: detection over octaves and intra-octaves from the next frame on
+ * (per-cell mask, no descriptors or refinement); a change marks every
+ * cell of the next frame */
+int orc_set_layers(orc_stream* s, int on)
+{
+    if (on && (s->desc_on || s->ref_on || s->id_mode != 0)) return -1;
+    if ((on != 0) != s->layers_on) s->force_all = 1;
+    s->layers_on = on != 0;
+    return 0;
+}
+
 int orc_set_descriptors(orc_stream* s, int on)
 {
     if (on && !s->desc_on) {
@@ -709,14 +728,26 @@ int orc_reset(orc_stream* s)
     return 0;
 }
 
-static int kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr;
+static int kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr, kp_cmp_ctx_layers;
+
+/* Cell of a keypoint: R6, or with layers (L5) the cell of its level-0
+ * footprint start, floor(x S_l / 2) with S_l in half pixels */
+static int kp_cell(int layers, const orc_kp* k, int W, int H, int Nc, int Nr)
+{
+    if (!layers) return orc_cell_of(k->x, k->y, k->octave, W, H, Nc, Nr);
+    const int l = k->octave, S = l % 2 == 0 ? (2 << (l / 2)) : (3 << (l / 2));
+    const int X = (int)(((long)k->x * S) / 2), Y = (int)(((long)k->y * S) / 2);
+    return cell_row(Y, H, Nr) * Nc + cell_col(X, W, Nc);
+}
+
+int orc_detect_layers(const uint8_t* img, int W, int H, int t, int O, orc_kp* out, int cap);
 
 static int kp_cmp(const void* a, const void* b)
 {
     const orc_kp* p = (const orc_kp*)a;
     const orc_kp* q = (const orc_kp*)b;
-    int cp = orc_cell_of(p->x, p->y, p->octave, kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr);
-    int cq = orc_cell_of(q->x, q->y, q->octave, kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr);
+    int cp = kp_cell(kp_cmp_ctx_layers, p, kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr);
+    int cq = kp_cell(kp_cmp_ctx_layers, q, kp_cmp_ctx_W, kp_cmp_ctx_H, kp_cmp_ctx_Nc, kp_cmp_ctx_Nr);
     if (cp != cq) return cp < cq ? -1 : 1;
     if (p->octave != q->octave) return p->octave < q->octave ? -1 : 1;
     if (p->y != q->y) return p->y < q->y ? -1 : 1;
@@ -800,7 +831,7 @@ int orc_push(orc_stream* s, const uint8_t* frame)
             }
         /* Eq. (3): histogram of the previous feature set over the bins */
         for (int i = 0; i < s->nK; ++i)
-            hist[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)] += 1;
+            hist[kp_cell(s->layers_on, &s->K[i], W, H, Nc, Nr)] += 1;
         for (int c = 0; c < ncell; ++c) {
             int id = s->sad[c] > (int64_t)s->TI * area[c];   /* Eq. (2), R7 */
             int kb = hist[c] >= s->TH;                         /* Eq. (4) */
@@ -818,7 +849,8 @@ int orc_push(orc_stream* s, const uint8_t* frame)
 
     /* full-frame detection of I_n */
     orc_kp* F = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)s->capK);
-    int nF = orc_detect(frame, W, H, s->t, s->O, F, s->capK);
+    int nF = s->layers_on ? orc_detect_layers(frame, W, H, s->t, s->O, F, s->capK)
+                          : orc_detect(frame, W, H, s->t, s->O, F, s->capK);
     if (nF < 0) { free(F); return -1; }
 
     /* Eq. (1): new features where the mask is 1, previous ones elsewhere;
@@ -838,7 +870,7 @@ int orc_push(orc_stream* s, const uint8_t* frame)
     int nD = 0;
     for (int i = 0; i < nF; ++i) {
         const int keep = per_pixel ? pixel_mask(s, pix, lw, lh, &F[i])
-                                   : s->mask[orc_cell_of(F[i].x, F[i].y, F[i].octave, W, H, Nc, Nr)] != 0;
+                                   : s->mask[kp_cell(s->layers_on, &F[i], W, H, Nc, Nr)] != 0;
         if (!keep) continue;
         D[nD].k = F[i];
         if (s->desc_on) {
@@ -848,9 +880,11 @@ int orc_push(orc_stream* s, const uint8_t* frame)
         if (s->ref_on) orc_refine_kp(lvp, dws, dhs, s->O, s->t, F[i].x, F[i].y, F[i].octave, D[nD].ref);
         ++nD;
     }
-    for (int i = 0; i < s->nK; ++i) {
+    /* a forced frame marks every cell and carries nothing (D_{n-1} may come
+     * from another scale space after a switch, L5) */
+    for (int i = 0; i < (s->force_all ? 0 : s->nK); ++i) {
         const int keep = per_pixel ? !pixel_mask(s, pix, lw, lh, &s->K[i])
-                                   : !s->mask[orc_cell_of(s->K[i].x, s->K[i].y, s->K[i].octave, W, H, Nc, Nr)];
+                                   : !s->mask[kp_cell(s->layers_on, &s->K[i], W, H, Nc, Nr)];
         if (!keep) continue;
         D[nD].k = s->K[i];
         if (s->desc_on) {
@@ -874,7 +908,7 @@ int orc_push(orc_stream* s, const uint8_t* frame)
             free(pix[l]);
         }
     }
-    kp_cmp_ctx_W = W; kp_cmp_ctx_H = H; kp_cmp_ctx_Nc = Nc; kp_cmp_ctx_Nr = Nr;
+    kp_cmp_ctx_W = W; kp_cmp_ctx_H = H; kp_cmp_ctx_Nc = Nc; kp_cmp_ctx_Nr = Nr; kp_cmp_ctx_layers = s->layers_on;
     qsort(D, (size_t)nD, sizeof(orc_feat), feat_cmp);
     if (nD > s->capK) { free(F); free(D); return -1; }
     for (int i = 0; i < nD; ++i) {
@@ -888,7 +922,7 @@ int orc_push(orc_stream* s, const uint8_t* frame)
     s->nK = nD;
     for (int c = 0; c < ncell; ++c) s->count[c] = 0;
     for (int i = 0; i < nD; ++i)
-        s->count[orc_cell_of(D[i].k.x, D[i].k.y, D[i].k.octave, W, H, Nc, Nr)] += 1;
+        s->count[kp_cell(s->layers_on, &D[i].k, W, H, Nc, Nr)] += 1;
     free(F);
     free(D);
 

@@ -471,3 +471,38 @@ def refine_layers(stack, t: int, x: int, y: int, l: int):
     else:
         f, other = (sg[1] - s) / (sg[1] - sg[0]), pts[0]
     return np.array([own[0] + f * (other[0] - own[0]), own[1] + f * (other[1] - own[1]), s, score_v])
+
+
+class LayerStream(Stream):
+    """Eq. (1) over the octave and intra-octave layers: the per-cell mask,
+    detection over the layers, a keypoint's cell from its level-0 footprint
+    start (layer pixel size times its coordinate, floored)."""
+
+    def _cell(self, k):
+        from fractions import Fraction
+        x, y, l = k[0], k[1], k[2]
+        s = Fraction(2 ** (l // 2)) * (Fraction(3, 2) if l % 2 else 1)
+        X, Y = int(x * s), int(y * s)
+        return (Y * self.Nr // self.H) * self.Nc + (X * self.Nc // self.W)
+
+    def push(self, frame: np.ndarray):
+        nc = self.Nc * self.Nr
+        if self.force:
+            mask = np.ones(nc, bool)
+        else:
+            diff = np.abs(frame.astype(np.int64) - self.prev.astype(np.int64))
+            sad = np.zeros(nc, np.int64)
+            np.add.at(sad, self.cells.ravel(), diff.ravel())
+            area = np.bincount(self.cells.ravel(), minlength=nc)
+            hist = np.zeros(nc, np.int64)
+            for k in self.K:
+                hist[self._cell(k)] += 1
+            mask = (sad > self.TI * area) | (hist >= self.TH)
+        F = detect_layers(frame, self.t, self.O)
+        new = [k for k in F if mask[self._cell(k)]] + [k for k in self.K if not mask[self._cell(k)]]
+        new.sort(key=lambda k: (self._cell(k), k[2], k[1], k[0]))
+        self.K = new
+        self.mask = mask.astype(np.uint8)
+        self.prev = frame.copy()
+        self.force = False
+        return new

@@ -1023,3 +1023,43 @@ def test_refine_layers_matches_bruteforce(seed, h, w, O, t, noise):
         s_hi = (l + 1) // 2 + (np.log2(1.5) if (l + 1) % 2 else 0.0)
         assert s_lo - 1e-6 <= g[2] <= s_hi + 1e-6
     assert any(int(k["octave"]) % 2 for k in kps) and any(int(k["octave"]) % 2 == 0 for k in kps)
+
+
+@pytest.mark.parametrize("TI,TH", [(8, KB_OFF), (3, KB_OFF), (255, 2), (6, 3), (-1, KB_OFF)])
+def test_layer_stream_matches_bruteforce(TI, TH):
+    # L5: the mask and Eq. 1 over octaves and intra-octaves, cells from the
+    # layers' footprints, against the brute-force stream
+    frames = _scene(seed=23, frames=4, w=72, h=54, move=0.8)
+    W, H, t, O, Nc, Nr = 72, 54, 15, 3, 5, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    s.set_layers(True)
+    b = bf.LayerStream(W, H, t, O, Nc, Nr, TI, TH)
+    for f in frames:
+        s.push(f)
+        exp = b.push(f)
+        kps, mask, _, cnt = s.get()
+        assert kps_tuples(kps) == exp
+        np.testing.assert_array_equal(mask, b.mask)
+        assert cnt.sum() == len(exp)
+    assert any(k[2] % 2 for k in exp)
+
+
+def test_layer_stream_carries_and_switches():
+    frames = _scene(seed=29, frames=3, w=96, h=72, move=0.8)
+    W, H, t, O, Nc, Nr = 96, 72, 15, 3, 6, 4
+    s = oracle.Stream(W, H, t, O, Nc, Nr, 6)
+    s.set_layers(True)
+    s.push(frames[0])
+    full = kps_tuples(s.get()[0])
+    assert sorted(full, key=lambda k: (k[2], k[1], k[0])) == kps_tuples(oracle.detect_layers(frames[0], t, O))
+    s.push(frames[0])                      # unchanged: nothing marked, D carried whole
+    k1, m1, _, _ = s.get()
+    assert kps_tuples(k1) == full and m1.sum() == 0
+    s.set_layers(False)                    # switching marks every cell once
+    s.push(frames[0])
+    k2, m2, _, _ = s.get()
+    assert m2.all()
+    assert sorted(kps_tuples(k2), key=lambda k: (k[2], k[1], k[0])) == kps_tuples(oracle.detect(frames[0], t, O))
+    s.set_descriptors(True)
+    with pytest.raises(AssertionError):
+        s.set_layers(True)                 # descriptors run over the octaves only
