@@ -405,6 +405,28 @@ int kpd_refine_layers(int width, int height, int n_octaves, void* workspace, siz
                       const kpd_keypoint* list, const uint32_t* count, uint32_t capacity, kpd_refined* out,
                       void* hip_stream);
 
+/* The masked stream over octaves and intra-octaves: push_frame's per-cell
+ * mask (the level-0 difference test against id_thresh, the count test of
+ * D_{n-1} against kb_thresh, every cell on the first frame and after
+ * kpd_lstream_reset) and Eq. 1, with F(I_n) the detection of
+ * kpd_detect_layers. A keypoint (x, y) of layer l lies in the cell of its
+ * level-0 footprint start (floor(x S_l / 2), floor(y S_l / 2)), S_l in half
+ * pixels (push_frame's rule for the octaves), for the count test, for Eq. 1
+ * and for D_n's order: cell, then layer, then y, then x. The `octave` field
+ * holds the layer index. Parameters used: fast_t, n_octaves, grid_cols,
+ * grid_rows, id_thresh, kb_thresh. Frames and flags as push_frame. */
+typedef struct kpd_lstream kpd_lstream;
+size_t kpd_lstream_bytes(int width, int height, const kpd_params* params);
+int kpd_lstream_open(int width, int height, const kpd_params* params, void* dev_arena, size_t arena_bytes,
+                     void* hip_stream, kpd_lstream** out);
+int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
+/* D_n and, when cell_mask is not NULL, M_n (one byte per cell); like
+ * get_keypoints (synchronises; KPD_ETRUNC copying nothing when D_n exceeds
+ * capacity). */
+int kpd_lstream_get(kpd_lstream* s, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask);
+int kpd_lstream_reset(kpd_lstream* s);
+int kpd_lstream_close(kpd_lstream* s);
+
 /* Where layer `layer` (1 .. 2 n_octaves - 1; layer 0 is the frame) lies in
  * the workspace after kpd_detect_layers: byte offset, width and height,
  * rows packed (pitch = width). */

@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/kpd.h"
 #include "kpd_errors.h"
@@ -69,9 +71,249 @@ kpd::LayArgs layer_args(const kpd::LayerGeom& g, const uint8_t* frame, size_t pi
     return a;
 }
 
+// Arena of the masked stream over the layers: the layer workspace, two
+// frame slots, the cell tables, the mask, and per-cell counts, offsets and
+// D lists that alternate between frames.
+struct LsLayout {
+    kpd::LayerGeom g;
+    int W = 0, H = 0, O = 0, nc = 0, nr = 0, ncell = 0;
+    int slot_pitch = 0;
+    size_t off_ws = 0, off_slot[2] = {0, 0}, off_xs = 0, off_ys = 0, off_mask = 0;
+    size_t off_cnt[2] = {0, 0}, off_off[2] = {0, 0}, off_list[2] = {0, 0}, off_total = 0;
+    uint32_t cap = 0;
+    size_t total = 0;
+};
+
+bool ls_layout(int W, int H, const kpd_params* p, LsLayout* L, std::string* why)
+{
+    if (!p) { *why = "params are NULL"; return false; }
+    if (!layer_geom(W, H, p->n_octaves, &L->g, why)) return false;
+    if (p->fast_t < 1 || p->fast_t > 254) { *why = "fast_t must be 1..254"; return false; }
+    if (p->grid_cols < 1 || p->grid_rows < 1 || p->grid_cols > W || p->grid_rows > H) {
+        *why = "grid must be 1..width x 1..height cells";
+        return false;
+    }
+    L->W = W; L->H = H; L->O = p->n_octaves; L->nc = p->grid_cols; L->nr = p->grid_rows;
+    L->ncell = L->nc * L->nr;
+    uint64_t cap = 16;
+    for (int l = 0; l < L->g.L; ++l) cap += (uint64_t)((L->g.w[l] + 1) / 2) * ((L->g.h[l] + 1) / 2);
+    L->cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFF0ull);
+    size_t off = 0;
+    L->off_ws = off; off = align_up(off + L->g.total);
+    L->slot_pitch = (W + 63) / 64 * 64;
+    for (int k = 0; k < 2; ++k) { L->off_slot[k] = off; off = align_up(off + (size_t)L->slot_pitch * H); }
+    L->off_xs = off; off = align_up(off + (size_t)L->g.L * (L->nc + 1) * 4);
+    L->off_ys = off; off = align_up(off + (size_t)L->g.L * (L->nr + 1) * 4);
+    L->off_mask = off; off = align_up(off + (size_t)L->ncell);
+    for (int k = 0; k < 2; ++k) {
+        L->off_cnt[k] = off;  off = align_up(off + (size_t)L->ncell * 4);
+        L->off_off[k] = off;  off = align_up(off + (size_t)L->ncell * 4);
+        L->off_list[k] = off; off = align_up(off + (size_t)L->cap * sizeof(kpd_keypoint));
+    }
+    L->off_total = off; off = align_up(off + 16);
+    L->total = off;
+    return true;
+}
+
+// For each layer, the first pixel column whose level-0 footprint start
+// floor(x S / 2) lies in cell column c or later, c = 0..nc (the last entry
+// is the layer's width); rows likewise. The cell column of level-0 column X
+// is floor(X nc / W).
+void ls_tables(const LsLayout& L, std::vector<uint32_t>* xs, std::vector<uint32_t>* ys)
+{
+    auto build = [](int n_layers, const int* len, const int* S, int extent, int cells, std::vector<uint32_t>* out) {
+        out->assign((size_t)n_layers * (cells + 1), 0);
+        for (int l = 0; l < n_layers; ++l) {
+            uint32_t* t = out->data() + (size_t)l * (cells + 1);
+            int c = 0;
+            for (int x = 0; x < len[l]; ++x) {
+                const long X0 = ((long)x * S[l]) / 2;
+                const int cx = (int)((X0 * cells) / extent);
+                while (c <= cx) t[c++] = (uint32_t)x;
+            }
+            while (c <= cells) t[c++] = (uint32_t)len[l];
+        }
+    };
+    build(L.g.L, L.g.w, L.g.S, L.W, L.nc, xs);
+    build(L.g.L, L.g.h, L.g.S, L.H, L.nr, ys);
+}
+
 }  // namespace
 
+struct kpd_lstream {
+    LsLayout L;
+    kpd_params p{};
+    hipStream_t stream = nullptr;
+    uint8_t* arena = nullptr;
+    std::vector<uint32_t> xs, ys;
+    bool force = true;
+    int fb = 0;              // buffer of the current D
+    int cur_slot = 0;
+    uint64_t n_pushed = 0;
+    const uint8_t* prev = nullptr;
+    int prev_pitch = 0;
+    bool closed = false;
+    template <class T> T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
+};
+
 extern "C" {
+
+size_t kpd_lstream_bytes(int width, int height, const kpd_params* params)
+{
+    LsLayout L;
+    std::string why;
+    if (!ls_layout(width, height, params, &L, &why)) {
+        kpd::api_fail(KPD_EINVAL, why);
+        return 0;
+    }
+    return L.total;
+}
+
+int kpd_lstream_open(int width, int height, const kpd_params* params, void* dev_arena, size_t arena_bytes,
+                     void* hip_stream, kpd_lstream** out)
+{
+    if (!out) return kpd::api_fail(KPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    LsLayout L;
+    std::string why;
+    if (!ls_layout(width, height, params, &L, &why)) return kpd::api_fail(KPD_EINVAL, why);
+    if (!dev_arena) return kpd::api_fail(KPD_EINVAL, "arena is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign) return kpd::api_fail(KPD_EINVAL, "arena not 256-byte aligned");
+    if (arena_bytes < L.total)
+        return kpd::api_fail(KPD_ENOMEM, "arena has " + std::to_string(arena_bytes) + " bytes, stream needs " +
+                                             std::to_string(L.total));
+    kpd_lstream* s = new (std::nothrow) kpd_lstream();
+    if (!s) return kpd::api_fail(KPD_ENOMEM, "host allocation failed");
+    s->L = L;
+    s->p = *params;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    s->arena = reinterpret_cast<uint8_t*>(dev_arena);
+    ls_tables(L, &s->xs, &s->ys);
+    hipError_t e = hipMemcpyAsync(s->at<uint32_t>(L.off_xs), s->xs.data(), s->xs.size() * 4, hipMemcpyHostToDevice,
+                                  s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->at<uint32_t>(L.off_ys), s->ys.data(), s->ys.size() * 4, hipMemcpyHostToDevice, s->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemsetAsync(s->at<uint32_t>(L.off_cnt[k]), 0, (size_t)L.ncell * 4, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->at<uint32_t>(L.off_total), 0, 16, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // the host tables are copied before they go
+    if (e != hipSuccess) {
+        delete s;
+        return kpd::api_hip_fail(e, "kpd_lstream_open");
+    }
+    *out = s;
+    return KPD_OK;
+}
+
+int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
+{
+    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    const LsLayout& L = s->L;
+    if (!frame) return kpd::api_fail(KPD_EINVAL, "frame is NULL");
+    if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return kpd::api_fail(KPD_EINVAL, "bad pitch");
+    if (flags != KPD_FRAME_HOST && flags != KPD_FRAME_DEVICE && flags != KPD_FRAME_DEVICE_RETAIN)
+        return kpd::api_fail(KPD_EINVAL, "bad flags");
+    const uint8_t* cur = frame;
+    int cur_pitch = (int)pitch_bytes;
+    if (flags != KPD_FRAME_DEVICE_RETAIN) {
+        uint8_t* dst = s->at<uint8_t>(L.off_slot[s->cur_slot]);
+        const hipMemcpyKind kind = flags == KPD_FRAME_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        hipError_t e = hipMemcpy2DAsync(dst, L.slot_pitch, frame, pitch_bytes, L.W, L.H, kind, s->stream);
+        if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_push");
+        cur = dst;
+        cur_pitch = L.slot_pitch;
+        s->cur_slot ^= 1;
+    }
+    const int fp = s->fb, fc = 1 - s->fb;
+    uint8_t* ws = s->at<uint8_t>(L.off_ws);
+    kpd::LayArgs la = layer_args(L.g, cur, (size_t)cur_pitch, ws);
+    la.t = s->p.fast_t;
+    kpd::LsArgs a{};
+    a.cur = cur;
+    a.prev = s->force ? cur : s->prev;
+    a.cur_pitch = cur_pitch;
+    a.prev_pitch = s->force ? cur_pitch : s->prev_pitch;
+    a.nc = L.nc;
+    a.nr = L.nr;
+    a.ncell = L.ncell;
+    a.force = s->force ? 1 : 0;
+    a.id_thresh = s->p.id_thresh;
+    a.kb_thresh = s->p.kb_thresh;
+    a.xs = s->at<uint32_t>(L.off_xs);
+    a.ys = s->at<uint32_t>(L.off_ys);
+    a.mask = s->at<uint8_t>(L.off_mask);
+    a.cnt_prev = s->at<uint32_t>(L.off_cnt[fp]);
+    a.off_prev = s->at<uint32_t>(L.off_off[fp]);
+    a.list_prev = s->at<kpd_keypoint>(L.off_list[fp]);
+    a.cnt_cur = s->at<uint32_t>(L.off_cnt[fc]);
+    a.off_cur = s->at<uint32_t>(L.off_off[fc]);
+    a.list_cur = s->at<kpd_keypoint>(L.off_list[fc]);
+    a.total_cur = s->at<uint32_t>(L.off_total) + fc;
+    a.cap = L.cap;
+    hipError_t e = kpd::launch_ls_mask(a, s->stream);
+    // the layers of I_n, as kpd_detect_layers builds them
+    auto plane = [&](int l) { return ws + L.g.plane_off[l]; };
+    for (int i = 1; i < L.O && e == hipSuccess; ++i) {
+        const int l = 2 * i, src = 2 * i - 2;
+        e = kpd::launch_lay_half(la.plane[src], la.pitch[src], plane(l), L.g.w[l], L.g.h[l], s->stream);
+    }
+    if (e == hipSuccess) e = kpd::launch_lay_twothirds(cur, cur_pitch, plane(1), L.g.w[1], L.g.h[1], s->stream);
+    for (int i = 1; i < L.O && e == hipSuccess; ++i) {
+        const int l = 2 * i + 1, src = 2 * i - 1;
+        e = kpd::launch_lay_half(plane(src), L.g.w[src], plane(l), L.g.w[l], L.g.h[l], s->stream);
+    }
+    if (e == hipSuccess) e = kpd::launch_lay_score_nms(la, s->stream);
+    if (e == hipSuccess) e = kpd::launch_ls_emit(a, la, s->stream);
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_push");
+    s->fb = fc;
+    s->prev = cur;
+    s->prev_pitch = cur_pitch;
+    s->force = false;
+    s->n_pushed += 1;
+    return KPD_OK;
+}
+
+int kpd_lstream_get(kpd_lstream* s, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask)
+{
+    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!count) return kpd::api_fail(KPD_EINVAL, "count is NULL");
+    if (s->n_pushed == 0) return kpd::api_fail(KPD_ESTATE, "no frame pushed yet");
+    const LsLayout& L = s->L;
+    uint32_t n = 0;
+    hipError_t e = hipMemcpyAsync(&n, s->at<uint32_t>(L.off_total) + s->fb, 4, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && cell_mask)
+        e = hipMemcpyAsync(cell_mask, s->at<uint8_t>(L.off_mask), (size_t)L.ncell, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_get");
+    n = std::min(n, L.cap);
+    *count = n;
+    if (n > capacity) return kpd::api_fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
+    if (n > 0) {
+        if (!out) return kpd::api_fail(KPD_EINVAL, "out is NULL");
+        e = hipMemcpyAsync(out, s->at<kpd_keypoint>(L.off_list[s->fb]), (size_t)n * sizeof(kpd_keypoint),
+                           hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_get");
+    }
+    return KPD_OK;
+}
+
+int kpd_lstream_reset(kpd_lstream* s)
+{
+    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    s->force = true;
+    return KPD_OK;
+}
+
+int kpd_lstream_close(kpd_lstream* s)
+{
+    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    const hipError_t e = hipStreamSynchronize(s->stream);
+    s->closed = true;
+    delete s;
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_close");
+    return KPD_OK;
+}
+
 
 size_t kpd_layers_bytes(int width, int height, int n_octaves)
 {

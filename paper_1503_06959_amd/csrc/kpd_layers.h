@@ -47,9 +47,39 @@ struct LayArgs {
     uint32_t* count;
 };
 
+// The masked stream over these layers: per-cell mask, Eq. 1 with cells
+// taken from the layers' footprints, D_n in (cell, layer, y, x) order.
+// xs[l * (nc + 1) + c] is the first pixel column of layer l whose footprint
+// start lies in cell column c or later (xs[.. + nc] = the layer's width);
+// ys likewise for rows.
+struct LsArgs {
+    const uint8_t* cur;
+    const uint8_t* prev;
+    int cur_pitch, prev_pitch;
+    int nc, nr, ncell;
+    int force;
+    int32_t id_thresh;
+    uint32_t kb_thresh;
+    const uint32_t* xs;
+    const uint32_t* ys;
+    uint8_t* mask;
+    const uint32_t* cnt_prev;
+    const uint32_t* off_prev;
+    const kpd_keypoint* list_prev;
+    uint32_t* cnt_cur;
+    uint32_t* off_cur;
+    kpd_keypoint* list_cur;
+    uint32_t* total_cur;
+    uint32_t cap;
+};
+
+hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s);
+hipError_t launch_ls_emit(const LsArgs& a, const LayArgs& l, hipStream_t s);
+
 hipError_t launch_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
 hipError_t launch_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
 hipError_t launch_lay_detect(const LayArgs& a, hipStream_t s);
+hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s);
 hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const uint32_t* count, uint32_t cap,
                              kpd_refined* out, hipStream_t s);
 

@@ -264,7 +264,166 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_refine(LayArgs a, const kpd_k
     out[i] = r;
 }
 
+// ---------------------------------------------------- the masked stream
+
+// Mask of one frame, one workgroup per cell: every cell on a forced frame;
+// otherwise the cell's summed |I_n - I_{n-1}| over its level-0 box against
+// T_I times its area, or its count in D_{n-1} against T_H.
+__global__ __launch_bounds__(256) void k_ls_mask(LsArgs a)
+{
+    __shared__ unsigned long long s_sum[4];
+    const int c = blockIdx.x, cc = c % a.nc, rr = c / a.nc;
+    if (a.force) {
+        if (threadIdx.x == 0) a.mask[c] = 1;
+        return;
+    }
+    const int x0 = (int)a.xs[cc], x1 = (int)a.xs[cc + 1], y0 = (int)a.ys[rr], y1 = (int)a.ys[rr + 1];
+    const int bw = x1 - x0, n = bw * (y1 - y0);
+    unsigned long long sum = 0;
+    for (int q = threadIdx.x; q < n; q += 256) {
+        const int y = y0 + q / bw, x = x0 + q % bw;
+        sum += (unsigned)abs((int)a.cur[(size_t)y * a.cur_pitch + x] - (int)a.prev[(size_t)y * a.prev_pitch + x]);
+    }
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        const bool id = (long long)t > (long long)a.id_thresh * (long long)n;
+        const bool kb = a.cnt_prev[c] >= a.kb_thresh;
+        a.mask[c] = (id || kb) ? 1 : 0;
+    }
+}
+
+// Per cell: a marked cell's new keypoints (the flagged pixels of its box on
+// every layer), an unmarked cell's count in D_{n-1}.
+__global__ __launch_bounds__(256) void k_ls_count(LsArgs a, LayArgs l)
+{
+    __shared__ uint32_t s_cnt[4];
+    const int c = blockIdx.x, cc = c % a.nc, rr = c / a.nc;
+    if (!a.mask[c]) {
+        if (threadIdx.x == 0) a.cnt_cur[c] = a.cnt_prev[c];
+        return;
+    }
+    uint32_t cnt = 0;
+    for (int m = 0; m < l.L; ++m) {
+        const int x0 = (int)a.xs[m * (a.nc + 1) + cc], x1 = (int)a.xs[m * (a.nc + 1) + cc + 1];
+        const int y0 = (int)a.ys[m * (a.nr + 1) + rr], y1 = (int)a.ys[m * (a.nr + 1) + rr + 1];
+        const int bw = x1 - x0, n = bw * (y1 - y0);
+        const uint8_t* fl = l.flag + l.base[m];
+        for (int q = threadIdx.x; q < n; q += 256) cnt += fl[(size_t)(y0 + q / bw) * l.w[m] + (x0 + q % bw)];
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) a.cnt_cur[c] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+}
+
+// Exclusive prefix of the per-cell counts (one workgroup) and D_n's size.
+__global__ __launch_bounds__(kScanBlock) void k_ls_scan(LsArgs a)
+{
+    __shared__ uint32_t s_wave[kScanBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < a.ncell; base += kScanBlock) {
+        const int i = base + threadIdx.x;
+        const uint32_t c = i < a.ncell ? a.cnt_cur[i] : 0;
+        uint32_t incl = c;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, round = 0;
+        for (int k = 0; k < kScanBlock / 64; ++k) {
+            before += k < wave ? s_wave[k] : 0;
+            round += s_wave[k];
+        }
+        if (i < a.ncell) a.off_cur[i] = carry + before + incl - c;
+        carry += round;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *a.total_cur = carry;
+}
+
+// D_n, one workgroup per cell: a marked cell emits the flagged pixels of
+// its boxes layer by layer in row-major order (ballot ranks, wave counts in
+// LDS), an unmarked cell copies its entries of D_{n-1}.
+__global__ __launch_bounds__(256) void k_ls_write(LsArgs a, LayArgs l)
+{
+    __shared__ uint32_t s_cnt[4];
+    const int c = blockIdx.x, cc = c % a.nc, rr = c / a.nc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t dst = a.off_cur[c];
+    if (!a.mask[c]) {
+        const uint32_t src = a.off_prev[c], n = a.cnt_prev[c];
+        for (uint32_t i = threadIdx.x; i < n; i += 256)
+            if (src + i < a.cap && dst + i < a.cap) a.list_cur[dst + i] = a.list_prev[src + i];
+        return;
+    }
+    uint32_t run = 0;
+    for (int m = 0; m < l.L; ++m) {
+        const int x0 = (int)a.xs[m * (a.nc + 1) + cc], x1 = (int)a.xs[m * (a.nc + 1) + cc + 1];
+        const int y0 = (int)a.ys[m * (a.nr + 1) + rr], y1 = (int)a.ys[m * (a.nr + 1) + rr + 1];
+        const int bw = x1 - x0, n = bw * (y1 - y0);
+        const size_t fb = l.base[m];
+        for (int base = 0; base < n; base += 256) {
+            const int q = base + threadIdx.x;
+            int x = 0, y = 0;
+            bool f = false;
+            if (q < n) {
+                y = y0 + q / bw;
+                x = x0 + q % bw;
+                f = l.flag[fb + (size_t)y * l.w[m] + x] != 0;
+            }
+            const uint64_t b = __ballot(f);
+            if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(b);
+            __syncthreads();
+            uint32_t pos = run + (uint32_t)__popcll(b & ((1ull << lane) - 1)), total = 0;
+            for (int k = 0; k < 4; ++k) {
+                pos += k < wave ? s_cnt[k] : 0;
+                total += s_cnt[k];
+            }
+            if (f && dst + pos < a.cap) {
+                kpd_keypoint kp;
+                kp.x = (uint16_t)x;
+                kp.y = (uint16_t)y;
+                kp.octave = (uint8_t)m;
+                kp.pad = 0;
+                kp.score = l.score[fb + (size_t)y * l.w[m] + x];
+                a.list_cur[dst + pos] = kp;
+            }
+            run += total;
+            __syncthreads();   // s_cnt is rewritten by the next round
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ls_mask, dim3(a.ncell), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_emit(const LsArgs& a, const LayArgs& l, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ls_count, dim3(a.ncell), dim3(256), 0, s, a, l);
+    hipLaunchKernelGGL(k_ls_scan, dim3(1), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_ls_write, dim3(a.ncell), dim3(256), 0, s, a, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s)
+{
+    if (a.nblocks > 0) {
+        hipLaunchKernelGGL(k_lay_score, dim3(a.nblocks), dim3(kLayBlock), 0, s, a);
+        hipLaunchKernelGGL(k_lay_nms, dim3(a.nblocks), dim3(kLayBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const uint32_t* count, uint32_t cap,
                              kpd_refined* out, hipStream_t s)

@@ -38,7 +38,8 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
             "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
             "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
-            "kpd_layer_plane", "kpd_refine_layers")
+            "kpd_layer_plane", "kpd_refine_layers", "kpd_lstream_bytes", "kpd_lstream_open", "kpd_lstream_push",
+            "kpd_lstream_get", "kpd_lstream_reset", "kpd_lstream_close")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
 TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2"),
                         ("sad", "<u4")])
@@ -107,6 +108,13 @@ def _load() -> ctypes.CDLL:
     L.kpd_layers_bytes.restype = sz
     L.kpd_detect_layers.argtypes = [P, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, u32, P, P]
     L.kpd_refine_layers.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, P, u32, P, P]
+    L.kpd_lstream_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams)]
+    L.kpd_lstream_bytes.restype = sz
+    L.kpd_lstream_open.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), P, sz, P, ctypes.POINTER(P)]
+    L.kpd_lstream_push.argtypes = [P, P, sz, ctypes.c_int]
+    L.kpd_lstream_get.argtypes = [P, P, sz, ctypes.POINTER(sz), P]
+    L.kpd_lstream_reset.argtypes = [P]
+    L.kpd_lstream_close.argtypes = [P]
     L.kpd_layer_plane.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz),
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     TP = ctypes.POINTER(KpdTcdParams)
@@ -577,3 +585,60 @@ class LayerDetector:
         """Layer l >= 1 of the last frame, as computed on the device."""
         off, w, h = layer_plane(self.width, self.height, self.n_octaves, l)
         return self.workspace[off:off + w * h].cpu().numpy().reshape(h, w)
+
+
+class LayerStream:
+    """The masked stream over octaves and intra-octaves (per-cell mask,
+    Eq. 1; D_n's `octave` field holds the layer index)."""
+
+    def __init__(self, width: int, height: int, params: KpdParams, stream=None, device="cuda"):
+        self.width, self.height, self.params = width, height, params
+        self.n_cells = params.grid_cols * params.grid_rows
+        n = lib.kpd_lstream_bytes(width, height, ctypes.byref(params))
+        if n == 0:
+            raise KpdError(KPD_EINVAL, lib.kpd_last_error().decode())
+        self.arena = torch.empty(n, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib.kpd_lstream_open(width, height, ctypes.byref(params), self.arena.data_ptr(), n,
+                                    _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h.value
+        self._held = [None, None]
+
+    def push(self, frame, retain: bool = False) -> None:
+        if isinstance(frame, np.ndarray):
+            if frame.dtype != np.uint8 or frame.ndim != 2 or frame.strides[1] != 1:
+                raise ValueError("host frame must be a uint8 [H, W] array with unit column stride")
+            _check(lib.kpd_lstream_push(self.handle, frame.ctypes.data, frame.strides[0], FRAME_HOST))
+            return
+        if not (isinstance(frame, torch.Tensor) and frame.device.type == "cuda" and frame.dtype == torch.uint8
+                and frame.dim() == 2 and frame.stride(1) == 1):
+            raise ValueError("device frame must be a CUDA uint8 [H, W] tensor with unit column stride")
+        _check(lib.kpd_lstream_push(self.handle, frame.data_ptr(), frame.stride(0),
+                                    FRAME_DEVICE_RETAIN if retain else FRAME_DEVICE))
+        if retain:
+            self._held = [self._held[1], frame]
+
+    def keypoints(self, capacity: int = 4096) -> Tuple[np.ndarray, np.ndarray]:
+        out = np.zeros(max(capacity, 1), KEYPOINT_DTYPE)
+        mask = np.zeros(self.n_cells, np.uint8)
+        cnt = ctypes.c_size_t()
+        rc = lib.kpd_lstream_get(self.handle, out.ctypes.data, len(out), ctypes.byref(cnt), mask.ctypes.data)
+        if rc == KPD_ETRUNC:
+            out = np.zeros(cnt.value, KEYPOINT_DTYPE)
+            rc = lib.kpd_lstream_get(self.handle, out.ctypes.data, len(out), ctypes.byref(cnt), mask.ctypes.data)
+        _check(rc)
+        return out[:cnt.value].copy(), mask
+
+    def reset(self) -> None:
+        _check(lib.kpd_lstream_reset(self.handle))
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib.kpd_lstream_close(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

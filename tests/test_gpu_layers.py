@@ -133,3 +133,67 @@ def test_refined_random(kpd):
     rng = np.random.default_rng(77)
     img = rng.integers(0, 256, (90, 120)).astype(np.uint8)
     assert check_refined(kpd, img, 25, 3) > 0
+
+
+# ----------------------------------------------- the masked stream over layers
+
+def run_lstream(kpd, frames, det, mode="retain", resets=()):
+    import torch
+    F, H, W = frames.shape
+    t, O, Nc, Nr, TI, TH = det
+    g = kpd.LayerStream(W, H, kpd.make_params(t, O, Nc, Nr, TI, TH))
+    o = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    o.set_layers(True)
+    dev = torch.from_numpy(frames).cuda() if mode != "host" else None
+    carried = 0
+    for i in range(F):
+        if i in resets:
+            g.reset()
+            o.reset()
+        if mode == "host":
+            g.push(frames[i])
+        else:
+            g.push(dev[i], retain=(mode == "retain"))
+        o.push(frames[i])
+        gk, gm = g.keypoints()
+        ok, om, _, _ = o.get()
+        assert tuples(gk) == tuples(ok), f"frame {i}: {len(gk)} vs {len(ok)}"
+        np.testing.assert_array_equal(gm, om, err_msg=f"mask frame {i}")
+        carried += int((om == 0).sum())
+    g.close()
+    return carried
+
+
+KB_OFF = 0xFFFFFFFF
+
+
+def lstream_det(name, **kw):
+    d = synth.DETECTORS[name]
+    v = dict(t=d.fast_t, O=d.n_octaves, Nc=d.grid_cols, Nr=d.grid_rows, TI=d.id_thresh, TH=d.kb_thresh)
+    v.update(kw)
+    return (v["t"], v["O"], v["Nc"], v["Nr"], v["TI"], v["TH"])
+
+
+def test_lstream_c1_and_c2(kpd):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 16)
+    assert run_lstream(kpd, frames, lstream_det("c1_320x240")) > 0
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 12)
+    assert run_lstream(kpd, frames, lstream_det("c2_640x480"), mode="device") > 0
+
+
+def test_lstream_c3_first_frames(kpd):
+    frames = synth.make_video(synth.SCENES["c3_1920x1080"], 3)
+    run_lstream(kpd, frames, lstream_det("c3_1920x1080"))
+
+
+@pytest.mark.parametrize("TI,TH", [(3, KB_OFF), (255, 2), (6, 3), (-1, KB_OFF), (0, 0)])
+def test_lstream_thresholds(kpd, TI, TH):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 6)
+    run_lstream(kpd, frames, lstream_det("c1_320x240", TI=TI, TH=TH), mode="host", resets=(3,))
+
+
+@pytest.mark.parametrize("W,H,det", [(333, 251, (25, 4, 7, 5, 4, KB_OFF)), (101, 77, (12, 3, 6, 4, 4, 3)),
+                                     (64, 48, (10, 1, 2, 2, 6, KB_OFF)), (97, 65, (10, 6, 5, 3, 6, KB_OFF))])
+def test_lstream_shapes(kpd, W, H, det):
+    sc = synth.Scene(W, H, 6, 8, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 910 + W)
+    run_lstream(kpd, synth.make_video(sc), det)
