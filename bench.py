@@ -391,14 +391,46 @@ def intra_octave_workload(kpd, wl: Workload, args) -> dict:
                                              det.capacity, det.refined_dev.data_ptr(), kpd._stream_ptr(None)))
     r1.record()
     torch.cuda.synchronize()
+    # the masked stream over the same layers (per-cell mask, Eq. 1)
+    streams = {}
+    for name, ti in (("masked", d.id_thresh), ("full_frame", -1)):
+        ls = kpd.LayerStream(wl.W, wl.H, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, ti,
+                                                         d.kb_thresh))
+
+        def ls_pass():
+            kpd._check(kpd.lib.kpd_lstream_reset(ls.handle))
+            for i in range(wl.F):
+                kpd._check(kpd.lib.kpd_lstream_push(ls.handle, wl.dev[i].data_ptr(), wl.W, kpd.FRAME_DEVICE_RETAIN))
+
+        ls_pass()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ls_pass()
+        torch.cuda.synchronize()
+        lt = (time.perf_counter() - t0) / steps
+        marked, kps = [], []
+        kpd._check(kpd.lib.kpd_lstream_reset(ls.handle))
+        for i in range(wl.F):
+            kpd._check(kpd.lib.kpd_lstream_push(ls.handle, wl.dev[i].data_ptr(), wl.W, kpd.FRAME_DEVICE_RETAIN))
+            if i % max(1, wl.F // 30) == 0:
+                k, m = ls.keypoints()
+                marked.append(float(m.mean()))
+                kps.append(len(k))
+        ls.close()
+        streams[name] = {"value": round(wl.F * wl.W * wl.H / lt / 1e6, 2), "unit": "Mpixel/s",
+                         "frames_per_s": round(wl.F / lt, 1), "marked_cell_frac": round(float(np.mean(marked)), 4),
+                         "keypoints_per_frame": round(float(np.mean(kps)), 1)}
     return {"value": round(wl.F * wl.W * wl.H / dt / 1e6, 2), "unit": "Mpixel/s", "frames_per_s": round(wl.F / dt, 1),
+            "stream": streams,
             "gpu_us_per_frame": round(e0.elapsed_time(e1) * 1e3 / wl.F, 3),
             "gpu_us_per_frame_with_refinement": round(r0.elapsed_time(r1) * 1e3 / wl.F, 3),
             "keypoints_per_frame": {"octave_layers": round(float(np.mean(oct_kp)), 1),
                                     "intra_octave_layers": round(float(np.mean(intra_kp)), 1)},
             "what": f"{wl.name}, full-frame detection over {2 * d.n_octaves} layers (octaves and intra-octaves), "
                     f"one kpd_detect_layers call per frame ({2 * d.n_octaves + 3} launches); with refinement, "
-                    "one kpd_refine_layers call after it"}
+                    "one kpd_refine_layers call after it; `stream`: the masked stream over the same layers "
+                    "(per-cell mask, Eq. 1), one kpd_lstream_push per frame, masked and full-frame"}
 
 
 def layer_study(kpd, wl: Workload, args) -> dict:
