@@ -45,6 +45,12 @@ struct LayArgs {
     kpd_keypoint* out;
     uint32_t cap;
     uint32_t* count;
+    // the masked stream: pixels whose cell (of the level-0 footprint start)
+    // has need_score[c] == 0 are not scored, those with need_flag[c] == 0
+    // not suppressed; NULL for full-frame detection
+    const uint8_t* need_score;
+    const uint8_t* need_flag;
+    int nc, nr, W, H;
 };
 
 // The masked stream over these layers: per-cell mask, Eq. 1 with cells
@@ -71,6 +77,8 @@ struct LsArgs {
     kpd_keypoint* list_cur;
     uint32_t* total_cur;
     uint32_t cap;
+    uint8_t* need_score;   // cells within (rx, ry) cells of a marked one
+    int rx, ry;
 };
 
 hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s);

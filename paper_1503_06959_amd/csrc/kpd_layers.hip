@@ -75,6 +75,14 @@ __device__ __forceinline__ int layer_of(const LayArgs& a, uint32_t i)
     return l;
 }
 
+// Cell of layer-l pixel (x, y): the cell of its level-0 footprint start
+// (floor(x S / 2), floor(y S / 2)).
+__device__ __forceinline__ int pixel_cell(const LayArgs& a, int l, int x, int y)
+{
+    const int X = (int)(((long long)x * a.S[l]) >> 1), Y = (int)(((long long)y * a.S[l]) >> 1);
+    return (int)(((long long)Y * a.nr) / a.H) * a.nc + (int)(((long long)X * a.nc) / a.W);
+}
+
 __global__ __launch_bounds__(kLayBlock) void k_lay_score(LayArgs a)
 {
     const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
@@ -83,7 +91,9 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_score(LayArgs a)
     const uint32_t r = i - a.base[l];
     const int w = a.w[l], h = a.h[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
     int v = 0;
-    if (x >= 3 && y >= 3 && x < w - 3 && y < h - 3) v = layer_score(a.plane[l] + (size_t)y * a.pitch[l] + x, a.pitch[l], a.t);
+    const bool need = !a.need_score || a.need_score[pixel_cell(a, l, x, y)];
+    if (need && x >= 3 && y >= 3 && x < w - 3 && y < h - 3)
+        v = layer_score(a.plane[l] + (size_t)y * a.pitch[l] + x, a.pitch[l], a.t);
     a.score[i] = (uint16_t)v;
 }
 
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
             const int l = layer_of(a, i);
             const uint32_t r = i - a.base[l];
             const int w = a.w[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
-            keep = true;
+            keep = !a.need_flag || a.need_flag[pixel_cell(a, l, x, y)];
             for (int m = max(l - 1, 0); m <= min(l + 1, a.L - 1) && keep; ++m) {
                 const int S1 = a.S[l], S2 = a.S[m], wm = a.w[m], hm = a.h[m];
                 const int x0 = max((x * S1 + S2 - 1) / S2 - 1, 0), x1 = min(((x + 1) * S1) / S2, wm - 1);
@@ -295,6 +305,24 @@ __global__ __launch_bounds__(256) void k_ls_mask(LsArgs a)
     }
 }
 
+// The cells whose pixels are scored: those within rx columns and ry rows
+// of a marked cell, which holds every neighbour that a marked cell's
+// suppression reads (one workgroup).
+__global__ __launch_bounds__(256) void k_ls_dilate(LsArgs a)
+{
+    for (int c = threadIdx.x; c < a.ncell; c += 256) {
+        const int cc = c % a.nc, rr = c / a.nc;
+        uint8_t need = 0;
+        for (int r2 = max(rr - a.ry, 0); r2 <= min(rr + a.ry, a.nr - 1) && !need; ++r2)
+            for (int c2 = max(cc - a.rx, 0); c2 <= min(cc + a.rx, a.nc - 1); ++c2)
+                if (a.mask[r2 * a.nc + c2]) {
+                    need = 1;
+                    break;
+                }
+        a.need_score[c] = need;
+    }
+}
+
 // Per cell: a marked cell's new keypoints (the flagged pixels of its box on
 // every layer), an unmarked cell's count in D_{n-1}.
 __global__ __launch_bounds__(256) void k_ls_count(LsArgs a, LayArgs l)
@@ -405,6 +433,7 @@ __global__ __launch_bounds__(256) void k_ls_write(LsArgs a, LayArgs l)
 hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ls_mask, dim3(a.ncell), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ls_dilate, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
