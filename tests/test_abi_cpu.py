@@ -206,3 +206,19 @@ def test_layer_workspace_sizes(kpd):
         kpd.layer_plane(640, 480, 4, 0)
     with pytest.raises(kpd.KpdError):
         kpd.layer_plane(640, 480, 4, 8)
+
+
+def test_layer_stream_radius_bound():
+    # the masked layered stream scores the cells within R / (narrowest
+    # cell) + 1 of a marked one, R = S_max / 2 + 1 level-0 pixels: every
+    # suppression neighbour's footprint start lies within max(S_p, S_q) / 2
+    # + 1 pixels of the pixel's own (S in half pixels)
+    import oracle
+    sizes = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48]
+    for i, S1 in enumerate(sizes):
+        for S2 in sizes[max(i - 1, 0):i + 2]:
+            for x in range(0, 200):
+                lo, hi = oracle.layer_range(S1, S2, x)
+                for q in range(max(lo, 0), hi + 1):
+                    d = abs((q * S2) // 2 - (x * S1) // 2)
+                    assert d <= max(S1, S2) // 2 + 1, (S1, S2, x, q)
