@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
     L.orc_layer_range.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
     L.orc_detect_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int]
     L.orc_set_layers.argtypes = [P, ctypes.c_int]
+    L.orc_set_lazy.argtypes = [P, ctypes.c_int]
     L.orc_refine_layers.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
     L.orc_tcd_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.orc_tcd_spiral.argtypes = [ctypes.c_int, P, P]
@@ -226,6 +227,11 @@ class Stream:
     def set_descriptors(self, on: bool = True):
         """Keep a descriptor with every feature of D_n (R13-R16)."""
         lib().orc_set_descriptors(self.h, 1 if on else 0)
+
+    def set_lazy(self, on: bool = True):
+        """CPU-masked mode: score only what the marked cells' suppression
+        reads (same results as the definitional mode)."""
+        assert lib().orc_set_lazy(self.h, 1 if on else 0) == 0
 
     def set_layers(self, on: bool = True):
         """Detect over octaves and intra-octaves (L5) from the next frame on."""

@@ -384,6 +384,72 @@ int orc_detect(const uint8_t* img, int W, int H, int t, int O, orc_kp* out, int 
 static int cell_col(int X, int W, int Nc) { return (int)(((long)X * Nc) / W); }
 static int cell_row(int Y, int H, int Nr) { return (int)(((long)Y * Nr) / H); }
 
+/* F(I_n) restricted to marked cells, computed the way the masked method
+ * saves work on a CPU: the keypoints of pixels whose cell (R6) is marked,
+ * with every score taken only when the suppression of such a pixel reads
+ * it (scores cached per level, -1 = not taken yet). Equal to orc_detect's
+ * list filtered by the mask, in the same order. */
+static int lazy_score(uint8_t* const* lv, const int* ws, const int* hs, int32_t* const* V, int t, int o, int x, int y)
+{
+    if (x < 0 || y < 0 || x >= ws[o] || y >= hs[o]) return 0;
+    int32_t* v = &V[o][(long)y * ws[o] + x];
+    if (*v < 0) *v = score_at(lv[o], ws[o], hs[o], x, y, t);
+    return *v;
+}
+
+int orc_detect_masked(const uint8_t* img, int W, int H, int t, int O, const uint8_t* mask, int Nc, int Nr,
+                      orc_kp* out, int cap)
+{
+    int ws[32], hs[32];
+    if (O < 1 || O > 32 || W < 1 || H < 1) return -2;
+    long total = orc_level_dims(W, H, O, ws, hs);
+    uint8_t* pyr = (uint8_t*)malloc((size_t)total);
+    int32_t* Vall = (int32_t*)malloc((size_t)total * sizeof(int32_t));
+    uint8_t* lv[32];
+    int32_t* V[32];
+    long off = 0;
+    for (int o = 0; o < O; ++o) { lv[o] = pyr + off; V[o] = Vall + off; off += (long)ws[o] * hs[o]; }
+    orc_pyramid(img, W, H, O, pyr);
+    for (long i = 0; i < total; ++i) Vall[i] = -1;
+    int n = 0;
+    for (int o = 0; o < O; ++o)
+        for (int y = 0; y < hs[o]; ++y) {
+            const int row = cell_row(y << o, H, Nr);
+            for (int x = 0; x < ws[o]; ++x) {
+                if (!mask[row * Nc + cell_col(x << o, W, Nc)]) continue;
+                const int v = lazy_score(lv, ws, hs, V, t, o, x, y);
+                if (v == 0) continue;
+                int keep = 1;
+                for (int dy = -1; dy <= 1 && keep; ++dy)
+                    for (int dx = -1; dx <= 1 && keep; ++dx) {
+                        if (dx == 0 && dy == 0) continue;
+                        if (beats(lazy_score(lv, ws, hs, V, t, o, x + dx, y + dy), o, y + dy, x + dx, v, o, y, x))
+                            keep = 0;
+                    }
+                if (o > 0)
+                    for (int qy = 2 * y - 1; qy <= 2 * y + 2 && keep; ++qy)
+                        for (int qx = 2 * x - 1; qx <= 2 * x + 2 && keep; ++qx)
+                            if (beats(lazy_score(lv, ws, hs, V, t, o - 1, qx, qy), o - 1, qy, qx, v, o, y, x)) keep = 0;
+                if (o + 1 < O)
+                    for (int qy = y / 2 - 2; qy <= y / 2 + 2 && keep; ++qy)
+                        for (int qx = x / 2 - 2; qx <= x / 2 + 2 && keep; ++qx) {
+                            if (!(2 * qx - 1 <= x && x <= 2 * qx + 2) || !(2 * qy - 1 <= y && y <= 2 * qy + 2)) continue;
+                            if (beats(lazy_score(lv, ws, hs, V, t, o + 1, qx, qy), o + 1, qy, qx, v, o, y, x)) keep = 0;
+                        }
+                if (!keep) continue;
+                if (n >= cap) { free(pyr); free(Vall); return -1; }
+                out[n].x = x;
+                out[n].y = y;
+                out[n].octave = o;
+                out[n].score = v;
+                ++n;
+            }
+        }
+    free(pyr);
+    free(Vall);
+    return n;
+}
+
 /* Cell index (row-major) of a keypoint at level o (R6). */
 int orc_cell_of(int x, int y, int o, int W, int H, int Nc, int Nr)
 {
@@ -613,6 +679,7 @@ typedef struct {
     int desc_on;         /* R13-R16: descriptors kept with D_n */
     int ref_on;          /* R17-R19: refined position, scale and score kept with D_n */
     int layers_on;       /* L5: detection over octaves and intra-octaves */
+    int lazy;            /* CPU-masked mode: scores only where marked cells' suppression reads them */
     float* ref;          /* 4 floats per feature of D_n */
     uint64_t* desc;      /* 8 words per feature of D_n */
     int32_t* bin;        /* orientation sector per feature of D_n */
@@ -676,6 +743,14 @@ int orc_set_layers(orc_stream* s, int on)
     if (on && (s->desc_on || s->ref_on || s->id_mode != 0)) return -1;
     if ((on != 0) != s->layers_on) s->force_all = 1;
     s->layers_on = on != 0;
+    return 0;
+}
+
+/* CPU-masked mode (same results): full-frame detection is replaced by
+ * detection that scores only what the marked cells' suppression reads */
+int orc_set_lazy(orc_stream* s, int on)
+{
+    s->lazy = on != 0;
     return 0;
 }
 
@@ -849,8 +924,13 @@ int orc_push(orc_stream* s, const uint8_t* frame)
 
     /* full-frame detection of I_n */
     orc_kp* F = (orc_kp*)malloc(sizeof(orc_kp) * (size_t)s->capK);
-    int nF = s->layers_on ? orc_detect_layers(frame, W, H, s->t, s->O, F, s->capK)
-                          : orc_detect(frame, W, H, s->t, s->O, F, s->capK);
+    int nF;
+    if (s->layers_on)
+        nF = orc_detect_layers(frame, W, H, s->t, s->O, F, s->capK);
+    else if (s->lazy && !per_pixel)
+        nF = orc_detect_masked(frame, W, H, s->t, s->O, s->mask, Nc, Nr, F, s->capK);
+    else
+        nF = orc_detect(frame, W, H, s->t, s->O, F, s->capK);
     if (nF < 0) { free(F); return -1; }
 
     /* Eq. (1): new features where the mask is 1, previous ones elsewhere;

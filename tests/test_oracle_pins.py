@@ -1063,3 +1063,24 @@ def test_layer_stream_carries_and_switches():
     s.set_descriptors(True)
     with pytest.raises(AssertionError):
         s.set_layers(True)                 # descriptors run over the octaves only
+
+
+@pytest.mark.parametrize("TI,TH", [(8, KB_OFF), (3, KB_OFF), (255, 2), (6, 3), (-1, KB_OFF)])
+def test_cpu_masked_mode_equals_definitional(TI, TH):
+    # the CPU-masked mode scores only what marked cells' suppression reads;
+    # D_n, the mask and the counts equal the definitional mode's on every frame
+    from paper_1503_06959_amd import synth
+    sc = synth.Scene(160, 120, 8, 10, 6, 30, 0.5, 2.0, True, 55)
+    frames = synth.make_video(sc)
+    W, H, t, O, Nc, Nr = 160, 120, 15, 3, 8, 6
+    a = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    b = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    b.set_lazy(True)
+    for f in frames:
+        a.push(f)
+        b.push(f)
+        ka, ma, _, ca = a.get()
+        kb, mb, _, cb = b.get()
+        assert kps_tuples(ka) == kps_tuples(kb)
+        np.testing.assert_array_equal(ma, mb)
+        np.testing.assert_array_equal(ca, cb)
