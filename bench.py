@@ -826,8 +826,8 @@ def summarize_profiles(out: str) -> None:
             continue
         path = os.path.join(out, case, "kt_kernel_stats.csv")
         rows = list(csv.DictReader(open(path)))
-        lines = [f"# kernel durations, {case}", "", "command (R = the repository root, run from /tmp):",
-                 "  " + profile_command(case, "$R/gpurun_out/prof"), "",
+        lines = [f"# kernel durations, {case}", "", "command (R = the repository root, OUT = the output folder given to --profile-script, run from /tmp):",
+                 "  " + profile_command(case, "$OUT"), "",
                  f"{'kernel':40s} {'calls':>7s} {'avg_us':>10s} {'min_us':>9s} {'max_us':>9s} {'share':>7s}"]
         for r in rows:
             lines.append(f"{short(r['Name']):40s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.3f} "
@@ -853,11 +853,11 @@ def summarize_profiles(out: str) -> None:
              f"scale: a plain copy of {copy_bytes} bytes reads FETCH_SIZE {fc['__amd_rocclr_copyBuffer'][0]:.1f} KiB "
              f"and WRITE_SIZE {wc['__amd_rocclr_copyBuffer'][0]:.1f} KiB per dispatch, so bytes = "
              f"FETCH_SIZE x 1024 x {f_scale:.3f} + WRITE_SIZE x 1024 x {w_scale:.3f}", "",
-             "commands (R = the repository root, run from /tmp):"]
+             "commands (R = the repository root, OUT = the output folder given to --profile-script, run from /tmp):"]
     for case in PROFILE_CASES:
         if PROFILE_CASES[case][0] == "pmc":
             for c in PMC_COUNTERS:
-                lines.append("  " + profile_command(case, "$R/gpurun_out/prof", c))
+                lines.append("  " + profile_command(case, "$OUT", c))
     lines += ["", f"{'case':34s} {'kernel':16s} {'dispatches':>10s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} "
                   f"{'bytes/launch':>13s}"]
     for case, (kind, _) in PROFILE_CASES.items():
@@ -885,9 +885,9 @@ def summarize_profiles(out: str) -> None:
     lv = level_sizes(1920, 1080, 5)
     px_oct = 300 * sum(lv)   # pixel-octaves one chunk launch covers (the whole video)
     lines = ["# VALU study, 1920x1080 full-frame chunks (300 frames per launch), one counter set per run", "",
-             "commands (R = the repository root, run from /tmp):"]
+             "commands (R = the repository root, OUT = the output folder given to --profile-script, run from /tmp):"]
     for c in VALU_SETS:
-        lines.append("  " + profile_command(case, "$R/gpurun_out/prof", " ".join(c)))
+        lines.append("  " + profile_command(case, "$OUT", " ".join(c)))
     lines += ["", f"{'kernel':16s} {'dispatches':>10s} {'VALUBusy%':>10s} {'VALU insts':>14s} {'waves':>10s} "
                   f"{'wait/wave cyc':>13s} {'lane-ops/px-oct':>16s}"]
     for k in ("k_frame_chunk", "k_detect_chunk", "k_compact_chunk"):
