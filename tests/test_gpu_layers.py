@@ -197,3 +197,19 @@ def test_lstream_thresholds(kpd, TI, TH):
 def test_lstream_shapes(kpd, W, H, det):
     sc = synth.Scene(W, H, 6, 8, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 910 + W)
     run_lstream(kpd, synth.make_video(sc), det)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_lstream_random_configs(kpd, seed):
+    # seeded random sizes, depths, grids (down to cells a few pixels wide,
+    # where the scoring radius spans many cells) and thresholds
+    rng = np.random.default_rng(4200 + seed)
+    W, H = int(rng.integers(40, 400)), int(rng.integers(40, 300))
+    O = int(rng.integers(1, 7))
+    Nc, Nr = int(rng.integers(1, max(2, W // 6))), int(rng.integers(1, max(2, H // 6)))
+    TI = int(rng.choice([-1, 0, 2, 5, 8, 20, 255]))
+    TH = int(rng.choice([0, 1, 2, 4, KB_OFF]))
+    t = int(rng.integers(8, 40))
+    sc = synth.Scene(W, H, 6, int(rng.integers(3, 12)), 3, max(4, min(W, H) // 3), float(rng.uniform(0.2, 1.0)),
+                     2.0, bool(seed % 2), 5000 + seed)
+    run_lstream(kpd, synth.make_video(sc), (t, O, Nc, Nr, TI, TH), mode="device" if seed % 3 else "retain")

@@ -109,3 +109,17 @@ def test_errors_and_device_result(kpd):
     g.close()
     with pytest.raises(kpd.KpdError):
         kpd.Tcd(320, 240, kpd.make_params(*det_of("c1_320x240")), gop=0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_configs(kpd, seed):
+    # seeded random sizes, depths, groups and thresholds on panning scenes
+    rng = np.random.default_rng(7300 + seed)
+    W, H = int(rng.integers(48, 360)), int(rng.integers(48, 280))
+    O = int(rng.integers(1, 5))
+    det = (int(rng.integers(8, 35)), O, int(rng.integers(1, 8)), int(rng.integers(1, 6)))
+    gop = int(rng.integers(1, 6))
+    t_bm = int(rng.choice([0, 600, 1800, 5000, 70000]))
+    t_et = int(rng.choice([0, 500, 1000, 3000]))
+    sc = synth.Scene(W, H, 8, int(rng.integers(3, 12)), 4, max(5, min(W, H) // 3), 1.0, 2.0, True, 6000 + seed)
+    run_tcd(kpd, synth.make_video(sc), det, gop=gop, t_bm=t_bm, t_et=t_et, mode="device" if seed % 2 else "retain")
