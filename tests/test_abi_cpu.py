@@ -222,3 +222,17 @@ def test_layer_stream_radius_bound():
                 for q in range(max(lo, 0), hi + 1):
                     d = abs((q * S2) // 2 - (x * S1) // 2)
                     assert d <= max(S1, S2) // 2 + 1, (S1, S2, x, q)
+
+
+def test_lstream_sizes(kpd):
+    # the masked layered stream holds the layer workspace, two frame slots,
+    # the cell tables and two D lists of the layers' keypoint bound
+    import oracle
+    p = kpd.make_params(20, 4, 16, 12)
+    n = kpd.lib.kpd_lstream_bytes(640, 480, ctypes.byref(p))
+    dims = oracle.layer_dims(640, 480, 4)
+    cap = sum(((w + 1) // 2) * ((h + 1) // 2) for w, h, _ in dims) + 16
+    assert n >= kpd.layers_bytes(640, 480, 4) + 2 * 640 * 480 + 2 * 8 * cap
+    for bad in (kpd.make_params(0, 4, 16, 12), kpd.make_params(20, 9, 16, 12), kpd.make_params(20, 4, 0, 12),
+                kpd.make_params(20, 4, 641, 12), kpd.make_params(20, 4, 16, 481)):
+        assert kpd.lib.kpd_lstream_bytes(640, 480, ctypes.byref(bad)) == 0
