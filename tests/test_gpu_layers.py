@@ -213,3 +213,31 @@ def test_lstream_random_configs(kpd, seed):
     sc = synth.Scene(W, H, 6, int(rng.integers(3, 12)), 3, max(4, min(W, H) // 3), float(rng.uniform(0.2, 1.0)),
                      2.0, bool(seed % 2), 5000 + seed)
     run_lstream(kpd, synth.make_video(sc), (t, O, Nc, Nr, TI, TH), mode="device" if seed % 3 else "retain")
+
+
+def test_lstream_c2_whole_video_as_benchmarked(kpd):
+    # the benchmark's configuration: the 300-frame 640x480 video, T_I = 8,
+    # frames read in place, one push per frame
+    frames = synth.make_video(synth.SCENES["c2_640x480"])
+    assert frames.shape[0] == 300
+    assert run_lstream(kpd, frames, lstream_det("c2_640x480"), mode="retain") > 0
+
+
+def test_detect_layers_c2_sampled_frames_as_benchmarked(kpd):
+    # every 10th frame of the benchmark's video through one detector, as the
+    # benchmark calls it, with refinement
+    import torch
+    d = synth.DETECTORS["c2_640x480"]
+    frames = synth.make_video(synth.SCENES["c2_640x480"])
+    dev = torch.from_numpy(frames).cuda()
+    det = kpd.LayerDetector(640, 480, d.fast_t, d.n_octaves)
+    for i in range(0, 300, 10):
+        det.detect_async(dev[i])
+        n = min(int(det.count.item()), det.capacity)
+        got = det.out[:n * kpd.KEYPOINT_DTYPE.itemsize].cpu().numpy().view(kpd.KEYPOINT_DTYPE)
+        exp = oracle.detect_layers(frames[i], d.fast_t, d.n_octaves)
+        assert tuples(got) == tuples(exp), i
+        r = det.refine()
+        g = np.stack([r["x"], r["y"], r["log2_scale"], r["score"]], axis=1).astype(np.float32)
+        e = oracle.refine_layers(frames[i], d.fast_t, d.n_octaves, exp)
+        assert (g.view(np.uint32) == e.view(np.uint32)).all(), i

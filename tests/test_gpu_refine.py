@@ -135,3 +135,11 @@ def test_refine_errors(kpd):
     ms, n = kpd.profile_read(g.handle)
     assert list(n) == [1, 1, 0, 0, 1]
     g.close()
+
+
+def test_c2_whole_video_with_descriptors_as_benchmarked(kpd):
+    # the benchmark's streaming configuration, both per-feature passes on,
+    # all 300 frames
+    frames = synth.make_video(synth.SCENES["c2_640x480"])
+    assert frames.shape[0] == 300
+    assert run_ref(kpd, frames, det_of("c2_640x480"), with_desc=True) > 0

@@ -123,3 +123,11 @@ def test_random_configs(kpd, seed):
     t_et = int(rng.choice([0, 500, 1000, 3000]))
     sc = synth.Scene(W, H, 8, int(rng.integers(3, 12)), 4, max(5, min(W, H) // 3), 1.0, 2.0, True, 6000 + seed)
     run_tcd(kpd, synth.make_video(sc), det, gop=gop, t_bm=t_bm, t_et=t_et, mode="device" if seed % 2 else "retain")
+
+
+def test_c2_whole_video_as_benchmarked(kpd):
+    # the benchmark's configuration: the 300-frame 640x480 video, groups of
+    # 10, T_BM = 1800, T_ET = 1000, frames read in place
+    frames = synth.make_video(synth.SCENES["c2_640x480"])
+    assert frames.shape[0] == 300
+    assert run_tcd(kpd, frames, det_of("c2_640x480"), gop=10, t_bm=1800, t_et=1000, mode="retain") > 0
