@@ -51,12 +51,16 @@ __device__ __forceinline__ void spiral_uv(int k, int& u, int& v)
 }
 
 // SAD between the reference patch and the bilinear patch whose top-left
-// sample has integer part (rx, ry) in the region and fraction (a, b).
-__device__ int patch_sad(const uint8_t* ref, const uint8_t* reg, int rx, int ry, int a, int b)
+// sample has integer part (rx, ry) in the region and fraction (a, b). Each
+// lane starts at a different patch row (`rot`), so the lanes of a wave,
+// whose candidates sit a few pixels apart, spread their LDS reads over the
+// banks.
+__device__ int patch_sad(const uint8_t* ref, const uint8_t* reg, int rx, int ry, int a, int b, int rot)
 {
     const int w00 = (4 - a) * (4 - b), w10 = a * (4 - b), w01 = (4 - a) * b, w11 = a * b;
     int sad = 0;
-    for (int j = 0; j < 16; ++j) {
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = (jj + rot) & 15;
         const uint8_t* r0 = reg + (ry + j) * kRegionPitch + rx;
         const uint8_t* r1 = r0 + kRegionPitch;
         const uint8_t* q = ref + j * 16;
@@ -96,7 +100,7 @@ __device__ Best search(const uint8_t* ref, const uint8_t* reg, int ox, int oy, i
         cy = Y + scale * v;
         ok = usable(W, H, cx, cy);
     }
-    if (ok) sad = patch_sad(ref, reg, (cx >> 2) - 8 - ox, (cy >> 2) - 8 - oy, cx & 3, cy & 3);
+    if (ok) sad = patch_sad(ref, reg, (cx >> 2) - 8 - ox, (cy >> 2) - 8 - oy, cx & 3, cy & 3, k);
     const uint64_t et = __ballot(ok && sad < t_et);
     int et_key = 0x7FFFFFFF;   // (index, SAD) of the wave's earliest candidate below t_et
     if (et) {
