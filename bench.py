@@ -366,6 +366,13 @@ def tcd_workload(kpd, wl: Workload, args) -> dict:
                     "T_BM=1800, T_ET=1000; one tcd_push per frame"}
 
 
+def layer_launches(O: int) -> int:
+    """Launches of one kpd_detect_layers call: the octaves two halvings per
+    launch, the 1.5x pass with d_1, the intra-octaves two per launch, then
+    score, suppression, scan and write."""
+    return O // 2 + 1 + (max(O - 2, 0) + 1) // 2 + 4
+
+
 def intra_octave_workload(kpd, wl: Workload, args) -> dict:
     """Full-frame detection over octaves and intra-octaves (Sec. 2's BRISK
     scale space, 2O layers), one call per frame of the video, frames in
@@ -445,7 +452,7 @@ def intra_octave_workload(kpd, wl: Workload, args) -> dict:
             "keypoints_per_frame": {"octave_layers": round(float(np.mean(oct_kp)), 1),
                                     "intra_octave_layers": round(float(np.mean(intra_kp)), 1)},
             "what": f"{wl.name}, full-frame detection over {2 * d.n_octaves} layers (octaves and intra-octaves), "
-                    f"one kpd_detect_layers call per frame ({2 * d.n_octaves + 3} launches); with refinement, "
+                    f"one kpd_detect_layers call per frame ({layer_launches(d.n_octaves)} launches); with refinement, "
                     "one kpd_refine_layers call after it; `stream`: the masked stream over the same layers "
                     "(per-cell mask, Eq. 1), one kpd_lstream_push per frame, masked and full-frame"}
 

@@ -149,6 +149,38 @@ void ls_tables(const LsLayout& L, std::vector<uint32_t>* xs, std::vector<uint32_
     build(L.g.L, L.g.h, L.g.S, L.H, L.nr, ys);
 }
 
+// The layers past the frame: the octaves two halvings per launch, the
+// intra-octaves from the 1.5x downsampling (with d_1) and then two halvings
+// per launch.
+hipError_t build_layers(const kpd::LayerGeom& g, const uint8_t* frame, int pitch, uint8_t* ws, hipStream_t s)
+{
+    const int O = g.L / 2;
+    auto plane = [&](int l) { return ws + g.plane_off[l]; };
+    hipError_t e = hipSuccess;
+    // octaves: c_i = layer 2i, from c_0 = the frame
+    for (int i = 1; i < O && e == hipSuccess; i += 2) {
+        const uint8_t* src = i == 1 ? frame : plane(2 * (i - 1));
+        const int sp = i == 1 ? pitch : g.w[2 * (i - 1)];
+        const int l1 = 2 * i, l2 = 2 * (i + 1);
+        const bool two = i + 1 < O;
+        e = kpd::launch_lay_quad(src, sp, plane(l1), g.w[l1], g.h[l1], two ? plane(l2) : nullptr, two ? g.w[l2] : 0,
+                                 two ? g.h[l2] : 0, s);
+    }
+    // intra-octaves: d_i = layer 2i + 1
+    if (e == hipSuccess) {
+        const bool d1 = O > 1;
+        e = kpd::launch_lay_third(frame, pitch, plane(1), g.w[1], g.h[1], d1 ? plane(3) : nullptr, d1 ? g.w[3] : 0,
+                                  d1 ? g.h[3] : 0, s);
+    }
+    for (int i = 2; i < O && e == hipSuccess; i += 2) {
+        const int ls = 2 * (i - 1) + 1, l1 = 2 * i + 1, l2 = 2 * (i + 1) + 1;
+        const bool two = i + 1 < O;
+        e = kpd::launch_lay_quad(plane(ls), g.w[ls], plane(l1), g.w[l1], g.h[l1], two ? plane(l2) : nullptr,
+                                 two ? g.w[l2] : 0, two ? g.h[l2] : 0, s);
+    }
+    return e;
+}
+
 }  // namespace
 
 struct kpd_lstream {
@@ -271,16 +303,7 @@ int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, i
     la.H = L.H;
     hipError_t e = kpd::launch_ls_mask(a, s->stream);
     // the layers of I_n, as kpd_detect_layers builds them
-    auto plane = [&](int l) { return ws + L.g.plane_off[l]; };
-    for (int i = 1; i < L.O && e == hipSuccess; ++i) {
-        const int l = 2 * i, src = 2 * i - 2;
-        e = kpd::launch_lay_half(la.plane[src], la.pitch[src], plane(l), L.g.w[l], L.g.h[l], s->stream);
-    }
-    if (e == hipSuccess) e = kpd::launch_lay_twothirds(cur, cur_pitch, plane(1), L.g.w[1], L.g.h[1], s->stream);
-    for (int i = 1; i < L.O && e == hipSuccess; ++i) {
-        const int l = 2 * i + 1, src = 2 * i - 1;
-        e = kpd::launch_lay_half(plane(src), L.g.w[src], plane(l), L.g.w[l], L.g.h[l], s->stream);
-    }
+    if (e == hipSuccess) e = build_layers(L.g, cur, cur_pitch, ws, s->stream);
     if (e == hipSuccess) e = kpd::launch_lay_score_nms(la, s->stream);
     if (e == hipSuccess) e = kpd::launch_ls_emit(a, la, s->stream);
     if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_push");
@@ -381,19 +404,8 @@ int kpd_detect_layers(const uint8_t* frame, size_t pitch_bytes, int width, int h
     a.count = count;
     // the layers: octaves by halving from the frame, d_0 from the frame,
     // the other intra-octaves by halving d_0
-    auto plane = [&](int l) { return ws + g.plane_off[l]; };
-    for (int i = 1; i < n_octaves; ++i) {
-        const int l = 2 * i, src = 2 * i - 2;
-        hipError_t e = kpd::launch_lay_half(a.plane[src], a.pitch[src], plane(l), g.w[l], g.h[l], s);
-        if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_detect_layers");
-    }
-    hipError_t e = kpd::launch_lay_twothirds(frame, (int)pitch_bytes, plane(1), g.w[1], g.h[1], s);
+    hipError_t e = build_layers(g, frame, (int)pitch_bytes, ws, s);
     if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_detect_layers");
-    for (int i = 1; i < n_octaves; ++i) {
-        const int l = 2 * i + 1, src = 2 * i - 1;
-        e = kpd::launch_lay_half(plane(src), g.w[src], plane(l), g.w[l], g.h[l], s);
-        if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_detect_layers");
-    }
     e = kpd::launch_lay_detect(a, s);
     if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_detect_layers");
     return KPD_OK;

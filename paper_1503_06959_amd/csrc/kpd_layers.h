@@ -84,8 +84,13 @@ struct LsArgs {
 hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s);
 hipError_t launch_ls_emit(const LsArgs& a, const LayArgs& l, hipStream_t s);
 
-hipError_t launch_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
-hipError_t launch_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s);
+// Two halvings of a chain (src -> d1 -> d2; d2 absent when w2 = 0), and the
+// 1.5x downsampling of the frame with the halving after it (d1 absent when
+// w1 = 0).
+hipError_t launch_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1, uint8_t* d2, int w2, int h2,
+                           hipStream_t s);
+hipError_t launch_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0, uint8_t* d1, int w1, int h1,
+                            hipStream_t s);
 hipError_t launch_lay_detect(const LayArgs& a, hipStream_t s);
 hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s);
 hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const uint32_t* count, uint32_t cap,

@@ -14,32 +14,63 @@ namespace {
 __constant__ int8_t kLayRingDx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
 __constant__ int8_t kLayRingDy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
 
-// 2x2 blocks, round half up (the octaves' halving).
-__global__ __launch_bounds__(256) void k_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh)
+// Two levels of a chain per launch. k_lay_quad: a thread per 2x2 quad of
+// level d1 (each pixel the 2x2 mean of src, round half up, for the quad
+// pixels inside d1) and, when the quad lies inside d2's reach, the d2 pixel
+// that is the mean of the quad; d2 may be absent (w2 = 0).
+__device__ __forceinline__ int mean4(int a, int b, int c, int d) { return (a + b + c + d + 2) >> 2; }
+
+__global__ __launch_bounds__(256) void k_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1,
+                                                  uint8_t* d2, int w2, int h2)
 {
-    const int x = blockIdx.x * 16 + (threadIdx.x & 15), y = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (x >= dw || y >= dh) return;
-    const uint8_t* p = src + (size_t)(2 * y) * spitch + 2 * x;
-    dst[(size_t)y * dw + x] = (uint8_t)((p[0] + p[1] + p[spitch] + p[spitch + 1] + 2) >> 2);
+    const int qx = blockIdx.x * 16 + (threadIdx.x & 15), qy = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (2 * qx >= w1 || 2 * qy >= h1) return;
+    int v[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int x = 2 * qx + i, y = 2 * qy + j;
+            if (x < w1 && y < h1) {
+                const uint8_t* p = src + (size_t)(2 * y) * spitch + 2 * x;
+                v[j][i] = mean4(p[0], p[1], p[spitch], p[spitch + 1]);
+                d1[(size_t)y * w1 + x] = (uint8_t)v[j][i];
+            }
+        }
+    if (qx < w2 && qy < h2) d2[(size_t)qy * w2 + qx] = (uint8_t)mean4(v[0][0], v[0][1], v[1][0], v[1][1]);
 }
 
-// Whole 3x3 blocks to 2x2 blocks: the output pixel (2a+p, 2b+q) is the
-// rounded mean over the 1.5 x 1.5 area it covers, weights (2, 1, 0) or
-// (0, 1, 2) along each axis, over 9.
-__global__ __launch_bounds__(256) void k_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh)
+// The 1.5x downsampling and the halving after it: a thread per whole 3x3
+// block (a, b) of the frame writes the block's 2x2 outputs of d_0 (output
+// (2a+p, 2b+q) = the rounded mean over the 1.5 x 1.5 area it covers,
+// weights (2, 1, 0) or (0, 1, 2) along each axis, over 9) and, when d_1 is
+// built here, their mean (d_1 has exactly one pixel per block).
+__global__ __launch_bounds__(256) void k_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0,
+                                                   uint8_t* d1, int w1, int h1)
 {
-    const int X = blockIdx.x * 16 + (threadIdx.x & 15), Y = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (X >= dw || Y >= dh) return;
-    const int a = X >> 1, p = X & 1, b = Y >> 1, q = Y & 1;
+    const int a = blockIdx.x * 16 + (threadIdx.x & 15), b = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (2 * a >= w0 || 2 * b >= h0) return;
     const uint8_t* s = src + (size_t)(3 * b) * spitch + 3 * a;
-    int sum = 0;
+    int r[3][3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int wy = q ? j : 2 - j;
-        const uint8_t* r = s + (size_t)j * spitch;
-        sum += wy * ((p ? 0 : 2) * r[0] + r[1] + (p ? 2 : 0) * r[2]);
-    }
-    dst[(size_t)Y * dw + X] = (uint8_t)((sum + 4) / 9);
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[j][i] = s[(size_t)j * spitch + i];
+    int v[2][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            int sum = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int wy = q ? j : 2 - j;
+                sum += wy * ((p ? 0 : 2) * r[j][0] + r[j][1] + (p ? 2 : 0) * r[j][2]);
+            }
+            v[q][p] = (sum + 4) / 9;
+            d0[(size_t)(2 * b + q) * w0 + 2 * a + p] = (uint8_t)v[q][p];
+        }
+    if (a < w1 && b < h1) d1[(size_t)b * w1 + a] = (uint8_t)mean4(v[0][0], v[0][1], v[1][0], v[1][1]);
 }
 
 __device__ __forceinline__ bool arc9(unsigned m)
@@ -463,18 +494,23 @@ hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const u
     return hipGetLastError();
 }
 
-hipError_t launch_lay_half(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s)
+hipError_t launch_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1, uint8_t* d2, int w2, int h2,
+                           hipStream_t s)
 {
-    if (dw <= 0 || dh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lay_half, dim3((dw + 15) / 16, (dh + 15) / 16), dim3(256), 0, s, src, spitch, dst, dw, dh);
+    if (w1 <= 0 || h1 <= 0) return hipSuccess;
+    const int qx = (w1 + 1) / 2, qy = (h1 + 1) / 2;
+    hipLaunchKernelGGL(k_lay_quad, dim3((qx + 15) / 16, (qy + 15) / 16), dim3(256), 0, s, src, spitch, d1, w1, h1, d2,
+                       w2, h2);
     return hipGetLastError();
 }
 
-hipError_t launch_lay_twothirds(const uint8_t* src, int spitch, uint8_t* dst, int dw, int dh, hipStream_t s)
+hipError_t launch_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0, uint8_t* d1, int w1, int h1,
+                            hipStream_t s)
 {
-    if (dw <= 0 || dh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lay_twothirds, dim3((dw + 15) / 16, (dh + 15) / 16), dim3(256), 0, s, src, spitch, dst, dw,
-                       dh);
+    if (w0 <= 0 || h0 <= 0) return hipSuccess;
+    const int bx = w0 / 2, by = h0 / 2;
+    hipLaunchKernelGGL(k_lay_third, dim3((bx + 15) / 16, (by + 15) / 16), dim3(256), 0, s, src, spitch, d0, w0, h0, d1,
+                       w1, h1);
     return hipGetLastError();
 }
 
