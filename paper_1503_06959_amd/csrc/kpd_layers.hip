@@ -145,21 +145,37 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
             const uint32_t r = i - a.base[l];
             const int w = a.w[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
             keep = !a.need_flag || a.need_flag[pixel_cell(a, l, x, y)];
-            for (int m = max(l - 1, 0); m <= min(l + 1, a.L - 1) && keep; ++m) {
+            // Between adjacent layers the size ratio is 1.5 or 4/3, so a
+            // range holds at most floor(ratio + 2) = 3 pixels a side: the
+            // reads of a 3 x 3 window per layer are issued together, with
+            // no early exit; a wider range (none arises) takes the loop.
+            bool above = false;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int m = l - 1 + k;
+                if (!keep || m < 0 || m >= a.L) continue;
                 const int S1 = a.S[l], S2 = a.S[m], wm = a.w[m], hm = a.h[m];
                 const int x0 = max((x * S1 + S2 - 1) / S2 - 1, 0), x1 = min(((x + 1) * S1) / S2, wm - 1);
                 const int y0 = max((y * S1 + S2 - 1) / S2 - 1, 0), y1 = min(((y + 1) * S1) / S2, hm - 1);
                 const uint16_t* sc = a.score + a.base[m];
-                for (int qy = y0; qy <= y1 && keep; ++qy)
-                    for (int qx = x0; qx <= x1; ++qx) {
-                        const int vq = sc[(size_t)qy * wm + qx];
-                        const bool above = vq > v || (vq == v && (m < l || (m == l && (qy < y || (qy == y && qx < x)))));
-                        if (above) {
-                            keep = false;
-                            break;
+                auto ranks_above = [&](int qx, int qy) {
+                    const int vq = sc[(size_t)qy * wm + qx];
+                    return vq > v || (vq == v && (m < l || (m == l && (qy < y || (qy == y && qx < x)))));
+                };
+                if (x1 - x0 < 3 && y1 - y0 < 3) {
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx) {
+                            const int qx = x0 + dx, qy = y0 + dy;
+                            if (qx <= x1 && qy <= y1) above |= ranks_above(qx, qy);
                         }
-                    }
+                } else {
+                    for (int qy = y0; qy <= y1; ++qy)
+                        for (int qx = x0; qx <= x1; ++qx) above |= ranks_above(qx, qy);
+                }
             }
+            keep = keep && !above;
         }
         a.flag[i] = keep ? 1 : 0;
     }
