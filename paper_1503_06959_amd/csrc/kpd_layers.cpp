@@ -78,7 +78,7 @@ struct LsLayout {
     kpd::LayerGeom g;
     int W = 0, H = 0, O = 0, nc = 0, nr = 0, ncell = 0;
     int slot_pitch = 0;
-    size_t off_ws = 0, off_slot[2] = {0, 0}, off_xs = 0, off_ys = 0, off_mask = 0, off_need = 0;
+    size_t off_ws = 0, off_slot[2] = {0, 0}, off_xs = 0, off_ys = 0, off_mask = 0, off_need = 0, off_new = 0;
     int rx = 0, ry = 0;   // cell radius of the scored neighbourhood of a marked cell
     size_t off_cnt[2] = {0, 0}, off_off[2] = {0, 0}, off_list[2] = {0, 0}, off_total = 0;
     uint32_t cap = 0;
@@ -107,6 +107,7 @@ bool ls_layout(int W, int H, const kpd_params* p, LsLayout* L, std::string* why)
     L->off_ys = off; off = align_up(off + (size_t)L->g.L * (L->nr + 1) * 4);
     L->off_mask = off; off = align_up(off + (size_t)L->ncell);
     L->off_need = off; off = align_up(off + (size_t)L->ncell);
+    L->off_new = off;  off = align_up(off + (size_t)L->ncell * 4);
     // A neighbour q (same or adjacent layer, footprints meeting) of a pixel
     // p has its level-0 footprint start within max(S_p, S_q) / 2 + 1 pixels
     // of p's, so within R = S_max / 2 + 1 pixels; points R apart lie at
@@ -293,6 +294,8 @@ int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, i
     a.total_cur = s->at<uint32_t>(L.off_total) + fc;
     a.cap = L.cap;
     a.need_score = s->at<uint8_t>(L.off_need);
+    a.cell_new = s->at<uint32_t>(L.off_new);
+    la.cell_new = a.cell_new;
     a.rx = L.rx;
     a.ry = L.ry;
     la.need_score = a.need_score;

@@ -50,6 +50,7 @@ struct LayArgs {
     // not suppressed; NULL for full-frame detection
     const uint8_t* need_score;
     const uint8_t* need_flag;
+    uint32_t* cell_new;   // keypoints found per cell (the masked stream; NULL otherwise)
     int nc, nr, W, H;
 };
 
@@ -78,6 +79,7 @@ struct LsArgs {
     uint32_t* total_cur;
     uint32_t cap;
     uint8_t* need_score;   // cells within (rx, ry) cells of a marked one
+    uint32_t* cell_new;    // keypoints the suppression keeps per marked cell
     int rx, ry;
 };
 

@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
             const int l = layer_of(a, i);
             const uint32_t r = i - a.base[l];
             const int w = a.w[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
-            keep = !a.need_flag || a.need_flag[pixel_cell(a, l, x, y)];
+            const int cell = a.need_flag ? pixel_cell(a, l, x, y) : 0;
+            keep = !a.need_flag || a.need_flag[cell];
             // Between adjacent layers the size ratio is 1.5 or 4/3, so a
             // range holds at most floor(ratio + 2) = 3 pixels a side: the
             // reads of a 3 x 3 window per layer are issued together, with
@@ -176,6 +177,7 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
                 }
             }
             keep = keep && !above;
+            if (keep && a.cell_new) atomicAdd(&a.cell_new[cell], 1u);
         }
         a.flag[i] = keep ? 1 : 0;
     }
@@ -330,6 +332,7 @@ __global__ __launch_bounds__(256) void k_ls_mask(LsArgs a)
 {
     __shared__ unsigned long long s_sum[4];
     const int c = blockIdx.x, cc = c % a.nc, rr = c / a.nc;
+    if (threadIdx.x == 0) a.cell_new[c] = 0;   // counted by this frame's suppression
     if (a.force) {
         if (threadIdx.x == 0) a.mask[c] = 1;
         return;
@@ -370,31 +373,9 @@ __global__ __launch_bounds__(256) void k_ls_dilate(LsArgs a)
     }
 }
 
-// Per cell: a marked cell's new keypoints (the flagged pixels of its box on
-// every layer), an unmarked cell's count in D_{n-1}.
-__global__ __launch_bounds__(256) void k_ls_count(LsArgs a, LayArgs l)
-{
-    __shared__ uint32_t s_cnt[4];
-    const int c = blockIdx.x, cc = c % a.nc, rr = c / a.nc;
-    if (!a.mask[c]) {
-        if (threadIdx.x == 0) a.cnt_cur[c] = a.cnt_prev[c];
-        return;
-    }
-    uint32_t cnt = 0;
-    for (int m = 0; m < l.L; ++m) {
-        const int x0 = (int)a.xs[m * (a.nc + 1) + cc], x1 = (int)a.xs[m * (a.nc + 1) + cc + 1];
-        const int y0 = (int)a.ys[m * (a.nr + 1) + rr], y1 = (int)a.ys[m * (a.nr + 1) + rr + 1];
-        const int bw = x1 - x0, n = bw * (y1 - y0);
-        const uint8_t* fl = l.flag + l.base[m];
-        for (int q = threadIdx.x; q < n; q += 256) cnt += fl[(size_t)(y0 + q / bw) * l.w[m] + (x0 + q % bw)];
-    }
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) a.cnt_cur[c] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-}
-
-// Exclusive prefix of the per-cell counts (one workgroup) and D_n's size.
+// D_n's per-cell counts (a marked cell's keypoints, as the suppression
+// counted them; an unmarked cell's count in D_{n-1}), their exclusive prefix
+// and D_n's size (one workgroup).
 __global__ __launch_bounds__(kScanBlock) void k_ls_scan(LsArgs a)
 {
     __shared__ uint32_t s_wave[kScanBlock / 64];
@@ -402,7 +383,11 @@ __global__ __launch_bounds__(kScanBlock) void k_ls_scan(LsArgs a)
     uint32_t carry = 0;
     for (int base = 0; base < a.ncell; base += kScanBlock) {
         const int i = base + threadIdx.x;
-        const uint32_t c = i < a.ncell ? a.cnt_cur[i] : 0;
+        uint32_t c = 0;
+        if (i < a.ncell) {
+            c = a.mask[i] ? a.cell_new[i] : a.cnt_prev[i];
+            a.cnt_cur[i] = c;
+        }
         uint32_t incl = c;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t o = __shfl_up(incl, off);
@@ -486,7 +471,6 @@ hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s)
 
 hipError_t launch_ls_emit(const LsArgs& a, const LayArgs& l, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ls_count, dim3(a.ncell), dim3(256), 0, s, a, l);
     hipLaunchKernelGGL(k_ls_scan, dim3(1), dim3(kScanBlock), 0, s, a);
     hipLaunchKernelGGL(k_ls_write, dim3(a.ncell), dim3(256), 0, s, a, l);
     return hipGetLastError();
