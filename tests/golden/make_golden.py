@@ -16,10 +16,12 @@ import oracle  # noqa: E402
 from paper_1503_06959_amd import synth  # noqa: E402
 
 
-def write_stream_fixture(name, scene, det, n_frames, cite):
+def write_stream_fixture(name, scene, det, n_frames, cite, layers=False):
     frames = synth.make_video(scene, n_frames)
     s = oracle.Stream(scene.width, scene.height, det.fast_t, det.n_octaves, det.grid_cols,
                       det.grid_rows, det.id_thresh, det.kb_thresh)
+    if layers:
+        s.set_layers(True)
     path = os.path.join(HERE, name)
     with open(path, "w") as f:
         f.write(f"# {cite}\n")
@@ -34,6 +36,24 @@ def write_stream_fixture(name, scene, det, n_frames, cite):
     print("wrote", path)
 
 
+def write_tcd_fixture(name, scene, det, n_frames, gop, t_bm, t_et, cite):
+    frames = synth.make_video(scene, n_frames)
+    s = oracle.Tcd(scene.width, scene.height, det.fast_t, det.n_octaves, det.grid_cols, det.grid_rows,
+                   gop, t_bm, t_et)
+    path = os.path.join(HERE, name)
+    with open(path, "w") as f:
+        f.write(f"# {cite}\n")
+        f.write(f"# scene {scene}\n# detector {det}\n# gop {gop} t_bm {t_bm} t_et {t_et}\n")
+        f.write("# per frame: 'frame n count' then 'x4 y4 octave score sad' lines\n")
+        for i in range(n_frames):
+            s.push(frames[i])
+            tr = s.tracks()
+            f.write(f"frame {i} {len(tr)}\n")
+            for t in tr:
+                f.write(f"{t['x4']} {t['y4']} {t['octave']} {t['score']} {t['sad']}\n")
+    print("wrote", path)
+
+
 if __name__ == "__main__":
     write_stream_fixture(
         "c1_320x240_first4.txt", synth.SCENES["c1_320x240"], synth.DETECTORS["c1_320x240"], 4,
@@ -43,3 +63,11 @@ if __name__ == "__main__":
     write_stream_fixture(
         "c1_320x240_kb2_first4.txt", synth.SCENES["c1_320x240"], kb, 4,
         "keypoint-binning mask only, T_H = 2 (Sec. 3.2 Eqs. 3-4), carry-forward (Sec. 3 Eq. 1)")
+    write_stream_fixture(
+        "c1_320x240_layers_first4.txt", synth.SCENES["c1_320x240"], synth.DETECTORS["c1_320x240"], 4,
+        "the masked stream over octaves and intra-octaves (Sec. 2 layers, Sec. 3.1 mask, Sec. 3 Eq. 1); "
+        "the octave column holds the layer index", layers=True)
+    write_tcd_fixture(
+        "c1_320x240_tcd_first7.txt", synth.SCENES["c1_320x240"], synth.DETECTORS["c1_320x240"], 7, 3, 1800, 1000,
+        "the temporally coherent detector of Sec. 4: groups of 3, 16x16 quarter-pixel block matching, "
+        "T_BM = 1800, T_ET = 1000")

@@ -17,3 +17,18 @@ def read_stream_fixture(name):
             else:
                 frames[-1][1].append(tuple(int(v) for v in parts))
     return frames
+
+
+def read_tcd_fixture(name):
+    """Returns a list of [(x4, y4, octave, score, sad), ...] per frame."""
+    frames = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "frame":
+                frames.append([])
+            else:
+                frames[-1].append(tuple(int(v) for v in parts))
+    return frames

@@ -760,6 +760,33 @@ def test_oracle_reproduces_stored_fixture(name, det):
         assert kps_tuples(got) == kps
 
 
+def test_oracle_reproduces_stored_layer_stream_fixture():
+    from golden_io import read_stream_fixture
+    from paper_1503_06959_amd import synth
+    exp = read_stream_fixture("c1_320x240_layers_first4.txt")
+    sc = synth.SCENES["c1_320x240"]
+    frames = synth.make_video(sc, len(exp))
+    s = oracle.Stream(sc.width, sc.height, 30, 3, 8, 6, 8, KB_OFF)
+    s.set_layers(True)
+    for f, (mask_bits, kps) in zip(frames, exp):
+        s.push(f)
+        got, mask, _, _ = s.get()
+        assert "".join(str(int(m)) for m in mask) == mask_bits
+        assert kps_tuples(got) == kps
+
+
+def test_oracle_reproduces_stored_tcd_fixture():
+    from golden_io import read_tcd_fixture
+    from paper_1503_06959_amd import synth
+    exp = read_tcd_fixture("c1_320x240_tcd_first7.txt")
+    sc = synth.SCENES["c1_320x240"]
+    frames = synth.make_video(sc, len(exp))
+    s = oracle.Tcd(sc.width, sc.height, 30, 3, 8, 6, 3, 1800, 1000)
+    for f, tr in zip(frames, exp):
+        s.push(f)
+        assert [tuple(int(v) for v in r) for r in s.tracks()] == tr
+
+
 # ------------------------------------------- temporally coherent detector
 
 def _texture(seed, h, w, passes=3, width=5):
