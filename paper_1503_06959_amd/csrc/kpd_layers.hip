@@ -409,26 +409,30 @@ __global__ __launch_bounds__(kScanBlock) void k_ls_scan(LsArgs a)
 
 // D_n, one workgroup per cell: a marked cell emits the flagged pixels of
 // its boxes layer by layer in row-major order (ballot ranks, wave counts in
-// LDS), an unmarked cell copies its entries of D_{n-1}.
-__global__ __launch_bounds__(256) void k_ls_write(LsArgs a, LayArgs l)
+// LDS, 1024 pixels a round) and stops once it has emitted the count the
+// suppression found; an unmarked cell copies its entries of D_{n-1}.
+constexpr int kLsWrite = 1024;
+
+__global__ __launch_bounds__(kLsWrite) void k_ls_write(LsArgs a, LayArgs l)
 {
-    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_cnt[kLsWrite / 64];
     const int c = blockIdx.x, cc = c % a.nc, rr = c / a.nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t dst = a.off_cur[c];
     if (!a.mask[c]) {
         const uint32_t src = a.off_prev[c], n = a.cnt_prev[c];
-        for (uint32_t i = threadIdx.x; i < n; i += 256)
+        for (uint32_t i = threadIdx.x; i < n; i += kLsWrite)
             if (src + i < a.cap && dst + i < a.cap) a.list_cur[dst + i] = a.list_prev[src + i];
         return;
     }
+    const uint32_t want = a.cnt_cur[c];
     uint32_t run = 0;
-    for (int m = 0; m < l.L; ++m) {
+    for (int m = 0; m < l.L && run < want; ++m) {
         const int x0 = (int)a.xs[m * (a.nc + 1) + cc], x1 = (int)a.xs[m * (a.nc + 1) + cc + 1];
         const int y0 = (int)a.ys[m * (a.nr + 1) + rr], y1 = (int)a.ys[m * (a.nr + 1) + rr + 1];
         const int bw = x1 - x0, n = bw * (y1 - y0);
         const size_t fb = l.base[m];
-        for (int base = 0; base < n; base += 256) {
+        for (int base = 0; base < n && run < want; base += kLsWrite) {
             const int q = base + threadIdx.x;
             int x = 0, y = 0;
             bool f = false;
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(256) void k_ls_write(LsArgs a, LayArgs l)
             if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(b);
             __syncthreads();
             uint32_t pos = run + (uint32_t)__popcll(b & ((1ull << lane) - 1)), total = 0;
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < kLsWrite / 64; ++k) {
                 pos += k < wave ? s_cnt[k] : 0;
                 total += s_cnt[k];
             }
@@ -472,7 +476,7 @@ hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s)
 hipError_t launch_ls_emit(const LsArgs& a, const LayArgs& l, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ls_scan, dim3(1), dim3(kScanBlock), 0, s, a);
-    hipLaunchKernelGGL(k_ls_write, dim3(a.ncell), dim3(256), 0, s, a, l);
+    hipLaunchKernelGGL(k_ls_write, dim3(a.ncell), dim3(kLsWrite), 0, s, a, l);
     return hipGetLastError();
 }
 
