@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--layer", type=int, default=None,
                     help="with --mode masked: the per-pixel mask on this pyramid layer (single-frame pushes)")
     ap.add_argument("--tile", type=int, default=0, help="level-0 tile of the tile pass (0: the library default)")
+    ap.add_argument("--groups", default="0x0x0", metavar="CxRxT",
+                    help="cells per workgroup (columns x rows) and threads of full-frame chunk detection "
+                         "(0x0x0: the library default)")
     ap.add_argument("--profile-script", metavar="OUTDIR", help="print the rocprofv3 script for the profiles")
     ap.add_argument("--summarize-profiles", metavar="OUTDIR", help="write profiles/ from that script's output")
     return ap.parse_args()
@@ -106,6 +109,7 @@ class Workload:
 
 
 TILE = 0
+GROUPS = (0, 0, 0)   # cells per workgroup of full-frame chunk detection (cols, rows) and its threads; 0: default
 
 
 def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool = False, kb_thresh=None,
@@ -114,7 +118,7 @@ def open_stream(wl: Workload, id_thresh: int, chunk: int = 0, layer_mask: bool =
     d = wl.det
     kb = d.kb_thresh if kb_thresh is None else kb_thresh
     params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, kb, TILE, chunk,
-                             int(layer_mask), features)
+                             int(layer_mask), features, *GROUPS)
     s = kpd.Stream(wl.W, wl.H, params)
     s.chunk = chunk
     return s
@@ -976,8 +980,9 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     from paper_1503_06959_amd import kpd
-    global TILE
+    global TILE, GROUPS
     TILE = args.tile
+    GROUPS = tuple(int(v) for v in args.groups.split("x"))
 
     wl = Workload(args.workload)
     if args.mode != "both":

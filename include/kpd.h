@@ -92,7 +92,17 @@ extern "C" {
  *              sector and a 512-bit binary descriptor (get_descriptors);
  *              KPD_FEAT_REFINE, the sub-pixel position and sub-scale of
  *              Sec. 2's interpolation (get_refined). push_frame only, mask
- *              mode 0. 0: nothing. */
+ *              mode 0. 0: nothing.
+ *   group_cols, group_rows
+ *              cells one detection workgroup covers when a chunk's
+ *              parameters mark every cell (full-frame detection): a
+ *              rectangle of group_cols x group_rows cells shares one pixel
+ *              tile and one score map per octave. A tuning knob that never
+ *              changes results: 0, 0 picks the default; otherwise
+ *              1..grid_cols and 1..grid_rows.
+ *   group_threads
+ *              threads of those workgroups: 0 (the default, 256), 256 or
+ *              512; never changes results. */
 typedef struct kpd_params {
     int32_t fast_t;
     int32_t n_octaves;
@@ -104,6 +114,9 @@ typedef struct kpd_params {
     int32_t chunk_frames;
     int32_t layer_mask;
     int32_t features;
+    int32_t group_cols;
+    int32_t group_rows;
+    int32_t group_threads;
 } kpd_params;
 
 #define KPD_FEAT_DESCRIPTOR 1
@@ -137,13 +150,20 @@ size_t stream_bytes(int width, int height, const kpd_params* params);
 int open_stream(int width, int height, const kpd_params* params, void* dev_arena,
                 size_t arena_bytes, void* hip_stream, kpd_stream** out);
 
-/* Change t, T_I and T_H from the next pushed frame on. A change of t re-marks
- * every cell of the next frame, since carried scores depend on t. */
+/* Change the AST threshold t (Sec. 2), the intensity-difference threshold
+ * T_I (Sec. 3.1, Eq. 2) and the keypoint-count threshold T_H (Sec. 3.2,
+ * Eqs. 3-4) from the next pushed frame on. A change of t re-marks every cell
+ * of the next frame, since carried scores depend on t. KPD_EINVAL when t is
+ * outside 1..254, KPD_ESTATE on a closed handle. */
 int set_thresholds(kpd_stream* s, int32_t fast_t, int32_t id_thresh, uint32_t kb_thresh);
 
-/* Process the next frame I_n (uint8 grey, width x height, rows `pitch_bytes`
- * apart, pitch >= width). Asynchronous: enqueues the mask, pyramid,
- * detection and output kernels and returns. Flags:
+/* Process the next frame I_n (Sec. 3: uint8 grey, width x height, rows
+ * `pitch_bytes` apart, pitch >= width): the cell mask M_n (Sec. 3.1 Eq. 2
+ * read per cell, Sec. 3.2 Eqs. 3-4), the octave pyramid and detection in
+ * the marked cells (Sec. 2), and D_n by Eq. 1 (new keypoints of marked
+ * cells, D_{n-1}'s of the others). Asynchronous: enqueues the kernels and
+ * returns; KPD_EINVAL for a bad pitch or flag, KPD_EDEVICE when a launch
+ * fails. Flags:
  *   KPD_FRAME_HOST           `frame` is host memory, copied into the arena;
  *                            it must stay valid until the stream has
  *                            synchronised (get_keypoints does).
@@ -155,8 +175,11 @@ int set_thresholds(kpd_stream* s, int32_t fast_t, int32_t id_thresh, uint32_t kb
 int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
 
 /* Process `n_frames` consecutive frames (1 <= n_frames <= chunk_frames) in
- * one pass of three launches: a pyramid/difference pass over all of them, a
- * detection pass over every (frame, cell), and a compaction pass per frame.
+ * one pass of three to six launches: a pyramid/difference pass over all of
+ * them, the mark passes (none when the parameters mark every cell), a
+ * detection pass over the marked (frame, cell) items or, when every cell is
+ * marked, over every (frame, group of cells), and a compaction pass per
+ * frame that applies Eq. 1.
  * Frame i is the device buffer frames + i * frame_stride (rows pitch_bytes
  * apart), read in place under the KPD_FRAME_DEVICE_RETAIN rules (the last
  * frame is I_{n-1} of the next push). Results are exactly those of pushing
@@ -233,8 +256,9 @@ typedef struct kpd_refined {
  * KPD_FEAT_REFINE); like get_descriptors otherwise. */
 int get_refined(kpd_stream* s, kpd_refined* out, size_t capacity, size_t* count);
 
-/* Wait for the last pushed frame and copy D_n to host memory `out`, ordered
- * by cell (row-major), then octave, then y, then x. `*count` receives the
+/* Wait for the last pushed frame and copy D_n (Sec. 3's feature set of
+ * frame n, Eq. 1) to host memory `out`, ordered by cell (row-major), then
+ * octave, then y, then x. `*count` receives the
  * number of keypoints; when it exceeds `capacity`, nothing is copied and
  * KPD_ETRUNC is returned. `cell_mask` (nullable, N_r*N_c bytes, row-major)
  * receives M_n (1 = detected this frame, 0 = carried). KPD_ESTATE before the
@@ -334,7 +358,7 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
  * compaction pass that builds each frame's D_n in cell order. */
 #define KPD_K_FRAME 0
 #define KPD_K_DETECT 1
-#define KPD_K_COMPACT 2 /* compaction pass of push_frames */
+#define KPD_K_COMPACT 2 /* compaction pass (Eq. 1) of push_frame and push_frames */
 #define KPD_K_MARK 3    /* mark, speculation and resolve passes of push_frames */
 #define KPD_K_DESCRIBE 4 /* feature pass of push_frame: descriptors, refinement */
 #define KPD_NKERNELS 5

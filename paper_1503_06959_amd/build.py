@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkpd.so")
-SOURCES = [os.path.join(CSRC, "kpd_api.cpp"), os.path.join(CSRC, "kpd_kernels.hip"),
+SOURCES = [os.path.join(CSRC, "kpd_api.cpp"), os.path.join(CSRC, "kpd_kernels.hip"), os.path.join(CSRC, "kpd_group.hip"),
            os.path.join(CSRC, "kpd_tcd.cpp"), os.path.join(CSRC, "kpd_tcd.hip"),
            os.path.join(CSRC, "kpd_layers.cpp"), os.path.join(CSRC, "kpd_layers.hip")]
 HEADERS = [os.path.join(CSRC, "kpd_geom.h"), os.path.join(CSRC, "kpd_kernels.h"), os.path.join(CSRC, "kpd_tcd.h"), os.path.join(CSRC, "kpd_errors.h"),

@@ -80,6 +80,14 @@ struct Layout {
     // and a second buffer for octave 1.. so the layer of I_{n-1} survives
     int lds_bits = 0, lds_carr = 0, lds_cwoff = 0, lds_cscore = 0, lds_bytes1 = 0;
     size_t off_lvl_alt = 0;
+    // the group detector of full-frame chunks: gx x gy cells per workgroup
+    // and the groups' layouts
+    int gx = 1, gy = 1, ngroups = 0, glds = 0, gthreads = 256;
+    size_t off_glay = 0;
+    // single frames: one-cell layouts of the same detector, and its LDS at
+    // 256 and 512 threads
+    size_t off_glay1 = 0;
+    int glds1_256 = 0, glds1_512 = 0;
     size_t total = 0;
 };
 
@@ -116,8 +124,62 @@ bool valid_params(int W, int H, const kpd_params* p, std::string* why)
     }
     if (p->layer_mask != 0 && p->layer_mask != 1) { *why = "layer_mask must be 0 or 1"; return false; }
     if (p->features & ~(KPD_FEAT_DESCRIPTOR | KPD_FEAT_REFINE)) { *why = "unknown feature bits"; return false; }
+    if ((p->group_cols == 0) != (p->group_rows == 0) || p->group_cols < 0 || p->group_rows < 0 ||
+        p->group_cols > p->grid_cols || p->group_rows > p->grid_rows) {
+        *why = "group_cols and group_rows must both be 0 or in 1..grid_cols and 1..grid_rows";
+        return false;
+    }
+    if (p->group_cols * p->group_rows > kpd::kGroupMaxCells) {
+        *why = "at most " + std::to_string(kpd::kGroupMaxCells) + " cells per group";
+        return false;
+    }
+    if (p->group_threads != 0 && p->group_threads != 256 && p->group_threads != 512) {
+        *why = "group_threads must be 0, 256 or 512";
+        return false;
+    }
     return true;
 }
+
+// Layouts of every group of gx x gy cells (row-major over the group grid);
+// false when a group is too large for the detector. *lds: the largest
+// workgroup LDS need at `waves` waves.
+// Each cell's first entry in a keypoint list of one feature per 2x2 block
+// of its decision boxes (cells in row-major order).
+std::vector<uint32_t> cell_bases(const Layout& L)
+{
+    std::vector<uint32_t> base(L.ncell);
+    uint32_t acc = 0;
+    for (int c = 0; c < L.ncell; ++c) {
+        base[c] = acc;
+        const kpd::Box r = kpd::cell_rect(c, L.W, L.H, L.nc, L.nr);
+        for (int o = 0; o < L.O; ++o) acc += (uint32_t)kpd::decision_capacity(kpd::decision_box(r, o, L.w[o], L.h[o]));
+    }
+    return base;
+}
+
+bool group_layouts(const Layout& L, int gx, int gy, int waves, std::vector<kpd::GroupLayout>* out, int* lds)
+{
+    const int ngc = (L.nc + gx - 1) / gx, ngr = (L.nr + gy - 1) / gy;
+    if (out) out->assign((size_t)ngc * ngr, kpd::GroupLayout{});
+    const std::vector<uint32_t> bases = out ? cell_bases(L) : std::vector<uint32_t>();
+    *lds = 0;
+    for (int r = 0; r < ngr; ++r)
+        for (int q = 0; q < ngc; ++q) {
+            const int c0 = q * gx, c1 = std::min(c0 + gx, L.nc), r0 = r * gy, r1 = std::min(r0 + gy, L.nr);
+            const kpd::Box a = kpd::cell_rect(r0 * L.nc + c0, L.W, L.H, L.nc, L.nr);
+            const kpd::Box b = kpd::cell_rect((r1 - 1) * L.nc + c1 - 1, L.W, L.H, L.nc, L.nr);
+            kpd::GroupLayout G;
+            if (!kpd::group_layout(kpd::Box{a.x0, b.x1, a.y0, b.y1}, L.O, L.w, L.h, c0, c1, r0, r1, L.W, L.H, L.nc,
+                                   L.nr, out ? bases.data() : nullptr, &G))
+                return false;
+            *lds = std::max(*lds, kpd::group_lds_bytes(G, waves));
+            if (out) (*out)[(size_t)r * ngc + q] = G;
+        }
+    return true;
+}
+
+constexpr int kGroupWaves = 4;           // 256-thread workgroups for one-cell layouts
+constexpr int kGroupLdsDefault = 48 * 1024;   // default groups: three workgroups per CU
 
 bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
 {
@@ -204,6 +266,41 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
 
     L->K = std::max(1, (int)p->chunk_frames);
 
+    // groups of the full-frame chunk detector: the given shape, or the widest
+    // run of cells along a cell row (a power of two) that fits the default LDS
+    if (L->K > 1) {
+        int lds = 0;
+        L->gthreads = p->group_threads ? p->group_threads : 256;
+        const int waves = L->gthreads / 64;
+        if (p->group_cols > 0) {
+            L->gx = p->group_cols;
+            L->gy = p->group_rows;
+            if (!group_layouts(*L, L->gx, L->gy, waves, nullptr, &lds) || lds > 160 * 1024) {
+                *why = "group of cells too large for one workgroup";
+                return false;
+            }
+        } else {
+            L->gx = L->gy = 1;
+            if (!group_layouts(*L, 1, 1, waves, nullptr, &lds) || lds > 160 * 1024) {
+                *why = "cells too large for the group detector";
+                return false;
+            }
+            for (int g = 2; g <= L->nc && g <= kpd::kGroupMaxCells; g *= 2) {
+                int l2 = 0;
+                if (!group_layouts(*L, g, 1, waves, nullptr, &l2) || l2 > kGroupLdsDefault) break;
+                L->gx = g;
+                lds = l2;
+            }
+        }
+        L->glds = lds;
+        L->ngroups = ((L->nc + L->gx - 1) / L->gx) * ((L->nr + L->gy - 1) / L->gy);
+    }
+    if (!group_layouts(*L, 1, 1, 4, nullptr, &L->glds1_256) || !group_layouts(*L, 1, 1, 8, nullptr, &L->glds1_512) ||
+        L->glds1_512 > 160 * 1024) {
+        *why = "cells too large for the detector";
+        return false;
+    }
+
     size_t off = 0;
     L->off_hdr = off; off = align_up(off + 64);
     for (int k = 0; k < 2; ++k) { L->off_slot[k] = off; off = align_up(off + (size_t)L->slot_pitch * H); }
@@ -232,6 +329,7 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->off_cbase = off; off = align_up(off + (size_t)L->ncell * 4);
     L->off_own1 = off; off = align_up(off + (size_t)L->ncell * 4);
     L->off_sparse1 = off; off = align_up(off + L->list_cap1 * sizeof(kpd_keypoint));
+    L->off_glay1 = off; off = align_up(off + (size_t)L->ncell * sizeof(kpd::GroupLayout));
     if (p->features & KPD_FEAT_DESCRIPTOR) {   // descriptors of D_{n-1} and D_n, and the pattern tables
         for (int k = 0; k < 2; ++k) { L->off_desc[k] = off; off = align_up(off + L->list_cap1 * sizeof(kpd_descriptor)); }
         L->off_dtab = off; off = align_up(off + sizeof(kpd::DescTables));
@@ -252,6 +350,7 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
         L->off_clist = off; off += L->clist_stride * (size_t)(L->K - 1);   // the last frame's D goes to D_n
         L->off_ctab = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs));
+        L->off_glay = off; off = align_up(off + (size_t)L->ngroups * sizeof(kpd::GroupLayout));
     }
     L->total = off;
     return true;
@@ -302,6 +401,8 @@ struct kpd_stream {
     int id_layer = 0;
     int layer_buf = 0;        // the mask's octaves >= 1 of the latest frame: 0 their usual buffers, 1 the second copy
     int chunk_n = 0;          // frames of the last push_frames call
+    std::vector<kpd::GroupLayout> glay;   // the group detector's layouts (chunks)
+    std::vector<kpd::GroupLayout> glay1;  // its one-cell layouts (single frames)
     kpd::FrameArgs chunk_fa{};  // tile-pass arguments of chunk frame 0
     bool closed = false;
     // pinned host staging for get_keypoints: header, the first kStage
@@ -494,7 +595,7 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     int dev = 0, lds_max = 0;
     KPD_HIP(hipGetDevice(&dev));
     KPD_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (L.lds_bytes > std::max(lds_max, 65536))
+    if (L.lds_bytes > std::max(lds_max, 65536) || std::max(L.glds, L.glds1_512) > std::max(lds_max, 65536))
         return fail(KPD_EINVAL, "cells need more LDS than a workgroup can hold");
     KPD_HIP(kpd::set_detect_lds_limit(L.lds_bytes));
 
@@ -543,14 +644,7 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_layouts, layouts.data(), layouts.size() * sizeof(kpd::CellLayout),
                            hipMemcpyHostToDevice, s->stream);
-    std::vector<uint32_t> cbase(L.ncell);
-    {
-        uint32_t acc = 0;
-        for (int c = 0; c < L.ncell; ++c) {
-            cbase[c] = acc;
-            for (int o = 0; o < L.O; ++o) acc += (uint32_t)kpd::decision_capacity(layouts[c].dec[o]);
-        }
-    }
+    const std::vector<uint32_t> cbase = cell_bases(L);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess && (params->features & KPD_FEAT_DESCRIPTOR))
@@ -567,6 +661,19 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
             e = hipMemcpyAsync(s->arena + L.off_ctab, ctab.data(), ctab.size() * sizeof(kpd::ChunkArgs),
                                hipMemcpyHostToDevice, s->stream);
         s->chunk_fa = ftab[0];   // later frames' octaves and SAD follow at fixed strides
+        int glds = 0;
+        group_layouts(L, L.gx, L.gy, L.gthreads / 64, &s->glay, &glds);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->arena + L.off_glay, s->glay.data(), s->glay.size() * sizeof(kpd::GroupLayout),
+                               hipMemcpyHostToDevice, s->stream);
+    }
+    {
+        int glds = 0;
+        group_layouts(L, 1, 1, kGroupWaves, &s->glay1, &glds);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->arena + L.off_glay1, s->glay1.data(), s->glay1.size() * sizeof(kpd::GroupLayout),
+                               hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = kpd::set_group_lds_limit(std::max(L.glds, L.glds1_512));
     }
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&s->stage), 64 + kStage * sizeof(kpd_keypoint) + (size_t)L.ncell,
@@ -793,8 +900,26 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
     const Layout& L = s->L;
     if (t.f_on)
         KPD_HIP(timed(s, KPD_K_FRAME, [&] { return kpd::launch_frame(t.f, s->stream); }));
-    const int lds = s->id_mode != 0 ? L.lds_bytes1 : L.lds_bytes;
-    KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, lds, s->stream); }));
+    if (s->id_mode == 0) {
+        // marks and detection of the marked cells (no waits between cells),
+        // then D_n by Eq. 1 in one compaction workgroup
+        kpd::GroupArgs ga{};
+        ga.layouts = s->at<kpd::GroupLayout>(L.off_glay1);
+        ga.ngroups = L.ncell;
+        ga.nc = L.nc;
+        ga.al16 = (reinterpret_cast<uintptr_t>(t.d.lvl[0]) % 16 == 0 && t.d.pitch[0] % 16 == 0) ? 1 : 0;
+        const int threads = t.d.all_marked ? 256 : 512;
+        const int lds = threads == 512 ? L.glds1_512 : L.glds1_256;
+        KPD_HIP(timed(s, KPD_K_DETECT, [&] {
+            return kpd::launch_det1_groups(t.d, ga, t.sparse, t.own_count, L.ncell, lds, threads, s->stream);
+        }));
+        KPD_HIP(timed(s, KPD_K_COMPACT, [&] {
+            return kpd::launch_compact1(t.d, t.sparse, t.sparse_base, t.own_count, s->stream);
+        }));
+    } else {
+        const int lds = L.lds_bytes1;
+        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect(t.d, L.ncell, lds, s->stream); }));
+    }
     if (s->p.features) {
         const int fb_prev = s->fb_last, fb_cur = 1 - s->fb_last;
         kpd::DescArgs da{};
@@ -899,7 +1024,14 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         }));
     if (h.all_marked) {
         // every cell of every frame: one workgroup per (frame, cell)
-        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_chunk(ctab, h, L.lds_bytes, s->stream); }));
+        kpd::GroupArgs ga{};
+        ga.layouts = s->at<kpd::GroupLayout>(L.off_glay);
+        ga.ngroups = L.ngroups;
+        ga.nc = L.nc;
+        ga.al16 = (reinterpret_cast<uintptr_t>(frames) % 16 == 0 && frame_stride % 16 == 0 && pitch % 16 == 0) ? 1 : 0;
+        KPD_HIP(timed(s, KPD_K_DETECT, [&] {
+            return kpd::launch_detect_chunk_groups(ctab, h, ga, L.glds, L.gthreads, s->stream);
+        }));
     } else if (h.kb_chain) {
         // marks that depend on the counts: detect every frame a cell's chain
         // can mark, then walk each cell's frames to keep the marks

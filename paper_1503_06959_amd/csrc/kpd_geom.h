@@ -244,4 +244,179 @@ KPD_HD void cell_layout(const Box& rect, int O, const int* w, const int* h, Cell
 // largest layout takes `bytes` (with kDetectWaves queues).
 KPD_HD int detect_lds_for(int bytes, int waves) { return bytes - (kDetectWaves - waves) * kQueue * 2; }
 
+// ---------------------------------------------------------------- groups
+//
+// The group detector covers a rectangle of cells (columns [gc0, gc1), rows
+// [gr0, gr1)) with one workgroup. Per octave it keeps one pixel tile and
+// one score map for the whole group, so neighbouring cells share their
+// aprons, and emits every cell's keypoints in the cell's own (octave, y, x)
+// order at the cell's base in a list. On each level the union of the
+// cells' decision boxes is the decision box of the group's rectangle,
+// because the cells' column and row boundaries map to ceil(X / 2^o).
+//
+// Score pixels are taken in groups of eight consecutive columns (one lane,
+// two dwords of a tile row), starting at a multiple of 8: a group may
+// cover columns outside the score box, whose scores are computed too and
+// land in the score map (which covers them), and columns outside the
+// detectable interior, which the full test drops. The pixel tile starts at
+// a multiple of 16 (16-byte staging loads) four or more columns left of
+// the first group and ends four or more right of the last, and has the
+// 3-row ring apron above and below; its columns outside the level are not
+// loaded and are only read for pixels the full test drops.
+
+constexpr int kGroupQueue = 128;     // entries (u32) of each of a wave's two queues
+constexpr int kGroupMaxPitch = 2047;  // tile columns fit 11 bits,
+constexpr int kGroupMaxRows = 1023;   // tile rows 10 bits (queue entries)
+constexpr int kGroupCands = 512;      // candidates of a group listed for suppression
+constexpr int kGroupMaxCells = 16;    // cells of one group
+
+struct GroupLayout {
+    Box dec[KPD_MAX_OCTAVES];                       // union decision box
+    Box qb[KPD_MAX_OCTAVES];                        // query box (what suppression reads)
+    int mx0[KPD_MAX_OCTAVES], my0[KPD_MAX_OCTAVES]; // score-map origin (level coords)
+    int vpitch[KPD_MAX_OCTAVES];                    // score-map row pitch (u16 elements)
+    int voff[KPD_MAX_OCTAVES];                      // score-map LDS byte offset
+    int tx0[KPD_MAX_OCTAVES], ty0[KPD_MAX_OCTAVES]; // pixel tile origin (tx0 a multiple of 16, may be < 0)
+    int tpitch[KPD_MAX_OCTAVES], th[KPD_MAX_OCTAVES], toff[KPD_MAX_OCTAVES];
+    int gx0[KPD_MAX_OCTAVES];                       // first 8-px group column (level coords, multiple of 8)
+    int ngx[KPD_MAX_OCTAVES];                       // groups per score row
+    int sy0[KPD_MAX_OCTAVES], nsr[KPD_MAX_OCTAVES]; // first score row, score rows
+    uint64_t gcm[KPD_MAX_OCTAVES];                  // div magic: groups per row
+    uint64_t sgm[KPD_MAX_OCTAVES];                  // div magic: 16-byte segments per tile row
+    uint64_t wpm[KPD_MAX_OCTAVES];                  // div magic: bitmap words per row
+    int ck_start[KPD_MAX_OCTAVES + 1];              // first 64-group chunk of each octave
+    int sg_start[KPD_MAX_OCTAVES + 1];              // first 16-byte tile segment of each octave
+    int cwoff[KPD_MAX_OCTAVES + 1];                 // first bitmap word of each octave
+    int wpr[KPD_MAX_OCTAVES];                       // bitmap words per decision row
+    int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];     // level sizes
+    int nwords;                                     // words of each bitmap
+    int cand_off;                                   // keep bitmap at 0, candidate bitmap here
+    int zero_bytes;                                 // bitmaps and score maps: cleared per group
+    int queue_off;                                  // wave queues, after the tiles
+    int gc0, gc1, gr0, gr1;                         // cells covered
+    int O;
+    int ncells;                                     // (gc1 - gc0) x (gr1 - gr0), row-major
+    // per cell: its index, its first entry in a keypoint list, and its
+    // level-0 rectangle (the cell's decision boxes follow from it)
+    int cell_c[kGroupMaxCells];
+    uint32_t cell_base[kGroupMaxCells];
+    Box cell_rect[kGroupMaxCells];
+};
+
+// Floor division by 16 for possibly negative values.
+KPD_HD int floor16(int v) { return v >= 0 ? (v & ~15) : -((-v + 15) & ~15); }
+
+// Layout of the group of cells [gc0, gc1) x [gr0, gr1) of a frame W x H
+// with nc x nr cells, whose level-0 rectangle is r; bases (nullable) gives
+// each cell's first entry in a keypoint list. Returns false when the group
+// has more than kGroupMaxCells cells or a tile is too large for the 11-bit
+// columns and 10-bit rows of the detector's queue entries.
+KPD_HD bool group_layout(const Box& r, int O, const int* w, const int* h, int gc0, int gc1, int gr0, int gr1,
+                         int W, int H, int nc, int nr, const uint32_t* bases, GroupLayout* G)
+{
+    G->O = O;
+    G->gc0 = gc0; G->gc1 = gc1; G->gr0 = gr0; G->gr1 = gr1;
+    G->ncells = (gc1 - gc0) * (gr1 - gr0);
+    if (G->ncells > kGroupMaxCells) return false;
+    for (int k = 0; k < kGroupMaxCells; ++k) {
+        G->cell_c[k] = 0;
+        G->cell_base[k] = 0;
+        G->cell_rect[k] = Box{0, 0, 0, 0};
+        if (k < G->ncells) {
+            const int c = (gr0 + k / (gc1 - gc0)) * nc + gc0 + k % (gc1 - gc0);
+            G->cell_c[k] = c;
+            G->cell_base[k] = bases ? bases[c] : 0u;
+            G->cell_rect[k] = cell_rect(c, W, H, nc, nr);
+        }
+    }
+    for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
+        G->dec[o] = G->qb[o] = Box{0, 0, 0, 0};
+        G->mx0[o] = G->my0[o] = G->vpitch[o] = G->voff[o] = 0;
+        G->tx0[o] = G->ty0[o] = G->tpitch[o] = G->th[o] = G->toff[o] = 0;
+        G->gx0[o] = G->ngx[o] = G->sy0[o] = G->nsr[o] = 0;
+        G->gcm[o] = G->sgm[o] = G->wpm[o] = 0;
+        G->wpr[o] = 0;
+        G->w[o] = o < O ? w[o] : 0;
+        G->h[o] = o < O ? h[o] : 0;
+    }
+    Box dec[KPD_MAX_OCTAVES];
+    for (int o = 0; o < O; ++o) dec[o] = decision_box(r, o, w[o], h[o]);
+    for (int o = 0; o < O; ++o) {
+        G->dec[o] = box_empty(dec[o]) ? Box{0, 0, 0, 0} : dec[o];
+        G->qb[o] = query_box(dec, o, O);
+    }
+    // bitmaps: rows of each decision box, whole words per row
+    int nw = 0;
+    for (int o = 0; o < O; ++o) {
+        G->cwoff[o] = nw;
+        if (box_empty(G->dec[o])) continue;
+        G->wpr[o] = (box_w(G->dec[o]) + 63) / 64;
+        nw += G->wpr[o] * box_h(G->dec[o]);
+    }
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) G->cwoff[o] = nw;
+    G->nwords = nw;
+    int off = 0;
+    off += nw * 8;
+    G->cand_off = off;
+    off += nw * 8;
+    off = round_up(off, 16);
+    // score groups and maps
+    int ck = 0;
+    for (int o = 0; o < O; ++o) {
+        G->ck_start[o] = ck;
+        const Box sb = score_box(dec, o, O, w[o], h[o]);
+        const Box q = G->qb[o];
+        if (box_empty(q)) continue;
+        int mx0 = q.x0, mx1 = q.x1;
+        if (!box_empty(sb)) {
+            G->gx0[o] = sb.x0 & ~7;
+            G->ngx[o] = ((sb.x1 + 7) & ~7) / 8 - G->gx0[o] / 8;
+            G->sy0[o] = sb.y0;
+            G->nsr[o] = box_h(sb);
+            const int sx0 = imax(G->gx0[o], kRingR), sx1 = imin(G->gx0[o] + 8 * G->ngx[o], w[o] - kRingR);
+            mx0 = imin(mx0, sx0);
+            mx1 = imax(mx1, sx1);
+            ck += (G->ngx[o] * G->nsr[o] + 63) / 64;
+        }
+        G->mx0[o] = mx0;
+        G->my0[o] = q.y0;
+        G->vpitch[o] = mx1 - mx0;
+        G->voff[o] = off;
+        off += round_up(G->vpitch[o] * box_h(q) * 2, 16);
+    }
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) G->ck_start[o] = ck;
+    G->zero_bytes = off;
+    // pixel tiles
+    int sg = 0;
+    for (int o = 0; o < O; ++o) {
+        G->sg_start[o] = sg;
+        G->toff[o] = off;
+        if (G->nsr[o] == 0) continue;
+        G->tx0[o] = floor16(G->gx0[o] - 4);
+        const int tx1 = round_up(G->gx0[o] + 8 * G->ngx[o] + 4, 16);
+        G->tpitch[o] = tx1 - G->tx0[o];
+        G->ty0[o] = G->sy0[o] - kRingR;
+        G->th[o] = G->nsr[o] + 2 * kRingR;
+        if (G->tpitch[o] > kGroupMaxPitch || G->th[o] > kGroupMaxRows) return false;
+        off += G->tpitch[o] * G->th[o];
+        sg += (G->tpitch[o] / 16) * G->th[o];
+    }
+    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) G->sg_start[o] = sg;
+    G->queue_off = round_up(off, 16);
+
+    for (int o = 0; o < O; ++o) {
+        G->gcm[o] = div_magic(imax(G->ngx[o], 1));
+        G->sgm[o] = div_magic(imax(G->tpitch[o] / 16, 1));
+        G->wpm[o] = div_magic(imax(G->wpr[o], 1));
+    }
+    return true;
+}
+
+// Dynamic LDS of a group workgroup of `waves` waves: two queues a wave,
+// then the suppression list (kGroupCands entries and its count).
+KPD_HD int group_lds_bytes(const GroupLayout& G, int waves)
+{
+    return G.queue_off + waves * 2 * kGroupQueue * 4 + kGroupCands * 4 + 16;
+}
+
 }  // namespace kpd

@@ -206,6 +206,25 @@ struct CompactArgs {
     uint32_t* work_count;            // both words cleared for the next chunk
 };
 
+// The group detector: the groups' layouts (a rectangle of cells each,
+// row-major over the group grid; each layout names its cells and their
+// list bases) and whether level 0's rows can be read 16 bytes at a time.
+struct GroupArgs {
+    const GroupLayout* layouts;
+    int ngroups, nc;
+    int al16;
+};
+
+hipError_t launch_detect_chunk_groups(const ChunkArgs* table, const ChunkHead& h, const GroupArgs& g, int lds_bytes,
+                                      int threads, hipStream_t s);
+hipError_t set_group_lds_limit(int lds_bytes);
+// one frame with the per-cell mask: marks and detection of the marked cells
+// with one-cell layouts (sparse list), then D_n by k_compact1
+hipError_t launch_det1_groups(const DetectArgs& a, const GroupArgs& g, kpd_keypoint* sparse, uint32_t* own,
+                              int ncell, int lds_bytes, int threads, hipStream_t s);
+hipError_t launch_compact1(const DetectArgs& a, const kpd_keypoint* sparse, const uint32_t* cbase,
+                           const uint32_t* own, hipStream_t s);
+
 hipError_t launch_frame_chunk(const FrameArgs& a, size_t pyr_stride, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s);

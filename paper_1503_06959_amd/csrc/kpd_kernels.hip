@@ -1819,6 +1819,66 @@ __global__ __launch_bounds__(NT) void k_detect_list_batch(const TickArgs* table,
     }
 }
 
+// D_n of one frame of one stream after k_det1_groups (Eq. 1): marked cells
+// take their new keypoints from the sparse list, the others D_{n-1}'s. A
+// workgroup per run of kCells1 cells: it sums the counts of every earlier
+// cell for its base offset, scans its own cells' counts and copies their
+// entries, a wave per cell; the last workgroup writes the total.
+constexpr int kCells1 = 16;
+constexpr int kCompact1Block = 256;
+
+__global__ __launch_bounds__(kCompact1Block) void k_compact1(DetectArgs a, const kpd_keypoint* sparse,
+                                                            const uint32_t* cbase, const uint32_t* own)
+{
+    __shared__ uint32_t s_wsum[kCompact1Block / 64];
+    __shared__ uint32_t s_off[kCells1], s_n[kCells1];
+    __shared__ const kpd_keypoint* s_src[kCells1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ncell = a.nc * a.nr;
+    const int c0 = blockIdx.x * kCells1, c1 = min(c0 + kCells1, ncell);
+    auto count_of = [&](int c) -> uint32_t {
+        return a.mask[c] ? clamp_count(cbase[c], own[c], a.list_cap)
+                         : clamp_count(a.off_prev[c], a.count_prev[c], a.list_cap);
+    };
+    uint32_t acc = 0;
+    for (int c = tid; c < c0; c += kCompact1Block) acc += count_of(c);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) s_wsum[wave] = acc;
+    if (tid < c1 - c0) {
+        const int c = c0 + tid;
+        s_n[tid] = count_of(c);
+        s_src[tid] = a.mask[c] ? sparse + cbase[c] : a.list_prev + a.off_prev[c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t base = 0;
+        for (int w = 0; w < kCompact1Block / 64; ++w) base += s_wsum[w];
+        for (int k = 0; k < c1 - c0; ++k) {
+            s_off[k] = base;
+            a.count_cur[c0 + k] = s_n[k];
+            a.off_cur[c0 + k] = base;
+            base += s_n[k];
+        }
+        if (c1 == ncell) *a.total_cur = base;
+    }
+    __syncthreads();
+    for (int k = wave; k < c1 - c0; k += kCompact1Block / 64) {
+        const uint32_t n = s_n[k], off = s_off[k];
+        const kpd_keypoint* src = s_src[k];
+        for (uint32_t e = lane; e < n; e += 64)
+            if (off + e < a.list_cap) a.list_cur[off + e] = src[e];
+    }
+}
+
+hipError_t launch_compact1(const DetectArgs& a, const kpd_keypoint* sparse, const uint32_t* cbase,
+                           const uint32_t* own, hipStream_t s)
+{
+    const int ncell = a.nc * a.nr;
+    hipLaunchKernelGGL(k_compact1, dim3((ncell + kCells1 - 1) / kCells1), dim3(kCompact1Block), 0, s, a, sparse,
+                       cbase, own);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kCompact) void k_compact_batch(const TickArgs* table, uint32_t* work_count)
 {
     const TickArgs& t = table[blockIdx.x];

@@ -53,7 +53,9 @@ class KpdParams(ctypes.Structure):
                 ("grid_cols", ctypes.c_int32), ("grid_rows", ctypes.c_int32),
                 ("id_thresh", ctypes.c_int32), ("kb_thresh", ctypes.c_uint32),
                 ("tile", ctypes.c_int32), ("chunk_frames", ctypes.c_int32),
-                ("layer_mask", ctypes.c_int32), ("features", ctypes.c_int32)]
+                ("layer_mask", ctypes.c_int32), ("features", ctypes.c_int32),
+                ("group_cols", ctypes.c_int32), ("group_rows", ctypes.c_int32),
+                ("group_threads", ctypes.c_int32)]
 
 
 class KpdTcdParams(ctypes.Structure):
@@ -142,10 +144,13 @@ def _check(rc: int) -> int:
 
 def make_params(fast_t: int, n_octaves: int, grid_cols: int, grid_rows: int,
                 id_thresh: int = 8, kb_thresh: int = KPD_KB_OFF, tile: int = 0, chunk_frames: int = 0,
-                layer_mask: int = 0, features: int = 0) -> KpdParams:
-    """features: FEAT_DESCRIPTOR | FEAT_REFINE bits."""
+                layer_mask: int = 0, features: int = 0, group_cols: int = 0, group_rows: int = 0,
+                group_threads: int = 0) -> KpdParams:
+    """features: FEAT_DESCRIPTOR | FEAT_REFINE bits; group_cols x group_rows:
+    cells per workgroup of full-frame chunk detection and group_threads its
+    threads (0: defaults)."""
     return KpdParams(fast_t, n_octaves, grid_cols, grid_rows, id_thresh, kb_thresh & 0xFFFFFFFF, tile, chunk_frames,
-                     layer_mask, features)
+                     layer_mask, features, group_cols, group_rows, group_threads)
 
 
 def stream_bytes(width: int, height: int, params: KpdParams) -> int:

@@ -52,7 +52,7 @@ def test_library_exports_every_declared_symbol(kpd):
 
 
 def test_struct_layouts_match_header(kpd):
-    assert ctypes.sizeof(kpd.KpdParams) == 40
+    assert ctypes.sizeof(kpd.KpdParams) == 52
     assert kpd.KEYPOINT_DTYPE.itemsize == 8
     assert kpd.KEYPOINT_DTYPE.fields["octave"][1] == 4
     assert kpd.KEYPOINT_DTYPE.fields["score"][1] == 6
@@ -143,6 +143,39 @@ def test_cell_geometry_partitions_and_covers_neighbourhoods(geom_check, shape):
     assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
     lds = int(out.stdout.split()[1])
     assert lds <= 160 * 1024
+
+
+@pytest.fixture(scope="module")
+def group_check(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("group") / "group_check")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-o", exe, os.path.join(ROOT, "tests", "group_check.cpp")],
+                   check=True)
+    return exe
+
+
+@pytest.mark.parametrize("shape", [
+    "320 240 3 8 6 1 1", "320 240 3 8 6 3 1", "320 240 3 8 6 2 3", "320 240 3 8 6 8 2", "320 240 3 8 6 4 4",
+    "640 480 4 16 12 4 1", "640 480 4 16 12 4 2", "1920 1080 5 32 18 2 1", "1920 1080 5 32 18 4 1",
+    "1920 1080 5 32 18 1 1", "1280 720 5 32 18 4 1", "2048 1536 8 16 12 1 1", "7 7 1 1 1 1 1",
+    "13 9 2 3 2 2 2", "9 13 2 3 2 2 2", "100 37 3 1 1 1 1", "127 255 7 1 2 1 2", "1000 999 6 8 8 3 3",
+    "333 251 4 7 5 3 2", "333 251 4 7 5 7 1", "64 64 7 1 1 1 1", "200 150 3 5 3 5 3", "170 130 4 3 2 3 2",
+])
+def test_group_geometry_covers_scores_reads_and_cells(group_check, shape):
+    out = subprocess.run([group_check, *shape.split()], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.startswith("ok"), out.stdout
+
+
+def test_group_params_are_validated(kpd):
+    ok = kpd.make_params(20, 4, 16, 12, chunk_frames=4, group_cols=4, group_rows=2)
+    assert kpd.lib.stream_bytes(640, 480, ctypes.byref(ok)) > 0
+    for gc, gr, gt in [(4, 0, 0), (0, 2, 0), (17, 1, 0), (1, 13, 0), (-1, 1, 0), (4, 1, 128), (4, 1, 1024)]:
+        p = kpd.make_params(20, 4, 16, 12, chunk_frames=4, group_cols=gc, group_rows=gr, group_threads=gt)
+        assert kpd.lib.stream_bytes(640, 480, ctypes.byref(p)) == 0, (gc, gr, gt)
+    p = kpd.make_params(20, 4, 16, 12, chunk_frames=4, group_cols=4, group_rows=1, group_threads=512)
+    assert kpd.lib.stream_bytes(640, 480, ctypes.byref(p)) > 0
+    # more LDS than a workgroup holds
+    p = kpd.make_params(20, 3, 8, 6, chunk_frames=4, group_cols=8, group_rows=6)
+    assert kpd.lib.stream_bytes(320, 240, ctypes.byref(p)) == 0
 
 
 def test_descriptor_pattern_matches_the_oracle(kpd):

@@ -118,7 +118,7 @@ def test_descriptor_errors(kpd):
     kpd.profile(g.handle, True)
     g.push(frames[1])
     ms, n = kpd.profile_read(g.handle)
-    assert list(n) == [1, 1, 0, 0, 1]
+    assert list(n) == [1, 1, 1, 0, 1]
     g.close()
     plain = kpd.Stream(320, 240, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows))
     plain.push(frames[0])

@@ -363,7 +363,7 @@ def test_kernel_timing_counts_launches(kpd):
     for f in frames:
         g.push(f)
     ms, n = kpd.profile_read(g.handle)
-    assert list(n) == [4, 4, 0, 0, 0]   # no chunk passes outside push_frames
+    assert list(n) == [4, 4, 4, 0, 0]   # tile pass, cell pass, compaction; no mark pass
     assert (ms[:2] > 0).all()
     kpd.profile(g.handle, False)
     g.push(frames[0])

@@ -133,7 +133,7 @@ def test_refine_errors(kpd):
     kpd.profile(g.handle, True)
     g.push(frames[1])
     ms, n = kpd.profile_read(g.handle)
-    assert list(n) == [1, 1, 0, 0, 1]
+    assert list(n) == [1, 1, 1, 0, 1]
     g.close()
 
 

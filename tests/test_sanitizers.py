@@ -60,7 +60,7 @@ class P(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("fast_t", "n_octaves", "grid_cols", "grid_rows", "id_thresh")] + \
                [("kb_thresh", ctypes.c_uint32)] + \
                [(n, ctypes.c_int32) for n in ("tile", "chunk_frames", "layer_mask", "features", "group_cols",
-                                               "group_rows")]
+                                               "group_rows", "group_threads")]
 L.stream_bytes.restype = ctypes.c_size_t
 L.stream_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
 L.kpd_last_error.restype = ctypes.c_char_p
@@ -73,14 +73,15 @@ good = [(320, 240, (30, 3, 8, 6, 8, 0xFFFFFFFF, 0, 0, 0, 0, 0, 0)),
         (1920, 1080, (20, 5, 32, 18, -1, 0, 0, 300, 0, 0, 2, 1)),
         (333, 251, (25, 4, 7, 5, 4, 3, 0, 5, 0, 0, 3, 2)),
         (7, 7, (10, 1, 1, 1, 8, 0xFFFFFFFF, 0, 2, 0, 0, 1, 1)),
-        (2048, 1536, (20, 8, 16, 12, 8, 0xFFFFFFFF, 128, 4, 0, 0, 0, 0))]
+        (2048, 1536, (20, 8, 16, 12, 8, 0xFFFFFFFF, 128, 4, 0, 0, 0, 0)),
+        (1920, 1080, (20, 5, 32, 18, -1, 0, 0, 300, 0, 0, 4, 1, 512))]
 bad = [(320, 240, (0, 3, 8, 6, 8, 0, 0, 0, 0, 0, 0, 0)), (320, 240, (30, 9, 8, 6, 8, 0, 0, 0, 0, 0, 0, 0)),
        (320, 240, (30, 3, 0, 6, 8, 0, 0, 0, 0, 0, 0, 0)), (320, 240, (30, 3, 1, 1, 8, 0, 0, 0, 0, 0, 0, 0)),
        (320, 240, (30, 3, 8, 6, 8, 0, 48, 0, 0, 0, 0, 0)), (320, 240, (30, 3, 8, 6, 8, 0, 0, 513, 0, 0, 0, 0)),
        (320, 240, (30, 3, 8, 6, 8, 0, 0, 0, 2, 0, 0, 0)), (320, 240, (30, 3, 8, 6, 8, 0, 0, 0, 0, 8, 0, 0)),
        (320, 240, (30, 3, 8, 6, 8, 0, 0, 4, 0, 0, 9, 1)), (320, 240, (30, 3, 8, 6, 8, 0, 0, 4, 0, 0, 8, 6)),
        (0, 240, (30, 3, 8, 6, 8, 0, 0, 0, 0, 0, 0, 0)), (20000, 240, (30, 3, 8, 6, 8, 0, 0, 0, 0, 0, 0, 0)),
-       (3, 3, (30, 3, 1, 1, 8, 0, 0, 0, 0, 0, 0, 0))]
+       (3, 3, (30, 3, 1, 1, 8, 0, 0, 0, 0, 0, 0, 0)), (320, 240, (30, 3, 8, 6, 8, 0, 0, 4, 0, 0, 1, 1, 300))]
 for W, H, v in good:
     p = P(*v)
     assert L.stream_bytes(W, H, ctypes.byref(p)) > 0, (W, H, v, L.kpd_last_error())
