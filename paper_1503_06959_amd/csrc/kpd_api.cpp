@@ -907,7 +907,7 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
         ga.layouts = s->at<kpd::GroupLayout>(L.off_glay1);
         ga.ngroups = L.ncell;
         ga.nc = L.nc;
-        ga.al16 = (reinterpret_cast<uintptr_t>(t.d.lvl[0]) % 16 == 0 && t.d.pitch[0] % 16 == 0) ? 1 : 0;
+        ga.al8 = (reinterpret_cast<uintptr_t>(t.d.lvl[0]) % 8 == 0 && t.d.pitch[0] % 8 == 0) ? 1 : 0;
         const int threads = t.d.all_marked ? 256 : 512;
         const int lds = threads == 512 ? L.glds1_512 : L.glds1_256;
         KPD_HIP(timed(s, KPD_K_DETECT, [&] {
@@ -1028,7 +1028,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         ga.layouts = s->at<kpd::GroupLayout>(L.off_glay);
         ga.ngroups = L.ngroups;
         ga.nc = L.nc;
-        ga.al16 = (reinterpret_cast<uintptr_t>(frames) % 16 == 0 && frame_stride % 16 == 0 && pitch % 16 == 0) ? 1 : 0;
+        ga.al8 = (reinterpret_cast<uintptr_t>(frames) % 8 == 0 && frame_stride % 8 == 0 && pitch % 8 == 0) ? 1 : 0;
         KPD_HIP(timed(s, KPD_K_DETECT, [&] {
             return kpd::launch_detect_chunk_groups(ctab, h, ga, L.glds, L.gthreads, s->stream);
         }));

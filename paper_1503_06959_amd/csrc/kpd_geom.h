@@ -255,14 +255,14 @@ KPD_HD int detect_lds_for(int bytes, int waves) { return bytes - (kDetectWaves -
 // because the cells' column and row boundaries map to ceil(X / 2^o).
 //
 // Score pixels are taken in groups of eight consecutive columns (one lane,
-// two dwords of a tile row), starting at a multiple of 8: a group may
+// two dwords of a level row), starting at a multiple of 8: a group may
 // cover columns outside the score box, whose scores are computed too and
 // land in the score map (which covers them), and columns outside the
-// detectable interior, which the full test drops. The pixel tile starts at
-// a multiple of 16 (16-byte staging loads) four or more columns left of
-// the first group and ends four or more right of the last, and has the
-// 3-row ring apron above and below; its columns outside the level are not
-// loaded and are only read for pixels the full test drops.
+// detectable interior, which the full test drops. Pixels are read from the
+// levels in place. Queue entries name a pixel by its offset from the
+// group's reference corner (tx0, ty0) of each octave: tx0 is a multiple of
+// 16 four or more columns left of the first group, ty0 three rows above
+// the first score row; tpitch and th bound the offsets.
 
 constexpr int kGroupQueue = 128;     // entries (u32) of each of a wave's two queues
 constexpr int kGroupMaxPitch = 2047;  // tile columns fit 11 bits,
@@ -276,23 +276,21 @@ struct GroupLayout {
     int mx0[KPD_MAX_OCTAVES], my0[KPD_MAX_OCTAVES]; // score-map origin (level coords)
     int vpitch[KPD_MAX_OCTAVES];                    // score-map row pitch (u16 elements)
     int voff[KPD_MAX_OCTAVES];                      // score-map LDS byte offset
-    int tx0[KPD_MAX_OCTAVES], ty0[KPD_MAX_OCTAVES]; // pixel tile origin (tx0 a multiple of 16, may be < 0)
-    int tpitch[KPD_MAX_OCTAVES], th[KPD_MAX_OCTAVES], toff[KPD_MAX_OCTAVES];
+    int tx0[KPD_MAX_OCTAVES], ty0[KPD_MAX_OCTAVES]; // queue-entry origin (tx0 a multiple of 16, may be < 0)
+    int tpitch[KPD_MAX_OCTAVES], th[KPD_MAX_OCTAVES]; // extent of the entries' columns and rows
     int gx0[KPD_MAX_OCTAVES];                       // first 8-px group column (level coords, multiple of 8)
     int ngx[KPD_MAX_OCTAVES];                       // groups per score row
     int sy0[KPD_MAX_OCTAVES], nsr[KPD_MAX_OCTAVES]; // first score row, score rows
     uint64_t gcm[KPD_MAX_OCTAVES];                  // div magic: groups per row
-    uint64_t sgm[KPD_MAX_OCTAVES];                  // div magic: 16-byte segments per tile row
     uint64_t wpm[KPD_MAX_OCTAVES];                  // div magic: bitmap words per row
     int ck_start[KPD_MAX_OCTAVES + 1];              // first 64-group chunk of each octave
-    int sg_start[KPD_MAX_OCTAVES + 1];              // first 16-byte tile segment of each octave
     int cwoff[KPD_MAX_OCTAVES + 1];                 // first bitmap word of each octave
     int wpr[KPD_MAX_OCTAVES];                       // bitmap words per decision row
     int w[KPD_MAX_OCTAVES], h[KPD_MAX_OCTAVES];     // level sizes
     int nwords;                                     // words of each bitmap
     int cand_off;                                   // keep bitmap at 0, candidate bitmap here
     int zero_bytes;                                 // bitmaps and score maps: cleared per group
-    int queue_off;                                  // wave queues, after the tiles
+    int queue_off;                                  // wave queues, after the score maps
     int gc0, gc1, gr0, gr1;                         // cells covered
     int O;
     int ncells;                                     // (gc1 - gc0) x (gr1 - gr0), row-major
@@ -332,9 +330,9 @@ KPD_HD bool group_layout(const Box& r, int O, const int* w, const int* h, int gc
     for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
         G->dec[o] = G->qb[o] = Box{0, 0, 0, 0};
         G->mx0[o] = G->my0[o] = G->vpitch[o] = G->voff[o] = 0;
-        G->tx0[o] = G->ty0[o] = G->tpitch[o] = G->th[o] = G->toff[o] = 0;
+        G->tx0[o] = G->ty0[o] = G->tpitch[o] = G->th[o] = 0;
         G->gx0[o] = G->ngx[o] = G->sy0[o] = G->nsr[o] = 0;
-        G->gcm[o] = G->sgm[o] = G->wpm[o] = 0;
+        G->gcm[o] = G->wpm[o] = 0;
         G->wpr[o] = 0;
         G->w[o] = o < O ? w[o] : 0;
         G->h[o] = o < O ? h[o] : 0;
@@ -386,11 +384,8 @@ KPD_HD bool group_layout(const Box& r, int O, const int* w, const int* h, int gc
     }
     for (int o = O; o <= KPD_MAX_OCTAVES; ++o) G->ck_start[o] = ck;
     G->zero_bytes = off;
-    // pixel tiles
-    int sg = 0;
+    // queue-entry origins and extents
     for (int o = 0; o < O; ++o) {
-        G->sg_start[o] = sg;
-        G->toff[o] = off;
         if (G->nsr[o] == 0) continue;
         G->tx0[o] = floor16(G->gx0[o] - 4);
         const int tx1 = round_up(G->gx0[o] + 8 * G->ngx[o] + 4, 16);
@@ -398,15 +393,10 @@ KPD_HD bool group_layout(const Box& r, int O, const int* w, const int* h, int gc
         G->ty0[o] = G->sy0[o] - kRingR;
         G->th[o] = G->nsr[o] + 2 * kRingR;
         if (G->tpitch[o] > kGroupMaxPitch || G->th[o] > kGroupMaxRows) return false;
-        off += G->tpitch[o] * G->th[o];
-        sg += (G->tpitch[o] / 16) * G->th[o];
     }
-    for (int o = O; o <= KPD_MAX_OCTAVES; ++o) G->sg_start[o] = sg;
     G->queue_off = round_up(off, 16);
-
     for (int o = 0; o < O; ++o) {
         G->gcm[o] = div_magic(imax(G->ngx[o], 1));
-        G->sgm[o] = div_magic(imax(G->tpitch[o] / 16, 1));
         G->wpm[o] = div_magic(imax(G->wpr[o], 1));
     }
     return true;

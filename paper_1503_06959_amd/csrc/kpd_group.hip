@@ -40,20 +40,22 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v)
     return ((uint64_t)(uint32_t)rfl((int)(v >> 32)) << 32) | (uint32_t)rfl((int)(uint32_t)v);
 }
 
-// 16 bytes of a tile row at level column gx of a level of width w, for a
-// segment that a single 16-byte load may not take (outside the level, or
-// rows not 16-byte aligned): dword loads when `dw`, else byte loads of the
-// columns inside the level (0 elsewhere).
-__device__ __noinline__ uint4 load_edge16(const uint8_t* src, int gx, int w, bool dw)
+// 8 bytes of a level row at column gx of a level of width w, for rows that
+// cannot be read 8 bytes at a time: dwords when mode = 1 (4-byte aligned
+// rows), else bytes; columns outside [0, w) read as 0.
+__device__ __noinline__ uint2 load8_slow(const uint8_t* src, int gx, int w, int mode)
 {
-    if (dw) {
-        const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
-        return make_uint4(s4[0], s4[1], s4[2], s4[3]);
+    uint32_t wv[2] = {0u, 0u};
+    for (int d = 0; d < 2; ++d) {
+        const int g = gx + 4 * d;
+        if (mode == 1 && g >= 0 && g + 4 <= w) {
+            wv[d] = *reinterpret_cast<const uint32_t*>(src + 4 * d);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (g + k >= 0 && g + k < w) wv[d] |= (uint32_t)src[4 * d + k] << (8 * k);
+        }
     }
-    uint32_t wv[4] = {0u, 0u, 0u, 0u};
-    for (int k = 0; k < 16; ++k)
-        if (gx + k >= 0 && gx + k < w) wv[k >> 2] |= (uint32_t)src[k] << (8 * (k & 3));
-    return make_uint4(wv[0], wv[1], wv[2], wv[3]);
+    return make_uint2(wv[0], wv[1]);
 }
 
 __device__ __forceinline__ int glevel(const int* start, int O, int i)
@@ -192,10 +194,10 @@ struct GroupOut {
 };
 
 // Detection of one group. lvl/pitch: the frame's levels (level 0 may be
-// any pointer and pitch; al16 / al4 say whether its rows can be read 16 /
-// 4 bytes at a time).
+// any pointer and pitch; al8 / al4 say whether its rows can be read 8 / 4
+// bytes at a time).
 template <int NT>
-__device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl, const int* pitch, int al16, int al4,
+__device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl, const int* pitch, int al8, int al4,
                              int t, const GroupOut& out, uint8_t* sm)
 {
     __shared__ GroupLayout G;
@@ -214,48 +216,14 @@ __device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl,
     __syncthreads();
     const int O = G.O;
 
-    // 1) clear bitmaps and score maps; stage the pixel tiles of every
-    //    octave as one flat run of 16-byte segments, four loads in flight per
-    //    thread
+    // 1) clear bitmaps and score maps (pixels are read from the levels in
+    //    place, through the caches)
     uint32_t* s_ncand = reinterpret_cast<uint32_t*>(sm + G.queue_off + (NT / 64) * 2 * kGroupQueue * 4);
     uint32_t* clist = s_ncand + 4;
     {
         uint4* z = reinterpret_cast<uint4*>(sm);
         for (int i = tid; i < G.zero_bytes / 16; i += NT) z[i] = make_uint4(0u, 0u, 0u, 0u);
         if (tid == 0) *s_ncand = 0u;
-        int sgs[KPD_MAX_OCTAVES];
-#pragma unroll
-        for (int o = 0; o < KPD_MAX_OCTAVES; ++o) sgs[o] = rfl(G.sg_start[o]);
-        const int nsg = rfl(G.sg_start[O]);
-        for (int i0 = tid; i0 < nsg; i0 += 4 * NT) {
-            uint4 v[4];
-            int dst[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + u * NT;
-                dst[u] = -1;
-                if (i < nsg) {
-                    int o = 0;
-#pragma unroll
-                    for (int k = 1; k < KPD_MAX_OCTAVES; ++k) o += (k < O && i >= sgs[k]) ? 1 : 0;
-                    const int j = i - G.sg_start[o];
-                    const int tp = G.tpitch[o], q = tp >> 4;
-                    const int ry = gdiv(j, G.sgm[o]), sx = j - ry * q;
-                    const int gx = G.tx0[o] + 16 * sx, wo = G.w[o];
-                    const int pitch = s_pitch[o];
-                    const uint8_t* src = s_lvl[o] + (size_t)(G.ty0[o] + ry) * pitch + gx;
-                    // levels 1.. are 16-byte aligned and readable to their
-                    // pitch; level 0 to its width
-                    const int lim = o == 0 ? wo : pitch;
-                    if (gx >= 0 && gx + 16 <= lim && (o > 0 || al16)) v[u] = *reinterpret_cast<const uint4*>(src);
-                    else v[u] = load_edge16(src, gx, wo, gx >= 0 && gx + 16 <= lim && al4);
-                    dst[u] = G.toff[o] + ry * tp + 16 * sx;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (dst[u] >= 0) *reinterpret_cast<uint4*>(sm + dst[u]) = v[u];
-        }
     }
     __syncthreads();
 
@@ -287,8 +255,8 @@ __device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl,
                 const int o = (int)(e >> 24), row = (int)((e >> 12) & 0xFFFu), col = (int)(e & 0xFFFu);
                 const int x = G.tx0[o] + col, y = G.ty0[o] + row;
                 if (x >= kRingR && x < G.w[o] - kRingR) {
-                    const int tp = G.tpitch[o];
-                    const int v = group_score(sm + G.toff[o] + (row - kRingR) * tp + (col - kRingR), tp, t);
+                    const int pt = s_pitch[o];
+                    const int v = group_score(s_lvl[o] + (size_t)(y - kRingR) * pt + (x - kRingR), pt, t);
                     if (v > 0) {
                         reinterpret_cast<uint16_t*>(sm + G.voff[o])[(y - G.my0[o]) * G.vpitch[o] + (x - G.mx0[o])] =
                             (uint16_t)v;
@@ -349,9 +317,16 @@ __device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl,
             const int ngroups = ngx * nsr;
             const int nck = (ngroups + 63) >> 6;
             if (nck == 0) continue;
-            const int tp = rfl(G.tpitch[o]), tx0 = rfl(G.tx0[o]), toff = rfl(G.toff[o]), gx0 = rfl(G.gx0[o]);
+            const int tx0 = rfl(G.tx0[o]), gx0 = rfl(G.gx0[o]), sy0 = rfl(G.sy0[o]), wo = rfl(G.w[o]);
             const uint64_t gcm = rfl64(G.gcm[o]);
-            const uint8_t* tile = sm + toff;
+            const int pt = rfl(s_pitch[o]);
+            const uint8_t* lvo = reinterpret_cast<const uint8_t*>(rfl64(reinterpret_cast<uint64_t>(s_lvl[o])));
+            // level 0 may be caller memory whose last row ends the buffer:
+            // its south rows are read only up to the frame's width, and its
+            // rows are read a dword or a byte at a time when not 8-byte
+            // aligned; levels 1.. are 8-byte aligned arena rows
+            const int mode = o > 0 ? 2 : (al8 ? 2 : (al4 ? 1 : 0));
+            const bool guard = o == 0;
             const uint32_t obits = (uint32_t)o << 29;
             int first = (wave - ck0) % NW;
             if (first < 0) first += NW;
@@ -360,13 +335,34 @@ __device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl,
                 uint32_t pass = 0u, gent = 0u;
                 if (g < ngroups) {
                     const int ry = gdiv(g, gcm);
-                    const int row = ry + kRingR, col = gx0 + 8 * (g - ry * ngx) - tx0;
-                    const uint8_t* T = tile + row * tp + col;
-                    const uint2 c = *reinterpret_cast<const uint2*>(T);
-                    const uint2 n = *reinterpret_cast<const uint2*>(T - 3 * tp);
-                    const uint2 s = *reinterpret_cast<const uint2*>(T + 3 * tp);
-                    const uint32_t cm = *reinterpret_cast<const uint32_t*>(T - 4);
-                    const uint32_t cp = *reinterpret_cast<const uint32_t*>(T + 8);
+                    const int gx = gx0 + 8 * (g - ry * ngx), y = sy0 + ry;
+                    const int row = ry + kRingR, col = gx - tx0;
+                    // the group's row and the rows 3 above and below; the
+                    // centre row is never a level's last, so its dword
+                    // right of the group stays inside the level, and its
+                    // dword left of the group (read from the row above when
+                    // gx = 0) only feeds pixels outside the interior
+                    const uint8_t* T = lvo + (size_t)y * pt + gx;
+                    uint2 c, n, s;
+                    uint32_t cm, cp;
+                    if (mode == 2) {
+                        c = *reinterpret_cast<const uint2*>(T);
+                        n = *reinterpret_cast<const uint2*>(T - 3 * pt);
+                        cm = *reinterpret_cast<const uint32_t*>(T - 4);
+                        cp = *reinterpret_cast<const uint32_t*>(T + 8);
+                        if (!guard || gx + 8 <= wo) {
+                            s = *reinterpret_cast<const uint2*>(T + 3 * pt);
+                        } else {   // bytes past the width feed no interior pixel
+                            s.x = gx + 4 <= wo ? *reinterpret_cast<const uint32_t*>(T + 3 * pt) : 0u;
+                            s.y = 0u;
+                        }
+                    } else {
+                        c = load8_slow(T, gx, wo, mode);
+                        n = load8_slow(T - 3 * pt, gx, wo, mode);
+                        s = load8_slow(T + 3 * pt, gx, wo, mode);
+                        cm = load8_slow(T - 4, gx - 4, wo, mode).x;
+                        cp = load8_slow(T + 8, gx + 8, wo, mode).x;
+                    }
                     // pixel i of the group is byte i of {c.y, c.x}; its east
                     // point is byte i + 3, its west point byte i - 3
                     const uint32_t r0 = compass2(pick2(c.y, c.x, 0, 1), pick2(n.y, n.x, 0, 1),
@@ -591,7 +587,7 @@ __global__ __launch_bounds__(NT) void k_detect_chunk_groups(const ChunkArgs* tab
     lv[0] = h.frames + (size_t)j * h.stride;
     pt[0] = h.pitch;
     const GroupOut out{t.d.list_cur, t.own_count, t.d.list_cap};
-    detect_group<NT>(gl, lv, pt, g.al16, h.aligned, h.t, out, sm);
+    detect_group<NT>(gl, lv, pt, g.al8, h.aligned, h.t, out, sm);
 }
 
 // One frame of one stream with the per-cell mask: cell c decides its mark
@@ -616,7 +612,7 @@ __global__ __launch_bounds__(NT) void k_det1_groups(DetectArgs a, GroupArgs g, k
     }
     if (!mark) return;
     const GroupOut out{sparse, own, a.list_cap};
-    detect_group<NT>(g.layouts + c, a.lvl, a.pitch, g.al16, a.lvl0_aligned, a.t, out, sm);
+    detect_group<NT>(g.layouts + c, a.lvl, a.pitch, g.al8, a.lvl0_aligned, a.t, out, sm);
 }
 
 hipError_t launch_det1_groups(const DetectArgs& a, const GroupArgs& g, kpd_keypoint* sparse, uint32_t* own,

@@ -208,11 +208,11 @@ struct CompactArgs {
 
 // The group detector: the groups' layouts (a rectangle of cells each,
 // row-major over the group grid; each layout names its cells and their
-// list bases) and whether level 0's rows can be read 16 bytes at a time.
+// list bases) and whether level 0's rows can be read 8 bytes at a time.
 struct GroupArgs {
     const GroupLayout* layouts;
     int ngroups, nc;
-    int al16;
+    int al8;
 };
 
 hipError_t launch_detect_chunk_groups(const ChunkArgs* table, const ChunkHead& h, const GroupArgs& g, int lds_bytes,

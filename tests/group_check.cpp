@@ -6,16 +6,16 @@
 //      level-0 starts of its column and row as the kernel does;
 //   2. the 8-pixel score groups cover every pixel of the score box, every
 //      scored pixel inside the detectable interior has a place in the score
-//      map, and every read of the compass pass (the group's two dwords, the
-//      dwords left and right, the rows 3 above and below) and of the full
-//      test (the 7 x 7 window) stays inside the pixel tile;
+//      map, queue-entry offsets stay within their bit widths, and the rows
+//      the compass pass reads in place (the group's row, not the level's
+//      last, and the rows 3 above and below) are level rows, the group
+//      starting at or before the last interior column;
 //   3. every scale-space neighbour a decision reads (8 in-plane pixels, the
 //      finer 4x4 block, the coarser 2x2 block) lies in its level's score map
 //      and is either scored or outside the interior (score 0);
-//   4. the pixel tile lies in the level's rows, starts at a multiple of 16
-//      and its 16-byte segments cover it once; the queue entries' 12-bit
-//      tile coordinates hold;
-//   5. LDS regions (bitmaps, score maps, tiles, queues) do not overlap, and
+//   4. the entry origin is a multiple of 16 and its extent lies in the
+//      level's rows;
+//   5. LDS regions (bitmaps, score maps, queues) do not overlap, and
 //      the bitmap words of each level hold its decision rows.
 // Prints "ok <max_lds_bytes> <groups>" or the first violation.
 #include <cstdio>
@@ -65,12 +65,9 @@ int main(int argc, char** argv)
                 if (G.voff[o] < mprev || mend > G.zero_bytes) return fail("score maps overlap or leave their region", g, o);
                 mprev = mend;
             }
-            for (int o = 0; o < O; ++o) {
-                if (G.toff[o] < G.zero_bytes || G.toff[o] + G.tpitch[o] * G.th[o] > G.queue_off)
-                    return fail("tile outside its region", g, o);
-                if (o + 1 < O && G.toff[o] + G.tpitch[o] * G.th[o] > G.toff[o + 1]) return fail("tiles overlap", g, o);
-                if (G.voff[o] % 16 || G.toff[o] % 16 || G.queue_off % 16) return fail("region not 16-byte aligned", g, o);
-            }
+            for (int o = 0; o < O; ++o)
+                if (G.voff[o] % 16 || G.queue_off % 16 || G.queue_off < G.zero_bytes)
+                    return fail("region not 16-byte aligned or queues overlap the maps", g, o);
             // 1) cells partition the group's decision box
             for (int o = 0; o < O; ++o) {
                 const Box d = G.dec[o];
@@ -112,7 +109,6 @@ int main(int argc, char** argv)
                 if (G.nsr[o] == 0) continue;
                 if (G.tx0[o] % 16 || tp % 16 || G.ty0[o] < 0 || G.ty0[o] + th > h[o]) return fail("tile placement", g, o);
                 if (tp > 2047 || th > 1023) return fail("tile coordinates exceed the queue entries' bits", g, o);
-                if ((G.sg_start[o + 1] - G.sg_start[o]) != (tp / 16) * th) return fail("tile segments", g, o);
                 const long tsz = (long)tp * th;
                 const int ngroups = G.ngx[o] * G.nsr[o];
                 if (G.ck_start[o + 1] - G.ck_start[o] != (ngroups + 63) / 64) return fail("chunks", g, o);
@@ -122,7 +118,13 @@ int main(int argc, char** argv)
                     const int row = ry + 3, col = G.gx0[o] + 8 * (gi - ry * G.ngx[o]) - G.tx0[o];
                     const long T = (long)row * tp + col;
                     if (col % 8 || T - 4 < 0 || T + 12 > tsz || T - 3L * tp < 0 || T + 3L * tp + 8 > tsz)
-                        return fail("compass read outside the tile", g, o);
+                        return fail("compass read outside the entry extent", g, o);
+                    // reads in place: rows 3 above and below the group's row
+                    // are level rows, the centre row is not the last, and the
+                    // group starts at or before the last interior column
+                    const int gxl = G.tx0[o] + col, yl = G.ty0[o] + row;
+                    if (yl - 3 < 0 || yl + 3 > h[o] - 1 || yl + 1 > h[o] - 1 || gxl < 0 || gxl > w[o] - 4)
+                        return fail("in-place compass read outside the level", g, o);
                     for (int k = 0; k < 8; ++k) {
                         const int x = G.tx0[o] + col + k, y = G.ty0[o] + row;
                         if (x < 3 || x >= w[o] - 3) continue;   // dropped by the full test
