@@ -404,6 +404,20 @@ int kpd_detect_layers(const uint8_t* frame, size_t pitch_bytes, int width, int h
                       void* workspace, size_t workspace_bytes, kpd_keypoint* out, uint32_t capacity, uint32_t* count,
                       void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * kpd_detect_layers with its workspace in a static device array of
+ * KPD_STATIC_WORKSPACE bytes, which the library keeps on every GPU it runs
+ * on until the process ends. Frames whose kpd_layers_bytes() exceeds it
+ * (1920 x 1080 fits) return KPD_EINVAL. Every call on one GPU shares the
+ * array, which keeps the last call's layers and score maps: calls that
+ * overlap on one GPU race, so queue them on one HIP stream. `hip_stream`
+ * must belong to the current device. Other arguments, ownership and errors
+ * as kpd_detect_layers; allocates nothing. */
+#define KPD_STATIC_WORKSPACE (16u << 20)
+int kpd_detect_layers_static(const uint8_t* frame, size_t pitch_bytes, int width, int height, int fast_t,
+                             int n_octaves, kpd_keypoint* out, uint32_t capacity, uint32_t* count, void* hip_stream);
+
 /* Refinement of keypoints on these layers (Sec. 2's sub-pixel and
  * sub-scale interpolation over the layered scale space), from the score
  * maps that the last kpd_detect_layers call left in `workspace`. For a

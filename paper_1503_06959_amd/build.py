@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkpd.so")
 SOURCES = [os.path.join(CSRC, "kpd_api.cpp"), os.path.join(CSRC, "kpd_kernels.hip"), os.path.join(CSRC, "kpd_group.hip"),
            os.path.join(CSRC, "kpd_tcd.cpp"), os.path.join(CSRC, "kpd_tcd.hip"),
-           os.path.join(CSRC, "kpd_layers.cpp"), os.path.join(CSRC, "kpd_layers.hip")]
+           os.path.join(CSRC, "kpd_layers.cpp"), os.path.join(CSRC, "kpd_layers.hip"),
+           os.path.join(CSRC, "kpd_noalloc.hip")]
 HEADERS = [os.path.join(CSRC, "kpd_geom.h"), os.path.join(CSRC, "kpd_kernels.h"), os.path.join(CSRC, "kpd_tcd.h"), os.path.join(CSRC, "kpd_errors.h"),
            os.path.join(CSRC, "kpd_layers.h"), os.path.join(CSRC, "kpd_fit.h"),
            os.path.join(os.path.dirname(HERE), "include", "kpd.h")]

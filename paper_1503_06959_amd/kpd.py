@@ -38,6 +38,7 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
             "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
             "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
+            "kpd_detect_layers_static",
             "kpd_layer_plane", "kpd_refine_layers", "kpd_lstream_bytes", "kpd_lstream_open", "kpd_lstream_push",
             "kpd_lstream_get", "kpd_lstream_reset", "kpd_lstream_close")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
@@ -45,6 +46,7 @@ TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "u1"), ("pad", 
                         ("sad", "<u4")])
 REFINED_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("log2_scale", "<f4"), ("score", "<f4")])
 FEAT_DESCRIPTOR, FEAT_REFINE = 1, 2
+STATIC_WORKSPACE = 16 << 20   # KPD_STATIC_WORKSPACE: bytes of kpd_detect_layers_static's workspace
 KERNEL_NAMES = ("k_frame", "k_detect", "k_compact", "k_mark", "k_describe")
 
 
@@ -109,6 +111,8 @@ def _load() -> ctypes.CDLL:
     L.kpd_layers_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.kpd_layers_bytes.restype = sz
     L.kpd_detect_layers.argtypes = [P, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, u32, P, P]
+    L.kpd_detect_layers_static.argtypes = [P, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, u32, P,
+                                           P]
     L.kpd_refine_layers.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, P, u32, P, P]
     L.kpd_lstream_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams)]
     L.kpd_lstream_bytes.restype = sz
@@ -564,6 +568,17 @@ class LayerDetector:
                                      self.n_octaves, self.workspace.data_ptr(), self.workspace.numel(),
                                      self.out.data_ptr(), self.capacity, self.count.data_ptr(),
                                      _stream_ptr(self.stream)))
+
+    def detect_static_async(self, frame: torch.Tensor) -> None:
+        """detect_async through kpd_detect_layers_static: the library's static
+        workspace instead of this detector's."""
+        if not (isinstance(frame, torch.Tensor) and frame.device.type == "cuda" and frame.dtype == torch.uint8
+                and frame.dim() == 2 and frame.stride(1) == 1
+                and tuple(frame.shape) == (self.height, self.width)):
+            raise ValueError("frame must be a CUDA uint8 [H, W] tensor with unit column stride")
+        _check(lib.kpd_detect_layers_static(frame.data_ptr(), frame.stride(0), self.width, self.height, self.fast_t,
+                                            self.n_octaves, self.out.data_ptr(), self.capacity,
+                                            self.count.data_ptr(), _stream_ptr(self.stream)))
 
     def detect(self, frame) -> np.ndarray:
         """Keypoints (KEYPOINT_DTYPE, `octave` = layer index) of one frame."""
