@@ -660,9 +660,9 @@ def pingpong(k: int, n: int) -> int:
 
 def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
     """64 mixed-resolution streams (24 x 320x240, 24 x 640x480, 16 x 1280x720),
-    one frame each per tick: batched ticks (two graph-replayed launches per
-    tick) against plain per-stream pushes (two launches per stream and
-    frame) over the same frames."""
+    one frame each per tick: batched ticks (four graph-replayed launches per
+    tick, and the single-launch form beside them) against plain per-stream
+    pushes (three launches per stream and frame) over the same frames."""
     import torch
     from concurrent.futures import ProcessPoolExecutor
     from paper_1503_06959_amd import autotune, synth
@@ -693,14 +693,19 @@ def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
             if rc:
                 raise kpd.KpdError(rc, kpd.lib.kpd_last_error().decode())
         kpd.batch_tick(b.handle)
-    for k in range(warmup):
-        tick(k)
-    b.synchronize()
-    t0 = time.perf_counter()
-    for k in range(warmup, warmup + n_ticks):
-        tick(k)
-    b.synchronize()
-    sec_b = (time.perf_counter() - t0) / n_ticks
+    def timed_ticks():
+        for k in range(warmup):
+            tick(k)
+        b.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup, warmup + n_ticks):
+            tick(k)
+        b.synchronize()
+        return (time.perf_counter() - t0) / n_ticks
+    sec_b = timed_ticks()
+    b.set_single_launch(True)
+    sec_1 = timed_ticks()
+    b.set_single_launch(False)
     for s in bs:
         b.detach(s)
         s.close()
@@ -733,9 +738,12 @@ def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
         "batched": {"mpix_per_s": round(px_per_tick / sec_b / 1e6, 2), "frames_per_s": round(64 / sec_b, 1),
                     "ms_per_tick": round(sec_b * 1e3, 4), "launches_per_tick": 4, "hip_graph": True,
                     "tiles": tiles},
+        "batched_single_launch": {"mpix_per_s": round(px_per_tick / sec_1 / 1e6, 2),
+                                  "ms_per_tick": round(sec_1 * 1e3, 4), "launches_per_tick": 1,
+                                  "hip_graph": True},
         "plain_per_stream": {"mpix_per_s": round(px_per_tick / sec_p / 1e6, 2),
                              "frames_per_s": round(64 / sec_p, 1), "ms_per_tick": round(sec_p * 1e3, 4),
-                             "launches_per_tick": 128},
+                             "launches_per_tick": 192},
         "batched_over_plain": round(sec_p / sec_b, 3),
         "cpu_all_cores": oracle_all_cores(clip, 10.0),
     }

@@ -281,9 +281,12 @@ const char* kpd_last_error(void);
 /* ------------------------------------------------------------- batching */
 
 /* A batch runs the next frame of many streams (of any sizes and parameters)
- * in one tick: two launches that cover every attached stream with a staged
- * frame, optionally replayed from a captured HIP graph. Results are exactly
- * those of pushing each stream's frame alone. */
+ * in one tick, optionally replayed from a captured HIP graph. By default a
+ * tick is four launches (tile passes; marks with the marked cells listed;
+ * detection of the listed cells; each stream's D_n by Eq. 1);
+ * batch_set_single_launch(b, 1) makes it one launch of co-resident
+ * workgroups whose phases are separated by device-wide barriers. Results
+ * are exactly those of pushing each stream's frame alone. */
 typedef struct kpd_batch kpd_batch;
 
 /* Device scratch bytes of a batch holding up to `max_streams` streams whose
@@ -309,8 +312,15 @@ int batch_detach(kpd_batch* b, kpd_stream* s);
 int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
 
 /* Run one tick over every attached stream with a staged frame.
- * Asynchronous; get_keypoints on a stream waits for it. */
+ * Asynchronous; get_keypoints on a stream waits for it. A barrier wait of
+ * the single-launch tick that does not end (the device holding fewer of its
+ * workgroups than it was sized for) gives up after about a second and makes
+ * get_keypoints of the ticked streams return KPD_EDEVICE. */
 int batch_tick(kpd_batch* b);
+
+/* Tick form: 1 one launch per tick, 0 (the default) four launches. Waits
+ * for the batch's queued work; results do not depend on the form. */
+int batch_set_single_launch(kpd_batch* b, int on);
 
 /* Gather the results of the last tick: counts[i] (uint32, device memory)
  * receives the size of D_n of the i-th attached stream (attach order; 0 for

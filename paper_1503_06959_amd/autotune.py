@@ -1,12 +1,19 @@
-"""Autotuner for the batched tick.
+"""Autotuner for the batched tick and the full-frame detection pass.
 
-The tunable is the side of the level-0 tiles of the pyramid/difference pass
-(32, 64 or 128 pixels, at least 2^(O-1)). It changes how the pass maps onto
-workgroups and XCD L2s, never the results (the GPU tests check that every
-tile size gives identical keypoints). For each resolution class
-(W, H, O, grid) the tuner times a short batched run of synthetic streams per
-candidate and keeps the fastest; choices are cached per GPU architecture in
-a JSON file.
+Two tunables, neither of which ever changes results (the GPU tests check
+that every choice gives identical keypoints):
+
+- the side of the level-0 tiles of the pyramid/difference pass (32, 64 or
+  128 pixels, at least 2^(O-1)): how that pass maps onto workgroups and XCD
+  L2s; timed on a short batched run of synthetic streams;
+- the cells per workgroup (a rectangle of group_cols x group_rows cells)
+  and the workgroup size (256 or 512 threads) of the detection pass when
+  every cell is marked (full-frame chunks), the pass that dominates
+  full-frame time; timed on a full-frame chunk of synthetic frames.
+
+For each resolution class (W, H, O, grid) the tuner times each candidate
+and keeps the fastest; choices are cached per GPU architecture in a JSON
+file.
 """
 from __future__ import annotations
 
@@ -100,5 +107,59 @@ def best_tile(width: int, height: int, det: synth.Detector, retune: bool = False
     times = {t: time_class(width, height, det, t) for t in candidates(det)}
     best = min(times, key=times.get)
     cache.setdefault(arch, {})[key] = best
+    _save(cache)
+    return best, times
+
+
+GROUP_SHAPES = ((1, 1), (2, 1), (4, 1), (8, 1), (2, 2), (4, 2))
+GROUP_THREADS = (256, 512)
+
+
+def group_candidates(width: int, height: int, det: synth.Detector) -> List[Tuple[int, int, int]]:
+    """(group_cols, group_rows, threads) that the library accepts for this class."""
+    out = []
+    for gx, gy in GROUP_SHAPES:
+        if gx > det.grid_cols or gy > det.grid_rows:
+            continue
+        for nt in GROUP_THREADS:
+            p = kpd.make_params(det.fast_t, det.n_octaves, det.grid_cols, det.grid_rows, -1, det.kb_thresh, 0, 16,
+                                group_cols=gx, group_rows=gy, group_threads=nt)
+            if kpd.lib.stream_bytes(width, height, kpd.ctypes.byref(p)) > 0:
+                out.append((gx, gy, nt))
+    return out
+
+
+def time_groups(width: int, height: int, det: synth.Detector, groups: Tuple[int, int, int], n_frames: int = 64,
+                reps: int = 3, frames: Optional[np.ndarray] = None) -> float:
+    """Seconds per full-frame detection pass over n_frames frames in one chunk."""
+    if frames is None:
+        _, m, smin, smax, sig = synth.RES_PRESETS.get((width, height), (det, 20, 10, 60, 2.0))
+        frames = synth.make_video(synth.Scene(width, height, n_frames, m, smin, smax, 0.5, sig, False, 7100))
+    dev = torch.from_numpy(frames[:n_frames]).cuda()
+    gx, gy, nt = groups
+    p = kpd.make_params(det.fast_t, det.n_octaves, det.grid_cols, det.grid_rows, -1, det.kb_thresh, 0, len(dev),
+                        group_cols=gx, group_rows=gy, group_threads=nt)
+    s = kpd.Stream(width, height, p)
+    s.push_chunk(dev)
+    torch.cuda.synchronize()
+    kpd.profile(s.handle, True)
+    for _ in range(reps):
+        s.push_chunk(dev)
+    ms, n = kpd.profile_read(s.handle)
+    s.close()
+    return float(ms[1]) / max(1, int(n[1])) * 1e-3
+
+
+def best_groups(width: int, height: int, det: synth.Detector,
+                retune: bool = False) -> Tuple[Tuple[int, int, int], Dict[Tuple[int, int, int], float]]:
+    """Fastest (group_cols, group_rows, threads) for this class, from the cache or by timing."""
+    cache = _load()
+    arch = _arch()
+    key = "groups/" + class_key(width, height, det)
+    if not retune and key in cache.get(arch, {}):
+        return tuple(cache[arch][key]), {}
+    times = {g: time_groups(width, height, det, g) for g in group_candidates(width, height, det)}
+    best = min(times, key=times.get)
+    cache.setdefault(arch, {})[key] = list(best)
     _save(cache)
     return best, times

@@ -3,9 +3,10 @@ include/kpd.h).
 
 A Batch owns a HIP stream (a torch stream) and a device scratch tensor for
 its tick tables. Streams are opened on that HIP stream and attached; each
-tick runs the next frame of every stream that staged one, in two launches
-covering all of them (captured once as a HIP graph and replayed while the
-set of attached streams stays the same).
+tick runs the next frame of every stream that staged one, in four launches
+(or, after set_single_launch(True), one launch of co-resident workgroups
+whose phases are separated by device-wide barriers), captured once as a HIP
+graph and replayed while the set of attached streams stays the same.
 """
 from __future__ import annotations
 
@@ -51,6 +52,9 @@ class Batch:
         if retain:
             h = self._held[s.handle]
             self._held[s.handle] = [h[1], frame]
+
+    def set_single_launch(self, on: bool) -> None:
+        kpd.batch_set_single_launch(self.handle, on)
 
     def tick(self) -> None:
         kpd.batch_tick(self.handle)

@@ -15,7 +15,7 @@ SOURCES = [os.path.join(CSRC, "kpd_api.cpp"), os.path.join(CSRC, "kpd_kernels.hi
            os.path.join(CSRC, "kpd_tcd.cpp"), os.path.join(CSRC, "kpd_tcd.hip"),
            os.path.join(CSRC, "kpd_layers.cpp"), os.path.join(CSRC, "kpd_layers.hip"),
            os.path.join(CSRC, "kpd_noalloc.hip")]
-HEADERS = [os.path.join(CSRC, "kpd_geom.h"), os.path.join(CSRC, "kpd_kernels.h"), os.path.join(CSRC, "kpd_tcd.h"), os.path.join(CSRC, "kpd_errors.h"),
+HEADERS = [os.path.join(CSRC, "kpd_geom.h"), os.path.join(CSRC, "kpd_kernels.h"), os.path.join(CSRC, "kpd_tcd.h"), os.path.join(CSRC, "kpd_errors.h"), os.path.join(CSRC, "kpd_group.h"),
            os.path.join(CSRC, "kpd_layers.h"), os.path.join(CSRC, "kpd_fit.h"),
            os.path.join(os.path.dirname(HERE), "include", "kpd.h")]
 

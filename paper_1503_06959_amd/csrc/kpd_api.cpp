@@ -790,6 +790,8 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     t->sparse = s->at<kpd_keypoint>(L.off_sparse1);
     t->sparse_base = s->at<uint32_t>(L.off_cbase);
     t->own_count = s->at<uint32_t>(L.off_own1);
+    t->glay1 = s->at<kpd::GroupLayout>(L.off_glay1);
+    t->al8 = (reinterpret_cast<uintptr_t>(cur) % 8 == 0 && cur_pitch % 8 == 0) ? 1 : 0;
 
     kpd::DetectArgs& d = t->d;
     d.lvl[0] = cur;
@@ -870,7 +872,7 @@ int copy_features(kpd_stream* s, const size_t* off, T* out, size_t capacity, siz
     uint32_t hdr[4];
     KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
-    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait on the device timed out");
     const uint32_t total = std::min<uint32_t>(hdr[k ? kHdrTotal1 : kHdrTotal0], (uint32_t)L.list_cap1);
     *count = total;
     if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the feature count");
@@ -1107,7 +1109,7 @@ int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity
     KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipMemcpyAsync(&total, s->at<uint32_t>(L.off_ctotal) + i, 4, hipMemcpyDeviceToHost, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
-    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait on the device timed out");
     *count = total;
     if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
     if (total > 0) {
@@ -1139,7 +1141,7 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
     KPD_HIP(hipStreamSynchronize(s->stream));
     uint32_t hdr[4];
     std::memcpy(hdr, s->stage, sizeof(hdr));
-    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait for an earlier cell timed out on the device");
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait on the device timed out");
     const uint32_t total = hdr[k ? kHdrTotal1 : kHdrTotal0];
     *count = total;
     if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
@@ -1272,6 +1274,11 @@ struct kpd_batch {
     std::vector<char> has_frame;
     int frame_blocks = 0, cell_blocks = 0;
     int frame_lds = 16, detect_lds = 16;
+    // the single-launch tick: its counters, LDS and grid (0 when it cannot
+    // run: the device holds too few of its workgroups at once)
+    bool single_launch = false;
+    kpd::TickSync* dev_sync = nullptr;
+    int tick_lds = 16, tick_grid = 0;
     bool maps_dirty = true;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     uint64_t ticks = 0;
@@ -1282,7 +1289,7 @@ namespace {
 // Batch scratch: two tick tables, the workgroup -> stream maps of the tile
 // and cell passes, the work list of marked cells and its counter.
 size_t batch_layout(int max_streams, int max_blocks, size_t* off_table, size_t* off_fmap, size_t* off_cmap,
-                    size_t* off_work = nullptr)
+                    size_t* off_work = nullptr, size_t* off_sync = nullptr)
 {
     size_t off = 0;
     off_table[0] = off; off = align_up(off + (size_t)max_streams * sizeof(kpd::TickArgs));
@@ -1291,6 +1298,8 @@ size_t batch_layout(int max_streams, int max_blocks, size_t* off_table, size_t* 
     *off_cmap = off; off = align_up(off + (size_t)max_blocks * 2);
     if (off_work) *off_work = off;
     off = align_up(off + 256 + (size_t)max_blocks * 4);   // counter, then the list
+    if (off_sync) *off_sync = off;
+    off = align_up(off + sizeof(kpd::TickSync));
     return off;
 }
 
@@ -1304,7 +1313,7 @@ void drop_graphs(kpd_batch* b)
 int rebuild_maps(kpd_batch* b)
 {
     std::vector<uint16_t> fmap, cmap;
-    int fl = 16, dl = 16;
+    int fl = 16, dl = 16, gl = 16;
     for (size_t i = 0; i < b->streams.size(); ++i) {
         const Layout& L = b->streams[i]->L;
         const int nt = L.tiles_x * L.tiles_y;
@@ -1312,6 +1321,7 @@ int rebuild_maps(kpd_batch* b)
         cmap.insert(cmap.end(), (size_t)L.ncell, (uint16_t)i);
         fl = std::max(fl, kpd::frame_lds_bytes(L.tile, L.O, L.sad_slots));
         dl = std::max(dl, L.lds_bytes);
+        gl = std::max(gl, L.glds1_256);
     }
     if ((int)fmap.size() > b->max_blocks || (int)cmap.size() > b->max_blocks)
         return fail(KPD_ENOMEM, "batch workgroup capacity exceeded");
@@ -1323,6 +1333,13 @@ int rebuild_maps(kpd_batch* b)
     b->cell_blocks = (int)cmap.size();
     b->frame_lds = fl;
     b->detect_lds = dl;
+    // the single-launch tick: as many workgroups as there are items, at most
+    // what the device holds at once, a multiple of the XCD count
+    b->tick_lds = std::max(fl, gl);
+    int cap = 0;
+    KPD_HIP(kpd::tick_capacity(b->tick_lds, &cap));
+    const int want = std::max(std::max(b->frame_blocks, b->cell_blocks), (int)b->streams.size());
+    b->tick_grid = std::min(cap, (want + 7) / 8 * 8) / 8 * 8;
     drop_graphs(b);
     b->maps_dirty = false;
     return KPD_OK;
@@ -1335,6 +1352,12 @@ hipError_t enqueue_tick(kpd_batch* b, int k)
     const size_t n = b->streams.size();
     hipError_t e = hipMemcpyAsync(b->dev_table[k], b->host_table[k], n * sizeof(kpd::TickArgs),
                                   hipMemcpyHostToDevice, b->stream);
+    if (b->single_launch && b->tick_grid > 0) {
+        if (e == hipSuccess)
+            e = kpd::launch_tick(b->dev_table[k], b->dev_fmap, b->frame_blocks, b->dev_cmap, b->cell_blocks, (int)n,
+                                 b->dev_sync, k, b->tick_grid, b->tick_lds, b->stream);
+        return e;
+    }
     if (e == hipSuccess && b->frame_blocks)
         e = kpd::launch_frame_batch(b->dev_table[k], b->dev_fmap, b->frame_blocks, b->frame_lds, b->stream);
     if (e == hipSuccess && b->cell_blocks)
@@ -1365,8 +1388,8 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
     if (!out) return fail(KPD_EINVAL, "out is NULL");
     *out = nullptr;
     if (max_streams < 1 || max_streams > 65535 || max_blocks < 1) return fail(KPD_EINVAL, "bad batch capacity");
-    size_t t[2], f, c, w;
-    const size_t need = batch_layout(max_streams, max_blocks, t, &f, &c, &w);
+    size_t t[2], f, c, w, y;
+    const size_t need = batch_layout(max_streams, max_blocks, t, &f, &c, &w, &y);
     if (!dev_scratch || reinterpret_cast<uintptr_t>(dev_scratch) % kAlign)
         return fail(KPD_EINVAL, "scratch is NULL or not 256-byte aligned");
     if (scratch_bytes < need) return fail(KPD_ENOMEM, "batch scratch too small");
@@ -1382,7 +1405,9 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
     b->dev_cmap = reinterpret_cast<uint16_t*>(b->scratch + c);
     b->dev_work_count = reinterpret_cast<uint32_t*>(b->scratch + w);
     b->dev_work = reinterpret_cast<uint32_t*>(b->scratch + w + 256);
+    b->dev_sync = reinterpret_cast<kpd::TickSync*>(b->scratch + y);
     hipError_t e = hipMemsetAsync(b->dev_work_count, 0, 4, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->dev_sync, 0, sizeof(kpd::TickSync), b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
         e = hipHostMalloc(reinterpret_cast<void**>(&b->host_table[k]), (size_t)max_streams * sizeof(kpd::TickArgs),
@@ -1394,6 +1419,16 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
         return hip_fail(e, "open_batch");
     }
     *out = b;
+    return KPD_OK;
+}
+
+int batch_set_single_launch(kpd_batch* b, int on)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (on != 0 && on != 1) return fail(KPD_EINVAL, "on must be 0 or 1");
+    KPD_HIP(hipStreamSynchronize(b->stream));   // no tick in flight uses the old form
+    b->single_launch = on != 0;
+    drop_graphs(b);
     return KPD_OK;
 }
 

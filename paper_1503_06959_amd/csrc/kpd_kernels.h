@@ -132,6 +132,17 @@ struct TickArgs {
     kpd_keypoint* sparse;
     const uint32_t* sparse_base;
     uint32_t* own_count;
+    // the stream's one-cell layouts of the group detector, and whether its
+    // level 0 can be read 8 bytes at a time (the single-launch tick)
+    const GroupLayout* glay1;
+    int al8;
+};
+
+// Counters of the single-launch tick: arrivals at its two device-wide
+// barriers, one set per tick parity (a tick clears the other parity's set,
+// which the next tick uses).
+struct TickSync {
+    uint32_t arrive[2][2];
 };
 
 // A chunk of consecutive frames of one stream, in two passes after the
@@ -249,5 +260,11 @@ hipError_t launch_mark_batch(const TickArgs* table, const uint16_t* map, int nce
 hipError_t launch_detect_list_batch(const TickArgs* table, const uint16_t* map, int ncells, const uint32_t* work,
                                     const uint32_t* work_count, int lds_bytes, hipStream_t s);
 hipError_t launch_compact_batch(const TickArgs* table, int n, uint32_t* work_count, hipStream_t s);
+// One batch tick in one launch of `grid` co-resident workgroups (phases
+// separated by device-wide barriers); `parity` selects the counter set.
+hipError_t launch_tick(const TickArgs* table, const uint16_t* fmap, int nframe, const uint16_t* cmap, int ncells,
+                       int nstreams, TickSync* sync, int parity, int grid, int lds_bytes, hipStream_t s);
+// Workgroups of the single-launch tick that fit on the device at once.
+hipError_t tick_capacity(int lds_bytes, int* blocks);
 
 }  // namespace kpd

@@ -44,6 +44,7 @@
 
 #include "kpd_fit.h"
 #include "kpd_geom.h"
+#include "kpd_group.h"
 #include "kpd_kernels.h"
 
 namespace kpd {
@@ -1638,19 +1639,19 @@ constexpr int kMaxChunk = KPD_MAX_CHUNK;
 // cell by binary search in LDS) writes D_n in cell order. Writes the counts,
 // offsets and total of D_n. A source whose entries would leave their list
 // has been clamped by source().
-template <class Source>
+template <int NT, class Source>
 __device__ void compact_frame(int ncell, uint32_t list_cap, kpd_keypoint* dst, uint32_t* cnt_out,
                               uint32_t* off_out, uint32_t* total_out, Source&& source)
 {
-    __shared__ uint32_t s_excl[kCompact], s_wsum[kCompact / 64];
-    __shared__ const kpd_keypoint* s_src[kCompact];
+    __shared__ uint32_t s_excl[NT], s_wsum[NT / 64];
+    __shared__ const kpd_keypoint* s_src[NT];
     __shared__ uint32_t s_base;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_base = 0;
     __syncthreads();
-    for (int c0 = 0; c0 < ncell; c0 += kCompact) {
+    for (int c0 = 0; c0 < ncell; c0 += NT) {
         const int c = c0 + tid;
-        const int ntile = min(kCompact, ncell - c0);
+        const int ntile = min(NT, ncell - c0);
         const uint32_t base = s_base;
         uint32_t n = 0;
         const kpd_keypoint* src = nullptr;
@@ -1676,7 +1677,7 @@ __device__ void compact_frame(int ncell, uint32_t list_cap, kpd_keypoint* dst, u
         if (tid == ntile - 1) s_wsum[0] = excl + n;
         __syncthreads();
         const uint32_t t1 = s_wsum[0];
-        for (uint32_t d = base + tid; d < t1; d += kCompact) {
+        for (uint32_t d = base + tid; d < t1; d += NT) {
             int lo = 0, hi = ntile - 1;   // largest cell of the tile starting at or before d
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
@@ -1706,7 +1707,7 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
     kpd_keypoint* dst = last ? a.next_list : a.lists + (size_t)j * a.list_stride;
     uint32_t* cnt_out = last ? a.next_count : a.counts + jc;
     uint32_t* off_out = last ? a.next_offs : a.offs + jc;
-    compact_frame(a.ncell, a.list_cap, dst, cnt_out, off_out, last ? a.next_total : a.totals + j,
+    compact_frame<kCompact>(a.ncell, a.list_cap, dst, cnt_out, off_out, last ? a.next_total : a.totals + j,
                   [&](int c, uint32_t* n, const kpd_keypoint** src) {
         // the newest frame <= j that marked this cell: its mark words up
         // to frame j, all loads issued before any is used
@@ -1884,7 +1885,7 @@ __global__ __launch_bounds__(kCompact) void k_compact_batch(const TickArgs* tabl
     const TickArgs& t = table[blockIdx.x];
     if (t.active) {
         const DetectArgs& a = t.d;
-        compact_frame(a.nc * a.nr, a.list_cap, a.list_cur, a.count_cur, a.off_cur, a.total_cur,
+        compact_frame<kCompact>(a.nc * a.nr, a.list_cap, a.list_cur, a.count_cur, a.off_cur, a.total_cur,
                       [&](int c, uint32_t* n, const kpd_keypoint** src) {
             if (a.mask[c]) {
                 const uint32_t off = t.sparse_base[c];
@@ -2041,6 +2042,118 @@ hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int ld
 hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t s)
 {
     hipLaunchKernelGGL(k_compact_chunk, dim3(n_frames), dim3(kCompact), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ k_tick
+
+// Device-wide barrier of the single-launch tick: every workgroup arrives,
+// then waits until all gridDim.x have. The fences publish each
+// workgroup's writes (pyramid, SAD sums, sparse lists) to every XCD before
+// it arrives and make the others' visible after it leaves. The wait is
+// bounded: on time-out it flags every active stream's error word and goes
+// on, so the kernel always ends.
+__device__ void tick_barrier(uint32_t* ctr, const TickArgs* table, int nstreams)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(ctr, 1u);
+        int spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+            if (++spins > kSpinLimit) {
+                for (int i = 0; i < nstreams; ++i)
+                    if (table[i].active) __hip_atomic_store(table[i].d.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// One batch tick in one launch: the tile passes of every active stream
+// (banded over the XCDs), a device-wide barrier, the marks of every cell
+// (Eq. 2 per cell, Eqs. 3-4) with the marked ones detected by the group
+// detector's one-cell layouts into their stream's sparse list, a second
+// barrier, and each stream's D_n (Eq. 1). Items are dealt to the
+// workgroups in turn; the grid is at most what fits on the device at once,
+// so every workgroup reaches every barrier.
+__global__ __launch_bounds__(kFrameBlock) void k_tick(const TickArgs* table, const uint16_t* fmap, int nframe,
+                                                      const uint16_t* cmap, int ncells, int nstreams, TickSync* sync,
+                                                      int parity)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const int G = gridDim.x;   // a multiple of kXcds: item i runs on XCD i % kXcds
+    for (int i = blockIdx.x; i < (nframe + kXcds - 1) / kXcds * kXcds; i += G) {
+        const int b = xcd_band_tile(i, nframe);
+        if (b >= nframe) continue;
+        const TickArgs& t = table[fmap[b]];
+        if (!t.active || !t.f_on) continue;
+        const FrameArgs& a = t.f;
+        const FrameSrc f{a.cur, a.prev, a.cur_pitch, a.prev_pitch, a.cur_aligned, a.prev_aligned, a.sad_on, 0, a.sad};
+        const int local = b - t.tile_base;
+        frame_tile(a, f, local % a.tiles_x, local / a.tiles_x, sm);
+        __syncthreads();   // the LDS is reused by the next tile
+    }
+    tick_barrier(&sync->arrive[parity][0], table, nstreams);
+    for (int g = blockIdx.x; g < ncells; g += G) {
+        const TickArgs& t = table[cmap[g]];
+        if (!t.active) continue;
+        const int c = g - t.cell_base;
+        const bool mark = cell_marked(t.d, c);
+        if (threadIdx.x == 0) {
+            t.d.mask[c] = (uint8_t)mark;
+            t.d.sad_next[c] = 0;
+        }
+        if (!mark) continue;
+        const GroupOut out{t.sparse, t.own_count, t.d.list_cap};
+        detect_group<kFrameBlock>(t.glay1 + c, t.d.lvl, t.d.pitch, t.al8, t.d.lvl0_aligned, t.d.t, out, sm);
+        __syncthreads();   // the LDS is reused by the next cell
+    }
+    tick_barrier(&sync->arrive[parity][1], table, nstreams);
+    for (int i = blockIdx.x; i < nstreams; i += G) {
+        const TickArgs& t = table[i];
+        if (!t.active) continue;
+        const DetectArgs& a = t.d;
+        compact_frame<kFrameBlock>(a.nc * a.nr, a.list_cap, a.list_cur, a.count_cur, a.off_cur, a.total_cur,
+                                   [&](int c, uint32_t* n, const kpd_keypoint** src) {
+            if (a.mask[c]) {
+                const uint32_t off = t.sparse_base[c];
+                *n = clamp_count(off, t.own_count[c], a.list_cap);
+                *src = t.sparse + off;
+            } else {
+                const uint32_t off = a.off_prev[c];
+                *n = clamp_count(off, a.count_prev[c], a.list_cap);
+                *src = a.list_prev + off;
+            }
+        });
+    }
+    // the next tick's counters; no workgroup of this tick reads them
+    if (blockIdx.x == 0 && threadIdx.x == 0) sync->arrive[parity ^ 1][0] = sync->arrive[parity ^ 1][1] = 0u;
+}
+
+hipError_t tick_capacity(int lds_bytes, int* blocks)
+{
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && lds_bytes > 65536)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_tick), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                lds_bytes);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_tick), kFrameBlock,
+                                                         (size_t)lds_bytes);
+    *blocks = per * cus;
+    return e;
+}
+
+hipError_t launch_tick(const TickArgs* table, const uint16_t* fmap, int nframe, const uint16_t* cmap, int ncells,
+                       int nstreams, TickSync* sync, int parity, int grid, int lds_bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tick, dim3(grid), dim3(kFrameBlock), lds_bytes, s, table, fmap, nframe, cmap, ncells,
+                       nstreams, sync, parity);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
             "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
             "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
-            "kpd_detect_layers_static",
+            "kpd_detect_layers_static", "batch_set_single_launch",
             "kpd_layer_plane", "kpd_refine_layers", "kpd_lstream_bytes", "kpd_lstream_open", "kpd_lstream_push",
             "kpd_lstream_get", "kpd_lstream_reset", "kpd_lstream_close")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
@@ -100,6 +100,7 @@ def _load() -> ctypes.CDLL:
     L.batch_detach.argtypes = [P, P]
     L.batch_push.argtypes = [P, P, P, sz, ctypes.c_int]
     L.batch_tick.argtypes = [P]
+    L.batch_set_single_launch.argtypes = [P, ctypes.c_int]
     L.batch_gather.argtypes = [P, P, sz, P]
     L.close_batch.argtypes = [P]
     L.push_frames.argtypes = [P, P, sz, sz, ctypes.c_int]
@@ -352,6 +353,10 @@ def batch_detach(batch: int, handle: int) -> None:
 def batch_push(batch: int, handle: int, frame, retain: bool = False) -> None:
     ptr, pitch, flags = _frame_args(frame, retain)
     _check(lib.batch_push(batch, handle, ptr, pitch, flags))
+
+
+def batch_set_single_launch(batch: int, on: bool) -> None:
+    _check(lib.batch_set_single_launch(batch, int(bool(on))))
 
 
 def batch_tick(batch: int) -> None:

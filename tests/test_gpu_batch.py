@@ -26,19 +26,25 @@ def tuples(arr):
     return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
 
 
-def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode="retain"):
+def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode="retain", single=True,
+              lazy=False):
     """specs: list of (Scene, (t, O, Nc, Nr, TI, TH, tile)). Every tick each
     stream not skipped pushes its next frame; after the tick every stream's
-    D_n and mask are compared with its oracle."""
+    D_n and mask are compared with its oracle. single: one launch per tick
+    (else four); lazy: the oracle's CPU-masked mode (equal to its
+    definitional mode, pinned on the CPU)."""
     import torch
     from paper_1503_06959_amd.batch import Batch
     b = Batch(max_streams=len(specs) + 2, use_graph=use_graph)
+    b.set_single_launch(single)
     streams = []
     for sc, det in specs:
         t, O, Nc, Nr, TI, TH, tile = det
         frames = synth.make_video(sc, n_ticks)
         g = b.open_stream(sc.width, sc.height, kpd.make_params(t, O, Nc, Nr, TI, TH, tile))
         o = oracle.Stream(sc.width, sc.height, t, O, Nc, Nr, TI, TH)
+        if lazy:
+            o.set_lazy(True)
         dev = torch.from_numpy(frames).cuda() if mode != "host" else None
         streams.append(dict(g=g, o=o, frames=frames, dev=dev, next=0))
     torch.cuda.synchronize()
@@ -78,17 +84,20 @@ def mixed_specs(n=8, seed0=4000):
     return specs
 
 
-def test_mixed_streams_graph(kpd):
-    run_batch(kpd, mixed_specs(8), 6, use_graph=True)
+@pytest.mark.parametrize("single", [True, False])
+def test_mixed_streams_graph(kpd, single):
+    run_batch(kpd, mixed_specs(8), 6, use_graph=True, single=single)
 
 
-def test_mixed_streams_eager_and_host_frames(kpd):
-    run_batch(kpd, mixed_specs(5, 4100), 4, use_graph=False, mode="host")
+@pytest.mark.parametrize("single", [True, False])
+def test_mixed_streams_eager_and_host_frames(kpd, single):
+    run_batch(kpd, mixed_specs(5, 4100), 4, use_graph=False, mode="host", single=single)
 
 
-def test_streams_skipping_ticks(kpd):
+@pytest.mark.parametrize("single", [True, False])
+def test_streams_skipping_ticks(kpd, single):
     # streams with no frame in a tick are inactive; their state must not move
-    run_batch(kpd, mixed_specs(6, 4200), 7, use_graph=True, skip=lambda s, t: (s + t) % 3 == 0)
+    run_batch(kpd, mixed_specs(6, 4200), 7, use_graph=True, skip=lambda s, t: (s + t) % 3 == 0, single=single)
 
 
 def test_tile_size_does_not_change_results(kpd):
@@ -102,12 +111,26 @@ def test_tile_size_does_not_change_results(kpd):
     run_batch(kpd, specs, 4)
 
 
-def test_batch_of_64_mixed_streams(kpd):
+@pytest.mark.parametrize("single", [True, False])
+def test_batch_of_64_mixed_streams(kpd, single):
     specs = []
     for sc, det in synth.batch_streams(8):
         specs.append((sc, (det.fast_t, det.n_octaves, det.grid_cols, det.grid_rows, det.id_thresh,
                            det.kb_thresh, 0)))
-    run_batch(kpd, specs, 8)
+    run_batch(kpd, specs, 8, single=single)
+
+
+def test_c4_64_streams_full_length(kpd):
+    # the batched workload at full length: 64 mixed streams, 120 generated
+    # frames each, one tick per frame (the default four-launch form), every
+    # stream's D_n and mask compared with its own oracle stream after every
+    # tick
+    specs = []
+    for sc, det in synth.batch_streams(120):
+        specs.append((sc, (det.fast_t, det.n_octaves, det.grid_cols, det.grid_rows, det.id_thresh,
+                           det.kb_thresh, 0)))
+    assert len(specs) == 64
+    run_batch(kpd, specs, 120, lazy=True, single=False)
 
 
 def test_attach_detach_between_ticks(kpd):

@@ -110,3 +110,19 @@ def test_512_threads(kpd, groups):
     rng = np.random.default_rng(9)
     frames = rng.integers(0, 256, size=(2, 130, 170), dtype=np.uint8)
     full_frame_chunk(kpd, frames, (5, 4, 3, 2, -1, KB_OFF), (min(groups[0], 3), min(groups[1], 2)), threads=512)
+
+
+def test_every_autotuner_choice_gives_identical_keypoints(kpd, tmp_path, monkeypatch):
+    # every (cells per workgroup, threads) the tuner may pick gives the
+    # oracle's D_n; the tuner's pick is one of them and is cached
+    from paper_1503_06959_amd import autotune
+    d = synth.DETECTORS["c2_640x480"]
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 3)
+    cands = autotune.group_candidates(640, 480, d)
+    assert (1, 1, 256) in cands and (4, 1, 512) in cands
+    for gx, gy, nt in cands:
+        full_frame_chunk(kpd, frames, (20, 4, 16, 12, -1, KB_OFF), (gx, gy), threads=nt)
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    best, times = autotune.best_groups(640, 480, d)
+    assert best in cands and set(times) == set(cands)
+    assert autotune.best_groups(640, 480, d) == (best, {})   # from the cache
