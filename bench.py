@@ -254,7 +254,9 @@ def kernel_profile(kpd, s, wl: Workload, steps: int):
 def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> dict:
     """Bytes the method must move per pass over the video, per kernel.
     The tile pass reads I_n (and I_{n-1} for the intensity-difference test)
-    and writes the coarser octaves. The cell pass reads the octave pixels of
+    and writes the coarser octaves: all of them in full-frame mode, the
+    marked cells' share f * P of them in masked mode (2N + f P per frame;
+    what a pass writes beyond that is waste, not method). The cell pass reads the octave pixels of
     the marked cells, writes their keypoints, and carries the others' (Eq. 1)
     with a 16-byte read+write per entry; 24 bytes per cell and frame cover
     the per-cell counts, offsets and SAD. In chunks the cell pass writes
@@ -274,7 +276,8 @@ def algorithmic_bytes(wl: Workload, st, masked: bool, chunked: bool = False) -> 
     carried = sum(t - n for t, n in zip(st["total_kp"], st["new_kp"]))
     meta = 24 * wl.ncell * F
     scan = sum(f * sum(lv) for f in frac) + 8 * sum(st["new_kp"])
-    out = {"k_frame": F * (N + P) + N * sad_frames}
+    pyr = P * (sum(frac) if masked and layer is None else F)
+    out = {"k_frame": F * N + pyr + N * sad_frames}
     if chunked:
         out["k_detect"] = scan + 16 * wl.ncell * F
         out["k_compact"] = 16 * sum(st["total_kp"]) + meta
@@ -560,9 +563,9 @@ def roofline_of(wl: Workload, res, masked: bool, traffic=None, stats=None):
     }
 
 
-def _time_oracle(wl: Workload, id_thresh: int, lazy: bool, seconds: float):
-    """Frames of the workload through one oracle stream for about `seconds`;
-    returns (frames, seconds)."""
+def _time_oracle(wl: Workload, id_thresh: int, lazy: bool, seconds: float, min_frames: int = 10):
+    """Frames of the workload through one oracle stream for about `seconds`
+    (at least min_frames); returns (frames, seconds)."""
     import oracle
     d = wl.det
     s = oracle.Stream(wl.W, wl.H, d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, id_thresh, d.kb_thresh)
@@ -573,7 +576,7 @@ def _time_oracle(wl: Workload, id_thresh: int, lazy: bool, seconds: float):
         for i in range(wl.F):
             s.push(wl.frames[i])
             n += 1
-            if time.perf_counter() - t0 >= seconds and n >= 30:
+            if time.perf_counter() - t0 >= seconds and n >= min_frames:
                 break
         if time.perf_counter() - t0 >= seconds:
             break
@@ -786,10 +789,16 @@ PROFILE_CASES = {
     "kt_c2_640x480_bench": ("trace", "--no-hd --no-batch --no-serve --no-cpu-baseline --steps 10 --warmup 2"),
     "kt_c2_640x480_masked_chunked": ("trace", "--workload c2_640x480 --mode masked --chunked --steps 20 --warmup 2"),
     "kt_c3_1920x1080_full_chunked": ("trace", "--workload c3_1920x1080 --mode full --chunked --steps 10 --warmup 2"),
+    "kt_c3_1920x1080_masked_chunked": ("trace",
+                                       "--workload c3_1920x1080 --mode masked --chunked --steps 10 --warmup 2"),
+    "kt_c3_1920x1080_masked_frame": ("trace", "--workload c3_1920x1080 --mode masked --steps 4 --warmup 1"),
+    "kt_c3_1920x1080_full_frame": ("trace", "--workload c3_1920x1080 --mode full --steps 4 --warmup 1"),
     "kt_c2_640x480_layer3_frame": ("trace", "--workload c2_640x480 --mode masked --layer 3 --steps 10 --warmup 2"),
     "pmc_c2_640x480_masked_chunked": ("pmc", "--workload c2_640x480 --mode masked --chunked --steps 2 --warmup 0"),
     "pmc_c2_640x480_full_chunked": ("pmc", "--workload c2_640x480 --mode full --chunked --steps 2 --warmup 0"),
     "pmc_c3_1920x1080_full_chunked": ("pmc", "--workload c3_1920x1080 --mode full --chunked --steps 2 --warmup 0"),
+    "pmc_c3_1920x1080_masked_chunked": ("pmc",
+                                        "--workload c3_1920x1080 --mode masked --chunked --steps 2 --warmup 0"),
     "pmc_c2_640x480_layer3_frame": ("pmc", "--workload c2_640x480 --mode masked --layer 3 --steps 2 --warmup 0"),
     "pmc_copy_256MiB": ("pmc", "--copy-calibration 256"),
     "valu_c3_1920x1080_full_chunked": ("valu", "--workload c3_1920x1080 --mode full --chunked --steps 2 --warmup 0"),
@@ -800,11 +809,13 @@ VALU_SETS = (("VALUBusy",), ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_
                              "GRBM_GUI_ACTIVE"))
 # kernel -> (push path, the timed kernel id its launches count under)
 KERNEL_IDS = {"k_frame1": ("frame", "k_frame"), "k_detect1": ("frame", "k_detect"),
+              "k_det1_groups": ("frame", "k_detect"), "k_compact1": ("frame", "k_compact"),
               "k_frame_chunk": ("chunk", "k_frame"), "k_detect_chunk": ("chunk", "k_detect"),
+              "k_detect_chunk_groups": ("chunk", "k_detect"),
               "k_detect_list": ("chunk", "k_detect"), "k_mark_chunk": ("chunk", "k_mark"),
               "k_compact_chunk": ("chunk", "k_compact")}
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ("kpd_kernels.hip", "kpd_kernels.h", "kpd_geom.h")
+KERNEL_SOURCES = ("kpd_kernels.hip", "kpd_kernels.h", "kpd_geom.h", "kpd_group.h", "kpd_group.hip")
 
 
 def kernel_source_hash() -> str:
@@ -895,7 +906,7 @@ def summarize_profiles(out: str) -> None:
         if PROFILE_CASES[case][0] == "pmc":
             for c in PMC_COUNTERS:
                 lines.append("  " + profile_command(case, "$OUT", c))
-    lines += ["", f"{'case':34s} {'kernel':16s} {'dispatches':>10s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} "
+    lines += ["", f"{'case':34s} {'kernel':22s} {'dispatches':>10s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} "
                   f"{'bytes/launch':>13s}"]
     for case, (kind, _) in PROFILE_CASES.items():
         if kind != "pmc" or case == "pmc_copy_256MiB":
@@ -910,7 +921,7 @@ def summarize_profiles(out: str) -> None:
             key = f"{wl}/{mode}/{KERNEL_IDS[k][0]}/{KERNEL_IDS[k][1]}"
             acc[key][0] += b * f[k][1]
             acc[key][1] += f[k][1]
-            lines.append(f"{case[4:]:34s} {k:16s} {f[k][1]:10d} {f[k][0]:11.2f} {w[k][0]:11.2f} {int(b):13d}")
+            lines.append(f"{case[4:]:34s} {k:22s} {f[k][1]:10d} {f[k][0]:11.2f} {w[k][0]:11.2f} {int(b):13d}")
         for key, (b, n) in acc.items():
             traffic["per_launch_bytes"][key] = int(b / n)
     open(os.path.join(pdir, "hbm_traffic_chunked_and_single.txt"), "w").write("\n".join(lines) + "\n")
@@ -925,16 +936,16 @@ def summarize_profiles(out: str) -> None:
              "commands (R = the repository root, OUT = the output folder given to --profile-script, run from /tmp):"]
     for c in VALU_SETS:
         lines.append("  " + profile_command(case, "$OUT", " ".join(c)))
-    lines += ["", f"{'kernel':16s} {'dispatches':>10s} {'VALUBusy%':>10s} {'VALU insts':>14s} {'waves':>10s} "
+    lines += ["", f"{'kernel':22s} {'dispatches':>10s} {'VALUBusy%':>10s} {'VALU insts':>14s} {'waves':>10s} "
                   f"{'wait/wave cyc':>13s} {'lane-ops/px-oct':>16s}"]
-    for k in ("k_frame_chunk", "k_detect_chunk", "k_compact_chunk"):
+    for k in ("k_frame_chunk", "k_detect_chunk_groups", "k_compact_chunk"):
         if k not in busy or k not in cnt["SQ_INSTS_VALU"]:
             continue
         insts, n = cnt["SQ_INSTS_VALU"][k]
         waves = cnt["SQ_WAVES"][k][0]
         wait = cnt["SQ_WAIT_ANY"][k][0] / max(cnt["SQ_WAVE_CYCLES"][k][0], 1)
-        per = insts * 64 / px_oct if k == "k_detect_chunk" else float("nan")
-        lines.append(f"{k:16s} {n:10d} {busy[k][0]:10.1f} {insts:14.0f} {waves:10.0f} {wait:13.3f} {per:16.1f}")
+        per = insts * 64 / px_oct if k == "k_detect_chunk_groups" else float("nan")
+        lines.append(f"{k:22s} {n:10d} {busy[k][0]:10.1f} {insts:14.0f} {waves:10.0f} {wait:13.3f} {per:16.1f}")
     lines += ["", "lane-ops/px-oct: VALU instructions x 64 lanes per pixel-octave of the launch "
                   f"({px_oct} = 300 frames x {sum(lv)})"]
     open(os.path.join(pdir, "valu_c3_1920x1080_full_chunked.txt"), "w").write("\n".join(lines) + "\n")
@@ -1138,13 +1149,28 @@ def main():
                 "masked": {"value": round(hm["mpix_per_s"], 2), "unit": "Mpixel/s",
                            "frames_per_s": round(hm["frames_per_s"], 1),
                            "latency_ms": {"p50": round(hm["lat_p50"], 4), "p99": round(hm["lat_p99"], 4)},
+                           "device_ms_per_frame": {"p50": round(hm["dev_p50"], 4), "p99": round(hm["dev_p99"], 4)},
                            "roofline": roofline_of(hd, hm, True)},
                 "full_frame": dict({"value": round(hf["mpix_per_s"], 2), "unit": "Mpixel/s",
                                     "frames_per_s": round(hf["frames_per_s"], 1),
                                     "latency_ms": {"p50": round(hf["lat_p50"], 4), "p99": round(hf["lat_p99"], 4)},
+                                    "device_ms_per_frame": {"p50": round(hf["dev_p50"], 4),
+                                                            "p99": round(hf["dev_p99"], 4)},
                                     "roofline": roofline_of(hd, hf, False)}, **eff(hf)),
+                "masked_over_full_device_p50": round(hm["dev_p50"] / hf["dev_p50"], 3),
+                "masked_over_full_device_p99": round(hm["dev_p99"] / hf["dev_p99"], 3),
             },
+            "skipped_cell_frac": round(1.0 - sum(hm["marked"][1:]) / max(1, (hd.F - 1) * hd.ncell), 4),
         }
+        # The headline roofline: the 1080p masked chunk pass, whose 300 frames
+        # (622 MB) exceed the 256 MB Infinity Cache, so its bytes come from HBM.
+        out["roofline_c2_640x480"] = dict(out["roofline"], note="the 300 C2 frames (92 MB) and their pyramid fit "
+                                          "in the 256 MB Infinity Cache across steps: not HBM evidence")
+        out["roofline"] = dict(out["hd_1080p"]["masked"]["roofline"],
+                               workload=f"{hd.name} masked (T_I={hd.det.id_thresh}), push_frames of {K} frames")
+        if not args.no_cpu_baseline:
+            log("[bench] 1080p cpu baseline (oracle)")
+            out["hd_1080p"]["cpu_baseline"] = cpu_baseline(hd, args.cpu_seconds)
         wl = hd
     if not args.no_batch:
         del wl

@@ -68,6 +68,8 @@ struct Layout {
     // tables of the tile and detection passes
     int K = 1, Kw = 1;
     int ctile = 32, ctiles_x = 0, ctiles_y = 0, csad_slots = 1;   // tile pass of chunks
+    bool seq_ok = false;   // the sequential tile pass of chunks can run (k_frame_chunk_seq)
+    int seq_tile_w = 256, seq_tiles_x = 0, seq_ntiles = 0, seq_slots = 1;   // its tiles, LDS slots a tile
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
     size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0, off_work = 0;
@@ -181,6 +183,27 @@ bool group_layouts(const Layout& L, int gx, int gy, int waves, std::vector<kpd::
 constexpr int kGroupWaves = 4;           // 256-thread workgroups for one-cell layouts
 constexpr int kGroupLdsDefault = 48 * 1024;   // default groups: three workgroups per CU
 
+// Whether the sequential tile pass takes this geometry: octaves to level 5
+// (O <= 6), the frame width a multiple of 16, every 16-column segment in at
+// most two cell columns, each dword in one, and every block of 4 rows (its
+// rows inside the frame) in at most two cell rows: the kernel sums such a
+// block in four registers. Column X is in cell column floor(X Nc / W), row
+// Y in cell row floor(Y Nr / H).
+bool seq_geometry_ok(const Layout& L)
+{
+    if (L.O > 6 || L.W % 16 != 0) return false;
+    auto ccol = [&](int x) { return (int)(((int64_t)x * L.nc) / L.W); };
+    auto crow = [&](int y) { return (int)(((int64_t)y * L.nr) / L.H); };
+    for (int x = 0; x < L.W; x += 16) {
+        for (int d = 0; d < 4; ++d)
+            if (ccol(x + 4 * d) != ccol(x + 4 * d + 3)) return false;
+        if (ccol(x + 15) - ccol(x) > 1) return false;
+    }
+    for (int y = 0; y < L.H; y += 4)
+        if (crow(std::min(y + 3, L.H - 1)) - crow(y) > 1) return false;
+    return true;
+}
+
 bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
 {
     if (!valid_params(W, H, p, why)) return false;
@@ -189,7 +212,9 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     for (int o = 0; o < L->O; ++o) {
         L->w[o] = W >> o;
         L->h[o] = H >> o;
-        L->pitch[o] = kpd::round_up(L->w[o], 64);
+        // whole 128-byte lines per level row: the tile passes write each
+        // row in aligned runs, which neighbouring tiles complete in the L2
+        L->pitch[o] = kpd::round_up(L->w[o], 128);
     }
     L->slot_pitch = kpd::round_up(W, 64);
     L->tile = p->tile ? p->tile : std::max(32, 1 << (L->O - 1));
@@ -224,6 +249,16 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->ctiles_x = (W + L->ctile - 1) / L->ctile;
     L->ctiles_y = (H + L->ctile - 1) / L->ctile;
     L->csad_slots = span_max(W, L->nc, L->ctile) * span_max(H, L->nr, L->ctile);
+    L->seq_ok = seq_geometry_ok(*L);
+    // 256 x 64 tiles (level-1 rows in whole lines) when their octaves reach
+    // far enough and at most a tenth of the last tile column lies past the
+    // frame, else 128 x 128
+    const int pad256 = (W + 255) / 256 * 256 - W;
+    L->seq_tile_w = (L->O <= 5 && pad256 * 10 <= W) ? 256 : 128;
+    const int seq_th = 4 * (256 / (L->seq_tile_w / 16));
+    L->seq_tiles_x = (W + L->seq_tile_w - 1) / L->seq_tile_w;
+    L->seq_ntiles = L->seq_tiles_x * ((H + seq_th - 1) / seq_th);
+    L->seq_slots = span_max(W, L->nc, L->seq_tile_w) * span_max(H, L->nr, seq_th);
 
     // keypoint list capacity and the detection kernel's LDS need
     size_t cap = 0, dec_px = 0;
@@ -396,6 +431,7 @@ struct kpd_stream {
     int prev_pitch = 0;
     int prev_dw = 0;
     int fb_last = 1;          // which of the two single-frame buffers holds the latest D_n
+    int seq_cap = 0;          // resident workgroups of the sequential chunk tile pass (0: not asked yet)
     int id_mode = 0;          // 0: per-cell mean difference at level 0; 1: per-pixel on layer id_layer;
                               // 2: per-pixel on every level, one mask per octave
     int id_layer = 0;
@@ -971,6 +1007,34 @@ int set_mask_mode(kpd_stream* s, int mode, int layer)
     return KPD_OK;
 }
 
+// Frames per workgroup of the sequential tile pass of a chunk of n frames
+// (0 when the stream's tiles cannot take it). Every workgroup of a chunk
+// does the same work, so the pass takes as long as its rounds of `cap`
+// resident workgroups: the run is chosen for the fullest last round over
+// one to four rounds, at least 8 frames a run (each run re-reads the frame
+// before it) and a multiple of four (the kernel's steps go in fours).
+int seq_run(const Layout& L, int n, int cap)
+{
+    if (!L.seq_ok || cap <= 0) return 0;
+    const int ntiles = L.seq_ntiles;
+    int best = 0;
+    double best_eff = 0.0;
+    for (int m = 1; m <= 4; ++m) {
+        const int nruns = std::max(1, m * cap / ntiles);
+        const int run = (std::max(6, (n + nruns - 1) / nruns) + 3) / 4 * 4;   // whole groups of four steps
+        const int used = (n + run - 1) / run;
+        const int rounds = (used * ntiles + cap - 1) / cap;
+        const double eff = (double)used * ntiles / ((double)rounds * cap);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = run;
+        }
+    }
+    best = std::min(best, n);
+    if (kpd::frame_seq_lds_bytes(L.seq_slots, best) > 65536) return 0;
+    return best;
+}
+
 int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes, int n_frames)
 {
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
@@ -1019,8 +1083,30 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     const bool any_tiles = L.O > 1 || (s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
                                        (n_frames > 1 || !h.force0));
     const kpd::ChunkArgs* ctab = s->at<kpd::ChunkArgs>(L.off_ctab);
+    // frames that test intensity differences walk each tile in frame order
+    // (each frame read once) when the tile builds its octaves in registers
+    // (16-byte aligned rows of the chunk's frames and of the frame before)
+    auto al16 = [](const uint8_t* p, size_t pitch_b) {
+        return reinterpret_cast<uintptr_t>(p) % 16 == 0 && pitch_b % 16 == 0;
+    };
+    if (L.seq_ok && s->seq_cap == 0) {
+        // resident workgroups of the sequential pass (its LDS is a few KB)
+        int cap = 0;
+        KPD_HIP(kpd::frame_seq_capacity(kpd::frame_seq_lds_bytes(L.seq_slots, 64), &cap));
+        s->seq_cap = std::max(cap, 1);
+    }
+    const int run = seq_run(L, n_frames, s->seq_cap);
+    const bool seq = run > 0 && s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
+                     (n_frames > 1 || !h.force0) && al16(frames, pitch_bytes) && frame_stride % 16 == 0 &&
+                     (h.force0 || al16(h.prev0, (size_t)h.prev0_pitch));
     if (any_tiles)
         KPD_HIP(timed(s, KPD_K_FRAME, [&] {
+            if (seq) {
+                // chunks above the 256 MB last level cache stream their frames
+                const bool nt = (double)n_frames * (double)frame_stride > 256.0 * 1024 * 1024;
+                const kpd::SeqGrid g{L.seq_tile_w, L.seq_tiles_x, L.seq_ntiles, L.seq_slots, run};
+                return kpd::launch_frame_chunk_seq(s->chunk_fa, L.pyr_stride, h, g, nt, s->stream);
+            }
             return kpd::launch_frame_chunk(s->chunk_fa, L.pyr_stride, h, kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots),
                                            s->stream);
         }));
@@ -1034,19 +1120,32 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         KPD_HIP(timed(s, KPD_K_DETECT, [&] {
             return kpd::launch_detect_chunk_groups(ctab, h, ga, L.glds, L.gthreads, s->stream);
         }));
-    } else if (h.kb_chain) {
-        // marks that depend on the counts: detect every frame a cell's chain
-        // can mark, then walk each cell's frames to keep the marks
-        const uint32_t* own = s->at<uint32_t>(L.off_own);
-        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_spec_chunk(h, s->stream); }));
-        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_list(ctab, h, L.lds_bytes, s->stream, 0); }));
-        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_spec2_chunk(h, own, s->stream); }));
-        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_list(ctab, h, L.lds_bytes, s->stream, 1); }));
-        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_resolve_chunk(h, own, s->stream); }));
     } else {
-        // marks from the SAD alone: list the marked cells, detect only those
-        KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(h, s->stream); }));
-        KPD_HIP(timed(s, KPD_K_DETECT, [&] { return kpd::launch_detect_list(ctab, h, L.lds_bytes, s->stream); }));
+        // listed (frame, cell) items, each detected with its one-cell layout
+        kpd::GroupArgs g1{};
+        g1.layouts = s->at<kpd::GroupLayout>(L.off_glay1);
+        g1.ngroups = L.ncell;
+        g1.nc = L.nc;
+        g1.al8 = (reinterpret_cast<uintptr_t>(frames) % 8 == 0 && frame_stride % 8 == 0 && pitch % 8 == 0) ? 1 : 0;
+        auto detect = [&](int round) {
+            return timed(s, KPD_K_DETECT, [&] {
+                return kpd::launch_detect_list_groups(ctab, h, g1, L.glds1_256, 256, round, s->stream);
+            });
+        };
+        if (h.kb_chain) {
+            // marks that depend on the counts: detect every frame a cell's
+            // chain can mark, then walk each cell's frames to keep the marks
+            const uint32_t* own = s->at<uint32_t>(L.off_own);
+            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_spec_chunk(h, s->stream); }));
+            KPD_HIP(detect(0));
+            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_spec2_chunk(h, own, s->stream); }));
+            KPD_HIP(detect(1));
+            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_resolve_chunk(h, own, s->stream); }));
+        } else {
+            // marks from the SAD alone: list the marked cells, detect only those
+            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(h, s->stream); }));
+            KPD_HIP(detect(0));
+        }
     }
     kpd::CompactArgs ca{};
     ca.ncell = L.ncell;
@@ -1273,7 +1372,7 @@ struct kpd_batch {
     std::vector<kpd::TickArgs> staged;                  // per attached stream
     std::vector<char> has_frame;
     int frame_blocks = 0, cell_blocks = 0;
-    int frame_lds = 16, detect_lds = 16;
+    int frame_lds = 16, detect_lds = 16, detect_glds = 16;
     // the single-launch tick: its counters, LDS and grid (0 when it cannot
     // run: the device holds too few of its workgroups at once)
     bool single_launch = false;
@@ -1333,6 +1432,7 @@ int rebuild_maps(kpd_batch* b)
     b->cell_blocks = (int)cmap.size();
     b->frame_lds = fl;
     b->detect_lds = dl;
+    b->detect_glds = gl;
     // the single-launch tick: as many workgroups as there are items, at most
     // what the device holds at once, a multiple of the XCD count
     b->tick_lds = std::max(fl, gl);
@@ -1364,8 +1464,8 @@ hipError_t enqueue_tick(kpd_batch* b, int k)
         e = kpd::launch_mark_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->dev_work, b->dev_work_count,
                                    b->stream);
     if (e == hipSuccess && b->cell_blocks)
-        e = kpd::launch_detect_list_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->dev_work,
-                                          b->dev_work_count, b->detect_lds, b->stream);
+        e = kpd::launch_detect_list_batch_groups(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->dev_work,
+                                                 b->dev_work_count, b->detect_glds, b->stream);
     if (e == hipSuccess && n)
         e = kpd::launch_compact_batch(b->dev_table[k], (int)n, b->dev_work_count, b->stream);
     return e;

@@ -1,6 +1,7 @@
 // Kernels of the gfx950 group detector (kpd_group.h): full-frame chunks,
-// one workgroup per (frame, group of cells), and single frames with the
-// per-cell mask, one workgroup per cell.
+// one workgroup per (frame, group of cells); single frames with the
+// per-cell mask, one workgroup per cell; and the listed marked cells of
+// masked chunks and batch ticks, one cell per workgroup at a time.
 #include <hip/hip_runtime.h>
 
 #include "kpd_group.h"
@@ -70,6 +71,77 @@ __global__ __launch_bounds__(NT) void k_det1_groups(DetectArgs a, GroupArgs g, k
     detect_group<NT>(g.layouts + c, a.lvl, a.pitch, g.al8, a.lvl0_aligned, a.t, out, sm);
 }
 
+// Listed (frame, cell) items of a chunk (marks from the SAD, or from the
+// counts in rounds): workgroups take items in turn; cell c of frame j
+// detects with its one-cell layout on frame j's levels and writes its
+// keypoints at its base of frame j's sparse list. Round 0 takes items
+// [0, count 0), round 1 [count 0, count 0 + count 1).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_detect_list_groups(const ChunkArgs* table, ChunkHead h, GroupArgs g, int round)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const uint32_t b = round ? h.work_count[0] : 0u;
+    const uint32_t n = b + h.work_count[round];
+    for (uint32_t it = b + blockIdx.x; it < n; it += gridDim.x) {
+        const uint32_t item = h.work[it];
+        const int j = (int)(item / (uint32_t)h.ncell);
+        const int c = (int)(item - (uint32_t)j * h.ncell);
+        const ChunkArgs& t = table[j];
+        const uint8_t* lv[KPD_MAX_OCTAVES];
+        int pt[KPD_MAX_OCTAVES];
+#pragma unroll
+        for (int o = 0; o < KPD_MAX_OCTAVES; ++o) {
+            lv[o] = t.d.lvl[o];
+            pt[o] = t.d.pitch[o];
+        }
+        lv[0] = h.frames + (size_t)j * h.stride;
+        pt[0] = h.pitch;
+        const GroupOut out{t.d.list_cur, t.own_count, t.d.list_cap};
+        detect_group<NT>(g.layouts + c, lv, pt, g.al8, h.aligned, h.t, out, sm);
+        __syncthreads();   // the layout and the LDS maps are reused by the next item
+    }
+}
+
+// Listed cells of a batch tick: work item g is cell g - cell_base of stream
+// map[g], detected with that stream's one-cell layout on its levels.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_detect_list_batch_groups(const TickArgs* table, const uint16_t* map,
+                                                                 const uint32_t* work, const uint32_t* work_count)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const uint32_t n = *work_count;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const int gi = (int)work[it];
+        const TickArgs& t = table[map[gi]];
+        const int c = gi - t.cell_base;
+        const GroupOut out{t.sparse, t.own_count, t.d.list_cap};
+        detect_group<NT>(t.glay1 + c, t.d.lvl, t.d.pitch, t.al8, t.d.lvl0_aligned, t.d.t, out, sm);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_detect_list_groups(const ChunkArgs* table, const ChunkHead& h, const GroupArgs& g, int lds_bytes,
+                                     int threads, int round, hipStream_t s)
+{
+    const int items = h.n_frames * h.ncell;
+    const int grid = items < 2048 ? items : 2048;
+    if (threads == 512)
+        hipLaunchKernelGGL(k_detect_list_groups<512>, dim3(grid), dim3(512), lds_bytes, s, table, h, g, round);
+    else
+        hipLaunchKernelGGL(k_detect_list_groups<256>, dim3(grid), dim3(256), lds_bytes, s, table, h, g, round);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_list_batch_groups(const TickArgs* table, const uint16_t* map, int ncells,
+                                           const uint32_t* work, const uint32_t* work_count, int lds_bytes,
+                                           hipStream_t s)
+{
+    const int grid = ncells < 2048 ? ncells : 2048;
+    hipLaunchKernelGGL(k_detect_list_batch_groups<256>, dim3(grid), dim3(256), lds_bytes, s, table, map, work,
+                       work_count);
+    return hipGetLastError();
+}
+
 hipError_t launch_det1_groups(const DetectArgs& a, const GroupArgs& g, kpd_keypoint* sparse, uint32_t* own,
                               int ncell, int lds_bytes, int threads, hipStream_t s)
 {
@@ -98,7 +170,10 @@ hipError_t set_group_lds_limit(int lds_bytes)
     const void* kernels[] = {reinterpret_cast<const void*>(k_detect_chunk_groups<512>),
                              reinterpret_cast<const void*>(k_detect_chunk_groups<256>),
                              reinterpret_cast<const void*>(k_det1_groups<512>),
-                             reinterpret_cast<const void*>(k_det1_groups<256>)};
+                             reinterpret_cast<const void*>(k_det1_groups<256>),
+                             reinterpret_cast<const void*>(k_detect_list_groups<512>),
+                             reinterpret_cast<const void*>(k_detect_list_groups<256>),
+                             reinterpret_cast<const void*>(k_detect_list_batch_groups<256>)};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) return e;

@@ -226,6 +226,11 @@ struct GroupArgs {
     int al8;
 };
 
+hipError_t launch_detect_list_groups(const ChunkArgs* table, const ChunkHead& h, const GroupArgs& g, int lds_bytes,
+                                     int threads, int round, hipStream_t s);
+hipError_t launch_detect_list_batch_groups(const TickArgs* table, const uint16_t* map, int ncells,
+                                           const uint32_t* work, const uint32_t* work_count, int lds_bytes,
+                                           hipStream_t s);
 hipError_t launch_detect_chunk_groups(const ChunkArgs* table, const ChunkHead& h, const GroupArgs& g, int lds_bytes,
                                       int threads, hipStream_t s);
 hipError_t set_group_lds_limit(int lds_bytes);
@@ -236,14 +241,24 @@ hipError_t launch_det1_groups(const DetectArgs& a, const GroupArgs& g, kpd_keypo
 hipError_t launch_compact1(const DetectArgs& a, const kpd_keypoint* sparse, const uint32_t* cbase,
                            const uint32_t* own, hipStream_t s);
 
+// The sequential tile pass of chunks with intensity differences (tiles of
+// 256 x 64 for O <= 5, or 128 x 128 for O <= 6): `run` frames per
+// workgroup, each read once; tiles_x and ntiles count its tiles, slots the
+// cells one tile can touch.
+struct SeqGrid {
+    int tile_w, tiles_x, ntiles, slots, run;
+};
+int frame_seq_lds_bytes(int slots, int run);
+// Workgroups of the sequential tile pass the device holds at once.
+hipError_t frame_seq_capacity(int lds_bytes, int* blocks);
+// nt: read the frames non-temporally (chunks larger than the last level cache).
+hipError_t launch_frame_chunk_seq(const FrameArgs& a, size_t pyr_stride, const ChunkHead& h, const SeqGrid& g,
+                                  bool nt, hipStream_t s);
 hipError_t launch_frame_chunk(const FrameArgs& a, size_t pyr_stride, const ChunkHead& h, int lds_bytes, hipStream_t s);
-hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s);
 hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s);
 hipError_t launch_spec_chunk(const ChunkHead& h, hipStream_t s);
 hipError_t launch_spec2_chunk(const ChunkHead& h, const uint32_t* own, hipStream_t s);
 hipError_t launch_resolve_chunk(const ChunkHead& h, const uint32_t* own, hipStream_t s);
-hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s,
-                              int round = 0);
 hipError_t launch_compact_chunk(const CompactArgs& a, int n_frames, hipStream_t s);
 
 int frame_sad_lds_off(int tile, int O);
@@ -257,8 +272,6 @@ hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, 
                                hipStream_t s);
 hipError_t launch_mark_batch(const TickArgs* table, const uint16_t* map, int ncells, uint32_t* work,
                              uint32_t* work_count, hipStream_t s);
-hipError_t launch_detect_list_batch(const TickArgs* table, const uint16_t* map, int ncells, const uint32_t* work,
-                                    const uint32_t* work_count, int lds_bytes, hipStream_t s);
 hipError_t launch_compact_batch(const TickArgs* table, int n, uint32_t* work_count, hipStream_t s);
 // One batch tick in one launch of `grid` co-resident workgroups (phases
 // separated by device-wide barriers); `parity` selects the counter set.

@@ -50,13 +50,9 @@
 namespace kpd {
 
 constexpr int kFrameBlock = 256;
-// Detection workgroup sizes: 512 threads where one cell's latency decides
-// (single frames, chunks with few cells to detect), 256 where many cells are
-// in flight at once (more, smaller workgroups keep the CUs busier).
+// Workgroup size of the cell-layout detector (the per-pixel mask modes of
+// single frames), where one cell's latency decides.
 constexpr int kDetLatency = kDetectBlock;
-constexpr int kDetThroughput = 256;
-// A chunk list pass takes the latency size up to this many (frame, cell) items.
-constexpr int kListLatencyItems = 65536;
 constexpr int kRegOctaves = 6;   // 128-px tiles build up to this many levels in registers
 
 // floor(i / d) with magic = div_magic(d) (see kpd_geom.h)
@@ -103,11 +99,13 @@ __device__ __forceinline__ void store_px(uint8_t* out, int pitch, int w, int h, 
 // its own; level 3 pairs it with the thread one row block down (8 lanes
 // on), level 4 with the threads 16 and 24 lanes on, and level 5 with the
 // thread 32 lanes on and the next segment. Outputs go straight to the
-// level buffers.
-__device__ __forceinline__ void pyramid_regs(const FrameArgs& a, const FrameSrc& f, const uint4* rows, int x0,
-                                             int y0, int rb, int seg)
+// level buffers through st.put<N>(octave, x, y, low dword, high dword, on):
+// N pixels, stored by the threads with `on` set.
+template <class Store>
+__device__ __forceinline__ void pyramid_regs(const Store& st, int O, const uint4* rows, int x0, int y0, int rb,
+                                             int seg)
 {
-    if (a.O <= 1) return;
+    if (O <= 1) return;
     const uint32_t r[4][4] = {{rows[0].x, rows[0].y, rows[0].z, rows[0].w},
                               {rows[1].x, rows[1].y, rows[1].z, rows[1].w},
                               {rows[2].x, rows[2].y, rows[2].z, rows[2].w},
@@ -119,35 +117,70 @@ __device__ __forceinline__ void pyramid_regs(const FrameArgs& a, const FrameSrc&
         for (int k = 0; k < 2; ++k) l1[y][k] = mean2x2(r[2 * y][2 * k], r[2 * y][2 * k + 1], r[2 * y + 1][2 * k],
                                                        r[2 * y + 1][2 * k + 1]);
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-        store_px<8>(a.lvl[1] + f.lvl_off, a.pitch[1], a.w[1], a.h[1], (x0 >> 1) + 8 * seg, (y0 >> 1) + 2 * rb + y,
-                    l1[y][0], l1[y][1]);
-    if (a.O <= 2) return;
+    for (int y = 0; y < 2; ++y) st.template put<8>(1, (x0 >> 1) + 8 * seg, (y0 >> 1) + 2 * rb + y, l1[y][0], l1[y][1], true);
+    if (O <= 2) return;
     const uint32_t l2 = mean2x2(l1[0][0], l1[0][1], l1[1][0], l1[1][1]);
-    store_px<4>(a.lvl[2] + f.lvl_off, a.pitch[2], a.w[2], a.h[2], (x0 >> 2) + 4 * seg, (y0 >> 2) + rb, l2, 0u);
-    if (a.O <= 3) return;
+    st.template put<4>(2, (x0 >> 2) + 4 * seg, (y0 >> 2) + rb, l2, 0u, true);
+    if (O <= 3) return;
     // level 3: rows rb (even) and rb + 1, four pixels each -> two pixels
     const uint32_t l2d = (uint32_t)__shfl_down((int)l2, 8);
     const uint32_t l3 = mean2x2(l2, 0u, l2d, 0u) & 0xFFFFu;
-    if ((rb & 1) == 0)
-        store_px<2>(a.lvl[3] + f.lvl_off, a.pitch[3], a.w[3], a.h[3], (x0 >> 3) + 2 * seg, (y0 >> 3) + rb / 2, l3,
-                    0u);
-    if (a.O <= 4) return;
+    st.template put<2>(3, (x0 >> 3) + 2 * seg, (y0 >> 3) + rb / 2, l3, 0u, (rb & 1) == 0);
+    if (O <= 4) return;
     // level 4: level-3 rows rb/2 and rb/2 + 1 (threads rb and rb + 2) -> one pixel
     const uint32_t l3d = (uint32_t)__shfl_down((int)l3, 16);
     const uint32_t l4 = mean2x2(l3, 0u, l3d, 0u) & 0xFFu;
-    if ((rb & 3) == 0)
-        store_px<1>(a.lvl[4] + f.lvl_off, a.pitch[4], a.w[4], a.h[4], (x0 >> 4) + seg, (y0 >> 4) + rb / 4, l4, 0u);
-    if (a.O <= 5) return;
+    st.template put<1>(4, (x0 >> 4) + seg, (y0 >> 4) + rb / 4, l4, 0u, (rb & 3) == 0);
+    if (O <= 5) return;
     // level 5: level-4 pixels of (rb, seg), (rb, seg + 1), (rb + 4, seg), (rb + 4, seg + 1)
     const uint32_t l4r = (uint32_t)__shfl_down((int)l4, 1);
     const uint32_t l4d = (uint32_t)__shfl_down((int)l4, 32);
     const uint32_t l4dr = (uint32_t)__shfl_down((int)l4, 33);
     const uint32_t l5 = (l4 + l4r + l4d + l4dr + 2) >> 2;
-    if ((rb & 7) == 0 && (seg & 1) == 0)
-        store_px<1>(a.lvl[5] + f.lvl_off, a.pitch[5], a.w[5], a.h[5], (x0 >> 5) + seg / 2, (y0 >> 5) + rb / 8, l5,
-                    0u);
+    st.template put<1>(5, (x0 >> 5) + seg / 2, (y0 >> 5) + rb / 8, l5, 0u, (rb & 7) == 0 && (seg & 1) == 0);
 }
+
+// Octave stores of the tile pass: level o at a.lvl[o] + lvl_off, clipped to
+// the level's size.
+struct PxStore {
+    const FrameArgs& a;
+    size_t lvl_off;
+    template <int N>
+    __device__ __forceinline__ void put(int o, int gx, int gy, uint32_t lo, uint32_t hi, bool on) const
+    {
+        if (on) store_px<N>(a.lvl[o] + lvl_off, a.pitch[o], a.w[o], a.h[o], gx, gy, lo, hi);
+    }
+};
+
+// Raw buffer access (gfx9 resource word 3 for untyped dword data): loads
+// past num_records return zeros and stores past it are dropped, so edge
+// rows need no branches.
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+constexpr int kRawBufferWord3 = 0x00020000;
+constexpr int kNonTemporal = 2;   // cache-policy operand of buffer loads: nt
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRawBufferWord3);
+}
+
+// Octave stores through buffer resources of the levels' rows (pitch x h
+// bytes each): rows below a level, and threads without `on` (sent past the
+// range), are dropped by the range check; columns must lie inside the level.
+struct BufStore {
+    __amdgpu_buffer_rsrc_t r[KPD_MAX_OCTAVES];
+    int pitch[KPD_MAX_OCTAVES];
+    template <int N>
+    __device__ __forceinline__ void put(int o, int gx, int gy, uint32_t lo, uint32_t hi, bool on) const
+    {
+        const int off = on ? gy * pitch[o] + gx : 0x7FFFFFF0;
+        if constexpr (N == 8) __builtin_amdgcn_raw_buffer_store_b64(v2u{lo, hi}, r[o], off, 0, 0);
+        else if constexpr (N == 4) __builtin_amdgcn_raw_buffer_store_b32(lo, r[o], off, 0, 0);
+        else if constexpr (N == 2) __builtin_amdgcn_raw_buffer_store_b16((unsigned short)lo, r[o], off, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b8((unsigned char)lo, r[o], off, 0, 0);
+    }
+};
 
 template <int B>
 __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int by, uint8_t* sm)
@@ -199,7 +232,7 @@ __device__ void frame_tile_b(const FrameArgs& a, const FrameSrc& f, int bx, int 
                 if (f.sad_on) pv[u] = load(f.prev + (size_t)gy * f.prev_pitch, f.prev_aligned);
             }
         }
-        if (a.O <= kRegOctaves) pyramid_regs(a, f, v, x0, y0, rb, seg);
+        if (a.O <= kRegOctaves) pyramid_regs(PxStore{a, f.lvl_off}, a.O, v, x0, y0, rb, seg);
     } else {
         auto load = [&](const uint8_t* src, bool al) -> uint32_t {
             if (al) return *reinterpret_cast<const uint32_t*>(src);
@@ -1167,54 +1200,6 @@ __device__ __forceinline__ bool chunk_all_marked(const ChunkHead& h, int j)
     return h.all_marked || (j == 0 && h.force0);
 }
 
-// Cell c of frame j of a chunk whose parameters mark every cell: its mark
-// bit, and its keypoints at the cell's fixed base in frame j's sparse list.
-template <int NT>
-__device__ void detect_cell_chunk(const ChunkArgs& t, const ChunkHead& h, int c, uint8_t* sm)
-{
-    __shared__ CellLayout L;
-    __shared__ uint32_t s_n;
-    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
-    __shared__ int s_pitch[KPD_MAX_OCTAVES];
-    const DetectArgs& a = t.d;
-    const int tid = threadIdx.x;
-    const int j = t.j;
-    if (tid == 0) {
-        load_level_ptrs(a, s_lvl, s_pitch);
-        s_lvl[0] = h.frames + (size_t)j * h.stride;
-        s_pitch[0] = h.pitch;
-        // frames of one cell share a mark word: each sets its own bit
-        atomicOr(&t.marks[(size_t)c * t.Kw + (j >> 6)], 1ull << (j & 63));
-        if (j == h.n_frames - 1) a.mask[c] = 1;
-    }
-    __syncthreads();
-    detect_marked<NT>(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
-    __syncthreads();
-    if (tid == 0) t.own_count[c] = s_n;
-    emit_marked<NT>(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
-}
-
-// Detection of marked cell c of chunk frame j (mark known, no count word).
-template <int NT>
-__device__ void detect_item(const ChunkArgs& t, const ChunkHead& h, int c, uint8_t* sm)
-{
-    __shared__ CellLayout L;
-    __shared__ uint32_t s_n;
-    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
-    __shared__ int s_pitch[KPD_MAX_OCTAVES];
-    const DetectArgs& a = t.d;
-    if (threadIdx.x == 0) {
-        load_level_ptrs(a, s_lvl, s_pitch);
-        s_lvl[0] = h.frames + (size_t)t.j * h.stride;
-        s_pitch[0] = h.pitch;
-    }
-    __syncthreads();
-    detect_marked<NT>(a, h.t, h.aligned, c, sm, L, s_lvl, s_pitch, &s_n);
-    if (threadIdx.x == 0) t.own_count[c] = s_n;
-    emit_marked<NT>(a, L, sm, t.cell_base[c], a.list_cur, a.list_cap);
-    __syncthreads();   // L and the LDS maps are reused by the next item
-}
-
 // ----------------------------------------------------------------- kernels
 
 // ------------------------------------------------------------ k_describe
@@ -1445,14 +1430,209 @@ __global__ __launch_bounds__(kFrameBlock) void k_frame_chunk(FrameArgs a, ChunkH
     frame_tile(a, f, local % a.tiles_x, local / a.tiles_x, sm);
 }
 
-// Detection pass of a chunk: workgroup b is cell b % ncell of frame
-// b / ncell (frames in order, cells in order).
-template <int NT>
-__global__ __launch_bounds__(NT) void k_detect_chunk(const ChunkArgs* table, ChunkHead h)
+// Tile pass of a chunk whose frames test intensity differences, frames in
+// sequence: workgroup (tile, run) walks frames j0 .. j0 + nf - 1 of its
+// level-0 tile (TW x TH: 256 x 64, or 128 x 128) in order. Each frame's
+// rows are loaded once (two frames ahead of the one being summed) and serve
+// as I_n of their frame and I_{n-1} of the next, so a frame is read once
+// instead of twice. Per frame: |I_n - I_{n-1}| summed per cell into an LDS
+// slot row of that frame (one global atomic per slot when the run ends) and
+// the octaves written from registers.
+//
+// Thread (rb, seg) holds rows 4rb..4rb+3 and columns 16seg..16seg+15 of
+// the tile (SEGS = TW / 16 segments a row block, 64 / SEGS row blocks a
+// wave): its level-1 block (2 x 8) and level-2 block (1 x 4) are its own,
+// level 3 pairs it with the thread one row block down (SEGS lanes on),
+// level 4 with the one two row blocks down, and (128-px tiles) level 5 with
+// the thread 32 lanes on and the next segment, so 256-px tiles build
+// octaves to level 4 (O <= 5), 128-px tiles to level 5. A level-1 tile row
+// of a 256-px tile is one 128-byte line of the level (pitches are multiples
+// of 128), which the L2 writes back whole.
+//
+// The host launches it only when the frame width is a multiple of 16 (a
+// segment lies inside the frame or past it), the chunk's frames (and the
+// frame before it) have 16-byte aligned rows, and every segment inside the
+// frame lies in at most two cell columns (its first dword's and its last
+// dword's, each dword in one of them) and every row block in at most two
+// cell rows (its first row's and its last row inside the frame's). Loads
+// and octave stores go through buffer resources (a frame, a level) whose
+// range checks zero the rows below the frame and the segments past it
+// (sent past the range), and drop the octave rows below a level and the
+// stores of threads that hold no output: the loop takes no branches around
+// memory accesses, so the compiler keeps two frames' loads in flight.
+template <int SEGS>
+__device__ __forceinline__ void pyramid_regs_buf(const BufStore& st, const uint4* rows, int x0, int y0, int rb,
+                                                 int seg, bool col_in)
 {
+    const uint32_t r[4][4] = {{rows[0].x, rows[0].y, rows[0].z, rows[0].w},
+                              {rows[1].x, rows[1].y, rows[1].z, rows[1].w},
+                              {rows[2].x, rows[2].y, rows[2].z, rows[2].w},
+                              {rows[3].x, rows[3].y, rows[3].z, rows[3].w}};
+    uint32_t l1[2][2];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) l1[y][k] = mean2x2(r[2 * y][2 * k], r[2 * y][2 * k + 1], r[2 * y + 1][2 * k],
+                                                       r[2 * y + 1][2 * k + 1]);
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+        st.put<8>(1, (x0 >> 1) + 8 * seg, (y0 >> 1) + 2 * rb + y, l1[y][0], l1[y][1], col_in);
+    const uint32_t l2 = mean2x2(l1[0][0], l1[0][1], l1[1][0], l1[1][1]);
+    st.put<4>(2, (x0 >> 2) + 4 * seg, (y0 >> 2) + rb, l2, 0u, col_in);
+    // level 3: rows rb (even) and rb + 1 (SEGS lanes on), four pixels each -> two
+    const uint32_t l2d = (uint32_t)__shfl_down((int)l2, SEGS);
+    const uint32_t l3 = mean2x2(l2, 0u, l2d, 0u) & 0xFFFFu;
+    st.put<2>(3, (x0 >> 3) + 2 * seg, (y0 >> 3) + rb / 2, l3, 0u, col_in && (rb & 1) == 0);
+    // level 4: level-3 rows of threads rb and rb + 2 -> one pixel
+    const uint32_t l3d = (uint32_t)__shfl_down((int)l3, 2 * SEGS);
+    const uint32_t l4 = mean2x2(l3, 0u, l3d, 0u) & 0xFFu;
+    st.put<1>(4, (x0 >> 4) + seg, (y0 >> 4) + rb / 4, l4, 0u, col_in && (rb & 3) == 0);
+    if constexpr (SEGS == 8) {
+        // level 5: level-4 pixels of (rb, seg), (rb, seg + 1), (rb + 4, seg), (rb + 4, seg + 1)
+        const uint32_t l4r = (uint32_t)__shfl_down((int)l4, 1);
+        const uint32_t l4d = (uint32_t)__shfl_down((int)l4, 32);
+        const uint32_t l4dr = (uint32_t)__shfl_down((int)l4, 33);
+        const uint32_t l5 = (l4 + l4r + l4d + l4dr + 2) >> 2;
+        st.put<1>(5, (x0 >> 5) + seg / 2, (y0 >> 5) + rb / 8, l5, 0u, col_in && (rb & 7) == 0 && (seg & 1) == 0);
+    }
+}
+
+// NT: the frames are read non-temporally (a chunk larger than the last
+// level cache streams through it; marking the reads evict-first keeps the
+// L2 lines of the octave rows that neighbouring tiles complete).
+template <int TW, bool NT>
+__global__ __launch_bounds__(kFrameBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_frame_chunk_seq(
+    FrameArgs a, ChunkHead h, size_t pyr_stride, SeqGrid g)
+{
+    constexpr int SEGS = TW / 16;                       // 16-column segments a row block
+    constexpr int TH = 4 * (kFrameBlock / SEGS);        // tile rows
+    constexpr int LEVELS = SEGS == 8 ? 6 : 5;           // levels the register pyramid builds
     extern __shared__ __align__(16) uint8_t sm[];
-    const int j = blockIdx.x / h.ncell;
-    detect_cell_chunk<NT>(table[j], h, (int)blockIdx.x - j * h.ncell, sm);
+    const int run = g.run;
+    const int nruns = (h.n_frames + run - 1) / run;
+    const int total = nruns * g.ntiles;
+    const int b = xcd_band_tile(blockIdx.x, total);
+    if (b >= total) return;
+    const int ri = b / g.ntiles, local = b - ri * g.ntiles;
+    const int j0 = ri * run, nf = min(run, h.n_frames - j0);
+    const int bx = local % g.tiles_x, by = local / g.tiles_x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int seg = lane % SEGS, rb = (tid >> 6) * (64 / SEGS) + lane / SEGS;
+    const int x0 = bx * TW, y0 = by * TH, gxs = x0 + 16 * seg;
+    const bool col_in = gxs < a.W;
+    auto sad_of = [&](int j) { return !chunk_all_marked(h, j) && h.id_thresh < 255; };
+
+    // the tile's cells and the thread's share of them (LDS: a slot row of
+    // g.slots per frame of the run, then the column and row tables)
+    const int rows4 = (run + 3) / 4 * 4;
+    uint32_t* sadl = reinterpret_cast<uint32_t*>(sm);
+    uint16_t* colcell = reinterpret_cast<uint16_t*>(sm + 4 * g.slots * rows4);
+    uint16_t* rowcell = colcell + TW;
+    const int xe = min(x0 + TW, a.W), ye = min(y0 + TH, a.H);
+    const int cx0 = a.colmap[x0], cy0 = a.rowmap[y0];
+    const int ncx = a.colmap[xe - 1] - cx0 + 1, ncy = a.rowmap[ye - 1] - cy0 + 1;
+    for (int i = tid; i < g.slots * nf; i += kFrameBlock) sadl[i] = 0;
+    for (int i = tid; i < TW; i += kFrameBlock) colcell[i] = (uint16_t)(x0 + i < a.W ? a.colmap[x0 + i] - cx0 : 0);
+    for (int i = tid; i < TH; i += kFrameBlock) rowcell[i] = (uint16_t)(y0 + i < a.H ? a.rowmap[y0 + i] - cy0 : 0);
+    __syncthreads();
+    // segments past the frame and rows below it load zeros in both frames
+    // and add nothing, wherever their sums go
+    const int c0 = colcell[16 * seg], c3 = colcell[16 * seg + 12];
+    bool left[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) left[d] = colcell[16 * seg + 4 * d] == c0;
+    const int r0 = rowcell[4 * rb], r3 = rowcell[max(4 * rb, min(4 * rb + 3, a.H - 1 - y0))];
+    bool top[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) top[u] = rowcell[4 * rb + u] == r0;
+    const int t0 = r0 * ncx, t1 = r3 * ncx;
+
+    const uint8_t* f0 = h.frames + (size_t)j0 * h.stride;
+    // row offsets inside a frame (the same for every frame of the chunk);
+    // a frame is a buffer of pitch x H bytes
+    int roff[4], poff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int gy = y0 + 4 * rb + u;
+        roff[u] = col_in ? gy * h.pitch + gxs : (int)0x80000000u;
+        poff[u] = col_in ? gy * h.prev0_pitch + gxs : (int)0x80000000u;
+    }
+    auto load4 = [&](uint4* v, const uint8_t* base, int pitch, const int* off) {
+        const __amdgpu_buffer_rsrc_t rs = raw_rsrc(base, (uint32_t)pitch * (uint32_t)a.H);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const v4u w = __builtin_amdgcn_raw_buffer_load_b128(rs, off[u], 0, NT ? kNonTemporal : 0);
+            v[u] = make_uint4(w.x, w.y, w.z, w.w);
+        }
+    };
+    // frame j0 + k's rows live in set S[k mod 4] (frame j0 - 1's in S[3]);
+    // step k loads frame k + 2 while it sums frame k against frame k - 1.
+    // Steps run in groups of four past the run's end (to a multiple of
+    // four): there the loads re-read the run's last frame, the sums are
+    // skipped and the octave stores go to empty buffers, so no step
+    // branches around a memory access.
+    uint4 S0[4], S1[4], S2[4], S3[4];
+    auto step = [&](int k, const uint4* pv, const uint4* cv, uint4* dst) {
+        const bool live = k < nf;
+        const int j = j0 + min(k, nf - 1);
+        load4(dst, f0 + (size_t)min(k + 2, nf - 1) * h.stride, h.pitch, roff);
+        if (live && sad_of(j)) {
+            uint32_t s00 = 0, s01 = 0, s10 = 0, s11 = 0;   // (first/last row cell, first/last column cell)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t cw[4] = {cv[u].x, cv[u].y, cv[u].z, cv[u].w};
+                const uint32_t pw[4] = {pv[u].x, pv[u].y, pv[u].z, pv[u].w};
+                uint32_t sa = 0, sb = 0;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const uint32_t sd = __builtin_amdgcn_sad_u8(cw[d], pw[d], 0u);
+                    sa += left[d] ? sd : 0u;
+                    sb += left[d] ? 0u : sd;
+                }
+                s00 += top[u] ? sa : 0u;
+                s01 += top[u] ? sb : 0u;
+                s10 += top[u] ? 0u : sa;
+                s11 += top[u] ? 0u : sb;
+            }
+            uint32_t* sl = sadl + k * g.slots;
+            if (s00) atomicAdd(&sl[t0 + c0], s00);
+            if (s01) atomicAdd(&sl[t0 + c3], s01);
+            if (s10) atomicAdd(&sl[t1 + c0], s10);
+            if (s11) atomicAdd(&sl[t1 + c3], s11);
+        }
+        // octaves 1..O-1 of frame j; levels from O on (and dead steps) get
+        // empty buffers, so the register pyramid runs to its full depth
+        BufStore st;
+#pragma unroll
+        for (int o = 0; o < LEVELS; ++o) {
+            const bool on = live && o < a.O;
+            st.r[o] = raw_rsrc(on ? a.lvl[o] + pyr_stride * (size_t)j : nullptr,
+                               on ? (uint32_t)a.pitch[o] * (uint32_t)a.h[o] : 0u);
+            st.pitch[o] = on ? a.pitch[o] : 0;
+        }
+        pyramid_regs_buf<SEGS>(st, cv, x0, y0, rb, seg, col_in);
+    };
+#pragma unroll
+    for (int u = 0; u < 4; ++u) S3[u] = make_uint4(0u, 0u, 0u, 0u);
+    if (sad_of(j0)) {
+        if (j0 == 0) load4(S3, h.prev0, h.prev0_pitch, poff);
+        else load4(S3, f0 - h.stride, h.pitch, roff);
+    }
+    load4(S0, f0, h.pitch, roff);
+    load4(S1, f0 + (size_t)min(1, nf - 1) * h.stride, h.pitch, roff);
+    for (int k = 0; k < nf; k += 4) {
+        step(k, S3, S0, S2);
+        step(k + 1, S0, S1, S3);
+        step(k + 2, S1, S2, S0);
+        step(k + 3, S2, S3, S1);
+    }
+    __syncthreads();
+    const int per = ncx * ncy;
+    for (int i = tid; i < per * nf; i += kFrameBlock) {
+        const int k = i / per, l = i - k * per;
+        const uint32_t v = sadl[k * g.slots + l];
+        if (v) atomicAdd(&a.sad[(size_t)(j0 + k) * (a.nc * a.nr) + (cy0 + l / ncx) * a.nc + cx0 + l % ncx], v);
+    }
 }
 
 // Mark pass of a chunk whose marks need no counts: one wave per cell and 64
@@ -1606,21 +1786,6 @@ __global__ __launch_bounds__(kWaveCells * 64) void k_resolve_chunk(ChunkHead h, 
         if (lane == 0) h.marks[(size_t)c * h.Kw + w] = M;
     }
     if (lane == 0) h.mask[c] = (uint8_t)m;
-}
-
-// Detection pass over the work list: workgroup b takes items b, b + grid, ...
-template <int NT>
-__global__ __launch_bounds__(NT) void k_detect_list(const ChunkArgs* table, ChunkHead h, int round)
-{
-    extern __shared__ __align__(16) uint8_t sm[];
-    // round 0: items [0, count 0); round 1: [count 0, count 0 + count 1)
-    const uint32_t b = round ? h.work_count[0] : 0u;
-    const uint32_t n = b + h.work_count[round];
-    for (uint32_t it = b + blockIdx.x; it < n; it += gridDim.x) {
-        const uint32_t item = h.work[it];
-        const int j = (int)(item / (uint32_t)h.ncell);
-        detect_item<NT>(table[j], h, (int)(item - (uint32_t)j * h.ncell), sm);
-    }
 }
 
 // Compaction of a chunk, one workgroup per frame j, cells in tiles of
@@ -1796,30 +1961,6 @@ __global__ __launch_bounds__(kMarkBlock) void k_mark_batch(const TickArgs* table
     }
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_detect_list_batch(const TickArgs* table, const uint16_t* map,
-                                                            const uint32_t* work, const uint32_t* work_count)
-{
-    extern __shared__ __align__(16) uint8_t sm[];
-    __shared__ CellLayout L;
-    __shared__ uint32_t s_n;
-    __shared__ const uint8_t* s_lvl[KPD_MAX_OCTAVES];
-    __shared__ int s_pitch[KPD_MAX_OCTAVES];
-    const uint32_t n = *work_count;
-    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
-        const int g = (int)work[it];
-        const TickArgs& t = table[map[g]];
-        const DetectArgs& a = t.d;
-        const int c = g - t.cell_base;
-        if (threadIdx.x == 0) load_level_ptrs(a, s_lvl, s_pitch);
-        __syncthreads();
-        detect_marked<NT>(a, a.t, a.lvl0_aligned, c, sm, L, s_lvl, s_pitch, &s_n);
-        if (threadIdx.x == 0) t.own_count[c] = s_n;
-        emit_marked<NT>(a, L, sm, t.sparse_base[c], t.sparse, a.list_cap);
-        __syncthreads();   // L and the LDS maps are reused by the next item
-    }
-}
-
 // D_n of one frame of one stream after k_det1_groups (Eq. 1): marked cells
 // take their new keypoints from the sparse list, the others D_{n-1}'s. A
 // workgroup per run of kCells1 cells: it sums the counts of every earlier
@@ -1954,10 +2095,6 @@ hipError_t set_detect_lds_limit(int lds_bytes)
     if (lds_bytes <= cur) return hipSuccess;
     const void* kernels[] = {
         reinterpret_cast<const void*>(k_detect1<kDetLatency>),
-        reinterpret_cast<const void*>(k_detect_list<kDetLatency>),
-        reinterpret_cast<const void*>(k_detect_list<kDetThroughput>),
-        reinterpret_cast<const void*>(k_detect_list_batch<kDetThroughput>),
-        reinterpret_cast<const void*>(k_detect_chunk<kDetThroughput>),
     };
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
@@ -1993,10 +2130,34 @@ hipError_t launch_frame_chunk(const FrameArgs& a, size_t pyr_stride, const Chunk
     return hipGetLastError();
 }
 
-hipError_t launch_detect_chunk(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s)
+int frame_seq_lds_bytes(int slots, int run) { return 4 * slots * ((run + 3) / 4 * 4) + 2 * (256 + 128); }
+
+hipError_t frame_seq_capacity(int lds_bytes, int* blocks)
 {
-    hipLaunchKernelGGL(k_detect_chunk<kDetThroughput>, dim3(h.n_frames * h.ncell), dim3(kDetThroughput),
-                       detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, h);
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_frame_chunk_seq<256, false>),
+                                                         kFrameBlock, (size_t)lds_bytes);
+    *blocks = per * cus;
+    return e;
+}
+
+hipError_t launch_frame_chunk_seq(const FrameArgs& a, size_t pyr_stride, const ChunkHead& h, const SeqGrid& g,
+                                  bool nt, hipStream_t s)
+{
+    const int total = (h.n_frames + g.run - 1) / g.run * g.ntiles;
+    const int grid = (total + kXcds - 1) / kXcds * kXcds;
+    const int lds = frame_seq_lds_bytes(g.slots, g.run);
+    if (g.tile_w == 256 && nt)
+        hipLaunchKernelGGL((k_frame_chunk_seq<256, true>), dim3(grid), dim3(kFrameBlock), lds, s, a, h, pyr_stride, g);
+    else if (g.tile_w == 256)
+        hipLaunchKernelGGL((k_frame_chunk_seq<256, false>), dim3(grid), dim3(kFrameBlock), lds, s, a, h, pyr_stride, g);
+    else if (nt)
+        hipLaunchKernelGGL((k_frame_chunk_seq<128, true>), dim3(grid), dim3(kFrameBlock), lds, s, a, h, pyr_stride, g);
+    else
+        hipLaunchKernelGGL((k_frame_chunk_seq<128, false>), dim3(grid), dim3(kFrameBlock), lds, s, a, h, pyr_stride, g);
     return hipGetLastError();
 }
 
@@ -2024,18 +2185,6 @@ hipError_t launch_mark_chunk(const ChunkHead& h, hipStream_t s)
 {
     const int n = (h.n_frames + 63) / 64 * 64 * h.ncell;   // a wave per cell and 64 frames
     hipLaunchKernelGGL(k_mark_chunk, dim3((n + kMarkBlock - 1) / kMarkBlock), dim3(kMarkBlock), 0, s, h);
-    return hipGetLastError();
-}
-
-hipError_t launch_detect_list(const ChunkArgs* table, const ChunkHead& h, int lds_bytes, hipStream_t s, int round)
-{
-    const int items = h.n_frames * h.ncell;
-    const int grid = items < 1024 ? items : 1024;
-    if (items <= kListLatencyItems)
-        hipLaunchKernelGGL(k_detect_list<kDetLatency>, dim3(grid), dim3(kDetLatency), lds_bytes, s, table, h, round);
-    else
-        hipLaunchKernelGGL(k_detect_list<kDetThroughput>, dim3(grid), dim3(kDetThroughput),
-                           detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, h, round);
     return hipGetLastError();
 }
 
@@ -2169,15 +2318,6 @@ hipError_t launch_mark_batch(const TickArgs* table, const uint16_t* map, int nce
 {
     hipLaunchKernelGGL(k_mark_batch, dim3((ncells + kMarkBlock - 1) / kMarkBlock), dim3(kMarkBlock), 0, s, table, map,
                        ncells, work, work_count);
-    return hipGetLastError();
-}
-
-hipError_t launch_detect_list_batch(const TickArgs* table, const uint16_t* map, int ncells, const uint32_t* work,
-                                    const uint32_t* work_count, int lds_bytes, hipStream_t s)
-{
-    const int grid = ncells < 1024 ? ncells : 1024;
-    hipLaunchKernelGGL(k_detect_list_batch<kDetThroughput>, dim3(grid), dim3(kDetThroughput),
-                       detect_lds_for(lds_bytes, kDetThroughput / 64), s, table, map, work, work_count);
     return hipGetLastError();
 }
 

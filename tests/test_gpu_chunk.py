@@ -138,6 +138,25 @@ def test_pyramid_after_chunk_is_last_frame(kpd):
     g.close()
 
 
+@pytest.mark.parametrize("W,H,O,Nc,Nr,plan", [(1280, 720, 5, 32, 18, [23, 9, 0, 17]),
+                                                 (640, 480, 6, 16, 12, [23, 6, 13]),
+                                                 (1920, 1080, 5, 32, 18, [13, 1, 9])])
+def test_sequential_tile_pass_shapes(kpd, W, H, O, Nc, Nr, plan):
+    # chunks whose tile pass walks frames in order (256 x 64 tiles at O <= 5,
+    # 128 x 128 at O = 6; runs of ragged length; a partial last tile column
+    # at 1920): every frame's keypoints and mask, then the last frame's pyramid
+    import torch
+    sc = synth.Scene(W, H, 45, 30, 12, max(40, H // 6), 0.75, 2.0, True, 700 + W + O)
+    frames = synth.make_video(sc)
+    run_chunks(kpd, frames, (20, O, Nc, Nr, 8, KB_OFF), plan, K=32)
+    g = kpd.Stream(W, H, kpd.make_params(20, O, Nc, Nr, 8, KB_OFF, 0, 32))
+    g.push_chunk(torch.from_numpy(frames[:21]).cuda())
+    ref = oracle.pyramid(frames[20], O)
+    for o in range(1, O):
+        np.testing.assert_array_equal(g.level(o), ref[o], err_msg=f"level {o}")
+    g.close()
+
+
 def test_chunk_errors(kpd):
     import torch
     frames = torch.from_numpy(synth.make_video(synth.SCENES["c1_320x240"], 4)).cuda()

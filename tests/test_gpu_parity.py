@@ -29,15 +29,19 @@ def orc_tuples(arr):
     return [(int(k["x"]), int(k["y"]), int(k["octave"]), int(k["score"])) for k in arr]
 
 
-def run_pair(kpd, frames, det, mode="host", thresholds=None, check_sad=True, tile=0):
+def run_pair(kpd, frames, det, mode="host", thresholds=None, check_sad=True, tile=0, lazy=False):
     """Push frames through a GPU stream and an oracle stream, compare every
-    frame. thresholds: {frame_index: (t, TI, TH)} applied before that frame."""
+    frame. thresholds: {frame_index: (t, TI, TH)} applied before that frame.
+    lazy: the oracle in its CPU-masked mode (the same results, pinned against
+    the definitional mode; scores only what the marked cells read)."""
     import torch
     F, H, W = frames.shape
     t, O, Nc, Nr, TI, TH = det
     params = kpd.make_params(t, O, Nc, Nr, TI, TH, tile)
     g = kpd.Stream(W, H, params)
     o = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    if lazy:
+        o.set_lazy(True)
     dev = torch.from_numpy(frames).cuda() if mode != "host" else None
     forced = True
     cur = (t, TI, TH)
@@ -93,9 +97,11 @@ def test_c2_640x480_all_300_frames(kpd):
     run_pair(kpd, frames, det_of("c2_640x480"), mode="retain")
 
 
-def test_c3_1920x1080_first_40_frames(kpd):
-    frames = scene_frames("c3_1920x1080", 40)
-    run_pair(kpd, frames, det_of("c3_1920x1080"), mode="device")
+def test_c3_1920x1080_all_300_frames(kpd):
+    # the whole streaming video, one push_frame per frame
+    frames = scene_frames("c3_1920x1080", 300)
+    totals = run_pair(kpd, frames, det_of("c3_1920x1080"), mode="device", lazy=True)
+    assert len(totals) == 300 and min(totals) > 0
 
 
 def test_c3_full_frame_mode(kpd):
