@@ -554,9 +554,15 @@ def roofline_of(wl: Workload, res, masked: bool, traffic=None, stats=None):
     achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
     if traffic is None:
         traffic = traffic_for(wl.name, masked, res.get("chunk", 0), dom, res.get("layer"))
+    measured = None
+    if traffic:
+        # the counters' bytes over the same launch time: what the kernel moved
+        mt = traffic / avg_s / 1e9 if avg_s > 0 else 0.0
+        measured = {"GBs": round(mt, 2), "frac": round(mt / HBM_PEAK_GBS, 5),
+                    "over_algorithmic": round(traffic / per_launch, 3) if per_launch else None}
     return {
         "kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "traffic_rate": measured,
         "algorithmic_bytes_per_launch": int(per_launch), "avg_launch_us": round(avg_s * 1e6, 3),
         "launches": n,
         "per_kernel_avg_us": {k: round(v[0] * 1e3 / max(v[1], 1), 3) for k, v in kern.items()},
@@ -806,12 +812,13 @@ PROFILE_CASES = {
 PMC_COUNTERS = ("FETCH_SIZE", "WRITE_SIZE")
 # counter sets of the VALU study, one rocprofv3 run each
 VALU_SETS = (("VALUBusy",), ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY",
-                             "GRBM_GUI_ACTIVE"))
+                             "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "GRBM_GUI_ACTIVE"))
 # kernel -> (push path, the timed kernel id its launches count under)
 KERNEL_IDS = {"k_frame1": ("frame", "k_frame"), "k_detect1": ("frame", "k_detect"),
               "k_det1_groups": ("frame", "k_detect"), "k_compact1": ("frame", "k_compact"),
-              "k_frame_chunk": ("chunk", "k_frame"), "k_detect_chunk": ("chunk", "k_detect"),
-              "k_detect_chunk_groups": ("chunk", "k_detect"),
+              "k_frame_chunk": ("chunk", "k_frame"), "k_frame_chunk_seq": ("chunk", "k_frame"),
+              "k_detect_chunk": ("chunk", "k_detect"), "k_detect_chunk_groups": ("chunk", "k_detect"),
+              "k_detect_list_groups": ("chunk", "k_detect"),
               "k_detect_list": ("chunk", "k_detect"), "k_mark_chunk": ("chunk", "k_mark"),
               "k_compact_chunk": ("chunk", "k_compact")}
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
@@ -937,7 +944,7 @@ def summarize_profiles(out: str) -> None:
     for c in VALU_SETS:
         lines.append("  " + profile_command(case, "$OUT", " ".join(c)))
     lines += ["", f"{'kernel':22s} {'dispatches':>10s} {'VALUBusy%':>10s} {'VALU insts':>14s} {'waves':>10s} "
-                  f"{'wait/wave cyc':>13s} {'lane-ops/px-oct':>16s}"]
+                  f"{'wait/wave cyc':>13s} {'lane-ops/px-oct':>16s} {'LDS insts':>12s} {'LDS conflict cyc':>17s}"]
     for k in ("k_frame_chunk", "k_detect_chunk_groups", "k_compact_chunk"):
         if k not in busy or k not in cnt["SQ_INSTS_VALU"]:
             continue
@@ -945,9 +952,13 @@ def summarize_profiles(out: str) -> None:
         waves = cnt["SQ_WAVES"][k][0]
         wait = cnt["SQ_WAIT_ANY"][k][0] / max(cnt["SQ_WAVE_CYCLES"][k][0], 1)
         per = insts * 64 / px_oct if k == "k_detect_chunk_groups" else float("nan")
-        lines.append(f"{k:22s} {n:10d} {busy[k][0]:10.1f} {insts:14.0f} {waves:10.0f} {wait:13.3f} {per:16.1f}")
+        lds = cnt["SQ_INSTS_LDS"].get(k, (float("nan"), 0))[0]
+        conf = cnt["SQ_LDS_BANK_CONFLICT"].get(k, (float("nan"), 0))[0]
+        lines.append(f"{k:22s} {n:10d} {busy[k][0]:10.1f} {insts:14.0f} {waves:10.0f} {wait:13.3f} {per:16.1f} "
+                     f"{lds:12.0f} {conf:17.0f}")
     lines += ["", "lane-ops/px-oct: VALU instructions x 64 lanes per pixel-octave of the launch "
-                  f"({px_oct} = 300 frames x {sum(lv)})"]
+                  f"({px_oct} = 300 frames x {sum(lv)}); wait/wave cyc: SQ_WAIT_ANY over SQ_WAVE_CYCLES; "
+                  "LDS conflict cyc: SQ_LDS_BANK_CONFLICT (cycles stalled on LDS bank conflicts)"]
     open(os.path.join(pdir, "valu_c3_1920x1080_full_chunked.txt"), "w").write("\n".join(lines) + "\n")
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump(traffic, fh, indent=1, sort_keys=True)

@@ -73,10 +73,11 @@ extern "C" {
  *   kb_thresh  T_H: a cell is marked when D_{n-1} has >= T_H keypoints in it
  *              (Eq. 4). 0: every cell is marked; KPD_KB_OFF: never fires.
  *   tile       side of the level-0 tiles of the pyramid/difference pass of
- *              single-frame pushes, a tuning knob that never changes
- *              results: 0 picks the default, otherwise a power of two in
- *              32..128 and >= 2^(O-1). Chunks (push_frames) use the widest
- *              tile up to 128 whose workgroup fits in LDS.
+ *              single-frame pushes and batch ticks, a tuning knob that
+ *              never changes results: 0 picks the default (the widest of
+ *              128, 64, 32 that gives the frame at least 128 tiles, at
+ *              least 2^(O-1)), otherwise a power of two in 32..128 and
+ *              >= 2^(O-1). Chunks (push_frames) use their own tiles.
  *   chunk_frames
  *              most frames one push_frames call may take (0 or 1: the
  *              stream takes single frames only; at most KPD_MAX_CHUNK). It

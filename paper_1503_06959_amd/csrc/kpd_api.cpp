@@ -89,7 +89,7 @@ struct Layout {
     // single frames: one-cell layouts of the same detector, and its LDS at
     // 256 and 512 threads
     size_t off_glay1 = 0;
-    int glds1_256 = 0, glds1_512 = 0;
+    int glds1_128 = 0, glds1_256 = 0, glds1_512 = 0;
     size_t total = 0;
 };
 
@@ -183,6 +183,17 @@ bool group_layouts(const Layout& L, int gx, int gy, int waves, std::vector<kpd::
 constexpr int kGroupWaves = 4;           // 256-thread workgroups for one-cell layouts
 constexpr int kGroupLdsDefault = 48 * 1024;   // default groups: three workgroups per CU
 
+// Threads of a workgroup of the listed-cell detection of chunks (128, 256
+// or 512; measured: 256 is the faster at 640x480, 128 by 4% at 1920x1080).
+constexpr int kListThreads = 256;
+
+// Dynamic LDS of a one-cell group workgroup of `threads` threads (its wave
+// queues scale with the waves).
+int glds1_for(const Layout& L, int threads)
+{
+    return threads == 128 ? L.glds1_128 : (threads == 512 ? L.glds1_512 : L.glds1_256);
+}
+
 // Whether the sequential tile pass takes this geometry: octaves to level 5
 // (O <= 6), the frame width a multiple of 16, every 16-column segment in at
 // most two cell columns, each dword in one, and every block of 4 rows (its
@@ -217,10 +228,6 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->pitch[o] = kpd::round_up(L->w[o], 128);
     }
     L->slot_pitch = kpd::round_up(W, 64);
-    L->tile = p->tile ? p->tile : std::max(32, 1 << (L->O - 1));
-    L->tiles_x = (W + L->tile - 1) / L->tile;
-    L->tiles_y = (H + L->tile - 1) / L->tile;
-
     // cells a k_frame tile can touch, per axis
     auto span_max = [](int len, int n, int T) {
         int m = 1;
@@ -230,6 +237,24 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         }
         return m;
     };
+    // Single frames: the widest tile that still gives at least 128
+    // workgroups (a frame's tile pass is short; wider tiles cost fewer
+    // workgroups per byte), at least 32 and 2^(O-1) pixels a side.
+    L->tile = p->tile;
+    if (!L->tile) {
+        const int tmin = std::max(32, 1 << (L->O - 1));
+        L->tile = tmin;
+        for (int T = 128; T > tmin; T >>= 1) {
+            const int nt = ((W + T - 1) / T) * ((H + T - 1) / T);
+            const int slots = span_max(W, L->nc, T) * span_max(H, L->nr, T);
+            if (nt >= 128 && kpd::frame_lds_bytes(T, L->O, slots) <= 65536) {
+                L->tile = T;
+                break;
+            }
+        }
+    }
+    L->tiles_x = (W + L->tile - 1) / L->tile;
+    L->tiles_y = (H + L->tile - 1) / L->tile;
     L->sad_slots = span_max(W, L->nc, L->tile) * span_max(H, L->nr, L->tile);
     if (kpd::frame_lds_bytes(L->tile, L->O, L->sad_slots) > 65536) {
         *why = "grid too fine for the pyramid tile";
@@ -330,7 +355,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->glds = lds;
         L->ngroups = ((L->nc + L->gx - 1) / L->gx) * ((L->nr + L->gy - 1) / L->gy);
     }
-    if (!group_layouts(*L, 1, 1, 4, nullptr, &L->glds1_256) || !group_layouts(*L, 1, 1, 8, nullptr, &L->glds1_512) ||
+    if (!group_layouts(*L, 1, 1, 2, nullptr, &L->glds1_128) || !group_layouts(*L, 1, 1, 4, nullptr, &L->glds1_256) ||
+        !group_layouts(*L, 1, 1, 8, nullptr, &L->glds1_512) ||
         L->glds1_512 > 160 * 1024) {
         *why = "cells too large for the detector";
         return false;
@@ -947,7 +973,7 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
         ga.nc = L.nc;
         ga.al8 = (reinterpret_cast<uintptr_t>(t.d.lvl[0]) % 8 == 0 && t.d.pitch[0] % 8 == 0) ? 1 : 0;
         const int threads = t.d.all_marked ? 256 : 512;
-        const int lds = threads == 512 ? L.glds1_512 : L.glds1_256;
+        const int lds = glds1_for(L, threads);
         KPD_HIP(timed(s, KPD_K_DETECT, [&] {
             return kpd::launch_det1_groups(t.d, ga, t.sparse, t.own_count, L.ncell, lds, threads, s->stream);
         }));
@@ -1129,7 +1155,8 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         g1.al8 = (reinterpret_cast<uintptr_t>(frames) % 8 == 0 && frame_stride % 8 == 0 && pitch % 8 == 0) ? 1 : 0;
         auto detect = [&](int round) {
             return timed(s, KPD_K_DETECT, [&] {
-                return kpd::launch_detect_list_groups(ctab, h, g1, L.glds1_256, 256, round, s->stream);
+                return kpd::launch_detect_list_groups(ctab, h, g1, glds1_for(L, kListThreads), kListThreads, round,
+                                                      s->stream);
             });
         };
         if (h.kb_chain) {

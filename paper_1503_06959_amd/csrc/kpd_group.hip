@@ -124,9 +124,12 @@ hipError_t launch_detect_list_groups(const ChunkArgs* table, const ChunkHead& h,
                                      int threads, int round, hipStream_t s)
 {
     const int items = h.n_frames * h.ncell;
-    const int grid = items < 2048 ? items : 2048;
+    const int cap = threads == 128 ? 4096 : 2048;
+    const int grid = items < cap ? items : cap;
     if (threads == 512)
         hipLaunchKernelGGL(k_detect_list_groups<512>, dim3(grid), dim3(512), lds_bytes, s, table, h, g, round);
+    else if (threads == 128)
+        hipLaunchKernelGGL(k_detect_list_groups<128>, dim3(grid), dim3(128), lds_bytes, s, table, h, g, round);
     else
         hipLaunchKernelGGL(k_detect_list_groups<256>, dim3(grid), dim3(256), lds_bytes, s, table, h, g, round);
     return hipGetLastError();
@@ -173,6 +176,7 @@ hipError_t set_group_lds_limit(int lds_bytes)
                              reinterpret_cast<const void*>(k_det1_groups<256>),
                              reinterpret_cast<const void*>(k_detect_list_groups<512>),
                              reinterpret_cast<const void*>(k_detect_list_groups<256>),
+                             reinterpret_cast<const void*>(k_detect_list_groups<128>),
                              reinterpret_cast<const void*>(k_detect_list_batch_groups<256>)};
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
