@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--serve-horizon", type=float, default=48.0)
     ap.add_argument("--serve-speedup", type=float, default=4.0)
     ap.add_argument("--serve-budget-mib", type=int, default=1024)
+    ap.add_argument("--saturation-seconds", type=float, default=4.0)
+    ap.add_argument("--saturation-budget-mib", type=int, default=4096)
     ap.add_argument("--batch-ticks", type=int, default=120)
     ap.add_argument("--batch-clip", type=int, default=40)
     ap.add_argument("--chunk", type=int, default=0,
@@ -788,6 +790,35 @@ def serving_workload(horizon: float, speedup: float, budget_mib: int) -> dict:
     return out
 
 
+def serving_saturation(duration: float, budget_mib: int) -> dict:
+    """Serving at saturation: 640 requests (200-2000 frames, resolutions
+    uniform over 320x240 .. 1920x1080) all waiting at the start, at most 256
+    concurrent streams under the HBM budget; every admitted stream has a
+    frame ready at every tick, and ended streams give their slot to waiting
+    ones. Batched ticks against plain per-stream pushes, `duration` wall
+    seconds each: throughput is the GPU's and the host loop's, not the
+    arrival rate's."""
+    import torch
+    from paper_1503_06959_amd import autotune, serve, synth
+    bank = serve.ClipBank(n_clips=2, clip_len=48, workers=min(16, os.cpu_count() or 1))
+    tiles = {res: autotune.best_tile(res[0], res[1], synth.RES_PRESETS[res][0])[0] for res in serve.RESOLUTIONS}
+    reqs = serve.poisson_requests(8.0, 80.0, 5001, clip_len=48)[:640]
+    out = {"workload": f"{len(reqs)} requests waiting at the start (200-2000 frames each, resolutions uniform over "
+                       f"{'/'.join(f'{w}x{h}' for w, h in serve.RESOLUTIONS)}), <= 256 concurrent, HBM budget "
+                       f"{budget_mib} MiB, every active stream has a frame ready at every tick, {duration:g}s per "
+                       "backend"}
+    for cls in (serve.BatchedBackend, serve.PlainBackend):
+        be = cls(max_streams=256, tiles=tiles)
+        srv = serve.Server(be, bank, reqs, budget_bytes=budget_mib << 20, max_streams=256, saturate=True)
+        st = srv.run(duration)
+        be.shutdown()
+        torch.cuda.synchronize()
+        out[be.name] = st.summary()
+        log(f"[bench] saturated serving {be.name}: {out[be.name]}")
+    out["batched_over_plain_mpix"] = round(out["batched"]["mpix_per_s"] / max(out["plain"]["mpix_per_s"], 1e-9), 3)
+    return out
+
+
 # rocprofv3 runs whose summaries live under profiles/: kernel traces of the
 # bench itself, and HBM byte counters (FETCH_SIZE, WRITE_SIZE, one counter
 # per run) of single-mode passes and of a plain copy that scales them.
@@ -1194,6 +1225,9 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] serving")
         out["serving"] = serving_workload(args.serve_horizon, args.serve_speedup, args.serve_budget_mib)
+        torch.cuda.empty_cache()
+        log("[bench] serving at saturation")
+        out["serving_saturated"] = serving_saturation(args.saturation_seconds, args.saturation_budget_mib)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         from paper_1503_06959_amd import synth

@@ -262,19 +262,29 @@ class Server:
     """Runs requests against a backend. Simulated time runs `speedup` times
     faster than the wall clock: frame k of a stream admitted at simulated
     time a arrives at a + k / fps. Latencies are wall-clock milliseconds from
-    a frame's arrival to its keypoints on the host."""
+    a frame's arrival to its keypoints on the host.
+
+    saturate: every request has arrived at the start and every admitted
+    stream has its next frame waiting at every tick (the GPU never waits for
+    a frame rate): each tick takes one frame of every active stream, streams
+    that end give their slot and budget to waiting ones, and the run lasts
+    `horizon` wall-clock seconds. A frame's latency runs from its tick's
+    start to its keypoints on the host."""
 
     def __init__(self, backend, bank, requests: List[Request], budget_bytes: int, max_streams: int = 256,
                  fps: float = 30.0, speedup: float = 1.0, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, record: Sequence[int] = ()):
+                 sleep: Callable[[float], None] = time.sleep, record: Sequence[int] = (), saturate: bool = False):
         self.backend, self.bank, self.requests = backend, bank, sorted(requests, key=lambda r: r.arrival)
         self.adm = Admission(budget_bytes, max_streams, backend.bytes_of)
         self.fps, self.speedup, self.clock, self.sleep = fps, speedup, clock, sleep
+        self.saturate = saturate
         self.record = set(record)
         self.recorded: Dict[int, List[np.ndarray]] = {sid: [] for sid in self.record}
         self.req_of: Dict[int, Request] = {r.sid: r for r in self.requests}
 
     def run(self, horizon: float) -> ServeStats:
+        if self.saturate:
+            return self._run_saturated(horizon)
         t0 = self.clock()
         sim = lambda: (self.clock() - t0) * self.speedup
         nxt = 0
@@ -325,6 +335,45 @@ class Server:
                     wake.append(self.requests[nxt].arrival)
                 gap = (min(wake) - now) / self.speedup if wake else 1e-3
                 self.sleep(min(max(gap, 0.0), 1e-3))
+        wall = self.clock() - t0
+        for sid in list(active):
+            self.backend.close(sid)
+            self.adm.release(sid)
+        return ServeStats(self.backend.name, wall, frames, pixels, lat, admitted, self.adm.deferred, max_active,
+                          ticks)
+
+    def _run_saturated(self, duration: float) -> ServeStats:
+        for req in self.requests:
+            self.adm.offer(req)
+        t0 = self.clock()
+        active: Dict[int, int] = {}      # sid -> next frame
+        lat, frames, pixels, ticks, admitted, max_active = [], 0, 0, 0, 0, 0
+        while self.clock() - t0 < duration:
+            for req in self.adm.admit():
+                self.backend.open(req)
+                active[req.sid] = 0
+                admitted += 1
+            if not active:
+                break
+            max_active = max(max_active, len(active))
+            start = self.clock()
+            for sid, k in active.items():
+                self.backend.push(sid, self.bank.frame(self.req_of[sid], k))
+            results = self.backend.run()
+            done = self.clock()
+            ticks += 1
+            for sid in active:
+                lat.append((done - start) * 1e3)
+                req = self.req_of[sid]
+                pixels += req.res[0] * req.res[1]
+                frames += 1
+                active[sid] += 1
+                if sid in self.record:
+                    self.recorded[sid].append(results[sid].copy())
+            for sid in [s for s, k in active.items() if k >= self.req_of[s].n_frames]:
+                self.backend.close(sid)
+                self.adm.release(sid)
+                del active[sid]
         wall = self.clock() - t0
         for sid in list(active):
             self.backend.close(sid)

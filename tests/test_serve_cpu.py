@@ -133,3 +133,30 @@ def test_server_speedup_scales_arrivals():
     assert st.frames == 30
     # 30 frames at 30 fps of simulated time take about 0.1 s of wall time at 10x
     assert 0.09 < clock.t < 0.25
+
+
+def test_server_saturated_keeps_every_slot_busy():
+    # every admitted stream gives a frame to every tick; ended streams hand
+    # their slot to waiting ones in arrival order
+    clock = FakeClock()
+    be = FakeBackend(clock, cost=0.001)
+    reqs = [req(i, 5.0 * i, 3 + i % 4) for i in range(12)]   # arrival times are ignored
+    srv = Server(be, FakeBank(), reqs, budget_bytes=10_000, max_streams=4, clock=clock, sleep=clock.sleep,
+                 saturate=True)
+    st = srv.run(horizon=1.0)
+    assert st.admitted == 12 and st.frames == sum(3 + i % 4 for i in range(12))
+    assert st.max_active == 4
+    assert all(len(t) == 4 for t in be.ticks[:2])            # full ticks while requests wait
+    for i in range(12):
+        assert sum(1 for t in be.ticks if i in t) == 3 + i % 4
+    assert sorted(be.closed) == list(range(12))
+    assert max(st.latencies_ms) <= 1.0 + 1e-9                  # one tick each
+
+
+def test_server_saturated_stops_at_its_duration():
+    clock = FakeClock()
+    be = FakeBackend(clock, cost=0.01)
+    reqs = [req(i, 0.0, 10_000) for i in range(3)]
+    st = Server(be, FakeBank(), reqs, budget_bytes=10_000, clock=clock, sleep=clock.sleep,
+                saturate=True).run(horizon=0.5)
+    assert 0.5 <= st.wall_s < 0.52 and st.frames == 3 * st.ticks
