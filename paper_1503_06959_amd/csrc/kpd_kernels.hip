@@ -1,42 +1,41 @@
-// gfx950 kernels of the masked multi-scale FAST detector. Two launches per
-// frame of one stream (k_frame1, k_detect1); four per batch tick over many
-// streams (k_frame_batch, k_mark_batch, k_detect_list_batch,
-// k_compact_batch); three or four per chunk of consecutive frames of one
-// stream (k_frame_chunk, then k_mark_chunk and k_detect_list, or
-// k_detect_chunk, then k_compact_chunk). All of them run the same bodies:
+// gfx950 kernels of the masked multi-scale FAST detector, beside the group
+// detector (kpd_group.h, kpd_group.hip). Three launches per frame of one
+// stream (k_frame1, then k_det1_groups and k_compact1; k_detect1 for the
+// per-pixel masks); four per batch tick over many streams (k_frame_batch,
+// k_mark_batch, k_detect_list_batch_groups, k_compact_batch) or one
+// persistent k_tick; three to six per chunk of consecutive frames of one
+// stream (k_frame_chunk_seq or k_frame_chunk, then k_mark_chunk and
+// k_detect_list_groups, the speculation passes, or k_detect_chunk_groups,
+// then k_compact_chunk). The bodies here:
 //
 //   frame_tile   one workgroup per level-0 tile, aligned to the coarsest
 //                octave: loads the tile of I_n (dwords, or 16-byte row
 //                segments for 128-px tiles), builds every coarser octave of
-//                it in LDS by 2x2 box average with round-half-up (Sec. 2,
-//                Sec. 3.1) and writes them out; when the intensity-difference
-//                mask is active it also sums |I_n - I_{n-1}| per cell
-//                (v_sad_u8 per dword, register and LDS partials, one atomic
-//                per tile and cell) for the per-cell mean-difference test
-//                (Sec. 3.1 Eq. 2, read per cell).
-//   detect_marked  one workgroup per marked cell: stages the pixel tiles of
-//                every octave in LDS, runs the compass pre-test on dword
-//                groups and the segment test and FAST score on the
-//                survivors over the cell's score boxes, keeps the
-//                scale-space maxima (Sec. 2) as a bitmask and ranks them
-//                with popcounts.
-//   detect_cell  (single frames, batch ticks) decides the cell's mark (Eq. 2
-//                from the SAD, Eqs. 3-4 from the cell's count in D_{n-1});
-//                the counts of earlier cells give the cell's offset in D_n,
-//                where it writes its new keypoints, or copies its D_{n-1}
-//                entries when unmarked (Eq. 1).
-//   chunks and batch ticks
-//                write each marked cell's keypoints at a fixed per-cell base
-//                of a sparse list; a compaction pass (compact_frame) applies
-//                Eq. 1 and builds each frame's D_n in cell order.
+//                it (from registers for 128-px tiles, else in LDS) by 2x2
+//                box average with round-half-up (Sec. 2, Sec. 3.1) and
+//                writes them out; when the intensity-difference mask is
+//                active it also sums |I_n - I_{n-1}| per cell (v_sad_u8 per
+//                dword, register and LDS partials, one atomic per tile and
+//                cell) for the per-cell mean-difference test (Sec. 3.1
+//                Eq. 2, read per cell).
+//   k_frame_chunk_seq  the tile pass of a chunk whose frames test
+//                differences, each workgroup walking a run of frames of its
+//                tile in order so that every frame is read once.
+//   detect_marked / detect_cell  the per-cell detector of the per-pixel
+//                mask modes: stages the cell's octave tiles in LDS, runs the
+//                compass pre-test and the segment test and FAST score, keeps
+//                the scale-space maxima (Sec. 2) as a bitmask; the counts of
+//                earlier cells give the cell's offset in D_n (Eq. 1).
+//   compact_frame  builds a frame's D_n in cell order from the marked
+//                cells' sparse lists and D_{n-1} (Eq. 1).
 //
 // The kernel boundary between passes publishes the pyramid and the SAD to
-// every XCD at once. Inside a single-frame cell pass, a cell only waits for
-// the counts of lower-numbered cells of its stream (relaxed agent-scope
-// count words, no fences); each XCD dispatches its workgroups in index
-// order, so the lowest unfinished cell can always run, and every wait is
-// bounded and sets an error flag instead of hanging. In a chunk, only T_H
-// marking waits, on the same cell's count word of the previous frame.
+// every XCD at once. In the per-pixel mask modes a cell only waits for the
+// counts of lower-numbered cells of its stream (relaxed agent-scope count
+// words, no fences); each XCD dispatches its workgroups in index order, so
+// the lowest unfinished cell can always run, and every wait is bounded and
+// sets an error flag instead of hanging. In a chunk, only T_H marking
+// waits, on the same cell's count word of the previous frame.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
