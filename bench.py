@@ -798,7 +798,7 @@ def serving_workload(horizon: float, speedup: float, budget_mib: int) -> dict:
 
 
 def serving_saturation(duration: float, budget_mib: int) -> dict:
-    """Serving at saturation: 640 requests (200-2000 frames, resolutions
+    """Serving at saturation: 2000 requests (200-2000 frames, resolutions
     uniform over 320x240 .. 1920x1080) all waiting at the start, at most 256
     concurrent streams under the HBM budget; every admitted stream has a
     frame ready at every tick, and ended streams give their slot to waiting
@@ -809,7 +809,7 @@ def serving_saturation(duration: float, budget_mib: int) -> dict:
     from paper_1503_06959_amd import autotune, serve, synth
     bank = serve.ClipBank(n_clips=2, clip_len=48, workers=min(16, os.cpu_count() or 1))
     tiles = {res: autotune.best_tile(res[0], res[1], synth.RES_PRESETS[res][0])[0] for res in serve.RESOLUTIONS}
-    reqs = serve.poisson_requests(8.0, 80.0, 5001, clip_len=48)[:640]
+    reqs = serve.poisson_requests(8.0, 250.0, 5001, clip_len=48)[:2000]
     out = {"workload": f"{len(reqs)} requests waiting at the start (200-2000 frames each, resolutions uniform over "
                        f"{'/'.join(f'{w}x{h}' for w, h in serve.RESOLUTIONS)}), <= 256 concurrent, HBM budget "
                        f"{budget_mib} MiB, every active stream has a frame ready at every tick, {duration:g}s per "

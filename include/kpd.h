@@ -312,6 +312,14 @@ int batch_detach(kpd_batch* b, kpd_stream* s);
  * frame per stream per tick: KPD_ESTATE if one is already staged. */
 int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags);
 
+/* Stage the next frame of n attached streams in one call: the same as n
+ * batch_push calls in array order (streams[k] gets frames[k] with row pitch
+ * pitch_bytes[k], all with `flags`), for servers that stage hundreds of
+ * streams per tick. Stops at the first failure and returns its code; the
+ * frames before it stay staged. */
+int batch_push_many(kpd_batch* b, int n, kpd_stream* const* streams, const uint8_t* const* frames,
+                    const size_t* pitch_bytes, int flags);
+
 /* Run one tick over every attached stream with a staged frame.
  * Asynchronous; get_keypoints on a stream waits for it. A barrier wait of
  * the single-launch tick that does not end (the device holding fewer of its

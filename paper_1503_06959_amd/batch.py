@@ -53,6 +53,16 @@ class Batch:
             h = self._held[s.handle]
             self._held[s.handle] = [h[1], frame]
 
+    def push_many(self, streams, frames, retain: bool = False) -> None:
+        """Stage one device frame for each stream in one library call (the
+        same as push() for each pair, in order)."""
+        kpd.batch_push_many(self.handle, [s.handle for s in streams], [f.data_ptr() for f in frames],
+                            [f.stride(0) for f in frames], retain)
+        if retain:
+            for s, f in zip(streams, frames):
+                h = self._held[s.handle]
+                self._held[s.handle] = [h[1], f]
+
     def set_single_launch(self, on: bool) -> None:
         kpd.batch_set_single_launch(self.handle, on)
 

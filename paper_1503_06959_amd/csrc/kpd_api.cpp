@@ -1593,18 +1593,51 @@ int batch_detach(kpd_batch* b, kpd_stream* s)
     return rebuild_maps(b);
 }
 
-int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
+}  // extern "C"
+
+namespace {
+
+// Stage stream s's frame; `hint` is where s is first looked for among the
+// attached streams (callers pushing in attach order find it there).
+int batch_stage(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags, size_t* hint)
 {
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
-    auto it = std::find(b->streams.begin(), b->streams.end(), s);
-    if (it == b->streams.end()) return fail(KPD_EINVAL, "stream not attached");
-    const size_t i = (size_t)(it - b->streams.begin());
+    size_t i = *hint;
+    if (i >= b->streams.size() || b->streams[i] != s) {
+        auto it = std::find(b->streams.begin(), b->streams.end(), s);
+        if (it == b->streams.end()) return fail(KPD_EINVAL, "stream not attached");
+        i = (size_t)(it - b->streams.begin());
+    }
+    *hint = i + 1;
     if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
     if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on single-frame pushes only");
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
     if (rc != KPD_OK) return rc;
     b->has_frame[i] = 1;
+    return KPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    size_t hint = 0;
+    return batch_stage(b, s, frame, pitch_bytes, flags, &hint);
+}
+
+int batch_push_many(kpd_batch* b, int n, kpd_stream* const* streams, const uint8_t* const* frames,
+                    const size_t* pitch_bytes, int flags)
+{
+    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (n < 0 || (n > 0 && (!streams || !frames || !pitch_bytes))) return fail(KPD_EINVAL, "bad arrays");
+    size_t hint = 0;
+    for (int k = 0; k < n; ++k) {
+        const int rc = batch_stage(b, streams[k], frames[k], pitch_bytes[k], flags, &hint);
+        if (rc != KPD_OK) return rc;
+    }
     return KPD_OK;
 }
 

@@ -34,7 +34,8 @@ KEYPOINT_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("octave", "u1"), ("pad",
 EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_keypoints",
             "close_stream", "reset_stream", "kpd_last_error", "kpd_device_result", "kpd_cell_stats",
             "kpd_pyramid_level", "kpd_profile", "kpd_profile_read", "batch_bytes", "open_batch",
-            "batch_attach", "batch_detach", "batch_push", "batch_tick", "batch_gather", "close_batch",
+            "batch_attach", "batch_detach", "batch_push", "batch_push_many", "batch_tick", "batch_gather",
+            "close_batch",
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
             "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
             "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
@@ -99,6 +100,7 @@ def _load() -> ctypes.CDLL:
     L.batch_attach.argtypes = [P, P]
     L.batch_detach.argtypes = [P, P]
     L.batch_push.argtypes = [P, P, P, sz, ctypes.c_int]
+    L.batch_push_many.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_int]
     L.batch_tick.argtypes = [P]
     L.batch_set_single_launch.argtypes = [P, ctypes.c_int]
     L.batch_gather.argtypes = [P, P, sz, P]
@@ -353,6 +355,20 @@ def batch_detach(batch: int, handle: int) -> None:
 def batch_push(batch: int, handle: int, frame, retain: bool = False) -> None:
     ptr, pitch, flags = _frame_args(frame, retain)
     _check(lib.batch_push(batch, handle, ptr, pitch, flags))
+
+
+def batch_push_many(batch: int, handles, frame_ptrs, pitches, retain: bool = False) -> None:
+    """Stage one device frame for each of several streams in one call:
+    handles, frame_ptrs (device addresses of uint8 frames) and pitches
+    (bytes) are equal-length sequences of ints."""
+    n = len(handles)
+    if len(frame_ptrs) != n or len(pitches) != n:
+        raise ValueError("handles, frame_ptrs and pitches differ in length")
+    h = np.asarray(handles, dtype=np.uint64)
+    f = np.asarray(frame_ptrs, dtype=np.uint64)
+    p = np.asarray(pitches, dtype=np.uint64)
+    _check(lib.batch_push_many(batch, n, h.ctypes.data, f.ctypes.data, p.ctypes.data,
+                               FRAME_DEVICE_RETAIN if retain else FRAME_DEVICE))
 
 
 def batch_set_single_launch(batch: int, on: bool) -> None:

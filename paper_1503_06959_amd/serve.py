@@ -116,9 +116,12 @@ class ClipBank:
             banks = list(ex.map(_gen_bank, [(w, h, n_clips, clip_len) for (w, h) in resolutions]))
         self.host = {res: b for res, b in zip(resolutions, banks)}
         self.dev = {res: torch.from_numpy(b).cuda() for res, b in self.host.items()}
+        # one view per frame, made once: a tick looks frames up by index
+        self.views = {res: [[d[c, f] for f in range(d.shape[1])] for c in range(d.shape[0])]
+                      for res, d in self.dev.items()}
 
     def frame(self, req: Request, k: int):
-        return self.dev[req.res][req.clip, pingpong(req.offset + k, self.clip_len)]
+        return self.views[req.res][req.clip][pingpong(req.offset + k, self.clip_len)]
 
     def host_frame(self, req: Request, k: int) -> np.ndarray:
         return self.host[req.res][req.clip, pingpong(req.offset + k, self.clip_len)]
@@ -149,6 +152,7 @@ class BatchedBackend:
         self.out = torch.empty(gather_cap * 8, dtype=torch.uint8, device="cuda")
         self.counts = torch.empty(max_streams, dtype=torch.int32, device="cuda")
         self.staged: List[int] = []
+        self.frames: List[object] = []
 
     def bytes_of(self, req: Request) -> int:
         return self.kpd.stream_bytes(req.res[0], req.res[1], preset_params(self.kpd, req.res))
@@ -160,12 +164,15 @@ class BatchedBackend:
         self.order.append(req.sid)
 
     def push(self, sid: int, frame) -> None:
-        with self.torch.cuda.stream(self.batch.torch_stream):
-            self.batch.push(self.streams[sid], frame, retain=True)
         self.staged.append(sid)
+        self.frames.append(frame)
 
     def run(self) -> Dict[int, np.ndarray]:
         kpd = self.kpd
+        # every staged frame in one library call, then the tick
+        with self.torch.cuda.stream(self.batch.torch_stream):
+            self.batch.push_many([self.streams[sid] for sid in self.staged], self.frames, retain=True)
+        self.frames = []
         self.batch.tick()
         kpd.batch_gather(self.batch.handle, self.out, self.counts)
         with self.torch.cuda.stream(self.batch.torch_stream):

@@ -56,12 +56,18 @@ def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode
             i = st["next"]
             if mode == "host":
                 b.push(st["g"], st["frames"][i])
-            else:
+            elif mode != "many":
                 with torch.cuda.stream(b.torch_stream):
                     b.push(st["g"], st["dev"][i], retain=(mode == "retain"))
             st["o"].push(st["frames"][i])
             st["next"] += 1
             pushed.append(si)
+        if mode == "many":
+            # every stream's frame staged in one library call, reversed order
+            # (each stream is looked up, not taken by position)
+            with torch.cuda.stream(b.torch_stream):
+                b.push_many([streams[si]["g"] for si in reversed(pushed)],
+                            [streams[si]["dev"][streams[si]["next"] - 1] for si in reversed(pushed)], retain=True)
         b.tick()
         for si in pushed:
             st = streams[si]
@@ -98,6 +104,11 @@ def test_mixed_streams_eager_and_host_frames(kpd, single):
 def test_streams_skipping_ticks(kpd, single):
     # streams with no frame in a tick are inactive; their state must not move
     run_batch(kpd, mixed_specs(6, 4200), 7, use_graph=True, skip=lambda s, t: (s + t) % 3 == 0, single=single)
+
+
+def test_streams_staged_in_one_call(kpd):
+    # batch_push_many: every tick's frames in one call, with streams skipping ticks
+    run_batch(kpd, mixed_specs(6, 4300), 6, mode="many", single=False, skip=lambda s, t: (s + t) % 3 == 0)
 
 
 def test_tile_size_does_not_change_results(kpd):
