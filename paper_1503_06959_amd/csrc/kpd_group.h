@@ -39,6 +39,30 @@ __device__ __forceinline__ unsigned gdiv(unsigned i, uint64_t magic)
     return (unsigned)(((uint64_t)i * magic) >> 32);
 }
 
+// Frames and levels are device global memory, but their pointers reach the
+// detector through LDS, where the compiler loses that and would emit flat
+// loads (which also count against the LDS counter, so LDS waits wait for
+// them). These read through global loads.
+template <typename T>
+__device__ __forceinline__ T gld(const uint8_t* p)
+{
+    // through scalar types: the compiler keeps the address space of those
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long v = *(const __attribute__((address_space(1))) unsigned long long*)p;
+        return T{(uint32_t)v, (uint32_t)(v >> 32)};
+    } else {
+        return *(const __attribute__((address_space(1))) T*)p;
+    }
+}
+
+// A global store of a scalar type (the output lists are device global
+// memory whose pointers also come through LDS or a table).
+template <typename T>
+__device__ __forceinline__ void gst(void* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // A value every lane of the wave holds, moved to a scalar register.
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t rfl64(uint64_t v)
@@ -55,10 +79,10 @@ __device__ __noinline__ uint2 load8_slow(const uint8_t* src, int gx, int w, int 
     for (int d = 0; d < 2; ++d) {
         const int g = gx + 4 * d;
         if (mode == 1 && g >= 0 && g + 4 <= w) {
-            wv[d] = *reinterpret_cast<const uint32_t*>(src + 4 * d);
+            wv[d] = gld<uint32_t>(src + 4 * d);
         } else {
             for (int k = 0; k < 4; ++k)
-                if (g + k >= 0 && g + k < w) wv[d] |= (uint32_t)src[4 * d + k] << (8 * k);
+                if (g + k >= 0 && g + k < w) wv[d] |= (uint32_t)gld<uint8_t>(src + 4 * d + k) << (8 * k);
         }
     }
     return make_uint2(wv[0], wv[1]);
@@ -133,8 +157,8 @@ __device__ __forceinline__ int group_score(const uint8_t* B, int tp, int t)
 {
     int c[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) c[k] = B[ring_row(k) * tp + ring_col(k)];
-    const int p = B[3 * tp + 3];
+    for (int k = 0; k < 16; ++k) c[k] = gld<uint8_t>(B + ring_row(k) * tp + ring_col(k));
+    const int p = gld<uint8_t>(B + 3 * tp + 3);
     const int hi = p + t, lo = p - t;
     unsigned bm = 0, dm = 0;
     int smax = 0, smin = 0;
@@ -352,14 +376,14 @@ __device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl,
                     uint2 c, n, s;
                     uint32_t cm, cp;
                     if (mode == 2) {
-                        c = *reinterpret_cast<const uint2*>(T);
-                        n = *reinterpret_cast<const uint2*>(T - 3 * pt);
-                        cm = *reinterpret_cast<const uint32_t*>(T - 4);
-                        cp = *reinterpret_cast<const uint32_t*>(T + 8);
+                        c = gld<uint2>(T);
+                        n = gld<uint2>(T - 3 * pt);
+                        cm = gld<uint32_t>(T - 4);
+                        cp = gld<uint32_t>(T + 8);
                         if (!guard || gx + 8 <= wo) {
-                            s = *reinterpret_cast<const uint2*>(T + 3 * pt);
+                            s = gld<uint2>(T + 3 * pt);
                         } else {   // bytes past the width feed no interior pixel
-                            s.x = gx + 4 <= wo ? *reinterpret_cast<const uint32_t*>(T + 3 * pt) : 0u;
+                            s.x = gx + 4 <= wo ? gld<uint32_t>(T + 3 * pt) : 0u;
                             s.y = 0u;
                         }
                     } else {
@@ -545,15 +569,16 @@ __device__ void detect_group(const GroupLayout* glob, const uint8_t* const* lvl,
                             const uint32_t v = (uint32_t)gv(sm, G, o, x, y);
                             // one keypoint per 2x2 block keeps pos below the cell's capacity
                             if (pos < out.list_cap)
-                                *reinterpret_cast<uint2*>(out.list + pos) =
-                                    make_uint2((uint32_t)x | ((uint32_t)y << 16), (uint32_t)o | (v << 16));
+                                gst<unsigned long long>(out.list + pos,
+                                                        (unsigned long long)((uint32_t)x | ((uint32_t)y << 16)) |
+                                                            ((unsigned long long)((uint32_t)o | (v << 16)) << 32));
                             ++pos;
                         }
                     }
                 }
                 run += total;
             }
-            if (lane == 0) out.own_count[c] = run;
+            if (lane == 0) gst<uint32_t>(out.own_count + c, run);
         }
     }
 }
