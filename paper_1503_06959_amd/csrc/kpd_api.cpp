@@ -183,9 +183,17 @@ bool group_layouts(const Layout& L, int gx, int gy, int waves, std::vector<kpd::
 constexpr int kGroupWaves = 4;           // 256-thread workgroups for one-cell layouts
 constexpr int kGroupLdsDefault = 48 * 1024;   // default groups: three workgroups per CU
 
-// Threads of a workgroup of the listed-cell detection of chunks (128, 256
-// or 512; measured: 256 is the faster at 640x480, 128 by 4% at 1920x1080).
-constexpr int kListThreads = 256;
+// Threads of a workgroup of the listed-cell detection of chunks. Few cells
+// a frame mean few listed items, whose latency decides: more waves per item
+// shorten its chain; many cells mean many items, whose throughput decides:
+// smaller workgroups keep more of them in flight. Measured on the masked
+// videos (listed detection per 300 frames): 640x480 with 192 cells 17.3,
+// 18.9 and 24.4 us at 512, 256 and 128 threads; 1920x1080 with 576 cells
+// 245, 172 and 162 us.
+int list_threads(const Layout& L)
+{
+    return L.ncell <= 256 ? 512 : (L.ncell >= 512 ? 128 : 256);
+}
 
 // Dynamic LDS of a one-cell group workgroup of `threads` threads (its wave
 // queues scale with the waves).
@@ -1155,8 +1163,8 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         g1.al8 = (reinterpret_cast<uintptr_t>(frames) % 8 == 0 && frame_stride % 8 == 0 && pitch % 8 == 0) ? 1 : 0;
         auto detect = [&](int round) {
             return timed(s, KPD_K_DETECT, [&] {
-                return kpd::launch_detect_list_groups(ctab, h, g1, glds1_for(L, kListThreads), kListThreads, round,
-                                                      s->stream);
+                const int nt = list_threads(L);
+                return kpd::launch_detect_list_groups(ctab, h, g1, glds1_for(L, nt), nt, round, s->stream);
             });
         };
         if (h.kb_chain) {

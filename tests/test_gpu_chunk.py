@@ -140,11 +140,14 @@ def test_pyramid_after_chunk_is_last_frame(kpd):
 
 @pytest.mark.parametrize("W,H,O,Nc,Nr,plan", [(1280, 720, 5, 32, 18, [23, 9, 0, 17]),
                                                  (640, 480, 6, 16, 12, [23, 6, 13]),
-                                                 (1920, 1080, 5, 32, 18, [13, 1, 9])])
+                                                 (1920, 1080, 5, 32, 18, [13, 1, 9]),
+                                                 (640, 480, 4, 24, 16, [23, 9, 0, 9])])
 def test_sequential_tile_pass_shapes(kpd, W, H, O, Nc, Nr, plan):
     # chunks whose tile pass walks frames in order (256 x 64 tiles at O <= 5,
     # 128 x 128 at O = 6; runs of ragged length; a partial last tile column
-    # at 1920): every frame's keypoints and mask, then the last frame's pyramid
+    # at 1920), and a grid whose cells cross dwords (the per-frame tile pass;
+    # 384 cells: the listed cells' mid-size workgroups): every frame's
+    # keypoints and mask, then the last frame's pyramid
     import torch
     sc = synth.Scene(W, H, 45, 30, 12, max(40, H // 6), 0.75, 2.0, True, 700 + W + O)
     frames = synth.make_video(sc)
