@@ -92,8 +92,9 @@ extern "C" {
  *              others (Sec. 3, Eq. 1): KPD_FEAT_DESCRIPTOR, an orientation
  *              sector and a 512-bit binary descriptor (get_descriptors);
  *              KPD_FEAT_REFINE, the sub-pixel position and sub-scale of
- *              Sec. 2's interpolation (get_refined). push_frame only, mask
- *              mode 0. 0: nothing.
+ *              Sec. 2's interpolation (get_refined). push_frame and
+ *              push_frames (get_chunk_descriptors, get_chunk_refined),
+ *              mask mode 0. 0: nothing.
  *   group_cols, group_rows
  *              cells one detection workgroup covers when a chunk's
  *              parameters mark every cell (full-frame detection): a
@@ -359,6 +360,15 @@ int kpd_chunk_result(kpd_stream* s, int i, const kpd_keypoint** d_list, const ui
  * *count set when capacity is too small). */
 int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count);
 
+/* Descriptors and refined values (Sec. 3 feature model, Sec. 2's
+ * interpolation; Eq. 1 carries them with their keypoints) of frame i of the
+ * last push_frames call, in get_chunk_keypoints' order: a feature is
+ * described on the levels of the frame that detected it. Streams opened
+ * with KPD_FEAT_DESCRIPTOR / KPD_FEAT_REFINE (KPD_EINVAL otherwise);
+ * count/capacity rules as get_chunk_keypoints'. */
+int get_chunk_descriptors(kpd_stream* s, int i, kpd_descriptor* out, size_t capacity, size_t* count);
+int get_chunk_refined(kpd_stream* s, int i, kpd_refined* out, size_t capacity, size_t* count);
+
 /* Wait and copy per-cell statistics of the last frame: the summed absolute
  * level-0 difference (uint32 per cell; meaningful only on frames whose mask
  * was computed from data, i.e. not the first frame, not after a change of t,
@@ -379,7 +389,7 @@ int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out);
 #define KPD_K_DETECT 1
 #define KPD_K_COMPACT 2 /* compaction pass (Eq. 1) of push_frame and push_frames */
 #define KPD_K_MARK 3    /* mark, speculation and resolve passes of push_frames */
-#define KPD_K_DESCRIBE 4 /* feature pass of push_frame: descriptors, refinement */
+#define KPD_K_DESCRIBE 4 /* feature pass of push_frame and push_frames: descriptors, refinement */
 #define KPD_NKERNELS 5
 
 /* Switch per-kernel GPU timing on (1) or off (0). While on, every kernel

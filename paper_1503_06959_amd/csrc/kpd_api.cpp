@@ -72,6 +72,7 @@ struct Layout {
     int seq_tile_w = 256, seq_tiles_x = 0, seq_ntiles = 0, seq_slots = 1;   // its tiles, LDS slots a tile
     size_t pyr_stride = 0;
     size_t off_csad = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_clist = 0, clist_stride = 0;
+    size_t off_cdesc = 0, off_cref = 0;   // features of chunk frames 0..K-2 (clist_stride entries apart)
     size_t off_sparse = 0, off_own = 0, off_marks = 0, off_cbase = 0, off_work = 0;
     size_t off_ctab = 0;
     size_t list_cap = 0;    // entries of chunk and sparse lists: one feature per 2x2 decision block
@@ -418,6 +419,9 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
         L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
         L->off_clist = off; off += L->clist_stride * (size_t)(L->K - 1);   // the last frame's D goes to D_n
+        const size_t centries = L->clist_stride / sizeof(kpd_keypoint) * (size_t)(L->K - 1);
+        if (p->features & KPD_FEAT_DESCRIPTOR) { L->off_cdesc = off; off = align_up(off + centries * sizeof(kpd_descriptor)); }
+        if (p->features & KPD_FEAT_REFINE) { L->off_cref = off; off = align_up(off + centries * sizeof(kpd_refined)); }
         L->off_ctab = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs));
         L->off_glay = off; off = align_up(off + (size_t)L->ngroups * sizeof(kpd::GroupLayout));
     }
@@ -954,6 +958,34 @@ int copy_features(kpd_stream* s, const size_t* off, T* out, size_t capacity, siz
     return KPD_OK;
 }
 
+// Features of frame i of the last chunk: D_n's for the last frame, else
+// the chunk buffer at coff, clist_stride entries apart.
+template <class T>
+int copy_chunk_features(kpd_stream* s, int i, const size_t* off_last, size_t coff, T* out, size_t capacity,
+                        size_t* count)
+{
+    if (!count) return fail(KPD_EINVAL, "count is NULL");
+    if (i < 0 || i >= s->chunk_n) return fail(KPD_EINVAL, "no such frame in the last chunk");
+    if (i == s->chunk_n - 1) return copy_features(s, off_last, out, capacity, count);
+    const Layout& L = s->L;
+    uint32_t hdr[4] = {0, 0, 0, 0}, total = 0;
+    KPD_HIP(hipMemcpyAsync(hdr, s->at<uint32_t>(L.off_hdr), sizeof(hdr), hipMemcpyDeviceToHost, s->stream));
+    KPD_HIP(hipMemcpyAsync(&total, s->at<uint32_t>(L.off_ctotal) + i, 4, hipMemcpyDeviceToHost, s->stream));
+    KPD_HIP(hipStreamSynchronize(s->stream));
+    if (hdr[kHdrErr]) return fail(KPD_EDEVICE, "a wait on the device timed out");
+    total = std::min<uint32_t>(total, (uint32_t)L.list_cap);
+    *count = total;
+    if (total > capacity) return fail(KPD_ETRUNC, "capacity smaller than the feature count");
+    if (total > 0) {
+        if (!out) return fail(KPD_EINVAL, "out is NULL");
+        const size_t stride = L.clist_stride / sizeof(kpd_keypoint);
+        KPD_HIP(hipMemcpyAsync(out, reinterpret_cast<const T*>(s->arena + coff) + stride * (size_t)i,
+                               (size_t)total * sizeof(T), hipMemcpyDeviceToHost, s->stream));
+        KPD_HIP(hipStreamSynchronize(s->stream));
+    }
+    return KPD_OK;
+}
+
 }  // namespace
 
 namespace kpd {
@@ -1075,7 +1107,6 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     const Layout& L = s->L;
     if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
-    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on single-frame pushes only");
     if (!frames) return fail(KPD_EINVAL, "frames is NULL");
     if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
@@ -1209,6 +1240,42 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     ca.sad_single_next = s->at<uint32_t>(L.off_sad[(n_last + 1) & 1]);
     ca.work_count = h.work_count;
     KPD_HIP(timed(s, KPD_K_COMPACT, [&] { return kpd::launch_compact_chunk(ca, n_frames, s->stream); }));
+    if (s->p.features) {
+        // features of every frame's list: computed where a frame marked a
+        // cell, carried with the keypoints elsewhere (Eq. 1)
+        kpd::DescChunkArgs da{};
+        da.table = ctab;
+        da.frames = frames;
+        da.stride = frame_stride;
+        da.pitch = pitch;
+        da.n_frames = n_frames;
+        da.ncell = L.ncell;
+        da.Kw = L.Kw;
+        da.O = L.O;
+        da.t = s->p.fast_t;
+        da.marks = ca.marks;
+        da.list_cap = ca.list_cap;
+        da.list_stride = ca.list_stride;
+        da.lists = ca.lists;
+        da.counts = ca.counts;
+        da.offs = ca.offs;
+        da.last_list = ca.next_list;
+        da.last_count = ca.next_count;
+        da.last_offs = ca.next_offs;
+        da.prev_offs = ca.prev_offs;
+        if (s->p.features & KPD_FEAT_DESCRIPTOR) {
+            da.tab = s->at<kpd::DescTables>(L.off_dtab);
+            da.descs = reinterpret_cast<kpd_descriptor*>(s->arena + L.off_cdesc);
+            da.last_desc = s->at<kpd_descriptor>(L.off_desc[fb_next]);
+            da.prev_desc = s->at<kpd_descriptor>(L.off_desc[fb_prev]);
+        }
+        if (s->p.features & KPD_FEAT_REFINE) {
+            da.refs = reinterpret_cast<kpd_refined*>(s->arena + L.off_cref);
+            da.last_ref = s->at<kpd_refined>(L.off_ref[fb_next]);
+            da.prev_ref = s->at<kpd_refined>(L.off_ref[fb_prev]);
+        }
+        KPD_HIP(timed(s, KPD_K_DESCRIBE, [&] { return kpd::launch_describe_chunk(da, s->stream); }));
+    }
 
     const uint8_t* last = frames + (size_t)(n_frames - 1) * frame_stride;
     s->prev0 = last;
@@ -1305,6 +1372,20 @@ int get_refined(kpd_stream* s, kpd_refined* out, size_t capacity, size_t* count)
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (!(s->p.features & KPD_FEAT_REFINE)) return fail(KPD_EINVAL, "stream opened without refinement");
     return copy_features(s, s->L.off_ref, out, capacity, count);
+}
+
+int get_chunk_descriptors(kpd_stream* s, int i, kpd_descriptor* out, size_t capacity, size_t* count)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!(s->p.features & KPD_FEAT_DESCRIPTOR)) return fail(KPD_EINVAL, "stream opened without descriptors");
+    return copy_chunk_features(s, i, s->L.off_desc, s->L.off_cdesc, out, capacity, count);
+}
+
+int get_chunk_refined(kpd_stream* s, int i, kpd_refined* out, size_t capacity, size_t* count)
+{
+    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!(s->p.features & KPD_FEAT_REFINE)) return fail(KPD_EINVAL, "stream opened without refinement");
+    return copy_chunk_features(s, i, s->L.off_ref, s->L.off_cref, out, capacity, count);
 }
 
 int kpd_desc_point(int sector, int i, int* dx, int* dy)
@@ -1571,7 +1652,7 @@ int batch_attach(kpd_batch* b, kpd_stream* s)
 {
     if (!b || !s || s->closed) return fail(KPD_ESTATE, "batch or stream is closed");
     if (s->stream != b->stream) return fail(KPD_EINVAL, "stream was opened on another HIP stream");
-    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on single-frame pushes only");
+    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on push_frame and push_frames only");
     if (std::find(b->streams.begin(), b->streams.end(), s) != b->streams.end())
         return fail(KPD_EINVAL, "stream already attached");
     if ((int)b->streams.size() >= b->max_streams) return fail(KPD_ENOMEM, "batch stream capacity exceeded");
@@ -1618,7 +1699,7 @@ int batch_stage(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_
     *hint = i + 1;
     if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
-    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on single-frame pushes only");
+    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on push_frame and push_frames only");
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
     if (rc != KPD_OK) return rc;
     b->has_frame[i] = 1;

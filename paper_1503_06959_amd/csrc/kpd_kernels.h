@@ -217,6 +217,34 @@ struct CompactArgs {
     uint32_t* work_count;            // both words cleared for the next chunk
 };
 
+// k_describe_chunk: features of a chunk's lists after compaction (the
+// lists, counts and offsets CompactArgs names). A null tab (descs,
+// last_desc) or refs (last_ref) leaves that part out.
+struct DescChunkArgs {
+    const ChunkArgs* table;            // frame j's octaves 1.. and level sizes
+    const uint8_t* frames;             // level 0 of frame j at frames + j * stride
+    size_t stride;
+    int pitch;
+    int n_frames, ncell, Kw, O, t;
+    const unsigned long long* marks;   // cells x Kw mark words (bit j = frame j)
+    const DescTables* tab;
+    uint32_t list_cap;
+    size_t list_stride;                // entries between consecutive chunk lists
+    const kpd_keypoint* lists;         // frames 0..n_frames-2: lists, counts and offsets
+    const uint32_t* counts;            // (chunk frames x cells)
+    const uint32_t* offs;
+    kpd_descriptor* descs;             // their features, list_stride entries apart
+    kpd_refined* refs;
+    const kpd_keypoint* last_list;     // the last frame's D_n
+    const uint32_t* last_count;
+    const uint32_t* last_offs;
+    kpd_descriptor* last_desc;
+    kpd_refined* last_ref;
+    const kpd_descriptor* prev_desc;   // features of the list before the chunk
+    const kpd_refined* prev_ref;
+    const uint32_t* prev_offs;
+};
+
 // The group detector: the groups' layouts (a rectangle of cells each,
 // row-major over the group grid; each layout names its cells and their
 // list bases) and whether level 0's rows can be read 8 bytes at a time.
@@ -267,6 +295,7 @@ hipError_t set_detect_lds_limit(int lds_bytes);
 hipError_t launch_frame(const FrameArgs& a, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s);
 hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s);
+hipError_t launch_describe_chunk(const DescChunkArgs& a, hipStream_t s);
 hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, uint32_t out_cap, uint32_t* counts,
                                hipStream_t s);

@@ -1241,73 +1241,79 @@ __device__ kpd_refined refine_feature(const int* S, int x, int y, int o, int O)
     return r;
 }
 
-// Features of one frame (Sec. 3 feature model; Eq. 1 carries whole
-// features). A workgroup per cell: an unmarked cell's features are D_{n-1}'s,
-// so their descriptors and refined values are copied in the same order; a
-// marked cell's are new and each of its four waves takes one feature at a
-// time. Refinement: 27 lanes score one pixel each of the three 3 x 3 patches
-// and one lane fits them. Descriptor: the wave loads the feature's 27 x 27
-// patch (every point of the pattern, turned any way, with its box) into LDS
-// in one round of loads, a lane per pattern point takes the box mean around
-// its point, the lanes sum the long pairs' gradient, 32 lanes test the
-// sector boundaries, the points are taken again turned to the sector, and
-// eight ballots over the short pairs give the bits.
+// Features (Sec. 3 feature model; Eq. 1 carries whole features). New
+// features are computed by the waves of a workgroup, one feature at a time
+// each. Refinement: 27 lanes score one pixel each of the three 3 x 3
+// patches and one lane fits them. Descriptor: the wave loads the feature's
+// 27 x 27 patch (every point of the pattern, turned any way, with its box)
+// into LDS in one round of loads, a lane per pattern point takes the box
+// mean around its point, the lanes sum the long pairs' gradient, 32 lanes
+// test the sector boundaries, the points are taken again turned to the
+// sector, and eight ballots over the short pairs give the bits. Carried
+// features keep the records they were computed with, copied in order.
 constexpr int kDescBlock = 256;
 constexpr int kPatchR = 13;                  // pattern radius 11 plus a box half-size 2
 constexpr int kPatch = 2 * kPatchR + 1;      // patch side
 
-__global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
+// Copies the records of n features from entry src0 of one list to entry
+// dst0 of another (a null descriptor or refined destination leaves that
+// part out); entries past list_cap on either side are left out.
+__device__ void copy_feature_records(const kpd_descriptor* dsrc, kpd_descriptor* ddst, const kpd_refined* rsrc,
+                                     kpd_refined* rdst, uint32_t src0, uint32_t dst0, uint32_t n, uint32_t list_cap)
 {
-    __shared__ int s_v[kDescBlock / 64][64];
-    __shared__ uint8_t s_patch[kDescBlock / 64][kPatch * kPatch];
-    const int c = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t n = a.count_cur[c], dst0 = a.off_cur[c];
-    if (!a.mask[c]) {
-        const uint32_t src0 = a.off_prev[c];
-        if (a.tab) {
-            constexpr int kw = sizeof(kpd_descriptor) / 8;
-            const uint64_t* src = reinterpret_cast<const uint64_t*>(a.desc_prev);
-            uint64_t* dst = reinterpret_cast<uint64_t*>(a.desc_cur);
-            for (uint32_t i = threadIdx.x; i < n * kw; i += kDescBlock) {
-                const uint32_t e = i / kw;
-                if (src0 + e < a.list_cap && dst0 + e < a.list_cap)
-                    dst[(size_t)(dst0 + e) * kw + i % kw] = src[(size_t)(src0 + e) * kw + i % kw];
-            }
+    if (ddst) {
+        constexpr int kw = sizeof(kpd_descriptor) / 8;
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(dsrc);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(ddst);
+        for (uint32_t i = threadIdx.x; i < n * kw; i += kDescBlock) {
+            const uint32_t e = i / kw;
+            if (src0 + e < list_cap && dst0 + e < list_cap)
+                dst[(size_t)(dst0 + e) * kw + i % kw] = src[(size_t)(src0 + e) * kw + i % kw];
         }
-        if (a.ref_cur)
-            for (uint32_t e = threadIdx.x; e < n; e += kDescBlock)
-                if (src0 + e < a.list_cap && dst0 + e < a.list_cap) a.ref_cur[dst0 + e] = a.ref_prev[src0 + e];
-        return;
     }
+    if (rdst)
+        for (uint32_t e = threadIdx.x; e < n; e += kDescBlock)
+            if (src0 + e < list_cap && dst0 + e < list_cap) rdst[dst0 + e] = rsrc[src0 + e];
+}
+
+// Features of entries [dst0, dst0 + n) of a keypoint list, computed on the
+// levels of their frame (lv: ptr, pitch, w and h of octave o) into the same
+// entries of desc and ref (either may be null: that part is left out; tab
+// is null exactly when desc is).
+template <class Lv>
+__device__ void describe_entries(const Lv& lv, const DescTables* tab, int O, int t, const kpd_keypoint* list,
+                                 kpd_descriptor* desc, kpd_refined* ref, uint32_t dst0, uint32_t n,
+                                 uint32_t list_cap, int (*s_v)[64], uint8_t (*s_patch)[kPatch * kPatch])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int* V = s_v[wave];
     uint8_t* patch = s_patch[wave];
     for (uint32_t k = wave; k < n; k += kDescBlock / 64) {
-        if (dst0 + k >= a.list_cap) break;
-        const kpd_keypoint kp = a.list_cur[dst0 + k];
+        if (dst0 + k >= list_cap) break;
+        const kpd_keypoint kp = list[dst0 + k];
         const int o = kp.octave;
-        if (a.ref_cur) {
+        if (ref) {
             if (lane < 27) {
                 const int kl = lane / 9, r = lane - 9 * kl, i = r / 3 - 1, j = r - 3 * (r / 3) - 1;
                 const int l = o - 1 + kl;
                 int sc = 0;
-                if (l >= 0 && l < a.O) {
+                if (l >= 0 && l < O) {
                     const int x = kl == 0 ? 2 * (int)kp.x + 1 : (kl == 1 ? (int)kp.x : (int)kp.x >> 1);
                     const int y = kl == 0 ? 2 * (int)kp.y + 1 : (kl == 1 ? (int)kp.y : (int)kp.y >> 1);
                     const int px = x + i, py = y + j;
-                    if (px >= 3 && py >= 3 && px < a.w[l] - 3 && py < a.h[l] - 3)
-                        sc = full_score(a.lvl[l] + (size_t)py * a.pitch[l] + px, a.pitch[l], a.t);
+                    if (px >= 3 && py >= 3 && px < lv.w(l) - 3 && py < lv.h(l) - 3)
+                        sc = full_score(lv.ptr(l) + (size_t)py * lv.pitch(l) + px, lv.pitch(l), t);
                 }
                 V[lane] = sc;
             }
             __builtin_amdgcn_wave_barrier();
-            if (lane == 0) a.ref_cur[dst0 + k] = refine_feature(V, kp.x, kp.y, o, a.O);
+            if (lane == 0) ref[dst0 + k] = refine_feature(V, kp.x, kp.y, o, O);
             __builtin_amdgcn_wave_barrier();   // V is reused below
         }
-        if (!a.tab) continue;
-        const DescTables& T = *a.tab;
-        const uint8_t* L = a.lvl[o];
-        const int pitch = a.pitch[o], w = a.w[o], h = a.h[o];
+        if (!tab) continue;
+        const DescTables& T = *tab;
+        const uint8_t* L = lv.ptr(o);
+        const int pitch = lv.pitch(o), w = lv.w(o), h = lv.h(o);
         // the patch around the feature, edge pixels repeated
         constexpr int kPer = (kPatch * kPatch + 63) / 64;
         uint8_t px[kPer];
@@ -1364,7 +1370,7 @@ __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
             const uint64_t b = __ballot(V[T.sp[q][0]] > V[T.sp[q][1]]);
             if (lane == r) mine = b;
         }
-        kpd_descriptor* D = a.desc_cur + dst0 + k;
+        kpd_descriptor* D = desc + dst0 + k;
         if (lane < kDescBits / 64) D->bits[lane] = mine;
         if (lane == kDescBits / 64) {
             D->sector = (uint32_t)sector;
@@ -1372,6 +1378,89 @@ __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
         }
         __builtin_amdgcn_wave_barrier();   // V is reused by the wave's next feature
     }
+}
+
+// The levels of one frame as the single-frame arguments give them.
+struct DescLevels {
+    const DescArgs& a;
+    __device__ const uint8_t* ptr(int o) const { return a.lvl[o]; }
+    __device__ int pitch(int o) const { return a.pitch[o]; }
+    __device__ int w(int o) const { return a.w[o]; }
+    __device__ int h(int o) const { return a.h[o]; }
+};
+
+// One frame, a workgroup per cell: an unmarked cell's features are
+// D_{n-1}'s, copied; a marked cell's are new.
+__global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
+{
+    __shared__ int s_v[kDescBlock / 64][64];
+    __shared__ uint8_t s_patch[kDescBlock / 64][kPatch * kPatch];
+    const int c = blockIdx.x;
+    const uint32_t n = a.count_cur[c], dst0 = a.off_cur[c];
+    if (!a.mask[c]) {
+        copy_feature_records(a.desc_prev, a.tab ? a.desc_cur : nullptr, a.ref_prev, a.ref_cur, a.off_prev[c], dst0, n,
+                             a.list_cap);
+        return;
+    }
+    describe_entries(DescLevels{a}, a.tab, a.O, a.t, a.list_cur, a.desc_cur, a.ref_cur, dst0, n, a.list_cap, s_v,
+                     s_patch);
+}
+
+// The levels of chunk frame j: level 0 is the frame itself, the others its
+// octave copies.
+struct ChunkLevels {
+    const ChunkArgs& t;
+    const uint8_t* f0;
+    int p0;
+    __device__ const uint8_t* ptr(int o) const { return o == 0 ? f0 : t.d.lvl[o]; }
+    __device__ int pitch(int o) const { return o == 0 ? p0 : t.d.pitch[o]; }
+    __device__ int w(int o) const { return t.d.w[o]; }
+    __device__ int h(int o) const { return t.d.h[o]; }
+};
+
+// Features of a chunk's lists, a workgroup per (cell c, frame j), after
+// compaction. Frame j's list holds cell c's entries of the newest frame
+// f <= j that marked c, or of the list before the chunk when none did. So
+// when j marked c, the workgroup computes the features of those entries on
+// frame j's levels and copies them to every following frame up to c's next
+// mark; when no frame up to j marked c, it copies the records of the list
+// before the chunk; otherwise another workgroup writes them.
+__global__ __launch_bounds__(kDescBlock) void k_describe_chunk(DescChunkArgs a)
+{
+    __shared__ int s_v[kDescBlock / 64][64];
+    __shared__ uint8_t s_patch[kDescBlock / 64][kPatch * kPatch];
+    const int c = blockIdx.x, j = blockIdx.y;
+    const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
+    auto marked = [&](int f) { return ((mw[f >> 6] >> (f & 63)) & 1ull) != 0; };
+    const bool last = j == a.n_frames - 1;
+    auto list_of = [&](int f) { return f == a.n_frames - 1 ? a.last_list : a.lists + (size_t)f * a.list_stride; };
+    auto count_of = [&](int f) { return f == a.n_frames - 1 ? a.last_count[c] : a.counts[(size_t)f * a.ncell + c]; };
+    auto off_of = [&](int f) { return f == a.n_frames - 1 ? a.last_offs[c] : a.offs[(size_t)f * a.ncell + c]; };
+    auto desc_of = [&](int f) -> kpd_descriptor* {
+        if (!a.tab) return nullptr;
+        return f == a.n_frames - 1 ? a.last_desc : a.descs + (size_t)f * a.list_stride;
+    };
+    auto ref_of = [&](int f) -> kpd_refined* {
+        if (!a.refs) return nullptr;
+        return f == a.n_frames - 1 ? a.last_ref : a.refs + (size_t)f * a.list_stride;
+    };
+    const uint32_t n = count_of(j), dst0 = off_of(j);
+    if (!marked(j)) {
+        // carried from before the chunk when no frame up to j marked c
+        const int qj = j >> 6;
+        const unsigned long long upto = (2ull << (j & 63)) - 1ull;   // bit 63 is j's own, unset here
+        for (int q = 0; q <= qj; ++q)
+            if ((q < qj ? mw[q] : mw[q] & upto) != 0ull) return;
+        copy_feature_records(a.prev_desc, desc_of(j), a.prev_ref, ref_of(j), a.prev_offs[c], dst0, n, a.list_cap);
+        return;
+    }
+    const ChunkArgs& t = a.table[j];
+    describe_entries(ChunkLevels{t, a.frames + (size_t)j * a.stride, a.pitch}, a.tab, a.O, a.t, list_of(j), desc_of(j),
+                     ref_of(j), dst0, n, a.list_cap, s_v, s_patch);
+    if (last) return;
+    __syncthreads();   // the records just written are the copies' source
+    for (int f = j + 1; f < a.n_frames && !marked(f); ++f)
+        copy_feature_records(desc_of(j), desc_of(f), ref_of(j), ref_of(f), dst0, off_of(f), count_of(f), a.list_cap);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by index. The tile pass
@@ -2118,6 +2207,12 @@ hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStrea
 hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s)
 {
     hipLaunchKernelGGL(k_describe1, dim3(ncell), dim3(kDescBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_describe_chunk(const DescChunkArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_describe_chunk, dim3(a.ncell, a.n_frames), dim3(kDescBlock), 0, s, a);
     return hipGetLastError();
 }
 

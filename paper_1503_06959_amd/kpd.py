@@ -37,7 +37,7 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "batch_attach", "batch_detach", "batch_push", "batch_push_many", "batch_tick", "batch_gather",
             "close_batch",
             "push_frames", "kpd_chunk_result", "get_chunk_keypoints", "set_mask_mode", "get_descriptors",
-            "kpd_desc_point", "get_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
+            "kpd_desc_point", "get_refined", "get_chunk_descriptors", "get_chunk_refined", "tcd_bytes", "tcd_open", "tcd_push", "tcd_get",
             "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
             "kpd_detect_layers_static", "batch_set_single_launch",
             "kpd_layer_plane", "kpd_refine_layers", "kpd_lstream_bytes", "kpd_lstream_open", "kpd_lstream_push",
@@ -111,6 +111,8 @@ def _load() -> ctypes.CDLL:
     L.set_mask_mode.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.get_descriptors.argtypes = [P, P, sz, ctypes.POINTER(sz)]
     L.get_refined.argtypes = [P, P, sz, ctypes.POINTER(sz)]
+    L.get_chunk_descriptors.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
+    L.get_chunk_refined.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
     L.kpd_layers_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.kpd_layers_bytes.restype = sz
     L.kpd_detect_layers.argtypes = [P, sz, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, sz, P, u32, P, P]
@@ -272,6 +274,17 @@ def get_refined(handle: int, capacity: int = 4096) -> np.ndarray:
     return _get_features(lib.get_refined, REFINED_DTYPE, handle, capacity)
 
 
+def get_chunk_descriptors(handle: int, i: int, capacity: int = 4096) -> np.ndarray:
+    """Descriptors of frame i of the last chunk, in get_chunk_keypoints' order."""
+    return _get_features(lambda h, o, n, c: lib.get_chunk_descriptors(h, i, o, n, c), DESCRIPTOR_DTYPE, handle,
+                         capacity)
+
+
+def get_chunk_refined(handle: int, i: int, capacity: int = 4096) -> np.ndarray:
+    """Refined values of frame i of the last chunk, in get_chunk_keypoints' order."""
+    return _get_features(lambda h, o, n, c: lib.get_chunk_refined(h, i, o, n, c), REFINED_DTYPE, handle, capacity)
+
+
 def desc_point(sector: int, i: int) -> Tuple[int, int, int]:
     """(dx, dy, box half-size) of the library's descriptor pattern point i
     turned to `sector`."""
@@ -414,6 +427,12 @@ class Stream:
 
     def chunk_keypoints(self, i: int) -> np.ndarray:
         return get_chunk_keypoints(self.handle, i)
+
+    def chunk_descriptors(self, i: int) -> np.ndarray:
+        return get_chunk_descriptors(self.handle, i)
+
+    def chunk_refined(self, i: int) -> np.ndarray:
+        return get_chunk_refined(self.handle, i)
 
     def set_thresholds(self, fast_t: int, id_thresh: int, kb_thresh: int = KPD_KB_OFF) -> None:
         set_thresholds(self.handle, fast_t, id_thresh, kb_thresh)

@@ -112,13 +112,19 @@ def test_descriptor_errors(kpd):
     with pytest.raises(kpd.KpdError):
         g.set_mask_mode(1, 2)                          # descriptors keep the per-cell mask
     with pytest.raises(kpd.KpdError):
-        g.push_chunk(torch.from_numpy(frames).cuda())  # single-frame pushes only
+        g.chunk_descriptors(0)                         # no chunk pushed yet
     g.push(frames[0])
     assert len(g.descriptors()) == len(g.keypoints()[0])
     kpd.profile(g.handle, True)
     g.push(frames[1])
     ms, n = kpd.profile_read(g.handle)
     assert list(n) == [1, 1, 1, 0, 1]
+    g.push_chunk(torch.from_numpy(frames[1:3]).cuda())
+    assert len(g.chunk_descriptors(0)) == len(g.chunk_keypoints(0))
+    with pytest.raises(kpd.KpdError):
+        g.chunk_descriptors(2)                         # the chunk had two frames
+    with pytest.raises(kpd.KpdError):
+        g.chunk_refined(0)                             # opened without refinement
     g.close()
     plain = kpd.Stream(320, 240, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows))
     plain.push(frames[0])
