@@ -92,9 +92,9 @@ extern "C" {
  *              others (Sec. 3, Eq. 1): KPD_FEAT_DESCRIPTOR, an orientation
  *              sector and a 512-bit binary descriptor (get_descriptors);
  *              KPD_FEAT_REFINE, the sub-pixel position and sub-scale of
- *              Sec. 2's interpolation (get_refined). push_frame and
- *              push_frames (get_chunk_descriptors, get_chunk_refined),
- *              mask mode 0. 0: nothing.
+ *              Sec. 2's interpolation (get_refined). push_frame,
+ *              push_frames (get_chunk_descriptors, get_chunk_refined) and
+ *              batch ticks, mask mode 0. 0: nothing.
  *   group_cols, group_rows
  *              cells one detection workgroup covers when a chunk's
  *              parameters mark every cell (full-frame detection): a
@@ -287,7 +287,9 @@ const char* kpd_last_error(void);
  * tick is four launches (tile passes; marks with the marked cells listed;
  * detection of the listed cells; each stream's D_n by Eq. 1);
  * batch_set_single_launch(b, 1) makes it one launch of co-resident
- * workgroups whose phases are separated by device-wide barriers. Results
+ * workgroups whose phases are separated by device-wide barriers. When an
+ * attached stream computes features (descriptors or refined values), one
+ * more launch follows that computes them for every such stream. Results
  * are exactly those of pushing each stream's frame alone. */
 typedef struct kpd_batch kpd_batch;
 

@@ -7,6 +7,7 @@ tick runs the next frame of every stream that staged one, in four launches
 (or, after set_single_launch(True), one launch of co-resident workgroups
 whose phases are separated by device-wide barriers), captured once as a HIP
 graph and replayed while the set of attached streams stays the same.
+Streams that compute descriptors or refined values add one launch per tick.
 """
 from __future__ import annotations
 

@@ -866,6 +866,15 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
     t->own_count = s->at<uint32_t>(L.off_own1);
     t->glay1 = s->at<kpd::GroupLayout>(L.off_glay1);
     t->al8 = (reinterpret_cast<uintptr_t>(cur) % 8 == 0 && cur_pitch % 8 == 0) ? 1 : 0;
+    if (s->p.features & KPD_FEAT_DESCRIPTOR) {
+        t->tab = s->at<kpd::DescTables>(L.off_dtab);
+        t->desc_prev = s->at<kpd_descriptor>(L.off_desc[fb_prev]);
+        t->desc_cur = s->at<kpd_descriptor>(L.off_desc[fb_cur]);
+    }
+    if (s->p.features & KPD_FEAT_REFINE) {
+        t->ref_prev = s->at<kpd_refined>(L.off_ref[fb_prev]);
+        t->ref_cur = s->at<kpd_refined>(L.off_ref[fb_cur]);
+    }
 
     kpd::DetectArgs& d = t->d;
     d.lvl[0] = cur;
@@ -1494,6 +1503,7 @@ struct kpd_batch {
     bool single_launch = false;
     kpd::TickSync* dev_sync = nullptr;
     int tick_lds = 16, tick_grid = 0;
+    bool features = false;   // an attached stream computes descriptors or refined values
     bool maps_dirty = true;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     uint64_t ticks = 0;
@@ -1529,8 +1539,10 @@ int rebuild_maps(kpd_batch* b)
 {
     std::vector<uint16_t> fmap, cmap;
     int fl = 16, dl = 16, gl = 16;
+    bool feats = false;
     for (size_t i = 0; i < b->streams.size(); ++i) {
         const Layout& L = b->streams[i]->L;
+        feats = feats || b->streams[i]->p.features != 0;
         const int nt = L.tiles_x * L.tiles_y;
         fmap.insert(fmap.end(), (size_t)nt, (uint16_t)i);
         cmap.insert(cmap.end(), (size_t)L.ncell, (uint16_t)i);
@@ -1549,6 +1561,7 @@ int rebuild_maps(kpd_batch* b)
     b->frame_lds = fl;
     b->detect_lds = dl;
     b->detect_glds = gl;
+    b->features = feats;
     // the single-launch tick: as many workgroups as there are items, at most
     // what the device holds at once, a multiple of the XCD count
     b->tick_lds = std::max(fl, gl);
@@ -1562,7 +1575,8 @@ int rebuild_maps(kpd_batch* b)
 }
 
 // Enqueue one tick reading table k: upload, tile pass, mark pass, detection
-// of the marked cells, compaction of every stream's D_n.
+// of the marked cells, compaction of every stream's D_n (or the one launch
+// that does all four); then, when a stream asks for them, the features.
 hipError_t enqueue_tick(kpd_batch* b, int k)
 {
     const size_t n = b->streams.size();
@@ -1572,6 +1586,8 @@ hipError_t enqueue_tick(kpd_batch* b, int k)
         if (e == hipSuccess)
             e = kpd::launch_tick(b->dev_table[k], b->dev_fmap, b->frame_blocks, b->dev_cmap, b->cell_blocks, (int)n,
                                  b->dev_sync, k, b->tick_grid, b->tick_lds, b->stream);
+        if (e == hipSuccess && b->features && b->cell_blocks)
+            e = kpd::launch_describe_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->stream);
         return e;
     }
     if (e == hipSuccess && b->frame_blocks)
@@ -1584,6 +1600,8 @@ hipError_t enqueue_tick(kpd_batch* b, int k)
                                                  b->dev_work_count, b->detect_glds, b->stream);
     if (e == hipSuccess && n)
         e = kpd::launch_compact_batch(b->dev_table[k], (int)n, b->dev_work_count, b->stream);
+    if (e == hipSuccess && b->features && b->cell_blocks)
+        e = kpd::launch_describe_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->stream);
     return e;
 }
 
@@ -1652,7 +1670,6 @@ int batch_attach(kpd_batch* b, kpd_stream* s)
 {
     if (!b || !s || s->closed) return fail(KPD_ESTATE, "batch or stream is closed");
     if (s->stream != b->stream) return fail(KPD_EINVAL, "stream was opened on another HIP stream");
-    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on push_frame and push_frames only");
     if (std::find(b->streams.begin(), b->streams.end(), s) != b->streams.end())
         return fail(KPD_EINVAL, "stream already attached");
     if ((int)b->streams.size() >= b->max_streams) return fail(KPD_ENOMEM, "batch stream capacity exceeded");
@@ -1699,7 +1716,6 @@ int batch_stage(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_
     *hint = i + 1;
     if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
     if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
-    if (s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run on push_frame and push_frames only");
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
     if (rc != KPD_OK) return rc;
     b->has_frame[i] = 1;

@@ -136,6 +136,13 @@ struct TickArgs {
     // level 0 can be read 8 bytes at a time (the single-launch tick)
     const GroupLayout* glay1;
     int al8;
+    // features of D_n (null when the stream computes none): as DescArgs's,
+    // with the levels, mask, lists, counts and offsets of d
+    const DescTables* tab;
+    const kpd_descriptor* desc_prev;
+    kpd_descriptor* desc_cur;
+    const kpd_refined* ref_prev;
+    kpd_refined* ref_cur;
 };
 
 // Counters of the single-launch tick: arrivals at its two device-wide
@@ -296,6 +303,7 @@ hipError_t launch_frame(const FrameArgs& a, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s);
 hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s);
 hipError_t launch_describe_chunk(const DescChunkArgs& a, hipStream_t s);
+hipError_t launch_describe_batch(const TickArgs* table, const uint16_t* map, int ncells, hipStream_t s);
 hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, uint32_t out_cap, uint32_t* counts,
                                hipStream_t s);

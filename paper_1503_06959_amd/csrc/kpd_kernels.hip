@@ -1406,6 +1406,37 @@ __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
                      s_patch);
 }
 
+// The levels of a batch tick's stream, from its detection arguments.
+struct TickLevels {
+    const DetectArgs& d;
+    __device__ const uint8_t* ptr(int o) const { return d.lvl[o]; }
+    __device__ int pitch(int o) const { return d.pitch[o]; }
+    __device__ int w(int o) const { return d.w[o]; }
+    __device__ int h(int o) const { return d.h[o]; }
+};
+
+// Features of a batch tick after its compaction: workgroup g takes cell
+// g - cell_base of stream map[g], as k_describe1 does for one stream;
+// streams without a frame in the tick or without features are skipped.
+__global__ __launch_bounds__(kDescBlock) void k_describe_batch(const TickArgs* table, const uint16_t* map)
+{
+    __shared__ int s_v[kDescBlock / 64][64];
+    __shared__ uint8_t s_patch[kDescBlock / 64][kPatch * kPatch];
+    const int g = blockIdx.x;
+    const TickArgs& t = table[map[g]];
+    if (!t.active || (!t.tab && !t.ref_cur)) return;
+    const DetectArgs& d = t.d;
+    const int c = g - t.cell_base;
+    const uint32_t n = d.count_cur[c], dst0 = d.off_cur[c];
+    if (!d.mask[c]) {
+        copy_feature_records(t.desc_prev, t.tab ? t.desc_cur : nullptr, t.ref_prev, t.ref_cur, d.off_prev[c], dst0, n,
+                             d.list_cap);
+        return;
+    }
+    describe_entries(TickLevels{d}, t.tab, d.O, d.t, d.list_cur, t.desc_cur, t.ref_cur, dst0, n, d.list_cap, s_v,
+                     s_patch);
+}
+
 // The levels of chunk frame j: level 0 is the frame itself, the others its
 // octave copies.
 struct ChunkLevels {
@@ -2207,6 +2238,12 @@ hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStrea
 hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s)
 {
     hipLaunchKernelGGL(k_describe1, dim3(ncell), dim3(kDescBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_describe_batch(const TickArgs* table, const uint16_t* map, int ncells, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_describe_batch, dim3(ncells), dim3(kDescBlock), 0, s, table, map);
     return hipGetLastError();
 }
 

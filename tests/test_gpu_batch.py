@@ -27,24 +27,27 @@ def tuples(arr):
 
 
 def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode="retain", single=True,
-              lazy=False):
+              lazy=False, feats=lambda s: 0):
     """specs: list of (Scene, (t, O, Nc, Nr, TI, TH, tile)). Every tick each
     stream not skipped pushes its next frame; after the tick every stream's
     D_n and mask are compared with its oracle. single: one launch per tick
     (else four); lazy: the oracle's CPU-masked mode (equal to its
-    definitional mode, pinned on the CPU)."""
+    definitional mode, pinned on the CPU); feats(s): stream s's features
+    (FEAT_* bits), compared with its oracle's after every tick."""
     import torch
     from paper_1503_06959_amd.batch import Batch
     b = Batch(max_streams=len(specs) + 2, use_graph=use_graph)
     b.set_single_launch(single)
     streams = []
-    for sc, det in specs:
+    for si, (sc, det) in enumerate(specs):
         t, O, Nc, Nr, TI, TH, tile = det
         frames = synth.make_video(sc, n_ticks)
-        g = b.open_stream(sc.width, sc.height, kpd.make_params(t, O, Nc, Nr, TI, TH, tile))
+        g = b.open_stream(sc.width, sc.height, kpd.make_params(t, O, Nc, Nr, TI, TH, tile, features=feats(si)))
         o = oracle.Stream(sc.width, sc.height, t, O, Nc, Nr, TI, TH)
         if lazy:
             o.set_lazy(True)
+        o.set_descriptors(bool(feats(si) & kpd.FEAT_DESCRIPTOR))
+        o.set_refine(bool(feats(si) & kpd.FEAT_REFINE))
         dev = torch.from_numpy(frames).cuda() if mode != "host" else None
         streams.append(dict(g=g, o=o, frames=frames, dev=dev, next=0))
     torch.cuda.synchronize()
@@ -75,6 +78,17 @@ def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode
             ok, om, _, _ = st["o"].get()
             assert tuples(gk) == tuples(ok), f"stream {si} tick {tick}"
             np.testing.assert_array_equal(gm, om, err_msg=f"mask stream {si} tick {tick}")
+            if feats(si) & kpd.FEAT_DESCRIPTOR:
+                gd = st["g"].descriptors()
+                ob, od = st["o"].descriptors()
+                np.testing.assert_array_equal(gd["sector"].astype(np.int64), ob.astype(np.int64),
+                                              err_msg=f"sectors stream {si} tick {tick}")
+                np.testing.assert_array_equal(gd["bits"], od, err_msg=f"bits stream {si} tick {tick}")
+            if feats(si) & kpd.FEAT_REFINE:
+                gr = st["g"].refined()
+                got = np.stack([gr["x"], gr["y"], gr["log2_scale"], gr["score"]], axis=1).astype(np.float32)
+                np.testing.assert_array_equal(got.view(np.uint32), st["o"].refined().view(np.uint32),
+                                              err_msg=f"refined stream {si} tick {tick}")
     b.close()
     return streams
 
@@ -109,6 +123,15 @@ def test_streams_skipping_ticks(kpd, single):
 def test_streams_staged_in_one_call(kpd):
     # batch_push_many: every tick's frames in one call, with streams skipping ticks
     run_batch(kpd, mixed_specs(6, 4300), 6, mode="many", single=False, skip=lambda s, t: (s + t) % 3 == 0)
+
+
+@pytest.mark.parametrize("single", [True, False])
+def test_streams_with_features(kpd, single):
+    # descriptors, refined values, both or neither, by stream, with streams
+    # skipping ticks (their features must stay those of their last frame)
+    both = kpd.FEAT_DESCRIPTOR | kpd.FEAT_REFINE
+    run_batch(kpd, mixed_specs(8, 4400), 6, single=single, skip=lambda s, t: (s + t) % 4 == 0,
+              feats=lambda s: [both, 0, kpd.FEAT_DESCRIPTOR, kpd.FEAT_REFINE][s % 4])
 
 
 def test_tile_size_does_not_change_results(kpd):
