@@ -202,8 +202,10 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
  * every level, a feature at level o tested on level o's pixel (x, y). The
  * reported cell mask flags cells marked by T_H or holding a changed pixel
  * (of any level, replicated to level 0, in mode 2). Modes 1 and 2 run on
- * push_frame only: push_frames and batch_push return KPD_EINVAL while one
- * is set, and so does either mode on a stream opened without layer_mask. */
+ * push_frame and on push_frames (there with T_H off, KPD_KB_OFF, unless
+ * every cell is marked anyway: a chunk's per-pixel marks cannot depend on
+ * the counts of the frame before); batch_push returns KPD_EINVAL while one
+ * is set, and either mode does on a stream opened without layer_mask. */
 int set_mask_mode(kpd_stream* s, int mode, int layer);
 
 /* Orientation and binary descriptor of one feature (Sec. 3: a feature is

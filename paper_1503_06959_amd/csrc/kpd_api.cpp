@@ -83,6 +83,13 @@ struct Layout {
     // and a second buffer for octave 1.. so the layer of I_{n-1} survives
     int lds_bits = 0, lds_carr = 0, lds_cwoff = 0, lds_cscore = 0, lds_bytes1 = 0;
     size_t off_lvl_alt = 0;
+    // per-pixel masks in chunks (layer_mask streams): the cells' layer-pixel
+    // change bits (fpw words per frame and cell) and change flags, the
+    // merged lists (decision-pixel bases pbase), their counts, and the
+    // merge pass's LDS
+    int fpw = 0, nwords_max = 0, dc_max = 0;
+    size_t off_pflag = 0, off_fp = 0, off_msparse = 0, off_mcount = 0, off_pbase = 0;
+    int pm_pres = 0, pm_score = 0, pm_fp = 0, pm_lds = 0;
     // the group detector of full-frame chunks: gx x gy cells per workgroup
     // and the groups' layouts
     int gx = 1, gy = 1, ngroups = 0, glds = 0, gthreads = 256;
@@ -322,6 +329,13 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     }
     L->list_cap = std::max<size_t>(cap, 1);
     L->list_cap1 = p->layer_mask ? std::max<size_t>(dec_px, 1) : L->list_cap;
+    L->fpw = npx_max / 64;
+    L->nwords_max = nwords_max;
+    L->dc_max = (int)cell_cap_max;
+    L->pm_pres = 0;
+    L->pm_score = kpd::round_up(nwords_max * 8, 16);
+    L->pm_fp = kpd::round_up(L->pm_score + (int)cell_cap_max * 2, 16);
+    L->pm_lds = L->pm_fp + L->fpw * 8;
     if (L->list_cap1 > 0xFFFFFFF0ull) { *why = "keypoint list too large"; return false; }
     L->lds_bytes = std::max(lds, 16);
     {
@@ -416,12 +430,20 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->off_marks = off; off = align_up(off + (size_t)L->ncell * L->Kw * 8);
         L->off_own = off; off = align_up(off + kc * 4);
         L->off_work = off; off = align_up(off + kc * 4);
-        L->clist_stride = align_up(L->list_cap * sizeof(kpd_keypoint));
+        // with the per-pixel mask a frame's list may hold an entry per decision pixel
+        L->clist_stride = align_up((p->layer_mask ? L->list_cap1 : L->list_cap) * sizeof(kpd_keypoint));
         L->off_sparse = off; off += L->clist_stride * (size_t)L->K;
         L->off_clist = off; off += L->clist_stride * (size_t)(L->K - 1);   // the last frame's D goes to D_n
         const size_t centries = L->clist_stride / sizeof(kpd_keypoint) * (size_t)(L->K - 1);
         if (p->features & KPD_FEAT_DESCRIPTOR) { L->off_cdesc = off; off = align_up(off + centries * sizeof(kpd_descriptor)); }
         if (p->features & KPD_FEAT_REFINE) { L->off_cref = off; off = align_up(off + centries * sizeof(kpd_refined)); }
+        if (p->layer_mask) {
+            L->off_pflag = off; off = align_up(off + kc * 4);
+            L->off_fp = off; off = align_up(off + kc * (size_t)L->fpw * 8);
+            L->off_msparse = off; off += L->clist_stride * (size_t)L->K;
+            L->off_mcount = off; off = align_up(off + kc * 4);
+            L->off_pbase = off; off = align_up(off + (size_t)L->ncell * 4);
+        }
         L->off_ctab = off; off = align_up(off + (size_t)L->K * sizeof(kpd::ChunkArgs));
         L->off_glay = off; off = align_up(off + (size_t)L->ngroups * sizeof(kpd::GroupLayout));
     }
@@ -721,6 +743,14 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     const std::vector<uint32_t> cbase = cell_bases(L);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->arena + L.off_cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice, s->stream);
+    std::vector<uint32_t> pbase(L.ncell);   // per-pixel bases: the decision pixels of the cells before
+    uint32_t acc = 0;
+    for (int c = 0; c < L.ncell; ++c) {
+        pbase[c] = acc;
+        acc += (uint32_t)layouts[c].dc_start[L.O];
+    }
+    if (e == hipSuccess && L.off_pbase)
+        e = hipMemcpyAsync(s->arena + L.off_pbase, pbase.data(), pbase.size() * 4, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess && (params->features & KPD_FEAT_DESCRIPTOR))
         e = hipMemcpyAsync(s->arena + L.off_dtab, &desc_tables(), sizeof(kpd::DescTables), hipMemcpyHostToDevice,
                            s->stream);
@@ -1115,7 +1145,12 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     const Layout& L = s->L;
     if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
-    if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
+    // per-pixel masks (Sec. 3.1): their marks come from pixels alone, so T_H
+    // (whose marks chain through the counts frame by frame) must be off
+    const bool pixel = s->id_mode != 0;
+    if (pixel && s->p.kb_thresh != KPD_KB_OFF && s->p.kb_thresh != 0 && s->p.id_thresh >= 0)
+        return fail(KPD_EINVAL, "the layer mask in chunks needs kb_thresh off");
+    if (pixel && L.pm_lds > 60 * 1024) return fail(KPD_EINVAL, "cells too large for the layer mask in chunks");
     if (!frames) return fail(KPD_EINVAL, "frames is NULL");
     if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
@@ -1154,7 +1189,8 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     h.work = s->at<uint32_t>(L.off_work);
     h.work_count = s->at<uint32_t>(L.off_hdr) + kHdrWork;
     // the tile pass is needed for coarser octaves or intensity differences
-    const bool any_tiles = L.O > 1 || (s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
+    // (per-cell ones: the per-pixel masks read the octaves it writes)
+    const bool any_tiles = L.O > 1 || (!pixel && s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
                                        (n_frames > 1 || !h.force0));
     const kpd::ChunkArgs* ctab = s->at<kpd::ChunkArgs>(L.off_ctab);
     // frames that test intensity differences walk each tile in frame order
@@ -1170,9 +1206,17 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         s->seq_cap = std::max(cap, 1);
     }
     const int run = seq_run(L, n_frames, s->seq_cap);
-    const bool seq = run > 0 && s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
+    const bool seq = run > 0 && !pixel && s->p.id_thresh >= 0 && s->p.id_thresh < 255 && !h.all_marked &&
                      (n_frames > 1 || !h.force0) && al16(frames, pitch_bytes) && frame_stride % 16 == 0 &&
                      (h.force0 || al16(h.prev0, (size_t)h.prev0_pitch));
+    // the layers of the frame before the chunk that a per-pixel mask reads:
+    // kept in the second octave buffer (octave buffer 0 is chunk frame 0's)
+    const bool pixel_diff = pixel && !h.all_marked;
+    if (pixel_diff && !h.force0 && L.O > 1 && s->layer_buf == 0)
+        KPD_HIP(hipMemcpyAsync(s->arena + L.off_lvl_alt, s->arena + L.off_lvl[1], L.pyr_stride,
+                               hipMemcpyDeviceToDevice, s->stream));
+    kpd::ChunkHead ht = h;
+    if (pixel) ht.id_thresh = 255;   // no per-cell differences in the tile pass
     if (any_tiles)
         KPD_HIP(timed(s, KPD_K_FRAME, [&] {
             if (seq) {
@@ -1181,9 +1225,10 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
                 const kpd::SeqGrid g{L.seq_tile_w, L.seq_tiles_x, L.seq_ntiles, L.seq_slots, run};
                 return kpd::launch_frame_chunk_seq(s->chunk_fa, L.pyr_stride, h, g, nt, s->stream);
             }
-            return kpd::launch_frame_chunk(s->chunk_fa, L.pyr_stride, h, kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots),
-                                           s->stream);
+            return kpd::launch_frame_chunk(s->chunk_fa, L.pyr_stride, ht,
+                                           kpd::frame_lds_bytes(L.ctile, L.O, L.csad_slots), s->stream);
         }));
+    kpd::PixelChunkArgs pa{};
     if (h.all_marked) {
         // every cell of every frame: one workgroup per (frame, cell)
         kpd::GroupArgs ga{};
@@ -1207,7 +1252,62 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
                 return kpd::launch_detect_list_groups(ctab, h, g1, glds1_for(L, nt), nt, round, s->stream);
             });
         };
-        if (h.kb_chain) {
+        if (pixel_diff) {
+            pa.table = ctab;
+            pa.frames = frames;
+            pa.stride = frame_stride;
+            pa.pitch = pitch;
+            pa.prev_lvl[0] = h.prev0;
+            pa.prev_pitch[0] = h.prev0_pitch;
+            for (int o = 1; o < L.O; ++o) {
+                pa.prev_lvl[o] = alt_level(s, o);
+                pa.prev_pitch[o] = L.pitch[o];
+            }
+            pa.n_frames = n_frames;
+            pa.ncell = L.ncell;
+            pa.nc = L.nc;
+            pa.nr = L.nr;
+            pa.W = L.W;
+            pa.H = L.H;
+            pa.O = L.O;
+            pa.Kw = L.Kw;
+            pa.one = s->id_mode == 1 ? 1 : 0;
+            pa.l_lo = s->id_mode == 1 ? s->id_layer : 0;
+            pa.l_hi = s->id_mode == 1 ? s->id_layer : L.O - 1;
+            pa.id_thresh = s->p.id_thresh;
+            pa.force0 = h.force0;
+            pa.flags = s->at<uint32_t>(L.off_pflag);
+            pa.fp = s->at<unsigned long long>(L.off_fp);
+            pa.fpw = L.fpw;
+            pa.marks = h.marks;
+            pa.layouts = s->at<kpd::CellLayout>(L.off_layouts);
+            pa.cell_base = s->at<uint32_t>(L.off_cbase);
+            pa.list_cap = (uint32_t)L.list_cap;
+            pa.pbase = s->at<uint32_t>(L.off_pbase);
+            pa.merged = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_msparse);
+            pa.mcount = s->at<uint32_t>(L.off_mcount);
+            pa.list_stride = L.clist_stride / sizeof(kpd_keypoint);
+            pa.plist_cap = (uint32_t)L.list_cap1;
+            pa.prev_list = s->at<kpd_keypoint>(L.off_list[fb_prev]);
+            pa.prev_count = s->at<uint32_t>(L.off_count[fb_prev]);
+            pa.prev_offs = s->at<uint32_t>(L.off_offs[fb_prev]);
+            pa.prev_cap = (uint32_t)L.list_cap1;
+            pa.lds_pres = L.pm_pres;
+            pa.lds_score = L.pm_score;
+            pa.lds_fp = L.pm_fp;
+            pa.lds_bytes = L.pm_lds;
+        }
+        if (pixel_diff) {
+            // changed mask pixels, marks of the cells with one, detection of
+            // those cells, then Eq. 1 per feature along each cell's frames
+            kpd::ChunkHead hm = h;
+            hm.sad0 = pa.flags;
+            hm.id_thresh = 0;   // a cell is marked when its change flag is above 0
+            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_pixel_diff_chunk(pa, s->stream); }));
+            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(hm, s->stream); }));
+            KPD_HIP(detect(0));
+            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_pixel_merge_chunk(pa, s->stream); }));
+        } else if (h.kb_chain) {
             // marks that depend on the counts: detect every frame a cell's
             // chain can mark, then walk each cell's frames to keep the marks
             const uint32_t* own = s->at<uint32_t>(L.off_own);
@@ -1248,6 +1348,13 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     ca.sad_stats = s->at<uint32_t>(L.off_sad[n_last & 1]);
     ca.sad_single_next = s->at<uint32_t>(L.off_sad[(n_last + 1) & 1]);
     ca.work_count = h.work_count;
+    if (pixel_diff) {
+        // the merged lists: one entry per decision pixel at most
+        ca.sparse = pa.merged;
+        ca.cell_base = pa.pbase;
+        ca.own_count = pa.mcount;
+        ca.list_cap = (uint32_t)L.list_cap1;
+    }
     KPD_HIP(timed(s, KPD_K_COMPACT, [&] { return kpd::launch_compact_chunk(ca, n_frames, s->stream); }));
     if (s->p.features) {
         // features of every frame's list: computed where a frame marked a
@@ -1290,6 +1397,18 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     s->prev0 = last;
     s->prev_pitch = pitch;
     s->prev_dw = dword_readable(last, pitch, L.W, false);
+    if (pixel && L.O > 1) {
+        // the last frame's octaves are I_{n-1}'s for the next push: octave
+        // buffer 0 holds them after a one-frame chunk, else they go to the
+        // second buffer
+        if (n_frames > 1) {
+            KPD_HIP(hipMemcpyAsync(s->arena + L.off_lvl_alt, s->arena + L.off_lvl[1] + L.pyr_stride * (n_frames - 1),
+                                   L.pyr_stride, hipMemcpyDeviceToDevice, s->stream));
+            s->layer_buf = 1;
+        } else {
+            s->layer_buf = 0;
+        }
+    }
     s->force_all = false;
     s->n_pushed += n_frames;
     s->fb_last = fb_next;

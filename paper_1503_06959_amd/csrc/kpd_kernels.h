@@ -252,6 +252,47 @@ struct DescChunkArgs {
     const uint32_t* prev_offs;
 };
 
+// Per-pixel masks in chunks (Sec. 3.1, Eq. 2 per pixel): mode 1 reads one
+// layer for every octave, mode 2 each octave on its own level. The diff
+// pass records, per (frame j, cell c), the changed pixels of the layers the
+// cell's level-0 pixels map to and whether any changed; the mark pass lists
+// the (frame, cell) items with a change; the listed detection writes F_j of
+// those cells; the merge pass walks each cell's listed frames in order and
+// applies Eq. 1 per feature, writing the cell's D_j at its per-pixel base.
+struct PixelChunkArgs {
+    const ChunkArgs* table;                     // frame j: octaves 1.., level sizes, F list and counts
+    const uint8_t* frames;                      // level 0 of frame j at frames + j * stride
+    size_t stride;
+    int pitch;
+    const uint8_t* prev_lvl[KPD_MAX_OCTAVES];   // the frame before the chunk (level 0: the frame itself)
+    int prev_pitch[KPD_MAX_OCTAVES];
+    int n_frames, ncell, nc, nr, W, H, O, Kw;
+    int l_lo, l_hi;                             // layers that hold mask pixels
+    int one;                                    // 1: layer l_lo masks every octave; 0: octave o on level o
+    int id_thresh;
+    int force0;                                 // frame 0 detects everything and carries nothing
+    uint32_t* flags;                            // frames x cells: a mask pixel of the cell changed
+    unsigned long long* fp;                     // frames x cells x fpw: changed bits of the cell's layer pixels
+    int fpw;
+    const unsigned long long* marks;            // cells x Kw mark words (bit j = frame j)
+    const CellLayout* layouts;
+    const uint32_t* cell_base;                  // F lists' bases
+    uint32_t list_cap;                          // F lists' entries
+    const uint32_t* pbase;                      // merged lists' bases (decision pixels of the earlier cells)
+    kpd_keypoint* merged;                       // frame j's at merged + j * list_stride
+    uint32_t* mcount;                           // frames x cells
+    size_t list_stride;
+    uint32_t plist_cap;                         // merged lists' entries
+    const kpd_keypoint* prev_list;              // D before the chunk, its counts and offsets
+    const uint32_t* prev_count;
+    const uint32_t* prev_offs;
+    uint32_t prev_cap;
+    int lds_pres, lds_score, lds_fp, lds_bytes; // dynamic LDS of the merge pass
+};
+
+hipError_t launch_pixel_diff_chunk(const PixelChunkArgs& a, hipStream_t s);
+hipError_t launch_pixel_merge_chunk(const PixelChunkArgs& a, hipStream_t s);
+
 // The group detector: the groups' layouts (a rectangle of cells each,
 // row-major over the group grid; each layout names its cells and their
 // list bases) and whether level 0's rows can be read 8 bytes at a time.

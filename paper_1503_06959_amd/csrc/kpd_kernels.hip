@@ -2025,6 +2025,244 @@ __global__ __launch_bounds__(kCompact) void k_compact_chunk(CompactArgs a)
     if (j == 0 && threadIdx.x == 0) a.work_count[0] = a.work_count[1] = 0;
 }
 
+// ------------------------------------------------ per-pixel masks in chunks
+
+// Layer l of chunk frame j (j = -1: the frame before the chunk).
+__device__ __forceinline__ const uint8_t* pixel_layer(const PixelChunkArgs& a, int j, int l, int* pitch)
+{
+    if (j < 0) {
+        *pitch = a.prev_pitch[l];
+        return a.prev_lvl[l];
+    }
+    if (l == 0) {
+        *pitch = a.pitch;
+        return a.frames + (size_t)j * a.stride;
+    }
+    *pitch = a.table[j].d.pitch[l];
+    return a.table[j].d.lvl[l];
+}
+
+// The layer pixels cell rectangle r maps to on a layer of lw x lh: its
+// level-0 pixels shifted down by l, clamped into the layer.
+struct LayerSpan {
+    int kx0, ky0, nx, npx;
+};
+
+__device__ __forceinline__ LayerSpan layer_span(const Box& r, int l, int lw, int lh)
+{
+    const int kx0 = min(r.x0 >> l, lw - 1), kx1 = min((r.x1 - 1) >> l, lw - 1);
+    const int ky0 = min(r.y0 >> l, lh - 1), ky1 = min((r.y1 - 1) >> l, lh - 1);
+    return LayerSpan{kx0, ky0, kx1 - kx0 + 1, (kx1 - kx0 + 1) * (ky1 - ky0 + 1)};
+}
+
+// A wave per (frame j, cell c): the changed bits (|I_j - I_{j-1}| > T_I on
+// the mask layers) of the layer pixels of the cell, each layer's bits
+// starting at a multiple of 64, and whether any is set. A forced frame 0
+// marks every cell without reading the frame before.
+constexpr int kDiffWaves = 4;
+
+__global__ __launch_bounds__(64 * kDiffWaves) void k_pixel_diff_chunk(PixelChunkArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int item = blockIdx.x * kDiffWaves + (threadIdx.x >> 6);
+    if (item >= a.n_frames * a.ncell) return;
+    const int j = item / a.ncell, c = item - j * a.ncell;
+    if (a.force0 && j == 0) {
+        if (lane == 0) a.flags[item] = 0u;
+        return;
+    }
+    const DetectArgs& d = a.table[j].d;
+    const Box r = cell_rect(c, a.W, a.H, a.nc, a.nr);
+    unsigned long long* fp = a.fp + (size_t)item * a.fpw;
+    bool any = false;
+    int boff = 0;
+    for (int l = a.l_lo; l <= a.l_hi; ++l) {
+        const LayerSpan sp = layer_span(r, l, d.w[l], d.h[l]);
+        int cp, pp;
+        const uint8_t* cur = pixel_layer(a, j, l, &cp);
+        const uint8_t* prv = pixel_layer(a, j - 1, l, &pp);
+        for (int base = 0; base < sp.npx; base += 64) {
+            const int i = base + lane;
+            bool ch = false;
+            if (i < sp.npx) {
+                const int ry = i / sp.nx, rx = i - ry * sp.nx;
+                const int vc = cur[(size_t)(sp.ky0 + ry) * cp + sp.kx0 + rx];
+                const int vp = prv[(size_t)(sp.ky0 + ry) * pp + sp.kx0 + rx];
+                ch = abs(vc - vp) > a.id_thresh;
+            }
+            const uint64_t bal = __ballot(ch);
+            if (lane == 0) fp[(boff + base) >> 6] = bal;
+            any = any || bal != 0;
+        }
+        boff += (sp.npx + 63) & ~63;
+    }
+    if (lane == 0) a.flags[item] = any ? 1u : 0u;
+}
+
+// A workgroup per cell walks the cell's listed frames in order, holding
+// D_j of the cell as a map over its decision pixels (a presence bit and a
+// score each) in LDS: at frame j the entries whose mask pixel changed are
+// dropped, F_j's maxima whose mask pixel changed are added (Eq. 1 per
+// feature; a forced frame replaces everything), and the map is written in
+// decision order, (octave, y, x), at the cell's per-pixel base of frame j's
+// merged list. The map starts from the cell's entries before the chunk.
+constexpr int kMergeBlock = 256;
+
+__global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArgs a)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    __shared__ CellLayout L;
+    __shared__ int s_kx0[KPD_MAX_OCTAVES], s_ky0[KPD_MAX_OCTAVES], s_nx[KPD_MAX_OCTAVES], s_boff[KPD_MAX_OCTAVES];
+    __shared__ int s_w[KPD_MAX_OCTAVES], s_h[KPD_MAX_OCTAVES];
+    __shared__ uint32_t s_part[kMergeBlock / 64];
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    unsigned long long* pres = reinterpret_cast<unsigned long long*>(sm + a.lds_pres);
+    uint16_t* score = reinterpret_cast<uint16_t*>(sm + a.lds_score);
+    unsigned long long* fpb = reinterpret_cast<unsigned long long*>(sm + a.lds_fp);
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
+        for (int i = tid; i < (int)(sizeof(CellLayout) / 4); i += kMergeBlock) dst[i] = src[i];
+    }
+    if (tid == 0) {
+        const Box r = cell_rect(c, a.W, a.H, a.nc, a.nr);
+        const DetectArgs& d = a.table[0].d;
+        int boff = 0;
+        for (int l = 0; l < KPD_MAX_OCTAVES; ++l) {
+            s_w[l] = d.w[l];
+            s_h[l] = d.h[l];
+            s_kx0[l] = s_ky0[l] = s_nx[l] = s_boff[l] = 0;
+            if (l < a.l_lo || l > a.l_hi) continue;
+            const LayerSpan sp = layer_span(r, l, d.w[l], d.h[l]);
+            s_kx0[l] = sp.kx0;
+            s_ky0[l] = sp.ky0;
+            s_nx[l] = sp.nx;
+            s_boff[l] = boff;
+            boff += (sp.npx + 63) & ~63;
+        }
+    }
+    __syncthreads();
+    const int nw = L.nwords, O = a.O;
+    for (int w = tid; w < nw; w += kMergeBlock) pres[w] = 0ull;
+    __syncthreads();
+    // decision index of (o, x, y), -1 outside the cell's decision box
+    auto index_of = [&](int o, int x, int y) -> int {
+        if (o >= O) return -1;
+        const Box d = L.dec[o];
+        if (x < d.x0 || x >= d.x1 || y < d.y0 || y >= d.y1) return -1;
+        return L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
+    };
+    // the mask pixel of a feature at level o, (x, y) changed in this frame
+    auto changed_at = [&](int o, int x, int y) -> bool {
+        const int l = a.one ? a.l_lo : o;
+        const int kx = min((x << o) >> l, s_w[l] - 1) - s_kx0[l];
+        const int ky = min((y << o) >> l, s_h[l] - 1) - s_ky0[l];
+        const int i = s_boff[l] + ky * s_nx[l] + kx;
+        return ((fpb[i >> 6] >> (i & 63)) & 1ull) != 0ull;
+    };
+    if (!a.force0) {
+        const uint32_t n0 = a.prev_count[c], src0 = a.prev_offs[c];
+        for (uint32_t e = tid; e < n0; e += kMergeBlock) {
+            if (src0 + e >= a.prev_cap) break;
+            const kpd_keypoint kp = a.prev_list[src0 + e];
+            const int i = index_of(kp.octave, kp.x, kp.y);
+            if (i < 0) continue;
+            atomicOr(&pres[i >> 6], 1ull << (i & 63));
+            score[i] = kp.score;
+        }
+    }
+    __syncthreads();
+    const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
+    const uint32_t cb = a.cell_base[c], pb = a.pbase[c];
+    for (int q = 0; q < a.Kw; ++q) {
+        unsigned long long word = mw[q];
+        if (q == (a.n_frames - 1) >> 6 && ((a.n_frames - 1) & 63) != 63)
+            word &= (2ull << ((a.n_frames - 1) & 63)) - 1ull;   // frames of this chunk only
+        if (q > (a.n_frames - 1) >> 6) word = 0ull;
+        while (word) {
+            const int j = 64 * q + __builtin_ctzll(word);
+            word &= word - 1ull;
+            const bool forced = a.force0 && j == 0;
+            if (!forced) {
+                const unsigned long long* src = a.fp + ((size_t)j * a.ncell + c) * a.fpw;
+                for (int w = tid; w < a.fpw; w += kMergeBlock) fpb[w] = src[w];
+            }
+            __syncthreads();
+            // entries whose mask pixel changed leave (all, when forced)
+            for (int w = tid; w < nw; w += kMergeBlock) {
+                unsigned long long k = pres[w], out = forced ? 0ull : k;
+                while (k && !forced) {
+                    const int b = __builtin_ctzll(k);
+                    k &= k - 1ull;
+                    const int i = w * 64 + b;
+                    const int o = level_of(L.dc_start, O, i);
+                    const unsigned r = (unsigned)(i - L.dc_start[o]);
+                    const Box d = L.dec[o];
+                    const int ry = (int)fast_div(r, L.dcm[o]);
+                    if (changed_at(o, d.x0 + (int)r - ry * box_w(d), d.y0 + ry)) out &= ~(1ull << b);
+                }
+                pres[w] = out;
+            }
+            __syncthreads();
+            // F_j's maxima whose mask pixel changed come in
+            const ChunkArgs& t = a.table[j];
+            const uint32_t nf = cb >= a.list_cap ? 0u : min(t.own_count[c], a.list_cap - cb);
+            for (uint32_t e = tid; e < nf; e += kMergeBlock) {
+                const kpd_keypoint kp = t.d.list_cur[cb + e];
+                const int i = index_of(kp.octave, kp.x, kp.y);
+                if (i < 0 || !(forced || changed_at(kp.octave, kp.x, kp.y))) continue;
+                atomicOr(&pres[i >> 6], 1ull << (i & 63));
+                score[i] = kp.score;
+            }
+            __syncthreads();
+            // D_j of the cell in decision order
+            uint32_t excl = 0, total = 0;
+            for (int w0 = 0; w0 < nw; w0 += kMergeBlock) {
+                const int w = w0 + tid;
+                const unsigned long long bits = w < nw ? pres[w] : 0ull;
+                const uint32_t cnt = (uint32_t)__popcll(bits);
+                uint32_t incl = cnt;
+                for (int dd = 1; dd < 64; dd <<= 1) {
+                    const uint32_t v = __shfl_up(incl, dd);
+                    if (lane >= dd) incl += v;
+                }
+                if (lane == 63) s_part[wave] = incl;
+                __syncthreads();
+                uint32_t before = total, sum = 0;
+                for (int k = 0; k < kMergeBlock / 64; ++k) {
+                    if (k < wave) before += s_part[k];
+                    sum += s_part[k];
+                }
+                excl = before + incl - cnt;
+                kpd_keypoint* dst = a.merged + (size_t)j * a.list_stride + pb;
+                unsigned long long k = bits;
+                uint32_t at = excl;
+                while (k) {
+                    const int b = __builtin_ctzll(k);
+                    k &= k - 1ull;
+                    const int i = w * 64 + b;
+                    const int o = level_of(L.dc_start, O, i);
+                    const unsigned r = (unsigned)(i - L.dc_start[o]);
+                    const Box d = L.dec[o];
+                    const int ry = (int)fast_div(r, L.dcm[o]);
+                    kpd_keypoint kp;
+                    kp.x = (uint16_t)(d.x0 + (int)r - ry * box_w(d));
+                    kp.y = (uint16_t)(d.y0 + ry);
+                    kp.octave = (uint8_t)o;
+                    kp.pad = 0;
+                    kp.score = score[i];
+                    if (pb + at < a.plist_cap) dst[at] = kp;
+                    ++at;
+                }
+                total += sum;
+                __syncthreads();   // s_part is reused
+            }
+            if (tid == 0) a.mcount[(size_t)j * a.ncell + c] = total;
+        }
+    }
+}
+
 // One batch tick: workgroup b works for stream map[b] (streams' workgroups
 // are contiguous and in stream order); inactive streams' workgroups exit.
 // Tiles are banded over the XCDs across the whole grid, as in k_frame1.
@@ -2238,6 +2476,20 @@ hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStrea
 hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s)
 {
     hipLaunchKernelGGL(k_describe1, dim3(ncell), dim3(kDescBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pixel_diff_chunk(const PixelChunkArgs& a, hipStream_t s)
+{
+    const int items = a.n_frames * a.ncell;
+    hipLaunchKernelGGL(k_pixel_diff_chunk, dim3((items + kDiffWaves - 1) / kDiffWaves), dim3(64 * kDiffWaves), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pixel_merge_chunk(const PixelChunkArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pixel_merge_chunk, dim3(a.ncell), dim3(kMergeBlock), a.lds_bytes, s, a);
     return hipGetLastError();
 }
 

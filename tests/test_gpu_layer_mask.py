@@ -151,6 +151,11 @@ def test_layer_readback_and_errors(kpd):
             ref = oracle.pyramid(f, d.n_octaves)
             for o in range(1, d.n_octaves):
                 np.testing.assert_array_equal(g.level(o), ref[o])   # the masked octaves alternate buffers
+    g.push_chunk(torch.from_numpy(frames).cuda())       # chunks take the per-pixel masks too
+    ref = oracle.pyramid(frames[-1], d.n_octaves)
+    for o in range(1, d.n_octaves):
+        np.testing.assert_array_equal(g.level(o), ref[o])
+    g.set_thresholds(d.fast_t, 8, 3)
     with pytest.raises(kpd.KpdError):
-        g.push_chunk(torch.from_numpy(frames).cuda())   # chunks keep the per-cell mask
+        g.push_chunk(torch.from_numpy(frames).cuda())   # T_H would chain a chunk's marks through its counts
     g.close()
