@@ -322,8 +322,18 @@ def feature_workload(kpd, wl: Workload, args, which: str) -> dict:
                      "features_per_frame": round(sum(st["total_kp"]) / wl.F, 1),
                      "k_describe_avg_us": round(prof["k_describe"][0] * 1e3 / max(prof["k_describe"][1], 1), 3)
                      if "k_describe" in prof else None}
-    out["what"] = (f"{wl.name}, one push_frame per frame with {label}: "
-                   "masked frames compute them for the new features only, carried ones keep theirs")
+    K = chunk_of(args, wl)
+    for name, ti in (("chunked_masked", wl.det.id_thresh), ("chunked_full_frame", -1)):
+        s = open_stream(wl, ti, K, features=features)
+        sec = timed_passes(kpd, s, wl, max(1, args.steps // 5), 1)
+        prof = kernel_profile(kpd, s, wl, 2)
+        s.close()
+        out[name] = {"value": round(wl.F * wl.W * wl.H / sec / 1e6, 2), "unit": "Mpixel/s",
+                     "frames_per_s": round(wl.F / sec, 1), "chunk": K,
+                     "k_describe_us_per_pass": round(prof["k_describe"][0] * 1e3 / prof["passes"], 3)
+                     if "k_describe" in prof else None}
+    out["what"] = (f"{wl.name}, {label}: one push_frame per frame (masked, full_frame) or chunks of {K} frames "
+                   "(chunked_*); masked frames compute them for the new features only, carried ones keep theirs")
     out["computed_masked_over_full"] = round(out["masked"]["computed_per_frame"] /
                                              max(out["full_frame"]["computed_per_frame"], 1e-9), 4)
     return out
@@ -523,13 +533,13 @@ def chunk_of(args, wl: Workload) -> int:
 
 
 def run_workload(kpd, wl: Workload, id_thresh: int, args, want_latency=True, want_profile=True, chunk=0,
-                 layer=None, kb_thresh=None):
+                 layer=None, kb_thresh=None, mask_mode=1):
     """layer: None for the per-cell mean-difference mask, else the pyramid
-    layer of the per-pixel mask (single-frame pushes only). kb_thresh: T_H
-    (default: the workload's)."""
+    layer of the per-pixel mask (mask_mode 1; mask_mode 2 masks each octave
+    on its own level). kb_thresh: T_H (default: the workload's)."""
     s = open_stream(wl, id_thresh, chunk, layer_mask=layer is not None, kb_thresh=kb_thresh)
     if layer is not None:
-        s.set_mask_mode(1, layer)
+        s.set_mask_mode(mask_mode, layer if mask_mode == 1 else 0)
     sec = timed_passes(kpd, s, wl, args.steps, args.warmup)
     res = {"sec_per_pass": sec, "frames": wl.F, "chunk": chunk, "layer": layer,
            "mpix_per_s": wl.F * wl.W * wl.H / sec / 1e6, "frames_per_s": wl.F / sec}
@@ -1140,6 +1150,19 @@ def main():
         "touched_cell_frac": round(sum(lm["marked"][1:]) / max(1, (wl.F - 1) * wl.ncell), 4),
         "roofline": roofline_of(wl, lm, True),
     }
+    for key, mode in (("chunked", 1), ("octave_masks_chunked", 2)):
+        log(f"[bench] per-pixel mask mode {mode} in chunks of {K}")
+        lc = run_workload(kpd, wl, wl.det.id_thresh, args, chunk=K, layer=top, mask_mode=mode)
+        kern = {k: round(v[0] * 1e3 / lc["kernels"]["passes"], 2) for k, v in lc["kernels"].items() if k != "passes"}
+        out["layer_mask"][key] = {
+            "what": (f"mode {mode} ({'layer ' + str(top) + ' for every octave' if mode == 1 else 'each octave on its own level'})"
+                     f", push_frames chunks of {K}: diff, mark, listed detection, per-cell merge of Eq. 1 per "
+                     "feature along the chunk, compaction"),
+            "value": round(lc["mpix_per_s"], 2), "unit": "Mpixel/s", "frames_per_s": round(lc["frames_per_s"], 1),
+            "ms_per_step": round(lc["sec_per_pass"] * 1e3, 4),
+            "chunk_latency_ms": {"p50": round(lc["lat_p50"], 4), "p99": round(lc["lat_p99"], 4)},
+            "kernel_us_per_pass": kern,
+        }
     log("[bench] keypoint-binning mask only (T_I off, T_H = 2)")
     kbc = run_workload(kpd, wl, 255, args, chunk=K, kb_thresh=2, want_profile=False)
     kbf = run_workload(kpd, wl, 255, args, kb_thresh=2, want_profile=False)

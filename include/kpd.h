@@ -202,10 +202,11 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
  * every level, a feature at level o tested on level o's pixel (x, y). The
  * reported cell mask flags cells marked by T_H or holding a changed pixel
  * (of any level, replicated to level 0, in mode 2). Modes 1 and 2 run on
- * push_frame and on push_frames (there with T_H off, KPD_KB_OFF, unless
- * every cell is marked anyway: a chunk's per-pixel marks cannot depend on
- * the counts of the frame before); batch_push returns KPD_EINVAL while one
- * is set, and either mode does on a stream opened without layer_mask. */
+ * push_frame, in batch ticks (whose batch then adds one launch per tick
+ * for the cells of its streams opened with layer_mask) and on push_frames
+ * (there with T_H off, KPD_KB_OFF, unless every cell is marked anyway: a
+ * chunk's per-pixel marks cannot depend on the counts of the frame before).
+ * Either mode returns KPD_EINVAL on a stream opened without layer_mask. */
 int set_mask_mode(kpd_stream* s, int mode, int layer);
 
 /* Orientation and binary descriptor of one feature (Sec. 3: a feature is
@@ -290,9 +291,11 @@ const char* kpd_last_error(void);
  * detection of the listed cells; each stream's D_n by Eq. 1);
  * batch_set_single_launch(b, 1) makes it one launch of co-resident
  * workgroups whose phases are separated by device-wide barriers. When an
+ * attached stream was opened with layer_mask, one more launch runs the
+ * cells of the streams with a per-pixel mask set (set_mask_mode); when an
  * attached stream computes features (descriptors or refined values), one
- * more launch follows that computes them for every such stream. Results
- * are exactly those of pushing each stream's frame alone. */
+ * more launch computes them for every such stream. Results are exactly
+ * those of pushing each stream's frame alone. */
 typedef struct kpd_batch kpd_batch;
 
 /* Device scratch bytes of a batch holding up to `max_streams` streams whose

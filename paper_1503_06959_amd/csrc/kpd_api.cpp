@@ -1623,6 +1623,8 @@ struct kpd_batch {
     kpd::TickSync* dev_sync = nullptr;
     int tick_lds = 16, tick_grid = 0;
     bool features = false;   // an attached stream computes descriptors or refined values
+    bool pixel = false;      // an attached stream may run a per-pixel mask (opened with layer_mask)
+    int pixel_lds = 16;      // the per-pixel cell pass's LDS
     bool maps_dirty = true;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     uint64_t ticks = 0;
@@ -1658,10 +1660,15 @@ int rebuild_maps(kpd_batch* b)
 {
     std::vector<uint16_t> fmap, cmap;
     int fl = 16, dl = 16, gl = 16;
-    bool feats = false;
+    bool feats = false, pix = false;
+    int pl = 16;
     for (size_t i = 0; i < b->streams.size(); ++i) {
         const Layout& L = b->streams[i]->L;
         feats = feats || b->streams[i]->p.features != 0;
+        if (b->streams[i]->p.layer_mask) {
+            pix = true;
+            pl = std::max(pl, L.lds_bytes1);
+        }
         const int nt = L.tiles_x * L.tiles_y;
         fmap.insert(fmap.end(), (size_t)nt, (uint16_t)i);
         cmap.insert(cmap.end(), (size_t)L.ncell, (uint16_t)i);
@@ -1674,13 +1681,15 @@ int rebuild_maps(kpd_batch* b)
     KPD_HIP(hipStreamSynchronize(b->stream));  // no tick in flight reads the old maps
     if (!fmap.empty()) KPD_HIP(hipMemcpy(b->dev_fmap, fmap.data(), fmap.size() * 2, hipMemcpyHostToDevice));
     if (!cmap.empty()) KPD_HIP(hipMemcpy(b->dev_cmap, cmap.data(), cmap.size() * 2, hipMemcpyHostToDevice));
-    KPD_HIP(kpd::set_detect_lds_limit(dl));
+    KPD_HIP(kpd::set_detect_lds_limit(std::max(dl, pl)));
     b->frame_blocks = (int)fmap.size();
     b->cell_blocks = (int)cmap.size();
     b->frame_lds = fl;
     b->detect_lds = dl;
     b->detect_glds = gl;
     b->features = feats;
+    b->pixel = pix;
+    b->pixel_lds = pl;
     // the single-launch tick: as many workgroups as there are items, at most
     // what the device holds at once, a multiple of the XCD count
     b->tick_lds = std::max(fl, gl);
@@ -1695,7 +1704,8 @@ int rebuild_maps(kpd_batch* b)
 
 // Enqueue one tick reading table k: upload, tile pass, mark pass, detection
 // of the marked cells, compaction of every stream's D_n (or the one launch
-// that does all four); then, when a stream asks for them, the features.
+// that does all four); then, when streams may run a per-pixel mask, their
+// cell pass, and when a stream asks for them, the features.
 hipError_t enqueue_tick(kpd_batch* b, int k)
 {
     const size_t n = b->streams.size();
@@ -1705,6 +1715,8 @@ hipError_t enqueue_tick(kpd_batch* b, int k)
         if (e == hipSuccess)
             e = kpd::launch_tick(b->dev_table[k], b->dev_fmap, b->frame_blocks, b->dev_cmap, b->cell_blocks, (int)n,
                                  b->dev_sync, k, b->tick_grid, b->tick_lds, b->stream);
+        if (e == hipSuccess && b->pixel && b->cell_blocks)
+            e = kpd::launch_detect_pixel_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->pixel_lds, b->stream);
         if (e == hipSuccess && b->features && b->cell_blocks)
             e = kpd::launch_describe_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->stream);
         return e;
@@ -1719,6 +1731,8 @@ hipError_t enqueue_tick(kpd_batch* b, int k)
                                                  b->dev_work_count, b->detect_glds, b->stream);
     if (e == hipSuccess && n)
         e = kpd::launch_compact_batch(b->dev_table[k], (int)n, b->dev_work_count, b->stream);
+    if (e == hipSuccess && b->pixel && b->cell_blocks)
+        e = kpd::launch_detect_pixel_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->pixel_lds, b->stream);
     if (e == hipSuccess && b->features && b->cell_blocks)
         e = kpd::launch_describe_batch(b->dev_table[k], b->dev_cmap, b->cell_blocks, b->stream);
     return e;
@@ -1834,7 +1848,6 @@ int batch_stage(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_
     }
     *hint = i + 1;
     if (b->has_frame[i]) return fail(KPD_ESTATE, "a frame is already staged for this tick");
-    if (s->id_mode != 0) return fail(KPD_EINVAL, "the layer mask runs on single-frame pushes only");
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &b->staged[i]);
     if (rc != KPD_OK) return rc;
     b->has_frame[i] = 1;

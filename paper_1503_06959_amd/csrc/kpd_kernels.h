@@ -345,6 +345,8 @@ hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStrea
 hipError_t launch_describe(const DescArgs& a, int ncell, hipStream_t s);
 hipError_t launch_describe_chunk(const DescChunkArgs& a, hipStream_t s);
 hipError_t launch_describe_batch(const TickArgs* table, const uint16_t* map, int ncells, hipStream_t s);
+hipError_t launch_detect_pixel_batch(const TickArgs* table, const uint16_t* map, int ncells, int lds_bytes,
+                                     hipStream_t s);
 hipError_t launch_frame_batch(const TickArgs* table, const uint16_t* map, int nblocks, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_batch(const TickArgs* table, int n, kpd_keypoint* out, uint32_t out_cap, uint32_t* counts,
                                hipStream_t s);

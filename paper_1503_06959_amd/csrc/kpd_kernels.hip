@@ -1523,6 +1523,20 @@ __global__ __launch_bounds__(NT) void k_detect1(DetectArgs a)
     detect_cell<NT>(a, blockIdx.x, sm);
 }
 
+// The streams of a batch tick with a per-pixel mask: workgroup g runs cell
+// g - cell_base of stream map[g] as k_detect1 does for one stream (marks,
+// detection, Eq. 1 per feature and the cell's place in D_n); the cells of
+// other streams return at once. A cell waits only on lower cells of its
+// own stream, whose workgroups come earlier in the grid.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_detect_pixel_batch(const TickArgs* table, const uint16_t* map)
+{
+    extern __shared__ __align__(16) uint8_t sm[];
+    const TickArgs& t = table[map[blockIdx.x]];
+    if (!t.active || t.d.id_mode == 0) return;
+    detect_cell<NT>(t.d, (int)blockIdx.x - t.cell_base, sm);
+}
+
 // Tile pass of a chunk: tiles of all its frames banded over the XCDs;
 // frame j's tile source is frame j of the chunk and its predecessor, its
 // octaves go pyr_stride * j bytes past frame 0's and its SAD accumulators
@@ -2295,7 +2309,7 @@ __global__ __launch_bounds__(kMarkBlock) void k_mark_batch(const TickArgs* table
     bool mark = false;
     if (g < ncells) {
         const TickArgs& t = table[map[g]];
-        if (t.active) {
+        if (t.active && t.d.id_mode == 0) {   // per-pixel streams run their own pass
             const int c = g - t.cell_base;
             mark = cell_marked(t.d, c);
             t.d.mask[c] = (uint8_t)mark;
@@ -2381,7 +2395,7 @@ hipError_t launch_compact1(const DetectArgs& a, const kpd_keypoint* sparse, cons
 __global__ __launch_bounds__(kCompact) void k_compact_batch(const TickArgs* table, uint32_t* work_count)
 {
     const TickArgs& t = table[blockIdx.x];
-    if (t.active) {
+    if (t.active && t.d.id_mode == 0) {
         const DetectArgs& a = t.d;
         compact_frame<kCompact>(a.nc * a.nr, a.list_cap, a.list_cur, a.count_cur, a.off_cur, a.total_cur,
                       [&](int c, uint32_t* n, const kpd_keypoint** src) {
@@ -2452,6 +2466,7 @@ hipError_t set_detect_lds_limit(int lds_bytes)
     if (lds_bytes <= cur) return hipSuccess;
     const void* kernels[] = {
         reinterpret_cast<const void*>(k_detect1<kDetLatency>),
+        reinterpret_cast<const void*>(k_detect_pixel_batch<kDetLatency>),
     };
     for (const void* k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
@@ -2470,6 +2485,13 @@ hipError_t launch_frame(const FrameArgs& a, hipStream_t s)
 hipError_t launch_detect(const DetectArgs& a, int ncell, int lds_bytes, hipStream_t s)
 {
     hipLaunchKernelGGL(k_detect1<kDetLatency>, dim3(ncell), dim3(kDetLatency), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_pixel_batch(const TickArgs* table, const uint16_t* map, int ncells, int lds_bytes,
+                                     hipStream_t s)
+{
+    hipLaunchKernelGGL(k_detect_pixel_batch<kDetLatency>, dim3(ncells), dim3(kDetLatency), lds_bytes, s, table, map);
     return hipGetLastError();
 }
 
@@ -2632,7 +2654,7 @@ __global__ __launch_bounds__(kFrameBlock) void k_tick(const TickArgs* table, con
     tick_barrier(&sync->arrive[parity][0], table, nstreams);
     for (int g = blockIdx.x; g < ncells; g += G) {
         const TickArgs& t = table[cmap[g]];
-        if (!t.active) continue;
+        if (!t.active || t.d.id_mode != 0) continue;
         const int c = g - t.cell_base;
         const bool mark = cell_marked(t.d, c);
         if (threadIdx.x == 0) {
@@ -2647,7 +2669,7 @@ __global__ __launch_bounds__(kFrameBlock) void k_tick(const TickArgs* table, con
     tick_barrier(&sync->arrive[parity][1], table, nstreams);
     for (int i = blockIdx.x; i < nstreams; i += G) {
         const TickArgs& t = table[i];
-        if (!t.active) continue;
+        if (!t.active || t.d.id_mode != 0) continue;
         const DetectArgs& a = t.d;
         compact_frame<kFrameBlock>(a.nc * a.nr, a.list_cap, a.list_cur, a.count_cur, a.off_cur, a.total_cur,
                                    [&](int c, uint32_t* n, const kpd_keypoint** src) {

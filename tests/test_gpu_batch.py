@@ -27,13 +27,14 @@ def tuples(arr):
 
 
 def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode="retain", single=True,
-              lazy=False, feats=lambda s: 0):
+              lazy=False, feats=lambda s: 0, masks=lambda s: None):
     """specs: list of (Scene, (t, O, Nc, Nr, TI, TH, tile)). Every tick each
     stream not skipped pushes its next frame; after the tick every stream's
     D_n and mask are compared with its oracle. single: one launch per tick
     (else four); lazy: the oracle's CPU-masked mode (equal to its
     definitional mode, pinned on the CPU); feats(s): stream s's features
-    (FEAT_* bits), compared with its oracle's after every tick."""
+    (FEAT_* bits), compared with its oracle's after every tick; masks(s):
+    stream s's per-pixel mask (mode, layer), None for the per-cell one."""
     import torch
     from paper_1503_06959_amd.batch import Batch
     b = Batch(max_streams=len(specs) + 2, use_graph=use_graph)
@@ -42,8 +43,12 @@ def run_batch(kpd, specs, n_ticks, use_graph=True, skip=lambda s, t: False, mode
     for si, (sc, det) in enumerate(specs):
         t, O, Nc, Nr, TI, TH, tile = det
         frames = synth.make_video(sc, n_ticks)
-        g = b.open_stream(sc.width, sc.height, kpd.make_params(t, O, Nc, Nr, TI, TH, tile, features=feats(si)))
+        g = b.open_stream(sc.width, sc.height, kpd.make_params(t, O, Nc, Nr, TI, TH, tile, features=feats(si),
+                                                               layer_mask=int(masks(si) is not None)))
         o = oracle.Stream(sc.width, sc.height, t, O, Nc, Nr, TI, TH)
+        if masks(si) is not None:
+            g.set_mask_mode(*masks(si))
+            o.set_id_mode(*masks(si))
         if lazy:
             o.set_lazy(True)
         o.set_descriptors(bool(feats(si) & kpd.FEAT_DESCRIPTOR))
@@ -132,6 +137,18 @@ def test_streams_with_features(kpd, single):
     both = kpd.FEAT_DESCRIPTOR | kpd.FEAT_REFINE
     run_batch(kpd, mixed_specs(8, 4400), 6, single=single, skip=lambda s, t: (s + t) % 4 == 0,
               feats=lambda s: [both, 0, kpd.FEAT_DESCRIPTOR, kpd.FEAT_REFINE][s % 4])
+
+
+@pytest.mark.parametrize("single", [True, False])
+def test_streams_with_per_pixel_masks(kpd, single):
+    # the top layer for every octave, one mask per octave, and per-cell
+    # streams side by side, with streams skipping ticks
+    specs = mixed_specs(9, 4500)
+
+    def masks(s):
+        O = specs[s][1][1]
+        return [(1, O - 1), (2, 0), None][s % 3]
+    run_batch(kpd, specs, 6, single=single, skip=lambda s, t: (s + t) % 4 == 0, masks=masks)
 
 
 def test_tile_size_does_not_change_results(kpd):
