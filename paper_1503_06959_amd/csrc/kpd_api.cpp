@@ -81,7 +81,8 @@ struct Layout {
     // the per-pixel layer mask (set_mask_mode): its LDS scratch past every
     // cell's layout (changed bits, carried bits, their offsets and scores),
     // and a second buffer for octave 1.. so the layer of I_{n-1} survives
-    int lds_bits = 0, lds_carr = 0, lds_cwoff = 0, lds_cscore = 0, lds_bytes1 = 0;
+    int lds_bits = 0, lds_carr = 0, lds_cwoff = 0, lds_cscore = 0, lds_csrc = 0, lds_bytes1 = 0;
+    size_t off_src = 0;   // features with a per-pixel mask: each D_n entry's source
     size_t off_lvl_alt = 0;
     // per-pixel masks in chunks (layer_mask streams): the cells' layer-pixel
     // change bits (fpw words per frame and cell) and change flags, the
@@ -344,6 +345,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         L->lds_carr = o1;   o1 += kpd::round_up(nwords_max * 8, 16);
         L->lds_cwoff = o1;  o1 += kpd::round_up(nwords_max * 4, 16);
         L->lds_cscore = o1; o1 += kpd::round_up((int)cell_cap_max * 2, 16);
+        L->lds_csrc = o1;
+        if (p->features) o1 += kpd::round_up((int)cell_cap_max * 4, 16);   // carried entries' sources
         L->lds_bytes1 = o1;
     }
 
@@ -418,6 +421,7 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         for (int k = 0; k < 2; ++k) { L->off_desc[k] = off; off = align_up(off + L->list_cap1 * sizeof(kpd_descriptor)); }
         L->off_dtab = off; off = align_up(off + sizeof(kpd::DescTables));
     }
+    if (p->features && p->layer_mask) { L->off_src = off; off = align_up(off + L->list_cap1 * 4); }
     if (p->features & KPD_FEAT_REFINE)   // refined values of D_{n-1} and D_n
         for (int k = 0; k < 2; ++k) { L->off_ref[k] = off; off = align_up(off + L->list_cap1 * sizeof(kpd_refined)); }
     if (L->K > 1) {
@@ -930,6 +934,8 @@ int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int fla
         d.lds_carr = L.lds_carr;
         d.lds_cwoff = L.lds_cwoff;
         d.lds_cscore = L.lds_cscore;
+        d.lds_csrc = L.lds_csrc;
+        d.src_cur = s->p.features ? s->at<uint32_t>(L.off_src) : nullptr;
     }
     d.W = L.W; d.H = L.H; d.O = L.O; d.nc = L.nc; d.nr = L.nr;
     d.t = s->p.fast_t;
@@ -1089,6 +1095,7 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
         da.off_prev = t.d.off_prev;
         da.list_cur = t.d.list_cur;
         da.list_cap = (uint32_t)L.list_cap1;
+        da.src_cur = t.d.src_cur;
         KPD_HIP(timed(s, KPD_K_DESCRIBE, [&] { return kpd::launch_describe(da, L.ncell, s->stream); }));
     }
     advance_frame(s, t);
@@ -1102,8 +1109,10 @@ int set_mask_mode(kpd_stream* s, int mode, int layer)
     if (layer < 0 || layer >= s->L.O) return fail(KPD_EINVAL, "layer must be an octave of the stream");
     if (mode == 2 && layer != 0) return fail(KPD_EINVAL, "mode 2 masks every octave on its own level: layer must be 0");
     if (mode != 0 && !s->p.layer_mask) return fail(KPD_EINVAL, "stream opened without layer_mask");
-    if (mode != 0 && s->p.features) return fail(KPD_EINVAL, "descriptors and refinement run with mask mode 0 only");
     if (mode == s->id_mode && (mode != 1 || layer == s->id_layer)) return KPD_OK;
+    if (mode != 0 && s->L.lds_bytes1 > 160 * 1024)
+        return fail(KPD_EINVAL, "cells too large for a per-pixel mask" +
+                                    std::string(s->p.features ? " with features" : "") + " (LDS)");
     if (mode != 0) KPD_HIP(kpd::set_detect_lds_limit(s->L.lds_bytes1));
     s->id_mode = mode;
     s->id_layer = mode == 1 ? layer : 0;
@@ -1151,6 +1160,8 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     if (pixel && s->p.kb_thresh != KPD_KB_OFF && s->p.kb_thresh != 0 && s->p.id_thresh >= 0)
         return fail(KPD_EINVAL, "the layer mask in chunks needs kb_thresh off");
     if (pixel && L.pm_lds > 60 * 1024) return fail(KPD_EINVAL, "cells too large for the layer mask in chunks");
+    if (pixel && s->p.features)
+        return fail(KPD_EINVAL, "features with a per-pixel mask run on push_frame and batch ticks only");
     if (!frames) return fail(KPD_EINVAL, "frames is NULL");
     if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");

@@ -76,6 +76,8 @@ struct DescArgs {
     const kpd_descriptor* desc_prev;
     kpd_descriptor* desc_cur;
     uint32_t list_cap;
+    // per-pixel masks: the entries' sources (DetectArgs::src_cur), null otherwise
+    const uint32_t* src_cur;
 };
 
 // k_detect: per-cell mark, detection, look-back offsets and output.
@@ -111,13 +113,18 @@ struct DetectArgs {
     // id_layer, id_mode 2 one per octave on its own level. lprev holds
     // I_{n-1}'s levels that the masks read (I_n's are lvl); the lds_ fields
     // say where the per-cell scratch lives in LDS (changed-pixel bits,
-    // carried-entry bits, their word offsets and scores), past every cell's
-    // detection layout
+    // carried-entry bits, their word offsets, scores and, with features,
+    // sources), past every cell's detection layout
     int id_mode, id_layer;
     const uint8_t* lprev[KPD_MAX_OCTAVES];
     int lprev_pitch[KPD_MAX_OCTAVES];
-    int lds_bits, lds_carr, lds_cwoff, lds_cscore;
+    int lds_bits, lds_carr, lds_cwoff, lds_cscore, lds_csrc;
+    // with features and a per-pixel mask: for every D_n entry of a marked
+    // cell, its index in D_{n-1}'s list when carried, else kNewFeature
+    uint32_t* src_cur;
 };
+
+constexpr uint32_t kNewFeature = 0xFFFFFFFFu;
 
 // Everything one stream needs for one batch tick. tile_base and cell_base
 // are the stream's first workgroups in the tick's two launches.

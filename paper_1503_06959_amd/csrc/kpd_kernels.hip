@@ -856,7 +856,10 @@ __device__ __forceinline__ void emit_marked(const DetectArgs& a, const CellLayou
             k.pad = 0;
             k.score = (uint16_t)vget(sm, L, o, x, y);
             // at most one keypoint per 2x2 block keeps pos below the capacity
-            if (pos < cap) list[pos] = k;
+            if (pos < cap) {
+                list[pos] = k;
+                if (a.src_cur) a.src_cur[pos] = kNewFeature;
+            }
             ++pos;
         }
     }
@@ -868,7 +871,7 @@ __device__ __forceinline__ void emit_marked(const DetectArgs& a, const CellLayou
 template <int NT>
 __device__ __forceinline__ void emit_merged(const DetectArgs& a, const CellLayout& L, const uint8_t* sm,
                                             uint32_t excl, kpd_keypoint* list, uint32_t cap, const uint64_t* carr,
-                                            const uint32_t* cwoff, const uint16_t* cscore)
+                                            const uint32_t* cwoff, const uint16_t* cscore, const uint32_t* csrc)
 {
     const int O = a.O;
     const uint64_t* keepw = reinterpret_cast<const uint64_t*>(sm);
@@ -891,9 +894,13 @@ __device__ __forceinline__ void emit_merged(const DetectArgs& a, const CellLayou
             k.y = (uint16_t)y;
             k.octave = (uint8_t)o;
             k.pad = 0;
-            k.score = ((cb >> b) & 1) ? cscore[cwoff[w] + __popcll(cb & ((1ull << b) - 1))]
-                                      : (uint16_t)vget(sm, L, o, x, y);
-            if (pos < cap) list[pos] = k;
+            const bool carried = ((cb >> b) & 1) != 0;
+            const uint32_t r = carried ? cwoff[w] + (uint32_t)__popcll(cb & ((1ull << b) - 1)) : 0u;
+            k.score = carried ? cscore[r] : (uint16_t)vget(sm, L, o, x, y);
+            if (pos < cap) {
+                list[pos] = k;
+                if (a.src_cur) a.src_cur[pos] = carried ? csrc[r] : kNewFeature;
+            }
             ++pos;
         }
     }
@@ -1020,6 +1027,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
     uint64_t* carr = reinterpret_cast<uint64_t*>(sm + a.lds_carr);
     uint32_t* cwoff = reinterpret_cast<uint32_t*>(sm + a.lds_cwoff);
     uint16_t* cscore = reinterpret_cast<uint16_t*>(sm + a.lds_cscore);
+    uint32_t* csrc = reinterpret_cast<uint32_t*>(sm + a.lds_csrc);   // with features: carried entries' sources
     if (state == 1) {
         uint64_t* keepw = reinterpret_cast<uint64_t*>(sm);
         // the mask pixel of the feature at level o, (x,y): on the chosen
@@ -1073,6 +1081,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
                 const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
                 cscore[before + below] = e.score;
+                if (a.src_cur) csrc[before + below] = src0 + jj;
                 const int o = e.octave;
                 const Box d = L.dec[o];
                 const int i = L.dc_start[o] + (e.y - d.y0) * box_w(d) + (e.x - d.x0);
@@ -1105,7 +1114,7 @@ __device__ void detect_cell_layer(const DetectArgs& a, int c, uint8_t* sm)
     if (state == 2) {
         emit_marked<NT>(a, L, sm, excl, a.list_cur, a.list_cap);
     } else if (state == 1) {
-        emit_merged<NT>(a, L, sm, excl, a.list_cur, a.list_cap, carr, cwoff, cscore);
+        emit_merged<NT>(a, L, sm, excl, a.list_cur, a.list_cap, carr, cwoff, cscore, csrc);
     } else {
         const uint32_t src0 = a.off_prev[c];
         for (uint32_t j = tid; j < n; j += NT)
@@ -1279,17 +1288,20 @@ __device__ void copy_feature_records(const kpd_descriptor* dsrc, kpd_descriptor*
 // Features of entries [dst0, dst0 + n) of a keypoint list, computed on the
 // levels of their frame (lv: ptr, pitch, w and h of octave o) into the same
 // entries of desc and ref (either may be null: that part is left out; tab
-// is null exactly when desc is).
+// is null exactly when desc is). With src, entries whose source is not
+// kNewFeature are left to the caller.
 template <class Lv>
 __device__ void describe_entries(const Lv& lv, const DescTables* tab, int O, int t, const kpd_keypoint* list,
                                  kpd_descriptor* desc, kpd_refined* ref, uint32_t dst0, uint32_t n,
-                                 uint32_t list_cap, int (*s_v)[64], uint8_t (*s_patch)[kPatch * kPatch])
+                                 uint32_t list_cap, int (*s_v)[64], uint8_t (*s_patch)[kPatch * kPatch],
+                                 const uint32_t* src = nullptr)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int* V = s_v[wave];
     uint8_t* patch = s_patch[wave];
     for (uint32_t k = wave; k < n; k += kDescBlock / 64) {
         if (dst0 + k >= list_cap) break;
+        if (src && src[dst0 + k] != kNewFeature) continue;   // a carried feature keeps its records
         const kpd_keypoint kp = list[dst0 + k];
         const int o = kp.octave;
         if (ref) {
@@ -1389,8 +1401,28 @@ struct DescLevels {
     __device__ int h(int o) const { return a.h[o]; }
 };
 
+// The records of a marked cell's carried entries (per-pixel masks: an
+// entry whose source is an index of D_{n-1}'s list).
+__device__ void copy_carried_records(const uint32_t* src, const kpd_descriptor* dsrc, kpd_descriptor* ddst,
+                                     const kpd_refined* rsrc, kpd_refined* rdst, uint32_t dst0, uint32_t n,
+                                     uint32_t list_cap)
+{
+    constexpr int kw = sizeof(kpd_descriptor) / 8;
+    for (uint32_t i = threadIdx.x; i < n * kw; i += kDescBlock) {
+        const uint32_t e = i / kw;
+        if (dst0 + e >= list_cap) break;
+        const uint32_t f = src[dst0 + e];
+        if (f == kNewFeature || f >= list_cap) continue;
+        if (ddst)
+            reinterpret_cast<uint64_t*>(ddst)[(size_t)(dst0 + e) * kw + i % kw] =
+                reinterpret_cast<const uint64_t*>(dsrc)[(size_t)f * kw + i % kw];
+        if (rdst && i % kw == 0) rdst[dst0 + e] = rsrc[f];
+    }
+}
+
 // One frame, a workgroup per cell: an unmarked cell's features are
-// D_{n-1}'s, copied; a marked cell's are new.
+// D_{n-1}'s, copied; a marked cell's are new, or with a per-pixel mask new
+// where the mask pixel changed and copied from D_{n-1} elsewhere.
 __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
 {
     __shared__ int s_v[kDescBlock / 64][64];
@@ -1402,8 +1434,11 @@ __global__ __launch_bounds__(kDescBlock) void k_describe1(DescArgs a)
                              a.list_cap);
         return;
     }
+    if (a.src_cur)
+        copy_carried_records(a.src_cur, a.desc_prev, a.tab ? a.desc_cur : nullptr, a.ref_prev, a.ref_cur, dst0, n,
+                             a.list_cap);
     describe_entries(DescLevels{a}, a.tab, a.O, a.t, a.list_cur, a.desc_cur, a.ref_cur, dst0, n, a.list_cap, s_v,
-                     s_patch);
+                     s_patch, a.src_cur);
 }
 
 // The levels of a batch tick's stream, from its detection arguments.
@@ -1433,8 +1468,11 @@ __global__ __launch_bounds__(kDescBlock) void k_describe_batch(const TickArgs* t
                              d.list_cap);
         return;
     }
+    if (d.src_cur)
+        copy_carried_records(d.src_cur, t.desc_prev, t.tab ? t.desc_cur : nullptr, t.ref_prev, t.ref_cur, dst0, n,
+                             d.list_cap);
     describe_entries(TickLevels{d}, t.tab, d.O, d.t, d.list_cur, t.desc_cur, t.ref_cur, dst0, n, d.list_cap, s_v,
-                     s_patch);
+                     s_patch, d.src_cur);
 }
 
 // The levels of chunk frame j: level 0 is the frame itself, the others its

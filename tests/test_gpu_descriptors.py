@@ -110,7 +110,7 @@ def test_descriptor_errors(kpd):
     with pytest.raises(kpd.KpdError):
         g.descriptors()                                # nothing pushed yet
     with pytest.raises(kpd.KpdError):
-        g.set_mask_mode(1, 2)                          # descriptors keep the per-cell mask
+        g.set_mask_mode(3, 0)                          # no such mask mode
     with pytest.raises(kpd.KpdError):
         g.chunk_descriptors(0)                         # no chunk pushed yet
     g.push(frames[0])
