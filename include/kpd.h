@@ -491,7 +491,8 @@ int kpd_refine_layers(int width, int height, int n_octaves, void* workspace, siz
  * pixels (push_frame's rule for the octaves), for the count test, for Eq. 1
  * and for D_n's order: cell, then layer, then y, then x. The `octave` field
  * holds the layer index. Parameters used: fast_t, n_octaves, grid_cols,
- * grid_rows, id_thresh, kb_thresh. Frames and flags as push_frame. */
+ * grid_rows, id_thresh, kb_thresh, chunk_frames. Frames and flags as
+ * push_frame. */
 typedef struct kpd_lstream kpd_lstream;
 size_t kpd_lstream_bytes(int width, int height, const kpd_params* params);
 int kpd_lstream_open(int width, int height, const kpd_params* params, void* dev_arena, size_t arena_bytes,
@@ -501,6 +502,19 @@ int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, i
  * get_keypoints (synchronises; KPD_ETRUNC copying nothing when D_n exceeds
  * capacity). */
 int kpd_lstream_get(kpd_lstream* s, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask);
+/* n_frames consecutive device frames (1 <= n_frames <= chunk_frames) in one
+ * pass of a few launches, read in place as push_frames reads them: the
+ * marks of every frame, the layers of every frame, scores and suppression
+ * in the cells the marks need, the marked cells' keypoints, and each
+ * frame's D by Eq. 1. kb_thresh must be KPD_KB_OFF unless id_thresh < 0 or
+ * kb_thresh == 0 mark every cell anyway (KPD_EINVAL): the count test would
+ * chain a chunk's marks frame by frame. Results are exactly those of
+ * pushing the frames one by one: kpd_lstream_get returns the last frame's
+ * D_n and M_n, kpd_lstream_get_chunk frame i's D (count/capacity rules as
+ * kpd_lstream_get). */
+int kpd_lstream_push_frames(kpd_lstream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes,
+                            int n_frames);
+int kpd_lstream_get_chunk(kpd_lstream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count);
 int kpd_lstream_reset(kpd_lstream* s);
 int kpd_lstream_close(kpd_lstream* s);
 

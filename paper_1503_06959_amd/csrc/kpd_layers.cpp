@@ -10,6 +10,7 @@
 
 #include "../../include/kpd.h"
 #include "kpd_errors.h"
+#include "kpd_kernels.h"
 #include "kpd_layers.h"
 
 namespace {
@@ -82,8 +83,35 @@ struct LsLayout {
     int rx = 0, ry = 0;   // cell radius of the scored neighbourhood of a marked cell
     size_t off_cnt[2] = {0, 0}, off_off[2] = {0, 0}, off_list[2] = {0, 0}, off_total = 0;
     uint32_t cap = 0;
+    // chunks (chunk_frames K >= 2): K layer workspaces ws_step apart, per
+    // frame and cell the mask, the scored-cell flags and the suppression
+    // counts, the mark words, the sparse lists (fixed per-cell bases), the
+    // lists of frames 0..K-2 with their counts, offsets and totals, and the
+    // compaction's difference accumulators (all zero here) and work words
+    int K = 1, Kw = 1;
+    size_t ws_step = 0;
+    size_t off_cmask = 0, off_cneed = 0, off_cnew = 0, off_marks = 0, off_cbase = 0, off_sparse = 0;
+    size_t off_clist = 0, off_ccount = 0, off_coffs = 0, off_ctotal = 0, off_csad = 0, off_sadstat = 0;
+    size_t off_sadnext = 0, off_cwork = 0;
+    size_t list_stride = 0;   // entries between consecutive frames' lists
     size_t total = 0;
 };
+
+void ls_tables(const LsLayout& L, std::vector<uint32_t>* xs, std::vector<uint32_t>* ys);
+
+// Room of cell c in a chunk's sparse list: one keypoint per 2x2 block of
+// each of its layer boxes (suppression keeps no two neighbours of a layer).
+uint64_t ls_cell_cap(const LsLayout& L, const std::vector<uint32_t>& xs, const std::vector<uint32_t>& ys, int c)
+{
+    const int cc = c % L.nc, rr = c / L.nc;
+    uint64_t n = 0;
+    for (int l = 0; l < L.g.L; ++l) {
+        const uint64_t bw = xs[(size_t)l * (L.nc + 1) + cc + 1] - xs[(size_t)l * (L.nc + 1) + cc];
+        const uint64_t bh = ys[(size_t)l * (L.nr + 1) + rr + 1] - ys[(size_t)l * (L.nr + 1) + rr];
+        n += ((bw + 1) / 2) * ((bh + 1) / 2);
+    }
+    return n;
+}
 
 bool ls_layout(int W, int H, const kpd_params* p, LsLayout* L, std::string* why)
 {
@@ -98,9 +126,21 @@ bool ls_layout(int W, int H, const kpd_params* p, LsLayout* L, std::string* why)
     L->ncell = L->nc * L->nr;
     uint64_t cap = 16;
     for (int l = 0; l < L->g.L; ++l) cap += (uint64_t)((L->g.w[l] + 1) / 2) * ((L->g.h[l] + 1) / 2);
-    L->cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFF0ull);
+    // the chunks' sparse lists give each cell room for one keypoint per 2x2
+    // block of each layer box; the lists hold their sum too
+    std::vector<uint32_t> xs, ys;
+    ls_tables(*L, &xs, &ys);
+    uint64_t cells_cap = 0;
+    for (int c = 0; c < L->ncell; ++c) cells_cap += ls_cell_cap(*L, xs, ys, c);
+    cap = std::max(cap, cells_cap);
+    if (cap > 0xFFFFFFF0ull) { *why = "frame too large"; return false; }
+    L->cap = (uint32_t)cap;
+    L->K = std::max(1, (int)p->chunk_frames);
+    if (L->K > KPD_MAX_CHUNK) { *why = "chunk_frames must be 0.." + std::to_string(KPD_MAX_CHUNK); return false; }
+    L->Kw = (L->K + 63) / 64;
+    L->ws_step = align_up(L->g.total);
     size_t off = 0;
-    L->off_ws = off; off = align_up(off + L->g.total);
+    L->off_ws = off; off = align_up(off + L->ws_step * (size_t)L->K);
     L->slot_pitch = (W + 63) / 64 * 64;
     for (int k = 0; k < 2; ++k) { L->off_slot[k] = off; off = align_up(off + (size_t)L->slot_pitch * H); }
     L->off_xs = off; off = align_up(off + (size_t)L->g.L * (L->nc + 1) * 4);
@@ -123,6 +163,24 @@ bool ls_layout(int W, int H, const kpd_params* p, LsLayout* L, std::string* why)
         L->off_list[k] = off; off = align_up(off + (size_t)L->cap * sizeof(kpd_keypoint));
     }
     L->off_total = off; off = align_up(off + 16);
+    if (L->K > 1) {
+        const size_t kc = (size_t)L->K * L->ncell;
+        L->list_stride = align_up((size_t)L->cap * sizeof(kpd_keypoint)) / sizeof(kpd_keypoint);
+        L->off_cmask = off;   off = align_up(off + kc);
+        L->off_cneed = off;   off = align_up(off + kc);
+        L->off_cnew = off;    off = align_up(off + kc * 4);
+        L->off_marks = off;   off = align_up(off + (size_t)L->ncell * L->Kw * 8);
+        L->off_cbase = off;   off = align_up(off + (size_t)L->ncell * 4);
+        L->off_sparse = off;  off += L->list_stride * sizeof(kpd_keypoint) * (size_t)L->K;
+        L->off_clist = off;   off += L->list_stride * sizeof(kpd_keypoint) * (size_t)(L->K - 1);
+        L->off_ccount = off;  off = align_up(off + kc * 4);
+        L->off_coffs = off;   off = align_up(off + kc * 4);
+        L->off_ctotal = off;  off = align_up(off + (size_t)L->K * 4);
+        L->off_csad = off;    off = align_up(off + kc * 4);
+        L->off_sadstat = off; off = align_up(off + (size_t)L->ncell * 4);
+        L->off_sadnext = off; off = align_up(off + (size_t)L->ncell * 4);
+        L->off_cwork = off;   off = align_up(off + 16);
+    }
     L->total = off;
     return true;
 }
@@ -152,8 +210,10 @@ void ls_tables(const LsLayout& L, std::vector<uint32_t>* xs, std::vector<uint32_
 
 // The layers past the frame: the octaves two halvings per launch, the
 // intra-octaves from the 1.5x downsampling (with d_1) and then two halvings
-// per launch.
-hipError_t build_layers(const kpd::LayerGeom& g, const uint8_t* frame, int pitch, uint8_t* ws, hipStream_t s)
+// per launch. n frames of a chunk: frame j at frame + j * fstep, its
+// workspace at ws + j * wstep.
+hipError_t build_layers(const kpd::LayerGeom& g, const uint8_t* frame, int pitch, uint8_t* ws, hipStream_t s,
+                        int n = 1, size_t fstep = 0, size_t wstep = 0)
 {
     const int O = g.L / 2;
     auto plane = [&](int l) { return ws + g.plane_off[l]; };
@@ -165,19 +225,19 @@ hipError_t build_layers(const kpd::LayerGeom& g, const uint8_t* frame, int pitch
         const int l1 = 2 * i, l2 = 2 * (i + 1);
         const bool two = i + 1 < O;
         e = kpd::launch_lay_quad(src, sp, plane(l1), g.w[l1], g.h[l1], two ? plane(l2) : nullptr, two ? g.w[l2] : 0,
-                                 two ? g.h[l2] : 0, s);
+                                 two ? g.h[l2] : 0, s, n, i == 1 ? fstep : wstep, wstep);
     }
     // intra-octaves: d_i = layer 2i + 1
     if (e == hipSuccess) {
         const bool d1 = O > 1;
         e = kpd::launch_lay_third(frame, pitch, plane(1), g.w[1], g.h[1], d1 ? plane(3) : nullptr, d1 ? g.w[3] : 0,
-                                  d1 ? g.h[3] : 0, s);
+                                  d1 ? g.h[3] : 0, s, n, fstep, wstep);
     }
     for (int i = 2; i < O && e == hipSuccess; i += 2) {
         const int ls = 2 * (i - 1) + 1, l1 = 2 * i + 1, l2 = 2 * (i + 1) + 1;
         const bool two = i + 1 < O;
         e = kpd::launch_lay_quad(plane(ls), g.w[ls], plane(l1), g.w[l1], g.h[l1], two ? plane(l2) : nullptr,
-                                 two ? g.w[l2] : 0, two ? g.h[l2] : 0, s);
+                                 two ? g.w[l2] : 0, two ? g.h[l2] : 0, s, n, wstep, wstep);
     }
     return e;
 }
@@ -192,6 +252,8 @@ struct kpd_lstream {
     std::vector<uint32_t> xs, ys;
     bool force = true;
     int fb = 0;              // buffer of the current D
+    int chunk_n = 0;         // frames of the last kpd_lstream_push_frames (0: a single push since)
+    std::vector<uint32_t> cbase;
     int cur_slot = 0;
     uint64_t n_pushed = 0;
     const uint8_t* prev = nullptr;
@@ -239,6 +301,19 @@ int kpd_lstream_open(int width, int height, const kpd_params* params, void* dev_
         e = hipMemcpyAsync(s->at<uint32_t>(L.off_ys), s->ys.data(), s->ys.size() * 4, hipMemcpyHostToDevice, s->stream);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemsetAsync(s->at<uint32_t>(L.off_cnt[k]), 0, (size_t)L.ncell * 4, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->at<uint32_t>(L.off_total), 0, 16, s->stream);
+    if (L.K > 1) {
+        s->cbase.resize(L.ncell);
+        uint32_t acc = 0;
+        for (int c = 0; c < L.ncell; ++c) {
+            s->cbase[c] = acc;
+            acc += (uint32_t)ls_cell_cap(L, s->xs, s->ys, c);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->at<uint32_t>(L.off_cbase), s->cbase.data(), (size_t)L.ncell * 4,
+                               hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(s->at<uint32_t>(L.off_csad), 0, (size_t)L.K * L.ncell * 4, s->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(s->at<uint32_t>(L.off_cwork), 0, 16, s->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // the host tables are copied before they go
     if (e != hipSuccess) {
         delete s;
@@ -315,6 +390,137 @@ int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, i
     s->prev_pitch = cur_pitch;
     s->force = false;
     s->n_pushed += 1;
+    s->chunk_n = 0;
+    return KPD_OK;
+}
+
+int kpd_lstream_push_frames(kpd_lstream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes,
+                            int n_frames)
+{
+    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    const LsLayout& L = s->L;
+    if (L.K < 2) return kpd::api_fail(KPD_EINVAL, "stream opened without chunk_frames");
+    if (!frames) return kpd::api_fail(KPD_EINVAL, "frames is NULL");
+    if (n_frames < 1 || n_frames > L.K) return kpd::api_fail(KPD_EINVAL, "n_frames out of range");
+    if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return kpd::api_fail(KPD_EINVAL, "bad pitch");
+    if (n_frames > 1 && frame_stride < pitch_bytes * (size_t)(L.H - 1) + (size_t)L.W)
+        return kpd::api_fail(KPD_EINVAL, "frames overlap");
+    // T_H marks a cell from the previous frame's counts, a chain through the
+    // chunk's frames that these passes do not follow
+    const bool all_marked = s->p.id_thresh < 0 || s->p.kb_thresh == 0;
+    if (!all_marked && s->p.kb_thresh != KPD_KB_OFF)
+        return kpd::api_fail(KPD_EINVAL, "chunks of the layered stream need kb_thresh off");
+    const int fp = s->fb, fc = 1 - s->fb;
+    const int pitch = (int)pitch_bytes;
+    uint8_t* ws = s->at<uint8_t>(L.off_ws);
+
+    kpd::LsChunkArgs ca{};
+    ca.frames = frames;
+    ca.stride = frame_stride;
+    ca.pitch = pitch;
+    ca.prev0 = s->prev ? s->prev : frames;   // read only when frame 0 tests differences
+    ca.prev0_pitch = s->prev ? s->prev_pitch : pitch;
+    ca.n_frames = n_frames;
+    ca.force0 = s->force ? 1 : 0;
+    ca.all_marked = all_marked ? 1 : 0;
+    ca.nc = L.nc;
+    ca.nr = L.nr;
+    ca.ncell = L.ncell;
+    ca.Kw = L.Kw;
+    ca.id_thresh = s->p.id_thresh;
+    ca.xs = s->at<uint32_t>(L.off_xs);
+    ca.ys = s->at<uint32_t>(L.off_ys);
+    ca.mask = s->at<uint8_t>(L.off_cmask);
+    ca.need = s->at<uint8_t>(L.off_cneed);
+    ca.cell_new = s->at<uint32_t>(L.off_cnew);
+    ca.marks = s->at<unsigned long long>(L.off_marks);
+    ca.last_mask = s->at<uint8_t>(L.off_mask);
+    ca.sparse = s->at<kpd_keypoint>(L.off_sparse);
+    ca.cbase = s->at<uint32_t>(L.off_cbase);
+    ca.list_stride = L.list_stride;
+    ca.cap = L.cap;
+    ca.rx = L.rx;
+    ca.ry = L.ry;
+
+    kpd::LayArgs la = layer_args(L.g, frames, pitch_bytes, ws);
+    la.t = s->p.fast_t;
+    la.need_score = ca.need;
+    la.need_flag = ca.mask;
+    la.cell_new = ca.cell_new;
+    la.nc = L.nc;
+    la.nr = L.nr;
+    la.W = L.W;
+    la.H = L.H;
+    la.frame_step = frame_stride;
+    la.ws_step = L.ws_step;
+    la.cells_step = L.ncell;
+
+    kpd::CompactArgs cp{};
+    cp.ncell = L.ncell;
+    cp.last = n_frames - 1;
+    cp.Kw = L.Kw;
+    cp.list_cap = L.cap;
+    cp.list_stride = L.list_stride;
+    cp.sparse = ca.sparse;
+    cp.cell_base = ca.cbase;
+    cp.marks = ca.marks;
+    cp.own_count = ca.cell_new;
+    cp.prev_list = s->at<kpd_keypoint>(L.off_list[fp]);
+    cp.prev_count = s->at<uint32_t>(L.off_cnt[fp]);
+    cp.prev_offs = s->at<uint32_t>(L.off_off[fp]);
+    cp.lists = s->at<kpd_keypoint>(L.off_clist);
+    cp.counts = s->at<uint32_t>(L.off_ccount);
+    cp.offs = s->at<uint32_t>(L.off_coffs);
+    cp.totals = s->at<uint32_t>(L.off_ctotal);
+    cp.next_list = s->at<kpd_keypoint>(L.off_list[fc]);
+    cp.next_count = s->at<uint32_t>(L.off_cnt[fc]);
+    cp.next_offs = s->at<uint32_t>(L.off_off[fc]);
+    cp.next_total = s->at<uint32_t>(L.off_total) + fc;
+    cp.sad_chunk = s->at<uint32_t>(L.off_csad);
+    cp.sad_stats = s->at<uint32_t>(L.off_sadstat);
+    cp.sad_single_next = s->at<uint32_t>(L.off_sadnext);
+    cp.work_count = s->at<uint32_t>(L.off_cwork);
+
+    // marks and scored cells of every frame, the layers of every frame,
+    // scores and suppression where needed, the marked cells' keypoints,
+    // then each frame's D by Eq. 1 (the newest frame up to it that marked
+    // a cell, else the list before the chunk)
+    hipError_t e = kpd::launch_ls_mask_chunk(ca, s->stream);
+    if (e == hipSuccess) e = build_layers(L.g, frames, pitch, ws, s->stream, n_frames, frame_stride, L.ws_step);
+    if (e == hipSuccess) e = kpd::launch_lay_score_nms(la, s->stream, n_frames);
+    if (e == hipSuccess) e = kpd::launch_ls_write_chunk(ca, la, s->stream);
+    if (e == hipSuccess) e = kpd::launch_compact_chunk(cp, n_frames, s->stream);
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_push_frames");
+    s->fb = fc;
+    s->prev = frames + (size_t)(n_frames - 1) * frame_stride;
+    s->prev_pitch = pitch;
+    s->force = false;
+    s->n_pushed += (uint64_t)n_frames;
+    s->chunk_n = n_frames;
+    return KPD_OK;
+}
+
+int kpd_lstream_get_chunk(kpd_lstream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count)
+{
+    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!count) return kpd::api_fail(KPD_EINVAL, "count is NULL");
+    if (i < 0 || i >= s->chunk_n) return kpd::api_fail(KPD_EINVAL, "no such frame in the last chunk");
+    if (i == s->chunk_n - 1) return kpd_lstream_get(s, out, capacity, count, nullptr);   // D_n itself
+    const LsLayout& L = s->L;
+    uint32_t total = 0;
+    hipError_t e = hipMemcpyAsync(&total, s->at<uint32_t>(L.off_ctotal) + i, 4, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_get_chunk");
+    total = std::min(total, L.cap);
+    *count = total;
+    if (total > capacity) return kpd::api_fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
+    if (total > 0) {
+        if (!out) return kpd::api_fail(KPD_EINVAL, "out is NULL");
+        e = hipMemcpyAsync(out, s->at<kpd_keypoint>(L.off_clist) + L.list_stride * (size_t)i,
+                           (size_t)total * sizeof(kpd_keypoint), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_get_chunk");
+    }
     return KPD_OK;
 }
 

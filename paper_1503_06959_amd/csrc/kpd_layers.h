@@ -52,6 +52,11 @@ struct LayArgs {
     const uint8_t* need_flag;
     uint32_t* cell_new;   // keypoints found per cell (the masked stream; NULL otherwise)
     int nc, nr, W, H;
+    // chunks: frame j's level 0 lies frame_step bytes past plane[0], its
+    // other planes and its score, flag and block-count maps ws_step bytes
+    // past frame 0's, its need and count arrays cells_step entries past
+    size_t frame_step, ws_step;
+    int cells_step;
 };
 
 // The masked stream over these layers: per-cell mask, Eq. 1 with cells
@@ -86,15 +91,47 @@ struct LsArgs {
 hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s);
 hipError_t launch_ls_emit(const LsArgs& a, const LayArgs& l, hipStream_t s);
 
+// A chunk of the masked stream over these layers (T_H off): frame j at
+// frames + j * stride (the frame before the chunk: prev0), its per-cell
+// mask, scored-cell flags and suppression counts at j * ncell, mark words
+// (cells x Kw, bit j = frame j) for the chunk compaction, and the marked
+// cells' keypoints at fixed per-cell bases of frame j's sparse list.
+struct LsChunkArgs {
+    const uint8_t* frames;
+    size_t stride;
+    int pitch;
+    const uint8_t* prev0;
+    int prev0_pitch;
+    int n_frames, force0, all_marked;
+    int nc, nr, ncell, Kw;
+    int32_t id_thresh;
+    const uint32_t* xs;
+    const uint32_t* ys;
+    uint8_t* mask;               // frames x cells
+    uint8_t* need;               // frames x cells
+    uint32_t* cell_new;          // frames x cells
+    unsigned long long* marks;   // cells x Kw
+    uint8_t* last_mask;          // the last frame's mask, the stream's reported M_n
+    kpd_keypoint* sparse;        // frame j's at sparse + j * list_stride
+    const uint32_t* cbase;       // cell c's first entry in a sparse list
+    size_t list_stride;
+    uint32_t cap;
+    int rx, ry;
+};
+
+hipError_t launch_ls_mask_chunk(const LsChunkArgs& a, hipStream_t s);
+hipError_t launch_ls_write_chunk(const LsChunkArgs& a, const LayArgs& l, hipStream_t s);
+
 // Two halvings of a chain (src -> d1 -> d2; d2 absent when w2 = 0), and the
 // 1.5x downsampling of the frame with the halving after it (d1 absent when
-// w1 = 0).
+// w1 = 0). `frames` consecutive frames of a chunk: sources sstep bytes
+// apart, destinations dstep bytes apart.
 hipError_t launch_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1, uint8_t* d2, int w2, int h2,
-                           hipStream_t s);
+                           hipStream_t s, int frames = 1, size_t sstep = 0, size_t dstep = 0);
 hipError_t launch_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0, uint8_t* d1, int w1, int h1,
-                            hipStream_t s);
+                            hipStream_t s, int frames = 1, size_t sstep = 0, size_t dstep = 0);
 hipError_t launch_lay_detect(const LayArgs& a, hipStream_t s);
-hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s);
+hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s, int frames = 1);
 hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const uint32_t* count, uint32_t cap,
                              kpd_refined* out, hipStream_t s);
 

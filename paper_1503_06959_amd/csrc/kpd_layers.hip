@@ -17,14 +17,18 @@ __constant__ int8_t kLayRingDy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0,
 // Two levels of a chain per launch. k_lay_quad: a thread per 2x2 quad of
 // level d1 (each pixel the 2x2 mean of src, round half up, for the quad
 // pixels inside d1) and, when the quad lies inside d2's reach, the d2 pixel
-// that is the mean of the quad; d2 may be absent (w2 = 0).
+// that is the mean of the quad; d2 may be absent (w2 = 0). Frame z of a
+// chunk (blockIdx.z) reads src + z * sstep and writes d1, d2 + z * dstep.
 __device__ __forceinline__ int mean4(int a, int b, int c, int d) { return (a + b + c + d + 2) >> 2; }
 
 __global__ __launch_bounds__(256) void k_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1,
-                                                  uint8_t* d2, int w2, int h2)
+                                                  uint8_t* d2, int w2, int h2, size_t sstep, size_t dstep)
 {
     const int qx = blockIdx.x * 16 + (threadIdx.x & 15), qy = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (2 * qx >= w1 || 2 * qy >= h1) return;
+    src += blockIdx.z * sstep;
+    d1 += blockIdx.z * dstep;
+    if (w2 > 0) d2 += blockIdx.z * dstep;
     int v[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -44,12 +48,16 @@ __global__ __launch_bounds__(256) void k_lay_quad(const uint8_t* src, int spitch
 // block (a, b) of the frame writes the block's 2x2 outputs of d_0 (output
 // (2a+p, 2b+q) = the rounded mean over the 1.5 x 1.5 area it covers,
 // weights (2, 1, 0) or (0, 1, 2) along each axis, over 9) and, when d_1 is
-// built here, their mean (d_1 has exactly one pixel per block).
+// built here, their mean (d_1 has exactly one pixel per block). Frames of a
+// chunk as in k_lay_quad.
 __global__ __launch_bounds__(256) void k_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0,
-                                                   uint8_t* d1, int w1, int h1)
+                                                   uint8_t* d1, int w1, int h1, size_t sstep, size_t dstep)
 {
     const int a = blockIdx.x * 16 + (threadIdx.x & 15), b = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (2 * a >= w0 || 2 * b >= h0) return;
+    src += blockIdx.z * sstep;
+    d0 += blockIdx.z * dstep;
+    if (w1 > 0) d1 += blockIdx.z * dstep;
     const uint8_t* s = src + (size_t)(3 * b) * spitch + 3 * a;
     int r[3][3];
 #pragma unroll
@@ -114,18 +122,27 @@ __device__ __forceinline__ int pixel_cell(const LayArgs& a, int l, int x, int y)
     return (int)(((long long)Y * a.nr) / a.H) * a.nc + (int)(((long long)X * a.nc) / a.W);
 }
 
+// Frame j (blockIdx.y) of a chunk: its level 0 frame_step bytes past
+// frame 0's, its other layers, scores, flags and block counts ws_step bytes
+// past, its per-cell arrays cells_step entries past.
+__device__ __forceinline__ const uint8_t* frame_plane(const LayArgs& a, int l, int j)
+{
+    return a.plane[l] + (size_t)j * (l == 0 ? a.frame_step : a.ws_step);
+}
+
 __global__ __launch_bounds__(kLayBlock) void k_lay_score(LayArgs a)
 {
     const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
     if (i >= a.N) return;
+    const int j = blockIdx.y;
     const int l = layer_of(a, i);
     const uint32_t r = i - a.base[l];
     const int w = a.w[l], h = a.h[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
     int v = 0;
-    const bool need = !a.need_score || a.need_score[pixel_cell(a, l, x, y)];
+    const bool need = !a.need_score || a.need_score[(size_t)j * a.cells_step + pixel_cell(a, l, x, y)];
     if (need && x >= 3 && y >= 3 && x < w - 3 && y < h - 3)
-        v = layer_score(a.plane[l] + (size_t)y * a.pitch[l] + x, a.pitch[l], a.t);
-    a.score[i] = (uint16_t)v;
+        v = layer_score(frame_plane(a, l, j) + (size_t)y * a.pitch[l] + x, a.pitch[l], a.t);
+    a.score[(size_t)j * (a.ws_step >> 1) + i] = (uint16_t)v;
 }
 
 // A pixel with V > 0 is kept when no pixel of its own layer or an adjacent
@@ -137,15 +154,18 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
 {
     __shared__ uint32_t s_cnt[kLayBlock / 64];
     const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
+    const int j = blockIdx.y;
+    const uint16_t* score = a.score + (size_t)j * (a.ws_step >> 1);
+    const size_t cj = (size_t)j * a.cells_step;
     bool keep = false;
     if (i < a.N) {
-        const int v = a.score[i];
+        const int v = score[i];
         if (v > 0) {
             const int l = layer_of(a, i);
             const uint32_t r = i - a.base[l];
             const int w = a.w[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
             const int cell = a.need_flag ? pixel_cell(a, l, x, y) : 0;
-            keep = !a.need_flag || a.need_flag[cell];
+            keep = !a.need_flag || a.need_flag[cj + cell];
             // Between adjacent layers the size ratio is 1.5 or 4/3, so a
             // range holds at most floor(ratio + 2) = 3 pixels a side: the
             // reads of a 3 x 3 window per layer are issued together, with
@@ -158,7 +178,7 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
                 const int S1 = a.S[l], S2 = a.S[m], wm = a.w[m], hm = a.h[m];
                 const int x0 = max((x * S1 + S2 - 1) / S2 - 1, 0), x1 = min(((x + 1) * S1) / S2, wm - 1);
                 const int y0 = max((y * S1 + S2 - 1) / S2 - 1, 0), y1 = min(((y + 1) * S1) / S2, hm - 1);
-                const uint16_t* sc = a.score + a.base[m];
+                const uint16_t* sc = score + a.base[m];
                 auto ranks_above = [&](int qx, int qy) {
                     const int vq = sc[(size_t)qy * wm + qx];
                     return vq > v || (vq == v && (m < l || (m == l && (qy < y || (qy == y && qx < x)))));
@@ -177,9 +197,9 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
                 }
             }
             keep = keep && !above;
-            if (keep && a.cell_new) atomicAdd(&a.cell_new[cell], 1u);
+            if (keep && a.cell_new) atomicAdd(&a.cell_new[cj + cell], 1u);
         }
-        a.flag[i] = keep ? 1 : 0;
+        a.flag[(size_t)j * a.ws_step + i] = keep ? 1 : 0;
     }
     const uint64_t b = __ballot(keep);
     if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = (uint32_t)__popcll(b);
@@ -187,7 +207,7 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
     if (threadIdx.x == 0) {
         uint32_t c = 0;
         for (int k = 0; k < kLayBlock / 64; ++k) c += s_cnt[k];
-        a.bcount[blockIdx.x] = c;
+        a.bcount[(size_t)j * (a.ws_step >> 2) + blockIdx.x] = c;
     }
 }
 
@@ -464,7 +484,138 @@ __global__ __launch_bounds__(kLsWrite) void k_ls_write(LsArgs a, LayArgs l)
     }
 }
 
+// ------------------------------------------- chunks of the masked stream
+
+// Marks of a chunk, a workgroup per (cell, frame): every cell of a forced
+// frame 0 or when the parameters mark every cell, otherwise the cell's
+// summed |I_j - I_{j-1}| over its level-0 box against T_I times its area
+// (I_{-1}: the frame before the chunk).
+__global__ __launch_bounds__(256) void k_ls_mask_chunk(LsChunkArgs a)
+{
+    __shared__ unsigned long long s_sum[4];
+    const int c = blockIdx.x, j = blockIdx.y, cc = c % a.nc, rr = c / a.nc;
+    const size_t jc = (size_t)j * a.ncell;
+    if (threadIdx.x == 0) a.cell_new[jc + c] = 0;   // counted by frame j's suppression
+    bool mark = a.all_marked || (a.force0 && j == 0);
+    if (!mark) {
+        const uint8_t* cur = a.frames + (size_t)j * a.stride;
+        const uint8_t* prev = j ? a.frames + (size_t)(j - 1) * a.stride : a.prev0;
+        const int pp = j ? a.pitch : a.prev0_pitch;
+        const int x0 = (int)a.xs[cc], x1 = (int)a.xs[cc + 1], y0 = (int)a.ys[rr], y1 = (int)a.ys[rr + 1];
+        const int bw = x1 - x0, n = bw * (y1 - y0);
+        unsigned long long sum = 0;
+        for (int q = threadIdx.x; q < n; q += 256) {
+            const int y = y0 + q / bw, x = x0 + q % bw;
+            sum += (unsigned)abs((int)cur[(size_t)y * a.pitch + x] - (int)prev[(size_t)y * pp + x]);
+        }
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = sum;
+        __syncthreads();
+        const unsigned long long t = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        mark = (long long)t > (long long)a.id_thresh * (long long)n;
+    }
+    if (threadIdx.x == 0) {
+        a.mask[jc + c] = mark ? 1 : 0;
+        if (j == a.n_frames - 1) a.last_mask[c] = mark ? 1 : 0;
+    }
+}
+
+// Per frame (a workgroup each): the cells scored, those within rx columns
+// and ry rows of a marked cell; per (cell, 64 frames) (the same grid's
+// threads): the cell's mark word.
+__global__ __launch_bounds__(256) void k_ls_dilate_chunk(LsChunkArgs a)
+{
+    const int j = blockIdx.x;
+    if (j < a.n_frames) {
+        const uint8_t* m = a.mask + (size_t)j * a.ncell;
+        for (int c = threadIdx.x; c < a.ncell; c += 256) {
+            const int cc = c % a.nc, rr = c / a.nc;
+            uint8_t need = 0;
+            for (int r2 = max(rr - a.ry, 0); r2 <= min(rr + a.ry, a.nr - 1) && !need; ++r2)
+                for (int c2 = max(cc - a.rx, 0); c2 <= min(cc + a.rx, a.nc - 1); ++c2)
+                    if (m[r2 * a.nc + c2]) {
+                        need = 1;
+                        break;
+                    }
+            a.need[(size_t)j * a.ncell + c] = need;
+        }
+    }
+    const int nw = (a.n_frames + 63) >> 6;
+    for (int g = blockIdx.x * 256 + threadIdx.x; g < a.ncell * nw; g += gridDim.x * 256) {
+        const int c = g / nw, w = g - c * nw;
+        unsigned long long bits = 0;
+        for (int k = 0; k < 64 && w * 64 + k < a.n_frames; ++k)
+            if (a.mask[(size_t)(w * 64 + k) * a.ncell + c]) bits |= 1ull << k;
+        a.marks[(size_t)c * a.Kw + w] = bits;
+    }
+}
+
+// A marked (cell, frame)'s keypoints at the cell's base of the frame's
+// sparse list: the flagged pixels of its boxes layer by layer in row-major
+// order (as k_ls_write), as many as the suppression counted.
+__global__ __launch_bounds__(kLsWrite) void k_ls_write_chunk(LsChunkArgs a, LayArgs l)
+{
+    __shared__ uint32_t s_cnt[kLsWrite / 64];
+    const int c = blockIdx.x, j = blockIdx.y, cc = c % a.nc, rr = c / a.nc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t jc = (size_t)j * a.ncell;
+    if (!a.mask[jc + c]) return;
+    const uint8_t* flag = l.flag + (size_t)j * l.ws_step;
+    const uint16_t* score = l.score + (size_t)j * (l.ws_step >> 1);
+    kpd_keypoint* list = a.sparse + (size_t)j * a.list_stride;
+    const uint32_t dst = a.cbase[c], want = a.cell_new[jc + c];
+    uint32_t run = 0;
+    for (int m = 0; m < l.L && run < want; ++m) {
+        const int x0 = (int)a.xs[m * (a.nc + 1) + cc], x1 = (int)a.xs[m * (a.nc + 1) + cc + 1];
+        const int y0 = (int)a.ys[m * (a.nr + 1) + rr], y1 = (int)a.ys[m * (a.nr + 1) + rr + 1];
+        const int bw = x1 - x0, n = bw * (y1 - y0);
+        const size_t fb = l.base[m];
+        for (int base = 0; base < n && run < want; base += kLsWrite) {
+            const int q = base + threadIdx.x;
+            int x = 0, y = 0;
+            bool f = false;
+            if (q < n) {
+                y = y0 + q / bw;
+                x = x0 + q % bw;
+                f = flag[fb + (size_t)y * l.w[m] + x] != 0;
+            }
+            const uint64_t b = __ballot(f);
+            if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(b);
+            __syncthreads();
+            uint32_t pos = run + (uint32_t)__popcll(b & ((1ull << lane) - 1)), total = 0;
+            for (int k = 0; k < kLsWrite / 64; ++k) {
+                pos += k < wave ? s_cnt[k] : 0;
+                total += s_cnt[k];
+            }
+            if (f && dst + pos < a.cap) {
+                kpd_keypoint kp;
+                kp.x = (uint16_t)x;
+                kp.y = (uint16_t)y;
+                kp.octave = (uint8_t)m;
+                kp.pad = 0;
+                kp.score = score[fb + (size_t)y * l.w[m] + x];
+                list[dst + pos] = kp;
+            }
+            run += total;
+            __syncthreads();   // s_cnt is rewritten by the next round
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_ls_mask_chunk(const LsChunkArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ls_mask_chunk, dim3(a.ncell, a.n_frames), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ls_dilate_chunk, dim3(a.n_frames), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_write_chunk(const LsChunkArgs& a, const LayArgs& l, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ls_write_chunk, dim3(a.ncell, a.n_frames), dim3(kLsWrite), 0, s, a, l);
+    return hipGetLastError();
+}
 
 hipError_t launch_ls_mask(const LsArgs& a, hipStream_t s)
 {
@@ -480,11 +631,11 @@ hipError_t launch_ls_emit(const LsArgs& a, const LayArgs& l, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s)
+hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s, int frames)
 {
-    if (a.nblocks > 0) {
-        hipLaunchKernelGGL(k_lay_score, dim3(a.nblocks), dim3(kLayBlock), 0, s, a);
-        hipLaunchKernelGGL(k_lay_nms, dim3(a.nblocks), dim3(kLayBlock), 0, s, a);
+    if (a.nblocks > 0 && frames > 0) {
+        hipLaunchKernelGGL(k_lay_score, dim3(a.nblocks, frames), dim3(kLayBlock), 0, s, a);
+        hipLaunchKernelGGL(k_lay_nms, dim3(a.nblocks, frames), dim3(kLayBlock), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -499,22 +650,22 @@ hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const u
 }
 
 hipError_t launch_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1, uint8_t* d2, int w2, int h2,
-                           hipStream_t s)
+                           hipStream_t s, int frames, size_t sstep, size_t dstep)
 {
-    if (w1 <= 0 || h1 <= 0) return hipSuccess;
+    if (w1 <= 0 || h1 <= 0 || frames < 1) return hipSuccess;
     const int qx = (w1 + 1) / 2, qy = (h1 + 1) / 2;
-    hipLaunchKernelGGL(k_lay_quad, dim3((qx + 15) / 16, (qy + 15) / 16), dim3(256), 0, s, src, spitch, d1, w1, h1, d2,
-                       w2, h2);
+    hipLaunchKernelGGL(k_lay_quad, dim3((qx + 15) / 16, (qy + 15) / 16, frames), dim3(256), 0, s, src, spitch, d1, w1,
+                       h1, d2, w2, h2, sstep, dstep);
     return hipGetLastError();
 }
 
 hipError_t launch_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0, uint8_t* d1, int w1, int h1,
-                            hipStream_t s)
+                            hipStream_t s, int frames, size_t sstep, size_t dstep)
 {
-    if (w0 <= 0 || h0 <= 0) return hipSuccess;
+    if (w0 <= 0 || h0 <= 0 || frames < 1) return hipSuccess;
     const int bx = w0 / 2, by = h0 / 2;
-    hipLaunchKernelGGL(k_lay_third, dim3((bx + 15) / 16, (by + 15) / 16), dim3(256), 0, s, src, spitch, d0, w0, h0, d1,
-                       w1, h1);
+    hipLaunchKernelGGL(k_lay_third, dim3((bx + 15) / 16, (by + 15) / 16, frames), dim3(256), 0, s, src, spitch, d0, w0,
+                       h0, d1, w1, h1, sstep, dstep);
     return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "tcd_device_result", "tcd_reset", "tcd_close", "kpd_layers_bytes", "kpd_detect_layers",
             "kpd_detect_layers_static", "batch_set_single_launch",
             "kpd_layer_plane", "kpd_refine_layers", "kpd_lstream_bytes", "kpd_lstream_open", "kpd_lstream_push",
-            "kpd_lstream_get", "kpd_lstream_reset", "kpd_lstream_close")
+            "kpd_lstream_get", "kpd_lstream_reset", "kpd_lstream_close", "kpd_lstream_push_frames",
+            "kpd_lstream_get_chunk")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
 TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2"),
                         ("sad", "<u4")])
@@ -124,6 +125,8 @@ def _load() -> ctypes.CDLL:
     L.kpd_lstream_open.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), P, sz, P, ctypes.POINTER(P)]
     L.kpd_lstream_push.argtypes = [P, P, sz, ctypes.c_int]
     L.kpd_lstream_get.argtypes = [P, P, sz, ctypes.POINTER(sz), P]
+    L.kpd_lstream_push_frames.argtypes = [P, P, sz, sz, ctypes.c_int]
+    L.kpd_lstream_get_chunk.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
     L.kpd_lstream_reset.argtypes = [P]
     L.kpd_lstream_close.argtypes = [P]
     L.kpd_layer_plane.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz),
@@ -677,6 +680,27 @@ class LayerStream:
                                     FRAME_DEVICE_RETAIN if retain else FRAME_DEVICE))
         if retain:
             self._held = [self._held[1], frame]
+
+    def push_chunk(self, frames: torch.Tensor) -> None:
+        """Consecutive frames [n, H, W] (a CUDA uint8 tensor with unit column
+        stride, n <= chunk_frames) in one call, read in place."""
+        if not (isinstance(frames, torch.Tensor) and frames.device.type == "cuda" and frames.dtype == torch.uint8
+                and frames.dim() == 3 and frames.stride(2) == 1):
+            raise ValueError("frames must be a CUDA uint8 [n, H, W] tensor with unit column stride")
+        _check(lib.kpd_lstream_push_frames(self.handle, frames.data_ptr(), frames.stride(0), frames.stride(1),
+                                           frames.shape[0]))
+        self._held = [self._held[1], frames]
+
+    def chunk_keypoints(self, i: int, capacity: int = 4096) -> np.ndarray:
+        """D of frame i of the last push_chunk."""
+        out = np.zeros(max(capacity, 1), KEYPOINT_DTYPE)
+        cnt = ctypes.c_size_t()
+        rc = lib.kpd_lstream_get_chunk(self.handle, i, out.ctypes.data, len(out), ctypes.byref(cnt))
+        if rc == KPD_ETRUNC:
+            out = np.zeros(cnt.value, KEYPOINT_DTYPE)
+            rc = lib.kpd_lstream_get_chunk(self.handle, i, out.ctypes.data, len(out), ctypes.byref(cnt))
+        _check(rc)
+        return out[:cnt.value].copy()
 
     def keypoints(self, capacity: int = 4096) -> Tuple[np.ndarray, np.ndarray]:
         out = np.zeros(max(capacity, 1), KEYPOINT_DTYPE)
