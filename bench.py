@@ -470,6 +470,29 @@ def intra_octave_workload(kpd, wl: Workload, args) -> dict:
         streams[name] = {"value": round(wl.F * wl.W * wl.H / lt / 1e6, 2), "unit": "Mpixel/s",
                          "frames_per_s": round(wl.F / lt, 1), "marked_cell_frac": round(float(np.mean(marked)), 4),
                          "keypoints_per_frame": round(float(np.mean(kps)), 1)}
+        # the same stream in chunks of consecutive frames (kpd_lstream_push_frames)
+        K = chunk_of(args, wl)
+        lc = kpd.LayerStream(wl.W, wl.H, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, ti,
+                                                         d.kb_thresh, 0, K))
+
+        def lc_pass():
+            kpd._check(kpd.lib.kpd_lstream_reset(lc.handle))
+            base, stride = wl.dev.data_ptr(), wl.W * wl.H
+            for i in range(0, wl.F, K):
+                kpd._check(kpd.lib.kpd_lstream_push_frames(lc.handle, base + i * stride, stride, wl.W,
+                                                           min(K, wl.F - i)))
+
+        lc_pass()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lc_pass()
+        torch.cuda.synchronize()
+        ct = (time.perf_counter() - t0) / steps
+        lc.close()
+        streams[name + "_chunked"] = {"value": round(wl.F * wl.W * wl.H / ct / 1e6, 2), "unit": "Mpixel/s",
+                                      "frames_per_s": round(wl.F / ct, 1), "chunk": K,
+                                      "over_per_frame_push": round(lt / ct, 2)}
     return {"value": round(wl.F * wl.W * wl.H / dt / 1e6, 2), "unit": "Mpixel/s", "frames_per_s": round(wl.F / dt, 1),
             "stream": streams,
             "gpu_us_per_frame": round(e0.elapsed_time(e1) * 1e3 / wl.F, 3),
@@ -479,7 +502,8 @@ def intra_octave_workload(kpd, wl: Workload, args) -> dict:
             "what": f"{wl.name}, full-frame detection over {2 * d.n_octaves} layers (octaves and intra-octaves), "
                     f"one kpd_detect_layers call per frame ({layer_launches(d.n_octaves)} launches); with refinement, "
                     "one kpd_refine_layers call after it; `stream`: the masked stream over the same layers "
-                    "(per-cell mask, Eq. 1), one kpd_lstream_push per frame, masked and full-frame"}
+                    "(per-cell mask, Eq. 1), one kpd_lstream_push per frame, masked and full-frame, and "
+                    "kpd_lstream_push_frames chunks of the whole video (*_chunked)"}
 
 
 def layer_study(kpd, wl: Workload, args) -> dict:
