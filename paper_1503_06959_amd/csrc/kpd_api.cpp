@@ -90,7 +90,7 @@ struct Layout {
     // merge pass's LDS
     int fpw = 0, nwords_max = 0, dc_max = 0;
     size_t off_pflag = 0, off_fp = 0, off_msparse = 0, off_mcount = 0, off_pbase = 0;
-    int pm_pres = 0, pm_score = 0, pm_fp = 0, pm_lds = 0;
+    int pm_pres = 0, pm_score = 0, pm_fp = 0, pm_ents = 0, pm_lds = 0, pm_batch = 1;
     // the group detector of full-frame chunks: gx x gy cells per workgroup
     // and the groups' layouts
     int gx = 1, gy = 1, ngroups = 0, glds = 0, gthreads = 256;
@@ -191,6 +191,7 @@ bool group_layouts(const Layout& L, int gx, int gy, int waves, std::vector<kpd::
 
 constexpr int kGroupWaves = 4;           // 256-thread workgroups for one-cell layouts
 constexpr int kGroupLdsDefault = 48 * 1024;   // default groups: three workgroups per CU
+constexpr uint32_t kPixelStagedMaxima = 1024;  // maxima of a batch the per-pixel merge stages in LDS
 
 // Threads of a workgroup of the listed-cell detection of chunks. Few cells
 // a frame mean few listed items, whose latency decides: more waves per item
@@ -336,7 +337,12 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->pm_pres = 0;
     L->pm_score = kpd::round_up(nwords_max * 8, 16);
     L->pm_fp = kpd::round_up(L->pm_score + (int)cell_cap_max * 2, 16);
-    L->pm_lds = L->pm_fp + L->fpw * 8;
+    // frames whose change words the merge stages at once: about 24 KB, less
+    // when the cell's maps leave less of the 60 KB the pass may take
+    const int pm_room = 60 * 1024 - L->pm_fp - (int)kPixelStagedMaxima * (int)sizeof(kpd_keypoint) - 16;
+    L->pm_batch = std::max(1, std::min(32, std::min(24 * 1024, pm_room) / std::max(1, L->fpw * 8)));
+    L->pm_ents = kpd::round_up(L->pm_fp + L->pm_batch * L->fpw * 8, 16);
+    L->pm_lds = L->pm_ents + (int)kPixelStagedMaxima * (int)sizeof(kpd_keypoint);
     if (L->list_cap1 > 0xFFFFFFF0ull) { *why = "keypoint list too large"; return false; }
     L->lds_bytes = std::max(lds, 16);
     {
@@ -1294,6 +1300,8 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
             pa.layouts = s->at<kpd::CellLayout>(L.off_layouts);
             pa.cell_base = s->at<uint32_t>(L.off_cbase);
             pa.list_cap = (uint32_t)L.list_cap;
+            pa.sparse = reinterpret_cast<const kpd_keypoint*>(s->arena + L.off_sparse);
+            pa.own = s->at<uint32_t>(L.off_own);
             pa.pbase = s->at<uint32_t>(L.off_pbase);
             pa.merged = reinterpret_cast<kpd_keypoint*>(s->arena + L.off_msparse);
             pa.mcount = s->at<uint32_t>(L.off_mcount);
@@ -1306,7 +1314,10 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
             pa.lds_pres = L.pm_pres;
             pa.lds_score = L.pm_score;
             pa.lds_fp = L.pm_fp;
+            pa.lds_ents = L.pm_ents;
             pa.lds_bytes = L.pm_lds;
+            pa.batch = L.pm_batch;
+            pa.ents_cap = kPixelStagedMaxima;
         }
         if (pixel_diff) {
             // changed mask pixels, marks of the cells with one, detection of

@@ -285,6 +285,8 @@ struct PixelChunkArgs {
     const CellLayout* layouts;
     const uint32_t* cell_base;                  // F lists' bases
     uint32_t list_cap;                          // F lists' entries
+    const kpd_keypoint* sparse;                 // frame j's F list at sparse + j * list_stride
+    const uint32_t* own;                        // F counts, frames x cells
     const uint32_t* pbase;                      // merged lists' bases (decision pixels of the earlier cells)
     kpd_keypoint* merged;                       // frame j's at merged + j * list_stride
     uint32_t* mcount;                           // frames x cells
@@ -294,7 +296,11 @@ struct PixelChunkArgs {
     const uint32_t* prev_count;
     const uint32_t* prev_offs;
     uint32_t prev_cap;
-    int lds_pres, lds_score, lds_fp, lds_bytes; // dynamic LDS of the merge pass
+    // the merge pass's dynamic LDS: map bits, scores, the staged change
+    // words of `batch` frames and up to ents_cap staged maxima
+    int lds_pres, lds_score, lds_fp, lds_ents, lds_bytes;
+    int batch;
+    uint32_t ents_cap;
 };
 
 hipError_t launch_pixel_diff_chunk(const PixelChunkArgs& a, hipStream_t s);

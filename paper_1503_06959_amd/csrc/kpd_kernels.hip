@@ -2158,7 +2158,11 @@ __global__ __launch_bounds__(64 * kDiffWaves) void k_pixel_diff_chunk(PixelChunk
 // feature; a forced frame replaces everything), and the map is written in
 // decision order, (octave, y, x), at the cell's per-pixel base of frame j's
 // merged list. The map starts from the cell's entries before the chunk.
+// The listed frames' change bits and maxima are staged in LDS a batch of
+// frames at a time (one round of loads per batch), so the walk itself
+// waits on no memory.
 constexpr int kMergeBlock = 256;
+constexpr int kMergeBatchMax = 32;   // listed frames staged at once
 
 __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArgs a)
 {
@@ -2167,11 +2171,15 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
     __shared__ int s_kx0[KPD_MAX_OCTAVES], s_ky0[KPD_MAX_OCTAVES], s_nx[KPD_MAX_OCTAVES], s_boff[KPD_MAX_OCTAVES];
     __shared__ int s_w[KPD_MAX_OCTAVES], s_h[KPD_MAX_OCTAVES];
     __shared__ uint32_t s_part[kMergeBlock / 64];
+    __shared__ uint16_t s_frames[KPD_MAX_CHUNK];
+    __shared__ uint32_t s_cnt[kMergeBatchMax], s_eoff[kMergeBatchMax + 1];
+    __shared__ int s_nl, s_nb;
     const int c = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     unsigned long long* pres = reinterpret_cast<unsigned long long*>(sm + a.lds_pres);
     uint16_t* score = reinterpret_cast<uint16_t*>(sm + a.lds_score);
-    unsigned long long* fpb = reinterpret_cast<unsigned long long*>(sm + a.lds_fp);
+    unsigned long long* fps = reinterpret_cast<unsigned long long*>(sm + a.lds_fp);
+    kpd_keypoint* ents = reinterpret_cast<kpd_keypoint*>(sm + a.lds_ents);
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
@@ -2193,6 +2201,19 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
             s_boff[l] = boff;
             boff += (sp.npx + 63) & ~63;
         }
+        // the listed frames of this chunk, in order
+        const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
+        int n = 0;
+        for (int q = 0; q <= (a.n_frames - 1) >> 6; ++q) {
+            unsigned long long w = mw[q];
+            if (q == (a.n_frames - 1) >> 6 && ((a.n_frames - 1) & 63) != 63)
+                w &= (2ull << ((a.n_frames - 1) & 63)) - 1ull;
+            while (w) {
+                s_frames[n++] = (uint16_t)(64 * q + __builtin_ctzll(w));
+                w &= w - 1ull;
+            }
+        }
+        s_nl = n;
     }
     __syncthreads();
     const int nw = L.nwords, O = a.O;
@@ -2205,8 +2226,8 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
         if (x < d.x0 || x >= d.x1 || y < d.y0 || y >= d.y1) return -1;
         return L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
     };
-    // the mask pixel of a feature at level o, (x, y) changed in this frame
-    auto changed_at = [&](int o, int x, int y) -> bool {
+    // the mask pixel of a feature at level o, (x, y) changed (change bits fpb)
+    auto changed_at = [&](const unsigned long long* fpb, int o, int x, int y) -> bool {
         const int l = a.one ? a.l_lo : o;
         const int kx = min((x << o) >> l, s_w[l] - 1) - s_kx0[l];
         const int ky = min((y << o) >> l, s_h[l] - 1) - s_ky0[l];
@@ -2225,51 +2246,81 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
         }
     }
     __syncthreads();
-    const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
     const uint32_t cb = a.cell_base[c], pb = a.pbase[c];
-    for (int q = 0; q < a.Kw; ++q) {
-        unsigned long long word = mw[q];
-        if (q == (a.n_frames - 1) >> 6 && ((a.n_frames - 1) & 63) != 63)
-            word &= (2ull << ((a.n_frames - 1) & 63)) - 1ull;   // frames of this chunk only
-        if (q > (a.n_frames - 1) >> 6) word = 0ull;
-        while (word) {
-            const int j = 64 * q + __builtin_ctzll(word);
-            word &= word - 1ull;
-            const bool forced = a.force0 && j == 0;
-            if (!forced) {
-                const unsigned long long* src = a.fp + ((size_t)j * a.ncell + c) * a.fpw;
-                for (int w = tid; w < a.fpw; w += kMergeBlock) fpb[w] = src[w];
+    const int nl = s_nl;
+    for (int b0 = 0; b0 < nl;) {
+        // the batch: up to a.batch listed frames whose maxima fit the staging
+        // area (the first frame always; past the area its maxima stay in
+        // global memory)
+        const int bm = min(a.batch, nl - b0);
+        if (tid < bm) {
+            const int j = s_frames[b0 + tid];
+            s_cnt[tid] = cb >= a.list_cap ? 0u : min(a.own[(size_t)j * a.ncell + c], a.list_cap - cb);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            int k = 0;
+            for (; k < bm; ++k) {
+                const uint32_t take = min(s_cnt[k], a.ents_cap);
+                if (k > 0 && acc + take > a.ents_cap) break;
+                s_eoff[k] = acc;
+                acc += take;
             }
-            __syncthreads();
+            s_eoff[k] = acc;
+            s_nb = k;
+        }
+        __syncthreads();
+        const int nb = s_nb;
+        for (int i = tid; i < nb * a.fpw; i += kMergeBlock) {
+            const int k = i / a.fpw;
+            fps[i] = a.fp[((size_t)s_frames[b0 + k] * a.ncell + c) * a.fpw + (i - k * a.fpw)];
+        }
+        const uint32_t tot = s_eoff[nb];
+        for (uint32_t i = tid; i < tot; i += kMergeBlock) {
+            int lo = 0, hi = nb - 1;   // the frame whose staged maxima hold entry i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_eoff[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            ents[i] = a.sparse[(size_t)s_frames[b0 + lo] * a.list_stride + cb + (i - s_eoff[lo])];
+        }
+        __syncthreads();
+        for (int k = 0; k < nb; ++k) {
+            const int j = s_frames[b0 + k];
+            const bool forced = a.force0 && j == 0;
+            const unsigned long long* fpb = fps + (size_t)k * a.fpw;
             // entries whose mask pixel changed leave (all, when forced)
             for (int w = tid; w < nw; w += kMergeBlock) {
-                unsigned long long k = pres[w], out = forced ? 0ull : k;
-                while (k && !forced) {
-                    const int b = __builtin_ctzll(k);
-                    k &= k - 1ull;
+                unsigned long long bits = pres[w], out = forced ? 0ull : bits;
+                while (bits && !forced) {
+                    const int b = __builtin_ctzll(bits);
+                    bits &= bits - 1ull;
                     const int i = w * 64 + b;
                     const int o = level_of(L.dc_start, O, i);
                     const unsigned r = (unsigned)(i - L.dc_start[o]);
                     const Box d = L.dec[o];
                     const int ry = (int)fast_div(r, L.dcm[o]);
-                    if (changed_at(o, d.x0 + (int)r - ry * box_w(d), d.y0 + ry)) out &= ~(1ull << b);
+                    if (changed_at(fpb, o, d.x0 + (int)r - ry * box_w(d), d.y0 + ry)) out &= ~(1ull << b);
                 }
                 pres[w] = out;
             }
             __syncthreads();
             // F_j's maxima whose mask pixel changed come in
-            const ChunkArgs& t = a.table[j];
-            const uint32_t nf = cb >= a.list_cap ? 0u : min(t.own_count[c], a.list_cap - cb);
+            const uint32_t nf = s_cnt[k], staged = s_eoff[k + 1] - s_eoff[k];
+            const kpd_keypoint* se = ents + s_eoff[k];
+            const kpd_keypoint* ge = a.sparse + (size_t)j * a.list_stride + cb;
             for (uint32_t e = tid; e < nf; e += kMergeBlock) {
-                const kpd_keypoint kp = t.d.list_cur[cb + e];
+                const kpd_keypoint kp = e < staged ? se[e] : ge[e];
                 const int i = index_of(kp.octave, kp.x, kp.y);
-                if (i < 0 || !(forced || changed_at(kp.octave, kp.x, kp.y))) continue;
+                if (i < 0 || !(forced || changed_at(fpb, kp.octave, kp.x, kp.y))) continue;
                 atomicOr(&pres[i >> 6], 1ull << (i & 63));
                 score[i] = kp.score;
             }
             __syncthreads();
             // D_j of the cell in decision order
-            uint32_t excl = 0, total = 0;
+            uint32_t total = 0;
             for (int w0 = 0; w0 < nw; w0 += kMergeBlock) {
                 const int w = w0 + tid;
                 const unsigned long long bits = w < nw ? pres[w] : 0ull;
@@ -2282,17 +2333,16 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
                 if (lane == 63) s_part[wave] = incl;
                 __syncthreads();
                 uint32_t before = total, sum = 0;
-                for (int k = 0; k < kMergeBlock / 64; ++k) {
-                    if (k < wave) before += s_part[k];
-                    sum += s_part[k];
+                for (int q = 0; q < kMergeBlock / 64; ++q) {
+                    if (q < wave) before += s_part[q];
+                    sum += s_part[q];
                 }
-                excl = before + incl - cnt;
                 kpd_keypoint* dst = a.merged + (size_t)j * a.list_stride + pb;
-                unsigned long long k = bits;
-                uint32_t at = excl;
-                while (k) {
-                    const int b = __builtin_ctzll(k);
-                    k &= k - 1ull;
+                unsigned long long m = bits;
+                uint32_t at = before + incl - cnt;
+                while (m) {
+                    const int b = __builtin_ctzll(m);
+                    m &= m - 1ull;
                     const int i = w * 64 + b;
                     const int o = level_of(L.dc_start, O, i);
                     const unsigned r = (unsigned)(i - L.dc_start[o]);
@@ -2308,10 +2358,11 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
                     ++at;
                 }
                 total += sum;
-                __syncthreads();   // s_part is reused
+                __syncthreads();   // s_part, and the map for the next frame
             }
             if (tid == 0) a.mcount[(size_t)j * a.ncell + c] = total;
         }
+        b0 += nb;
     }
 }
 
