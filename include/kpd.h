@@ -515,6 +515,34 @@ int kpd_lstream_get(kpd_lstream* s, kpd_keypoint* out, size_t capacity, size_t* 
 int kpd_lstream_push_frames(kpd_lstream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes,
                             int n_frames);
 int kpd_lstream_get_chunk(kpd_lstream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count);
+
+/* A batch of masked streams over the layers that share one frame size and
+ * one set of parameters: max_streams slots, each a stream of its own with
+ * kpd_lstream's rules, advanced together by ticks. A tick runs every slot
+ * with a staged frame in a fixed set of launches (the marks of every slot's
+ * cells, the layers of every slot's frame, scores and suppression where
+ * the marks need them, each slot's D_n by Eq. 1); slots without a frame keep
+ * their state. Results are exactly those of one kpd_lstream per slot.
+ * Parameters used: those of kpd_lstream but chunk_frames. The arena
+ * (caller-owned device memory, 256-byte aligned, >= kpd_lbatch_bytes)
+ * holds every slot's state. */
+typedef struct kpd_lbatch kpd_lbatch;
+size_t kpd_lbatch_bytes(int width, int height, const kpd_params* params, int max_streams);
+int kpd_lbatch_open(int width, int height, const kpd_params* params, int max_streams, void* dev_arena,
+                    size_t arena_bytes, void* hip_stream, kpd_lbatch** out);
+/* Stage slot's next frame: device memory read in place, as push_frame's
+ * KPD_FRAME_DEVICE_RETAIN frames (it must stay unchanged until the slot's
+ * next tick has completed, which reads it as I_{n-1}). KPD_ESTATE when a
+ * frame is already staged for the slot. */
+int kpd_lbatch_push(kpd_lbatch* b, int slot, const uint8_t* frame, size_t pitch_bytes);
+/* Run one tick (asynchronous on the batch's HIP stream). */
+int kpd_lbatch_tick(kpd_lbatch* b);
+/* Slot's D_n and M_n after its last tick, as kpd_lstream_get (waits);
+ * KPD_ESTATE before the slot's first tick. */
+int kpd_lbatch_get(kpd_lbatch* b, int slot, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask);
+/* The slot's next frame is treated as a first frame. */
+int kpd_lbatch_reset(kpd_lbatch* b, int slot);
+int kpd_lbatch_close(kpd_lbatch* b);
 int kpd_lstream_reset(kpd_lstream* s);
 int kpd_lstream_close(kpd_lstream* s);
 

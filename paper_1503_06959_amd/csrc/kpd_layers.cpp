@@ -213,7 +213,7 @@ void ls_tables(const LsLayout& L, std::vector<uint32_t>* xs, std::vector<uint32_
 // per launch. n frames of a chunk: frame j at frame + j * fstep, its
 // workspace at ws + j * wstep.
 hipError_t build_layers(const kpd::LayerGeom& g, const uint8_t* frame, int pitch, uint8_t* ws, hipStream_t s,
-                        int n = 1, size_t fstep = 0, size_t wstep = 0)
+                        int n = 1, size_t fstep = 0, size_t wstep = 0, const kpd::LbSlot* slots = nullptr)
 {
     const int O = g.L / 2;
     auto plane = [&](int l) { return ws + g.plane_off[l]; };
@@ -225,19 +225,19 @@ hipError_t build_layers(const kpd::LayerGeom& g, const uint8_t* frame, int pitch
         const int l1 = 2 * i, l2 = 2 * (i + 1);
         const bool two = i + 1 < O;
         e = kpd::launch_lay_quad(src, sp, plane(l1), g.w[l1], g.h[l1], two ? plane(l2) : nullptr, two ? g.w[l2] : 0,
-                                 two ? g.h[l2] : 0, s, n, i == 1 ? fstep : wstep, wstep);
+                                 two ? g.h[l2] : 0, s, n, i == 1 ? fstep : wstep, wstep, slots, i == 1 ? 1 : 0);
     }
     // intra-octaves: d_i = layer 2i + 1
     if (e == hipSuccess) {
         const bool d1 = O > 1;
         e = kpd::launch_lay_third(frame, pitch, plane(1), g.w[1], g.h[1], d1 ? plane(3) : nullptr, d1 ? g.w[3] : 0,
-                                  d1 ? g.h[3] : 0, s, n, fstep, wstep);
+                                  d1 ? g.h[3] : 0, s, n, fstep, wstep, slots);
     }
     for (int i = 2; i < O && e == hipSuccess; i += 2) {
         const int ls = 2 * (i - 1) + 1, l1 = 2 * i + 1, l2 = 2 * (i + 1) + 1;
         const bool two = i + 1 < O;
         e = kpd::launch_lay_quad(plane(ls), g.w[ls], plane(l1), g.w[l1], g.h[l1], two ? plane(l2) : nullptr,
-                                 two ? g.w[l2] : 0, two ? g.h[l2] : 0, s, n, wstep, wstep);
+                                 two ? g.w[l2] : 0, two ? g.h[l2] : 0, s, n, wstep, wstep, slots, 0);
     }
     return e;
 }
@@ -563,6 +563,266 @@ int kpd_lstream_close(kpd_lstream* s)
     s->closed = true;
     delete s;
     if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_close");
+    return KPD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Arena of a batch of layered streams: per slot a layer workspace, the mask,
+// scored cells, suppression counts and two sets of D counts, offsets, lists
+// and sizes; the cell tables and the tick's slot table.
+struct LbLayout {
+    LsLayout s;   // one slot's geometry, capacity and cell tables
+    int nslots = 0;
+    size_t off_ws = 0, off_xs = 0, off_ys = 0, off_mask = 0, off_need = 0, off_new = 0, off_table = 0;
+    size_t off_cnt[2] = {0, 0}, off_off[2] = {0, 0}, off_list[2] = {0, 0}, off_total[2] = {0, 0};
+    size_t list_stride = 0;
+    size_t total = 0;
+};
+
+bool lb_layout(int W, int H, const kpd_params* p, int nslots, LbLayout* B, std::string* why)
+{
+    if (nslots < 1 || nslots > 65535) { *why = "max_streams must be 1..65535"; return false; }
+    kpd_params q = *p;
+    q.chunk_frames = 0;
+    if (!ls_layout(W, H, &q, &B->s, why)) return false;
+    const LsLayout& L = B->s;
+    B->nslots = nslots;
+    const size_t sc = (size_t)nslots * L.ncell;
+    B->list_stride = align_up((size_t)L.cap * sizeof(kpd_keypoint)) / sizeof(kpd_keypoint);
+    size_t off = 0;
+    B->off_ws = off;    off = align_up(off + L.ws_step * (size_t)nslots);
+    B->off_xs = off;    off = align_up(off + (size_t)L.g.L * (L.nc + 1) * 4);
+    B->off_ys = off;    off = align_up(off + (size_t)L.g.L * (L.nr + 1) * 4);
+    B->off_mask = off;  off = align_up(off + sc);
+    B->off_need = off;  off = align_up(off + sc);
+    B->off_new = off;   off = align_up(off + sc * 4);
+    B->off_table = off; off = align_up(off + (size_t)nslots * sizeof(kpd::LbSlot));
+    for (int k = 0; k < 2; ++k) {
+        B->off_cnt[k] = off;   off = align_up(off + sc * 4);
+        B->off_off[k] = off;   off = align_up(off + sc * 4);
+        B->off_list[k] = off;  off += B->list_stride * sizeof(kpd_keypoint) * (size_t)nslots;
+        B->off_total[k] = off; off = align_up(off + (size_t)nslots * 4);
+    }
+    B->total = off;
+    return true;
+}
+
+}  // namespace
+
+struct kpd_lbatch {
+    LbLayout B;
+    kpd_params p{};
+    hipStream_t stream = nullptr;
+    uint8_t* arena = nullptr;
+    std::vector<uint32_t> xs, ys;
+    std::vector<kpd::LbSlot> slot;   // host state: previous frame, force, next buffer, staged frame
+    std::vector<char> staged, ticked;
+    kpd::LbSlot* host_table[2] = {nullptr, nullptr};
+    hipEvent_t table_free[2] = {nullptr, nullptr};
+    int tk = 0;
+    bool closed = false;
+    template <class T> T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
+};
+
+extern "C" {
+
+size_t kpd_lbatch_bytes(int width, int height, const kpd_params* params, int max_streams)
+{
+    LbLayout B;
+    std::string why;
+    if (!params || !lb_layout(width, height, params, max_streams, &B, &why)) {
+        kpd::api_fail(KPD_EINVAL, params ? why : "params are NULL");
+        return 0;
+    }
+    return B.total;
+}
+
+int kpd_lbatch_close(kpd_lbatch* b);
+
+int kpd_lbatch_open(int width, int height, const kpd_params* params, int max_streams, void* dev_arena,
+                    size_t arena_bytes, void* hip_stream, kpd_lbatch** out)
+{
+    if (!out) return kpd::api_fail(KPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params) return kpd::api_fail(KPD_EINVAL, "params are NULL");
+    LbLayout B;
+    std::string why;
+    if (!lb_layout(width, height, params, max_streams, &B, &why)) return kpd::api_fail(KPD_EINVAL, why);
+    if (!dev_arena) return kpd::api_fail(KPD_EINVAL, "arena is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign) return kpd::api_fail(KPD_EINVAL, "arena not 256-byte aligned");
+    if (arena_bytes < B.total)
+        return kpd::api_fail(KPD_ENOMEM, "arena has " + std::to_string(arena_bytes) + " bytes, the batch needs " +
+                                             std::to_string(B.total));
+    kpd_lbatch* b = new (std::nothrow) kpd_lbatch();
+    if (!b) return kpd::api_fail(KPD_ENOMEM, "host allocation failed");
+    b->B = B;
+    b->p = *params;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->arena = reinterpret_cast<uint8_t*>(dev_arena);
+    b->slot.assign((size_t)max_streams, kpd::LbSlot{});
+    for (auto& sl : b->slot) sl.force = 1;
+    b->staged.assign((size_t)max_streams, 0);
+    b->ticked.assign((size_t)max_streams, 0);
+    ls_tables(B.s, &b->xs, &b->ys);
+    hipError_t e = hipMemcpyAsync(b->at<uint32_t>(B.off_xs), b->xs.data(), b->xs.size() * 4, hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->at<uint32_t>(B.off_ys), b->ys.data(), b->ys.size() * 4, hipMemcpyHostToDevice, b->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->host_table[k]), (size_t)max_streams * sizeof(kpd::LbSlot),
+                          hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->table_free[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // the host tables are copied before they go
+    if (e != hipSuccess) {
+        kpd_lbatch_close(b);
+        return kpd::api_hip_fail(e, "kpd_lbatch_open");
+    }
+    *out = b;
+    return KPD_OK;
+}
+
+int kpd_lbatch_push(kpd_lbatch* b, int slot, const uint8_t* frame, size_t pitch_bytes)
+{
+    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (slot < 0 || slot >= b->B.nslots) return kpd::api_fail(KPD_EINVAL, "no such slot");
+    if (!frame) return kpd::api_fail(KPD_EINVAL, "frame is NULL");
+    if (pitch_bytes < (size_t)b->B.s.W || pitch_bytes > (1u << 30)) return kpd::api_fail(KPD_EINVAL, "bad pitch");
+    if (b->staged[slot]) return kpd::api_fail(KPD_ESTATE, "a frame is already staged for this tick");
+    b->slot[slot].cur = frame;
+    b->slot[slot].cur_pitch = (int)pitch_bytes;
+    b->staged[slot] = 1;
+    return KPD_OK;
+}
+
+int kpd_lbatch_tick(kpd_lbatch* b)
+{
+    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    const LbLayout& B = b->B;
+    const LsLayout& L = B.s;
+    const int n = B.nslots;
+    // this host table's previous copy has been done before it is rewritten
+    hipError_t e = hipEventSynchronize(b->table_free[b->tk]);
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lbatch_tick");
+    kpd::LbSlot* t = b->host_table[b->tk];
+    for (int i = 0; i < n; ++i) {
+        t[i] = b->slot[i];
+        t[i].active = b->staged[i] ? 1 : 0;
+        if (!t[i].prev) {   // a slot's first frame marks every cell and reads no previous frame
+            t[i].prev = t[i].cur;
+            t[i].prev_pitch = t[i].cur_pitch;
+        }
+    }
+    kpd::LbSlot* dt = b->at<kpd::LbSlot>(B.off_table);
+    e = hipMemcpyAsync(dt, t, (size_t)n * sizeof(kpd::LbSlot), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->table_free[b->tk], b->stream);
+
+    kpd::LbArgs a{};
+    a.slots = dt;
+    a.nslots = n;
+    a.nc = L.nc;
+    a.nr = L.nr;
+    a.ncell = L.ncell;
+    a.id_thresh = b->p.id_thresh;
+    a.kb_thresh = b->p.kb_thresh;
+    a.xs = b->at<uint32_t>(B.off_xs);
+    a.ys = b->at<uint32_t>(B.off_ys);
+    a.mask = b->at<uint8_t>(B.off_mask);
+    a.need = b->at<uint8_t>(B.off_need);
+    a.cell_new = b->at<uint32_t>(B.off_new);
+    for (int k = 0; k < 2; ++k) {
+        a.cnt[k] = b->at<uint32_t>(B.off_cnt[k]);
+        a.off[k] = b->at<uint32_t>(B.off_off[k]);
+        a.list[k] = b->at<kpd_keypoint>(B.off_list[k]);
+        a.total[k] = b->at<uint32_t>(B.off_total[k]);
+    }
+    a.list_stride = B.list_stride;
+    a.cap = L.cap;
+    a.rx = L.rx;
+    a.ry = L.ry;
+
+    uint8_t* ws = b->at<uint8_t>(B.off_ws);
+    kpd::LayArgs la = layer_args(L.g, nullptr, (size_t)L.W, ws);
+    la.t = b->p.fast_t;
+    la.need_score = a.need;
+    la.need_flag = a.mask;
+    la.cell_new = a.cell_new;
+    la.nc = L.nc;
+    la.nr = L.nr;
+    la.W = L.W;
+    la.H = L.H;
+    la.ws_step = L.ws_step;
+    la.cells_step = L.ncell;
+    la.slots = dt;
+    if (e == hipSuccess) e = kpd::launch_lb_mask(a, b->stream);
+    if (e == hipSuccess) e = build_layers(L.g, nullptr, 0, ws, b->stream, n, 0, L.ws_step, dt);
+    if (e == hipSuccess) e = kpd::launch_lay_score_nms(la, b->stream, n);
+    if (e == hipSuccess) e = kpd::launch_lb_emit(a, la, b->stream);
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lbatch_tick");
+    for (int i = 0; i < n; ++i) {
+        if (!b->staged[i]) continue;
+        kpd::LbSlot& sl = b->slot[i];
+        sl.prev = sl.cur;
+        sl.prev_pitch = sl.cur_pitch;
+        sl.force = 0;
+        sl.fb ^= 1;   // D_n went to the old fb; the next frame's goes to the other
+        b->staged[i] = 0;
+        b->ticked[i] = 1;
+    }
+    b->tk ^= 1;
+    return KPD_OK;
+}
+
+int kpd_lbatch_get(kpd_lbatch* b, int slot, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask)
+{
+    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (slot < 0 || slot >= b->B.nslots) return kpd::api_fail(KPD_EINVAL, "no such slot");
+    if (!count) return kpd::api_fail(KPD_EINVAL, "count is NULL");
+    if (!b->ticked[slot]) return kpd::api_fail(KPD_ESTATE, "the slot has had no frame yet");
+    const LbLayout& B = b->B;
+    const int k = 1 - b->slot[slot].fb;   // the buffer holding D_n
+    uint32_t total = 0;
+    hipError_t e = hipMemcpyAsync(&total, b->at<uint32_t>(B.off_total[k]) + slot, 4, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess && cell_mask)
+        e = hipMemcpyAsync(cell_mask, b->at<uint8_t>(B.off_mask) + (size_t)slot * B.s.ncell, (size_t)B.s.ncell,
+                           hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lbatch_get");
+    total = std::min(total, B.s.cap);
+    *count = total;
+    if (total > capacity) return kpd::api_fail(KPD_ETRUNC, "capacity smaller than the keypoint count");
+    if (total > 0) {
+        if (!out) return kpd::api_fail(KPD_EINVAL, "out is NULL");
+        e = hipMemcpyAsync(out, b->at<kpd_keypoint>(B.off_list[k]) + B.list_stride * (size_t)slot,
+                           (size_t)total * sizeof(kpd_keypoint), hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lbatch_get");
+    }
+    return KPD_OK;
+}
+
+int kpd_lbatch_reset(kpd_lbatch* b, int slot)
+{
+    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (slot < 0 || slot >= b->B.nslots) return kpd::api_fail(KPD_EINVAL, "no such slot");
+    b->slot[slot].force = 1;
+    return KPD_OK;
+}
+
+int kpd_lbatch_close(kpd_lbatch* b)
+{
+    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (b->host_table[k]) (void)hipHostFree(b->host_table[k]);
+        if (b->table_free[k]) (void)hipEventDestroy(b->table_free[k]);
+    }
+    b->closed = true;
+    delete b;
+    if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lbatch_close");
     return KPD_OK;
 }
 

@@ -30,6 +30,17 @@ struct LayerGeom {
 
 constexpr int kLayBlock = 256;
 
+// A batch of layered streams of one shape and one set of parameters:
+// slot s's frame of a tick and its state.
+struct LbSlot {
+    const uint8_t* cur;    // the frame of this tick (device memory, read in place)
+    const uint8_t* prev;   // the slot's previous frame (read when not forced)
+    int cur_pitch, prev_pitch;
+    int active;            // a frame is staged for this tick
+    int force;             // every cell is marked (first frame, reset)
+    int fb;                // the list buffer D_n goes to (D_{n-1} is in the other)
+};
+
 struct LayArgs {
     const uint8_t* plane[kMaxLayers];
     int pitch[kMaxLayers];
@@ -57,6 +68,9 @@ struct LayArgs {
     // past frame 0's, its need and count arrays cells_step entries past
     size_t frame_step, ws_step;
     int cells_step;
+    // a batch of layered streams: frame j is slot j's, from this table
+    // (inactive slots are skipped); null otherwise
+    const LbSlot* slots;
 };
 
 // The masked stream over these layers: per-cell mask, Eq. 1 with cells
@@ -122,14 +136,44 @@ struct LsChunkArgs {
 hipError_t launch_ls_mask_chunk(const LsChunkArgs& a, hipStream_t s);
 hipError_t launch_ls_write_chunk(const LsChunkArgs& a, const LayArgs& l, hipStream_t s);
 
+// A tick of a batch of layered streams: per slot the mask, scored cells,
+// suppression counts and the D lists of the masked stream (two buffers per
+// slot, D_n in slots[s].fb), slots x cells arrays and list_stride entries
+// between slots' lists.
+struct LbArgs {
+    const LbSlot* slots;
+    int nslots, nc, nr, ncell;
+    int32_t id_thresh;
+    uint32_t kb_thresh;
+    const uint32_t* xs;
+    const uint32_t* ys;
+    uint8_t* mask;
+    uint8_t* need;
+    uint32_t* cell_new;
+    uint32_t* cnt[2];
+    uint32_t* off[2];
+    kpd_keypoint* list[2];
+    uint32_t* total[2];   // one per slot
+    size_t list_stride;
+    uint32_t cap;
+    int rx, ry;
+};
+
+hipError_t launch_lb_mask(const LbArgs& a, hipStream_t s);
+hipError_t launch_lb_emit(const LbArgs& a, const LayArgs& l, hipStream_t s);
+
 // Two halvings of a chain (src -> d1 -> d2; d2 absent when w2 = 0), and the
 // 1.5x downsampling of the frame with the halving after it (d1 absent when
 // w1 = 0). `frames` consecutive frames of a chunk: sources sstep bytes
 // apart, destinations dstep bytes apart.
+// With a slot table, frame z is slot z's (inactive slots skipped) and a
+// step that reads the frame (from_frame) takes it from the table.
 hipError_t launch_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1, uint8_t* d2, int w2, int h2,
-                           hipStream_t s, int frames = 1, size_t sstep = 0, size_t dstep = 0);
+                           hipStream_t s, int frames = 1, size_t sstep = 0, size_t dstep = 0,
+                           const LbSlot* slots = nullptr, int from_frame = 0);
 hipError_t launch_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0, uint8_t* d1, int w1, int h1,
-                            hipStream_t s, int frames = 1, size_t sstep = 0, size_t dstep = 0);
+                            hipStream_t s, int frames = 1, size_t sstep = 0, size_t dstep = 0,
+                            const LbSlot* slots = nullptr);
 hipError_t launch_lay_detect(const LayArgs& a, hipStream_t s);
 hipError_t launch_lay_score_nms(const LayArgs& a, hipStream_t s, int frames = 1);
 hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const uint32_t* count, uint32_t cap,

@@ -18,15 +18,24 @@ __constant__ int8_t kLayRingDy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0,
 // level d1 (each pixel the 2x2 mean of src, round half up, for the quad
 // pixels inside d1) and, when the quad lies inside d2's reach, the d2 pixel
 // that is the mean of the quad; d2 may be absent (w2 = 0). Frame z of a
-// chunk (blockIdx.z) reads src + z * sstep and writes d1, d2 + z * dstep.
+// chunk (blockIdx.z) reads src + z * sstep and writes d1, d2 + z * dstep;
+// with a slot table, slot z's (skipped when inactive), whose frame is the
+// source when from_frame is set.
 __device__ __forceinline__ int mean4(int a, int b, int c, int d) { return (a + b + c + d + 2) >> 2; }
 
 __global__ __launch_bounds__(256) void k_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1,
-                                                  uint8_t* d2, int w2, int h2, size_t sstep, size_t dstep)
+                                                  uint8_t* d2, int w2, int h2, size_t sstep, size_t dstep,
+                                                  const LbSlot* slots, int from_frame)
 {
     const int qx = blockIdx.x * 16 + (threadIdx.x & 15), qy = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (2 * qx >= w1 || 2 * qy >= h1) return;
-    src += blockIdx.z * sstep;
+    if (slots && !slots[blockIdx.z].active) return;
+    if (slots && from_frame) {
+        src = slots[blockIdx.z].cur;
+        spitch = slots[blockIdx.z].cur_pitch;
+    } else {
+        src += blockIdx.z * sstep;
+    }
     d1 += blockIdx.z * dstep;
     if (w2 > 0) d2 += blockIdx.z * dstep;
     int v[2][2] = {{0, 0}, {0, 0}};
@@ -51,11 +60,18 @@ __global__ __launch_bounds__(256) void k_lay_quad(const uint8_t* src, int spitch
 // built here, their mean (d_1 has exactly one pixel per block). Frames of a
 // chunk as in k_lay_quad.
 __global__ __launch_bounds__(256) void k_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0,
-                                                   uint8_t* d1, int w1, int h1, size_t sstep, size_t dstep)
+                                                   uint8_t* d1, int w1, int h1, size_t sstep, size_t dstep,
+                                                   const LbSlot* slots)
 {
     const int a = blockIdx.x * 16 + (threadIdx.x & 15), b = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (2 * a >= w0 || 2 * b >= h0) return;
-    src += blockIdx.z * sstep;
+    if (slots) {
+        if (!slots[blockIdx.z].active) return;
+        src = slots[blockIdx.z].cur;
+        spitch = slots[blockIdx.z].cur_pitch;
+    } else {
+        src += blockIdx.z * sstep;
+    }
     d0 += blockIdx.z * dstep;
     if (w1 > 0) d1 += blockIdx.z * dstep;
     const uint8_t* s = src + (size_t)(3 * b) * spitch + 3 * a;
@@ -127,7 +143,13 @@ __device__ __forceinline__ int pixel_cell(const LayArgs& a, int l, int x, int y)
 // past, its per-cell arrays cells_step entries past.
 __device__ __forceinline__ const uint8_t* frame_plane(const LayArgs& a, int l, int j)
 {
+    if (l == 0 && a.slots) return a.slots[j].cur;
     return a.plane[l] + (size_t)j * (l == 0 ? a.frame_step : a.ws_step);
+}
+
+__device__ __forceinline__ int frame_pitch(const LayArgs& a, int l, int j)
+{
+    return l == 0 && a.slots ? a.slots[j].cur_pitch : a.pitch[l];
 }
 
 __global__ __launch_bounds__(kLayBlock) void k_lay_score(LayArgs a)
@@ -135,13 +157,14 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_score(LayArgs a)
     const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
     if (i >= a.N) return;
     const int j = blockIdx.y;
+    if (a.slots && !a.slots[j].active) return;
     const int l = layer_of(a, i);
     const uint32_t r = i - a.base[l];
     const int w = a.w[l], h = a.h[l], y = (int)(r / (uint32_t)w), x = (int)(r - (uint32_t)y * w);
     int v = 0;
     const bool need = !a.need_score || a.need_score[(size_t)j * a.cells_step + pixel_cell(a, l, x, y)];
     if (need && x >= 3 && y >= 3 && x < w - 3 && y < h - 3)
-        v = layer_score(frame_plane(a, l, j) + (size_t)y * a.pitch[l] + x, a.pitch[l], a.t);
+        v = layer_score(frame_plane(a, l, j) + (size_t)y * frame_pitch(a, l, j) + x, frame_pitch(a, l, j), a.t);
     a.score[(size_t)j * (a.ws_step >> 1) + i] = (uint16_t)v;
 }
 
@@ -155,6 +178,7 @@ __global__ __launch_bounds__(kLayBlock) void k_lay_nms(LayArgs a)
     __shared__ uint32_t s_cnt[kLayBlock / 64];
     const uint32_t i = blockIdx.x * kLayBlock + threadIdx.x;
     const int j = blockIdx.y;
+    if (a.slots && !a.slots[j].active) return;   // the whole workgroup: one slot
     const uint16_t* score = a.score + (size_t)j * (a.ws_step >> 1);
     const size_t cj = (size_t)j * a.cells_step;
     bool keep = false;
@@ -602,7 +626,173 @@ __global__ __launch_bounds__(kLsWrite) void k_ls_write_chunk(LsChunkArgs a, LayA
     }
 }
 
+// ------------------------------------- batches of layered streams (ticks)
+
+// Slot s's mask, a workgroup per (cell, slot): every cell of a forced
+// slot, otherwise the cell's summed |I_n - I_{n-1}| over its level-0 box
+// against T_I times its area, or its count in the slot's D_{n-1} against T_H.
+__global__ __launch_bounds__(256) void k_lb_mask(LbArgs a)
+{
+    __shared__ unsigned long long s_sum[4];
+    const int c = blockIdx.x, sl = blockIdx.y, cc = c % a.nc, rr = c / a.nc;
+    const LbSlot& S = a.slots[sl];
+    if (!S.active) return;
+    const size_t sc = (size_t)sl * a.ncell;
+    if (threadIdx.x == 0) a.cell_new[sc + c] = 0;
+    if (S.force) {
+        if (threadIdx.x == 0) a.mask[sc + c] = 1;
+        return;
+    }
+    const int x0 = (int)a.xs[cc], x1 = (int)a.xs[cc + 1], y0 = (int)a.ys[rr], y1 = (int)a.ys[rr + 1];
+    const int bw = x1 - x0, n = bw * (y1 - y0);
+    unsigned long long sum = 0;
+    for (int q = threadIdx.x; q < n; q += 256) {
+        const int y = y0 + q / bw, x = x0 + q % bw;
+        sum += (unsigned)abs((int)S.cur[(size_t)y * S.cur_pitch + x] - (int)S.prev[(size_t)y * S.prev_pitch + x]);
+    }
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        const bool id = (long long)t > (long long)a.id_thresh * (long long)n;
+        const bool kb = a.cnt[1 - S.fb][sc + c] >= a.kb_thresh;
+        a.mask[sc + c] = (id || kb) ? 1 : 0;
+    }
+}
+
+// Slot s's scored cells (a workgroup per slot).
+__global__ __launch_bounds__(256) void k_lb_dilate(LbArgs a)
+{
+    const int sl = blockIdx.x;
+    if (!a.slots[sl].active) return;
+    const uint8_t* m = a.mask + (size_t)sl * a.ncell;
+    for (int c = threadIdx.x; c < a.ncell; c += 256) {
+        const int cc = c % a.nc, rr = c / a.nc;
+        uint8_t need = 0;
+        for (int r2 = max(rr - a.ry, 0); r2 <= min(rr + a.ry, a.nr - 1) && !need; ++r2)
+            for (int c2 = max(cc - a.rx, 0); c2 <= min(cc + a.rx, a.nc - 1); ++c2)
+                if (m[r2 * a.nc + c2]) {
+                    need = 1;
+                    break;
+                }
+        a.need[(size_t)sl * a.ncell + c] = need;
+    }
+}
+
+// Slot s's D_n counts, offsets and size (a workgroup per slot), as k_ls_scan.
+__global__ __launch_bounds__(kScanBlock) void k_lb_scan(LbArgs a)
+{
+    __shared__ uint32_t s_wave[kScanBlock / 64];
+    const int sl = blockIdx.x;
+    const LbSlot& S = a.slots[sl];
+    if (!S.active) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t sc = (size_t)sl * a.ncell;
+    const uint32_t* cnt_prev = a.cnt[1 - S.fb] + sc;
+    uint32_t* cnt_cur = a.cnt[S.fb] + sc;
+    uint32_t* off_cur = a.off[S.fb] + sc;
+    uint32_t carry = 0;
+    for (int base = 0; base < a.ncell; base += kScanBlock) {
+        const int i = base + threadIdx.x;
+        uint32_t c = 0;
+        if (i < a.ncell) {
+            c = a.mask[sc + i] ? a.cell_new[sc + i] : cnt_prev[i];
+            cnt_cur[i] = c;
+        }
+        uint32_t incl = c;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, round = 0;
+        for (int k = 0; k < kScanBlock / 64; ++k) {
+            before += k < wave ? s_wave[k] : 0;
+            round += s_wave[k];
+        }
+        if (i < a.ncell) off_cur[i] = carry + before + incl - c;
+        carry += round;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.total[S.fb][sl] = carry;
+}
+
+// Slot s's D_n, a workgroup per (cell, slot), as k_ls_write.
+__global__ __launch_bounds__(kLsWrite) void k_lb_write(LbArgs a, LayArgs l)
+{
+    __shared__ uint32_t s_cnt[kLsWrite / 64];
+    const int c = blockIdx.x, sl = blockIdx.y, cc = c % a.nc, rr = c / a.nc;
+    const LbSlot& S = a.slots[sl];
+    if (!S.active) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t sc = (size_t)sl * a.ncell;
+    kpd_keypoint* list_cur = a.list[S.fb] + (size_t)sl * a.list_stride;
+    const uint32_t dst = a.off[S.fb][sc + c];
+    if (!a.mask[sc + c]) {
+        const kpd_keypoint* list_prev = a.list[1 - S.fb] + (size_t)sl * a.list_stride;
+        const uint32_t src = a.off[1 - S.fb][sc + c], n = a.cnt[1 - S.fb][sc + c];
+        for (uint32_t i = threadIdx.x; i < n; i += kLsWrite)
+            if (src + i < a.cap && dst + i < a.cap) list_cur[dst + i] = list_prev[src + i];
+        return;
+    }
+    const uint8_t* flag = l.flag + (size_t)sl * l.ws_step;
+    const uint16_t* score = l.score + (size_t)sl * (l.ws_step >> 1);
+    const uint32_t want = a.cnt[S.fb][sc + c];
+    uint32_t run = 0;
+    for (int m = 0; m < l.L && run < want; ++m) {
+        const int x0 = (int)a.xs[m * (a.nc + 1) + cc], x1 = (int)a.xs[m * (a.nc + 1) + cc + 1];
+        const int y0 = (int)a.ys[m * (a.nr + 1) + rr], y1 = (int)a.ys[m * (a.nr + 1) + rr + 1];
+        const int bw = x1 - x0, n = bw * (y1 - y0);
+        const size_t fb = l.base[m];
+        for (int base = 0; base < n && run < want; base += kLsWrite) {
+            const int q = base + threadIdx.x;
+            int x = 0, y = 0;
+            bool f = false;
+            if (q < n) {
+                y = y0 + q / bw;
+                x = x0 + q % bw;
+                f = flag[fb + (size_t)y * l.w[m] + x] != 0;
+            }
+            const uint64_t b = __ballot(f);
+            if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(b);
+            __syncthreads();
+            uint32_t pos = run + (uint32_t)__popcll(b & ((1ull << lane) - 1)), total = 0;
+            for (int k = 0; k < kLsWrite / 64; ++k) {
+                pos += k < wave ? s_cnt[k] : 0;
+                total += s_cnt[k];
+            }
+            if (f && dst + pos < a.cap) {
+                kpd_keypoint kp;
+                kp.x = (uint16_t)x;
+                kp.y = (uint16_t)y;
+                kp.octave = (uint8_t)m;
+                kp.pad = 0;
+                kp.score = score[fb + (size_t)y * l.w[m] + x];
+                list_cur[dst + pos] = kp;
+            }
+            run += total;
+            __syncthreads();   // s_cnt is rewritten by the next round
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_lb_mask(const LbArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lb_mask, dim3(a.ncell, a.nslots), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lb_dilate, dim3(a.nslots), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb_emit(const LbArgs& a, const LayArgs& l, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lb_scan, dim3(a.nslots), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_lb_write, dim3(a.ncell, a.nslots), dim3(kLsWrite), 0, s, a, l);
+    return hipGetLastError();
+}
 
 hipError_t launch_ls_mask_chunk(const LsChunkArgs& a, hipStream_t s)
 {
@@ -650,22 +840,22 @@ hipError_t launch_lay_refine(const LayArgs& a, const kpd_keypoint* list, const u
 }
 
 hipError_t launch_lay_quad(const uint8_t* src, int spitch, uint8_t* d1, int w1, int h1, uint8_t* d2, int w2, int h2,
-                           hipStream_t s, int frames, size_t sstep, size_t dstep)
+                           hipStream_t s, int frames, size_t sstep, size_t dstep, const LbSlot* slots, int from_frame)
 {
     if (w1 <= 0 || h1 <= 0 || frames < 1) return hipSuccess;
     const int qx = (w1 + 1) / 2, qy = (h1 + 1) / 2;
     hipLaunchKernelGGL(k_lay_quad, dim3((qx + 15) / 16, (qy + 15) / 16, frames), dim3(256), 0, s, src, spitch, d1, w1,
-                       h1, d2, w2, h2, sstep, dstep);
+                       h1, d2, w2, h2, sstep, dstep, slots, from_frame);
     return hipGetLastError();
 }
 
 hipError_t launch_lay_third(const uint8_t* src, int spitch, uint8_t* d0, int w0, int h0, uint8_t* d1, int w1, int h1,
-                            hipStream_t s, int frames, size_t sstep, size_t dstep)
+                            hipStream_t s, int frames, size_t sstep, size_t dstep, const LbSlot* slots)
 {
     if (w0 <= 0 || h0 <= 0 || frames < 1) return hipSuccess;
     const int bx = w0 / 2, by = h0 / 2;
     hipLaunchKernelGGL(k_lay_third, dim3((bx + 15) / 16, (by + 15) / 16, frames), dim3(256), 0, s, src, spitch, d0, w0,
-                       h0, d1, w1, h1, sstep, dstep);
+                       h0, d1, w1, h1, sstep, dstep, slots);
     return hipGetLastError();
 }
 

@@ -42,7 +42,8 @@ EXPORTED = ("stream_bytes", "open_stream", "set_thresholds", "push_frame", "get_
             "kpd_detect_layers_static", "batch_set_single_launch",
             "kpd_layer_plane", "kpd_refine_layers", "kpd_lstream_bytes", "kpd_lstream_open", "kpd_lstream_push",
             "kpd_lstream_get", "kpd_lstream_reset", "kpd_lstream_close", "kpd_lstream_push_frames",
-            "kpd_lstream_get_chunk")
+            "kpd_lstream_get_chunk", "kpd_lbatch_bytes", "kpd_lbatch_open", "kpd_lbatch_push", "kpd_lbatch_tick",
+            "kpd_lbatch_get", "kpd_lbatch_reset", "kpd_lbatch_close")
 DESCRIPTOR_DTYPE = np.dtype([("sector", "<u4"), ("pad", "<u4"), ("bits", "<u8", (8,))])
 TRACK_DTYPE = np.dtype([("x4", "<i4"), ("y4", "<i4"), ("octave", "u1"), ("pad", "u1"), ("score", "<u2"),
                         ("sad", "<u4")])
@@ -126,6 +127,15 @@ def _load() -> ctypes.CDLL:
     L.kpd_lstream_push.argtypes = [P, P, sz, ctypes.c_int]
     L.kpd_lstream_get.argtypes = [P, P, sz, ctypes.POINTER(sz), P]
     L.kpd_lstream_push_frames.argtypes = [P, P, sz, sz, ctypes.c_int]
+    L.kpd_lbatch_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), ctypes.c_int]
+    L.kpd_lbatch_bytes.restype = sz
+    L.kpd_lbatch_open.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(KpdParams), ctypes.c_int, P, sz, P,
+                                  ctypes.POINTER(P)]
+    L.kpd_lbatch_push.argtypes = [P, ctypes.c_int, P, sz]
+    L.kpd_lbatch_tick.argtypes = [P]
+    L.kpd_lbatch_get.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz), P]
+    L.kpd_lbatch_reset.argtypes = [P, ctypes.c_int]
+    L.kpd_lbatch_close.argtypes = [P]
     L.kpd_lstream_get_chunk.argtypes = [P, ctypes.c_int, P, sz, ctypes.POINTER(sz)]
     L.kpd_lstream_reset.argtypes = [P]
     L.kpd_lstream_close.argtypes = [P]
@@ -719,6 +729,60 @@ class LayerStream:
     def close(self) -> None:
         if self.handle:
             _check(lib.kpd_lstream_close(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LayerBatch:
+    """A batch of masked streams over octaves and intra-octaves sharing one
+    frame size and one set of parameters: `n_slots` streams advanced
+    together, one tick at a time (frames read in place from the device)."""
+
+    def __init__(self, width: int, height: int, params: KpdParams, n_slots: int, stream=None, device="cuda"):
+        self.width, self.height, self.params, self.n_slots = width, height, params, n_slots
+        self.n_cells = params.grid_cols * params.grid_rows
+        n = lib.kpd_lbatch_bytes(width, height, ctypes.byref(params), n_slots)
+        if n == 0:
+            raise KpdError(KPD_EINVAL, lib.kpd_last_error().decode())
+        self.arena = torch.empty(n, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib.kpd_lbatch_open(width, height, ctypes.byref(params), n_slots, self.arena.data_ptr(), n,
+                                   _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h.value
+        self._held = [[None, None] for _ in range(n_slots)]
+
+    def push(self, slot: int, frame: torch.Tensor) -> None:
+        if not (isinstance(frame, torch.Tensor) and frame.device.type == "cuda" and frame.dtype == torch.uint8
+                and frame.dim() == 2 and frame.stride(1) == 1):
+            raise ValueError("frame must be a CUDA uint8 [H, W] tensor with unit column stride")
+        _check(lib.kpd_lbatch_push(self.handle, slot, frame.data_ptr(), frame.stride(0)))
+        self._held[slot] = [self._held[slot][1], frame]
+
+    def tick(self) -> None:
+        _check(lib.kpd_lbatch_tick(self.handle))
+
+    def keypoints(self, slot: int, capacity: int = 4096) -> Tuple[np.ndarray, np.ndarray]:
+        out = np.zeros(max(capacity, 1), KEYPOINT_DTYPE)
+        mask = np.zeros(self.n_cells, np.uint8)
+        cnt = ctypes.c_size_t()
+        rc = lib.kpd_lbatch_get(self.handle, slot, out.ctypes.data, len(out), ctypes.byref(cnt), mask.ctypes.data)
+        if rc == KPD_ETRUNC:
+            out = np.zeros(cnt.value, KEYPOINT_DTYPE)
+            rc = lib.kpd_lbatch_get(self.handle, slot, out.ctypes.data, len(out), ctypes.byref(cnt), mask.ctypes.data)
+        _check(rc)
+        return out[:cnt.value].copy(), mask
+
+    def reset(self, slot: int) -> None:
+        _check(lib.kpd_lbatch_reset(self.handle, slot))
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib.kpd_lbatch_close(self.handle))
             self.handle = None
 
     def __del__(self):
