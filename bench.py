@@ -506,6 +506,54 @@ def intra_octave_workload(kpd, wl: Workload, args) -> dict:
                     "kpd_lstream_push_frames chunks of the whole video (*_chunked)"}
 
 
+def layered_batch_workload(kpd, wl: Workload, args, n_slots: int = 64, n_ticks: int = 60) -> dict:
+    """64 masked streams over octaves and intra-octaves of one shape advanced
+    together: kpd_lbatch ticks against one kpd_lstream per stream pushed one
+    frame per tick. Slot s plays the video from frame 5 s on (wrapping)."""
+    import torch
+    d = wl.det
+    params = kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, d.id_thresh, d.kb_thresh)
+    frame_of = lambda s, t: wl.dev[(5 * s + t) % wl.F]
+    b = kpd.LayerBatch(wl.W, wl.H, params, n_slots)
+
+    def batched(t0):
+        for t in range(t0, t0 + n_ticks):
+            for s in range(n_slots):
+                kpd._check(kpd.lib.kpd_lbatch_push(b.handle, s, frame_of(s, t).data_ptr(), wl.W))
+            kpd._check(kpd.lib.kpd_lbatch_tick(b.handle))
+
+    batched(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batched(n_ticks)
+    torch.cuda.synchronize()
+    bt = (time.perf_counter() - t0) / n_ticks
+    b.close()
+    streams = [kpd.LayerStream(wl.W, wl.H, params) for _ in range(n_slots)]
+
+    def plain(t0):
+        for t in range(t0, t0 + n_ticks):
+            for s, ls in enumerate(streams):
+                kpd._check(kpd.lib.kpd_lstream_push(ls.handle, frame_of(s, t).data_ptr(), wl.W,
+                                                    kpd.FRAME_DEVICE_RETAIN))
+
+    plain(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain(n_ticks)
+    torch.cuda.synchronize()
+    pt = (time.perf_counter() - t0) / n_ticks
+    for ls in streams:
+        ls.close()
+    px = n_slots * wl.W * wl.H
+    return {"what": f"{n_slots} masked streams over octaves and intra-octaves of {wl.name} (slot s plays the video "
+                    f"from frame 5 s), {n_ticks} timed ticks: one kpd_lbatch tick against {n_slots} kpd_lstream_push "
+                    "calls per tick",
+            "batched": {"mpix_per_s": round(px / bt / 1e6, 2), "ms_per_tick": round(bt * 1e3, 4)},
+            "plain_per_stream": {"mpix_per_s": round(px / pt / 1e6, 2), "ms_per_tick": round(pt * 1e3, 4)},
+            "batched_over_plain": round(pt / bt, 3)}
+
+
 def layer_study(kpd, wl: Workload, args) -> dict:
     """The mask variants side by side on one workload (the paper tries every
     layer and keeps the top one since results are alike): per-frame push
@@ -1209,6 +1257,8 @@ def main():
     out["tcd"] = tcd_workload(kpd, wl, args)
     log("[bench] intra-octave layers")
     out["intra_octaves"] = intra_octave_workload(kpd, wl, args)
+    log("[bench] batch of layered streams")
+    out["intra_octaves"]["batched_64_streams"] = layered_batch_workload(kpd, wl, args)
     out["host_frames"] = host_frames_pass(kpd, wl, max(1, args.steps // 10))
     if not args.no_hd:
         del wl
