@@ -1326,8 +1326,25 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
             hm.sad0 = pa.flags;
             hm.id_thresh = 0;   // a cell is marked when its change flag is above 0
             KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_pixel_diff_chunk(pa, s->stream); }));
-            KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(hm, s->stream); }));
-            KPD_HIP(detect(0));
+            if (s->id_layer == 0) {
+                // masks on level 0 (mode 2, or mode 1 on layer 0): pixel noise
+                // lists nearly every (frame, cell), so every cell of every
+                // frame is detected by the full-frame group detector, and the
+                // mark pass then replaces the mark words it sets (the merge
+                // reads only the listed frames' maxima)
+                kpd::GroupArgs ga{};
+                ga.layouts = s->at<kpd::GroupLayout>(L.off_glay);
+                ga.ngroups = L.ngroups;
+                ga.nc = L.nc;
+                ga.al8 = g1.al8;
+                KPD_HIP(timed(s, KPD_K_DETECT, [&] {
+                    return kpd::launch_detect_chunk_groups(ctab, h, ga, L.glds, L.gthreads, s->stream);
+                }));
+                KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(hm, s->stream); }));
+            } else {
+                KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_mark_chunk(hm, s->stream); }));
+                KPD_HIP(detect(0));
+            }
             KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_pixel_merge_chunk(pa, s->stream); }));
         } else if (h.kb_chain) {
             // marks that depend on the counts: detect every frame a cell's
