@@ -91,6 +91,7 @@ struct Layout {
     int fpw = 0, nwords_max = 0, dc_max = 0;
     size_t off_pflag = 0, off_fp = 0, off_msparse = 0, off_mcount = 0, off_pbase = 0;
     int pm_pres = 0, pm_score = 0, pm_fp = 0, pm_ents = 0, pm_lds = 0, pm_batch = 1;
+    int pm_tgate = 0, pm_txy = 0, pm_toct = 0, pm_tab = 0;
     // the group detector of full-frame chunks: gx x gy cells per workgroup
     // and the groups' layouts
     int gx = 1, gy = 1, ngroups = 0, glds = 0, gthreads = 256;
@@ -337,12 +338,22 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->pm_pres = 0;
     L->pm_score = kpd::round_up(nwords_max * 8, 16);
     L->pm_fp = kpd::round_up(L->pm_score + (int)cell_cap_max * 2, 16);
-    // frames whose change words the merge stages at once: about 24 KB, less
-    // when the cell's maps leave less of the 60 KB the pass may take
-    const int pm_room = 60 * 1024 - L->pm_fp - (int)kPixelStagedMaxima * (int)sizeof(kpd_keypoint) - 16;
+    // the decision-pixel tables (7 bytes a pixel) when they leave room for
+    // one frame's change words; then frames whose change words the merge
+    // stages at once: about 24 KB, less when the rest leaves less of the
+    // 60 KB the pass may take
+    const int dcm = (int)cell_cap_max;
+    const int tab_bytes = kpd::round_up(dcm * 2, 16) + kpd::round_up(dcm * 4, 16) + kpd::round_up(dcm, 16);
+    const int ents_bytes = kpd::round_up((int)kPixelStagedMaxima * (int)sizeof(kpd_keypoint), 16);
+    const int fixed = L->pm_fp + ents_bytes + 16;
+    L->pm_tab = (fixed + kpd::round_up(L->fpw * 8, 16) + tab_bytes <= 60 * 1024 && L->fpw * 64 <= 65536) ? 1 : 0;
+    const int pm_room = 60 * 1024 - fixed - (L->pm_tab ? tab_bytes : 0);
     L->pm_batch = std::max(1, std::min(32, std::min(24 * 1024, pm_room) / std::max(1, L->fpw * 8)));
     L->pm_ents = kpd::round_up(L->pm_fp + L->pm_batch * L->fpw * 8, 16);
-    L->pm_lds = L->pm_ents + (int)kPixelStagedMaxima * (int)sizeof(kpd_keypoint);
+    L->pm_tgate = L->pm_ents + ents_bytes;
+    L->pm_txy = L->pm_tgate + kpd::round_up(dcm * 2, 16);
+    L->pm_toct = L->pm_txy + kpd::round_up(dcm * 4, 16);
+    L->pm_lds = L->pm_tab ? L->pm_toct + kpd::round_up(dcm, 16) : L->pm_tgate;
     if (L->list_cap1 > 0xFFFFFFF0ull) { *why = "keypoint list too large"; return false; }
     L->lds_bytes = std::max(lds, 16);
     {
@@ -1315,6 +1326,10 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
             pa.lds_score = L.pm_score;
             pa.lds_fp = L.pm_fp;
             pa.lds_ents = L.pm_ents;
+            pa.lds_tgate = L.pm_tgate;
+            pa.lds_txy = L.pm_txy;
+            pa.lds_toct = L.pm_toct;
+            pa.tab_on = L.pm_tab;
             pa.lds_bytes = L.pm_lds;
             pa.batch = L.pm_batch;
             pa.ents_cap = kPixelStagedMaxima;

@@ -297,9 +297,11 @@ struct PixelChunkArgs {
     const uint32_t* prev_offs;
     uint32_t prev_cap;
     // the merge pass's dynamic LDS: map bits, scores, the staged change
-    // words of `batch` frames and up to ents_cap staged maxima
-    int lds_pres, lds_score, lds_fp, lds_ents, lds_bytes;
-    int batch;
+    // words of `batch` frames, up to ents_cap staged maxima and, with tab_on,
+    // per decision pixel its mask bit (u16), level position (x | y << 16)
+    // and octave (u8)
+    int lds_pres, lds_score, lds_fp, lds_ents, lds_tgate, lds_txy, lds_toct, lds_bytes;
+    int batch, tab_on;
     uint32_t ents_cap;
 };
 

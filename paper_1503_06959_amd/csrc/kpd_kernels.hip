@@ -2160,7 +2160,8 @@ __global__ __launch_bounds__(64 * kDiffWaves) void k_pixel_diff_chunk(PixelChunk
 // merged list. The map starts from the cell's entries before the chunk.
 // The listed frames' change bits and maxima are staged in LDS a batch of
 // frames at a time (one round of loads per batch), so the walk itself
-// waits on no memory.
+// waits on no memory; when they fit, tables of every decision pixel's
+// position and mask bit (built once per cell) replace the decoding.
 constexpr int kMergeBlock = 256;
 constexpr int kMergeBatchMax = 32;   // listed frames staged at once
 
@@ -2180,6 +2181,9 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
     uint16_t* score = reinterpret_cast<uint16_t*>(sm + a.lds_score);
     unsigned long long* fps = reinterpret_cast<unsigned long long*>(sm + a.lds_fp);
     kpd_keypoint* ents = reinterpret_cast<kpd_keypoint*>(sm + a.lds_ents);
+    uint16_t* tgate = reinterpret_cast<uint16_t*>(sm + a.lds_tgate);
+    uint32_t* txy = reinterpret_cast<uint32_t*>(sm + a.lds_txy);
+    uint8_t* toct = sm + a.lds_toct;
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
@@ -2218,7 +2222,6 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
     __syncthreads();
     const int nw = L.nwords, O = a.O;
     for (int w = tid; w < nw; w += kMergeBlock) pres[w] = 0ull;
-    __syncthreads();
     // decision index of (o, x, y), -1 outside the cell's decision box
     auto index_of = [&](int o, int x, int y) -> int {
         if (o >= O) return -1;
@@ -2226,13 +2229,39 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
         if (x < d.x0 || x >= d.x1 || y < d.y0 || y >= d.y1) return -1;
         return L.dc_start[o] + (y - d.y0) * box_w(d) + (x - d.x0);
     };
-    // the mask pixel of a feature at level o, (x, y) changed (change bits fpb)
-    auto changed_at = [&](const unsigned long long* fpb, int o, int x, int y) -> bool {
+    // the octave and level position of decision pixel i, computed
+    auto decode = [&](int i, int& o, int& x, int& y) {
+        o = level_of(L.dc_start, O, i);
+        const unsigned r = (unsigned)(i - L.dc_start[o]);
+        const Box d = L.dec[o];
+        const int ry = (int)fast_div(r, L.dcm[o]);
+        x = d.x0 + (int)r - ry * box_w(d);
+        y = d.y0 + ry;
+    };
+    // the mask bit (index into a frame's change bits) of a feature at level o, (x, y)
+    auto gate_of = [&](int o, int x, int y) -> int {
         const int l = a.one ? a.l_lo : o;
         const int kx = min((x << o) >> l, s_w[l] - 1) - s_kx0[l];
         const int ky = min((y << o) >> l, s_h[l] - 1) - s_ky0[l];
-        const int i = s_boff[l] + ky * s_nx[l] + kx;
-        return ((fpb[i >> 6] >> (i & 63)) & 1ull) != 0ull;
+        return s_boff[l] + ky * s_nx[l] + kx;
+    };
+    const int ndc = L.dc_start[O];
+    if (a.tab_on)
+        for (int i = tid; i < ndc; i += kMergeBlock) {
+            int o, x, y;
+            decode(i, o, x, y);
+            tgate[i] = (uint16_t)gate_of(o, x, y);
+            txy[i] = (uint32_t)x | ((uint32_t)y << 16);
+            toct[i] = (uint8_t)o;
+        }
+    __syncthreads();
+    auto bit_at = [](const unsigned long long* fpb, int g) -> bool { return ((fpb[g >> 6] >> (g & 63)) & 1ull) != 0ull; };
+    // decision pixel i's mask pixel changed (change bits fpb)
+    auto changed_i = [&](const unsigned long long* fpb, int i) -> bool {
+        if (a.tab_on) return bit_at(fpb, tgate[i]);
+        int o, x, y;
+        decode(i, o, x, y);
+        return bit_at(fpb, gate_of(o, x, y));
     };
     if (!a.force0) {
         const uint32_t n0 = a.prev_count[c], src0 = a.prev_offs[c];
@@ -2297,12 +2326,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
                 while (bits && !forced) {
                     const int b = __builtin_ctzll(bits);
                     bits &= bits - 1ull;
-                    const int i = w * 64 + b;
-                    const int o = level_of(L.dc_start, O, i);
-                    const unsigned r = (unsigned)(i - L.dc_start[o]);
-                    const Box d = L.dec[o];
-                    const int ry = (int)fast_div(r, L.dcm[o]);
-                    if (changed_at(fpb, o, d.x0 + (int)r - ry * box_w(d), d.y0 + ry)) out &= ~(1ull << b);
+                    if (changed_i(fpb, w * 64 + b)) out &= ~(1ull << b);
                 }
                 pres[w] = out;
             }
@@ -2314,7 +2338,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
             for (uint32_t e = tid; e < nf; e += kMergeBlock) {
                 const kpd_keypoint kp = e < staged ? se[e] : ge[e];
                 const int i = index_of(kp.octave, kp.x, kp.y);
-                if (i < 0 || !(forced || changed_at(fpb, kp.octave, kp.x, kp.y))) continue;
+                if (i < 0 || !(forced || changed_i(fpb, i))) continue;
                 atomicOr(&pres[i >> 6], 1ull << (i & 63));
                 score[i] = kp.score;
             }
@@ -2344,14 +2368,19 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
                     const int b = __builtin_ctzll(m);
                     m &= m - 1ull;
                     const int i = w * 64 + b;
-                    const int o = level_of(L.dc_start, O, i);
-                    const unsigned r = (unsigned)(i - L.dc_start[o]);
-                    const Box d = L.dec[o];
-                    const int ry = (int)fast_div(r, L.dcm[o]);
                     kpd_keypoint kp;
-                    kp.x = (uint16_t)(d.x0 + (int)r - ry * box_w(d));
-                    kp.y = (uint16_t)(d.y0 + ry);
-                    kp.octave = (uint8_t)o;
+                    if (a.tab_on) {
+                        const uint32_t xy = txy[i];
+                        kp.x = (uint16_t)(xy & 0xFFFFu);
+                        kp.y = (uint16_t)(xy >> 16);
+                        kp.octave = toct[i];
+                    } else {
+                        int o, x, y;
+                        decode(i, o, x, y);
+                        kp.x = (uint16_t)x;
+                        kp.y = (uint16_t)y;
+                        kp.octave = (uint8_t)o;
+                    }
                     kp.pad = 0;
                     kp.score = score[i];
                     if (pb + at < a.plist_cap) dst[at] = kp;
