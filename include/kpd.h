@@ -94,10 +94,9 @@ extern "C" {
  *              KPD_FEAT_REFINE, the sub-pixel position and sub-scale of
  *              Sec. 2's interpolation (get_refined). push_frame,
  *              push_frames (get_chunk_descriptors, get_chunk_refined) and
- *              batch ticks; with a per-pixel mask (set_mask_mode 1, 2) a
- *              marked cell holds new and carried features side by side,
- *              on push_frame and in batch ticks (push_frames: mask mode 0).
- *              0: nothing.
+ *              batch ticks, in every mask mode (with a per-pixel mask,
+ *              set_mask_mode 1 or 2, a marked cell holds new and carried
+ *              features side by side). 0: nothing.
  *   group_cols, group_rows
  *              cells one detection workgroup covers when a chunk's
  *              parameters mark every cell (full-frame detection): a

@@ -91,7 +91,8 @@ struct Layout {
     int fpw = 0, nwords_max = 0, dc_max = 0;
     size_t off_pflag = 0, off_fp = 0, off_msparse = 0, off_mcount = 0, off_pbase = 0;
     int pm_pres = 0, pm_score = 0, pm_fp = 0, pm_ents = 0, pm_lds = 0, pm_batch = 1;
-    int pm_tgate = 0, pm_txy = 0, pm_toct = 0, pm_tab = 0;
+    int pm_tgate = 0, pm_txy = 0, pm_toct = 0, pm_tab = 0, pm_tsrc = 0;
+    size_t off_msrc = 0, off_sdesc = 0, off_sref = 0;   // features with a per-pixel mask in chunks
     // the group detector of full-frame chunks: gx x gy cells per workgroup
     // and the groups' layouts
     int gx = 1, gy = 1, ngroups = 0, glds = 0, gthreads = 256;
@@ -345,7 +346,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     const int dcm = (int)cell_cap_max;
     const int tab_bytes = kpd::round_up(dcm * 2, 16) + kpd::round_up(dcm * 4, 16) + kpd::round_up(dcm, 16);
     const int ents_bytes = kpd::round_up((int)kPixelStagedMaxima * (int)sizeof(kpd_keypoint), 16);
-    const int fixed = L->pm_fp + ents_bytes + 16;
+    const int src_bytes = p->features ? kpd::round_up(dcm * 4, 16) : 0;   // each map entry's source
+    const int fixed = L->pm_fp + ents_bytes + src_bytes + 16;
     L->pm_tab = (fixed + kpd::round_up(L->fpw * 8, 16) + tab_bytes <= 60 * 1024 && L->fpw * 64 <= 65536) ? 1 : 0;
     const int pm_room = 60 * 1024 - fixed - (L->pm_tab ? tab_bytes : 0);
     L->pm_batch = std::max(1, std::min(32, std::min(24 * 1024, pm_room) / std::max(1, L->fpw * 8)));
@@ -353,7 +355,8 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
     L->pm_tgate = L->pm_ents + ents_bytes;
     L->pm_txy = L->pm_tgate + kpd::round_up(dcm * 2, 16);
     L->pm_toct = L->pm_txy + kpd::round_up(dcm * 4, 16);
-    L->pm_lds = L->pm_tab ? L->pm_toct + kpd::round_up(dcm, 16) : L->pm_tgate;
+    L->pm_tsrc = L->pm_tab ? L->pm_toct + kpd::round_up(dcm, 16) : L->pm_tgate;
+    L->pm_lds = L->pm_tsrc + src_bytes;
     if (L->list_cap1 > 0xFFFFFFF0ull) { *why = "keypoint list too large"; return false; }
     L->lds_bytes = std::max(lds, 16);
     {
@@ -458,6 +461,15 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         const size_t centries = L->clist_stride / sizeof(kpd_keypoint) * (size_t)(L->K - 1);
         if (p->features & KPD_FEAT_DESCRIPTOR) { L->off_cdesc = off; off = align_up(off + centries * sizeof(kpd_descriptor)); }
         if (p->features & KPD_FEAT_REFINE) { L->off_cref = off; off = align_up(off + centries * sizeof(kpd_refined)); }
+        if (p->layer_mask && p->features) {
+            L->off_msrc = off; off = align_up(off + (L->clist_stride / sizeof(kpd_keypoint)) * (size_t)L->K * 4);
+            if (p->features & KPD_FEAT_DESCRIPTOR) {
+                L->off_sdesc = off; off = align_up(off + L->list_cap * (size_t)L->K * sizeof(kpd_descriptor));
+            }
+            if (p->features & KPD_FEAT_REFINE) {
+                L->off_sref = off; off = align_up(off + L->list_cap * (size_t)L->K * sizeof(kpd_refined));
+            }
+        }
         if (p->layer_mask) {
             L->off_pflag = off; off = align_up(off + kc * 4);
             L->off_fp = off; off = align_up(off + kc * (size_t)L->fpw * 8);
@@ -1177,8 +1189,8 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
     if (pixel && s->p.kb_thresh != KPD_KB_OFF && s->p.kb_thresh != 0 && s->p.id_thresh >= 0)
         return fail(KPD_EINVAL, "the layer mask in chunks needs kb_thresh off");
     if (pixel && L.pm_lds > 60 * 1024) return fail(KPD_EINVAL, "cells too large for the layer mask in chunks");
-    if (pixel && s->p.features)
-        return fail(KPD_EINVAL, "features with a per-pixel mask run on push_frame and batch ticks only");
+    if (pixel && s->p.features && L.list_cap >= (1u << kpd::kPixelFrameShift))
+        return fail(KPD_EINVAL, "frame too large for features with a per-pixel mask in chunks");
     if (!frames) return fail(KPD_EINVAL, "frames is NULL");
     if (n_frames < 1 || n_frames > L.K) return fail(KPD_EINVAL, "n_frames out of range");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
@@ -1330,7 +1342,30 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
             pa.lds_txy = L.pm_txy;
             pa.lds_toct = L.pm_toct;
             pa.tab_on = L.pm_tab;
+            pa.lds_tsrc = L.pm_tsrc;
             pa.lds_bytes = L.pm_lds;
+            if (s->p.features) {
+                pa.msrc = s->at<uint32_t>(L.off_msrc);
+                pa.t = s->p.fast_t;
+                pa.counts = s->at<uint32_t>(L.off_ccount);
+                pa.offs = s->at<uint32_t>(L.off_coffs);
+                pa.last_count = s->at<uint32_t>(L.off_count[fb_next]);
+                pa.last_offs = s->at<uint32_t>(L.off_offs[fb_next]);
+                pa.dlist_cap = (uint32_t)L.list_cap1;
+                if (s->p.features & KPD_FEAT_DESCRIPTOR) {
+                    pa.tab = s->at<kpd::DescTables>(L.off_dtab);
+                    pa.sdesc = s->at<kpd_descriptor>(L.off_sdesc);
+                    pa.cdesc = reinterpret_cast<kpd_descriptor*>(s->arena + L.off_cdesc);
+                    pa.last_desc = s->at<kpd_descriptor>(L.off_desc[fb_next]);
+                    pa.prev_desc = s->at<kpd_descriptor>(L.off_desc[fb_prev]);
+                }
+                if (s->p.features & KPD_FEAT_REFINE) {
+                    pa.sref = s->at<kpd_refined>(L.off_sref);
+                    pa.cref = reinterpret_cast<kpd_refined*>(s->arena + L.off_cref);
+                    pa.last_ref = s->at<kpd_refined>(L.off_ref[fb_next]);
+                    pa.prev_ref = s->at<kpd_refined>(L.off_ref[fb_prev]);
+                }
+            }
             pa.batch = L.pm_batch;
             pa.ents_cap = kPixelStagedMaxima;
         }
@@ -1361,6 +1396,8 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
                 KPD_HIP(detect(0));
             }
             KPD_HIP(timed(s, KPD_K_MARK, [&] { return kpd::launch_pixel_merge_chunk(pa, s->stream); }));
+            if (s->p.features)   // the listed frames' maxima, on their frames' levels
+                KPD_HIP(timed(s, KPD_K_DESCRIBE, [&] { return kpd::launch_pixel_features_chunk(pa, s->stream); }));
         } else if (h.kb_chain) {
             // marks that depend on the counts: detect every frame a cell's
             // chain can mark, then walk each cell's frames to keep the marks
@@ -1410,7 +1447,10 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
         ca.list_cap = (uint32_t)L.list_cap1;
     }
     KPD_HIP(timed(s, KPD_K_COMPACT, [&] { return kpd::launch_compact_chunk(ca, n_frames, s->stream); }));
-    if (s->p.features) {
+    if (s->p.features && pixel_diff) {
+        // each frame's records from the sources the merge kept
+        KPD_HIP(timed(s, KPD_K_DESCRIBE, [&] { return kpd::launch_pixel_gather_chunk(pa, s->stream); }));
+    } else if (s->p.features) {
         // features of every frame's list: computed where a frame marked a
         // cell, carried with the keypoints elsewhere (Eq. 1)
         kpd::DescChunkArgs da{};

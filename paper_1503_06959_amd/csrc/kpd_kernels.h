@@ -303,10 +303,39 @@ struct PixelChunkArgs {
     int lds_pres, lds_score, lds_fp, lds_ents, lds_tgate, lds_txy, lds_toct, lds_bytes;
     int batch, tab_on;
     uint32_t ents_cap;
+    // features (msrc non-null): the merge keeps each map entry's source in
+    // LDS (lds_tsrc) and writes it beside the entry: kPixelFromPrev | index
+    // in the list before the chunk, or (frame << kPixelFrameShift) | index in
+    // that frame's F list. Features of every listed (frame, cell)'s maxima
+    // go to sdesc / sref at their F list places (list_cap apart by frame);
+    // after the compaction each frame's list gathers its records from there
+    // or from the list before the chunk.
+    int lds_tsrc;
+    uint32_t* msrc;                 // frame j's at msrc + j * list_stride
+    const DescTables* tab;          // null: no descriptors
+    kpd_descriptor* sdesc;
+    kpd_refined* sref;
+    int t;
+    const uint32_t* counts;         // the compaction's lists, frames 0..n-2, and the last frame's
+    const uint32_t* offs;
+    kpd_descriptor* cdesc;          // their features, list_stride entries apart
+    kpd_refined* cref;
+    const uint32_t* last_count;
+    const uint32_t* last_offs;
+    kpd_descriptor* last_desc;
+    kpd_refined* last_ref;
+    const kpd_descriptor* prev_desc; // features of the list before the chunk
+    const kpd_refined* prev_ref;
+    uint32_t dlist_cap;             // entries of the compaction's lists
 };
+
+constexpr uint32_t kPixelFromPrev = 0x80000000u;
+constexpr int kPixelFrameShift = 22;   // F list indices below 2^22
 
 hipError_t launch_pixel_diff_chunk(const PixelChunkArgs& a, hipStream_t s);
 hipError_t launch_pixel_merge_chunk(const PixelChunkArgs& a, hipStream_t s);
+hipError_t launch_pixel_features_chunk(const PixelChunkArgs& a, hipStream_t s);
+hipError_t launch_pixel_gather_chunk(const PixelChunkArgs& a, hipStream_t s);
 
 // The group detector: the groups' layouts (a rectangle of cells each,
 // row-major over the group grid; each layout names its cells and their

@@ -2184,6 +2184,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
     uint16_t* tgate = reinterpret_cast<uint16_t*>(sm + a.lds_tgate);
     uint32_t* txy = reinterpret_cast<uint32_t*>(sm + a.lds_txy);
     uint8_t* toct = sm + a.lds_toct;
+    uint32_t* tsrc = reinterpret_cast<uint32_t*>(sm + a.lds_tsrc);
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(a.layouts + c);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
@@ -2272,6 +2273,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
             if (i < 0) continue;
             atomicOr(&pres[i >> 6], 1ull << (i & 63));
             score[i] = kp.score;
+            if (a.msrc) tsrc[i] = kPixelFromPrev | (src0 + e);
         }
     }
     __syncthreads();
@@ -2341,6 +2343,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
                 if (i < 0 || !(forced || changed_i(fpb, i))) continue;
                 atomicOr(&pres[i >> 6], 1ull << (i & 63));
                 score[i] = kp.score;
+                if (a.msrc) tsrc[i] = ((uint32_t)j << kPixelFrameShift) | (cb + e);
             }
             __syncthreads();
             // D_j of the cell in decision order
@@ -2383,7 +2386,10 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
                     }
                     kp.pad = 0;
                     kp.score = score[i];
-                    if (pb + at < a.plist_cap) dst[at] = kp;
+                    if (pb + at < a.plist_cap) {
+                        dst[at] = kp;
+                        if (a.msrc) a.msrc[(size_t)j * a.list_stride + pb + at] = tsrc[i];
+                    }
                     ++at;
                 }
                 total += sum;
@@ -2392,6 +2398,65 @@ __global__ __launch_bounds__(kMergeBlock) void k_pixel_merge_chunk(PixelChunkArg
             if (tid == 0) a.mcount[(size_t)j * a.ncell + c] = total;
         }
         b0 += nb;
+    }
+}
+
+// Features of the maxima of every listed (frame, cell) of a chunk with a
+// per-pixel mask, on that frame's levels, at their places in its F list
+// (a 256-thread workgroup per (cell, frame), as k_describe_chunk).
+__global__ __launch_bounds__(kDescBlock) void k_pixel_features_chunk(PixelChunkArgs a)
+{
+    __shared__ int s_v[kDescBlock / 64][64];
+    __shared__ uint8_t s_patch[kDescBlock / 64][kPatch * kPatch];
+    const int c = blockIdx.x, j = blockIdx.y;
+    if (((a.marks[(size_t)c * a.Kw + (j >> 6)] >> (j & 63)) & 1ull) == 0ull) return;
+    const uint32_t cb = a.cell_base[c];
+    const uint32_t n = cb >= a.list_cap ? 0u : min(a.table[j].own_count[c], a.list_cap - cb);
+    const ChunkArgs& t = a.table[j];
+    describe_entries(ChunkLevels{t, a.frames + (size_t)j * a.stride, a.pitch}, a.tab, a.O, a.t, t.d.list_cur,
+                     a.tab ? a.sdesc + (size_t)j * a.list_cap : nullptr,
+                     a.sref ? a.sref + (size_t)j * a.list_cap : nullptr, cb, n, a.list_cap, s_v, s_patch);
+}
+
+// Each chunk frame's records after the compaction, a workgroup per (cell,
+// frame): frame j's entries of cell c are the merged list of the newest
+// listed frame f <= j (in order), so entry k takes the record its source
+// names; with no listed frame, the records of the list before the chunk.
+__global__ __launch_bounds__(kDescBlock) void k_pixel_gather_chunk(PixelChunkArgs a)
+{
+    const int c = blockIdx.x, j = blockIdx.y;
+    const bool last = j == a.n_frames - 1;
+    const uint32_t n = last ? a.last_count[c] : a.counts[(size_t)j * a.ncell + c];
+    const uint32_t dst0 = last ? a.last_offs[c] : a.offs[(size_t)j * a.ncell + c];
+    kpd_descriptor* ddst = a.tab ? (last ? a.last_desc : a.cdesc + (size_t)j * a.list_stride) : nullptr;
+    kpd_refined* rdst = a.sref ? (last ? a.last_ref : a.cref + (size_t)j * a.list_stride) : nullptr;
+    // the newest listed frame up to j
+    const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
+    int f = -1;
+    for (int q = j >> 6; q >= 0 && f < 0; --q) {
+        unsigned long long w = mw[q];
+        if (q == (j >> 6) && (j & 63) != 63) w &= (2ull << (j & 63)) - 1ull;
+        if (w) f = 64 * q + 63 - __clzll(w);
+    }
+    constexpr int kw = sizeof(kpd_descriptor) / 8;
+    for (uint32_t i = threadIdx.x; i < n * kw; i += kDescBlock) {
+        const uint32_t e = i / kw, q = i % kw;
+        if (dst0 + e >= a.dlist_cap) break;
+        uint32_t src;
+        if (f < 0) {
+            src = kPixelFromPrev | (a.prev_offs[c] + e);
+        } else {
+            src = a.msrc[(size_t)f * a.list_stride + a.pbase[c] + e];
+        }
+        const bool prev = (src & kPixelFromPrev) != 0u;
+        const size_t at = prev ? (size_t)(src & ~kPixelFromPrev)
+                               : (size_t)(src >> kPixelFrameShift) * a.list_cap + (src & ((1u << kPixelFrameShift) - 1u));
+        if (prev && at >= a.prev_cap) continue;
+        if (ddst) {
+            const uint64_t* s64 = reinterpret_cast<const uint64_t*>(prev ? a.prev_desc : a.sdesc);
+            reinterpret_cast<uint64_t*>(ddst)[(size_t)(dst0 + e) * kw + q] = s64[at * kw + q];
+        }
+        if (rdst && q == 0) rdst[dst0 + e] = prev ? a.prev_ref[at] : a.sref[at];
     }
 }
 
@@ -2624,6 +2689,18 @@ hipError_t launch_pixel_diff_chunk(const PixelChunkArgs& a, hipStream_t s)
     const int items = a.n_frames * a.ncell;
     hipLaunchKernelGGL(k_pixel_diff_chunk, dim3((items + kDiffWaves - 1) / kDiffWaves), dim3(64 * kDiffWaves), 0, s,
                        a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pixel_features_chunk(const PixelChunkArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pixel_features_chunk, dim3(a.ncell, a.n_frames), dim3(kDescBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pixel_gather_chunk(const PixelChunkArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pixel_gather_chunk, dim3(a.ncell, a.n_frames), dim3(kDescBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -2,7 +2,7 @@
 Sec. 2's interpolation) under the per-pixel masks of Sec. 3.1: with Eq. 1
 per feature a marked cell holds both new features (computed) and carried
 ones (whose records come from D_{n-1}). Every frame's features against the
-oracle's, bit for bit, for single-frame pushes and batch ticks."""
+oracle's, bit for bit, for single-frame pushes, batch ticks and chunks."""
 import numpy as np
 import pytest
 
@@ -144,16 +144,80 @@ def test_cells_too_large_for_the_lds(kpd):
     g.close()
 
 
-def test_chunks_reject_features_with_a_per_pixel_mask(kpd):
+def run_chunks(kpd, frames, det, plan, K, modes, desc=True, ref=True):
+    """Chunks (plan: lengths, 0 = one push_frame call) with modes {step:
+    (mode, layer)}: every frame's keypoints, mask after each call and
+    features against the oracle's."""
     import torch
-    sc, d = synth.SCENES["c1_320x240"], synth.DETECTORS["c1_320x240"]
-    frames = synth.make_video(sc, 4)
-    g = kpd.Stream(320, 240, kpd.make_params(d.fast_t, d.n_octaves, d.grid_cols, d.grid_rows, 8, KB_OFF, 0, 4,
-                                             layer_mask=1, features=kpd.FEAT_DESCRIPTOR))
-    g.set_mask_mode(1, 2)
-    with pytest.raises(kpd.KpdError):
-        g.push_chunk(torch.from_numpy(frames).cuda())
-    g.set_mask_mode(0, 0)
-    g.push_chunk(torch.from_numpy(frames).cuda())
-    assert len(g.chunk_descriptors(3)) == len(g.chunk_keypoints(3))
+    F, H, W = frames.shape
+    t, O, Nc, Nr, TI, TH = det
+    feats = (kpd.FEAT_DESCRIPTOR if desc else 0) | (kpd.FEAT_REFINE if ref else 0)
+    g = kpd.Stream(W, H, kpd.make_params(t, O, Nc, Nr, TI, TH, 0, K, layer_mask=1, features=feats))
+    o = oracle.Stream(W, H, t, O, Nc, Nr, TI, TH)
+    o.set_descriptors(desc)
+    o.set_refine(ref)
+    dev = torch.from_numpy(frames).cuda()
+    i = 0
+    n = 0
+    for step, m in enumerate(plan):
+        if i >= F:
+            break
+        if step in modes:
+            g.set_mask_mode(*modes[step])
+            o.set_id_mode(*modes[step])
+        if m == 0:
+            g.push(dev[i], retain=True)
+            o.push(frames[i])
+            n += compare(kpd, g, o, f"single frame {i}", desc, ref)
+            i += 1
+            continue
+        m = min(m, F - i)
+        g.push_chunk(dev[i:i + m])
+        for j in range(m):
+            o.push(frames[i + j])
+            ok, _, _, _ = o.get()
+            where = f"chunk at {i} frame {i + j}"
+            assert tuples(g.chunk_keypoints(j)) == tuples(ok), where
+            if desc:
+                gd = g.chunk_descriptors(j)
+                ob, od = o.descriptors()
+                np.testing.assert_array_equal(gd["sector"].astype(np.int64), ob.astype(np.int64),
+                                              err_msg=f"sectors {where}")
+                np.testing.assert_array_equal(gd["bits"], od, err_msg=f"bits {where}")
+            if ref:
+                gr = g.chunk_refined(j)
+                got = np.stack([gr["x"], gr["y"], gr["log2_scale"], gr["score"]], axis=1).astype(np.float32)
+                np.testing.assert_array_equal(got.view(np.uint32), o.refined().view(np.uint32),
+                                              err_msg=f"refined {where}")
+            n += len(ok)
+        n += compare(kpd, g, o, f"last frame of chunk at {i}", desc, ref)
+        i += m
     g.close()
+    return n
+
+
+@pytest.mark.parametrize("mode,layer", [(1, 2), (1, 0), (2, 0)])
+def test_c1_chunks(kpd, mode, layer):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 24)
+    assert run_chunks(kpd, frames, det_of("c1_320x240"), [5, 0, 8, 1, 0, 8], K=8, modes={0: (mode, layer)}) > 0
+
+
+def test_c2_top_layer_whole_video_in_one_chunk(kpd):
+    frames = synth.make_video(synth.SCENES["c2_640x480"], 300)
+    assert run_chunks(kpd, frames, det_of("c2_640x480"), [300], K=300, modes={0: (1, 3)}) > 0
+
+
+def test_chunks_mode_switches_and_parts(kpd):
+    frames = synth.make_video(synth.SCENES["c1_320x240"], 40)
+    run_chunks(kpd, frames, det_of("c1_320x240"), [4, 0, 6, 6, 0, 6, 6, 6], K=6,
+               modes={0: (1, 2), 2: (2, 0), 4: (0, 0), 6: (1, 1)}, ref=False)
+    run_chunks(kpd, frames[:20], det_of("c1_320x240"), [6, 7, 7], K=7, modes={0: (2, 0)}, desc=False)
+
+
+@pytest.mark.parametrize("W,H,det,mode,layer", [
+    (333, 251, (25, 4, 7, 5, 4, KB_OFF), 1, 3),
+    (200, 120, (18, 6, 7, 5, 8, KB_OFF), 2, 0),
+])
+def test_chunk_shapes(kpd, W, H, det, mode, layer):
+    sc = synth.Scene(W, H, 6, 6, 3, max(4, min(W, H) // 3), 1.0, 2.0, False, 980 + W)
+    run_chunks(kpd, synth.make_video(sc, 14), det, [7, 0, 6], K=7, modes={0: (mode, layer)})
