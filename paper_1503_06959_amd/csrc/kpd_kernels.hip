@@ -1487,49 +1487,74 @@ struct ChunkLevels {
     __device__ int h(int o) const { return t.d.h[o]; }
 };
 
-// Features of a chunk's lists, a workgroup per (cell c, frame j), after
-// compaction. Frame j's list holds cell c's entries of the newest frame
-// f <= j that marked c, or of the list before the chunk when none did. So
-// when j marked c, the workgroup computes the features of those entries on
-// frame j's levels and copies them to every following frame up to c's next
-// mark; when no frame up to j marked c, it copies the records of the list
-// before the chunk; otherwise another workgroup writes them.
+// Features of a chunk's lists after compaction, in two launches of a
+// 256-thread workgroup per (cell c, frame j). Frame j's list holds cell c's
+// entries of the newest frame f <= j that marked c, or of the list before
+// the chunk when none did. The first launch computes, where j marked c,
+// the features of those entries on frame j's levels; the second copies,
+// where j did not, the records of frame f's entries (or of the list before
+// the chunk) to frame j's.
+struct ChunkFeatureLists {
+    const DescChunkArgs& a;
+    int c;
+    __device__ const kpd_keypoint* list(int f) const
+    {
+        return f == a.n_frames - 1 ? a.last_list : a.lists + (size_t)f * a.list_stride;
+    }
+    __device__ uint32_t count(int f) const
+    {
+        return f == a.n_frames - 1 ? a.last_count[c] : a.counts[(size_t)f * a.ncell + c];
+    }
+    __device__ uint32_t off(int f) const
+    {
+        return f == a.n_frames - 1 ? a.last_offs[c] : a.offs[(size_t)f * a.ncell + c];
+    }
+    __device__ kpd_descriptor* desc(int f) const
+    {
+        if (!a.tab) return nullptr;
+        return f == a.n_frames - 1 ? a.last_desc : a.descs + (size_t)f * a.list_stride;
+    }
+    __device__ kpd_refined* ref(int f) const
+    {
+        if (!a.refs) return nullptr;
+        return f == a.n_frames - 1 ? a.last_ref : a.refs + (size_t)f * a.list_stride;
+    }
+    // the newest frame <= j whose bit is set in the cell's mark words, -1 if none
+    __device__ int newest_marked(int j) const
+    {
+        const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
+        for (int q = j >> 6; q >= 0; --q) {
+            unsigned long long w = mw[q];
+            if (q == (j >> 6) && (j & 63) != 63) w &= (2ull << (j & 63)) - 1ull;
+            if (w) return 64 * q + 63 - __clzll(w);
+        }
+        return -1;
+    }
+};
+
 __global__ __launch_bounds__(kDescBlock) void k_describe_chunk(DescChunkArgs a)
 {
     __shared__ int s_v[kDescBlock / 64][64];
     __shared__ uint8_t s_patch[kDescBlock / 64][kPatch * kPatch];
     const int c = blockIdx.x, j = blockIdx.y;
-    const unsigned long long* mw = a.marks + (size_t)c * a.Kw;
-    auto marked = [&](int f) { return ((mw[f >> 6] >> (f & 63)) & 1ull) != 0; };
-    const bool last = j == a.n_frames - 1;
-    auto list_of = [&](int f) { return f == a.n_frames - 1 ? a.last_list : a.lists + (size_t)f * a.list_stride; };
-    auto count_of = [&](int f) { return f == a.n_frames - 1 ? a.last_count[c] : a.counts[(size_t)f * a.ncell + c]; };
-    auto off_of = [&](int f) { return f == a.n_frames - 1 ? a.last_offs[c] : a.offs[(size_t)f * a.ncell + c]; };
-    auto desc_of = [&](int f) -> kpd_descriptor* {
-        if (!a.tab) return nullptr;
-        return f == a.n_frames - 1 ? a.last_desc : a.descs + (size_t)f * a.list_stride;
-    };
-    auto ref_of = [&](int f) -> kpd_refined* {
-        if (!a.refs) return nullptr;
-        return f == a.n_frames - 1 ? a.last_ref : a.refs + (size_t)f * a.list_stride;
-    };
-    const uint32_t n = count_of(j), dst0 = off_of(j);
-    if (!marked(j)) {
-        // carried from before the chunk when no frame up to j marked c
-        const int qj = j >> 6;
-        const unsigned long long upto = (2ull << (j & 63)) - 1ull;   // bit 63 is j's own, unset here
-        for (int q = 0; q <= qj; ++q)
-            if ((q < qj ? mw[q] : mw[q] & upto) != 0ull) return;
-        copy_feature_records(a.prev_desc, desc_of(j), a.prev_ref, ref_of(j), a.prev_offs[c], dst0, n, a.list_cap);
-        return;
-    }
+    if (((a.marks[(size_t)c * a.Kw + (j >> 6)] >> (j & 63)) & 1ull) == 0ull) return;
+    const ChunkFeatureLists F{a, c};
     const ChunkArgs& t = a.table[j];
-    describe_entries(ChunkLevels{t, a.frames + (size_t)j * a.stride, a.pitch}, a.tab, a.O, a.t, list_of(j), desc_of(j),
-                     ref_of(j), dst0, n, a.list_cap, s_v, s_patch);
-    if (last) return;
-    __syncthreads();   // the records just written are the copies' source
-    for (int f = j + 1; f < a.n_frames && !marked(f); ++f)
-        copy_feature_records(desc_of(j), desc_of(f), ref_of(j), ref_of(f), dst0, off_of(f), count_of(f), a.list_cap);
+    describe_entries(ChunkLevels{t, a.frames + (size_t)j * a.stride, a.pitch}, a.tab, a.O, a.t, F.list(j), F.desc(j),
+                     F.ref(j), F.off(j), F.count(j), a.list_cap, s_v, s_patch);
+}
+
+__global__ __launch_bounds__(kDescBlock) void k_carry_chunk_features(DescChunkArgs a)
+{
+    const int c = blockIdx.x, j = blockIdx.y;
+    const ChunkFeatureLists F{a, c};
+    const int f = F.newest_marked(j);
+    if (f == j) return;   // computed by the first launch
+    if (f < 0)
+        copy_feature_records(a.prev_desc, F.desc(j), a.prev_ref, F.ref(j), a.prev_offs[c], F.off(j), F.count(j),
+                             a.list_cap);
+    else
+        copy_feature_records(F.desc(f), F.desc(j), F.ref(f), F.ref(j), F.off(f), F.off(j), F.count(j), a.list_cap);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin by index. The tile pass
@@ -2719,6 +2744,7 @@ hipError_t launch_describe_batch(const TickArgs* table, const uint16_t* map, int
 hipError_t launch_describe_chunk(const DescChunkArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_describe_chunk, dim3(a.ncell, a.n_frames), dim3(kDescBlock), 0, s, a);
+    hipLaunchKernelGGL(k_carry_chunk_features, dim3(a.ncell, a.n_frames), dim3(kDescBlock), 0, s, a);
     return hipGetLastError();
 }
 
