@@ -16,7 +16,7 @@ SOURCES = [os.path.join(CSRC, "kpd_api.cpp"), os.path.join(CSRC, "kpd_kernels.hi
            os.path.join(CSRC, "kpd_layers.cpp"), os.path.join(CSRC, "kpd_layers.hip"),
            os.path.join(CSRC, "kpd_noalloc.hip")]
 HEADERS = [os.path.join(CSRC, "kpd_geom.h"), os.path.join(CSRC, "kpd_kernels.h"), os.path.join(CSRC, "kpd_tcd.h"), os.path.join(CSRC, "kpd_errors.h"), os.path.join(CSRC, "kpd_group.h"),
-           os.path.join(CSRC, "kpd_layers.h"), os.path.join(CSRC, "kpd_fit.h"),
+           os.path.join(CSRC, "kpd_layers.h"), os.path.join(CSRC, "kpd_fit.h"), os.path.join(CSRC, "kpd_trace.h"),
            os.path.join(os.path.dirname(HERE), "include", "kpd.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,9 +30,13 @@ FLAGS = [
 ]
 
 
+# named ranges around the entry points (roctx)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES, *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

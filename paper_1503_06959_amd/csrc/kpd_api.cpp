@@ -16,6 +16,7 @@
 #include "kpd_errors.h"
 #include "kpd_geom.h"
 #include "kpd_kernels.h"
+#include "kpd_trace.h"
 
 namespace {
 
@@ -1072,6 +1073,7 @@ extern "C" {
 
 int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
 {
+    const kpd::TraceRange trace_range("kpd:push_frame");
     kpd::TickArgs t;
     const int rc = stage_frame(s, frame, pitch_bytes, flags, &t);
     if (rc != KPD_OK) return rc;
@@ -1180,6 +1182,7 @@ int seq_run(const Layout& L, int n, int cap)
 
 int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes, int n_frames)
 {
+    const kpd::TraceRange trace_range("kpd:push_frames");
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     const Layout& L = s->L;
     if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
@@ -1546,6 +1549,7 @@ int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity
 
 int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask)
 {
+    const kpd::TraceRange trace_range("kpd:get_keypoints");
     if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
     if (!count) return fail(KPD_EINVAL, "count is NULL");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
@@ -1974,6 +1978,7 @@ int batch_push_many(kpd_batch* b, int n, kpd_stream* const* streams, const uint8
 
 int batch_tick(kpd_batch* b)
 {
+    const kpd::TraceRange trace_range("kpd:batch_tick");
     if (!b) return fail(KPD_ESTATE, "batch is closed");
     if (b->maps_dirty) {
         const int rc = rebuild_maps(b);

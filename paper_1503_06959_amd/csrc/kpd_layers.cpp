@@ -12,6 +12,7 @@
 #include "kpd_errors.h"
 #include "kpd_kernels.h"
 #include "kpd_layers.h"
+#include "kpd_trace.h"
 
 namespace {
 
@@ -325,6 +326,7 @@ int kpd_lstream_open(int width, int height, const kpd_params* params, void* dev_
 
 int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
 {
+    const kpd::TraceRange trace_range("kpd:lstream_push");
     if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     const LsLayout& L = s->L;
     if (!frame) return kpd::api_fail(KPD_EINVAL, "frame is NULL");
@@ -397,6 +399,7 @@ int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, i
 int kpd_lstream_push_frames(kpd_lstream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes,
                             int n_frames)
 {
+    const kpd::TraceRange trace_range("kpd:lstream_push_frames");
     if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     const LsLayout& L = s->L;
     if (L.K < 2) return kpd::api_fail(KPD_EINVAL, "stream opened without chunk_frames");
@@ -700,6 +703,7 @@ int kpd_lbatch_push(kpd_lbatch* b, int slot, const uint8_t* frame, size_t pitch_
 
 int kpd_lbatch_tick(kpd_lbatch* b)
 {
+    const kpd::TraceRange trace_range("kpd:lbatch_tick");
     if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
     const LbLayout& B = b->B;
     const LsLayout& L = B.s;
@@ -854,6 +858,7 @@ int kpd_detect_layers(const uint8_t* frame, size_t pitch_bytes, int width, int h
                       void* workspace, size_t workspace_bytes, kpd_keypoint* out, uint32_t capacity, uint32_t* count,
                       void* hip_stream)
 {
+    const kpd::TraceRange trace_range("kpd:detect_layers");
     kpd::LayerGeom g;
     std::string why;
     if (!layer_geom(width, height, n_octaves, &g, &why)) return kpd::api_fail(KPD_EINVAL, why);

@@ -11,6 +11,7 @@
 #include "../../include/kpd.h"
 #include "kpd_errors.h"
 #include "kpd_tcd.h"
+#include "kpd_trace.h"
 
 namespace {
 
@@ -140,6 +141,7 @@ int tcd_open(int width, int height, const kpd_params* det, const kpd_tcd_params*
 
 int tcd_push(kpd_tcd* s, const uint8_t* frame, size_t pitch_bytes, int flags)
 {
+    const kpd::TraceRange trace_range("kpd:tcd_push");
     if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
     const TcdLayout& L = s->L;
     if (!frame) return kpd::api_fail(KPD_EINVAL, "frame is NULL");

@@ -98,6 +98,7 @@ print("ok")
 
 
 def test_library_parameter_validation_under_asan_ubsan(tmp_path):
+    from paper_1503_06959_amd import build as kbuild
     # host code sanitized (the device code is built plainly; the calls here never launch)
     src = os.path.join(ROOT, "paper_1503_06959_amd", "csrc")
     lib = str(tmp_path / "libkpd_san.so")
@@ -106,7 +107,7 @@ def test_library_parameter_validation_under_asan_ubsan(tmp_path):
     subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O1", "-g", "-std=c++17",
                     "-fPIC", "-shared", "-ffp-contract=off", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
                     "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=undefined", "-shared-libsan",
-                    "-o", lib, *sources], check=True, capture_output=True)
+                    "-o", lib, *sources, *kbuild.LIBS], check=True, capture_output=True)
     rt = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
     if not rt:
         pytest.skip("clang's address-sanitizer runtime is not installed")
