@@ -537,7 +537,8 @@ struct kpd_stream {
     bool closed = false;
     // pinned host staging for get_keypoints: header, the first kStage
     // entries of D_n and the mask come back in one round trip
-    uint8_t* stage = nullptr;
+    uint8_t* stage = nullptr;       // pinned host staging of get_keypoints
+    uint8_t* stage_dev = nullptr;   // its address on the device
 
     ~kpd_stream()
     {
@@ -816,6 +817,7 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&s->stage), 64 + kStage * sizeof(kpd_keypoint) + (size_t)L.ncell,
                           hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->stage_dev), s->stage, 0);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         delete s;
@@ -1555,16 +1557,15 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
     const Layout& L = s->L;
     const int k = s->fb_last;
-    // one round trip: the header, the first entries of D_n and the mask
+    // one round trip: a kernel writes the header, the first entries of D_n
+    // and the mask into the pinned staging buffer
     const size_t pre = std::min(L.list_cap1, kStage);
     uint8_t* st_list = s->stage + 64;
     uint8_t* st_mask = st_list + kStage * sizeof(kpd_keypoint);
-    KPD_HIP(hipMemcpyAsync(s->stage, s->at<uint32_t>(L.off_hdr), 16, hipMemcpyDeviceToHost, s->stream));
-    KPD_HIP(hipMemcpyAsync(st_list, s->at<kpd_keypoint>(L.off_list[k]), pre * sizeof(kpd_keypoint),
-                           hipMemcpyDeviceToHost, s->stream));
-    if (cell_mask)
-        KPD_HIP(hipMemcpyAsync(st_mask, s->at<uint8_t>(L.off_mask), (size_t)L.ncell, hipMemcpyDeviceToHost,
-                               s->stream));
+    KPD_HIP(kpd::launch_publish(s->at<uint32_t>(L.off_hdr), k ? kHdrTotal1 : kHdrTotal0,
+                                s->at<kpd_keypoint>(L.off_list[k]), (uint32_t)pre,
+                                cell_mask ? s->at<uint8_t>(L.off_mask) : nullptr, L.ncell, (uint32_t)kStage,
+                                s->stage_dev, s->stream));
     KPD_HIP(hipStreamSynchronize(s->stream));
     uint32_t hdr[4];
     std::memcpy(hdr, s->stage, sizeof(hdr));

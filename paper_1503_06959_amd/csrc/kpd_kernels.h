@@ -358,6 +358,12 @@ hipError_t set_group_lds_limit(int lds_bytes);
 // with one-cell layouts (sparse list), then D_n by k_compact1
 hipError_t launch_det1_groups(const DetectArgs& a, const GroupArgs& g, kpd_keypoint* sparse, uint32_t* own,
                               int ncell, int lds_bytes, int threads, hipStream_t s);
+// Copy a stream's header words (4), the first min(its D_n size, pre)
+// entries of D_n and, when mask is not null, the cell mask into pinned host
+// memory: words at stage, entries from stage + 64, the mask after kStage
+// entries. total_word: the header word that holds D_n's size.
+hipError_t launch_publish(const uint32_t* hdr, int total_word, const kpd_keypoint* list, uint32_t pre,
+                          const uint8_t* mask, int ncell, uint32_t stage_entries, uint8_t* stage, hipStream_t s);
 hipError_t launch_compact1(const DetectArgs& a, const kpd_keypoint* sparse, const uint32_t* cbase,
                            const uint32_t* own, hipStream_t s);
 

@@ -1557,6 +1557,28 @@ __global__ __launch_bounds__(kDescBlock) void k_carry_chunk_features(DescChunkAr
         copy_feature_records(F.desc(f), F.desc(j), F.ref(f), F.ref(j), F.off(f), F.off(j), F.count(j), a.list_cap);
 }
 
+// One workgroup copies what get_keypoints reads into its pinned staging
+// buffer (host memory the device writes over the bus): one launch and one
+// wait instead of a copy per part.
+constexpr int kPublishBlock = 1024;
+
+__global__ __launch_bounds__(kPublishBlock) void k_publish(const uint32_t* hdr, int total_word,
+                                                           const kpd_keypoint* list, uint32_t pre,
+                                                           const uint8_t* mask, int ncell, uint32_t stage_entries,
+                                                           uint8_t* stage)
+{
+    const uint32_t total = hdr[total_word];
+    const uint32_t n = min(total, pre);
+    if (threadIdx.x < 4) reinterpret_cast<uint32_t*>(stage)[threadIdx.x] = hdr[threadIdx.x];
+    uint2* dst = reinterpret_cast<uint2*>(stage + 64);
+    const uint2* src = reinterpret_cast<const uint2*>(list);
+    for (uint32_t i = threadIdx.x; i < n; i += kPublishBlock) dst[i] = src[i];
+    if (mask) {
+        uint8_t* m = stage + 64 + (size_t)stage_entries * sizeof(kpd_keypoint);
+        for (int c = threadIdx.x; c < ncell; c += kPublishBlock) m[c] = mask[c];
+    }
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin by index. The tile pass
 // runs on a grid rounded up to a multiple of 8 and hands XCD k the k-th
 // contiguous band of row-major tiles, so tiles that share cache lines share
@@ -2700,6 +2722,14 @@ hipError_t launch_detect_pixel_batch(const TickArgs* table, const uint16_t* map,
                                      hipStream_t s)
 {
     hipLaunchKernelGGL(k_detect_pixel_batch<kDetLatency>, dim3(ncells), dim3(kDetLatency), lds_bytes, s, table, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish(const uint32_t* hdr, int total_word, const kpd_keypoint* list, uint32_t pre,
+                          const uint8_t* mask, int ncell, uint32_t stage_entries, uint8_t* stage, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(kPublishBlock), 0, s, hdr, total_word, list, pre, mask, ncell,
+                       stage_entries, stage);
     return hipGetLastError();
 }
 
