@@ -726,7 +726,10 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     int dev = 0, lds_max = 0;
     KPD_HIP(hipGetDevice(&dev));
     KPD_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (L.lds_bytes > std::max(lds_max, 65536) || std::max(L.glds, L.glds1_512) > std::max(lds_max, 65536))
+    int group_static = 0;
+    KPD_HIP(kpd::group_static_lds(&group_static));
+    if (L.lds_bytes > std::max(lds_max, 65536) ||
+        std::max(L.glds, L.glds1_512) + group_static > std::max(lds_max, 65536))
         return fail(KPD_EINVAL, "cells need more LDS than a workgroup can hold");
     KPD_HIP(kpd::set_detect_lds_limit(L.lds_bytes));
 

@@ -4,6 +4,8 @@
 // masked chunks and batch ticks, one cell per workgroup at a time.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kpd_group.h"
 
 namespace kpd {
@@ -167,18 +169,33 @@ hipError_t launch_detect_chunk_groups(const ChunkArgs* table, const ChunkHead& h
     return hipGetLastError();
 }
 
+namespace {
+const void* const kGroupKernels[] = {reinterpret_cast<const void*>(k_detect_chunk_groups<512>),
+                                     reinterpret_cast<const void*>(k_detect_chunk_groups<256>),
+                                     reinterpret_cast<const void*>(k_det1_groups<512>),
+                                     reinterpret_cast<const void*>(k_det1_groups<256>),
+                                     reinterpret_cast<const void*>(k_detect_list_groups<512>),
+                                     reinterpret_cast<const void*>(k_detect_list_groups<256>),
+                                     reinterpret_cast<const void*>(k_detect_list_groups<128>),
+                                     reinterpret_cast<const void*>(k_detect_list_batch_groups<256>)};
+}  // namespace
+
+hipError_t group_static_lds(int* bytes)
+{
+    *bytes = 0;
+    for (const void* k : kGroupKernels) {
+        hipFuncAttributes fa{};
+        const hipError_t e = hipFuncGetAttributes(&fa, k);
+        if (e != hipSuccess) return e;
+        *bytes = std::max(*bytes, (int)fa.sharedSizeBytes);
+    }
+    return hipSuccess;
+}
+
 hipError_t set_group_lds_limit(int lds_bytes)
 {
     if (lds_bytes <= 65536) return hipSuccess;
-    const void* kernels[] = {reinterpret_cast<const void*>(k_detect_chunk_groups<512>),
-                             reinterpret_cast<const void*>(k_detect_chunk_groups<256>),
-                             reinterpret_cast<const void*>(k_det1_groups<512>),
-                             reinterpret_cast<const void*>(k_det1_groups<256>),
-                             reinterpret_cast<const void*>(k_detect_list_groups<512>),
-                             reinterpret_cast<const void*>(k_detect_list_groups<256>),
-                             reinterpret_cast<const void*>(k_detect_list_groups<128>),
-                             reinterpret_cast<const void*>(k_detect_list_batch_groups<256>)};
-    for (const void* k : kernels) {
+    for (const void* k : kGroupKernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) return e;
     }

@@ -354,6 +354,8 @@ hipError_t launch_detect_list_batch_groups(const TickArgs* table, const uint16_t
 hipError_t launch_detect_chunk_groups(const ChunkArgs* table, const ChunkHead& h, const GroupArgs& g, int lds_bytes,
                                       int threads, hipStream_t s);
 hipError_t set_group_lds_limit(int lds_bytes);
+// largest static LDS of the group kernels, which their dynamic LDS sits beside
+hipError_t group_static_lds(int* bytes);
 // one frame with the per-cell mask: marks and detection of the marked cells
 // with one-cell layouts (sparse list), then D_n by k_compact1
 hipError_t launch_det1_groups(const DetectArgs& a, const GroupArgs& g, kpd_keypoint* sparse, uint32_t* own,
