@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 64-stream batched ticks (both forms) and print their line (for profiling)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-horizon", type=float, default=48.0)
     ap.add_argument("--serve-speedup", type=float, default=4.0)
@@ -758,7 +760,7 @@ def pingpong(k: int, n: int) -> int:
     return m if m < n else 2 * n - 2 - m
 
 
-def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
+def batched_workload(kpd, n_ticks: int, clip: int, warmup: int, cpu: bool = True) -> dict:
     """64 mixed-resolution streams (24 x 320x240, 24 x 640x480, 16 x 1280x720),
     one frame each per tick: batched ticks (four graph-replayed launches per
     tick, and the single-launch form beside them) against plain per-stream
@@ -845,7 +847,7 @@ def batched_workload(kpd, n_ticks: int, clip: int, warmup: int) -> dict:
                              "frames_per_s": round(64 / sec_p, 1), "ms_per_tick": round(sec_p * 1e3, 4),
                              "launches_per_tick": 192},
         "batched_over_plain": round(sec_p / sec_b, 3),
-        "cpu_all_cores": oracle_all_cores(clip, 10.0),
+        **({"cpu_all_cores": oracle_all_cores(clip, 10.0)} if cpu else {}),
     }
 
 
@@ -920,6 +922,7 @@ PROFILE_CASES = {
     "kt_c3_1920x1080_masked_frame": ("trace", "--workload c3_1920x1080 --mode masked --steps 4 --warmup 1"),
     "kt_c3_1920x1080_full_frame": ("trace", "--workload c3_1920x1080 --mode full --steps 4 --warmup 1"),
     "kt_c2_640x480_layer3_frame": ("trace", "--workload c2_640x480 --mode masked --layer 3 --steps 10 --warmup 2"),
+    "kt_batch_64_streams_tick": ("trace", "--batch-only --batch-ticks 60 --warmup 5"),
     "pmc_c2_640x480_masked_chunked": ("pmc", "--workload c2_640x480 --mode masked --chunked --steps 2 --warmup 0"),
     "pmc_c2_640x480_full_chunked": ("pmc", "--workload c2_640x480 --mode full --chunked --steps 2 --warmup 0"),
     "pmc_c3_1920x1080_full_chunked": ("pmc", "--workload c3_1920x1080 --mode full --chunked --steps 2 --warmup 0"),
@@ -1000,6 +1003,9 @@ def summarize_profiles(out: str) -> None:
         if kind != "trace":
             continue
         path = os.path.join(out, case, "kt_kernel_stats.csv")
+        if not os.path.exists(path):
+            log(f"[bench] no kernel trace of {case} under {out}: its summary is left as it is")
+            continue
         rows = list(csv.DictReader(open(path)))
         lines = [f"# kernel durations, {case}", "", "command (R = the repository root, OUT = the output folder given to --profile-script, run from /tmp):",
                  "  " + profile_command(case, "$OUT"), "",
@@ -1018,6 +1024,9 @@ def summarize_profiles(out: str) -> None:
                 agg[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
         return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
+    if not os.path.exists(os.path.join(out, "pmc_copy_256MiB_FETCH_SIZE", "p_counter_collection.csv")):
+        log(f"[bench] no counter runs under {out}: traffic and VALU summaries are left as they are")
+        return
     copy_bytes = 256 << 20
     fc, wc = pmc("pmc_copy_256MiB", "FETCH_SIZE"), pmc("pmc_copy_256MiB", "WRITE_SIZE")
     f_scale = copy_bytes / (fc["__amd_rocclr_copyBuffer"][0] * 1024)
@@ -1133,6 +1142,9 @@ def main():
     global TILE, GROUPS
     TILE = args.tile
     GROUPS = tuple(int(v) for v in args.groups.split("x"))
+    if args.batch_only:
+        print(json.dumps(batched_workload(kpd, args.batch_ticks, args.batch_clip, args.warmup, cpu=False)), flush=True)
+        return
 
     wl = Workload(args.workload)
     if args.mode != "both":
