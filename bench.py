@@ -1162,6 +1162,8 @@ def main():
                           "value": round(r["mpix_per_s"], 2), "unit": "Mpixel/s",
                           "frames_per_s": round(r["frames_per_s"], 1),
                           "latency_ms": {"p50": round(r["lat_p50"], 4), "p99": round(r["lat_p99"], 4)},
+                          **({"device_ms_per_frame": {"p50": round(r["dev_p50"], 4), "p99": round(r["dev_p99"], 4)}}
+                             if "dev_p50" in r else {}),
                           "roofline": roofline_of(wl, r, masked, stats=stats)}), flush=True)
         return
     K = chunk_of(args, wl)
