@@ -102,6 +102,7 @@ struct Layout {
     // 256 and 512 threads
     size_t off_glay1 = 0;
     int glds1_128 = 0, glds1_256 = 0, glds1_512 = 0;
+    int glds1_1024 = 0;   // 0: one cell does not fit a 1024-thread workgroup's LDS
     size_t total = 0;
 };
 
@@ -212,7 +213,8 @@ int list_threads(const Layout& L)
 // queues scale with the waves).
 int glds1_for(const Layout& L, int threads)
 {
-    return threads == 128 ? L.glds1_128 : (threads == 512 ? L.glds1_512 : L.glds1_256);
+    return threads == 128 ? L.glds1_128
+                          : (threads == 512 ? L.glds1_512 : (threads == 1024 ? L.glds1_1024 : L.glds1_256));
 }
 
 // Whether the sequential tile pass takes this geometry: octaves to level 5
@@ -408,6 +410,7 @@ bool make_layout(int W, int H, const kpd_params* p, Layout* L, std::string* why)
         *why = "cells too large for the detector";
         return false;
     }
+    if (!group_layouts(*L, 1, 1, 16, nullptr, &L->glds1_1024) || L->glds1_1024 > 160 * 1024) L->glds1_1024 = 0;
 
     size_t off = 0;
     L->off_hdr = off; off = align_up(off + 64);
@@ -525,6 +528,7 @@ struct kpd_stream {
     int prev_pitch = 0;
     int prev_dw = 0;
     int fb_last = 1;          // which of the two single-frame buffers holds the latest D_n
+    int det1_threads = 512;   // workgroup size of a single frame's marked cells
     int seq_cap = 0;          // resident workgroups of the sequential chunk tile pass (0: not asked yet)
     int id_mode = 0;          // 0: per-cell mean difference at level 0; 1: per-pixel on layer id_layer;
                               // 2: per-pixel on every level, one mask per octave
@@ -731,12 +735,16 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
     if (L.lds_bytes > std::max(lds_max, 65536) ||
         std::max(L.glds, L.glds1_512) + group_static > std::max(lds_max, 65536))
         return fail(KPD_EINVAL, "cells need more LDS than a workgroup can hold");
+    // a single frame's marked cells run 1024 threads each when one cell fits
+    const int det1_threads =
+        L.glds1_1024 > 0 && L.glds1_1024 + group_static <= std::max(lds_max, 65536) ? 1024 : 512;
     KPD_HIP(kpd::set_detect_lds_limit(L.lds_bytes));
 
     kpd_stream* s = new (std::nothrow) kpd_stream();
     if (!s) return fail(KPD_ENOMEM, "host allocation failed");
     s->L = L;
     s->p = *params;
+    s->det1_threads = det1_threads;
     s->stream = reinterpret_cast<hipStream_t>(hip_stream);
     s->arena = reinterpret_cast<uint8_t*>(dev_arena);
 
@@ -815,7 +823,8 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         if (e == hipSuccess)
             e = hipMemcpyAsync(s->arena + L.off_glay1, s->glay1.data(), s->glay1.size() * sizeof(kpd::GroupLayout),
                                hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = kpd::set_group_lds_limit(std::max(L.glds, L.glds1_512));
+        if (e == hipSuccess)
+            e = kpd::set_group_lds_limit(std::max({L.glds, L.glds1_512, glds1_for(L, s->det1_threads)}));
     }
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&s->stage), 64 + kStage * sizeof(kpd_keypoint) + (size_t)L.ncell,
@@ -1093,7 +1102,7 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
         ga.ngroups = L.ncell;
         ga.nc = L.nc;
         ga.al8 = (reinterpret_cast<uintptr_t>(t.d.lvl[0]) % 8 == 0 && t.d.pitch[0] % 8 == 0) ? 1 : 0;
-        const int threads = t.d.all_marked ? 256 : 512;
+        const int threads = t.d.all_marked ? 256 : s->det1_threads;
         const int lds = glds1_for(L, threads);
         KPD_HIP(timed(s, KPD_K_DETECT, [&] {
             return kpd::launch_det1_groups(t.d, ga, t.sparse, t.own_count, L.ncell, lds, threads, s->stream);

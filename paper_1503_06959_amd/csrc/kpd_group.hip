@@ -150,7 +150,9 @@ hipError_t launch_detect_list_batch_groups(const TickArgs* table, const uint16_t
 hipError_t launch_det1_groups(const DetectArgs& a, const GroupArgs& g, kpd_keypoint* sparse, uint32_t* own,
                               int ncell, int lds_bytes, int threads, hipStream_t s)
 {
-    if (threads == 512)
+    if (threads == 1024)
+        hipLaunchKernelGGL(k_det1_groups<1024>, dim3(ncell), dim3(1024), lds_bytes, s, a, g, sparse, own);
+    else if (threads == 512)
         hipLaunchKernelGGL(k_det1_groups<512>, dim3(ncell), dim3(512), lds_bytes, s, a, g, sparse, own);
     else
         hipLaunchKernelGGL(k_det1_groups<256>, dim3(ncell), dim3(256), lds_bytes, s, a, g, sparse, own);
@@ -172,6 +174,7 @@ hipError_t launch_detect_chunk_groups(const ChunkArgs* table, const ChunkHead& h
 namespace {
 const void* const kGroupKernels[] = {reinterpret_cast<const void*>(k_detect_chunk_groups<512>),
                                      reinterpret_cast<const void*>(k_detect_chunk_groups<256>),
+                                     reinterpret_cast<const void*>(k_det1_groups<1024>),
                                      reinterpret_cast<const void*>(k_det1_groups<512>),
                                      reinterpret_cast<const void*>(k_det1_groups<256>),
                                      reinterpret_cast<const void*>(k_detect_list_groups<512>),
