@@ -202,8 +202,8 @@ constexpr uint32_t kPixelStagedMaxima = 1024;  // maxima of a batch the per-pixe
 // shorten its chain; many cells mean many items, whose throughput decides:
 // smaller workgroups keep more of them in flight. Measured on the masked
 // videos (listed detection per 300 frames): 640x480 with 192 cells 17.3,
-// 18.9 and 24.4 us at 512, 256 and 128 threads; 1920x1080 with 576 cells
-// 245, 172 and 162 us.
+// 18.9 and 24.4 us at 512, 256 and 128 threads (26.3 at 1024, one
+// workgroup per CU); 1920x1080 with 576 cells 245, 172 and 162 us.
 int list_threads(const Layout& L)
 {
     return L.ncell <= 256 ? 512 : (L.ncell >= 512 ? 128 : 256);
