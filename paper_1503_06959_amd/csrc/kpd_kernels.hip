@@ -2579,18 +2579,24 @@ __global__ __launch_bounds__(kCompact1Block) void k_compact1(DetectArgs a, const
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ncell = a.nc * a.nr;
     const int c0 = blockIdx.x * kCells1, c1 = min(c0 + kCells1, ncell);
+    // both sources' words are loaded with the mark and one is kept, so a
+    // cell's count costs one round trip to memory instead of two
     auto count_of = [&](int c) -> uint32_t {
-        return a.mask[c] ? clamp_count(cbase[c], own[c], a.list_cap)
-                         : clamp_count(a.off_prev[c], a.count_prev[c], a.list_cap);
+        const uint8_t m = a.mask[c];
+        const uint32_t nb = cbase[c], nn = own[c], pb = a.off_prev[c], pn = a.count_prev[c];
+        return clamp_count(m ? nb : pb, m ? nn : pn, a.list_cap);
     };
     uint32_t acc = 0;
+#pragma unroll 4
     for (int c = tid; c < c0; c += kCompact1Block) acc += count_of(c);
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) s_wsum[wave] = acc;
     if (tid < c1 - c0) {
         const int c = c0 + tid;
-        s_n[tid] = count_of(c);
-        s_src[tid] = a.mask[c] ? sparse + cbase[c] : a.list_prev + a.off_prev[c];
+        const uint8_t m = a.mask[c];
+        const uint32_t nb = cbase[c], nn = own[c], pb = a.off_prev[c], pn = a.count_prev[c];
+        s_n[tid] = clamp_count(m ? nb : pb, m ? nn : pn, a.list_cap);
+        s_src[tid] = m ? sparse + nb : a.list_prev + pb;
     }
     __syncthreads();
     if (tid == 0) {
