@@ -274,7 +274,12 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
                   uint8_t* cell_mask);
 
 /* Release the handle (waits for its queued work). The arena may be freed
- * afterwards. */
+ * afterwards. A stream attached to a batch is detached first (KPD_ESTATE,
+ * and the stream stays open, when it has a frame staged for the next tick).
+ * Every later call with the handle, close_stream included, returns
+ * KPD_ESTATE: the library keeps a set of the handles it has handed out and
+ * not released, and checks each handle against it (until a new handle
+ * happens to reuse the address). */
 int close_stream(kpd_stream* s);
 
 /* Forget the previous frame (e.g. at a scene cut): the next pushed frame is
@@ -312,8 +317,9 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
                int use_graph, kpd_batch** out);
 
 /* Attach or detach a stream. The stream must have been opened on the
- * batch's HIP stream. KPD_ENOMEM when the batch's stream or workgroup
- * capacity would be exceeded. */
+ * batch's HIP stream and may belong to one batch at a time (KPD_EINVAL
+ * otherwise). KPD_ENOMEM when the batch's stream or workgroup capacity
+ * would be exceeded. */
 int batch_attach(kpd_batch* b, kpd_stream* s);
 int batch_detach(kpd_batch* b, kpd_stream* s);
 
@@ -350,7 +356,8 @@ int batch_set_single_launch(kpd_batch* b, int on);
  * it gathers, before the next tick. */
 int batch_gather(kpd_batch* b, kpd_keypoint* out, size_t out_cap, uint32_t* counts);
 
-/* Wait for the batch's work and release it. Attached streams stay open. */
+/* Wait for the batch's work and release it. Attached streams stay open,
+ * detached. */
 int close_batch(kpd_batch* b);
 
 /* ------------------------------------------------------- inspection calls */

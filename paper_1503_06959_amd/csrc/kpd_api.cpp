@@ -7,8 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_set>
 #include <utility>
 #include <vector>
 
@@ -538,7 +540,7 @@ struct kpd_stream {
     std::vector<kpd::GroupLayout> glay;   // the group detector's layouts (chunks)
     std::vector<kpd::GroupLayout> glay1;  // its one-cell layouts (single frames)
     kpd::FrameArgs chunk_fa{};  // tile-pass arguments of chunk frame 0
-    bool closed = false;
+    kpd_batch* batch = nullptr;   // the batch it is attached to
     // pinned host staging for get_keypoints: header, the first kStage
     // entries of D_n and the mask come back in one round trip
     uint8_t* stage = nullptr;       // pinned host staging of get_keypoints
@@ -835,13 +837,17 @@ int open_stream(int width, int height, const kpd_params* params, void* dev_arena
         delete s;
         return hip_fail(e, "open_stream initialisation");
     }
+    if (!kpd::handle_add(s)) {
+        delete s;
+        return fail(KPD_ENOMEM, "host allocation failed");
+    }
     *out = s;
     return KPD_OK;
 }
 
 int set_thresholds(kpd_stream* s, int32_t fast_t, int32_t id_thresh, uint32_t kb_thresh)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (fast_t < 1 || fast_t > 254) return fail(KPD_EINVAL, "fast_t must be in 1..254");
     if (fast_t != s->p.fast_t) s->force_all = true;
     s->p.fast_t = fast_t;
@@ -871,7 +877,7 @@ uint8_t* alt_level(kpd_stream* s, int o)
 
 int stage_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags, kpd::TickArgs* t)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     const Layout& L = s->L;
     if (!frame) return fail(KPD_EINVAL, "frame is NULL");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return fail(KPD_EINVAL, "bad pitch");
@@ -1077,10 +1083,39 @@ int copy_chunk_features(kpd_stream* s, int i, const size_t* off_last, size_t cof
 
 }  // namespace
 
+namespace {
+std::mutex g_handles_mu;
+std::unordered_set<const void*> g_handles;
+}  // namespace
+
 namespace kpd {
 // error reporting for the other host files of the library
 int api_fail(int code, const std::string& msg) { return fail(code, msg); }
 int api_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+bool handle_add(const void* h)
+{
+    try {
+        const std::lock_guard<std::mutex> lock(g_handles_mu);
+        g_handles.insert(h);
+        return true;
+    } catch (...) {
+        return false;
+    }
+}
+
+void handle_remove(const void* h)
+{
+    const std::lock_guard<std::mutex> lock(g_handles_mu);
+    g_handles.erase(h);
+}
+
+bool handle_live(const void* h)
+{
+    if (!h) return false;
+    const std::lock_guard<std::mutex> lock(g_handles_mu);
+    return g_handles.count(h) != 0;
+}
 }  // namespace kpd
 
 extern "C" {
@@ -1149,7 +1184,7 @@ int push_frame(kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flag
 
 int set_mask_mode(kpd_stream* s, int mode, int layer)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (mode < 0 || mode > 2) return fail(KPD_EINVAL, "mode must be 0, 1 or 2");
     if (layer < 0 || layer >= s->L.O) return fail(KPD_EINVAL, "layer must be an octave of the stream");
     if (mode == 2 && layer != 0) return fail(KPD_EINVAL, "mode 2 masks every octave on its own level: layer must be 0");
@@ -1197,7 +1232,7 @@ int seq_run(const Layout& L, int n, int cap)
 int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_t pitch_bytes, int n_frames)
 {
     const kpd::TraceRange trace_range("kpd:push_frames");
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     const Layout& L = s->L;
     if (L.K < 2) return fail(KPD_EINVAL, "stream opened without chunk_frames");
     // per-pixel masks (Sec. 3.1): their marks come from pixels alone, so T_H
@@ -1529,7 +1564,7 @@ int push_frames(kpd_stream* s, const uint8_t* frames, size_t frame_stride, size_
 
 int kpd_chunk_result(kpd_stream* s, int i, const kpd_keypoint** d_list, const uint32_t** d_count)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (i < 0 || i >= s->chunk_n) return fail(KPD_EINVAL, "no such frame in the last chunk");
     const Layout& L = s->L;
     if (i == s->chunk_n - 1) return kpd_device_result(s, d_list, d_count);   // the last frame's D is D_n
@@ -1540,7 +1575,7 @@ int kpd_chunk_result(kpd_stream* s, int i, const kpd_keypoint** d_list, const ui
 
 int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (!count) return fail(KPD_EINVAL, "count is NULL");
     if (i < 0 || i >= s->chunk_n) return fail(KPD_EINVAL, "no such frame in the last chunk");
     if (i == s->chunk_n - 1) return get_keypoints(s, out, capacity, count, nullptr);   // D_n itself
@@ -1564,7 +1599,7 @@ int get_chunk_keypoints(kpd_stream* s, int i, kpd_keypoint* out, size_t capacity
 int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask)
 {
     const kpd::TraceRange trace_range("kpd:get_keypoints");
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (!count) return fail(KPD_EINVAL, "count is NULL");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
     const Layout& L = s->L;
@@ -1601,28 +1636,28 @@ int get_keypoints(kpd_stream* s, kpd_keypoint* out, size_t capacity, size_t* cou
 
 int get_descriptors(kpd_stream* s, kpd_descriptor* out, size_t capacity, size_t* count)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (!(s->p.features & KPD_FEAT_DESCRIPTOR)) return fail(KPD_EINVAL, "stream opened without descriptors");
     return copy_features(s, s->L.off_desc, out, capacity, count);
 }
 
 int get_refined(kpd_stream* s, kpd_refined* out, size_t capacity, size_t* count)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (!(s->p.features & KPD_FEAT_REFINE)) return fail(KPD_EINVAL, "stream opened without refinement");
     return copy_features(s, s->L.off_ref, out, capacity, count);
 }
 
 int get_chunk_descriptors(kpd_stream* s, int i, kpd_descriptor* out, size_t capacity, size_t* count)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (!(s->p.features & KPD_FEAT_DESCRIPTOR)) return fail(KPD_EINVAL, "stream opened without descriptors");
     return copy_chunk_features(s, i, s->L.off_desc, s->L.off_cdesc, out, capacity, count);
 }
 
 int get_chunk_refined(kpd_stream* s, int i, kpd_refined* out, size_t capacity, size_t* count)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (!(s->p.features & KPD_FEAT_REFINE)) return fail(KPD_EINVAL, "stream opened without refinement");
     return copy_chunk_features(s, i, s->L.off_ref, s->L.off_cref, out, capacity, count);
 }
@@ -1638,9 +1673,13 @@ int kpd_desc_point(int sector, int i, int* dx, int* dy)
 
 int close_stream(kpd_stream* s)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
+    if (s->batch) {   // leave the batch first, so that it holds no released stream
+        const int rc = batch_detach(s->batch, s);
+        if (rc != KPD_OK) return rc;
+    }
     hipError_t e = hipStreamSynchronize(s->stream);
-    s->closed = true;
+    kpd::handle_remove(s);
     delete s;
     if (e != hipSuccess) return hip_fail(e, "close_stream");
     return KPD_OK;
@@ -1648,21 +1687,21 @@ int close_stream(kpd_stream* s)
 
 int reset_stream(kpd_stream* s)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     s->force_all = true;
     return KPD_OK;
 }
 
 int kpd_profile(kpd_stream* s, int enable)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     s->timer.on = enable != 0;
     return KPD_OK;
 }
 
 int kpd_profile_read(kpd_stream* s, double* ms, uint64_t* launches)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     KPD_HIP(hipStreamSynchronize(s->stream));
     for (auto& p : s->timer.pending) {
         float t = 0.f;
@@ -1684,7 +1723,7 @@ int kpd_profile_read(kpd_stream* s, double* ms, uint64_t* launches)
 
 int kpd_device_result(kpd_stream* s, const kpd_keypoint** d_list, const uint32_t** d_count)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
     const int k = s->fb_last;
     if (d_list) *d_list = s->at<kpd_keypoint>(s->L.off_list[k]);
@@ -1694,7 +1733,7 @@ int kpd_device_result(kpd_stream* s, const kpd_keypoint** d_list, const uint32_t
 
 int kpd_cell_stats(kpd_stream* s, uint32_t* sad, uint32_t* counts)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
     const int k = (s->n_pushed - 1) & 1;
     const size_t n = (size_t)s->L.ncell * 4;
@@ -1873,6 +1912,10 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
     if (scratch_bytes < need) return fail(KPD_ENOMEM, "batch scratch too small");
     kpd_batch* b = new (std::nothrow) kpd_batch();
     if (!b) return fail(KPD_ENOMEM, "host allocation failed");
+    if (!kpd::handle_add(b)) {
+        delete b;
+        return fail(KPD_ENOMEM, "host allocation failed");
+    }
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);
     b->max_streams = max_streams;
     b->max_blocks = max_blocks;
@@ -1902,7 +1945,7 @@ int open_batch(int max_streams, int max_blocks, void* dev_scratch, size_t scratc
 
 int batch_set_single_launch(kpd_batch* b, int on)
 {
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return fail(KPD_ESTATE, "batch is closed");
     if (on != 0 && on != 1) return fail(KPD_EINVAL, "on must be 0 or 1");
     KPD_HIP(hipStreamSynchronize(b->stream));   // no tick in flight uses the old form
     b->single_launch = on != 0;
@@ -1912,10 +1955,9 @@ int batch_set_single_launch(kpd_batch* b, int on)
 
 int batch_attach(kpd_batch* b, kpd_stream* s)
 {
-    if (!b || !s || s->closed) return fail(KPD_ESTATE, "batch or stream is closed");
+    if (!kpd::handle_live(b) || !kpd::handle_live(s)) return fail(KPD_ESTATE, "batch or stream is closed");
     if (s->stream != b->stream) return fail(KPD_EINVAL, "stream was opened on another HIP stream");
-    if (std::find(b->streams.begin(), b->streams.end(), s) != b->streams.end())
-        return fail(KPD_EINVAL, "stream already attached");
+    if (s->batch) return fail(KPD_EINVAL, "stream already attached");
     if ((int)b->streams.size() >= b->max_streams) return fail(KPD_ENOMEM, "batch stream capacity exceeded");
     b->streams.push_back(s);
     b->staged.push_back(kpd::TickArgs{});
@@ -1926,13 +1968,15 @@ int batch_attach(kpd_batch* b, kpd_stream* s)
         b->staged.pop_back();
         b->has_frame.pop_back();
         rebuild_maps(b);
+    } else {
+        s->batch = b;
     }
     return rc;
 }
 
 int batch_detach(kpd_batch* b, kpd_stream* s)
 {
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return fail(KPD_ESTATE, "batch is closed");
     auto it = std::find(b->streams.begin(), b->streams.end(), s);
     if (it == b->streams.end()) return fail(KPD_EINVAL, "stream not attached");
     const size_t i = (size_t)(it - b->streams.begin());
@@ -1940,6 +1984,7 @@ int batch_detach(kpd_batch* b, kpd_stream* s)
     b->streams.erase(it);
     b->staged.erase(b->staged.begin() + (long)i);
     b->has_frame.erase(b->has_frame.begin() + (long)i);
+    s->batch = nullptr;
     return rebuild_maps(b);
 }
 
@@ -1971,7 +2016,7 @@ extern "C" {
 
 int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
 {
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return fail(KPD_ESTATE, "batch is closed");
     size_t hint = 0;
     return batch_stage(b, s, frame, pitch_bytes, flags, &hint);
 }
@@ -1979,7 +2024,7 @@ int batch_push(kpd_batch* b, kpd_stream* s, const uint8_t* frame, size_t pitch_b
 int batch_push_many(kpd_batch* b, int n, kpd_stream* const* streams, const uint8_t* const* frames,
                     const size_t* pitch_bytes, int flags)
 {
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return fail(KPD_ESTATE, "batch is closed");
     if (n < 0 || (n > 0 && (!streams || !frames || !pitch_bytes))) return fail(KPD_EINVAL, "bad arrays");
     size_t hint = 0;
     for (int k = 0; k < n; ++k) {
@@ -1992,7 +2037,7 @@ int batch_push_many(kpd_batch* b, int n, kpd_stream* const* streams, const uint8
 int batch_tick(kpd_batch* b)
 {
     const kpd::TraceRange trace_range("kpd:batch_tick");
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return fail(KPD_ESTATE, "batch is closed");
     if (b->maps_dirty) {
         const int rc = rebuild_maps(b);
         if (rc != KPD_OK) return rc;
@@ -2043,7 +2088,7 @@ int batch_tick(kpd_batch* b)
 
 int batch_gather(kpd_batch* b, kpd_keypoint* out, size_t out_cap, uint32_t* counts)
 {
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return fail(KPD_ESTATE, "batch is closed");
     if (!out || !counts) return fail(KPD_EINVAL, "NULL output");
     if (b->ticks == 0) return fail(KPD_ESTATE, "no tick yet");
     if (b->streams.empty()) return KPD_OK;
@@ -2055,13 +2100,15 @@ int batch_gather(kpd_batch* b, kpd_keypoint* out, size_t out_cap, uint32_t* coun
 
 int close_batch(kpd_batch* b)
 {
-    if (!b) return fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return fail(KPD_ESTATE, "batch is closed");
     const hipError_t e = hipStreamSynchronize(b->stream);
     drop_graphs(b);
     for (int k = 0; k < 2; ++k) {
         if (b->host_table[k]) (void)hipHostFree(b->host_table[k]);
         if (b->table_free[k]) (void)hipEventDestroy(b->table_free[k]);
     }
+    for (kpd_stream* s : b->streams) s->batch = nullptr;   // they stay open, detached
+    kpd::handle_remove(b);
     delete b;
     if (e != hipSuccess) return hip_fail(e, "close_batch");
     return KPD_OK;
@@ -2069,7 +2116,7 @@ int close_batch(kpd_batch* b)
 
 int kpd_pyramid_level(kpd_stream* s, int octave, uint8_t* out)
 {
-    if (!s || s->closed) return fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return fail(KPD_ESTATE, "stream is closed");
     if (s->n_pushed == 0) return fail(KPD_ESTATE, "no frame pushed yet");
     if (octave < 1 || octave >= s->L.O || !out) return fail(KPD_EINVAL, "bad octave or NULL output");
     const Layout& L = s->L;

@@ -259,7 +259,6 @@ struct kpd_lstream {
     uint64_t n_pushed = 0;
     const uint8_t* prev = nullptr;
     int prev_pitch = 0;
-    bool closed = false;
     template <class T> T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
 };
 
@@ -320,6 +319,10 @@ int kpd_lstream_open(int width, int height, const kpd_params* params, void* dev_
         delete s;
         return kpd::api_hip_fail(e, "kpd_lstream_open");
     }
+    if (!kpd::handle_add(s)) {
+        delete s;
+        return kpd::api_fail(KPD_ENOMEM, "host allocation failed");
+    }
     *out = s;
     return KPD_OK;
 }
@@ -327,7 +330,7 @@ int kpd_lstream_open(int width, int height, const kpd_params* params, void* dev_
 int kpd_lstream_push(kpd_lstream* s, const uint8_t* frame, size_t pitch_bytes, int flags)
 {
     const kpd::TraceRange trace_range("kpd:lstream_push");
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     const LsLayout& L = s->L;
     if (!frame) return kpd::api_fail(KPD_EINVAL, "frame is NULL");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return kpd::api_fail(KPD_EINVAL, "bad pitch");
@@ -400,7 +403,7 @@ int kpd_lstream_push_frames(kpd_lstream* s, const uint8_t* frames, size_t frame_
                             int n_frames)
 {
     const kpd::TraceRange trace_range("kpd:lstream_push_frames");
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     const LsLayout& L = s->L;
     if (L.K < 2) return kpd::api_fail(KPD_EINVAL, "stream opened without chunk_frames");
     if (!frames) return kpd::api_fail(KPD_EINVAL, "frames is NULL");
@@ -505,7 +508,7 @@ int kpd_lstream_push_frames(kpd_lstream* s, const uint8_t* frames, size_t frame_
 
 int kpd_lstream_get_chunk(kpd_lstream* s, int i, kpd_keypoint* out, size_t capacity, size_t* count)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     if (!count) return kpd::api_fail(KPD_EINVAL, "count is NULL");
     if (i < 0 || i >= s->chunk_n) return kpd::api_fail(KPD_EINVAL, "no such frame in the last chunk");
     if (i == s->chunk_n - 1) return kpd_lstream_get(s, out, capacity, count, nullptr);   // D_n itself
@@ -529,7 +532,7 @@ int kpd_lstream_get_chunk(kpd_lstream* s, int i, kpd_keypoint* out, size_t capac
 
 int kpd_lstream_get(kpd_lstream* s, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     if (!count) return kpd::api_fail(KPD_EINVAL, "count is NULL");
     if (s->n_pushed == 0) return kpd::api_fail(KPD_ESTATE, "no frame pushed yet");
     const LsLayout& L = s->L;
@@ -554,16 +557,16 @@ int kpd_lstream_get(kpd_lstream* s, kpd_keypoint* out, size_t capacity, size_t* 
 
 int kpd_lstream_reset(kpd_lstream* s)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     s->force = true;
     return KPD_OK;
 }
 
 int kpd_lstream_close(kpd_lstream* s)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "stream is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "stream is closed");
     const hipError_t e = hipStreamSynchronize(s->stream);
-    s->closed = true;
+    kpd::handle_remove(s);
     delete s;
     if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lstream_close");
     return KPD_OK;
@@ -626,7 +629,6 @@ struct kpd_lbatch {
     kpd::LbSlot* host_table[2] = {nullptr, nullptr};
     hipEvent_t table_free[2] = {nullptr, nullptr};
     int tk = 0;
-    bool closed = false;
     template <class T> T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
 };
 
@@ -661,6 +663,10 @@ int kpd_lbatch_open(int width, int height, const kpd_params* params, int max_str
                                              std::to_string(B.total));
     kpd_lbatch* b = new (std::nothrow) kpd_lbatch();
     if (!b) return kpd::api_fail(KPD_ENOMEM, "host allocation failed");
+    if (!kpd::handle_add(b)) {   // first, so that the error path below can close it
+        delete b;
+        return kpd::api_fail(KPD_ENOMEM, "host allocation failed");
+    }
     b->B = B;
     b->p = *params;
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -690,7 +696,7 @@ int kpd_lbatch_open(int width, int height, const kpd_params* params, int max_str
 
 int kpd_lbatch_push(kpd_lbatch* b, int slot, const uint8_t* frame, size_t pitch_bytes)
 {
-    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return kpd::api_fail(KPD_ESTATE, "batch is closed");
     if (slot < 0 || slot >= b->B.nslots) return kpd::api_fail(KPD_EINVAL, "no such slot");
     if (!frame) return kpd::api_fail(KPD_EINVAL, "frame is NULL");
     if (pitch_bytes < (size_t)b->B.s.W || pitch_bytes > (1u << 30)) return kpd::api_fail(KPD_EINVAL, "bad pitch");
@@ -704,7 +710,7 @@ int kpd_lbatch_push(kpd_lbatch* b, int slot, const uint8_t* frame, size_t pitch_
 int kpd_lbatch_tick(kpd_lbatch* b)
 {
     const kpd::TraceRange trace_range("kpd:lbatch_tick");
-    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return kpd::api_fail(KPD_ESTATE, "batch is closed");
     const LbLayout& B = b->B;
     const LsLayout& L = B.s;
     const int n = B.nslots;
@@ -782,7 +788,7 @@ int kpd_lbatch_tick(kpd_lbatch* b)
 
 int kpd_lbatch_get(kpd_lbatch* b, int slot, kpd_keypoint* out, size_t capacity, size_t* count, uint8_t* cell_mask)
 {
-    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return kpd::api_fail(KPD_ESTATE, "batch is closed");
     if (slot < 0 || slot >= b->B.nslots) return kpd::api_fail(KPD_EINVAL, "no such slot");
     if (!count) return kpd::api_fail(KPD_EINVAL, "count is NULL");
     if (!b->ticked[slot]) return kpd::api_fail(KPD_ESTATE, "the slot has had no frame yet");
@@ -810,7 +816,7 @@ int kpd_lbatch_get(kpd_lbatch* b, int slot, kpd_keypoint* out, size_t capacity, 
 
 int kpd_lbatch_reset(kpd_lbatch* b, int slot)
 {
-    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return kpd::api_fail(KPD_ESTATE, "batch is closed");
     if (slot < 0 || slot >= b->B.nslots) return kpd::api_fail(KPD_EINVAL, "no such slot");
     b->slot[slot].force = 1;
     return KPD_OK;
@@ -818,13 +824,13 @@ int kpd_lbatch_reset(kpd_lbatch* b, int slot)
 
 int kpd_lbatch_close(kpd_lbatch* b)
 {
-    if (!b || b->closed) return kpd::api_fail(KPD_ESTATE, "batch is closed");
+    if (!kpd::handle_live(b)) return kpd::api_fail(KPD_ESTATE, "batch is closed");
     hipError_t e = hipStreamSynchronize(b->stream);
     for (int k = 0; k < 2; ++k) {
         if (b->host_table[k]) (void)hipHostFree(b->host_table[k]);
         if (b->table_free[k]) (void)hipEventDestroy(b->table_free[k]);
     }
-    b->closed = true;
+    kpd::handle_remove(b);
     delete b;
     if (e != hipSuccess) return kpd::api_hip_fail(e, "kpd_lbatch_close");
     return KPD_OK;

@@ -87,7 +87,6 @@ struct kpd_tcd {
     int cur_slot = 0;
     const uint8_t* prev = nullptr;
     int prev_pitch = 0;
-    bool closed = false;
     template <class T> T* at(size_t off) { return reinterpret_cast<T*>(arena + off); }
 };
 
@@ -130,10 +129,10 @@ int tcd_open(int width, int height, const kpd_params* det, const kpd_tcd_params*
     s->arena = reinterpret_cast<uint8_t*>(dev_arena);
     s->det = inner;
     hipError_t e = hipMemsetAsync(s->arena + L.off_count, 0, 64, s->stream);
-    if (e != hipSuccess) {
+    if (e != hipSuccess || !kpd::handle_add(s)) {
         close_stream(inner);
         delete s;
-        return kpd::api_hip_fail(e, "tcd_open");
+        return e != hipSuccess ? kpd::api_hip_fail(e, "tcd_open") : kpd::api_fail(KPD_ENOMEM, "host allocation failed");
     }
     *out = s;
     return KPD_OK;
@@ -142,7 +141,7 @@ int tcd_open(int width, int height, const kpd_params* det, const kpd_tcd_params*
 int tcd_push(kpd_tcd* s, const uint8_t* frame, size_t pitch_bytes, int flags)
 {
     const kpd::TraceRange trace_range("kpd:tcd_push");
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
     const TcdLayout& L = s->L;
     if (!frame) return kpd::api_fail(KPD_EINVAL, "frame is NULL");
     if (pitch_bytes < (size_t)L.W || pitch_bytes > (1u << 30)) return kpd::api_fail(KPD_EINVAL, "bad pitch");
@@ -201,7 +200,7 @@ int tcd_push(kpd_tcd* s, const uint8_t* frame, size_t pitch_bytes, int flags)
 
 int tcd_device_result(kpd_tcd* s, const kpd_track** d_tracks, const uint32_t** d_count)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
     if (s->n_frames == 0 && s->prev == nullptr) return kpd::api_fail(KPD_ESTATE, "no frame pushed yet");
     if (d_tracks) *d_tracks = s->at<kpd_track>(s->L.off_tracks[s->fb]);
     if (d_count) *d_count = s->at<uint32_t>(s->L.off_count) + s->fb;
@@ -210,7 +209,7 @@ int tcd_device_result(kpd_tcd* s, const kpd_track** d_tracks, const uint32_t** d
 
 int tcd_get(kpd_tcd* s, kpd_track* out, size_t capacity, size_t* count)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
     if (!count) return kpd::api_fail(KPD_EINVAL, "count is NULL");
     if (s->n_frames == 0 && s->prev == nullptr) return kpd::api_fail(KPD_ESTATE, "no frame pushed yet");
     const TcdLayout& L = s->L;
@@ -231,16 +230,16 @@ int tcd_get(kpd_tcd* s, kpd_track* out, size_t capacity, size_t* count)
 
 int tcd_reset(kpd_tcd* s)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
     s->n_frames = 0;
     return KPD_OK;
 }
 
 int tcd_close(kpd_tcd* s)
 {
-    if (!s || s->closed) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
+    if (!kpd::handle_live(s)) return kpd::api_fail(KPD_ESTATE, "tracker is closed");
     const int rc = close_stream(s->det);
-    s->closed = true;
+    kpd::handle_remove(s);
     delete s;
     return rc;
 }

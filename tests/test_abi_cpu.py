@@ -269,3 +269,39 @@ def test_lstream_sizes(kpd):
     for bad in (kpd.make_params(0, 4, 16, 12), kpd.make_params(20, 9, 16, 12), kpd.make_params(20, 4, 0, 12),
                 kpd.make_params(20, 4, 641, 12), kpd.make_params(20, 4, 16, 481)):
         assert kpd.lib.kpd_lstream_bytes(640, 480, ctypes.byref(bad)) == 0
+
+
+HANDLE_TYPES = ("kpd_stream", "kpd_batch", "kpd_lstream", "kpd_lbatch", "kpd_tcd")
+
+
+def handle_calls():
+    """(name, number of parameters) of every int-returning call of the header
+    whose first parameter is a handle (opens, which take a handle's address,
+    excluded)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = []
+    for ret, name, params in re.findall(r"^(int)\s+([A-Za-z_]\w*)\s*\(([^;{]*)\)\s*;", text, flags=re.M):
+        ps = [p.strip() for p in params.split(",")]
+        first = ps[0].replace("const", "").replace("*", " * ").split()
+        if first and first[0] in HANDLE_TYPES and first.count("*") == 1:
+            out.append((name, len(ps)))
+    return out
+
+
+def test_unknown_handles_are_refused_before_use(kpd):
+    # a pointer the library never handed out (here zeroed host memory) is
+    # refused with KPD_ESTATE by every call that takes a handle, closes
+    # included, without reading through it
+    calls = handle_calls()
+    names = {n for n, _ in calls}
+    for n in ("push_frame", "get_keypoints", "close_stream", "batch_tick", "close_batch", "kpd_lbatch_tick",
+              "kpd_lstream_push", "tcd_push"):
+        assert n in names, n
+    fake = ctypes.create_string_buffer(4096)
+    lib = ctypes.CDLL(kpd.lib._name)
+    for name, nparams in calls:
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_void_p] * nparams
+        rc = fn(ctypes.addressof(fake), *([None] * (nparams - 1)))
+        assert rc == kpd.KPD_ESTATE, f"{name} returned {rc}"

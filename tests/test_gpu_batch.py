@@ -230,3 +230,38 @@ def test_batch_errors(kpd):
     g.keypoints()
     other.close()
     b.close()
+
+
+def test_closing_attached_streams_and_closed_handles(kpd):
+    from paper_1503_06959_amd.batch import Batch
+    b = Batch(max_streams=2)
+    p = kpd.make_params(30, 3, 8, 6, 8)
+    f = synth.make_video(synth.SCENES["c1_320x240"], 3)
+    g = b.open_stream(320, 240, p)
+    b.push(g, f[0])
+    # a staged frame keeps the stream attached and open
+    assert kpd.lib.close_stream(g.handle) == kpd.KPD_ESTATE
+    b.tick()
+    g.keypoints()
+    h = g.handle
+    assert kpd.lib.close_stream(h) == kpd.KPD_OK   # leaves the batch, then is released
+    b.streams.pop(h, None)
+    g.handle = None
+    assert kpd.lib.close_stream(h) == kpd.KPD_ESTATE
+    assert kpd.lib.push_frame(h, f[1].ctypes.data, 320, 0) == kpd.KPD_ESTATE
+    # its place in the batch is free again
+    g2 = b.open_stream(320, 240, p)
+    g3 = b.open_stream(320, 240, p)
+    o2 = oracle.Stream(320, 240, 30, 3, 8, 6, 8, KB_OFF)
+    for i in range(2):
+        b.push(g2, f[i])
+        b.push(g3, f[i])
+        o2.push(f[i])
+        b.tick()
+        assert tuples(g2.keypoints()[0]) == tuples(o2.get()[0])
+    hb = b.handle
+    b.close()
+    assert kpd.lib.batch_tick(hb) == kpd.KPD_ESTATE
+    # the batch's streams stay open, detached, and close normally
+    g2.close()
+    g3.close()
